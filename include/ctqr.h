@@ -1,0 +1,222 @@
+/*
+ * ctqr.h -- C ABI of the MI355X (gfx950) QR least-squares CT reconstruction
+ * library libctqr.so.
+ *
+ * The method (Chillaron, Quintana-Orti, Vidal, Verdu, "Computed tomography
+ * medical image reconstruction on affordable equipment by using out-of-core
+ * techniques"):
+ *   Section II-A, Eq. 1   A X = B (+ W): A is M x N (rays x pixels), B is M x S
+ *                         (one sinogram per column), X is N x S (one image per
+ *                         column).
+ *   Section II-A, Eq. 3   A = QR, computed once (it does not depend on B).
+ *   Section II-A, Eq. 4   X = R^-1 (Q^T B), Q applied implicitly through its
+ *                         Householder reflectors, R^-1 by backward substitution
+ *                         (Section II-C, "System solving").
+ *
+ * Conventions shared by every call:
+ *   - Dense matrices are column-major with a leading dimension (ld >= rows).
+ *     Dense A/factor pointers must be 16-byte aligned and their leading
+ *     dimension a multiple of 4 elements, so every column starts 16-byte
+ *     aligned.
+ *   - Every pointer marked "device" must point to device memory of the GPU
+ *     that is current on the calling thread; "host" pointers are ordinary host
+ *     memory.  The library never allocates or frees caller memory; all scratch
+ *     comes from a caller-provided device workspace whose size the matching
+ *     *_workspace() call reports.
+ *   - Calls that take a stream only enqueue work on it and return at once.
+ *   - Return value: CTQR_OK (0), or a negative code for an invalid call
+ *     detected on the host before anything is enqueued (nothing is enqueued
+ *     then), or CTQR_EHIP when the HIP runtime rejects a launch.  Numerical
+ *     events (rank deficiency, non-finite values, refinement that does not
+ *     converge) are written by the kernels into the caller's device-side
+ *     ctqr_info; read it after synchronising the stream.
+ *   - No C++ exception crosses this boundary.  Calls on different streams with
+ *     different workspaces may run concurrently.
+ */
+#ifndef CTQR_H
+#define CTQR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Same underlying type as HIP's own hipStream_t; NULL is the default stream. */
+typedef struct ihipStream_t *hipStream_t;
+
+typedef int32_t ctqr_status;
+#define CTQR_OK               0
+#define CTQR_EINVAL          (-1)  /* bad argument (null pointer, size, alignment, enum) */
+#define CTQR_ENOMEM          (-2)  /* caller workspace or capacity too small */
+#define CTQR_EHIP            (-3)  /* a HIP runtime call failed */
+#define CTQR_EUNSUPPORTED    (-4)  /* valid but not supported (e.g. no gfx950 device) */
+#define CTQR_RANK_DEFICIENT    1   /* info: |R_kk| <= n * u * max|R_ii| at column first_bad_col */
+#define CTQR_NOT_CONVERGED     2   /* info: refinement stopped without meeting its tolerance */
+#define CTQR_NONFINITE         3   /* info: NaN/Inf met in A, B or the refinement */
+#define CTQR_CAPACITY          4   /* info: a sparse capacity (nnz_cap, column length) was exceeded */
+#define CTQR_BARRIER_TIMEOUT   5   /* info: a grid barrier gave up waiting (results invalid) */
+
+/* Storage precision of the dense A and of its factor. */
+typedef int32_t ctqr_dtype;
+#define CTQR_F64 0
+#define CTQR_F32 1
+
+/* Arithmetic of the blocked trailing update and of Q^T B.
+ *   CTQR_PREC_FP64       FP64 storage, FP64 MFMA.
+ *   CTQR_PREC_FP32_MFMA  FP32 storage, FP32 MFMA with FP32 accumulation; panel
+ *                        norms and reflectors in FP64.
+ *   CTQR_PREC_BF16_MFMA  FP32 storage, operands rounded to BF16 for MFMA with
+ *                        FP32 accumulation; panel in FP64. */
+typedef int32_t ctqr_prec;
+#define CTQR_PREC_FP64      0
+#define CTQR_PREC_FP32_MFMA 1
+#define CTQR_PREC_BF16_MFMA 2
+
+/* Fan-beam scanner (Section II-A, Table I) and reconstruction grid.
+ * Rays: one per (view, bin), row index view * n_bins + bin.  The source turns
+ * on a circle of radius src_iso_cm; the flat detector, src_det_cm from the
+ * source and perpendicular to the central ray, has n_bins equal bins spanning
+ * the fan_deg fan; each ray joins the source to a bin centre.
+ * Pixels: side x side square of side fov_side_cm centred on the rotation axis,
+ * column index iy * side + ix (x fastest, origin at the lower-left corner).
+ * angle_schedule: 0 = uniform 360/n_views steps, 1 = Eq. 2 (quarter-turn
+ * shifts +0.5, -0.75, -0.25 degrees, each quarter continuing from the last
+ * angle of the previous one). */
+typedef struct {
+    int32_t side, n_views, n_bins;
+    int32_t angle_schedule;
+    double src_iso_cm, src_det_cm, fan_deg, fov_side_cm;
+} ctqr_geometry;
+
+/* FP64 sparse copy of A for exact residuals: CSR (row-major) and CSC
+ * (column-major, rows ascending within each column).  All arrays device. */
+typedef struct {
+    int64_t m, n, nnz_cap;
+    int64_t *rowptr;  int32_t *col;  double *val;    /* CSR: m+1, nnz_cap, nnz_cap */
+    int64_t *colptr;  int32_t *row;  double *cval;   /* CSC: n+1, nnz_cap, nnz_cap */
+} ctqr_sparse;
+
+/* Numerical outcome, written by the kernels (device memory, caller-owned). */
+typedef struct {
+    int32_t status;          /* 0 or one of the positive codes above           */
+    int32_t first_bad_col;   /* rank deficiency: first column k with tiny R_kk */
+    int32_t iters;           /* refinement iterations performed                */
+    int32_t pad;
+    double  max_rel_update;  /* last refinement: max_s ||dx_s||_inf / ||x_s||_inf */
+    double  rdiag_max;       /* max |R_kk|                                      */
+    double  rdiag_min;       /* min |R_kk|                                      */
+    int64_t nnz;             /* system matrix build: nonzeros of A              */
+} ctqr_info;
+
+/* Human-readable name of a status code (static string, never NULL). */
+const char *ctqr_status_string(ctqr_status s);
+
+/* Library version string and the device architecture it was built for. */
+const char *ctqr_version(void);
+
+/* Text of the last HIP failure seen by this thread (empty if none). */
+const char *ctqr_last_error(void);
+
+/* Sizes of A for a geometry (host only, no HIP call): m = n_views * n_bins
+ * rays, n = side^2 pixels, nnz_upper = m * (2 side - 1), an upper bound on the
+ * nonzeros (a straight ray crosses at most 2 side - 1 pixels).  Section II-A. */
+ctqr_status ctqr_geometry_sizes(const ctqr_geometry *g, int64_t *m, int64_t *n,
+                                int64_t *nnz_upper);
+
+/* Workspace (device bytes) for ctqr_build_system_matrix. */
+ctqr_status ctqr_build_workspace(const ctqr_geometry *g, size_t *bytes);
+
+/* Build the system matrix A (Section II-A, Eq. 1): a_ij = length of ray i
+ * inside pixel j in units of the pixel pitch (Siddon ray tracing).
+ *   A      device, dense m x n column-major in `dtype`, leading dim lda; may be
+ *          NULL (no dense copy).  Every entry is written (zeros included).
+ *   sp     sparse FP64 copy (CSR + CSC) with caller-allocated arrays of
+ *          capacity sp->nnz_cap; may be NULL.  sp->m, sp->n must match.
+ *   info   device; info->nnz receives the nonzero count, info->status
+ *          CTQR_CAPACITY if nnz_cap was too small (the sparse arrays are then
+ *          incomplete).
+ *   work   device workspace of at least ctqr_build_workspace() bytes.
+ * Cites: Section II-A (A models the scanner; M = detectors x views), Table I,
+ * Eq. 2 (angles). */
+ctqr_status ctqr_build_system_matrix(const ctqr_geometry *g, ctqr_dtype dtype,
+                                     void *A, int64_t lda, ctqr_sparse *sp,
+                                     void *work, size_t work_bytes,
+                                     ctqr_info *info, hipStream_t stream);
+
+/* Workspace (device bytes) for ctqr_qr_factor.  nb = 0 picks the default
+ * outer block (256). */
+ctqr_status ctqr_qr_workspace(int64_t m, int64_t n, ctqr_dtype dtype, ctqr_prec prec,
+                              int32_t nb, size_t *bytes);
+
+/* Blocked Householder QR, A = QR (Eq. 3), right-looking with compact-WY
+ * block reflectors H_k ... H_{k+nb-1} = I - V T V^T.
+ *   A      device, m x n (m >= n >= 1) in `dtype`, leading dim lda.  On exit
+ *          R is in the upper triangle and the Householder vectors v_k (unit
+ *          diagonal implied) below it: the in-place output of the paper's
+ *          Compute_dense_QR (Section II-C).
+ *   prec   CTQR_PREC_FP64 requires dtype CTQR_F64; the two MFMA modes require
+ *          CTQR_F32.
+ *   nb     outer block width (multiple of 32, <= 256), 0 = default.  The same
+ *          nb must be passed to the solve.
+ *   T      device, nb x n in `dtype` (leading dim nb): the nb x nb upper
+ *          triangular T of each block column (the paper's "S factors").
+ *   tau    device, n doubles: the reflector scalars (LAPACK larfg convention:
+ *          beta = -sign(alpha)||x||, tau = (beta - alpha)/beta).
+ *   info   device: rank deficiency / non-finite / barrier time-out.
+ * Sections II-C ("QR factorization"), Eq. 3. */
+ctqr_status ctqr_qr_factor(int64_t m, int64_t n, ctqr_dtype dtype, void *A, int64_t lda,
+                           ctqr_prec prec, int32_t nb, void *T, double *tau,
+                           void *work, size_t work_bytes, ctqr_info *info,
+                           hipStream_t stream);
+
+/* Workspace (device bytes) for ctqr_qr_solve_slices with up to nslices
+ * right-hand sides; refine != 0 reserves the refinement vectors. */
+ctqr_status ctqr_solve_workspace(int64_t m, int64_t n, ctqr_dtype dtype, int32_t nb,
+                                 int32_t nslices, int32_t refine, size_t *bytes);
+
+/* Least-squares reconstruction of nslices sinograms with a stored factor:
+ * X = R^-1 (Q^T B) (Eq. 4), Q^T applied block by block with the compact-WY
+ * factors, then block backward substitution with R (Section II-C, "System
+ * solving").
+ *   QR, T, tau  the outputs of ctqr_qr_factor (same m, n, dtype, nb).
+ *   B      device, m x nslices FP64, leading dim ldb (not modified).
+ *   X      device, n x nslices FP64, leading dim ldx (output).
+ *   A64    optional FP64 sparse A (from ctqr_build_system_matrix).  When given,
+ *          the solution is refined by corrected semi-normal equations:
+ *          r = B - A X (FP64), R^T y = A^T r, R d = y, X += d, until
+ *          max_s ||d_s||_inf <= tol ||X_s||_inf or max_iters iterations.
+ *          NULL = no refinement.
+ *   info   device: iterations, last relative update, CTQR_NOT_CONVERGED /
+ *          CTQR_NONFINITE. */
+ctqr_status ctqr_qr_solve_slices(int64_t m, int64_t n, ctqr_dtype dtype,
+                                 const void *QR, int64_t lda, const void *T,
+                                 const double *tau, int32_t nb,
+                                 const double *B, int64_t ldb, int32_t nslices,
+                                 double *X, int64_t ldx,
+                                 const ctqr_sparse *A64, double tol, int32_t max_iters,
+                                 void *work, size_t work_bytes, ctqr_info *info,
+                                 hipStream_t stream);
+
+/* Sinogram synthesis and residual helper: Y = alpha * A X + beta * Y with the
+ * FP64 CSR copy of A.  X (n x nslices, ldx) and Y (m x nslices, ldy) are
+ * column-major FP64 device arrays.  Eq. 1. */
+ctqr_status ctqr_spmm(const ctqr_sparse *A64, int32_t nslices, double alpha,
+                      const double *X, int64_t ldx, double beta, double *Y, int64_t ldy,
+                      hipStream_t stream);
+
+/* Kernel-level timing of the dominant kernel (the trailing-update GEMM
+ * C -= V W of ctqr_qr_factor).  While enabled, every launch of it is
+ * bracketed by HIP events on the stream it runs on; ctqr_profile_read returns
+ * the number of launches, their summed duration (ms, resolved after the
+ * caller has synchronised the stream) and their summed algorithmic flops
+ * (2 * rows * cols * nb per launch).  Host-side bookkeeping only; enabling it
+ * clears the previous record. */
+ctqr_status ctqr_profile_enable(int32_t on);
+ctqr_status ctqr_profile_read(int64_t *launches, double *total_ms, double *total_flops);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CTQR_H */

@@ -1,0 +1,488 @@
+// C ABI of libctqr: argument checking, workspace carving and the host-side
+// drivers of the blocked QR factorization and of the multi-slice solve.
+#include <mutex>
+#include <string>
+#include <vector>
+#include <cstdio>
+#include <cstring>
+#include <cmath>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace {
+
+constexpr int PANEL_W = 32;             // inner panel width
+constexpr int DEFAULT_NB = 256;         // outer block width
+constexpr int MAX_PANEL_WG = 1024;      // partial-sum slots of the panel kernel
+constexpr int64_t SPLIT_PART_ELEMS = 2LL * 512 * 128 * 128;   // split-K partial buffer
+
+thread_local std::string g_last_error;
+
+struct ProfRec {
+    hipEvent_t a, b;
+    double flops;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof;
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
+
+// Bump allocator over the caller's workspace (256-byte aligned pieces).
+struct Carve {
+    char *base;
+    size_t off = 0;
+    explicit Carve(void *b) : base((char *)b) {}
+    template <typename T>
+    T *take(int64_t count)
+    {
+        off = (size_t)round_up((int64_t)off, 256);
+        T *p = base ? (T *)(base + off) : nullptr;
+        off += (size_t)count * sizeof(T);
+        return p;
+    }
+};
+
+template <typename T>
+struct FactorWS {
+    unsigned *bars;
+    double *part, *part2, *gram_part, *gram, *Tw;
+    T *Tin, *GW, *W2, *split;
+    size_t bytes;
+};
+
+template <typename T>
+FactorWS<T> carve_factor(void *work, int64_t m, int64_t n, int nb)
+{
+    (void)m;
+    Carve c(work);
+    FactorWS<T> w;
+    w.bars = c.take<unsigned>(ceil_div(n, PANEL_W) + 64);
+    w.part = c.take<double>(MAX_PANEL_WG + 1);
+    w.part2 = c.take<double>((int64_t)MAX_PANEL_WG * PANEL_W);
+    w.gram_part = c.take<double>((int64_t)MAX_PANEL_WG * PANEL_W * PANEL_W);
+    w.gram = c.take<double>(PANEL_W * PANEL_W);
+    w.Tw = c.take<double>((int64_t)nb * nb);
+    w.Tin = c.take<T>(PANEL_W * PANEL_W);
+    w.GW = c.take<T>((int64_t)nb * n);
+    w.W2 = c.take<T>((int64_t)nb * n);
+    w.split = c.take<T>(SPLIT_PART_ELEMS);
+    w.bytes = c.off + 256;
+    return w;
+}
+
+template <typename T>
+struct SolveWS {
+    T *Bw, *W, *W2, *split, *Rinv, *RinvT, *Xw;
+    double *xr, *Br, *r, *s, *hist;
+    T *s32, *y32, *d32;
+    unsigned long long *dmax, *xmax;
+    int *done;
+    int64_t ldbw, ldxw;
+    size_t bytes;
+};
+
+template <typename T>
+SolveWS<T> carve_solve(void *work, int64_t m, int64_t n, int nb, int S, bool refine)
+{
+    Carve c(work);
+    SolveWS<T> w{};
+    w.ldbw = round_up(m, 4);
+    w.ldxw = round_up(n, 4);
+    w.Bw = c.take<T>(w.ldbw * S);
+    w.W = c.take<T>((int64_t)nb * S);
+    w.W2 = c.take<T>((int64_t)nb * S);
+    int64_t sp = std::max<int64_t>(SPLIT_PART_ELEMS, 64LL * nb * S);
+    w.split = c.take<T>(sp);
+    int64_t nbt = round_up(n, TRSM_BT);
+    w.Rinv = c.take<T>(nbt * TRSM_BT);
+    w.RinvT = c.take<T>(nbt * TRSM_BT);
+    w.Xw = c.take<T>(w.ldxw * S);
+    w.done = c.take<int>(64);
+    if (refine) {
+        w.xr = c.take<double>(n * S);
+        w.Br = c.take<double>(m * S);
+        w.r = c.take<double>(m * S);
+        w.s = c.take<double>(n * S);
+        w.s32 = c.take<T>(w.ldxw * S);
+        w.y32 = c.take<T>(w.ldxw * S);
+        w.d32 = c.take<T>(w.ldxw * S);
+        w.dmax = c.take<unsigned long long>(S);
+        w.xmax = c.take<unsigned long long>(S);
+        w.hist = c.take<double>(8);
+    }
+    w.bytes = c.off + 256;
+    return w;
+}
+
+int device_cus()
+{
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        hipDeviceProp_t p;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess)
+            cus = p.multiProcessorCount;
+        if (cus <= 0) cus = 256;
+    }
+    return cus;
+}
+
+ctqr_status ensure_setup()
+{
+    static std::once_flag once;
+    static ctqr_status st = CTQR_OK;
+    std::call_once(once, [] { st = panel_setup(panel_max_rows_per_wg()); });
+    return st;
+}
+
+template <typename T>
+ctqr_status factor_impl(int64_t m64, int64_t n64, T *A, int64_t lda, int nb, T *Tout, double *tau,
+                        void *work, ctqr_info *info, hipStream_t st)
+{
+    const int m = (int)m64, n = (int)n64;
+    FactorWS<T> w = carve_factor<T>(work, m64, n64, nb);
+    const int ncu = std::min(device_cus(), MAX_PANEL_WG);
+    if (panel_rows_per_wg(m, ncu) > panel_max_rows_per_wg()) return CTQR_EUNSUPPORTED;
+    ctqr_status s;
+    if ((s = info_reset(info, st))) return s;
+    if ((s = fill_u32(w.bars, ceil_div(n, PANEL_W) + 64, 0u, st))) return s;
+    int ipanel = 0;
+    for (int k0 = 0; k0 < n; k0 += nb) {
+        const int nbk = std::min(nb, n - k0);
+        // inner panels of the block column, each followed by its update of
+        // the rest of the block column
+        for (int c0 = k0; c0 < k0 + nbk; c0 += PANEL_W) {
+            const int wdt = std::min(PANEL_W, k0 + nbk - c0);
+            s = panel_qr<T>(A, lda, m, c0, wdt, tau + c0, w.part, w.part2, w.gram_part, w.gram,
+                            w.bars + ipanel, info, ncu, st);
+            if (s) return s;
+            ++ipanel;
+            const int ncr = k0 + nbk - (c0 + wdt);
+            if (ncr <= 0) continue;
+            if ((s = tbuild<double, T>(wdt, w.gram, PANEL_W, tau + c0, w.Tin, PANEL_W, w.Tw, st))) return s;
+            const T *Vp = A + (int64_t)c0 * lda + c0;
+            T *Cp = A + (int64_t)(c0 + wdt) * lda + c0;
+            s = gemm_tn<T>(wdt, ncr, m - c0, Vp, lda, wdt, Cp, lda, 0, T(1), T(0), w.GW, PANEL_W,
+                           w.split, SPLIT_PART_ELEMS, nullptr, st);
+            if (s) return s;
+            s = gemm_tn<T>(wdt, ncr, wdt, w.Tin, PANEL_W, 0, w.GW, PANEL_W, 0, T(1), T(0), w.W2, PANEL_W,
+                           w.split, SPLIT_PART_ELEMS, nullptr, st);
+            if (s) return s;
+            s = gemm_nn<T>(m - c0, ncr, wdt, Vp, lda, 1, w.W2, PANEL_W, T(-1), Cp, lda, nullptr, st);
+            if (s) return s;
+        }
+        // block reflector of the whole block column: [G | W] = V^T [V | C]
+        const int nc = n - (k0 + nbk);
+        const T *V = A + (int64_t)k0 * lda + k0;
+        s = gemm_tn<T>(nbk, nbk + nc, m - k0, V, lda, nbk, V, lda, nbk, T(1), T(0), w.GW, nb, w.split,
+                       SPLIT_PART_ELEMS, nullptr, st);
+        if (s) return s;
+        T *Tk = Tout + (int64_t)k0 * nb;
+        if ((s = tbuild<T, T>(nbk, w.GW, nb, tau + k0, Tk, nb, w.Tw, st))) return s;
+        if (nc <= 0) continue;
+        // W' = T^T W;  C -= V W'
+        s = gemm_tn<T>(nbk, nc, nbk, Tk, nb, 0, w.GW + (int64_t)nbk * nb, nb, 0, T(1), T(0), w.W2, nb,
+                       w.split, SPLIT_PART_ELEMS, nullptr, st);
+        if (s) return s;
+        T *C = A + (int64_t)(k0 + nbk) * lda + k0;
+        bool prof;
+        {
+            std::lock_guard<std::mutex> lk(g_prof_mu);
+            prof = g_prof_on;
+        }
+        ProfRec rec{};
+        if (prof) {
+            HIP_TRY(hipEventCreate(&rec.a));
+            HIP_TRY(hipEventCreate(&rec.b));
+            HIP_TRY(hipEventRecord(rec.a, st));
+        }
+        s = gemm_nn<T>(m - k0, nc, nbk, V, lda, 1, w.W2, nb, T(-1), C, lda, nullptr, st);
+        if (s) return s;
+        if (prof) {
+            HIP_TRY(hipEventRecord(rec.b, st));
+            rec.flops = 2.0 * (double)(m - k0) * (double)nc * (double)nbk;
+            std::lock_guard<std::mutex> lk(g_prof_mu);
+            g_prof.push_back(rec);
+        }
+    }
+    return rdiag_check<T>(n, A, lda, nullptr, info, st);
+}
+
+template <typename T>
+ctqr_status solve_impl(int64_t m64, int64_t n64, const T *QR, int64_t lda, const T *Tf,
+                       const double *tau, int nb, const double *B, int64_t ldb, int S, double *X,
+                       int64_t ldx, const ctqr_sparse *A64, double tol, int max_iters, void *work,
+                       ctqr_info *info, hipStream_t st)
+{
+    (void)tau;
+    const int m = (int)m64, n = (int)n64;
+    const bool refine = A64 != nullptr && max_iters > 0;
+    SolveWS<T> w = carve_solve<T>(work, m64, n64, nb, S, refine);
+    const int64_t sp_elems = std::max<int64_t>(SPLIT_PART_ELEMS, 64LL * nb * S);
+    ctqr_status s;
+    if ((s = info_reset(info, st))) return s;
+    if ((s = fill_u32((unsigned *)w.done, 64, 0u, st))) return s;
+    // working copy of B in the factor's precision
+    if ((s = copy_cm<T, double>(m, S, B, ldb, w.Bw, w.ldbw, st))) return s;
+    // Q^T B, one block reflector at a time: B -= V (T^T (V^T B))
+    for (int k0 = 0; k0 < n; k0 += nb) {
+        const int nbk = std::min(nb, n - k0);
+        const T *V = QR + (int64_t)k0 * lda + k0;
+        T *Bk = w.Bw + k0;
+        s = gemm_tn<T>(nbk, S, m - k0, V, lda, nbk, Bk, w.ldbw, 0, T(1), T(0), w.W, nb, w.split, sp_elems,
+                       nullptr, st);
+        if (s) return s;
+        s = gemm_tn<T>(nbk, S, nbk, Tf + (int64_t)k0 * nb, nb, 0, w.W, nb, 0, T(1), T(0), w.W2, nb, w.split,
+                       sp_elems, nullptr, st);
+        if (s) return s;
+        s = gemm_nn<T>(m - k0, S, nbk, V, lda, 1, w.W2, nb, T(-1), Bk, w.ldbw, nullptr, st);
+        if (s) return s;
+    }
+    // back substitution R X = (Q^T B)[0:n]
+    if ((s = trinv_blocks<T>(n, QR, lda, w.Rinv, w.RinvT, info, st))) return s;
+    s = trsm_upper<T>(n, S, QR, lda, w.RinvT, w.Bw, w.ldbw, w.Xw, w.ldxw, w.split, sp_elems, nullptr, st);
+    if (s) return s;
+    if (!refine) return copy_cm<double, T>(n, S, w.Xw, w.ldxw, X, ldx, st);
+
+    // corrected semi-normal equations: r = B - A x, R^T y = A^T r, R d = y, x += d
+    if ((s = cm_to_rm<double, T>(n, S, w.Xw, w.ldxw, w.xr, nullptr, st))) return s;
+    if ((s = cm_to_rm<double, double>(m, S, B, ldb, w.Br, nullptr, st))) return s;
+    if ((s = fill_f64(w.hist, 8, 0.0, st))) return s;
+    if ((s = fill_u32((unsigned *)w.dmax, 2LL * S, 0u, st))) return s;
+    if ((s = fill_u32((unsigned *)w.xmax, 2LL * S, 0u, st))) return s;
+    for (int it = 0; it < max_iters; ++it) {
+        const int *skip = w.done;
+        s = spmm_rowmajor(m, S, A64->rowptr, A64->col, A64->val, -1.0, w.xr, 1.0, w.Br, w.r, skip, st);
+        if (s) return s;
+        s = spmm_rowmajor(n, S, A64->colptr, A64->row, A64->cval, 1.0, w.r, 0.0, nullptr, w.s, skip, st);
+        if (s) return s;
+        if ((s = rm_to_cm<T, double>(n, S, w.s, w.s32, w.ldxw, skip, st))) return s;
+        s = trsm_upper_trans<T>(n, S, QR, lda, w.Rinv, w.s32, w.ldxw, w.y32, w.ldxw, w.split, sp_elems,
+                                skip, st);
+        if (s) return s;
+        s = trsm_upper<T>(n, S, QR, lda, w.RinvT, w.y32, w.ldxw, w.d32, w.ldxw, w.split, sp_elems, skip, st);
+        if (s) return s;
+        if ((s = refine_update<T>(n, S, w.xr, w.d32, w.ldxw, w.dmax, w.xmax, skip, st))) return s;
+        if ((s = refine_check(S, w.dmax, w.xmax, tol, it, max_iters, w.hist, w.done, info, st))) return s;
+    }
+    return rm_to_cm<double, double>(n, S, w.xr, X, ldx, nullptr, st);
+}
+
+bool geometry_ok(const ctqr_geometry *g)
+{
+    if (!g) return false;
+    if (g->side < 1 || g->n_views < 1 || g->n_bins < 1) return false;
+    if (g->angle_schedule != 0 && g->angle_schedule != 1) return false;
+    if (g->angle_schedule == 1 && g->n_views < 4) return false;
+    if (!(g->src_iso_cm > 0) || !(g->src_det_cm > g->src_iso_cm)) return false;
+    if (!(g->fan_deg > 0 && g->fan_deg < 180) || !(g->fov_side_cm > 0)) return false;
+    int64_t m = (int64_t)g->n_views * g->n_bins, n = (int64_t)g->side * g->side;
+    return m < INT32_MAX && n < INT32_MAX;
+}
+
+bool prec_ok(ctqr_dtype dtype, ctqr_prec prec)
+{
+    if (dtype == CTQR_F64) return prec == CTQR_PREC_FP64;
+    if (dtype == CTQR_F32) return prec == CTQR_PREC_FP32_MFMA;
+    return false;
+}
+
+int resolve_nb(int nb) { return nb == 0 ? DEFAULT_NB : nb; }
+bool nb_ok(int nb) { return nb >= 32 && nb <= 256 && nb % 32 == 0; }
+
+}  // namespace
+
+void ctqr_last_hip_error(hipError_t e, const char *what, const char *file, int line)
+{
+    char buf[512];
+    snprintf(buf, sizeof buf, "%s failed: %s (%s:%d)", what, hipGetErrorString(e), file, line);
+    g_last_error = buf;
+}
+
+extern "C" {
+
+const char *ctqr_status_string(ctqr_status s)
+{
+    switch (s) {
+    case CTQR_OK: return "CTQR_OK";
+    case CTQR_EINVAL: return "CTQR_EINVAL: invalid argument";
+    case CTQR_ENOMEM: return "CTQR_ENOMEM: workspace or capacity too small";
+    case CTQR_EHIP: return "CTQR_EHIP: HIP runtime error";
+    case CTQR_EUNSUPPORTED: return "CTQR_EUNSUPPORTED: unsupported configuration";
+    case CTQR_RANK_DEFICIENT: return "CTQR_RANK_DEFICIENT: R has a negligible diagonal entry";
+    case CTQR_NOT_CONVERGED: return "CTQR_NOT_CONVERGED: refinement did not converge";
+    case CTQR_NONFINITE: return "CTQR_NONFINITE: NaN or Inf encountered";
+    case CTQR_CAPACITY: return "CTQR_CAPACITY: sparse capacity exceeded";
+    case CTQR_BARRIER_TIMEOUT: return "CTQR_BARRIER_TIMEOUT: grid barrier timed out";
+    default: return "unknown ctqr status";
+    }
+}
+
+const char *ctqr_version(void) { return "ctqr 0.1 gfx950"; }
+
+const char *ctqr_last_error(void) { return g_last_error.c_str(); }
+
+ctqr_status ctqr_geometry_sizes(const ctqr_geometry *g, int64_t *m, int64_t *n, int64_t *nnz_upper)
+{
+    if (!geometry_ok(g) || !m || !n || !nnz_upper) return CTQR_EINVAL;
+    *m = (int64_t)g->n_views * g->n_bins;
+    *n = (int64_t)g->side * g->side;
+    *nnz_upper = *m * (2LL * g->side - 1);
+    return CTQR_OK;
+}
+
+ctqr_status ctqr_build_workspace(const ctqr_geometry *g, size_t *bytes)
+{
+    if (!geometry_ok(g) || !bytes) return CTQR_EINVAL;
+    *bytes = siddon_workspace(g);
+    return CTQR_OK;
+}
+
+ctqr_status ctqr_build_system_matrix(const ctqr_geometry *g, ctqr_dtype dtype, void *A, int64_t lda,
+                                     ctqr_sparse *sp, void *work, size_t work_bytes, ctqr_info *info,
+                                     hipStream_t stream)
+{
+    try {
+        if (!geometry_ok(g) || !info || !work) return CTQR_EINVAL;
+        if (dtype != CTQR_F64 && dtype != CTQR_F32) return CTQR_EINVAL;
+        const int64_t m = (int64_t)g->n_views * g->n_bins, n = (int64_t)g->side * g->side;
+        if (A && (lda < m || !aligned16(A))) return CTQR_EINVAL;
+        if (!A && !sp) return CTQR_EINVAL;
+        if (sp) {
+            if (sp->m != m || sp->n != n || sp->nnz_cap < 0 || !sp->rowptr || !sp->col || !sp->val)
+                return CTQR_EINVAL;
+            if ((sp->colptr != nullptr) != (sp->row != nullptr) || (sp->row != nullptr) != (sp->cval != nullptr))
+                return CTQR_EINVAL;
+        }
+        if (work_bytes < siddon_workspace(g)) return CTQR_ENOMEM;
+        ctqr_status s = info_reset(info, stream);
+        if (s) return s;
+        return siddon_build(g, dtype, A, lda, sp, work, work_bytes, info, stream);
+    } catch (...) {
+        return CTQR_EHIP;
+    }
+}
+
+ctqr_status ctqr_qr_workspace(int64_t m, int64_t n, ctqr_dtype dtype, ctqr_prec prec, int32_t nb,
+                              size_t *bytes)
+{
+    if (!bytes || m < n || n < 1 || m >= INT32_MAX) return CTQR_EINVAL;
+    if (!prec_ok(dtype, prec)) return (dtype == CTQR_F32 && prec == CTQR_PREC_BF16_MFMA) ? CTQR_EUNSUPPORTED : CTQR_EINVAL;
+    nb = resolve_nb(nb);
+    if (!nb_ok(nb)) return CTQR_EINVAL;
+    *bytes = dtype == CTQR_F64 ? carve_factor<double>(nullptr, m, n, nb).bytes
+                               : carve_factor<float>(nullptr, m, n, nb).bytes;
+    return CTQR_OK;
+}
+
+ctqr_status ctqr_qr_factor(int64_t m, int64_t n, ctqr_dtype dtype, void *A, int64_t lda, ctqr_prec prec,
+                           int32_t nb, void *T, double *tau, void *work, size_t work_bytes,
+                           ctqr_info *info, hipStream_t stream)
+{
+    try {
+        if (m < n || n < 1 || m >= INT32_MAX || !A || !T || !tau || !work || !info) return CTQR_EINVAL;
+        if (lda < m || lda % 4 != 0 || !aligned16(A) || !aligned16(T)) return CTQR_EINVAL;
+        if (!prec_ok(dtype, prec))
+            return (dtype == CTQR_F32 && prec == CTQR_PREC_BF16_MFMA) ? CTQR_EUNSUPPORTED : CTQR_EINVAL;
+        nb = resolve_nb(nb);
+        if (!nb_ok(nb)) return CTQR_EINVAL;
+        size_t need = 0;
+        ctqr_qr_workspace(m, n, dtype, prec, nb, &need);
+        if (work_bytes < need || !aligned16(work)) return work_bytes < need ? CTQR_ENOMEM : CTQR_EINVAL;
+        if (panel_rows_per_wg((int)m, 256) > panel_max_rows_per_wg()) return CTQR_EUNSUPPORTED;
+        ctqr_status s = ensure_setup();
+        if (s) return s;
+        if (dtype == CTQR_F64)
+            return factor_impl<double>(m, n, (double *)A, lda, nb, (double *)T, tau, work, info, stream);
+        return factor_impl<float>(m, n, (float *)A, lda, nb, (float *)T, tau, work, info, stream);
+    } catch (...) {
+        return CTQR_EHIP;
+    }
+}
+
+ctqr_status ctqr_solve_workspace(int64_t m, int64_t n, ctqr_dtype dtype, int32_t nb, int32_t nslices,
+                                 int32_t refine, size_t *bytes)
+{
+    if (!bytes || m < n || n < 1 || m >= INT32_MAX || nslices < 1) return CTQR_EINVAL;
+    if (dtype != CTQR_F64 && dtype != CTQR_F32) return CTQR_EINVAL;
+    nb = resolve_nb(nb);
+    if (!nb_ok(nb)) return CTQR_EINVAL;
+    *bytes = dtype == CTQR_F64 ? carve_solve<double>(nullptr, m, n, nb, nslices, refine != 0).bytes
+                               : carve_solve<float>(nullptr, m, n, nb, nslices, refine != 0).bytes;
+    return CTQR_OK;
+}
+
+ctqr_status ctqr_qr_solve_slices(int64_t m, int64_t n, ctqr_dtype dtype, const void *QR, int64_t lda,
+                                 const void *T, const double *tau, int32_t nb, const double *B,
+                                 int64_t ldb, int32_t nslices, double *X, int64_t ldx,
+                                 const ctqr_sparse *A64, double tol, int32_t max_iters, void *work,
+                                 size_t work_bytes, ctqr_info *info, hipStream_t stream)
+{
+    try {
+        if (m < n || n < 1 || m >= INT32_MAX || nslices < 1) return CTQR_EINVAL;
+        if (!QR || !T || !tau || !B || !X || !work || !info) return CTQR_EINVAL;
+        if (dtype != CTQR_F64 && dtype != CTQR_F32) return CTQR_EINVAL;
+        if (lda < m || lda % 4 != 0 || ldb < m || ldx < n) return CTQR_EINVAL;
+        if (!aligned16(QR) || !aligned16(T) || !aligned16(work)) return CTQR_EINVAL;
+        nb = resolve_nb(nb);
+        if (!nb_ok(nb)) return CTQR_EINVAL;
+        if (A64 && (A64->m != m || A64->n != n || !A64->rowptr || !A64->col || !A64->val ||
+                    !A64->colptr || !A64->row || !A64->cval))
+            return CTQR_EINVAL;
+        if (A64 && (max_iters < 0 || !(tol >= 0.0))) return CTQR_EINVAL;
+        size_t need = 0;
+        ctqr_solve_workspace(m, n, dtype, nb, nslices, A64 != nullptr && max_iters > 0, &need);
+        if (work_bytes < need) return CTQR_ENOMEM;
+        if (dtype == CTQR_F64)
+            return solve_impl<double>(m, n, (const double *)QR, lda, (const double *)T, tau, nb, B, ldb,
+                                      nslices, X, ldx, A64, tol, max_iters, work, info, stream);
+        return solve_impl<float>(m, n, (const float *)QR, lda, (const float *)T, tau, nb, B, ldb, nslices,
+                                 X, ldx, A64, tol, max_iters, work, info, stream);
+    } catch (...) {
+        return CTQR_EHIP;
+    }
+}
+
+ctqr_status ctqr_spmm(const ctqr_sparse *A64, int32_t nslices, double alpha, const double *X, int64_t ldx,
+                      double beta, double *Y, int64_t ldy, hipStream_t stream)
+{
+    if (!A64 || !A64->rowptr || !A64->col || !A64->val || !X || !Y || nslices < 1) return CTQR_EINVAL;
+    if (ldx < A64->n || ldy < A64->m) return CTQR_EINVAL;
+    return spmm_colmajor(A64->m, A64->n, nslices, A64->rowptr, A64->col, A64->val, alpha, X, ldx, beta, Y,
+                         ldy, stream);
+}
+
+ctqr_status ctqr_profile_enable(int32_t on)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (auto &r : g_prof) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    g_prof.clear();
+    g_prof_on = on != 0;
+    return CTQR_OK;
+}
+
+ctqr_status ctqr_profile_read(int64_t *launches, double *total_ms, double *total_flops)
+{
+    if (!launches || !total_ms || !total_flops) return CTQR_EINVAL;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    double ms = 0.0, fl = 0.0;
+    for (auto &r : g_prof) {
+        float t = 0.f;
+        HIP_TRY(hipEventSynchronize(r.b));
+        HIP_TRY(hipEventElapsedTime(&t, r.a, r.b));
+        ms += t;
+        fl += r.flops;
+    }
+    *launches = (int64_t)g_prof.size();
+    *total_ms = ms;
+    *total_flops = fl;
+    return CTQR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,569 @@
+// MFMA GEMMs for the block-reflector applications of the QR path.
+//
+// Applying a compact-WY block reflector H = I - V T V^T from the left,
+// C <- H^T C = C - V (T^T (V^T C)), is the paper's Apply_left_Qt_of_dense_QR
+// (Section II-C) and the whole of the trailing update and of Q^T B.  It needs
+// two product shapes, both column-major:
+//
+//   TN:  Out (M x N) = alpha * A^T B + beta * Out,  A: K x M,  B: K x N
+//        (W = V^T C and W' = T^T W; the reduction runs down the columns, i.e.
+//        along contiguous memory, for both operands; split over K when the
+//        output has too few tiles to fill the chip)
+//   NN:  C (M x N) += alpha * A B,                  A: M x K,  B: K x N
+//        (C -= V W', the rank-nb update, and the block back substitution)
+//
+// Either operand that is a Householder block V (unit lower trapezoidal: 1 on
+// its diagonal, 0 above, the stored vector below) is read straight out of the
+// factored matrix with that structure applied while loading, so no separate
+// copy of V is kept.
+//
+// Tiling (gfx950, 64-wide waves): a 256-thread workgroup owns a 128 x 128
+// output tile, each of its 4 waves a 64 x 64 sub-tile built from MFMA blocks
+// (FP32: v_mfma_f32_32x32x2f32, FP64: v_mfma_f64_16x16x4f64).  The k-step is
+// 128 bytes of every operand column (32 floats / 16 doubles), staged through
+// double-buffered LDS from 16-byte coalesced global loads.  The MFMA output is
+// computed transposed, so that the 32 (FP32) or 16 (FP64) lanes that share an
+// output column hold consecutive rows of the column-major result and its
+// stores coalesce.  Within a k-group the k index a lane feeds to successive
+// MFMAs is permuted (k = 4*slot + s) so each lane fetches 4 consecutive k
+// values with one LDS read; the sum over k is unchanged.  Workgroup ids are
+// remapped so the tiles one XCD runs are neighbours (shared L2 lines).
+#include "common.h"
+#include "kernels.h"
+
+namespace {
+
+constexpr int TILE = 128;     // output tile edge
+constexpr int NTHR = 256;     // threads per workgroup
+constexpr int GROUP_M = 8;    // row tiles per group in the tile order
+
+template <typename T> struct Mf;
+template <> struct Mf<float> {
+    static constexpr int BK = 32;      // k per LDS stage (128 bytes)
+    static constexpr int MB = 32;      // MFMA block edge
+    static constexpr int NBLK = 2;     // MFMA blocks per wave edge (64/MB)
+    static constexpr int SLOTS = 2;    // lanes groups sharing a row (64/MB)
+    static constexpr int KG = 8;       // k per group of 4 MFMAs
+    static constexpr int PAD_KC = 4;   // LDS pad (elements) of [col][k] tiles
+    static constexpr int PAD_MK = 8;   // LDS pad (elements) of [k][row] tiles
+    using acc_t = floatx16;
+};
+template <> struct Mf<double> {
+    static constexpr int BK = 16;
+    static constexpr int MB = 16;
+    static constexpr int NBLK = 4;
+    static constexpr int SLOTS = 4;
+    static constexpr int KG = 16;
+    static constexpr int PAD_KC = 2;
+    static constexpr int PAD_MK = 4;
+    using acc_t = doublex4;
+};
+
+__device__ inline floatx16 mfma(float a, float b, floatx16 c)
+{
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+__device__ inline doublex4 mfma(double a, double b, doublex4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Maps blockIdx.x to an output tile: XCD-contiguous ranges of logical ids,
+// then GROUP_M row tiles sweeping across the column tiles.
+__device__ inline void tile_of_block(int tiles_m, int tiles_n, int &tm, int &tn)
+{
+    int total = tiles_m * tiles_n;
+    int id = blockIdx.x;
+    int per = total / 8;
+    if (id < per * 8) id = (id % 8) * per + id / 8;
+    int span = GROUP_M * tiles_n;
+    int group = id / span;
+    int first = group * GROUP_M;
+    int gsize = min(tiles_m - first, GROUP_M);
+    int in = id - group * span;
+    tm = first + in % gsize;
+    tn = in / gsize;
+}
+
+// Value of a unit-lower-trapezoidal Householder block at (row, col).
+template <typename T>
+__device__ inline T vmask(T stored, int row, int col)
+{
+    return row > col ? stored : (row == col ? T(1) : T(0));
+}
+
+// 16-byte global chunk of `E` elements of one column, rows [k, k+E), with rows
+// >= kmax zeroed.  ptr points at element (k, col).  E = 4 (float) or 2 (double).
+template <typename T>
+struct Chunk16 {
+    static constexpr int E = 16 / sizeof(T);
+    T v[E];
+};
+
+template <typename T>
+__device__ inline Chunk16<T> load_chunk(const T *ptr, int k, int kmax, bool colok)
+{
+    Chunk16<T> c;
+    if (colok && k < kmax) {
+        if constexpr (sizeof(T) == 4) {
+            floatx4 x = *reinterpret_cast<const floatx4 *>(ptr);
+            c.v[0] = x[0]; c.v[1] = x[1]; c.v[2] = x[2]; c.v[3] = x[3];
+        } else {
+            doublex2 x = *reinterpret_cast<const doublex2 *>(ptr);
+            c.v[0] = x[0]; c.v[1] = x[1];
+        }
+#pragma unroll
+        for (int e = 0; e < Chunk16<T>::E; ++e)
+            if (k + e >= kmax) c.v[e] = T(0);
+    } else {
+#pragma unroll
+        for (int e = 0; e < Chunk16<T>::E; ++e) c.v[e] = T(0);
+    }
+    return c;
+}
+
+template <typename T>
+__device__ inline void store_chunk_lds(T *dst, const Chunk16<T> &c)
+{
+    if constexpr (sizeof(T) == 4) {
+        floatx4 x = {c.v[0], c.v[1], c.v[2], c.v[3]};
+        *reinterpret_cast<floatx4 *>(dst) = x;
+    } else {
+        doublex2 x = {c.v[0], c.v[1]};
+        *reinterpret_cast<doublex2 *>(dst) = x;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Loader of a 128-column x BK tile whose columns are contiguous in k
+// ("[col][k]" LDS layout, padded), used for both TN operands and for the B
+// operand of NN.  Column c of the tile is operand column col0 + c, rows
+// k0 .. k0+BK-1.  mask_cols > 0 marks the first mask_cols operand columns as
+// a Householder block (diagonal at row == column).
+// ---------------------------------------------------------------------------
+template <typename T>
+struct KcTile {
+    static constexpr int BK = Mf<T>::BK;
+    static constexpr int LD = BK + Mf<T>::PAD_KC;
+    static constexpr int E = 16 / sizeof(T);
+    static constexpr int CPC = BK / E;                 // chunks per column (8)
+    static constexpr int PER_THR = TILE * CPC / NTHR;  // 4
+    Chunk16<T> r[PER_THR];
+
+    __device__ inline void load(const T *P, int64_t ld, int ncols, int col0, int k0, int kmax,
+                                int mask_cols)
+    {
+#pragma unroll
+        for (int q = 0; q < PER_THR; ++q) {
+            int f = threadIdx.x + NTHR * q;
+            int c = f / CPC, h = f % CPC;
+            int col = col0 + c, k = k0 + h * E;
+            bool ok = col < ncols;
+            r[q] = load_chunk(P + (int64_t)col * ld + k, k, kmax, ok);
+            if (col < mask_cols && k < mask_cols + E) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) r[q].v[e] = vmask(r[q].v[e], k + e, col);
+            }
+        }
+    }
+    __device__ inline void store(T *lds) const
+    {
+#pragma unroll
+        for (int q = 0; q < PER_THR; ++q) {
+            int f = threadIdx.x + NTHR * q;
+            int c = f / CPC, h = f % CPC;
+            store_chunk_lds(lds + c * LD + h * E, r[q]);
+        }
+    }
+};
+
+// Loader of a BK-column x 128-row tile of a column-major M x K operand
+// ("[k][row]" LDS layout), the A operand of NN.  mask: operand is a
+// Householder block (value at (row, k) is 1 on row == k, 0 above).
+template <typename T>
+struct MkTile {
+    static constexpr int BK = Mf<T>::BK;
+    static constexpr int LD = TILE + Mf<T>::PAD_MK;
+    static constexpr int E = 16 / sizeof(T);
+    static constexpr int CPC = TILE / E;                // chunks per column (32/64)
+    static constexpr int PER_THR = BK * CPC / NTHR;     // 4
+    Chunk16<T> r[PER_THR];
+
+    __device__ inline void load(const T *P, int64_t ld, int mrows, int row0, int k0, int kmax,
+                                bool mask)
+    {
+#pragma unroll
+        for (int q = 0; q < PER_THR; ++q) {
+            int f = threadIdx.x + NTHR * q;
+            int kk = f / CPC, h = f % CPC;
+            int k = k0 + kk, row = row0 + h * E;
+            bool ok = k < kmax;
+            r[q] = load_chunk(P + (int64_t)k * ld + row, row, mrows, ok);
+            if (mask && row < k + E) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) r[q].v[e] = vmask(r[q].v[e], row + e, k);
+            }
+        }
+    }
+    __device__ inline void store(T *lds) const
+    {
+#pragma unroll
+        for (int q = 0; q < PER_THR; ++q) {
+            int f = threadIdx.x + NTHR * q;
+            int kk = f / CPC, h = f % CPC;
+            store_chunk_lds(lds + kk * LD + h * E, r[q]);
+        }
+    }
+};
+
+// One BK-deep step of a wave's 64x64 MFMA accumulation from LDS.
+// opA: [n][k] tile (MFMA rows = output columns n), opB: [m][k] tile when
+// B_KC (TN) or [k][m] tile otherwise (NN).  Output block (ib, jb) covers
+// output columns wn + ib*MB .. and rows wm + jb*MB ..
+template <typename T, bool B_KC>
+__device__ inline void mfma_step(const T *opA, const T *opB, int wn, int wm,
+                                 typename Mf<T>::acc_t (&acc)[Mf<T>::NBLK][Mf<T>::NBLK])
+{
+    using M = Mf<T>;
+    const int lane = threadIdx.x % CTQR_WAVE;
+    const int li = lane % M::MB, slot = lane / M::MB;
+    if constexpr (sizeof(T) == 8) {
+        // FP64: 4x4 blocks; fetch two k values per operand at a time to keep
+        // the register footprint inside two waves per SIMD.
+        const int kk = 4 * slot;
+#pragma unroll
+        for (int sp = 0; sp < 2; ++sp) {
+            doublex2 a[M::NBLK], b[M::NBLK];
+#pragma unroll
+            for (int ib = 0; ib < M::NBLK; ++ib)
+                a[ib] = *reinterpret_cast<const doublex2 *>(opA + (wn + ib * M::MB + li) * KcTile<T>::LD + kk + 2 * sp);
+#pragma unroll
+            for (int jb = 0; jb < M::NBLK; ++jb) {
+                if constexpr (B_KC) {
+                    b[jb] = *reinterpret_cast<const doublex2 *>(opB + (wm + jb * M::MB + li) * KcTile<T>::LD + kk + 2 * sp);
+                } else {
+                    const T *p = opB + (kk + 2 * sp) * MkTile<T>::LD + wm + jb * M::MB + li;
+                    b[jb][0] = p[0];
+                    b[jb][1] = p[MkTile<T>::LD];
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+#pragma unroll
+                for (int ib = 0; ib < M::NBLK; ++ib)
+#pragma unroll
+                    for (int jb = 0; jb < M::NBLK; ++jb)
+                        acc[ib][jb] = mfma(a[ib][s], b[jb][s], acc[ib][jb]);
+        }
+        return;
+    }
+#pragma unroll
+    for (int kg = 0; kg < M::BK; kg += M::KG) {
+        T a[M::NBLK][4], b[M::NBLK][4];
+        const int kk = kg + 4 * slot;
+#pragma unroll
+        for (int ib = 0; ib < M::NBLK; ++ib) {
+            const T *p = opA + (wn + ib * M::MB + li) * KcTile<T>::LD + kk;
+            if constexpr (sizeof(T) == 4) {
+                floatx4 x = *reinterpret_cast<const floatx4 *>(p);
+                a[ib][0] = x[0]; a[ib][1] = x[1]; a[ib][2] = x[2]; a[ib][3] = x[3];
+            } else {
+                doublex2 x = *reinterpret_cast<const doublex2 *>(p);
+                doublex2 y = *reinterpret_cast<const doublex2 *>(p + 2);
+                a[ib][0] = x[0]; a[ib][1] = x[1]; a[ib][2] = y[0]; a[ib][3] = y[1];
+            }
+        }
+#pragma unroll
+        for (int jb = 0; jb < M::NBLK; ++jb) {
+            if constexpr (B_KC) {
+                const T *p = opB + (wm + jb * M::MB + li) * KcTile<T>::LD + kk;
+                if constexpr (sizeof(T) == 4) {
+                    floatx4 x = *reinterpret_cast<const floatx4 *>(p);
+                    b[jb][0] = x[0]; b[jb][1] = x[1]; b[jb][2] = x[2]; b[jb][3] = x[3];
+                } else {
+                    doublex2 x = *reinterpret_cast<const doublex2 *>(p);
+                    doublex2 y = *reinterpret_cast<const doublex2 *>(p + 2);
+                    b[jb][0] = x[0]; b[jb][1] = x[1]; b[jb][2] = y[0]; b[jb][3] = y[1];
+                }
+            } else {
+                const T *p = opB + kk * MkTile<T>::LD + wm + jb * M::MB + li;
+#pragma unroll
+                for (int s = 0; s < 4; ++s) b[jb][s] = p[s * MkTile<T>::LD];
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int ib = 0; ib < M::NBLK; ++ib)
+#pragma unroll
+                for (int jb = 0; jb < M::NBLK; ++jb)
+                    acc[ib][jb] = mfma(a[ib][s], b[jb][s], acc[ib][jb]);
+    }
+}
+
+// Output coordinates of accumulator element r of block (ib, jb) for this lane:
+// output column (n) and row (m) offsets inside the wave's 64x64 sub-tile.
+template <typename T>
+__device__ inline void acc_coords(int ib, int jb, int r, int &n, int &m)
+{
+    using M = Mf<T>;
+    const int lane = threadIdx.x % CTQR_WAVE;
+    if constexpr (sizeof(T) == 4) {
+        n = ib * 32 + 8 * (r / 4) + 4 * (lane / 32) + (r % 4);
+        m = jb * 32 + lane % 32;
+    } else {
+        n = ib * 16 + 4 * (lane / 16) + r;
+        m = jb * 16 + lane % 16;
+    }
+    (void)sizeof(M);
+}
+
+template <typename T> constexpr int acc_len() { return sizeof(T) == 4 ? 16 : 4; }
+
+// ---------------------------------------------------------------------------
+// TN:  Out = alpha * A^T B + beta * Out   (or split-K partials)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(NTHR, 2)
+void gemm_tn_kernel(int M, int N, int K,
+                    const T *__restrict__ A, int64_t lda, int amask,
+                    const T *__restrict__ B, int64_t ldb, int bmask,
+                    T alpha, T beta, T *__restrict__ Out, int64_t ldo,
+                    T *__restrict__ part, int kchunk, const int *skip)
+{
+    using Mt = Mf<T>;
+    if (skip && *skip) return;
+    __shared__ __attribute__((aligned(16))) T sA[2][TILE * KcTile<T>::LD];
+    __shared__ __attribute__((aligned(16))) T sB[2][TILE * KcTile<T>::LD];
+
+    int tm, tn;
+    tile_of_block((M + TILE - 1) / TILE, (N + TILE - 1) / TILE, tm, tn);
+    const int m0 = tm * TILE, n0 = tn * TILE;
+    const int kbeg = blockIdx.z * kchunk;
+    const int kend = min(K, kbeg + kchunk);
+    const int wave = threadIdx.x / CTQR_WAVE;
+    const int wn = (wave / 2) * 64, wm = (wave % 2) * 64;
+
+    typename Mt::acc_t acc[Mt::NBLK][Mt::NBLK];
+#pragma unroll
+    for (int i = 0; i < Mt::NBLK; ++i)
+#pragma unroll
+        for (int j = 0; j < Mt::NBLK; ++j)
+#pragma unroll
+            for (int e = 0; e < acc_len<T>(); ++e) acc[i][j][e] = T(0);
+
+    KcTile<T> la, lb;
+    if (kbeg < kend) {
+        la.load(A, lda, M, m0, kbeg, kend, amask);
+        lb.load(B, ldb, N, n0, kbeg, kend, bmask);
+        la.store(sA[0]);
+        lb.store(sB[0]);
+    }
+    __syncthreads();
+    int cur = 0;
+    for (int k = kbeg; k < kend; k += Mt::BK) {
+        const bool more = k + Mt::BK < kend;
+        if (more) {
+            la.load(A, lda, M, m0, k + Mt::BK, kend, amask);
+            lb.load(B, ldb, N, n0, k + Mt::BK, kend, bmask);
+        }
+        mfma_step<T, true>(sB[cur], sA[cur], wn, wm, acc);
+        if (more) {
+            la.store(sA[cur ^ 1]);
+            lb.store(sB[cur ^ 1]);
+        }
+        __syncthreads();
+        cur ^= 1;
+    }
+
+    const bool split = gridDim.z > 1;
+#pragma unroll
+    for (int ib = 0; ib < Mt::NBLK; ++ib)
+#pragma unroll
+        for (int jb = 0; jb < Mt::NBLK; ++jb)
+#pragma unroll
+            for (int r = 0; r < acc_len<T>(); ++r) {
+                int n, m;
+                acc_coords<T>(ib, jb, r, n, m);
+                n += n0 + wn;
+                m += m0 + wm;
+                if (m < M && n < N) {
+                    T v = acc[ib][jb][r];
+                    if (split) {
+                        part[((int64_t)blockIdx.z * N + n) * M + m] = v;
+                    } else {
+                        T *o = Out + (int64_t)n * ldo + m;
+                        *o = beta == T(0) ? alpha * v : alpha * v + beta * *o;
+                    }
+                }
+            }
+}
+
+// Deterministic split-K reduction: Out = alpha * sum_z part[z] + beta * Out.
+template <typename T>
+__global__ void splitk_reduce_kernel(int M, int N, int splits, const T *__restrict__ part,
+                                     T alpha, T beta, T *__restrict__ Out, int64_t ldo,
+                                     const int *skip)
+{
+    if (skip && *skip) return;
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t total = (int64_t)M * N;
+    if (idx >= total) return;
+    int n = (int)(idx / M), m = (int)(idx % M);
+    T s = T(0);
+    for (int z = 0; z < splits; ++z) s += part[(int64_t)z * total + idx];
+    T *o = Out + (int64_t)n * ldo + m;
+    *o = beta == T(0) ? alpha * s : alpha * s + beta * *o;
+}
+
+// ---------------------------------------------------------------------------
+// NN:  C += alpha * A B   (A: M x K, optionally a Householder block; B: K x N)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(NTHR, 2)
+void gemm_nn_kernel(int M, int N, int K,
+                    const T *__restrict__ A, int64_t lda, int amask,
+                    const T *__restrict__ B, int64_t ldb,
+                    T alpha, T *__restrict__ C, int64_t ldc, const int *skip)
+{
+    using Mt = Mf<T>;
+    if (skip && *skip) return;
+    __shared__ __attribute__((aligned(16))) T sA[2][Mt::BK * MkTile<T>::LD];
+    __shared__ __attribute__((aligned(16))) T sB[2][TILE * KcTile<T>::LD];
+
+    int tm, tn;
+    tile_of_block((M + TILE - 1) / TILE, (N + TILE - 1) / TILE, tm, tn);
+    const int m0 = tm * TILE, n0 = tn * TILE;
+    const int wave = threadIdx.x / CTQR_WAVE;
+    const int wn = (wave / 2) * 64, wm = (wave % 2) * 64;
+
+    typename Mt::acc_t acc[Mt::NBLK][Mt::NBLK];
+#pragma unroll
+    for (int i = 0; i < Mt::NBLK; ++i)
+#pragma unroll
+        for (int j = 0; j < Mt::NBLK; ++j)
+#pragma unroll
+            for (int e = 0; e < acc_len<T>(); ++e) acc[i][j][e] = T(0);
+
+    MkTile<T> la;
+    KcTile<T> lb;
+    la.load(A, lda, M, m0, 0, K, amask != 0);
+    lb.load(B, ldb, N, n0, 0, K, 0);
+    la.store(sA[0]);
+    lb.store(sB[0]);
+    __syncthreads();
+    int cur = 0;
+    for (int k = 0; k < K; k += Mt::BK) {
+        const bool more = k + Mt::BK < K;
+        if (more) {
+            la.load(A, lda, M, m0, k + Mt::BK, K, amask != 0);
+            lb.load(B, ldb, N, n0, k + Mt::BK, K, 0);
+        }
+        mfma_step<T, false>(sB[cur], sA[cur], wn, wm, acc);
+        if (more) {
+            la.store(sA[cur ^ 1]);
+            lb.store(sB[cur ^ 1]);
+        }
+        __syncthreads();
+        cur ^= 1;
+    }
+
+#pragma unroll
+    for (int ib = 0; ib < Mt::NBLK; ++ib)
+#pragma unroll
+        for (int jb = 0; jb < Mt::NBLK; ++jb)
+#pragma unroll
+            for (int r = 0; r < acc_len<T>(); ++r) {
+                int n, m;
+                acc_coords<T>(ib, jb, r, n, m);
+                n += n0 + wn;
+                m += m0 + wm;
+                if (m < M && n < N) {
+                    T *c = C + (int64_t)n * ldc + m;
+                    *c += alpha * acc[ib][jb][r];
+                }
+            }
+}
+
+int g_num_cus = 0;
+
+int num_cus()
+{
+    if (g_num_cus == 0) {
+        int dev = 0;
+        hipDeviceProp_t p;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess)
+            g_num_cus = p.multiProcessorCount;
+        else
+            g_num_cus = 256;
+    }
+    return g_num_cus;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+size_t gemm_tn_partial_elems(int M, int N, int K)
+{
+    int splits = gemm_tn_splits(M, N, K);
+    return splits > 1 ? (size_t)splits * M * N : 0;
+}
+
+int gemm_tn_splits(int M, int N, int K)
+{
+    int64_t tiles = ceil_div(M, TILE) * ceil_div(N, TILE);
+    int target = 2 * num_cus();
+    if (tiles >= target) return 1;
+    int64_t splits = ceil_div(target, tiles);
+    int64_t max_by_k = K / (4 * 32);   // keep at least 4 k-steps per split
+    if (splits > max_by_k) splits = max_by_k;
+    if (splits < 1) splits = 1;
+    if (splits > 64) splits = 64;
+    return (int)splits;
+}
+
+template <typename T>
+ctqr_status gemm_tn(int M, int N, int K, const T *A, int64_t lda, int amask, const T *B,
+                    int64_t ldb, int bmask, T alpha, T beta, T *Out, int64_t ldo, T *part,
+                    size_t part_elems, const int *skip, hipStream_t st)
+{
+    if (M <= 0 || N <= 0) return CTQR_OK;
+    int splits = gemm_tn_splits(M, N, K);
+    if (splits > 1 && (part == nullptr || part_elems < (size_t)splits * M * N)) splits = 1;
+    int kchunk = (int)ceil_div(ceil_div(K, splits), Mf<T>::BK) * Mf<T>::BK;
+    if (kchunk <= 0) kchunk = Mf<T>::BK;
+    splits = (int)ceil_div(K > 0 ? K : 1, kchunk);
+    dim3 grid((unsigned)(ceil_div(M, TILE) * ceil_div(N, TILE)), 1, (unsigned)splits);
+    LAUNCH_TRY(gemm_tn_kernel<T>, grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B, ldb, bmask,
+               alpha, beta, Out, ldo, part, kchunk, skip);
+    if (splits > 1) {
+        int64_t total = (int64_t)M * N;
+        LAUNCH_TRY(splitk_reduce_kernel<T>, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, st,
+                   M, N, splits, part, alpha, beta, Out, ldo, skip);
+    }
+    return CTQR_OK;
+}
+
+template <typename T>
+ctqr_status gemm_nn(int M, int N, int K, const T *A, int64_t lda, int amask, const T *B,
+                    int64_t ldb, T alpha, T *C, int64_t ldc, const int *skip, hipStream_t st)
+{
+    if (M <= 0 || N <= 0 || K <= 0) return CTQR_OK;
+    dim3 grid((unsigned)(ceil_div(M, TILE) * ceil_div(N, TILE)));
+    LAUNCH_TRY(gemm_nn_kernel<T>, grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B, ldb, alpha,
+               C, ldc, skip);
+    return CTQR_OK;
+}
+
+template ctqr_status gemm_tn<float>(int, int, int, const float *, int64_t, int, const float *,
+                                    int64_t, int, float, float, float *, int64_t, float *, size_t,
+                                    const int *, hipStream_t);
+template ctqr_status gemm_tn<double>(int, int, int, const double *, int64_t, int, const double *,
+                                     int64_t, int, double, double, double *, int64_t, double *,
+                                     size_t, const int *, hipStream_t);
+template ctqr_status gemm_nn<float>(int, int, int, const float *, int64_t, int, const float *,
+                                    int64_t, float, float *, int64_t, const int *, hipStream_t);
+template ctqr_status gemm_nn<double>(int, int, int, const double *, int64_t, int, const double *,
+                                     int64_t, double, double *, int64_t, const int *, hipStream_t);

@@ -1,0 +1,79 @@
+// Host-side launchers of the libctqr kernels (internal interface).
+#pragma once
+#include "common.h"
+
+// ---- gemm.hip --------------------------------------------------------------
+int gemm_tn_splits(int M, int N, int K);
+size_t gemm_tn_partial_elems(int M, int N, int K);
+template <typename T>
+ctqr_status gemm_tn(int M, int N, int K, const T *A, int64_t lda, int amask, const T *B,
+                    int64_t ldb, int bmask, T alpha, T beta, T *Out, int64_t ldo, T *part,
+                    size_t part_elems, const int *skip, hipStream_t st);
+template <typename T>
+ctqr_status gemm_nn(int M, int N, int K, const T *A, int64_t lda, int amask, const T *B,
+                    int64_t ldb, T alpha, T *C, int64_t ldc, const int *skip, hipStream_t st);
+
+// ---- panel.hip -------------------------------------------------------------
+int panel_rows_per_wg(int mrem, int ncu);
+int panel_max_rows_per_wg();
+ctqr_status panel_setup(int max_rows);
+template <typename TS>
+ctqr_status panel_qr(TS *A, int64_t lda, int m, int r0, int w, double *tau, double *part,
+                     double *part2, double *gram_part, double *gram, unsigned *bar, ctqr_info *info,
+                     int ncu, hipStream_t st);
+template <typename TG, typename TT>
+ctqr_status tbuild(int nb, const TG *G, int64_t ldg, const double *tau, TT *T, int64_t ldt, double *Tw,
+                   hipStream_t st);
+
+// ---- trsm.hip --------------------------------------------------------------
+constexpr int TRSM_BT = 64;   // diagonal block of the block substitutions
+template <typename T>
+ctqr_status trinv_blocks(int n, const T *R, int64_t ldr, T *Rinv, T *RinvT, ctqr_info *info,
+                         hipStream_t st);
+template <typename T>
+ctqr_status trsm_upper(int n, int S, const T *R, int64_t ldr, const T *RinvT, T *C, int64_t ldc,
+                       T *X, int64_t ldx, T *part, size_t part_elems, const int *skip, hipStream_t st);
+template <typename T>
+ctqr_status trsm_upper_trans(int n, int S, const T *R, int64_t ldr, const T *Rinv, T *C, int64_t ldc,
+                             T *Y, int64_t ldy, T *part, size_t part_elems, const int *skip,
+                             hipStream_t st);
+template <typename T>
+ctqr_status rdiag_check(int n, const T *R, int64_t ldr, double *scratch, ctqr_info *info,
+                        hipStream_t st);
+
+// ---- siddon.hip ------------------------------------------------------------
+ctqr_status siddon_build(const ctqr_geometry *g, int dtype, void *A, int64_t lda, ctqr_sparse *sp,
+                         void *work, size_t work_bytes, ctqr_info *info, hipStream_t st);
+size_t siddon_workspace(const ctqr_geometry *g);
+
+// ---- sparse.hip / util ------------------------------------------------------
+// y[i, :] = alpha * sum_k val[k] x[idx[k], :] + beta * y[i, :] for rows i of a
+// compressed matrix (CSR or CSC), x and y row-major (slice index fastest).
+ctqr_status spmm_rowmajor(int64_t rows, int S, const int64_t *ptr, const int32_t *idx,
+                          const double *val, double alpha, const double *x, double beta,
+                          const double *y_in, double *y, const int *skip, hipStream_t st);
+ctqr_status spmm_colmajor(int64_t rows, int64_t cols, int S, const int64_t *ptr, const int32_t *idx,
+                          const double *val, double alpha, const double *X, int64_t ldx,
+                          double beta, double *Y, int64_t ldy, hipStream_t st);
+// dst (rows x S, column-major, ld) <-> row-major copies with type conversion
+template <typename TD, typename TSRC>
+ctqr_status cm_to_rm(int64_t rows, int S, const TSRC *src, int64_t lds, TD *dst, const int *skip,
+                     hipStream_t st);
+template <typename TD, typename TSRC>
+ctqr_status rm_to_cm(int64_t rows, int S, const TSRC *src, TD *dst, int64_t ldd, const int *skip,
+                     hipStream_t st);
+template <typename TD, typename TSRC>
+ctqr_status copy_cm(int64_t rows, int S, const TSRC *src, int64_t lds, TD *dst, int64_t ldd,
+                    hipStream_t st);
+ctqr_status fill_u32(unsigned *p, int64_t n, unsigned v, hipStream_t st);
+ctqr_status fill_f64(double *p, int64_t n, double v, hipStream_t st);
+ctqr_status info_reset(ctqr_info *info, hipStream_t st);
+// Refinement step: x += d (row-major x FP64, column-major d of type TD),
+// per-slice max|d| and max|x| into dmax/xmax (bit patterns, atomic max).
+template <typename TD>
+ctqr_status refine_update(int64_t n, int S, double *x, const TD *d, int64_t ldd,
+                          unsigned long long *dmax, unsigned long long *xmax, const int *skip,
+                          hipStream_t st);
+ctqr_status refine_check(int S, unsigned long long *dmax, unsigned long long *xmax, double tol,
+                         int it, int max_iters, double *hist, int *done, ctqr_info *info,
+                         hipStream_t st);

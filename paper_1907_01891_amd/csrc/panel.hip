@@ -1,0 +1,339 @@
+// Panel factorization and compact-WY T build.
+//
+// Panel (the paper's Compute_dense_QR applied to one block column,
+// Section II-C): unblocked Householder QR of a tall m_rem x w panel
+// (w <= 32).  The panel's rows are split into contiguous slabs, one per
+// workgroup, held in LDS in FP64 for the whole panel whatever the storage
+// precision.  For each column the workgroups exchange one partial sum of
+// squares (grid barrier 1), all of them form beta/tau/v identically, then
+// exchange the partial products v^T a_c for the columns to the right (grid
+// barrier 2) and update their slab.  Reflector convention (LAPACK larfg):
+// beta = -sign(alpha) ||[alpha; x]||, tau = (beta - alpha) / beta,
+// v = [1; x / (alpha - beta)]; tau = 0 when x = 0.  Every cross-workgroup sum
+// is taken in workgroup order, so the result is deterministic and identical
+// in every workgroup.  The kernel also leaves each workgroup's partial Gram
+// matrix V^T V of the panel for the T build.
+//
+// T build (the "S factors" of Section II-C): for H_1 ... H_w = I - V T V^T,
+// T is upper triangular with T_jj = tau_j and
+// T(0:j, j) = -tau_j T(0:j, 0:j) G(0:j, j), G = V^T V (the larft recurrence).
+// It runs in one workgroup: the 32 x 32 diagonal blocks by that recurrence,
+// then each further column block q by T(0:32q, q) = -T(0:32q, 0:32q)
+// (G(0:32q, q) T_qq), which is the same recurrence taken 32 columns at a time.
+#include "common.h"
+#include "kernels.h"
+
+namespace {
+
+constexpr int PNT = 256;          // threads per panel workgroup
+constexpr int PW = 32;            // max panel width
+constexpr int SLD = PW + 1;       // slab LDS row stride (doubles)
+
+__device__ inline double block_sum(double v, double *red)
+{
+    // Deterministic tree sum over the 256 threads of the workgroup.
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = PNT / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+template <typename TS>
+__global__ __launch_bounds__(PNT)
+void panel_qr_kernel(TS *__restrict__ A, int64_t lda, int m, int r0, int w, int rows_per_wg,
+                     double *__restrict__ tau_out, double *part, double *part2,
+                     double *__restrict__ gram_part, unsigned *bar, ctqr_info *info)
+{
+    extern __shared__ double slab[];              // rows_per_wg x SLD
+    __shared__ double red[PNT];
+    __shared__ double wred[8][PW];
+    __shared__ double wcol[PW];
+    __shared__ double tau_s[PW];
+
+    const int G = gridDim.x, wg = blockIdx.x, tid = threadIdx.x;
+    const int row0 = r0 + wg * rows_per_wg;
+    const int nrows = max(0, min(rows_per_wg, m - row0));
+    unsigned epoch = 0;
+
+    for (int idx = tid; idx < nrows * w; idx += PNT) {
+        int c = idx / nrows, rr = idx % nrows;
+        slab[rr * SLD + c] = (double)A[(int64_t)(r0 + c) * lda + row0 + rr];
+    }
+    __syncthreads();
+
+    bool nonfinite = false;
+    for (int j = 0; j < w; ++j) {
+        const int p = r0 + j;                     // pivot row
+        const int owner = (p - r0) / rows_per_wg;
+
+        // partial sum of squares below the pivot
+        double ss = 0.0;
+        for (int rr = tid; rr < nrows; rr += PNT)
+            if (row0 + rr > p) {
+                double x = slab[rr * SLD + j];
+                ss += x * x;
+            }
+        ss = block_sum(ss, red);
+        if (tid == 0) {
+            store_coherent(&part[wg], ss);
+            if (wg == owner) store_coherent(&part[G], slab[(p - row0) * SLD + j]);
+        }
+        grid_barrier(bar, epoch, info);
+
+        double tot = 0.0;
+        for (int q = tid; q < G; q += PNT) tot += load_coherent(&part[q]);
+        tot = block_sum(tot, red);
+        const double alpha = load_coherent(&part[G]);
+        double tau = 0.0, beta = alpha, scale = 1.0;
+        if (tot != 0.0) {
+            double norm = sqrt(alpha * alpha + tot);
+            beta = alpha >= 0.0 ? -norm : norm;
+            tau = (beta - alpha) / beta;
+            scale = 1.0 / (alpha - beta);
+        }
+        if (!(tot == tot) || !(alpha == alpha) || isinf(tot) || isinf(alpha)) nonfinite = true;
+        if (tid == 0) tau_s[j] = tau;
+
+        if (tau != 0.0)
+            for (int rr = tid; rr < nrows; rr += PNT)
+                if (row0 + rr > p) slab[rr * SLD + j] *= scale;
+        __syncthreads();
+
+        if (j + 1 < w) {
+            // partial w_c = sum_{g >= p} v_g a_gc, v_p = 1, for c > j
+            const int cl = tid % PW, rg = tid / PW;
+            const int c = j + 1 + cl;
+            double acc = 0.0;
+            if (c < w && tau != 0.0)
+                for (int rr = rg; rr < nrows; rr += PNT / PW) {
+                    int g = row0 + rr;
+                    if (g >= p) {
+                        double v = g == p ? 1.0 : slab[rr * SLD + j];
+                        acc += v * slab[rr * SLD + c];
+                    }
+                }
+            wred[rg][cl] = acc;
+            __syncthreads();
+            if (tid < PW) {
+                double s = 0.0;
+                for (int q = 0; q < PNT / PW; ++q) s += wred[q][tid];
+                if (j + 1 + tid < w) store_coherent(&part2[(int64_t)wg * PW + tid], s);
+            }
+            grid_barrier(bar, epoch, info);
+
+            // w_c = sum over workgroups, in workgroup order
+            {
+                double s = 0.0;
+                if (c < w)
+                    for (int q = rg; q < G; q += PNT / PW) s += load_coherent(&part2[(int64_t)q * PW + cl]);
+                wred[rg][cl] = s;
+                __syncthreads();
+                if (tid < PW) {
+                    double t = 0.0;
+                    for (int q = 0; q < PNT / PW; ++q) t += wred[q][tid];
+                    wcol[tid] = t * tau;
+                }
+                __syncthreads();
+            }
+            if (tau != 0.0) {
+                const int nc = w - j - 1;
+                for (int idx = tid; idx < nrows * nc; idx += PNT) {
+                    int rr = idx / nc, cc = j + 1 + idx % nc;
+                    int g = row0 + rr;
+                    if (g >= p) {
+                        double v = g == p ? 1.0 : slab[rr * SLD + j];
+                        slab[rr * SLD + cc] -= wcol[cc - j - 1] * v;
+                    }
+                }
+            }
+        }
+        if (wg == owner && tid == 0) slab[(p - row0) * SLD + j] = beta;
+        __syncthreads();
+    }
+
+    // write the factored slab back in storage precision
+    for (int idx = tid; idx < nrows * w; idx += PNT) {
+        int c = idx / nrows, rr = idx % nrows;
+        A[(int64_t)(r0 + c) * lda + row0 + rr] = (TS)slab[rr * SLD + c];
+    }
+    if (wg == 0 && tid < w) tau_out[tid] = tau_s[tid];
+    if (nonfinite && tid == 0 && wg == 0) info_event(info, CTQR_NONFINITE, r0);
+
+    // partial Gram V^T V over this slab (V unit lower trapezoidal), rounded to
+    // storage precision first so it describes the stored vectors
+    for (int e = tid; e < PW * PW; e += PNT) {
+        int c1 = e % PW, c2 = e / PW;
+        double s = 0.0;
+        if (c1 < w && c2 < w)
+            for (int rr = 0; rr < nrows; ++rr) {
+                int g = row0 + rr;
+                double v1 = g == r0 + c1 ? 1.0 : (g > r0 + c1 ? (double)(TS)slab[rr * SLD + c1] : 0.0);
+                double v2 = g == r0 + c2 ? 1.0 : (g > r0 + c2 ? (double)(TS)slab[rr * SLD + c2] : 0.0);
+                s += v1 * v2;
+            }
+        gram_part[(int64_t)wg * PW * PW + e] = s;
+    }
+}
+
+// Sum of the per-workgroup Gram partials, in workgroup order.
+__global__ void gram_reduce_kernel(int G, const double *__restrict__ gram_part, double *__restrict__ gram)
+{
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= PW * PW) return;
+    double s = 0.0;
+    for (int q = 0; q < G; ++q) s += gram_part[(int64_t)q * PW * PW + e];
+    gram[e] = s;
+}
+
+// T from G and tau; see the file comment.  Single workgroup of 256 threads.
+template <typename TG, typename TT>
+__global__ __launch_bounds__(256)
+void tbuild_kernel(int nb, const TG *__restrict__ Gm, int64_t ldg, const double *__restrict__ tau,
+                   TT *__restrict__ Tout, int64_t ldt, double *__restrict__ Tw)
+{
+    __shared__ double buf[8 * 32 * 32];            // 64 KB: G blocks, later Y and T_qq
+    const int tid = threadIdx.x;
+    const int nq = (nb + 31) / 32;
+
+    // Stage 1: diagonal blocks, one 32-thread group per block
+    for (int e = tid; e < nq * 1024; e += 256) {
+        int q = e / 1024, c = (e % 1024) % 32, j = (e % 1024) / 32;
+        int gc = 32 * q + c, gj = 32 * q + j;
+        buf[e] = (gc < nb && gj < nb) ? (double)Gm[(int64_t)gj * ldg + gc] : 0.0;
+    }
+    __syncthreads();
+    {
+        const int q = tid / 32, r = tid % 32;
+        if (q < nq) {
+            const double *Gq = buf + q * 1024;         // Gq[j*32 + c] = G(32q+c, 32q+j)
+            double t[32];
+            const int gi = 32 * q + r;
+#pragma unroll
+            for (int j = 0; j < 32; ++j) {
+                const int gj = 32 * q + j;
+                double val;
+                if (gj >= nb || gi >= nb || j < r) {
+                    val = 0.0;
+                } else if (j == r) {
+                    val = tau[gj];
+                } else {
+                    double s = 0.0;
+#pragma unroll
+                    for (int c = 0; c < j; ++c) s += t[c] * Gq[j * 32 + c];
+                    val = -tau[gj] * s;
+                }
+                t[j] = val;
+            }
+#pragma unroll
+            for (int j = 0; j < 32; ++j) {
+                const int gj = 32 * q + j;
+                if (gi < nb && gj < nb) Tw[(int64_t)gj * nb + gi] = t[j];
+            }
+        }
+    }
+    // zero the strictly lower block part
+    for (int e = tid; e < nb * nb; e += 256) {
+        int i = e % nb, j = e / nb;
+        if (i / 32 > j / 32) Tw[e] = 0.0;
+    }
+    __threadfence_block();
+    __syncthreads();
+
+    // Stage 2: column blocks q >= 1
+    double *Y = buf;                    // 32q x 32, Y[c*rows + i]
+    double *Tqq = buf + 7 * 1024;       // 32 x 32, Tqq[j*32 + i]
+    for (int q = 1; q < nq; ++q) {
+        const int rows = 32 * q;
+        const int qc = min(32, nb - rows);
+        for (int e = tid; e < 1024; e += 256) {
+            int i = e % 32, j = e / 32;
+            Tqq[e] = (i < qc && j < qc) ? Tw[(int64_t)(rows + j) * nb + rows + i] : 0.0;
+        }
+        __syncthreads();
+        // Y = G(0:rows, q-block) * T_qq
+        for (int e = tid; e < rows * 32; e += 256) {
+            int i = e % rows, c = e / rows;
+            double s = 0.0;
+            if (c < qc)
+                for (int k = 0; k <= c; ++k)
+                    s += (double)Gm[(int64_t)(rows + k) * ldg + i] * Tqq[c * 32 + k];
+            Y[c * rows + i] = s;
+        }
+        __syncthreads();
+        // X = -T(0:rows, 0:rows) * Y  (T upper triangular)
+        for (int e = tid; e < rows * 32; e += 256) {
+            int i = e % rows, c = e / rows;
+            if (c < qc) {
+                double s = 0.0;
+                for (int k = i; k < rows; ++k) s += Tw[(int64_t)k * nb + i] * Y[c * rows + k];
+                Tw[(int64_t)(rows + c) * nb + i] = -s;
+            }
+        }
+        __threadfence_block();
+        __syncthreads();
+    }
+    for (int e = tid; e < nb * nb; e += 256) Tout[(int64_t)(e / nb) * ldt + e % nb] = (TT)Tw[e];
+}
+
+}  // namespace
+
+int panel_rows_per_wg(int mrem, int ncu)
+{
+    int rows = (int)ceil_div(mrem, ncu);
+    if (rows < 64) rows = 64;
+    return rows;
+}
+
+size_t panel_lds_bytes(int rows_per_wg) { return (size_t)rows_per_wg * SLD * sizeof(double); }
+
+int panel_max_rows_per_wg() { return (int)((144 * 1024) / (SLD * sizeof(double))); }
+
+template <typename TS>
+ctqr_status panel_qr(TS *A, int64_t lda, int m, int r0, int w, double *tau, double *part,
+                     double *part2, double *gram_part, double *gram, unsigned *bar, ctqr_info *info,
+                     int ncu, hipStream_t st)
+{
+    const int mrem = m - r0;
+    const int rows = panel_rows_per_wg(mrem, ncu);
+    if (rows > panel_max_rows_per_wg()) return CTQR_EUNSUPPORTED;
+    const int G = (int)ceil_div(mrem, rows);
+    const size_t lds = panel_lds_bytes(rows);
+    void *args[] = {&A, (void *)&lda, &m, &r0, &w, (void *)&rows, &tau, &part, &part2, &gram_part, &bar, &info};
+    HIP_TRY(hipLaunchCooperativeKernel((const void *)panel_qr_kernel<TS>, dim3(G), dim3(PNT), args, lds, st));
+    LAUNCH_TRY(gram_reduce_kernel, dim3(4), dim3(256), 0, st, G, (const double *)gram_part, gram);
+    return CTQR_OK;
+}
+
+ctqr_status panel_setup(int max_rows)
+{
+    size_t lds = panel_lds_bytes(max_rows);
+    HIP_TRY(hipFuncSetAttribute((const void *)panel_qr_kernel<float>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    HIP_TRY(hipFuncSetAttribute((const void *)panel_qr_kernel<double>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    return CTQR_OK;
+}
+
+template <typename TG, typename TT>
+ctqr_status tbuild(int nb, const TG *G, int64_t ldg, const double *tau, TT *T, int64_t ldt, double *Tw,
+                   hipStream_t st)
+{
+    LAUNCH_TRY((tbuild_kernel<TG, TT>), dim3(1), dim3(256), 0, st, nb, G, ldg, tau, T, ldt, Tw);
+    return CTQR_OK;
+}
+
+template ctqr_status panel_qr<float>(float *, int64_t, int, int, int, double *, double *, double *,
+                                     double *, double *, unsigned *, ctqr_info *, int, hipStream_t);
+template ctqr_status panel_qr<double>(double *, int64_t, int, int, int, double *, double *, double *,
+                                      double *, double *, unsigned *, ctqr_info *, int, hipStream_t);
+template ctqr_status tbuild<double, float>(int, const double *, int64_t, const double *, float *, int64_t,
+                                           double *, hipStream_t);
+template ctqr_status tbuild<double, double>(int, const double *, int64_t, const double *, double *, int64_t,
+                                            double *, hipStream_t);
+template ctqr_status tbuild<float, float>(int, const float *, int64_t, const double *, float *, int64_t,
+                                          double *, hipStream_t);

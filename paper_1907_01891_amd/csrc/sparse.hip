@@ -1,0 +1,340 @@
+// FP64 sparse products with the Siddon matrix, layout conversions and the
+// refinement bookkeeping kernels.
+//
+// The refinement (corrected semi-normal equations) needs r = B - A X and
+// s = A^T r in FP64 with the exact sparse A.  Both are gathers: rows of the
+// CSR for A X, rows of the CSC (= columns of A) for A^T r, with the slice
+// vectors stored row-major (slice index fastest) so that the lanes of a
+// workgroup read one contiguous row of X per nonzero.
+#include "common.h"
+#include "kernels.h"
+
+namespace {
+
+// y[i, s] = alpha * sum_k val[k] x[idx[k], s] + beta * y_in[i, s]
+// Workgroup of 256 threads: SW = min(256, S rounded up to 64) threads per row.
+__global__ __launch_bounds__(256)
+void spmm_rm_kernel(int64_t rows, int S, int SW, const int64_t *__restrict__ ptr,
+                    const int32_t *__restrict__ idx, const double *__restrict__ val, double alpha,
+                    const double *__restrict__ x, double beta, const double *__restrict__ y_in,
+                    double *__restrict__ y, const int *skip)
+{
+    if (skip && *skip) return;
+    const int rpb = 256 / SW;
+    const int64_t i = (int64_t)blockIdx.x * rpb + threadIdx.x / SW;
+    const int lane = threadIdx.x % SW;
+    if (i >= rows) return;
+    const int64_t b = ptr[i], e = ptr[i + 1];
+    for (int s0 = 0; s0 < S; s0 += SW) {
+        const int s = s0 + lane;
+        if (s >= S) break;
+        double acc = 0.0;
+        for (int64_t k = b; k < e; ++k) acc += val[k] * x[(int64_t)idx[k] * S + s];
+        double out = alpha * acc;
+        if (beta != 0.0) out += beta * y_in[i * S + s];
+        y[i * S + s] = out;
+    }
+}
+
+// Column-major variant for the public helper: thread per (row, slice).
+__global__ void spmm_cm_kernel(int64_t rows, int S, const int64_t *__restrict__ ptr,
+                               const int32_t *__restrict__ idx, const double *__restrict__ val,
+                               double alpha, const double *__restrict__ X, int64_t ldx, double beta,
+                               double *__restrict__ Y, int64_t ldy)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = blockIdx.y;
+    if (i >= rows) return;
+    double acc = 0.0;
+    for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k) acc += val[k] * X[(int64_t)s * ldx + idx[k]];
+    double *o = Y + (int64_t)s * ldy + i;
+    *o = beta == 0.0 ? alpha * acc : alpha * acc + beta * *o;
+}
+
+// Tiled transposes between column-major (rows x S, ld) and row-major (rows x S).
+template <typename TD, typename TSRC>
+__global__ void cm_to_rm_kernel(int64_t rows, int S, const TSRC *__restrict__ src, int64_t lds,
+                                TD *__restrict__ dst, const int *skip)
+{
+    if (skip && *skip) return;
+    __shared__ double t[32][33];
+    const int64_t r0 = (int64_t)blockIdx.x * 32;
+    const int s0 = blockIdx.y * 32;
+    for (int k = threadIdx.y; k < 32; k += 8) {
+        int64_t r = r0 + threadIdx.x;
+        int s = s0 + k;
+        t[k][threadIdx.x] = (r < rows && s < S) ? (double)src[(int64_t)s * lds + r] : 0.0;
+    }
+    __syncthreads();
+    for (int k = threadIdx.y; k < 32; k += 8) {
+        int64_t r = r0 + k;
+        int s = s0 + threadIdx.x;
+        if (r < rows && s < S) dst[r * S + s] = (TD)t[threadIdx.x][k];
+    }
+}
+
+template <typename TD, typename TSRC>
+__global__ void rm_to_cm_kernel(int64_t rows, int S, const TSRC *__restrict__ src,
+                                TD *__restrict__ dst, int64_t ldd, const int *skip)
+{
+    if (skip && *skip) return;
+    __shared__ double t[32][33];
+    const int64_t r0 = (int64_t)blockIdx.x * 32;
+    const int s0 = blockIdx.y * 32;
+    for (int k = threadIdx.y; k < 32; k += 8) {
+        int64_t r = r0 + k;
+        int s = s0 + threadIdx.x;
+        t[k][threadIdx.x] = (r < rows && s < S) ? (double)src[r * S + s] : 0.0;
+    }
+    __syncthreads();
+    for (int k = threadIdx.y; k < 32; k += 8) {
+        int64_t r = r0 + threadIdx.x;
+        int s = s0 + k;
+        if (r < rows && s < S) dst[(int64_t)s * ldd + r] = (TD)t[threadIdx.x][k];
+    }
+}
+
+template <typename TD, typename TSRC>
+__global__ void copy_cm_kernel(int64_t rows, int S, const TSRC *__restrict__ src, int64_t lds,
+                               TD *__restrict__ dst, int64_t ldd)
+{
+    const int s = blockIdx.y;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < rows;
+         r += (int64_t)gridDim.x * blockDim.x)
+        dst[(int64_t)s * ldd + r] = (TD)src[(int64_t)s * lds + r];
+}
+
+__global__ void fill_u32_kernel(unsigned *p, int64_t n, unsigned v)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * blockDim.x)
+        p[e] = v;
+}
+
+__global__ void fill_f64_kernel(double *p, int64_t n, double v)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * blockDim.x)
+        p[e] = v;
+}
+
+__global__ void info_reset_kernel(ctqr_info *info)
+{
+    info->status = 0;
+    info->first_bad_col = -1;
+    info->iters = 0;
+    info->pad = 0;
+    info->max_rel_update = 0.0;
+    info->rdiag_max = 0.0;
+    info->rdiag_min = 0.0;
+    info->nnz = 0;
+}
+
+// Non-negative doubles order like their bit patterns; NaN maps to all ones.
+__device__ inline unsigned long long order_bits(double v)
+{
+    v = fabs(v);
+    return v == v ? (unsigned long long)__double_as_longlong(v) : ~0ull;
+}
+
+template <typename TD>
+__global__ void refine_update_kernel(int64_t n, int S, double *__restrict__ x, const TD *__restrict__ d,
+                                     int64_t ldd, unsigned long long *dmax, unsigned long long *xmax,
+                                     const int *skip)
+{
+    if (skip && *skip) return;
+    __shared__ double t[32][33];
+    const int64_t r0 = (int64_t)blockIdx.x * 32;
+    const int s0 = blockIdx.y * 32;
+    for (int k = threadIdx.y; k < 32; k += 8) {
+        int64_t r = r0 + threadIdx.x;
+        int s = s0 + k;
+        t[k][threadIdx.x] = (r < n && s < S) ? (double)d[(int64_t)s * ldd + r] : 0.0;
+    }
+    __syncthreads();
+    unsigned long long dm = 0, xm = 0;
+    const int s = s0 + threadIdx.x;
+    for (int k = threadIdx.y; k < 32; k += 8) {
+        int64_t r = r0 + k;
+        if (r < n && s < S) {
+            double dv = t[threadIdx.x][k];
+            double xv = x[r * S + s] + dv;
+            x[r * S + s] = xv;
+            unsigned long long a = order_bits(dv), b = order_bits(xv);
+            dm = a > dm ? a : dm;
+            xm = b > xm ? b : xm;
+        }
+    }
+    if (s < S) {
+        atomicMax(&dmax[s], dm);
+        atomicMax(&xmax[s], xm);
+    }
+}
+
+// Decide convergence after refinement iteration `it` (0-based) and reset the
+// per-slice maxima for the next one.  hist[0] keeps the previous relative
+// update, hist[1] the number of consecutive non-contracting iterations.
+__global__ __launch_bounds__(256)
+void refine_check_kernel(int S, unsigned long long *dmax, unsigned long long *xmax, double tol, int it,
+                         int max_iters, double *hist, int *done, ctqr_info *info)
+{
+    if (*done) return;
+    __shared__ double red[256];
+    double worst = 0.0;
+    bool bad = false;
+    for (int s = threadIdx.x; s < S; s += 256) {
+        unsigned long long a = dmax[s], b = xmax[s];
+        if (a == ~0ull || b == ~0ull) { bad = true; continue; }
+        double dv = __longlong_as_double((long long)a), xv = __longlong_as_double((long long)b);
+        double rel = xv > 0.0 ? dv / xv : (dv > 0.0 ? INFINITY : 0.0);
+        worst = fmax(worst, rel);
+    }
+    red[threadIdx.x] = bad ? INFINITY : worst;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + k]);
+        __syncthreads();
+    }
+    for (int s = threadIdx.x; s < S; s += 256) {
+        dmax[s] = 0;
+        xmax[s] = 0;
+    }
+    if (threadIdx.x == 0) {
+        double rel = red[0];
+        info->iters = it + 1;
+        info->max_rel_update = rel;
+        if (!(rel <= 1e300)) {
+            info_event(info, CTQR_NONFINITE, -1);
+            *done = 1;
+        } else if (rel <= tol) {
+            *done = 1;
+        } else {
+            double prev = hist[0];
+            int stalls = (it > 0 && rel > 0.9 * prev) ? (int)hist[1] + 1 : 0;
+            hist[0] = rel;
+            hist[1] = stalls;
+            if (stalls >= 2 || it + 1 >= max_iters) {
+                info_event(info, CTQR_NOT_CONVERGED, -1);
+                *done = 1;
+            }
+        }
+    }
+}
+
+}  // namespace
+
+ctqr_status spmm_rowmajor(int64_t rows, int S, const int64_t *ptr, const int32_t *idx,
+                          const double *val, double alpha, const double *x, double beta,
+                          const double *y_in, double *y, const int *skip, hipStream_t st)
+{
+    if (rows <= 0 || S <= 0) return CTQR_OK;
+    int SW = (int)std::min<int64_t>(256, ceil_div(S, 64) * 64);
+    int rpb = 256 / SW;
+    LAUNCH_TRY(spmm_rm_kernel, dim3((unsigned)ceil_div(rows, rpb)), dim3(256), 0, st, rows, S, SW, ptr,
+               idx, val, alpha, x, beta, y_in, y, skip);
+    return CTQR_OK;
+}
+
+ctqr_status spmm_colmajor(int64_t rows, int64_t cols, int S, const int64_t *ptr, const int32_t *idx,
+                          const double *val, double alpha, const double *X, int64_t ldx,
+                          double beta, double *Y, int64_t ldy, hipStream_t st)
+{
+    (void)cols;
+    if (rows <= 0 || S <= 0) return CTQR_OK;
+    LAUNCH_TRY(spmm_cm_kernel, dim3((unsigned)ceil_div(rows, 256), (unsigned)S), dim3(256), 0, st, rows,
+               S, ptr, idx, val, alpha, X, ldx, beta, Y, ldy);
+    return CTQR_OK;
+}
+
+template <typename TD, typename TSRC>
+ctqr_status cm_to_rm(int64_t rows, int S, const TSRC *src, int64_t lds, TD *dst, const int *skip,
+                     hipStream_t st)
+{
+    if (rows <= 0 || S <= 0) return CTQR_OK;
+    LAUNCH_TRY((cm_to_rm_kernel<TD, TSRC>), dim3((unsigned)ceil_div(rows, 32), (unsigned)ceil_div(S, 32)),
+               dim3(32, 8), 0, st, rows, S, src, lds, dst, skip);
+    return CTQR_OK;
+}
+
+template <typename TD, typename TSRC>
+ctqr_status rm_to_cm(int64_t rows, int S, const TSRC *src, TD *dst, int64_t ldd, const int *skip,
+                     hipStream_t st)
+{
+    if (rows <= 0 || S <= 0) return CTQR_OK;
+    LAUNCH_TRY((rm_to_cm_kernel<TD, TSRC>), dim3((unsigned)ceil_div(rows, 32), (unsigned)ceil_div(S, 32)),
+               dim3(32, 8), 0, st, rows, S, src, dst, ldd, skip);
+    return CTQR_OK;
+}
+
+template <typename TD, typename TSRC>
+ctqr_status copy_cm(int64_t rows, int S, const TSRC *src, int64_t lds, TD *dst, int64_t ldd,
+                    hipStream_t st)
+{
+    if (rows <= 0 || S <= 0) return CTQR_OK;
+    unsigned gx = (unsigned)std::min<int64_t>(ceil_div(rows, 256), 4096);
+    LAUNCH_TRY((copy_cm_kernel<TD, TSRC>), dim3(gx, (unsigned)S), dim3(256), 0, st, rows, S, src, lds,
+               dst, ldd);
+    return CTQR_OK;
+}
+
+ctqr_status fill_u32(unsigned *p, int64_t n, unsigned v, hipStream_t st)
+{
+    if (n <= 0) return CTQR_OK;
+    unsigned g = (unsigned)std::min<int64_t>(ceil_div(n, 256), 4096);
+    LAUNCH_TRY(fill_u32_kernel, dim3(g), dim3(256), 0, st, p, n, v);
+    return CTQR_OK;
+}
+
+ctqr_status fill_f64(double *p, int64_t n, double v, hipStream_t st)
+{
+    if (n <= 0) return CTQR_OK;
+    unsigned g = (unsigned)std::min<int64_t>(ceil_div(n, 256), 4096);
+    LAUNCH_TRY(fill_f64_kernel, dim3(g), dim3(256), 0, st, p, n, v);
+    return CTQR_OK;
+}
+
+ctqr_status info_reset(ctqr_info *info, hipStream_t st)
+{
+    LAUNCH_TRY(info_reset_kernel, dim3(1), dim3(1), 0, st, info);
+    return CTQR_OK;
+}
+
+template <typename TD>
+ctqr_status refine_update(int64_t n, int S, double *x, const TD *d, int64_t ldd,
+                          unsigned long long *dmax, unsigned long long *xmax, const int *skip,
+                          hipStream_t st)
+{
+    LAUNCH_TRY(refine_update_kernel<TD>, dim3((unsigned)ceil_div(n, 32), (unsigned)ceil_div(S, 32)),
+               dim3(32, 8), 0, st, n, S, x, d, ldd, dmax, xmax, skip);
+    return CTQR_OK;
+}
+
+ctqr_status refine_check(int S, unsigned long long *dmax, unsigned long long *xmax, double tol,
+                         int it, int max_iters, double *hist, int *done, ctqr_info *info,
+                         hipStream_t st)
+{
+    LAUNCH_TRY(refine_check_kernel, dim3(1), dim3(256), 0, st, S, dmax, xmax, tol, it, max_iters, hist,
+               done, info);
+    return CTQR_OK;
+}
+
+template ctqr_status cm_to_rm<double, double>(int64_t, int, const double *, int64_t, double *,
+                                              const int *, hipStream_t);
+template ctqr_status cm_to_rm<double, float>(int64_t, int, const float *, int64_t, double *,
+                                             const int *, hipStream_t);
+template ctqr_status rm_to_cm<double, double>(int64_t, int, const double *, double *, int64_t,
+                                              const int *, hipStream_t);
+template ctqr_status rm_to_cm<float, double>(int64_t, int, const double *, float *, int64_t,
+                                             const int *, hipStream_t);
+template ctqr_status copy_cm<double, double>(int64_t, int, const double *, int64_t, double *, int64_t,
+                                             hipStream_t);
+template ctqr_status copy_cm<float, double>(int64_t, int, const double *, int64_t, float *, int64_t,
+                                            hipStream_t);
+template ctqr_status copy_cm<double, float>(int64_t, int, const float *, int64_t, double *, int64_t,
+                                            hipStream_t);
+template ctqr_status refine_update<float>(int64_t, int, double *, const float *, int64_t,
+                                          unsigned long long *, unsigned long long *, const int *,
+                                          hipStream_t);
+template ctqr_status refine_update<double>(int64_t, int, double *, const double *, int64_t,
+                                           unsigned long long *, unsigned long long *, const int *,
+                                           hipStream_t);

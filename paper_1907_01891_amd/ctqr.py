@@ -1,0 +1,168 @@
+"""ctypes binding of libctqr.so (the C ABI in include/ctqr.h).
+
+Argument marshalling only: every function here forwards to the C entry point
+of the same name.  The library is loaded from this package directory; if it
+is missing or cannot be loaded, ``lib()`` raises -- there is no fallback.
+"""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libctqr.so")
+
+c_i32, c_i64, c_dbl, c_sz, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t, ctypes.c_void_p
+
+# status codes
+CTQR_OK = 0
+CTQR_EINVAL = -1
+CTQR_ENOMEM = -2
+CTQR_EHIP = -3
+CTQR_EUNSUPPORTED = -4
+CTQR_RANK_DEFICIENT = 1
+CTQR_NOT_CONVERGED = 2
+CTQR_NONFINITE = 3
+CTQR_CAPACITY = 4
+CTQR_BARRIER_TIMEOUT = 5
+# dtypes / precisions
+CTQR_F64 = 0
+CTQR_F32 = 1
+CTQR_PREC_FP64 = 0
+CTQR_PREC_FP32_MFMA = 1
+CTQR_PREC_BF16_MFMA = 2
+
+
+class ctqr_geometry(ctypes.Structure):
+    _fields_ = [("side", c_i32), ("n_views", c_i32), ("n_bins", c_i32), ("angle_schedule", c_i32),
+                ("src_iso_cm", c_dbl), ("src_det_cm", c_dbl), ("fan_deg", c_dbl), ("fov_side_cm", c_dbl)]
+
+
+class ctqr_sparse(ctypes.Structure):
+    _fields_ = [("m", c_i64), ("n", c_i64), ("nnz_cap", c_i64),
+                ("rowptr", c_vp), ("col", c_vp), ("val", c_vp),
+                ("colptr", c_vp), ("row", c_vp), ("cval", c_vp)]
+
+
+class ctqr_info(ctypes.Structure):
+    _fields_ = [("status", c_i32), ("first_bad_col", c_i32), ("iters", c_i32), ("pad", c_i32),
+                ("max_rel_update", c_dbl), ("rdiag_max", c_dbl), ("rdiag_min", c_dbl), ("nnz", c_i64)]
+
+
+_P = ctypes.POINTER
+_SIGNATURES = {
+    "ctqr_status_string": (ctypes.c_char_p, [c_i32]),
+    "ctqr_version": (ctypes.c_char_p, []),
+    "ctqr_last_error": (ctypes.c_char_p, []),
+    "ctqr_geometry_sizes": (c_i32, [_P(ctqr_geometry), _P(c_i64), _P(c_i64), _P(c_i64)]),
+    "ctqr_build_workspace": (c_i32, [_P(ctqr_geometry), _P(c_sz)]),
+    "ctqr_build_system_matrix": (c_i32, [_P(ctqr_geometry), c_i32, c_vp, c_i64, _P(ctqr_sparse),
+                                         c_vp, c_sz, c_vp, c_vp]),
+    "ctqr_qr_workspace": (c_i32, [c_i64, c_i64, c_i32, c_i32, c_i32, _P(c_sz)]),
+    "ctqr_qr_factor": (c_i32, [c_i64, c_i64, c_i32, c_vp, c_i64, c_i32, c_i32, c_vp, c_vp,
+                               c_vp, c_sz, c_vp, c_vp]),
+    "ctqr_solve_workspace": (c_i32, [c_i64, c_i64, c_i32, c_i32, c_i32, c_i32, _P(c_sz)]),
+    "ctqr_qr_solve_slices": (c_i32, [c_i64, c_i64, c_i32, c_vp, c_i64, c_vp, c_vp, c_i32,
+                                     c_vp, c_i64, c_i32, c_vp, c_i64, _P(ctqr_sparse), c_dbl, c_i32,
+                                     c_vp, c_sz, c_vp, c_vp]),
+    "ctqr_spmm": (c_i32, [_P(ctqr_sparse), c_i32, c_dbl, c_vp, c_i64, c_dbl, c_vp, c_i64, c_vp]),
+    "ctqr_profile_enable": (c_i32, [c_i32]),
+    "ctqr_profile_read": (c_i32, [_P(c_i64), _P(c_dbl), _P(c_dbl)]),
+}
+EXPORTS = tuple(_SIGNATURES)
+
+_lib = None
+
+
+def lib():
+    """The loaded libctqr (raises OSError/RuntimeError if it is absent)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libctqr.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+class CtqrError(RuntimeError):
+    def __init__(self, code, where):
+        msg = "%s returned %d (%s)" % (where, code, status_string(code))
+        last = lib().ctqr_last_error()
+        if last:
+            msg += ": " + last.decode()
+        super().__init__(msg)
+        self.code = code
+
+
+def check(code, where):
+    if code != CTQR_OK:
+        raise CtqrError(code, where)
+    return code
+
+
+def status_string(code):
+    return lib().ctqr_status_string(int(code)).decode()
+
+
+def ctqr_version():
+    return lib().ctqr_version().decode()
+
+
+def ctqr_geometry_sizes(geom):
+    m, n, nnz = c_i64(), c_i64(), c_i64()
+    check(lib().ctqr_geometry_sizes(ctypes.byref(geom), ctypes.byref(m), ctypes.byref(n), ctypes.byref(nnz)),
+          "ctqr_geometry_sizes")
+    return m.value, n.value, nnz.value
+
+
+def ctqr_build_workspace(geom):
+    b = c_sz()
+    check(lib().ctqr_build_workspace(ctypes.byref(geom), ctypes.byref(b)), "ctqr_build_workspace")
+    return b.value
+
+
+def ctqr_build_system_matrix(geom, dtype, A_ptr, lda, sparse, work_ptr, work_bytes, info_ptr, stream):
+    return lib().ctqr_build_system_matrix(ctypes.byref(geom), dtype, A_ptr, lda,
+                                          ctypes.byref(sparse) if sparse is not None else None,
+                                          work_ptr, work_bytes, info_ptr, stream)
+
+
+def ctqr_qr_workspace(m, n, dtype, prec, nb):
+    b = c_sz()
+    check(lib().ctqr_qr_workspace(m, n, dtype, prec, nb, ctypes.byref(b)), "ctqr_qr_workspace")
+    return b.value
+
+
+def ctqr_qr_factor(m, n, dtype, A_ptr, lda, prec, nb, T_ptr, tau_ptr, work_ptr, work_bytes, info_ptr, stream):
+    return lib().ctqr_qr_factor(m, n, dtype, A_ptr, lda, prec, nb, T_ptr, tau_ptr, work_ptr, work_bytes,
+                                info_ptr, stream)
+
+
+def ctqr_solve_workspace(m, n, dtype, nb, nslices, refine):
+    b = c_sz()
+    check(lib().ctqr_solve_workspace(m, n, dtype, nb, nslices, refine, ctypes.byref(b)), "ctqr_solve_workspace")
+    return b.value
+
+
+def ctqr_qr_solve_slices(m, n, dtype, QR_ptr, lda, T_ptr, tau_ptr, nb, B_ptr, ldb, nslices, X_ptr, ldx,
+                         sparse, tol, max_iters, work_ptr, work_bytes, info_ptr, stream):
+    return lib().ctqr_qr_solve_slices(m, n, dtype, QR_ptr, lda, T_ptr, tau_ptr, nb, B_ptr, ldb, nslices,
+                                      X_ptr, ldx, ctypes.byref(sparse) if sparse is not None else None,
+                                      tol, max_iters, work_ptr, work_bytes, info_ptr, stream)
+
+
+def ctqr_spmm(sparse, nslices, alpha, X_ptr, ldx, beta, Y_ptr, ldy, stream):
+    return lib().ctqr_spmm(ctypes.byref(sparse), nslices, alpha, X_ptr, ldx, beta, Y_ptr, ldy, stream)
+
+
+def ctqr_profile_enable(on):
+    return lib().ctqr_profile_enable(1 if on else 0)
+
+
+def ctqr_profile_read():
+    n, ms, fl = c_i64(), c_dbl(), c_dbl()
+    check(lib().ctqr_profile_read(ctypes.byref(n), ctypes.byref(ms), ctypes.byref(fl)), "ctqr_profile_read")
+    return n.value, ms.value, fl.value

@@ -1,0 +1,173 @@
+"""Device memory for the libctqr calls, allocated through PyTorch.
+
+PyTorch supplies HBM buffers and the current HIP stream; every computation is
+a libctqr call (ctqr.py).  Matrices are column-major: an m x n matrix with
+leading dimension ld is a torch tensor of shape (m, n) and strides (1, ld),
+carved from a (n, ld) row-major allocation.
+"""
+import ctypes
+
+import torch
+
+from . import ctqr as C
+
+_DT = {C.CTQR_F64: torch.float64, C.CTQR_F32: torch.float32}
+
+
+def round_up(a, b):
+    return (a + b - 1) // b * b
+
+
+def colmajor(rows, cols, dtype, device="cuda", ld=None, fill=None):
+    """(rows x cols) column-major tensor with leading dimension ld (default
+    rows rounded up to 64 elements), 256-byte aligned columns."""
+    ld = ld or round_up(max(rows, 1), 64)
+    base = torch.empty((cols, ld), dtype=dtype, device=device)
+    if fill is not None:
+        base.fill_(fill)
+    return base.t()[:rows, :]
+
+
+def ld_of(t):
+    """Leading dimension of a column-major 2-D tensor."""
+    if t.dim() != 2 or t.stride(0) != 1:
+        raise ValueError("expected a column-major 2-D tensor")
+    return t.stride(1) if t.shape[1] > 1 else max(t.stride(1), t.shape[0])
+
+
+def to_colmajor(x, dtype=None, device="cuda", ld=None):
+    x = torch.as_tensor(x)
+    if x.dim() == 1:
+        x = x[:, None]
+    out = colmajor(x.shape[0], x.shape[1], dtype or x.dtype, device, ld=ld)
+    out.copy_(x.to(device=device, dtype=dtype or x.dtype))
+    return out
+
+
+def stream_handle(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def geometry(d):
+    """ctqr_geometry from a dict with the keys of synthetic.Workload.geometry()."""
+    return C.ctqr_geometry(int(d["side"]), int(d["n_views"]), int(d["n_bins"]), int(d.get("angle_schedule", 1)),
+                           float(d["src_iso_cm"]), float(d["src_det_cm"]), float(d["fan_deg"]),
+                           float(d["fov_side_cm"]))
+
+
+class Info:
+    """Device-side ctqr_info."""
+
+    def __init__(self, device="cuda"):
+        self.buf = torch.zeros(ctypes.sizeof(C.ctqr_info), dtype=torch.uint8, device=device)
+
+    @property
+    def ptr(self):
+        return ctypes.c_void_p(self.buf.data_ptr())
+
+    def read(self):
+        return C.ctqr_info.from_buffer_copy(bytes(self.buf.cpu().numpy()))
+
+
+class Workspace:
+    """Grow-only device workspace."""
+
+    def __init__(self, device="cuda"):
+        self.device = device
+        self.buf = None
+
+    def get(self, nbytes):
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = None
+            torch.cuda.empty_cache()
+            self.buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=self.device)
+        return ctypes.c_void_p(self.buf.data_ptr()), self.buf.numel()
+
+
+class SystemMatrix:
+    """A for one geometry: dense (optional, FP64 or FP32) and the FP64 sparse
+    copy (CSR + CSC, optional), built on the GPU by ctqr_build_system_matrix."""
+
+    def __init__(self, geom_dict, dtype=C.CTQR_F64, dense=True, sparse=True, device="cuda", stream=None):
+        self.geom = geometry(geom_dict)
+        self.m, self.n, self.nnz_cap = C.ctqr_geometry_sizes(self.geom)
+        self.dtype = dtype
+        self.device = device
+        self.A = colmajor(self.m, self.n, _DT[dtype], device) if dense else None
+        self.sp = None
+        if sparse:
+            cap = self.nnz_cap
+            self.rowptr = torch.empty(self.m + 1, dtype=torch.int64, device=device)
+            self.col = torch.empty(cap, dtype=torch.int32, device=device)
+            self.val = torch.empty(cap, dtype=torch.float64, device=device)
+            self.colptr = torch.empty(self.n + 1, dtype=torch.int64, device=device)
+            self.row = torch.empty(cap, dtype=torch.int32, device=device)
+            self.cval = torch.empty(cap, dtype=torch.float64, device=device)
+            self.sp = C.ctqr_sparse(self.m, self.n, cap, self.rowptr.data_ptr(), self.col.data_ptr(),
+                                    self.val.data_ptr(), self.colptr.data_ptr(), self.row.data_ptr(),
+                                    self.cval.data_ptr())
+        self.info = Info(device)
+        self.work = Workspace(device)
+        self.build(stream)
+
+    def build(self, stream=None):
+        wp, wb = self.work.get(C.ctqr_build_workspace(self.geom))
+        A_ptr = ctypes.c_void_p(self.A.data_ptr()) if self.A is not None else None
+        lda = ld_of(self.A) if self.A is not None else 0
+        C.check(C.ctqr_build_system_matrix(self.geom, self.dtype, A_ptr, lda, self.sp, wp, wb, self.info.ptr,
+                                           stream_handle(stream)), "ctqr_build_system_matrix")
+
+    def nnz(self):
+        return int(self.info.read().nnz)
+
+    def spmm(self, X, alpha=1.0, beta=0.0, Y=None, stream=None):
+        """Y = alpha A X + beta Y (FP64, column-major), with the sparse copy."""
+        S = X.shape[1]
+        if Y is None:
+            Y = colmajor(self.m, S, torch.float64, self.device, fill=0.0)
+        C.check(C.ctqr_spmm(self.sp, S, alpha, ctypes.c_void_p(X.data_ptr()), ld_of(X), beta,
+                            ctypes.c_void_p(Y.data_ptr()), ld_of(Y), stream_handle(stream)), "ctqr_spmm")
+        return Y
+
+
+class QRFactor:
+    """A = QR in place on a column-major dense A (ctqr_qr_factor), plus the
+    stored T blocks and tau for ctqr_qr_solve_slices."""
+
+    def __init__(self, A, prec, nb=0, device="cuda"):
+        self.A = A
+        self.m, self.n = A.shape
+        self.dtype = C.CTQR_F64 if A.dtype == torch.float64 else C.CTQR_F32
+        self.prec = prec
+        self.nb = nb or 256
+        self.T = colmajor(self.nb, self.n, A.dtype, device, ld=self.nb)
+        self.tau = torch.zeros(self.n, dtype=torch.float64, device=device)
+        self.info = Info(device)
+        self.work = Workspace(device)
+        self.swork = Workspace(device)
+        self.sinfo = Info(device)
+
+    def factor(self, stream=None):
+        wp, wb = self.work.get(C.ctqr_qr_workspace(self.m, self.n, self.dtype, self.prec, self.nb))
+        C.check(C.ctqr_qr_factor(self.m, self.n, self.dtype, ctypes.c_void_p(self.A.data_ptr()), ld_of(self.A),
+                                 self.prec, self.nb, ctypes.c_void_p(self.T.data_ptr()),
+                                 ctypes.c_void_p(self.tau.data_ptr()), wp, wb, self.info.ptr,
+                                 stream_handle(stream)), "ctqr_qr_factor")
+        return self
+
+    def solve(self, B, X=None, sparse=None, tol=1e-13, max_iters=0, stream=None):
+        """X = R^-1 Q^T B (FP64, column-major), refined with the sparse A if given."""
+        S = B.shape[1]
+        if X is None:
+            X = colmajor(self.n, S, torch.float64, B.device)
+        refine = 1 if (sparse is not None and max_iters > 0) else 0
+        wp, wb = self.swork.get(C.ctqr_solve_workspace(self.m, self.n, self.dtype, self.nb, S, refine))
+        C.check(C.ctqr_qr_solve_slices(self.m, self.n, self.dtype, ctypes.c_void_p(self.A.data_ptr()),
+                                       ld_of(self.A), ctypes.c_void_p(self.T.data_ptr()),
+                                       ctypes.c_void_p(self.tau.data_ptr()), self.nb,
+                                       ctypes.c_void_p(B.data_ptr()), ld_of(B), S,
+                                       ctypes.c_void_p(X.data_ptr()), ld_of(X), sparse, tol, max_iters,
+                                       wp, wb, self.sinfo.ptr, stream_handle(stream)),
+                "ctqr_qr_solve_slices")
+        return X

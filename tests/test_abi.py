@@ -1,0 +1,148 @@
+"""The C ABI of libctqr: symbols, struct layouts and host-side argument
+checking.  Runs without a GPU: every call here is rejected (or answered) on
+the host before any HIP call is made."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1907_01891_amd import ctqr as C
+from synthetic import get_workload
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ctqr.h")
+
+
+def _header_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(ctqr_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = C.lib()
+    declared = _header_functions()
+    assert declared, "no functions parsed from the header"
+    for name in declared:
+        assert hasattr(L, name), name
+    assert set(declared) == set(C.EXPORTS)
+
+
+def test_status_strings():
+    for code in (0, -1, -2, -3, -4, 1, 2, 3, 4, 5):
+        s = C.status_string(code)
+        assert s and "unknown" not in s
+    assert "unknown" in C.status_string(99)
+    assert "gfx950" in C.ctqr_version()
+
+
+def test_struct_layouts():
+    assert ctypes.sizeof(C.ctqr_geometry) == 48
+    assert ctypes.sizeof(C.ctqr_sparse) == 72
+    assert ctypes.sizeof(C.ctqr_info) == 48
+
+
+def _geom(**kw):
+    from paper_1907_01891_amd.device import geometry
+    d = dict(get_workload("ct32").geometry())
+    d.update(kw)
+    return geometry(d)
+
+
+def test_geometry_sizes():
+    assert C.ctqr_geometry_sizes(_geom()) == (3072, 1024, 3072 * 63)
+    g = get_workload("paper512").geometry()
+    from paper_1907_01891_amd.device import geometry
+    m, n, _ = C.ctqr_geometry_sizes(geometry(g))
+    assert (m, n) == (266500, 262144)     # Section III-B
+
+
+@pytest.mark.parametrize("kw", [dict(side=0), dict(n_views=0), dict(n_bins=-1), dict(angle_schedule=3),
+                                dict(n_views=3), dict(src_det_cm=10.0), dict(fan_deg=0.0),
+                                dict(fov_side_cm=-1.0)])
+def test_geometry_rejected(kw):
+    m, n, z = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    assert C.lib().ctqr_geometry_sizes(ctypes.byref(_geom(**kw)), ctypes.byref(m), ctypes.byref(n),
+                                       ctypes.byref(z)) == C.CTQR_EINVAL
+
+
+def test_workspace_queries():
+    a = C.ctqr_qr_workspace(3072, 1024, C.CTQR_F64, C.CTQR_PREC_FP64, 0)
+    b = C.ctqr_qr_workspace(3072, 1024, C.CTQR_F32, C.CTQR_PREC_FP32_MFMA, 0)
+    assert a > 0 and b > 0 and a > b
+    s0 = C.ctqr_solve_workspace(3072, 1024, C.CTQR_F64, 0, 4, 0)
+    s1 = C.ctqr_solve_workspace(3072, 1024, C.CTQR_F64, 0, 4, 1)
+    assert 0 < s0 < s1
+    assert C.ctqr_build_workspace(_geom()) > 0
+
+
+def _sz():
+    return ctypes.c_size_t()
+
+
+@pytest.mark.parametrize("args,code", [
+    ((100, 200, C.CTQR_F64, C.CTQR_PREC_FP64, 0), C.CTQR_EINVAL),        # m < n
+    ((100, 0, C.CTQR_F64, C.CTQR_PREC_FP64, 0), C.CTQR_EINVAL),          # n < 1
+    ((100, 50, C.CTQR_F64, C.CTQR_PREC_FP32_MFMA, 0), C.CTQR_EINVAL),    # dtype/prec mismatch
+    ((100, 50, 7, C.CTQR_PREC_FP64, 0), C.CTQR_EINVAL),                  # bad dtype
+    ((100, 50, C.CTQR_F64, C.CTQR_PREC_FP64, 48), C.CTQR_EINVAL),        # nb not a multiple of 32
+    ((100, 50, C.CTQR_F64, C.CTQR_PREC_FP64, 512), C.CTQR_EINVAL),       # nb too large
+])
+def test_qr_workspace_rejects(args, code):
+    assert C.lib().ctqr_qr_workspace(*args, ctypes.byref(_sz())) == code
+
+
+def test_factor_rejects_before_any_hip_call():
+    L = C.lib()
+    p = ctypes.c_void_p(4096)       # never dereferenced: every case fails validation
+    # null A
+    assert L.ctqr_qr_factor(100, 50, C.CTQR_F64, None, 100, C.CTQR_PREC_FP64, 0, p, p, p, 1 << 40, p, None) == C.CTQR_EINVAL
+    # lda < m
+    assert L.ctqr_qr_factor(100, 50, C.CTQR_F64, p, 96, C.CTQR_PREC_FP64, 0, p, p, p, 1 << 40, p, None) == C.CTQR_EINVAL
+    # lda not a multiple of 4
+    assert L.ctqr_qr_factor(100, 50, C.CTQR_F64, p, 102, C.CTQR_PREC_FP64, 0, p, p, p, 1 << 40, p, None) == C.CTQR_EINVAL
+    # misaligned A
+    assert L.ctqr_qr_factor(100, 50, C.CTQR_F64, ctypes.c_void_p(4100), 100, C.CTQR_PREC_FP64, 0, p, p, p, 1 << 40, p, None) == C.CTQR_EINVAL
+    # workspace too small
+    assert L.ctqr_qr_factor(100, 50, C.CTQR_F64, p, 100, C.CTQR_PREC_FP64, 0, p, p, p, 16, p, None) == C.CTQR_ENOMEM
+    # BF16 storage path not offered for FP64 storage
+    assert L.ctqr_qr_factor(100, 50, C.CTQR_F64, p, 100, C.CTQR_PREC_BF16_MFMA, 0, p, p, p, 1 << 40, p, None) == C.CTQR_EINVAL
+
+
+def test_solve_rejects_before_any_hip_call():
+    L = C.lib()
+    p = ctypes.c_void_p(4096)
+    ok = dict(m=100, n=50, dtype=C.CTQR_F64, QR=p, lda=100, T=p, tau=p, nb=0, B=p, ldb=100, S=2, X=p, ldx=50,
+              sp=None, tol=1e-13, it=0, work=p, wb=1 << 40, info=p, st=None)
+
+    def call(**kw):
+        a = dict(ok)
+        a.update(kw)
+        return L.ctqr_qr_solve_slices(a["m"], a["n"], a["dtype"], a["QR"], a["lda"], a["T"], a["tau"], a["nb"],
+                                      a["B"], a["ldb"], a["S"], a["X"], a["ldx"], a["sp"], a["tol"], a["it"],
+                                      a["work"], a["wb"], a["info"], a["st"])
+    assert call(S=0) == C.CTQR_EINVAL
+    assert call(ldb=99) == C.CTQR_EINVAL
+    assert call(ldx=49) == C.CTQR_EINVAL
+    assert call(B=None) == C.CTQR_EINVAL
+    assert call(wb=8) == C.CTQR_ENOMEM
+    bad = C.ctqr_sparse(99, 50, 10, 4096, 4096, 4096, 4096, 4096, 4096)
+    assert call(sp=ctypes.byref(bad), it=3) == C.CTQR_EINVAL
+
+
+def test_build_rejects():
+    L = C.lib()
+    p = ctypes.c_void_p(4096)
+    g = _geom()
+    # neither dense nor sparse output requested
+    assert L.ctqr_build_system_matrix(ctypes.byref(g), C.CTQR_F64, None, 0, None, p, 1 << 30, p, None) == C.CTQR_EINVAL
+    # lda < m
+    assert L.ctqr_build_system_matrix(ctypes.byref(g), C.CTQR_F64, p, 100, None, p, 1 << 30, p, None) == C.CTQR_EINVAL
+    # sparse with wrong sizes
+    sp = C.ctqr_sparse(3071, 1024, 10, 4096, 4096, 4096, 0, 0, 0)
+    assert L.ctqr_build_system_matrix(ctypes.byref(g), C.CTQR_F64, None, 0, ctypes.byref(sp), p, 1 << 30, p, None) == C.CTQR_EINVAL
+    # workspace too small
+    assert L.ctqr_build_system_matrix(ctypes.byref(g), C.CTQR_F64, p, 3072, None, p, 4, p, None) == C.CTQR_ENOMEM
+    # spmm argument checks
+    assert L.ctqr_spmm(None, 1, 1.0, p, 10, 0.0, p, 10, None) == C.CTQR_EINVAL
