@@ -312,7 +312,8 @@ __device__ inline void acc_coords(int ib, int jb, int r, int &n, int &m)
         n = ib * 32 + 8 * (r / 4) + 4 * (lane / 32) + (r % 4);
         m = jb * 32 + lane % 32;
     } else {
-        n = ib * 16 + 4 * (lane / 16) + r;
+        // v_mfma_f64_16x16x4f64: register r of lane l holds row 4r + l/16
+        n = ib * 16 + 4 * r + lane / 16;
         m = jb * 16 + lane % 16;
     }
     (void)sizeof(M);
