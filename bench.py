@@ -1,0 +1,262 @@
+"""Benchmark of the QR least-squares CT reconstruction hot path on one MI355X.
+
+Workload (default ct256): 256x256 image (n = 65,536 pixels), fan-beam scanner
+of Table I with 120 views x 736 bins (m = 88,320 rays), A stored in FP32 for
+the factorization, 256 seeded ellipse-phantom sinograms with 1e-3 relative
+Gaussian noise.  One step is the whole hot path on resident inputs:
+  1. build the dense FP32 system matrix A on the GPU (Siddon),
+  2. blocked Householder QR with FP32-MFMA trailing updates (A = QR, Eq. 3),
+  3. X = R^-1 Q^T B for all 256 slices (Eq. 4), refined by corrected
+     semi-normal equations with FP64 residuals against the FP64 sparse A.
+value = QR TFLOP/s of step 2 ((2 m n^2 - 2 n^3 / 3) / t_QR); slices/s of
+step 3 are reported beside it, as are the same two figures for the plain FP64
+GPU path (FP64 A, FP64 MFMA, no refinement), timed once after the K steps.
+
+The "roofline" object covers the dominant kernel (the trailing-update GEMM
+C -= V W'), timed per launch with HIP events on the stream it runs on.  The
+"cpu_baseline" leg times the CPU oracle (unblocked FP64 Householder QR) on a
+bounded column sample of the same A.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
+HBM_PEAK_GBS = 8000.0
+
+
+def qr_flops(m, n):
+    return 2.0 * m * n * n - 2.0 * n ** 3 / 3.0
+
+
+def solve_flops(m, n):
+    return 4.0 * m * n - 2.0 * n * n + n * n
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=2)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--workload", default="ct256")
+    p.add_argument("--nb", type=int, default=256)
+    p.add_argument("--max-iters", type=int, default=30)
+    p.add_argument("--tol", type=float, default=1e-14)
+    p.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU comparison run")
+    p.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
+    p.add_argument("--cpu-seconds", type=float, default=15.0)
+    return p.parse_args()
+
+
+def cpu_baseline(workload, target_s):
+    """Oracle QR (unblocked FP64 Householder, OpenMP) on A[:, :k] of the same
+    geometry, k chosen for about target_s seconds; TFLOP/s by the flop count of
+    that k-column factorization."""
+    import numpy as np
+    from synthetic import get_workload
+    from oracle.siddon import system_matrix_csr
+    from oracle import householder as hh
+    g = get_workload(workload).geometry()
+    A = system_matrix_csr(g).tocsc()
+    m = A.shape[0]
+    hh.build(force=False)
+    k = 128
+    t0 = time.perf_counter()
+    hh.geqr2(A[:, :k].toarray())
+    t = time.perf_counter() - t0
+    rate = qr_flops(m, k) / max(t, 1e-6)
+    # flops grow ~ k^2: pick k for the target time
+    k = int(min(A.shape[1], max(k, (target_s * rate / (2.0 * m)) ** 0.5)))
+    k = max(128, k // 32 * 32)
+    Ad = A[:, :k].toarray()
+    t0 = time.perf_counter()
+    hh.geqr2(Ad)
+    t = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": qr_flops(m, k) / t / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": "unblocked FP64 Householder QR of A[:, :%d] (%d x %d) of the %s geometry, %.1f s"
+                      % (k, m, k, workload, t)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from synthetic import get_workload, phantom_batch, noise_batch, NOISE_REL_LEVEL
+    from paper_1907_01891_amd import ctqr as C
+    from paper_1907_01891_amd.device import SystemMatrix, QRFactor, colmajor, to_colmajor
+
+    C.lib()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    w = get_workload(args.workload)
+    g = w.geometry()
+    m, n, S = w.m, w.n, w.n_slices
+    log = lambda *a: print("[bench]", *a, file=sys.stderr, flush=True)
+    log("workload %s m=%d n=%d slices=%d" % (w.name, m, n, S))
+
+    # ---- untimed input synthesis: sparse FP64 A, phantoms, noisy sinograms
+    sp = SystemMatrix(g, C.CTQR_F64, dense=False, sparse=True)
+    Xtrue = to_colmajor(torch.as_tensor(phantom_batch(w.side, S)), dtype=torch.float64)
+    B = sp.spmm(Xtrue)
+    torch.cuda.synchronize()
+    sigma = NOISE_REL_LEVEL * B.abs().amax(dim=0)
+    Z = torch.as_tensor(noise_batch(w.side, m, S), device=dev)
+    n_clean = 4
+    Bclean = colmajor(m, n_clean, torch.float64, dev)
+    Bclean.copy_(B[:, :n_clean])
+    B.add_(Z * sigma[None, :])
+    del Z
+    log("inputs ready, nnz=%d" % sp.nnz())
+
+    A32 = colmajor(m, n, torch.float32, dev)
+    stream = torch.cuda.current_stream()
+
+    def build_dense(A, dtype):
+        from paper_1907_01891_amd.device import Workspace, stream_handle, ld_of
+        import ctypes
+        ws = build_dense.ws
+        wp, wb = ws.get(C.ctqr_build_workspace(sp.geom))
+        C.check(C.ctqr_build_system_matrix(sp.geom, dtype, ctypes.c_void_p(A.data_ptr()), ld_of(A), None,
+                                           wp, wb, sp.info.ptr, stream_handle()), "build")
+    from paper_1907_01891_amd.device import Workspace
+    build_dense.ws = Workspace()
+
+    F = QRFactor(A32, C.CTQR_PREC_FP32_MFMA, nb=args.nb)
+    X = colmajor(n, S, torch.float64, dev)
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+
+    def step(profile):
+        e0, e1, e2, e3 = ev(), ev(), ev(), ev()
+        e0.record()
+        build_dense(A32, C.CTQR_F32)
+        e1.record()
+        if profile:
+            C.ctqr_profile_enable(True)
+        F.factor()
+        e2.record()
+        F.solve(B, X=X, sparse=sp.sp, tol=args.tol, max_iters=args.max_iters)
+        e3.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1), e1.elapsed_time(e2), e2.elapsed_time(e3)
+
+    for i in range(args.warmup):
+        t = step(False)
+        log("warmup %d: build %.1f ms, qr %.1f ms, solve %.1f ms" % (i, *t))
+    torch.cuda.synchronize()
+    times = []
+    tw0 = time.perf_counter()
+    for i in range(args.steps):
+        t = step(True)
+        times.append(t)
+        log("step %d: build %.1f ms, qr %.1f ms, solve %.1f ms" % (i, *t))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - tw0
+    launches, kern_ms, kern_flops = C.ctqr_profile_read()
+    C.ctqr_profile_enable(False)
+    finfo, sinfo = F.info.read(), F.sinfo.read()
+    t_build = np.mean([t[0] for t in times])
+    t_qr = np.mean([t[1] for t in times])
+    t_solve = np.mean([t[2] for t in times])
+    qr_tf = qr_flops(m, n) / (t_qr * 1e-3) / 1e12
+    slices_s = S / (t_solve * 1e-3)
+
+    # accuracy: exact recovery on noise-free slices (the least-squares solution
+    # of consistent data is the phantom itself)
+    Xc = F.solve(Bclean, sparse=sp.sp, tol=args.tol, max_iters=args.max_iters)
+    torch.cuda.synchronize()
+    rec_err = ((Xc - Xtrue[:, :n_clean]).norm(dim=0) / Xtrue[:, :n_clean].norm(dim=0)).max().item()
+    Xmixed = X.clone()
+    log("mixed: qr %.2f TFLOP/s, %.0f slices/s, refine iters %d (status %d), recovery err %.2e"
+        % (qr_tf, slices_s, sinfo.iters, sinfo.status, rec_err))
+    del A32, F
+    torch.cuda.empty_cache()
+
+    fp64 = {}
+    if not args.no_fp64:
+        A64 = colmajor(m, n, torch.float64, dev)
+        build_dense(A64, C.CTQR_F64)
+        F64 = QRFactor(A64, C.CTQR_PREC_FP64, nb=args.nb)
+        torch.cuda.synchronize()
+        e0, e1, e2 = ev(), ev(), ev()
+        e0.record()
+        F64.factor()
+        e1.record()
+        X64 = F64.solve(B)
+        e2.record()
+        torch.cuda.synchronize()
+        t64_qr, t64_solve = e0.elapsed_time(e1), e1.elapsed_time(e2)
+        diff = ((Xmixed - X64).norm(dim=0) / X64.norm(dim=0)).max().item()
+        Xc64 = F64.solve(Bclean)
+        torch.cuda.synchronize()
+        rec64 = ((Xc64 - Xtrue[:, :n_clean]).norm(dim=0) / Xtrue[:, :n_clean].norm(dim=0)).max().item()
+        fp64 = {"fp64_qr_tflops": qr_flops(m, n) / (t64_qr * 1e-3) / 1e12,
+                "fp64_slices_per_s": S / (t64_solve * 1e-3), "fp64_qr_ms": t64_qr, "fp64_solve_ms": t64_solve,
+                "fp64_recovery_err": rec64, "mixed_vs_fp64_rel_diff": diff,
+                "fp64_info_status": F64.info.read().status}
+        log("fp64: qr %.2f TFLOP/s (%.0f ms), %.0f slices/s, mixed-vs-fp64 %.2e, recovery %.2e"
+            % (fp64["fp64_qr_tflops"], t64_qr, fp64["fp64_slices_per_s"], diff, rec64))
+        del A64, F64
+        torch.cuda.empty_cache()
+
+    cpu = None
+    if not args.no_cpu:
+        log("cpu baseline ...")
+        cpu = cpu_baseline(args.workload, args.cpu_seconds)
+        log("cpu baseline %.4f TFLOP/s (%s)" % (cpu["value"], cpu["sample"]))
+
+    achieved = kern_flops / (kern_ms * 1e-3) / 1e12 if kern_ms > 0 else None
+    out = {
+        "metric": "QR TFLOP/s + slices/s at 256^2 (mixed vs FP64 GPU, rel err <= 1e-10)",
+        "value": qr_tf,
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": float(np.mean([sum(t) for t in times])),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "%s: %dx%d image, %d views x %d bins (m=%d, n=%d), %d ellipse-phantom slices, "
+                        "1e-3 relative noise; FP32 A, FP32-MFMA trailing updates, FP64 panel, "
+                        "CSNE refinement with FP64 sparse residuals" % (w.name, w.side, w.side, w.n_views,
+                                                                       w.n_bins, m, n, S),
+            "nb": args.nb, "slices": S, "parallelism": "single GPU",
+        },
+        "slices_per_s": slices_s,
+        "qr_ms": t_qr, "solve_ms": t_solve, "build_ms": t_build,
+        "solve_tflops": S * solve_flops(m, n) / (t_solve * 1e-3) / 1e12,
+        "refine_iters": int(sinfo.iters), "refine_status": int(sinfo.status),
+        "refine_last_rel_update": sinfo.max_rel_update,
+        "recovery_rel_err_max": rec_err,
+        "qr_info_status": int(finfo.status),
+        "rdiag_min_max": [finfo.rdiag_min, finfo.rdiag_max],
+        "roofline": {
+            "bound": "mfma", "kernel": "gemm_nn_kernel<float> (trailing update C -= V W')",
+            "achieved": achieved, "peak": PEAK_TFLOPS["f32"], "unit": "TFLOP/s",
+            "frac": (achieved / PEAK_TFLOPS["f32"]) if achieved else None,
+            "traffic": None, "launches": launches,
+            "avg_launch_ms": kern_ms / launches if launches else None,
+            "flops_per_launch": kern_flops / launches if launches else None,
+        },
+        "cpu_baseline": cpu,
+        "wall_s_timed": wall,
+    }
+    out.update(fp64)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()
