@@ -14,7 +14,7 @@ namespace {
 
 constexpr int PANEL_W = 32;             // inner panel width
 constexpr int DEFAULT_NB = 256;         // outer block width
-constexpr int MAX_PANEL_WG = 1024;      // partial-sum slots of the panel kernel
+constexpr int MAX_PANEL_WG = GB_GROUP * GB_MAX_GROUPS;   // partial-sum slots of the panel kernel
 constexpr int64_t SPLIT_PART_ELEMS = 2LL * 512 * 128 * 128;   // split-K partial buffer
 
 thread_local std::string g_last_error;
@@ -59,7 +59,7 @@ FactorWS<T> carve_factor(void *work, int64_t m, int64_t n, int nb)
     (void)m;
     Carve c(work);
     FactorWS<T> w;
-    w.bars = c.take<unsigned>(ceil_div(n, PANEL_W) + 64);
+    w.bars = c.take<unsigned>((ceil_div(n, PANEL_W) + 1) * GB_WORDS);
     w.part = c.take<double>(MAX_PANEL_WG + 1);
     w.part2 = c.take<double>((int64_t)MAX_PANEL_WG * PANEL_W);
     w.gram_part = c.take<double>((int64_t)MAX_PANEL_WG * PANEL_W * PANEL_W);
@@ -148,7 +148,7 @@ ctqr_status factor_impl(int64_t m64, int64_t n64, T *A, int64_t lda, int nb, T *
     if (panel_rows_per_wg(m, ncu) > panel_max_rows_per_wg()) return CTQR_EUNSUPPORTED;
     ctqr_status s;
     if ((s = info_reset(info, st))) return s;
-    if ((s = fill_u32(w.bars, ceil_div(n, PANEL_W) + 64, 0u, st))) return s;
+    if ((s = fill_u32(w.bars, (ceil_div(n, PANEL_W) + 1) * GB_WORDS, 0u, st))) return s;
     int ipanel = 0;
     for (int k0 = 0; k0 < n; k0 += nb) {
         const int nbk = std::min(nb, n - k0);
@@ -157,7 +157,7 @@ ctqr_status factor_impl(int64_t m64, int64_t n64, T *A, int64_t lda, int nb, T *
         for (int c0 = k0; c0 < k0 + nbk; c0 += PANEL_W) {
             const int wdt = std::min(PANEL_W, k0 + nbk - c0);
             s = panel_qr<T>(A, lda, m, c0, wdt, tau + c0, w.part, w.part2, w.gram_part, w.gram,
-                            w.bars + ipanel, info, ncu, st);
+                            w.bars + (int64_t)ipanel * GB_WORDS, info, ncu, st);
             if (s) return s;
             ++ipanel;
             const int ncr = k0 + nbk - (c0 + wdt);

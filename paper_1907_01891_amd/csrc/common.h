@@ -44,23 +44,41 @@ __device__ inline void info_event(ctqr_info *info, int code, int col)
 
 // ---------------------------------------------------------------------------
 // Grid-wide barrier for cooperative launches (all workgroups co-resident).
-// `bar` is a zero-initialised counter owned by this launch; `epoch` advances
-// by gridDim.x per barrier so the counter never needs resetting.  The wait is
-// bounded: after ~2^26 polls (well over a second) it records
-// CTQR_BARRIER_TIMEOUT and lets the workgroup continue, so every wave exits.
-// Returns false if the barrier timed out.
+// Arrival is a two-level tree: each workgroup bumps the counter of its group
+// of GB_GROUP workgroups; the last arriver of a group bumps the root counter;
+// the last group releases everyone by publishing the new generation, which
+// the workgroups poll with relaxed loads.  No address sees more than
+// GB_GROUP atomics per barrier.  `bar` points at GB_WORDS zeroed words owned
+// by this launch; `epoch` counts the barriers passed.  The wait is bounded:
+// after ~2^26 polls it records CTQR_BARRIER_TIMEOUT and lets the workgroup
+// continue, so every wave exits.  Returns false on a time-out.
 // ---------------------------------------------------------------------------
+#define GB_GROUP 16
+#define GB_LINE 32                       /* words per counter (128-byte lines) */
+#define GB_MAX_GROUPS 64
+#define GB_WORDS (GB_LINE * (GB_MAX_GROUPS + 2))
+
 __device__ inline bool grid_barrier(unsigned *bar, unsigned &epoch, ctqr_info *info)
 {
     __syncthreads();
-    epoch += gridDim.x;
+    ++epoch;
     __shared__ int timed_out;
     if (threadIdx.x == 0) {
         timed_out = 0;
+        const unsigned G = gridDim.x, g = blockIdx.x / GB_GROUP;
+        const unsigned ngroups = (G + GB_GROUP - 1) / GB_GROUP;
+        const unsigned gsize = min((unsigned)GB_GROUP, G - g * GB_GROUP);
         __threadfence();
-        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned old = __hip_atomic_fetch_add(&bar[GB_LINE * (1 + g)], 1u, __ATOMIC_ACQ_REL,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+        if (old == epoch * gsize - 1) {
+            unsigned o2 = __hip_atomic_fetch_add(&bar[GB_LINE * (1 + GB_MAX_GROUPS)], 1u, __ATOMIC_ACQ_REL,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+            if (o2 == epoch * ngroups - 1)
+                __hip_atomic_store(&bar[0], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
         unsigned polls = 0;
-        while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
+        while (__hip_atomic_load(&bar[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
             __builtin_amdgcn_s_sleep(1);
             if (++polls > (1u << 26)) {
                 timed_out = 1;

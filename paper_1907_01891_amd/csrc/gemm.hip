@@ -92,47 +92,17 @@ __device__ inline T vmask(T stored, int row, int col)
     return row > col ? stored : (row == col ? T(1) : T(0));
 }
 
-// 16-byte global chunk of `E` elements of one column, rows [k, k+E), with rows
-// >= kmax zeroed.  ptr points at element (k, col).  E = 4 (float) or 2 (double).
-template <typename T>
-struct Chunk16 {
-    static constexpr int E = 16 / sizeof(T);
-    T v[E];
-};
+// 16-byte vector of E = 16 / sizeof(T) consecutive elements of one column.
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { using type = floatx4; };
+template <> struct Vec16<double> { using type = doublex2; };
+template <typename T> using vec16_t = typename Vec16<T>::type;
 
-template <typename T>
-__device__ inline Chunk16<T> load_chunk(const T *ptr, int k, int kmax, bool colok)
-{
-    Chunk16<T> c;
-    if (colok && k < kmax) {
-        if constexpr (sizeof(T) == 4) {
-            floatx4 x = *reinterpret_cast<const floatx4 *>(ptr);
-            c.v[0] = x[0]; c.v[1] = x[1]; c.v[2] = x[2]; c.v[3] = x[3];
-        } else {
-            doublex2 x = *reinterpret_cast<const doublex2 *>(ptr);
-            c.v[0] = x[0]; c.v[1] = x[1];
-        }
-#pragma unroll
-        for (int e = 0; e < Chunk16<T>::E; ++e)
-            if (k + e >= kmax) c.v[e] = T(0);
-    } else {
-#pragma unroll
-        for (int e = 0; e < Chunk16<T>::E; ++e) c.v[e] = T(0);
-    }
-    return c;
-}
-
-template <typename T>
-__device__ inline void store_chunk_lds(T *dst, const Chunk16<T> &c)
-{
-    if constexpr (sizeof(T) == 4) {
-        floatx4 x = {c.v[0], c.v[1], c.v[2], c.v[3]};
-        *reinterpret_cast<floatx4 *>(dst) = x;
-    } else {
-        doublex2 x = {c.v[0], c.v[1]};
-        *reinterpret_cast<doublex2 *>(dst) = x;
-    }
-}
+// Loads are issued unconditionally (an out-of-range chunk reads the operand's
+// first chunk instead), so every load of a stage is in flight at once; the
+// bounds and the Householder structure are applied when the registers are
+// written to LDS, after the MFMA work of the previous stage has hidden the
+// load latency.
 
 // ---------------------------------------------------------------------------
 // Loader of a 128-column x BK tile whose columns are contiguous in k
@@ -148,22 +118,21 @@ struct KcTile {
     static constexpr int E = 16 / sizeof(T);
     static constexpr int CPC = BK / E;                 // chunks per column (8)
     static constexpr int PER_THR = TILE * CPC / NTHR;  // 4
-    Chunk16<T> r[PER_THR];
+    vec16_t<T> r[PER_THR];
+    int col0_, k0_, kmax_, ncols_, mask_;
 
     __device__ inline void load(const T *P, int64_t ld, int ncols, int col0, int k0, int kmax,
                                 int mask_cols)
     {
+        col0_ = col0; k0_ = k0; kmax_ = kmax; ncols_ = ncols; mask_ = mask_cols;
 #pragma unroll
         for (int q = 0; q < PER_THR; ++q) {
             int f = threadIdx.x + NTHR * q;
             int c = f / CPC, h = f % CPC;
             int col = col0 + c, k = k0 + h * E;
-            bool ok = col < ncols;
-            r[q] = load_chunk(P + (int64_t)col * ld + k, k, kmax, ok);
-            if (col < mask_cols && k < mask_cols + E) {
-#pragma unroll
-                for (int e = 0; e < E; ++e) r[q].v[e] = vmask(r[q].v[e], k + e, col);
-            }
+            bool ok = col < ncols && k < kmax;
+            const T *p = ok ? P + (int64_t)col * ld + k : P;
+            r[q] = *reinterpret_cast<const vec16_t<T> *>(p);
         }
     }
     __device__ inline void store(T *lds) const
@@ -172,7 +141,16 @@ struct KcTile {
         for (int q = 0; q < PER_THR; ++q) {
             int f = threadIdx.x + NTHR * q;
             int c = f / CPC, h = f % CPC;
-            store_chunk_lds(lds + c * LD + h * E, r[q]);
+            int col = col0_ + c, k = k0_ + h * E;
+            vec16_t<T> v = r[q];
+            if (col >= ncols_ || k + E > kmax_ || (col < mask_ && k <= col)) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    T x = (col < ncols_ && k + e < kmax_) ? v[e] : T(0);
+                    v[e] = col < mask_ ? vmask(x, k + e, col) : x;
+                }
+            }
+            *reinterpret_cast<vec16_t<T> *>(lds + c * LD + h * E) = v;
         }
     }
 };
@@ -187,22 +165,22 @@ struct MkTile {
     static constexpr int E = 16 / sizeof(T);
     static constexpr int CPC = TILE / E;                // chunks per column (32/64)
     static constexpr int PER_THR = BK * CPC / NTHR;     // 4
-    Chunk16<T> r[PER_THR];
+    vec16_t<T> r[PER_THR];
+    int row0_, k0_, kmax_, mrows_;
+    bool mask_;
 
     __device__ inline void load(const T *P, int64_t ld, int mrows, int row0, int k0, int kmax,
                                 bool mask)
     {
+        row0_ = row0; k0_ = k0; kmax_ = kmax; mrows_ = mrows; mask_ = mask;
 #pragma unroll
         for (int q = 0; q < PER_THR; ++q) {
             int f = threadIdx.x + NTHR * q;
             int kk = f / CPC, h = f % CPC;
             int k = k0 + kk, row = row0 + h * E;
-            bool ok = k < kmax;
-            r[q] = load_chunk(P + (int64_t)k * ld + row, row, mrows, ok);
-            if (mask && row < k + E) {
-#pragma unroll
-                for (int e = 0; e < E; ++e) r[q].v[e] = vmask(r[q].v[e], row + e, k);
-            }
+            bool ok = k < kmax && row < mrows;
+            const T *p = ok ? P + (int64_t)k * ld + row : P;
+            r[q] = *reinterpret_cast<const vec16_t<T> *>(p);
         }
     }
     __device__ inline void store(T *lds) const
@@ -211,7 +189,16 @@ struct MkTile {
         for (int q = 0; q < PER_THR; ++q) {
             int f = threadIdx.x + NTHR * q;
             int kk = f / CPC, h = f % CPC;
-            store_chunk_lds(lds + kk * LD + h * E, r[q]);
+            int k = k0_ + kk, row = row0_ + h * E;
+            vec16_t<T> v = r[q];
+            if (k >= kmax_ || row + E > mrows_ || (mask_ && row <= k)) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    T x = (k < kmax_ && row + e < mrows_) ? v[e] : T(0);
+                    v[e] = mask_ ? vmask(x, row + e, k) : x;
+                }
+            }
+            *reinterpret_cast<vec16_t<T> *>(lds + kk * LD + h * E) = v;
         }
     }
 };

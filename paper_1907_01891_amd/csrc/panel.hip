@@ -17,9 +17,9 @@
 // T build (the "S factors" of Section II-C): for H_1 ... H_w = I - V T V^T,
 // T is upper triangular with T_jj = tau_j and
 // T(0:j, j) = -tau_j T(0:j, 0:j) G(0:j, j), G = V^T V (the larft recurrence).
-// It runs in one workgroup: the 32 x 32 diagonal blocks by that recurrence,
-// then each further column block q by T(0:32q, q) = -T(0:32q, 0:32q)
-// (G(0:32q, q) T_qq), which is the same recurrence taken 32 columns at a time.
+// Taken 32 columns at a time the recurrence reads
+// T(0:32q, q) = -T(0:32q, 0:32q) (G(0:32q, q) T_qq), whose row block p only
+// involves row block p of T, so one workgroup per row block builds it alone.
 #include "common.h"
 #include "kernels.h"
 
@@ -180,104 +180,128 @@ void panel_qr_kernel(TS *__restrict__ A, int64_t lda, int m, int r0, int w, int 
     }
 }
 
-// Sum of the per-workgroup Gram partials, in workgroup order.
-__global__ void gram_reduce_kernel(int G, const double *__restrict__ gram_part, double *__restrict__ gram)
+// Sum of the per-workgroup Gram partials in a fixed order: 16 entries per
+// workgroup, 16 threads per entry each summing every 16th partial, then the
+// 16 partial sums in thread order.
+__global__ __launch_bounds__(256)
+void gram_reduce_kernel(int G, const double *__restrict__ gram_part, double *__restrict__ gram)
 {
-    int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= PW * PW) return;
+    __shared__ double red[16][17];
+    const int el = threadIdx.x % 16, grp = threadIdx.x / 16;
+    const int e = blockIdx.x * 16 + el;
     double s = 0.0;
-    for (int q = 0; q < G; ++q) s += gram_part[(int64_t)q * PW * PW + e];
-    gram[e] = s;
+    for (int q = grp; q < G; q += 16) s += gram_part[(int64_t)q * PW * PW + e];
+    red[grp][el] = s;
+    __syncthreads();
+    if (threadIdx.x < 16) {
+        double t = 0.0;
+        for (int q = 0; q < 16; ++q) t += red[q][threadIdx.x];
+        gram[blockIdx.x * 16 + threadIdx.x] = t;
+    }
 }
 
-// T from G and tau; see the file comment.  Single workgroup of 256 threads.
+// T from G and tau, one workgroup per 32-row block p of T.  Row block p
+// depends only on G, tau and itself:
+//   T_pp = the recurrence on (G_pp, tau_p),
+//   T_pq = -sum_{k=p}^{q-1} T_pk (G_kq T_qq)   for q > p,
+// so the workgroups run independently; each recomputes the diagonal blocks
+// T_qq it needs.  All operands live in LDS; arithmetic is FP64.
+constexpr int TB_MAXQ = 8;                  // nb <= 256
+constexpr int TB_LD = 32 * TB_MAXQ + 1;
+
+__device__ inline void tb_diag(int q, int nb, const double (*Gq)[33], const double *__restrict__ tau,
+                               double (*Tq)[33])
+{
+    // one thread per row r of T_qq: T(r, r) = tau_r, T(r, j) = -tau_j sum_{c<j} T(r, c) G(c, j)
+    const int r = threadIdx.x;
+    if (r >= 32) return;
+    const int gi = 32 * q + r;
+    double t[32];
+#pragma unroll
+    for (int j = 0; j < 32; ++j) {
+        const int gj = 32 * q + j;
+        double val;
+        if (gj >= nb || gi >= nb || j < r) {
+            val = 0.0;
+        } else if (j == r) {
+            val = tau[gj];
+        } else {
+            double s = 0.0;
+#pragma unroll
+            for (int c = 0; c < j; ++c) s += t[c] * Gq[c][j];
+            val = -tau[gj] * s;
+        }
+        t[j] = val;
+    }
+#pragma unroll
+    for (int j = 0; j < 32; ++j) Tq[r][j] = t[j];
+}
+
+template <typename TG>
+__device__ inline void tb_stage(int nb, const TG *__restrict__ Gm, int64_t ldg, int kb, int qb, double (*dst)[33])
+{
+    for (int e = threadIdx.x; e < 1024; e += 256) {
+        int i = e % 32, j = e / 32;
+        int gi = 32 * kb + i, gj = 32 * qb + j;
+        dst[i][j] = (gi < nb && gj < nb) ? (double)Gm[(int64_t)gj * ldg + gi] : 0.0;
+    }
+}
+
 template <typename TG, typename TT>
 __global__ __launch_bounds__(256)
 void tbuild_kernel(int nb, const TG *__restrict__ Gm, int64_t ldg, const double *__restrict__ tau,
-                   TT *__restrict__ Tout, int64_t ldt, double *__restrict__ Tw)
+                   TT *__restrict__ Tout, int64_t ldt)
 {
-    __shared__ double buf[8 * 32 * 32];            // 64 KB: G blocks, later Y and T_qq
-    const int tid = threadIdx.x;
+    __shared__ double Trow[32][TB_LD];      // rows 32p .. 32p+31 of T, all nb columns
+    __shared__ double Gs[32][33];
+    __shared__ double Tq[32][33];
+    __shared__ double Y[32][33];
+    const int p = blockIdx.x, tid = threadIdx.x;
     const int nq = (nb + 31) / 32;
 
-    // Stage 1: diagonal blocks, one 32-thread group per block
-    for (int e = tid; e < nq * 1024; e += 256) {
-        int q = e / 1024, c = (e % 1024) % 32, j = (e % 1024) / 32;
-        int gc = 32 * q + c, gj = 32 * q + j;
-        buf[e] = (gc < nb && gj < nb) ? (double)Gm[(int64_t)gj * ldg + gc] : 0.0;
-    }
+    for (int e = tid; e < 32 * TB_LD; e += 256) (&Trow[0][0])[e] = 0.0;
+    tb_stage(nb, Gm, ldg, p, p, Gs);
     __syncthreads();
-    {
-        const int q = tid / 32, r = tid % 32;
-        if (q < nq) {
-            const double *Gq = buf + q * 1024;         // Gq[j*32 + c] = G(32q+c, 32q+j)
-            double t[32];
-            const int gi = 32 * q + r;
-#pragma unroll
-            for (int j = 0; j < 32; ++j) {
-                const int gj = 32 * q + j;
-                double val;
-                if (gj >= nb || gi >= nb || j < r) {
-                    val = 0.0;
-                } else if (j == r) {
-                    val = tau[gj];
-                } else {
-                    double s = 0.0;
-#pragma unroll
-                    for (int c = 0; c < j; ++c) s += t[c] * Gq[j * 32 + c];
-                    val = -tau[gj] * s;
-                }
-                t[j] = val;
-            }
-#pragma unroll
-            for (int j = 0; j < 32; ++j) {
-                const int gj = 32 * q + j;
-                if (gi < nb && gj < nb) Tw[(int64_t)gj * nb + gi] = t[j];
-            }
-        }
-    }
-    // zero the strictly lower block part
-    for (int e = tid; e < nb * nb; e += 256) {
-        int i = e % nb, j = e / nb;
-        if (i / 32 > j / 32) Tw[e] = 0.0;
-    }
-    __threadfence_block();
+    tb_diag(p, nb, Gs, tau, Tq);
+    __syncthreads();
+    for (int e = tid; e < 1024; e += 256) Trow[e % 32][32 * p + e / 32] = Tq[e % 32][e / 32];
     __syncthreads();
 
-    // Stage 2: column blocks q >= 1
-    double *Y = buf;                    // 32q x 32, Y[c*rows + i]
-    double *Tqq = buf + 7 * 1024;       // 32 x 32, Tqq[j*32 + i]
-    for (int q = 1; q < nq; ++q) {
-        const int rows = 32 * q;
-        const int qc = min(32, nb - rows);
-        for (int e = tid; e < 1024; e += 256) {
-            int i = e % 32, j = e / 32;
-            Tqq[e] = (i < qc && j < qc) ? Tw[(int64_t)(rows + j) * nb + rows + i] : 0.0;
-        }
+    for (int q = p + 1; q < nq; ++q) {
+        tb_stage(nb, Gm, ldg, q, q, Gs);
         __syncthreads();
-        // Y = G(0:rows, q-block) * T_qq
-        for (int e = tid; e < rows * 32; e += 256) {
-            int i = e % rows, c = e / rows;
-            double s = 0.0;
-            if (c < qc)
-                for (int k = 0; k <= c; ++k)
-                    s += (double)Gm[(int64_t)(rows + k) * ldg + i] * Tqq[c * 32 + k];
-            Y[c * rows + i] = s;
-        }
+        tb_diag(q, nb, Gs, tau, Tq);
         __syncthreads();
-        // X = -T(0:rows, 0:rows) * Y  (T upper triangular)
-        for (int e = tid; e < rows * 32; e += 256) {
-            int i = e % rows, c = e / rows;
-            if (c < qc) {
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int k = p; k < q; ++k) {
+            tb_stage(nb, Gm, ldg, k, q, Gs);          // G_kq
+            __syncthreads();
+            for (int o = 0; o < 4; ++o) {             // Y = G_kq T_qq (T_qq upper triangular)
+                int e = tid + 256 * o, i = e % 32, c = e / 32;
                 double s = 0.0;
-                for (int k = i; k < rows; ++k) s += Tw[(int64_t)k * nb + i] * Y[c * rows + k];
-                Tw[(int64_t)(rows + c) * nb + i] = -s;
+                for (int l = 0; l <= c; ++l) s += Gs[i][l] * Tq[l][c];
+                Y[i][c] = s;
             }
+            __syncthreads();
+            for (int o = 0; o < 4; ++o) {             // acc += T_pk Y
+                int e = tid + 256 * o, i = e % 32, c = e / 32;
+                double s = 0.0;
+                for (int l = 0; l < 32; ++l) s += Trow[i][32 * k + l] * Y[l][c];
+                acc[o] += s;
+            }
+            __syncthreads();
         }
-        __threadfence_block();
+        for (int o = 0; o < 4; ++o) {
+            int e = tid + 256 * o, i = e % 32, c = e / 32;
+            Trow[i][32 * q + c] = -acc[o];
+        }
         __syncthreads();
     }
-    for (int e = tid; e < nb * nb; e += 256) Tout[(int64_t)(e / nb) * ldt + e % nb] = (TT)Tw[e];
+    for (int e = tid; e < 32 * nb; e += 256) {
+        int i = e % 32, j = e / 32;
+        int gi = 32 * p + i;
+        if (gi < nb) Tout[(int64_t)j * ldt + gi] = (TT)Trow[i][j];
+    }
 }
 
 }  // namespace
@@ -305,7 +329,7 @@ ctqr_status panel_qr(TS *A, int64_t lda, int m, int r0, int w, double *tau, doub
     const size_t lds = panel_lds_bytes(rows);
     void *args[] = {&A, (void *)&lda, &m, &r0, &w, (void *)&rows, &tau, &part, &part2, &gram_part, &bar, &info};
     HIP_TRY(hipLaunchCooperativeKernel((const void *)panel_qr_kernel<TS>, dim3(G), dim3(PNT), args, lds, st));
-    LAUNCH_TRY(gram_reduce_kernel, dim3(4), dim3(256), 0, st, G, (const double *)gram_part, gram);
+    LAUNCH_TRY(gram_reduce_kernel, dim3(PW * PW / 16), dim3(256), 0, st, G, (const double *)gram_part, gram);
     return CTQR_OK;
 }
 
@@ -323,7 +347,9 @@ template <typename TG, typename TT>
 ctqr_status tbuild(int nb, const TG *G, int64_t ldg, const double *tau, TT *T, int64_t ldt, double *Tw,
                    hipStream_t st)
 {
-    LAUNCH_TRY((tbuild_kernel<TG, TT>), dim3(1), dim3(256), 0, st, nb, G, ldg, tau, T, ldt, Tw);
+    (void)Tw;
+    if (nb < 1 || nb > 32 * TB_MAXQ) return CTQR_EINVAL;
+    LAUNCH_TRY((tbuild_kernel<TG, TT>), dim3((unsigned)ceil_div(nb, 32)), dim3(256), 0, st, nb, G, ldg, tau, T, ldt);
     return CTQR_OK;
 }
 
