@@ -47,7 +47,7 @@ def parse():
     p.add_argument("--workload", default="ct256")
     p.add_argument("--nb", type=int, default=256)
     p.add_argument("--max-iters", type=int, default=30)
-    p.add_argument("--tol", type=float, default=1e-14)
+    p.add_argument("--tol", type=float, default=1e-12)
     p.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU comparison run")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
     p.add_argument("--cpu-seconds", type=float, default=15.0)

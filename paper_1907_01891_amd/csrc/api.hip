@@ -130,6 +130,14 @@ int device_cus()
     return cus;
 }
 
+// Per-thread pinned word the refinement loop reads its convergence flag into.
+int *host_flag()
+{
+    thread_local int *p = nullptr;
+    if (!p && hipHostMalloc((void **)&p, 64, hipHostMallocDefault) != hipSuccess) p = nullptr;
+    return p;
+}
+
 ctqr_status ensure_setup()
 {
     static std::once_flag once;
@@ -267,6 +275,13 @@ ctqr_status solve_impl(int64_t m64, int64_t n64, const T *QR, int64_t lda, const
         if (s) return s;
         if ((s = refine_update<T>(n, S, w.xr, w.d32, w.ldxw, w.dmax, w.xmax, skip, st))) return s;
         if ((s = refine_check(S, w.dmax, w.xmax, tol, it, max_iters, w.hist, w.done, info, st))) return s;
+        // stop enqueuing once the device-side flag says the refinement ended
+        // (the kernels of any extra iteration would return at once anyway)
+        int *flag = host_flag();
+        if (!flag) return CTQR_EHIP;
+        HIP_TRY(hipMemcpyAsync(flag, w.done, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (*flag) break;
     }
     return rm_to_cm<double, double>(n, S, w.xr, X, ldx, nullptr, st);
 }

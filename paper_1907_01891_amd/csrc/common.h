@@ -47,11 +47,21 @@ __device__ inline void info_event(ctqr_info *info, int code, int col)
 // Arrival is a two-level tree: each workgroup bumps the counter of its group
 // of GB_GROUP workgroups; the last arriver of a group bumps the root counter;
 // the last group releases everyone by publishing the new generation, which
-// the workgroups poll with relaxed loads.  No address sees more than
-// GB_GROUP atomics per barrier.  `bar` points at GB_WORDS zeroed words owned
-// by this launch; `epoch` counts the barriers passed.  The wait is bounded:
-// after ~2^26 polls it records CTQR_BARRIER_TIMEOUT and lets the workgroup
-// continue, so every wave exits.  Returns false on a time-out.
+// the workgroups poll.  No address sees more than GB_GROUP atomics per
+// barrier.  `bar` points at GB_WORDS zeroed words owned by this launch;
+// `epoch` counts the barriers passed.
+//
+// No cache-maintenance fences: data exchanged across workgroups must be
+// written with store_coherent and read with load_coherent (agent-scope
+// atomics, performed at the device-coherent level past the per-XCD L2s).
+// Every thread waits for its own stores to complete before the workgroup
+// arrives, and the counters and the generation word are themselves atomics,
+// so a workgroup that sees the new generation sees every store made before
+// any arrival.
+//
+// The wait is bounded: after ~2^26 polls it records CTQR_BARRIER_TIMEOUT and
+// lets the workgroup continue, so every wave exits.  Returns false on a
+// time-out.
 // ---------------------------------------------------------------------------
 #define GB_GROUP 16
 #define GB_LINE 32                       /* words per counter (128-byte lines) */
@@ -60,6 +70,7 @@ __device__ inline void info_event(ctqr_info *info, int code, int col)
 
 __device__ inline bool grid_barrier(unsigned *bar, unsigned &epoch, ctqr_info *info)
 {
+    __builtin_amdgcn_s_waitcnt(0);          // this thread's stores have completed
     __syncthreads();
     ++epoch;
     __shared__ int timed_out;
@@ -68,14 +79,13 @@ __device__ inline bool grid_barrier(unsigned *bar, unsigned &epoch, ctqr_info *i
         const unsigned G = gridDim.x, g = blockIdx.x / GB_GROUP;
         const unsigned ngroups = (G + GB_GROUP - 1) / GB_GROUP;
         const unsigned gsize = min((unsigned)GB_GROUP, G - g * GB_GROUP);
-        __threadfence();
-        unsigned old = __hip_atomic_fetch_add(&bar[GB_LINE * (1 + g)], 1u, __ATOMIC_ACQ_REL,
+        unsigned old = __hip_atomic_fetch_add(&bar[GB_LINE * (1 + g)], 1u, __ATOMIC_RELAXED,
                                               __HIP_MEMORY_SCOPE_AGENT);
         if (old == epoch * gsize - 1) {
-            unsigned o2 = __hip_atomic_fetch_add(&bar[GB_LINE * (1 + GB_MAX_GROUPS)], 1u, __ATOMIC_ACQ_REL,
+            unsigned o2 = __hip_atomic_fetch_add(&bar[GB_LINE * (1 + GB_MAX_GROUPS)], 1u, __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_AGENT);
             if (o2 == epoch * ngroups - 1)
-                __hip_atomic_store(&bar[0], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&bar[0], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         unsigned polls = 0;
         while (__hip_atomic_load(&bar[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
@@ -86,14 +96,14 @@ __device__ inline bool grid_barrier(unsigned *bar, unsigned &epoch, ctqr_info *i
                 break;
             }
         }
-        __threadfence();
     }
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);   // no compiler motion across the wait
     __syncthreads();
     return !timed_out;
 }
 
-// Agent-scope coherent load/store of a double (bypasses stale per-XCD L2 lines
-// together with the barrier's release/acquire).
+// Agent-scope coherent store/load of a double, for data exchanged through
+// grid_barrier.
 __device__ inline void store_coherent(double *p, double v)
 {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

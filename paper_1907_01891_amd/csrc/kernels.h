@@ -26,7 +26,7 @@ ctqr_status tbuild(int nb, const TG *G, int64_t ldg, const double *tau, TT *T, i
                    hipStream_t st);
 
 // ---- trsm.hip --------------------------------------------------------------
-constexpr int TRSM_BT = 64;   // diagonal block of the block substitutions
+constexpr int TRSM_BT = 256;  // diagonal block of the block substitutions
 template <typename T>
 ctqr_status trinv_blocks(int n, const T *R, int64_t ldr, T *Rinv, T *RinvT, ctqr_info *info,
                          hipStream_t st);

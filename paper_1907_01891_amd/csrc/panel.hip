@@ -31,14 +31,15 @@ constexpr int SLD = PW + 1;       // slab LDS row stride (doubles)
 
 __device__ inline double block_sum(double v, double *red)
 {
-    // Deterministic tree sum over the 256 threads of the workgroup.
-    red[threadIdx.x] = v;
+    // Deterministic sum over the 256 threads: butterfly within each wave,
+    // then the four wave sums in wave order.
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (threadIdx.x % CTQR_WAVE == 0) red[threadIdx.x / CTQR_WAVE] = v;
     __syncthreads();
-    for (int s = PNT / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-        __syncthreads();
-    }
     double r = red[0];
+#pragma unroll
+    for (int w = 1; w < PNT / CTQR_WAVE; ++w) r += red[w];
     __syncthreads();
     return r;
 }

@@ -21,7 +21,12 @@ void spmm_rm_kernel(int64_t rows, int S, int SW, const int64_t *__restrict__ ptr
 {
     if (skip && *skip) return;
     const int rpb = 256 / SW;
-    const int64_t i = (int64_t)blockIdx.x * rpb + threadIdx.x / SW;
+    // consecutive rows (neighbouring rays, which cross neighbouring pixels)
+    // go to the same XCD so the gathered rows of x are shared in its L2
+    unsigned blk = blockIdx.x;
+    const unsigned per = gridDim.x / 8;
+    if (blk < per * 8) blk = (blk % 8) * per + blk / 8;
+    const int64_t i = (int64_t)blk * rpb + threadIdx.x / SW;
     const int lane = threadIdx.x % SW;
     if (i >= rows) return;
     const int64_t b = ptr[i], e = ptr[i + 1];

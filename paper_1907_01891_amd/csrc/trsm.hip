@@ -7,9 +7,13 @@
 //                      refinement's semi-normal equations):
 //                      Y_i = R_ii^-T C_i;  C_{i+1:} -= R_{i, i+1:}^T Y_i
 //
-// The diagonal 64 x 64 blocks are inverted once (trinv_blocks, one workgroup
-// per block, FP64 arithmetic), so both the diagonal solve and the off-diagonal
-// update are MFMA products; only the 64-row block chain is sequential.
+// The diagonal BT x BT blocks (BT = 256) are inverted once per solve
+// (trinv_blocks), so both the diagonal solve and the off-diagonal update are
+// MFMA products; only the chain of n / BT block rows is sequential.  Row
+// block p (32 rows) of inv(U), U upper triangular, depends only on U and on
+// itself: X_pp = inv(U_pp), X_pq = -(sum_{k=p}^{q-1} X_pk U_kq) X_qq, so each
+// 32-row block is built by its own workgroup (FP64, operands in LDS), each
+// recomputing the small diagonal inverses X_qq it needs.
 #include "common.h"
 #include "kernels.h"
 
@@ -17,42 +21,103 @@ namespace {
 
 constexpr int BT = TRSM_BT;
 
-// Inverse of each BT x BT upper-triangular diagonal block of R.  Thread j
-// computes column j of the inverse by back substitution on e_j.  Rinv holds
-// the inverse blocks (BT x n, block i at columns i*BT), RinvT their
-// transposes.  Zero or non-finite diagonals are reported (rank deficiency is
-// diagnosed separately by rdiag_check).
+constexpr int RB = 32;                 // row block of the inversion
+constexpr int NQ = BT / RB;            // row blocks per diagonal block
+constexpr int XLD = BT + 1;
+
+// Rs <- R(b*BT + 32*kb .., b*BT + 32*qb ..) as a 32 x 32 FP64 tile (zero
+// outside the n x n matrix)
 template <typename T>
-__global__ __launch_bounds__(BT)
+__device__ inline void stage_r(int n, const T *__restrict__ R, int64_t ldr, int base, int kb, int qb,
+                               double (*Rs)[33])
+{
+    for (int e = threadIdx.x; e < 1024; e += 256) {
+        int i = e % 32, j = e / 32;
+        int gi = base + 32 * kb + i, gj = base + 32 * qb + j;
+        Rs[i][j] = (gi < n && gj < n) ? (double)R[(int64_t)gj * ldr + gi] : 0.0;
+    }
+}
+
+// Xq <- inv(Rs) for an upper-triangular 32 x 32 tile: thread c builds column
+// c by back substitution (rows past the matrix edge give zero columns).
+__device__ inline void inv32(const double (*Rs)[33], double (*Xq)[33], int valid)
+{
+    const int c = threadIdx.x;
+    if (c >= 32) return;
+    double x[32];
+#pragma unroll
+    for (int i = 31; i >= 0; --i) {
+        double v = 0.0;
+        if (i <= c && c < valid) {
+            double s = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+            for (int k = i + 1; k < 32; ++k)
+                if (k <= c) s -= Rs[i][k] * x[k];
+            v = s / Rs[i][i];
+        }
+        x[i] = v;
+    }
+#pragma unroll
+    for (int i = 0; i < 32; ++i) Xq[i][c] = x[i];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256)
 void trinv_kernel(int n, const T *__restrict__ R, int64_t ldr, T *__restrict__ Rinv,
                   T *__restrict__ RinvT)
 {
-    __shared__ double Rs[BT][BT + 1];
-    __shared__ double Xs[BT][BT + 1];
-    const int blk = blockIdx.x, j = threadIdx.x;
+    __shared__ double Xrow[RB][XLD];
+    __shared__ double Rs[32][33];
+    __shared__ double Xq[32][33];
+    __shared__ double Y[32][33];
+    const int blk = blockIdx.x, p = blockIdx.y, tid = threadIdx.x;
     const int base = blk * BT;
     const int nbk = min(BT, n - base);
-    for (int c = 0; c < BT; ++c) {
-        double v = 0.0;
-        if (j < nbk && c < nbk) v = (double)R[(int64_t)(base + c) * ldr + base + j];
-        Rs[j][c] = v;   // Rs[row][col]
-    }
+    const int nq = (nbk + RB - 1) / RB;
+    if (p >= nq) return;
+    for (int e = tid; e < RB * XLD; e += 256) (&Xrow[0][0])[e] = 0.0;
+    stage_r(n, R, ldr, base, p, p, Rs);
     __syncthreads();
-    // column j of inv(R_bb)
-    for (int i = BT - 1; i >= 0; --i) {
-        double x = 0.0;
-        if (j < nbk && i < nbk && i <= j) {
-            double s = (i == j) ? 1.0 : 0.0;
-            for (int k = i + 1; k <= j; ++k) s -= Rs[i][k] * Xs[k][j];
-            x = s / Rs[i][i];
+    inv32(Rs, Xq, nbk - RB * p);
+    __syncthreads();
+    for (int e = tid; e < 1024; e += 256) Xrow[e % 32][RB * p + e / 32] = Xq[e % 32][e / 32];
+    __syncthreads();
+    for (int q = p + 1; q < nq; ++q) {
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int k = p; k < q; ++k) {
+            stage_r(n, R, ldr, base, k, q, Rs);        // U_kq
+            __syncthreads();
+            for (int o = 0; o < 4; ++o) {
+                int e = tid + 256 * o, i = e % 32, c = e / 32;
+                double s = 0.0;
+                for (int l = 0; l < 32; ++l) s += Xrow[i][RB * k + l] * Rs[l][c];
+                acc[o] += s;
+            }
+            __syncthreads();
         }
-        Xs[i][j] = x;
+        for (int o = 0; o < 4; ++o) {
+            int e = tid + 256 * o;
+            Y[e % 32][e / 32] = acc[o];
+        }
+        stage_r(n, R, ldr, base, q, q, Rs);
+        __syncthreads();
+        inv32(Rs, Xq, nbk - RB * q);
+        __syncthreads();
+        for (int o = 0; o < 4; ++o) {                  // X_pq = -Y X_qq
+            int e = tid + 256 * o, i = e % 32, c = e / 32;
+            double s = 0.0;
+            for (int l = 0; l <= c; ++l) s += Y[i][l] * Xq[l][c];
+            Xrow[i][RB * q + c] = -s;
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    for (int i = 0; i < BT; ++i) {
-        // Rinv block: column j contiguous in i; RinvT block: (i, j) -> (j, i)
-        Rinv[(int64_t)(base + j) * BT + i] = (T)Xs[i][j];
-        RinvT[(int64_t)(base + i) * BT + j] = (T)Xs[i][j];
+    // Rinv block: BT x BT at columns base.., column-major (ld BT); RinvT its transpose
+    for (int e = tid; e < RB * BT; e += 256) {
+        int i = e % RB, j = e / RB;
+        int gi = RB * p + i;
+        T v = (T)Xrow[i][j];
+        Rinv[(int64_t)(base + j) * BT + gi] = v;
+        RinvT[(int64_t)(base + gi) * BT + j] = v;
     }
 }
 
@@ -109,7 +174,7 @@ ctqr_status trinv_blocks(int n, const T *R, int64_t ldr, T *Rinv, T *RinvT, ctqr
                          hipStream_t st)
 {
     (void)info;
-    LAUNCH_TRY(trinv_kernel<T>, dim3((unsigned)ceil_div(n, BT)), dim3(BT), 0, st, n, R, ldr, Rinv, RinvT);
+    LAUNCH_TRY(trinv_kernel<T>, dim3((unsigned)ceil_div(n, BT), NQ), dim3(256), 0, st, n, R, ldr, Rinv, RinvT);
     return CTQR_OK;
 }
 
