@@ -207,7 +207,7 @@ ctqr_status factor_impl(int64_t m64, int64_t n64, T *A, int64_t lda, int nb, T *
             HIP_TRY(hipEventCreate(&rec.b));
             HIP_TRY(hipEventRecord(rec.a, st));
         }
-        s = gemm_nn<T>(m - k0, nc, nbk, V, lda, 1, w.W2, nb, T(-1), C, lda, nullptr, st);
+        s = gemm_nn<T>(m - k0, nc, nbk, V, lda, 1, w.W2, nb, T(-1), C, lda, nullptr, st, 1);
         if (s) return s;
         if (prof) {
             HIP_TRY(hipEventRecord(rec.b, st));

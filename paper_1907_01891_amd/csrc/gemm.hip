@@ -244,47 +244,38 @@ __device__ inline void mfma_step(const T *opA, const T *opB, int wn, int wm,
         }
         return;
     }
+    // FP32: 4 k-groups of 8 per stage; the LDS fragments of k-group g+1 are
+    // fetched into the second register set while the 16 MFMAs of group g issue.
+    constexpr int NG = M::BK / M::KG;
+    floatx4 a[2][M::NBLK], b[2][M::NBLK];
+    auto fetch = [&](int g, int buf) {
+        const int kk = g * M::KG + 4 * slot;
 #pragma unroll
-    for (int kg = 0; kg < M::BK; kg += M::KG) {
-        T a[M::NBLK][4], b[M::NBLK][4];
-        const int kk = kg + 4 * slot;
-#pragma unroll
-        for (int ib = 0; ib < M::NBLK; ++ib) {
-            const T *p = opA + (wn + ib * M::MB + li) * KcTile<T>::LD + kk;
-            if constexpr (sizeof(T) == 4) {
-                floatx4 x = *reinterpret_cast<const floatx4 *>(p);
-                a[ib][0] = x[0]; a[ib][1] = x[1]; a[ib][2] = x[2]; a[ib][3] = x[3];
-            } else {
-                doublex2 x = *reinterpret_cast<const doublex2 *>(p);
-                doublex2 y = *reinterpret_cast<const doublex2 *>(p + 2);
-                a[ib][0] = x[0]; a[ib][1] = x[1]; a[ib][2] = y[0]; a[ib][3] = y[1];
-            }
-        }
+        for (int ib = 0; ib < M::NBLK; ++ib)
+            a[buf][ib] = *reinterpret_cast<const floatx4 *>(opA + (wn + ib * M::MB + li) * KcTile<T>::LD + kk);
 #pragma unroll
         for (int jb = 0; jb < M::NBLK; ++jb) {
             if constexpr (B_KC) {
-                const T *p = opB + (wm + jb * M::MB + li) * KcTile<T>::LD + kk;
-                if constexpr (sizeof(T) == 4) {
-                    floatx4 x = *reinterpret_cast<const floatx4 *>(p);
-                    b[jb][0] = x[0]; b[jb][1] = x[1]; b[jb][2] = x[2]; b[jb][3] = x[3];
-                } else {
-                    doublex2 x = *reinterpret_cast<const doublex2 *>(p);
-                    doublex2 y = *reinterpret_cast<const doublex2 *>(p + 2);
-                    b[jb][0] = x[0]; b[jb][1] = x[1]; b[jb][2] = y[0]; b[jb][3] = y[1];
-                }
+                b[buf][jb] = *reinterpret_cast<const floatx4 *>(opB + (wm + jb * M::MB + li) * KcTile<T>::LD + kk);
             } else {
                 const T *p = opB + kk * MkTile<T>::LD + wm + jb * M::MB + li;
 #pragma unroll
-                for (int s = 0; s < 4; ++s) b[jb][s] = p[s * MkTile<T>::LD];
+                for (int s = 0; s < 4; ++s) b[buf][jb][s] = p[s * MkTile<T>::LD];
             }
         }
+    };
+    fetch(0, 0);
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+        const int cb = g & 1;
+        if (g + 1 < NG) fetch(g + 1, cb ^ 1);
 #pragma unroll
         for (int s = 0; s < 4; ++s)
 #pragma unroll
             for (int ib = 0; ib < M::NBLK; ++ib)
 #pragma unroll
                 for (int jb = 0; jb < M::NBLK; ++jb)
-                    acc[ib][jb] = mfma(a[ib][s], b[jb][s], acc[ib][jb]);
+                    acc[ib][jb] = mfma(a[cb][ib][s], b[cb][jb][s], acc[ib][jb]);
     }
 }
 
@@ -407,7 +398,9 @@ __global__ void splitk_reduce_kernel(int M, int N, int splits, const T *__restri
 // ---------------------------------------------------------------------------
 // NN:  C += alpha * A B   (A: M x K, optionally a Householder block; B: K x N)
 // ---------------------------------------------------------------------------
-template <typename T>
+// KIND only separates the symbols of the launch sites in a profile: 1 is the
+// trailing update of the factorization, 0 every other use.
+template <typename T, int KIND>
 __global__ __launch_bounds__(NTHR, 2)
 void gemm_nn_kernel(int M, int N, int K,
                     const T *__restrict__ A, int64_t lda, int amask,
@@ -432,6 +425,24 @@ void gemm_nn_kernel(int M, int N, int K,
         for (int j = 0; j < Mt::NBLK; ++j)
 #pragma unroll
             for (int e = 0; e < acc_len<T>(); ++e) acc[i][j][e] = T(0);
+
+    // FP32: fetch the C tile now; its HBM latency hides behind the K loop
+    constexpr bool PRE = sizeof(T) == 4;
+    T cpre[PRE ? Mt::NBLK : 1][PRE ? Mt::NBLK : 1][PRE ? 16 : 1];
+    if constexpr (PRE) {
+#pragma unroll
+        for (int ib = 0; ib < Mt::NBLK; ++ib)
+#pragma unroll
+            for (int jb = 0; jb < Mt::NBLK; ++jb)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    int n, m;
+                    acc_coords<T>(ib, jb, r, n, m);
+                    n += n0 + wn;
+                    m += m0 + wm;
+                    cpre[ib][jb][r] = (m < M && n < N) ? C[(int64_t)n * ldc + m] : T(0);
+                }
+    }
 
     MkTile<T> la;
     KcTile<T> lb;
@@ -468,7 +479,10 @@ void gemm_nn_kernel(int M, int N, int K,
                 m += m0 + wm;
                 if (m < M && n < N) {
                     T *c = C + (int64_t)n * ldc + m;
-                    *c += alpha * acc[ib][jb][r];
+                    if constexpr (PRE)
+                        *c = cpre[ib][jb][r] + alpha * acc[ib][jb][r];
+                    else
+                        *c += alpha * acc[ib][jb][r];
                 }
             }
 }
@@ -536,12 +550,16 @@ ctqr_status gemm_tn(int M, int N, int K, const T *A, int64_t lda, int amask, con
 
 template <typename T>
 ctqr_status gemm_nn(int M, int N, int K, const T *A, int64_t lda, int amask, const T *B,
-                    int64_t ldb, T alpha, T *C, int64_t ldc, const int *skip, hipStream_t st)
+                    int64_t ldb, T alpha, T *C, int64_t ldc, const int *skip, hipStream_t st, int kind)
 {
     if (M <= 0 || N <= 0 || K <= 0) return CTQR_OK;
     dim3 grid((unsigned)(ceil_div(M, TILE) * ceil_div(N, TILE)));
-    LAUNCH_TRY(gemm_nn_kernel<T>, grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B, ldb, alpha,
-               C, ldc, skip);
+    if (kind == 1)
+        LAUNCH_TRY((gemm_nn_kernel<T, 1>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B, ldb, alpha,
+                   C, ldc, skip);
+    else
+        LAUNCH_TRY((gemm_nn_kernel<T, 0>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B, ldb, alpha,
+                   C, ldc, skip);
     return CTQR_OK;
 }
 
@@ -552,6 +570,6 @@ template ctqr_status gemm_tn<double>(int, int, int, const double *, int64_t, int
                                      int64_t, int, double, double, double *, int64_t, double *,
                                      size_t, const int *, hipStream_t);
 template ctqr_status gemm_nn<float>(int, int, int, const float *, int64_t, int, const float *,
-                                    int64_t, float, float *, int64_t, const int *, hipStream_t);
+                                    int64_t, float, float *, int64_t, const int *, hipStream_t, int);
 template ctqr_status gemm_nn<double>(int, int, int, const double *, int64_t, int, const double *,
-                                     int64_t, double, double *, int64_t, const int *, hipStream_t);
+                                     int64_t, double, double *, int64_t, const int *, hipStream_t, int);

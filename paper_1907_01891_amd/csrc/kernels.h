@@ -11,7 +11,8 @@ ctqr_status gemm_tn(int M, int N, int K, const T *A, int64_t lda, int amask, con
                     size_t part_elems, const int *skip, hipStream_t st);
 template <typename T>
 ctqr_status gemm_nn(int M, int N, int K, const T *A, int64_t lda, int amask, const T *B,
-                    int64_t ldb, T alpha, T *C, int64_t ldc, const int *skip, hipStream_t st);
+                    int64_t ldb, T alpha, T *C, int64_t ldc, const int *skip, hipStream_t st,
+                    int kind = 0);
 
 // ---- panel.hip -------------------------------------------------------------
 int panel_rows_per_wg(int mrem, int ncu);
