@@ -186,8 +186,13 @@ ctqr_status ctqr_solve_workspace(int64_t m, int64_t n, ctqr_dtype dtype, int32_t
  *   A64    optional FP64 sparse A (from ctqr_build_system_matrix).  When given,
  *          the solution is refined by corrected semi-normal equations:
  *          r = B - A X (FP64), R^T y = A^T r, R d = y, X += d, until
- *          max_s ||d_s||_inf <= tol ||X_s||_inf or max_iters iterations.
- *          NULL = no refinement.
+ *          max_s ||d_s||_inf <= tol ||X_s||_inf, or the relative update
+ *          stops shrinking while below 1e-9 (the rounding floor of the FP64
+ *          residuals: converged), or it stops shrinking above that floor or
+ *          max_iters is reached (CTQR_NOT_CONVERGED).  NULL = no refinement.
+ *          With refinement the call waits on the stream after each
+ *          iteration (it reads the convergence flag back) and returns once
+ *          the refinement has ended; without it the call only enqueues.
  *   info   device: iterations, last relative update, CTQR_NOT_CONVERGED /
  *          CTQR_NONFINITE. */
 ctqr_status ctqr_qr_solve_slices(int64_t m, int64_t n, ctqr_dtype dtype,

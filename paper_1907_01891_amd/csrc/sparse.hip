@@ -214,11 +214,19 @@ void refine_check_kernel(int S, unsigned long long *dmax, unsigned long long *xm
         } else if (rel <= tol) {
             *done = 1;
         } else {
+            // Updates that stop shrinking (twice no better than 0.9x the
+            // previous one) have met the rounding floor of the FP64 residuals
+            // when they are already tiny (<= STALL_FLOOR): that is the
+            // attainable accuracy, so it ends the refinement normally.  A
+            // stall above that floor means the iteration does not contract.
+            const double STALL_FLOOR = 1e-9;
             double prev = hist[0];
             int stalls = (it > 0 && rel > 0.9 * prev) ? (int)hist[1] + 1 : 0;
             hist[0] = rel;
             hist[1] = stalls;
-            if (stalls >= 2 || it + 1 >= max_iters) {
+            if (stalls >= 2 && rel <= STALL_FLOOR) {
+                *done = 1;
+            } else if (stalls >= 2 || it + 1 >= max_iters) {
                 info_event(info, CTQR_NOT_CONVERGED, -1);
                 *done = 1;
             }
