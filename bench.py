@@ -51,7 +51,46 @@ def parse():
     p.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU comparison run")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--calibrate-copy", action="store_true",
+                   help="only run 3 device-to-device copies of 1 GiB (counter calibration) and exit")
     return p.parse_args()
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_nn_trailing_update_ct256_traffic.txt")
+
+
+def gemm_source_hash():
+    import hashlib
+    with open(os.path.join(ROOT, "paper_1907_01891_amd", "csrc", "gemm.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(workload):
+    """HBM bytes per launch of the trailing-update GEMM from the committed
+    counter summary (FETCH_SIZE + WRITE_SIZE scaled by a copy kernel), or None
+    if there is none for this workload or the kernel source changed since."""
+    try:
+        kv = dict(l.strip().split("=", 1) for l in open(TRAFFIC_FILE)
+                  if "=" in l and not l.lstrip().startswith("#"))
+    except OSError:
+        return None
+    if kv.get("workload") != workload or kv.get("gemm_hip_sha256") != gemm_source_hash():
+        return None
+    return float(kv["bytes_per_launch"])
+
+
+def calibrate_copy():
+    """Three 1 GiB device-to-device copies (a plain copy kernel of known size)."""
+    import torch
+    x = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    x.fill_(1.0)
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibrate_copy_bytes_read": x.numel() * 4, "calibrate_copy_bytes_written": y.numel() * 4,
+                      "copies": 3}))
 
 
 def cpu_baseline(workload, target_s):
@@ -89,6 +128,9 @@ def main():
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     import numpy as np
     import torch
     from synthetic import get_workload, phantom_batch, noise_batch, NOISE_REL_LEVEL
@@ -215,6 +257,16 @@ def main():
         log("cpu baseline %.4f TFLOP/s (%s)" % (cpu["value"], cpu["sample"]))
 
     achieved = kern_flops / (kern_ms * 1e-3) / 1e12 if kern_ms > 0 else None
+    # algorithmic HBM bytes of one trailing update C -= V W' (FP32): read and
+    # write C (m_k x n_k), read V (m_k x nb) and W' (nb x n_k) once
+    alg, nl = 0.0, 0
+    for k0 in range(0, n, args.nb):
+        nbk = min(args.nb, n - k0)
+        nc = n - k0 - nbk
+        if nc > 0:
+            alg += 8.0 * (m - k0) * nc + 4.0 * nbk * ((m - k0) + nc)
+            nl += 1
+    alg_bytes = alg / nl if nl else None
     out = {
         "metric": "QR TFLOP/s + slices/s at 256^2 (mixed vs FP64 GPU, rel err <= 1e-10)",
         "value": qr_tf,
@@ -247,7 +299,10 @@ def main():
             "bound": "mfma", "kernel": "gemm_nn_kernel<float> (trailing update C -= V W')",
             "achieved": achieved, "peak": PEAK_TFLOPS["f32"], "unit": "TFLOP/s",
             "frac": (achieved / PEAK_TFLOPS["f32"]) if achieved else None,
-            "traffic": None, "launches": launches,
+            "traffic": measured_traffic(args.workload) if args.nb == 256 else None,
+            "traffic_unit": "bytes per launch (HBM, FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "algorithmic_bytes_per_launch": alg_bytes,
+            "launches": launches,
             "avg_launch_ms": kern_ms / launches if launches else None,
             "flops_per_launch": kern_flops / launches if launches else None,
         },
