@@ -61,7 +61,7 @@ FactorWS<T> carve_factor(void *work, int64_t m, int64_t n, int nb)
     FactorWS<T> w;
     w.bars = c.take<unsigned>((ceil_div(n, PANEL_W) + 1) * GB_WORDS);
     w.part = c.take<double>(MAX_PANEL_WG + 1);
-    w.part2 = c.take<double>((int64_t)MAX_PANEL_WG * PANEL_W);
+    w.part2 = c.take<double>(2LL * MAX_PANEL_WG * PANEL_XCH_STRIDE);
     w.gram_part = c.take<double>((int64_t)MAX_PANEL_WG * PANEL_W * PANEL_W);
     w.gram = c.take<double>(PANEL_W * PANEL_W);
     w.Tw = c.take<double>((int64_t)nb * nb);

@@ -14,7 +14,8 @@ ctqr_status gemm_nn(int M, int N, int K, const T *A, int64_t lda, int amask, con
                     int64_t ldb, T alpha, T *C, int64_t ldc, const int *skip, hipStream_t st,
                     int kind = 0);
 
-// ---- panel.hip -------------------------------------------------------------
+// ---- panel_qr.hip ----------------------------------------------------------
+constexpr int PANEL_XCH_STRIDE = 40;   // doubles per workgroup per exchange buffer (two buffers)
 int panel_rows_per_wg(int mrem, int ncu);
 int panel_max_rows_per_wg();
 ctqr_status panel_setup(int max_rows);

@@ -4,15 +4,23 @@
 // Section II-C): unblocked Householder QR of a tall m_rem x w panel
 // (w <= 32).  The panel's rows are split into contiguous slabs, one per
 // workgroup, held in LDS in FP64 for the whole panel whatever the storage
-// precision.  For each column the workgroups exchange one partial sum of
-// squares (grid barrier 1), all of them form beta/tau/v identically, then
-// exchange the partial products v^T a_c for the columns to the right (grid
-// barrier 2) and update their slab.  Reflector convention (LAPACK larfg):
+// precision.  Reflector convention (LAPACK larfg):
 // beta = -sign(alpha) ||[alpha; x]||, tau = (beta - alpha) / beta,
-// v = [1; x / (alpha - beta)]; tau = 0 when x = 0.  Every cross-workgroup sum
-// is taken in workgroup order, so the result is deterministic and identical
-// in every workgroup.  The kernel also leaves each workgroup's partial Gram
-// matrix V^T V of the panel for the T build.
+// v = [1; x / (alpha - beta)]; tau = 0 when x = 0.
+//
+// One grid barrier per column: after forming reflector j, each workgroup
+// publishes its partial products w_c = v^T a_c for the columns c > j and,
+// for column j+1, its partial sums S_aa = sum a^2, S_av = sum a v and
+// S_vv = sum v^2 over the rows below the next pivot.  After the exchange
+// every workgroup knows w and the squared norm of column j+1 after the
+// update, S_aa - 2 tau w S_av + (tau w)^2 S_vv, so the next reflector needs
+// no second exchange.  When that difference has cancelled below S_aa / 4
+// (possible loss of digits) every workgroup instead takes the exact route:
+// one more exchange of plain partial sums of squares of the updated column.
+// The decision depends only on exchanged totals, so all workgroups take the
+// same route.  Every cross-workgroup sum is taken in workgroup order, so the
+// result is deterministic and identical in every workgroup.  The kernel
+// also leaves each workgroup's partial Gram matrix V^T V for the T build.
 //
 // T build (the "S factors" of Section II-C): for H_1 ... H_w = I - V T V^T,
 // T is upper triangular with T_jj = tau_j and
@@ -28,6 +36,10 @@ namespace {
 constexpr int PNT = 256;          // threads per panel workgroup
 constexpr int PW = 32;            // max panel width
 constexpr int SLD = PW + 1;       // slab LDS row stride (doubles)
+constexpr int PS = PANEL_XCH_STRIDE;   // per-workgroup exchange slots (see below)
+// exchange slots: [0, 32) partial w_c for c = j+1+slot; 32: S_aa; 33: S_av;
+// 34: S_vv; 35, 36: a(p+1, j+1) and v(p+1) before the update (workgroup 0)
+constexpr int X_SAA = 32, X_SAV = 33, X_SVV = 34, X_A1 = 35, X_V1 = 36, X_N = 37;
 
 __device__ inline double block_sum(double v, double *red)
 {
@@ -51,9 +63,10 @@ void panel_qr_kernel(TS *__restrict__ A, int64_t lda, int m, int r0, int w, int 
                      double *__restrict__ gram_part, unsigned *bar, ctqr_info *info)
 {
     extern __shared__ double slab[];              // rows_per_wg x SLD
-    __shared__ double red[PNT];
-    __shared__ double wred[8][PW];
-    __shared__ double wcol[PW];
+    __shared__ double red[PNT / CTQR_WAVE];
+    __shared__ double wred[PNT / PW][PS];
+    __shared__ double red4[PNT / CTQR_WAVE][CTQR_WAVE];
+    __shared__ double xch[PS];
     __shared__ double tau_s[PW];
 
     const int G = gridDim.x, wg = blockIdx.x, tid = threadIdx.x;
@@ -67,78 +80,109 @@ void panel_qr_kernel(TS *__restrict__ A, int64_t lda, int m, int r0, int w, int 
     }
     __syncthreads();
 
+    // pivot rows r0 .. r0+w-1 all lie in workgroup 0's slab (rows_per_wg >= 64)
+    bool have = false;           // norm and alpha of column j known from the last exchange
+    double ss = 0.0, alpha = 0.0;
     bool nonfinite = false;
     for (int j = 0; j < w; ++j) {
         const int p = r0 + j;                     // pivot row
-        const int owner = (p - r0) / rows_per_wg;
-
-        // partial sum of squares below the pivot
-        double ss = 0.0;
-        for (int rr = tid; rr < nrows; rr += PNT)
-            if (row0 + rr > p) {
-                double x = slab[rr * SLD + j];
-                ss += x * x;
+        if (!have) {
+            double s = 0.0;
+            for (int rr = tid; rr < nrows; rr += PNT)
+                if (row0 + rr > p) {
+                    double x = slab[rr * SLD + j];
+                    s += x * x;
+                }
+            s = block_sum(s, red);
+            if (tid == 0) {
+                store_coherent(&part[wg], s);
+                if (wg == 0) store_coherent(&part[G], slab[(p - row0) * SLD + j]);
             }
-        ss = block_sum(ss, red);
-        if (tid == 0) {
-            store_coherent(&part[wg], ss);
-            if (wg == owner) store_coherent(&part[G], slab[(p - row0) * SLD + j]);
+            grid_barrier(bar, epoch, info);
+            double t = 0.0;
+            for (int q = tid; q < G; q += PNT) t += load_coherent(&part[q]);
+            ss = block_sum(t, red);
+            alpha = load_coherent(&part[G]);
         }
-        grid_barrier(bar, epoch, info);
 
-        double tot = 0.0;
-        for (int q = tid; q < G; q += PNT) tot += load_coherent(&part[q]);
-        tot = block_sum(tot, red);
-        const double alpha = load_coherent(&part[G]);
         double tau = 0.0, beta = alpha, scale = 1.0;
-        if (tot != 0.0) {
-            double norm = sqrt(alpha * alpha + tot);
+        if (ss != 0.0) {
+            double norm = sqrt(alpha * alpha + ss);
             beta = alpha >= 0.0 ? -norm : norm;
             tau = (beta - alpha) / beta;
             scale = 1.0 / (alpha - beta);
         }
-        if (!(tot == tot) || !(alpha == alpha) || isinf(tot) || isinf(alpha)) nonfinite = true;
+        if (!(ss == ss) || !(alpha == alpha) || isinf(ss) || isinf(alpha)) nonfinite = true;
         if (tid == 0) tau_s[j] = tau;
-
         if (tau != 0.0)
             for (int rr = tid; rr < nrows; rr += PNT)
                 if (row0 + rr > p) slab[rr * SLD + j] *= scale;
         __syncthreads();
 
+        have = false;
         if (j + 1 < w) {
-            // partial w_c = sum_{g >= p} v_g a_gc, v_p = 1, for c > j
+            double *x2 = part2 + (int64_t)(j & 1) * G * PS;    // alternate buffers by column
             const int cl = tid % PW, rg = tid / PW;
             const int c = j + 1 + cl;
-            double acc = 0.0;
-            if (c < w && tau != 0.0)
+            double acc = 0.0, saa = 0.0, sav = 0.0, svv = 0.0;
+            if (c < w)
                 for (int rr = rg; rr < nrows; rr += PNT / PW) {
-                    int g = row0 + rr;
+                    const int g = row0 + rr;
                     if (g >= p) {
-                        double v = g == p ? 1.0 : slab[rr * SLD + j];
-                        acc += v * slab[rr * SLD + c];
+                        const double v = g == p ? 1.0 : slab[rr * SLD + j];
+                        const double a = slab[rr * SLD + c];
+                        acc += v * a;
+                        if (cl == 0 && g >= p + 2) {
+                            saa += a * a;
+                            sav += a * v;
+                            svv += v * v;
+                        }
                     }
                 }
             wred[rg][cl] = acc;
+            if (cl == 0) {
+                wred[rg][X_SAA] = saa;
+                wred[rg][X_SAV] = sav;
+                wred[rg][X_SVV] = svv;
+            }
             __syncthreads();
-            if (tid < PW) {
+            if (tid < X_A1) {
                 double s = 0.0;
                 for (int q = 0; q < PNT / PW; ++q) s += wred[q][tid];
-                if (j + 1 + tid < w) store_coherent(&part2[(int64_t)wg * PW + tid], s);
+                if (tid >= PW || j + 1 + tid < w) store_coherent(&x2[(int64_t)wg * PS + tid], s);
+            }
+            if (wg == 0 && tid == 0) {
+                const int rr = p + 1 - row0;
+                store_coherent(&x2[X_A1], slab[rr * SLD + j + 1]);
+                store_coherent(&x2[X_V1], slab[rr * SLD + j]);
             }
             grid_barrier(bar, epoch, info);
 
-            // w_c = sum over workgroups, in workgroup order
+            // totals over the workgroups, in workgroup order
             {
+                const int e = tid % CTQR_WAVE, grp = tid / CTQR_WAVE;
+                constexpr int NG = PNT / CTQR_WAVE, BATCH = 16;
                 double s = 0.0;
-                if (c < w)
-                    for (int q = rg; q < G; q += PNT / PW) s += load_coherent(&part2[(int64_t)q * PW + cl]);
-                wred[rg][cl] = s;
+                if (e < X_A1 && (e >= PW || j + 1 + e < w))
+                    for (int q0 = grp; q0 < G; q0 += NG * BATCH) {
+                        // BATCH loads in flight, then summed in workgroup order
+                        double v[BATCH];
+#pragma unroll
+                        for (int u = 0; u < BATCH; ++u) {
+                            const int q = q0 + NG * u;
+                            v[u] = q < G ? load_coherent(&x2[(int64_t)q * PS + e]) : 0.0;
+                        }
+#pragma unroll
+                        for (int u = 0; u < BATCH; ++u) s += v[u];
+                    }
+                red4[grp][e] = s;
                 __syncthreads();
-                if (tid < PW) {
-                    double t = 0.0;
-                    for (int q = 0; q < PNT / PW; ++q) t += wred[q][tid];
-                    wcol[tid] = t * tau;
+                if (tid < X_A1) {
+                    double t = red4[0][tid];
+                    for (int q = 1; q < PNT / CTQR_WAVE; ++q) t += red4[q][tid];
+                    xch[tid] = t;
                 }
+                if (tid == X_A1 || tid == X_V1) xch[tid] = load_coherent(&x2[tid]);
                 __syncthreads();
             }
             if (tau != 0.0) {
@@ -148,12 +192,20 @@ void panel_qr_kernel(TS *__restrict__ A, int64_t lda, int m, int r0, int w, int 
                     int g = row0 + rr;
                     if (g >= p) {
                         double v = g == p ? 1.0 : slab[rr * SLD + j];
-                        slab[rr * SLD + cc] -= wcol[cc - j - 1] * v;
+                        slab[rr * SLD + cc] -= (tau * xch[cc - j - 1]) * v;
                     }
                 }
             }
+            // squared norm below the next pivot and the next alpha, after the update
+            const double tw = tau * xch[0];
+            const double ssn = xch[X_SAA] - 2.0 * tw * xch[X_SAV] + tw * tw * xch[X_SVV];
+            if (ssn >= 0.25 * xch[X_SAA]) {
+                have = true;
+                ss = ssn;
+                alpha = xch[X_A1] - tw * xch[X_V1];
+            }
         }
-        if (wg == owner && tid == 0) slab[(p - row0) * SLD + j] = beta;
+        if (wg == 0 && tid == 0) slab[(p - row0) * SLD + j] = beta;
         __syncthreads();
     }
 
