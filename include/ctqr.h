@@ -164,12 +164,21 @@ ctqr_status ctqr_qr_workspace(int64_t m, int64_t n, ctqr_dtype dtype, ctqr_prec 
  *          triangular T of each block column (the paper's "S factors").
  *   tau    device, n doubles: the reflector scalars (LAPACK larfg convention:
  *          beta = -sign(alpha)||x||, tau = (beta - alpha)/beta).
+ *   Rinv   device, ctqr_qr_rinv_bytes(n, dtype) bytes in `dtype`, or NULL: the
+ *          inverses of the 2048 x 2048 diagonal blocks of R and their
+ *          transposes, stored with the factor so every later solve's block
+ *          back substitution is a chain of MFMA products (the factorization
+ *          "is computed just once and stored", Section II-A).  NULL skips them;
+ *          the solve then builds them in its workspace each call.
  *   info   device: rank deficiency / non-finite / barrier time-out.
  * Sections II-C ("QR factorization"), Eq. 3. */
 ctqr_status ctqr_qr_factor(int64_t m, int64_t n, ctqr_dtype dtype, void *A, int64_t lda,
-                           ctqr_prec prec, int32_t nb, void *T, double *tau,
+                           ctqr_prec prec, int32_t nb, void *T, double *tau, void *Rinv,
                            void *work, size_t work_bytes, ctqr_info *info,
                            hipStream_t stream);
+
+/* Bytes of the Rinv array of ctqr_qr_factor / ctqr_qr_solve_slices (host only). */
+ctqr_status ctqr_qr_rinv_bytes(int64_t n, ctqr_dtype dtype, size_t *bytes);
 
 /* Workspace (device bytes) for ctqr_qr_solve_slices with up to nslices
  * right-hand sides; refine != 0 reserves the refinement vectors. */
@@ -180,7 +189,8 @@ ctqr_status ctqr_solve_workspace(int64_t m, int64_t n, ctqr_dtype dtype, int32_t
  * X = R^-1 (Q^T B) (Eq. 4), Q^T applied block by block with the compact-WY
  * factors, then block backward substitution with R (Section II-C, "System
  * solving").
- *   QR, T, tau  the outputs of ctqr_qr_factor (same m, n, dtype, nb).
+ *   QR, T, tau, Rinv  the outputs of ctqr_qr_factor (same m, n, dtype, nb);
+ *          Rinv may be NULL (then it is rebuilt in the workspace).
  *   B      device, m x nslices FP64, leading dim ldb (not modified).
  *   X      device, n x nslices FP64, leading dim ldx (output).
  *   A64    optional FP64 sparse A (from ctqr_build_system_matrix).  When given,
@@ -197,7 +207,7 @@ ctqr_status ctqr_solve_workspace(int64_t m, int64_t n, ctqr_dtype dtype, int32_t
  *          CTQR_NONFINITE. */
 ctqr_status ctqr_qr_solve_slices(int64_t m, int64_t n, ctqr_dtype dtype,
                                  const void *QR, int64_t lda, const void *T,
-                                 const double *tau, int32_t nb,
+                                 const double *tau, const void *Rinv, int32_t nb,
                                  const double *B, int64_t ldb, int32_t nslices,
                                  double *X, int64_t ldx,
                                  const ctqr_sparse *A64, double tol, int32_t max_iters,

@@ -49,7 +49,7 @@ template <typename T>
 struct FactorWS {
     unsigned *bars;
     double *part, *part2, *gram_part, *gram, *Tw;
-    T *Tin, *GW, *W2, *split;
+    T *Tin, *GW, *W2, *split, *rtmp;
     size_t bytes;
 };
 
@@ -69,6 +69,7 @@ FactorWS<T> carve_factor(void *work, int64_t m, int64_t n, int nb)
     w.GW = c.take<T>((int64_t)nb * n);
     w.W2 = c.take<T>((int64_t)nb * n);
     w.split = c.take<T>(SPLIT_PART_ELEMS);
+    w.rtmp = c.take<T>((int64_t)trinv_tmp_elems());
     w.bytes = c.off + 256;
     return w;
 }
@@ -96,9 +97,8 @@ SolveWS<T> carve_solve(void *work, int64_t m, int64_t n, int nb, int S, bool ref
     w.W2 = c.take<T>((int64_t)nb * S);
     int64_t sp = std::max<int64_t>(SPLIT_PART_ELEMS, 64LL * nb * S);
     w.split = c.take<T>(sp);
-    int64_t nbt = round_up(n, TRSM_BT);
-    w.Rinv = c.take<T>(nbt * TRSM_BT);
-    w.RinvT = c.take<T>(nbt * TRSM_BT);
+    w.Rinv = c.take<T>(2 * (int64_t)trinv_elems((int)n));     // used when the factor has none
+    w.RinvT = c.take<T>((int64_t)trinv_tmp_elems());   // scratch of the inverse doubling
     w.Xw = c.take<T>(w.ldxw * S);
     w.done = c.take<int>(64);
     if (refine) {
@@ -147,7 +147,7 @@ ctqr_status ensure_setup()
 }
 
 template <typename T>
-ctqr_status factor_impl(int64_t m64, int64_t n64, T *A, int64_t lda, int nb, T *Tout, double *tau,
+ctqr_status factor_impl(int64_t m64, int64_t n64, T *A, int64_t lda, int nb, T *Tout, double *tau, T *Rinv,
                         void *work, ctqr_info *info, hipStream_t st)
 {
     const int m = (int)m64, n = (int)n64;
@@ -216,13 +216,14 @@ ctqr_status factor_impl(int64_t m64, int64_t n64, T *A, int64_t lda, int nb, T *
             g_prof.push_back(rec);
         }
     }
-    return rdiag_check<T>(n, A, lda, nullptr, info, st);
+    if ((s = rdiag_check<T>(n, A, lda, nullptr, info, st))) return s;
+    return Rinv ? trinv_blocks<T>(n, A, lda, Rinv, w.rtmp, info, st) : CTQR_OK;
 }
 
 template <typename T>
 ctqr_status solve_impl(int64_t m64, int64_t n64, const T *QR, int64_t lda, const T *Tf,
-                       const double *tau, int nb, const double *B, int64_t ldb, int S, double *X,
-                       int64_t ldx, const ctqr_sparse *A64, double tol, int max_iters, void *work,
+                       const double *tau, const T *Rinv_in, int nb, const double *B, int64_t ldb, int S,
+                       double *X, int64_t ldx, const ctqr_sparse *A64, double tol, int max_iters, void *work,
                        ctqr_info *info, hipStream_t st)
 {
     (void)tau;
@@ -249,9 +250,14 @@ ctqr_status solve_impl(int64_t m64, int64_t n64, const T *QR, int64_t lda, const
         s = gemm_nn<T>(m - k0, S, nbk, V, lda, 1, w.W2, nb, T(-1), Bk, w.ldbw, nullptr, st);
         if (s) return s;
     }
-    // back substitution R X = (Q^T B)[0:n]
-    if ((s = trinv_blocks<T>(n, QR, lda, w.Rinv, w.RinvT, info, st))) return s;
-    s = trsm_upper<T>(n, S, QR, lda, w.RinvT, w.Bw, w.ldbw, w.Xw, w.ldxw, w.split, sp_elems, nullptr, st);
+    // back substitution R X = (Q^T B)[0:n], with the factor's diagonal-block
+    // inverses (built here when the factor was stored without them)
+    const T *Rinv = Rinv_in;
+    if (!Rinv) {
+        if ((s = trinv_blocks<T>(n, QR, lda, w.Rinv, w.RinvT, info, st))) return s;
+        Rinv = w.Rinv;
+    }
+    s = trsm_upper<T>(n, S, QR, lda, Rinv, w.Bw, w.ldbw, w.Xw, w.ldxw, w.split, sp_elems, nullptr, st);
     if (s) return s;
     if (!refine) return copy_cm<double, T>(n, S, w.Xw, w.ldxw, X, ldx, st);
 
@@ -268,10 +274,10 @@ ctqr_status solve_impl(int64_t m64, int64_t n64, const T *QR, int64_t lda, const
         s = spmm_rowmajor(n, S, A64->colptr, A64->row, A64->cval, 1.0, w.r, 0.0, nullptr, w.s, skip, st);
         if (s) return s;
         if ((s = rm_to_cm<T, double>(n, S, w.s, w.s32, w.ldxw, skip, st))) return s;
-        s = trsm_upper_trans<T>(n, S, QR, lda, w.Rinv, w.s32, w.ldxw, w.y32, w.ldxw, w.split, sp_elems,
+        s = trsm_upper_trans<T>(n, S, QR, lda, Rinv, w.s32, w.ldxw, w.y32, w.ldxw, w.split, sp_elems,
                                 skip, st);
         if (s) return s;
-        s = trsm_upper<T>(n, S, QR, lda, w.RinvT, w.y32, w.ldxw, w.d32, w.ldxw, w.split, sp_elems, skip, st);
+        s = trsm_upper<T>(n, S, QR, lda, Rinv, w.y32, w.ldxw, w.d32, w.ldxw, w.split, sp_elems, skip, st);
         if (s) return s;
         if ((s = refine_update<T>(n, S, w.xr, w.d32, w.ldxw, w.dmax, w.xmax, skip, st))) return s;
         if ((s = refine_check(S, w.dmax, w.xmax, tol, it, max_iters, w.hist, w.done, info, st))) return s;
@@ -393,13 +399,21 @@ ctqr_status ctqr_qr_workspace(int64_t m, int64_t n, ctqr_dtype dtype, ctqr_prec 
     return CTQR_OK;
 }
 
+ctqr_status ctqr_qr_rinv_bytes(int64_t n, ctqr_dtype dtype, size_t *bytes)
+{
+    if (!bytes || n < 1 || n >= INT32_MAX || (dtype != CTQR_F64 && dtype != CTQR_F32)) return CTQR_EINVAL;
+    *bytes = 2 * trinv_elems((int)n) * (dtype == CTQR_F64 ? sizeof(double) : sizeof(float));
+    return CTQR_OK;
+}
+
 ctqr_status ctqr_qr_factor(int64_t m, int64_t n, ctqr_dtype dtype, void *A, int64_t lda, ctqr_prec prec,
-                           int32_t nb, void *T, double *tau, void *work, size_t work_bytes,
+                           int32_t nb, void *T, double *tau, void *Rinv, void *work, size_t work_bytes,
                            ctqr_info *info, hipStream_t stream)
 {
     try {
         if (m < n || n < 1 || m >= INT32_MAX || !A || !T || !tau || !work || !info) return CTQR_EINVAL;
         if (lda < m || lda % 4 != 0 || !aligned16(A) || !aligned16(T)) return CTQR_EINVAL;
+        if (Rinv && !aligned16(Rinv)) return CTQR_EINVAL;
         if (!prec_ok(dtype, prec))
             return (dtype == CTQR_F32 && prec == CTQR_PREC_BF16_MFMA) ? CTQR_EUNSUPPORTED : CTQR_EINVAL;
         nb = resolve_nb(nb);
@@ -411,8 +425,9 @@ ctqr_status ctqr_qr_factor(int64_t m, int64_t n, ctqr_dtype dtype, void *A, int6
         ctqr_status s = ensure_setup();
         if (s) return s;
         if (dtype == CTQR_F64)
-            return factor_impl<double>(m, n, (double *)A, lda, nb, (double *)T, tau, work, info, stream);
-        return factor_impl<float>(m, n, (float *)A, lda, nb, (float *)T, tau, work, info, stream);
+            return factor_impl<double>(m, n, (double *)A, lda, nb, (double *)T, tau, (double *)Rinv, work, info,
+                                       stream);
+        return factor_impl<float>(m, n, (float *)A, lda, nb, (float *)T, tau, (float *)Rinv, work, info, stream);
     } catch (...) {
         return CTQR_EHIP;
     }
@@ -431,7 +446,7 @@ ctqr_status ctqr_solve_workspace(int64_t m, int64_t n, ctqr_dtype dtype, int32_t
 }
 
 ctqr_status ctqr_qr_solve_slices(int64_t m, int64_t n, ctqr_dtype dtype, const void *QR, int64_t lda,
-                                 const void *T, const double *tau, int32_t nb, const double *B,
+                                 const void *T, const double *tau, const void *Rinv, int32_t nb, const double *B,
                                  int64_t ldb, int32_t nslices, double *X, int64_t ldx,
                                  const ctqr_sparse *A64, double tol, int32_t max_iters, void *work,
                                  size_t work_bytes, ctqr_info *info, hipStream_t stream)
@@ -451,11 +466,12 @@ ctqr_status ctqr_qr_solve_slices(int64_t m, int64_t n, ctqr_dtype dtype, const v
         size_t need = 0;
         ctqr_solve_workspace(m, n, dtype, nb, nslices, A64 != nullptr && max_iters > 0, &need);
         if (work_bytes < need) return CTQR_ENOMEM;
+        if (Rinv && !aligned16(Rinv)) return CTQR_EINVAL;
         if (dtype == CTQR_F64)
-            return solve_impl<double>(m, n, (const double *)QR, lda, (const double *)T, tau, nb, B, ldb,
-                                      nslices, X, ldx, A64, tol, max_iters, work, info, stream);
-        return solve_impl<float>(m, n, (const float *)QR, lda, (const float *)T, tau, nb, B, ldb, nslices,
-                                 X, ldx, A64, tol, max_iters, work, info, stream);
+            return solve_impl<double>(m, n, (const double *)QR, lda, (const double *)T, tau, (const double *)Rinv,
+                                      nb, B, ldb, nslices, X, ldx, A64, tol, max_iters, work, info, stream);
+        return solve_impl<float>(m, n, (const float *)QR, lda, (const float *)T, tau, (const float *)Rinv, nb, B,
+                                 ldb, nslices, X, ldx, A64, tol, max_iters, work, info, stream);
     } catch (...) {
         return CTQR_EHIP;
     }

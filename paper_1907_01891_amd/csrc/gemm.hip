@@ -405,8 +405,9 @@ __global__ __launch_bounds__(NTHR, 2)
 void gemm_nn_kernel(int M, int N, int K,
                     const T *__restrict__ A, int64_t lda, int amask,
                     const T *__restrict__ B, int64_t ldb,
-                    T alpha, T *__restrict__ C, int64_t ldc, const int *skip)
+                    T alpha, T *__restrict__ C, int64_t ldc, int accum, const int *skip)
 {
+    // accum != 0: C += alpha A B;  accum == 0: C = alpha A B (C is not read)
     using Mt = Mf<T>;
     if (skip && *skip) return;
     __shared__ __attribute__((aligned(16))) T sA[2][Mt::BK * MkTile<T>::LD];
@@ -440,7 +441,7 @@ void gemm_nn_kernel(int M, int N, int K,
                     acc_coords<T>(ib, jb, r, n, m);
                     n += n0 + wn;
                     m += m0 + wm;
-                    cpre[ib][jb][r] = (m < M && n < N) ? C[(int64_t)n * ldc + m] : T(0);
+                    cpre[ib][jb][r] = (accum && m < M && n < N) ? C[(int64_t)n * ldc + m] : T(0);
                 }
     }
 
@@ -482,7 +483,7 @@ void gemm_nn_kernel(int M, int N, int K,
                     if constexpr (PRE)
                         *c = cpre[ib][jb][r] + alpha * acc[ib][jb][r];
                     else
-                        *c += alpha * acc[ib][jb][r];
+                        *c = accum ? *c + alpha * acc[ib][jb][r] : alpha * acc[ib][jb][r];
                 }
             }
 }
@@ -550,16 +551,21 @@ ctqr_status gemm_tn(int M, int N, int K, const T *A, int64_t lda, int amask, con
 
 template <typename T>
 ctqr_status gemm_nn(int M, int N, int K, const T *A, int64_t lda, int amask, const T *B,
-                    int64_t ldb, T alpha, T *C, int64_t ldc, const int *skip, hipStream_t st, int kind)
+                    int64_t ldb, T alpha, T *C, int64_t ldc, const int *skip, hipStream_t st, int kind,
+                    int accum)
 {
-    if (M <= 0 || N <= 0 || K <= 0) return CTQR_OK;
+    if (M <= 0 || N <= 0) return CTQR_OK;
+    if (K <= 0) {
+        if (accum) return CTQR_OK;
+        K = 0;   // C = 0: the kernel runs with an empty k loop
+    }
     dim3 grid((unsigned)(ceil_div(M, TILE) * ceil_div(N, TILE)));
     if (kind == 1)
         LAUNCH_TRY((gemm_nn_kernel<T, 1>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B, ldb, alpha,
-                   C, ldc, skip);
+                   C, ldc, accum, skip);
     else
         LAUNCH_TRY((gemm_nn_kernel<T, 0>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B, ldb, alpha,
-                   C, ldc, skip);
+                   C, ldc, accum, skip);
     return CTQR_OK;
 }
 
@@ -570,6 +576,6 @@ template ctqr_status gemm_tn<double>(int, int, int, const double *, int64_t, int
                                      int64_t, int, double, double, double *, int64_t, double *,
                                      size_t, const int *, hipStream_t);
 template ctqr_status gemm_nn<float>(int, int, int, const float *, int64_t, int, const float *,
-                                    int64_t, float, float *, int64_t, const int *, hipStream_t, int);
+                                    int64_t, float, float *, int64_t, const int *, hipStream_t, int, int);
 template ctqr_status gemm_nn<double>(int, int, int, const double *, int64_t, int, const double *,
-                                     int64_t, double, double *, int64_t, const int *, hipStream_t, int);
+                                     int64_t, double, double *, int64_t, const int *, hipStream_t, int, int);

@@ -12,7 +12,7 @@ ctqr_status gemm_tn(int M, int N, int K, const T *A, int64_t lda, int amask, con
 template <typename T>
 ctqr_status gemm_nn(int M, int N, int K, const T *A, int64_t lda, int amask, const T *B,
                     int64_t ldb, T alpha, T *C, int64_t ldc, const int *skip, hipStream_t st,
-                    int kind = 0);
+                    int kind = 0, int accum = 1);
 
 // ---- panel_qr.hip ----------------------------------------------------------
 constexpr int PANEL_XCH_STRIDE = 40;   // doubles per workgroup per exchange buffer (two buffers)
@@ -28,12 +28,15 @@ ctqr_status tbuild(int nb, const TG *G, int64_t ldg, const double *tau, TT *T, i
                    hipStream_t st);
 
 // ---- trsm.hip --------------------------------------------------------------
-constexpr int TRSM_BT = 256;  // diagonal block of the block substitutions
+constexpr int TRSM_BASE = 256;  // diagonal block inverted directly
+constexpr int TRSM_BIG = 2048;  // diagonal block of the block substitutions
+size_t trinv_elems(int n);      // Rinv: TRSM_BIG x round_up(n, TRSM_BIG)
+size_t trinv_tmp_elems();
 template <typename T>
-ctqr_status trinv_blocks(int n, const T *R, int64_t ldr, T *Rinv, T *RinvT, ctqr_info *info,
+ctqr_status trinv_blocks(int n, const T *R, int64_t ldr, T *Rinv, T *tmp, ctqr_info *info,
                          hipStream_t st);
 template <typename T>
-ctqr_status trsm_upper(int n, int S, const T *R, int64_t ldr, const T *RinvT, T *C, int64_t ldc,
+ctqr_status trsm_upper(int n, int S, const T *R, int64_t ldr, const T *Rinv, T *C, int64_t ldc,
                        T *X, int64_t ldx, T *part, size_t part_elems, const int *skip, hipStream_t st);
 template <typename T>
 ctqr_status trsm_upper_trans(int n, int S, const T *R, int64_t ldr, const T *Rinv, T *C, int64_t ldc,

@@ -7,25 +7,29 @@
 //                      refinement's semi-normal equations):
 //                      Y_i = R_ii^-T C_i;  C_{i+1:} -= R_{i, i+1:}^T Y_i
 //
-// The diagonal BT x BT blocks (BT = 256) are inverted once per solve
-// (trinv_blocks), so both the diagonal solve and the off-diagonal update are
-// MFMA products; only the chain of n / BT block rows is sequential.  Row
-// block p (32 rows) of inv(U), U upper triangular, depends only on U and on
-// itself: X_pp = inv(U_pp), X_pq = -(sum_{k=p}^{q-1} X_pk U_kq) X_qq, so each
-// 32-row block is built by its own workgroup (FP64, operands in LDS), each
-// recomputing the small diagonal inverses X_qq it needs.
+// The diagonal blocks R_ii are TRSM_BIG (2048) wide, so a solve is a chain of
+// n / 2048 steps, each two large MFMA products.  Their inverses are built
+// once per solve: 256 x 256 diagonal inverses by trinv_kernel, then doubled to
+// 512, 1024 and 2048 with inv([A B; 0 D]) = [inv(A), -inv(A) B inv(D); 0,
+// inv(D)] as MFMA products.
+//
+// trinv_kernel: row block p (32 rows) of inv(U), U upper triangular, depends
+// only on U and on itself: X_pp = inv(U_pp), X_pq = -(sum_{k=p}^{q-1} X_pk
+// U_kq) X_qq, so each 32-row block is built by its own workgroup (FP64,
+// operands in LDS), each recomputing the small diagonal inverses X_qq it
+// needs.
 #include "common.h"
 #include "kernels.h"
 
 namespace {
 
-constexpr int BT = TRSM_BT;
-
+constexpr int BT = TRSM_BASE;          // block inverted by trinv_kernel
+constexpr int BIG = TRSM_BIG;          // diagonal block of the substitutions
 constexpr int RB = 32;                 // row block of the inversion
-constexpr int NQ = BT / RB;            // row blocks per diagonal block
+constexpr int NQ = BT / RB;            // row blocks per base block
 constexpr int XLD = BT + 1;
 
-// Rs <- R(b*BT + 32*kb .., b*BT + 32*qb ..) as a 32 x 32 FP64 tile (zero
+// Rs <- R(base + 32*kb .., base + 32*qb ..) as a 32 x 32 FP64 tile (zero
 // outside the n x n matrix)
 template <typename T>
 __device__ inline void stage_r(int n, const T *__restrict__ R, int64_t ldr, int base, int kb, int qb,
@@ -39,7 +43,7 @@ __device__ inline void stage_r(int n, const T *__restrict__ R, int64_t ldr, int 
 }
 
 // Xq <- inv(Rs) for an upper-triangular 32 x 32 tile: thread c builds column
-// c by back substitution (rows past the matrix edge give zero columns).
+// c by back substitution (columns past the matrix edge are zero).
 __device__ inline void inv32(const double (*Rs)[33], double (*Xq)[33], int valid)
 {
     const int c = threadIdx.x;
@@ -61,10 +65,12 @@ __device__ inline void inv32(const double (*Rs)[33], double (*Xq)[33], int valid
     for (int i = 0; i < 32; ++i) Xq[i][c] = x[i];
 }
 
+// inv of the 256 x 256 diagonal block blk of R, row block p, written into
+// the BIG-wide inverse array (column j of the matrix at Rinv + j * BIG, row
+// (j's block offset inside its BIG block) + i).
 template <typename T>
 __global__ __launch_bounds__(256)
-void trinv_kernel(int n, const T *__restrict__ R, int64_t ldr, T *__restrict__ Rinv,
-                  T *__restrict__ RinvT)
+void trinv_kernel(int n, const T *__restrict__ R, int64_t ldr, T *__restrict__ Rinv)
 {
     __shared__ double Xrow[RB][XLD];
     __shared__ double Rs[32][33];
@@ -111,13 +117,10 @@ void trinv_kernel(int n, const T *__restrict__ R, int64_t ldr, T *__restrict__ R
         }
         __syncthreads();
     }
-    // Rinv block: BT x BT at columns base.., column-major (ld BT); RinvT its transpose
-    for (int e = tid; e < RB * BT; e += 256) {
+    const int off = base % BIG;
+    for (int e = tid; e < RB * nbk; e += 256) {
         int i = e % RB, j = e / RB;
-        int gi = RB * p + i;
-        T v = (T)Xrow[i][j];
-        Rinv[(int64_t)(base + j) * BT + gi] = v;
-        RinvT[(int64_t)(base + gi) * BT + j] = v;
+        Rinv[(int64_t)(base + j) * BIG + off + RB * p + i] = (T)Xrow[i][j];
     }
 }
 
@@ -167,14 +170,63 @@ void rdiag_kernel(int n, const T *__restrict__ R, int64_t ldr, ctqr_info *info)
     }
 }
 
+template <typename T>
+__global__ void zero_kernel(T *__restrict__ p, int64_t count)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+         e += (int64_t)gridDim.x * blockDim.x)
+        p[e] = T(0);
+}
+
+// RinvT block i = transpose of Rinv block i (each BIG x BIG, ld BIG)
+template <typename T>
+__global__ void block_transpose_kernel(const T *__restrict__ Rinv, T *__restrict__ RinvT)
+{
+    __shared__ T t[32][33];
+    const int64_t base = (int64_t)blockIdx.z * BIG * BIG;
+    const int r0 = blockIdx.x * 32, c0 = blockIdx.y * 32;
+    for (int k = threadIdx.y; k < 32; k += 8)
+        t[k][threadIdx.x] = Rinv[base + (int64_t)(c0 + k) * BIG + r0 + threadIdx.x];
+    __syncthreads();
+    for (int k = threadIdx.y; k < 32; k += 8)
+        RinvT[base + (int64_t)(r0 + k) * BIG + c0 + threadIdx.x] = t[threadIdx.x][k];
+}
+
 }  // namespace
 
+// elements of the block inverses of R; the block transposes follow them, so a
+// factor stores 2 * trinv_elems(n)
+size_t trinv_elems(int n) { return (size_t)BIG * (size_t)ceil_div(n, BIG) * BIG; }
+size_t trinv_tmp_elems() { return (size_t)(BIG / 2) * (BIG / 2); }
+
 template <typename T>
-ctqr_status trinv_blocks(int n, const T *R, int64_t ldr, T *Rinv, T *RinvT, ctqr_info *info,
-                         hipStream_t st)
+ctqr_status trinv_blocks(int n, const T *R, int64_t ldr, T *Rinv, T *tmp, ctqr_info *info, hipStream_t st)
 {
+    // Rinv holds the inverses, Rinv + trinv_elems(n) their block transposes
     (void)info;
-    LAUNCH_TRY(trinv_kernel<T>, dim3((unsigned)ceil_div(n, BT), NQ), dim3(256), 0, st, n, R, ldr, Rinv, RinvT);
+    const int64_t total = (int64_t)trinv_elems(n);
+    LAUNCH_TRY(zero_kernel<T>, dim3((unsigned)std::min<int64_t>(ceil_div(total, 256), 8192)), dim3(256), 0, st,
+               Rinv, total);
+    LAUNCH_TRY(trinv_kernel<T>, dim3((unsigned)ceil_div(n, BT), NQ), dim3(256), 0, st, n, R, ldr, Rinv);
+    // doubling inside every BIG block: [A B; 0 D] -> X12 = -inv(A) (B inv(D))
+    const int64_t ldy = BIG / 2;
+    for (int s = BT; s < BIG; s *= 2) {
+        for (int g0 = 0; g0 < n; g0 += 2 * s) {
+            const int d = std::min(s, n - (g0 + s));
+            if (d <= 0) continue;
+            const int off = g0 % BIG;
+            const T *Bblk = R + (int64_t)(g0 + s) * ldr + g0;               // s x d
+            const T *Dinv = Rinv + (int64_t)(g0 + s) * BIG + off + s;         // d x d
+            const T *Ainv = Rinv + (int64_t)g0 * BIG + off;                   // s x s
+            T *X12 = Rinv + (int64_t)(g0 + s) * BIG + off;                    // s x d
+            ctqr_status e = gemm_nn<T>(s, d, d, Bblk, ldr, 0, Dinv, BIG, T(1), tmp, ldy, nullptr, st, 0, 0);
+            if (e) return e;
+            e = gemm_nn<T>(s, d, s, Ainv, BIG, 0, tmp, ldy, T(-1), X12, BIG, nullptr, st, 0, 0);
+            if (e) return e;
+        }
+    }
+    LAUNCH_TRY(block_transpose_kernel<T>, dim3(BIG / 32, BIG / 32, (unsigned)ceil_div(n, BIG)), dim3(32, 8), 0,
+               st, (const T *)Rinv, Rinv + total);
     return CTQR_OK;
 }
 
@@ -188,20 +240,20 @@ ctqr_status rdiag_check(int n, const T *R, int64_t ldr, double *scratch, ctqr_in
 }
 
 template <typename T>
-ctqr_status trsm_upper(int n, int S, const T *R, int64_t ldr, const T *RinvT, T *C, int64_t ldc,
+ctqr_status trsm_upper(int n, int S, const T *R, int64_t ldr, const T *Rinv, T *C, int64_t ldc,
                        T *X, int64_t ldx, T *part, size_t part_elems, const int *skip, hipStream_t st)
 {
-    const int nblk = (int)ceil_div(n, BT);
+    const T *RinvT = Rinv + trinv_elems(n);
+    const int nblk = (int)ceil_div(n, BIG);
     for (int i = nblk - 1; i >= 0; --i) {
-        const int r0 = i * BT, bw = min(BT, n - r0);
-        // X_i = inv(R_ii) C_i  ==  (RinvT_i)^T C_i
-        ctqr_status s = gemm_tn<T>(bw, S, bw, RinvT + (int64_t)r0 * BT, BT, 0, C + r0, ldc, 0,
-                                   T(1), T(0), X + r0, ldx, part, part_elems, skip, st);
+        const int r0 = i * BIG, bw = min(BIG, n - r0);
+        // X_i = inv(R_ii) C_i = (inv(R_ii)^T)^T C_i  (split-K TN product)
+        ctqr_status s = gemm_tn<T>(bw, S, bw, RinvT + (int64_t)r0 * BIG, BIG, 0, C + r0, ldc, 0, T(1), T(0),
+                                   X + r0, ldx, part, part_elems, skip, st);
         if (s) return s;
         if (r0 > 0) {
             // C_{0:r0} -= R_{0:r0, i} X_i
-            s = gemm_nn<T>(r0, S, bw, R + (int64_t)r0 * ldr, ldr, 0, X + r0, ldx, T(-1), C, ldc,
-                           skip, st);
+            s = gemm_nn<T>(r0, S, bw, R + (int64_t)r0 * ldr, ldr, 0, X + r0, ldx, T(-1), C, ldc, skip, st);
             if (s) return s;
         }
     }
@@ -213,11 +265,11 @@ ctqr_status trsm_upper_trans(int n, int S, const T *R, int64_t ldr, const T *Rin
                              T *Y, int64_t ldy, T *part, size_t part_elems, const int *skip,
                              hipStream_t st)
 {
-    const int nblk = (int)ceil_div(n, BT);
+    const int nblk = (int)ceil_div(n, BIG);
     for (int i = 0; i < nblk; ++i) {
-        const int r0 = i * BT, bw = min(BT, n - r0);
+        const int r0 = i * BIG, bw = min(BIG, n - r0);
         // Y_i = inv(R_ii)^T C_i
-        ctqr_status s = gemm_tn<T>(bw, S, bw, Rinv + (int64_t)r0 * BT, BT, 0, C + r0, ldc, 0,
+        ctqr_status s = gemm_tn<T>(bw, S, bw, Rinv + (int64_t)r0 * BIG, BIG, 0, C + r0, ldc, 0,
                                    T(1), T(0), Y + r0, ldy, part, part_elems, skip, st);
         if (s) return s;
         const int rest = n - r0 - bw;
@@ -231,12 +283,12 @@ ctqr_status trsm_upper_trans(int n, int S, const T *R, int64_t ldr, const T *Rin
     return CTQR_OK;
 }
 
-#define INST(T)                                                                                   \
-    template ctqr_status trinv_blocks<T>(int, const T *, int64_t, T *, T *, ctqr_info *, hipStream_t); \
-    template ctqr_status rdiag_check<T>(int, const T *, int64_t, double *, ctqr_info *, hipStream_t);  \
-    template ctqr_status trsm_upper<T>(int, int, const T *, int64_t, const T *, T *, int64_t, T *,      \
-                                       int64_t, T *, size_t, const int *, hipStream_t);                \
-    template ctqr_status trsm_upper_trans<T>(int, int, const T *, int64_t, const T *, T *, int64_t,    \
+#define INST(T)                                                                                        \
+    template ctqr_status trinv_blocks<T>(int, const T *, int64_t, T *, T *, ctqr_info *, hipStream_t);  \
+    template ctqr_status rdiag_check<T>(int, const T *, int64_t, double *, ctqr_info *, hipStream_t);   \
+    template ctqr_status trsm_upper<T>(int, int, const T *, int64_t, const T *, T *, int64_t, T *,       \
+                                       int64_t, T *, size_t, const int *, hipStream_t);                 \
+    template ctqr_status trsm_upper_trans<T>(int, int, const T *, int64_t, const T *, T *, int64_t,     \
                                              T *, int64_t, T *, size_t, const int *, hipStream_t);
 INST(float)
 INST(double)

@@ -57,10 +57,11 @@ _SIGNATURES = {
     "ctqr_build_system_matrix": (c_i32, [_P(ctqr_geometry), c_i32, c_vp, c_i64, _P(ctqr_sparse),
                                          c_vp, c_sz, c_vp, c_vp]),
     "ctqr_qr_workspace": (c_i32, [c_i64, c_i64, c_i32, c_i32, c_i32, _P(c_sz)]),
-    "ctqr_qr_factor": (c_i32, [c_i64, c_i64, c_i32, c_vp, c_i64, c_i32, c_i32, c_vp, c_vp,
+    "ctqr_qr_factor": (c_i32, [c_i64, c_i64, c_i32, c_vp, c_i64, c_i32, c_i32, c_vp, c_vp, c_vp,
                                c_vp, c_sz, c_vp, c_vp]),
+    "ctqr_qr_rinv_bytes": (c_i32, [c_i64, c_i32, _P(c_sz)]),
     "ctqr_solve_workspace": (c_i32, [c_i64, c_i64, c_i32, c_i32, c_i32, c_i32, _P(c_sz)]),
-    "ctqr_qr_solve_slices": (c_i32, [c_i64, c_i64, c_i32, c_vp, c_i64, c_vp, c_vp, c_i32,
+    "ctqr_qr_solve_slices": (c_i32, [c_i64, c_i64, c_i32, c_vp, c_i64, c_vp, c_vp, c_vp, c_i32,
                                      c_vp, c_i64, c_i32, c_vp, c_i64, _P(ctqr_sparse), c_dbl, c_i32,
                                      c_vp, c_sz, c_vp, c_vp]),
     "ctqr_spmm": (c_i32, [_P(ctqr_sparse), c_i32, c_dbl, c_vp, c_i64, c_dbl, c_vp, c_i64, c_vp]),
@@ -136,9 +137,16 @@ def ctqr_qr_workspace(m, n, dtype, prec, nb):
     return b.value
 
 
-def ctqr_qr_factor(m, n, dtype, A_ptr, lda, prec, nb, T_ptr, tau_ptr, work_ptr, work_bytes, info_ptr, stream):
-    return lib().ctqr_qr_factor(m, n, dtype, A_ptr, lda, prec, nb, T_ptr, tau_ptr, work_ptr, work_bytes,
+def ctqr_qr_factor(m, n, dtype, A_ptr, lda, prec, nb, T_ptr, tau_ptr, rinv_ptr, work_ptr, work_bytes, info_ptr,
+                   stream):
+    return lib().ctqr_qr_factor(m, n, dtype, A_ptr, lda, prec, nb, T_ptr, tau_ptr, rinv_ptr, work_ptr, work_bytes,
                                 info_ptr, stream)
+
+
+def ctqr_qr_rinv_bytes(n, dtype):
+    b = c_sz()
+    check(lib().ctqr_qr_rinv_bytes(n, dtype, ctypes.byref(b)), "ctqr_qr_rinv_bytes")
+    return b.value
 
 
 def ctqr_solve_workspace(m, n, dtype, nb, nslices, refine):
@@ -147,9 +155,9 @@ def ctqr_solve_workspace(m, n, dtype, nb, nslices, refine):
     return b.value
 
 
-def ctqr_qr_solve_slices(m, n, dtype, QR_ptr, lda, T_ptr, tau_ptr, nb, B_ptr, ldb, nslices, X_ptr, ldx,
+def ctqr_qr_solve_slices(m, n, dtype, QR_ptr, lda, T_ptr, tau_ptr, rinv_ptr, nb, B_ptr, ldb, nslices, X_ptr, ldx,
                          sparse, tol, max_iters, work_ptr, work_bytes, info_ptr, stream):
-    return lib().ctqr_qr_solve_slices(m, n, dtype, QR_ptr, lda, T_ptr, tau_ptr, nb, B_ptr, ldb, nslices,
+    return lib().ctqr_qr_solve_slices(m, n, dtype, QR_ptr, lda, T_ptr, tau_ptr, rinv_ptr, nb, B_ptr, ldb, nslices,
                                       X_ptr, ldx, ctypes.byref(sparse) if sparse is not None else None,
                                       tol, max_iters, work_ptr, work_bytes, info_ptr, stream)
 

@@ -143,6 +143,8 @@ class QRFactor:
         self.nb = nb or 256
         self.T = colmajor(self.nb, self.n, A.dtype, device, ld=self.nb)
         self.tau = torch.zeros(self.n, dtype=torch.float64, device=device)
+        rb = C.ctqr_qr_rinv_bytes(self.n, self.dtype)
+        self.Rinv = torch.empty(rb // A.element_size(), dtype=A.dtype, device=device)
         self.info = Info(device)
         self.work = Workspace(device)
         self.swork = Workspace(device)
@@ -152,8 +154,8 @@ class QRFactor:
         wp, wb = self.work.get(C.ctqr_qr_workspace(self.m, self.n, self.dtype, self.prec, self.nb))
         C.check(C.ctqr_qr_factor(self.m, self.n, self.dtype, ctypes.c_void_p(self.A.data_ptr()), ld_of(self.A),
                                  self.prec, self.nb, ctypes.c_void_p(self.T.data_ptr()),
-                                 ctypes.c_void_p(self.tau.data_ptr()), wp, wb, self.info.ptr,
-                                 stream_handle(stream)), "ctqr_qr_factor")
+                                 ctypes.c_void_p(self.tau.data_ptr()), ctypes.c_void_p(self.Rinv.data_ptr()),
+                                 wp, wb, self.info.ptr, stream_handle(stream)), "ctqr_qr_factor")
         return self
 
     def solve(self, B, X=None, sparse=None, tol=1e-13, max_iters=0, stream=None):
@@ -165,7 +167,8 @@ class QRFactor:
         wp, wb = self.swork.get(C.ctqr_solve_workspace(self.m, self.n, self.dtype, self.nb, S, refine))
         C.check(C.ctqr_qr_solve_slices(self.m, self.n, self.dtype, ctypes.c_void_p(self.A.data_ptr()),
                                        ld_of(self.A), ctypes.c_void_p(self.T.data_ptr()),
-                                       ctypes.c_void_p(self.tau.data_ptr()), self.nb,
+                                       ctypes.c_void_p(self.tau.data_ptr()),
+                                       ctypes.c_void_p(self.Rinv.data_ptr()), self.nb,
                                        ctypes.c_void_p(B.data_ptr()), ld_of(B), S,
                                        ctypes.c_void_p(X.data_ptr()), ld_of(X), sparse, tol, max_iters,
                                        wp, wb, self.sinfo.ptr, stream_handle(stream)),

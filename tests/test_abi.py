@@ -96,18 +96,18 @@ def test_qr_workspace_rejects(args, code):
 def test_factor_rejects_before_any_hip_call():
     L = C.lib()
     p = ctypes.c_void_p(4096)       # never dereferenced: every case fails validation
-    # null A
-    assert L.ctqr_qr_factor(100, 50, C.CTQR_F64, None, 100, C.CTQR_PREC_FP64, 0, p, p, p, 1 << 40, p, None) == C.CTQR_EINVAL
-    # lda < m
-    assert L.ctqr_qr_factor(100, 50, C.CTQR_F64, p, 96, C.CTQR_PREC_FP64, 0, p, p, p, 1 << 40, p, None) == C.CTQR_EINVAL
-    # lda not a multiple of 4
-    assert L.ctqr_qr_factor(100, 50, C.CTQR_F64, p, 102, C.CTQR_PREC_FP64, 0, p, p, p, 1 << 40, p, None) == C.CTQR_EINVAL
-    # misaligned A
-    assert L.ctqr_qr_factor(100, 50, C.CTQR_F64, ctypes.c_void_p(4100), 100, C.CTQR_PREC_FP64, 0, p, p, p, 1 << 40, p, None) == C.CTQR_EINVAL
-    # workspace too small
-    assert L.ctqr_qr_factor(100, 50, C.CTQR_F64, p, 100, C.CTQR_PREC_FP64, 0, p, p, p, 16, p, None) == C.CTQR_ENOMEM
-    # BF16 storage path not offered for FP64 storage
-    assert L.ctqr_qr_factor(100, 50, C.CTQR_F64, p, 100, C.CTQR_PREC_BF16_MFMA, 0, p, p, p, 1 << 40, p, None) == C.CTQR_EINVAL
+
+    def call(A=p, lda=100, prec=C.CTQR_PREC_FP64, rinv=p, wb=1 << 40, dtype=C.CTQR_F64):
+        return L.ctqr_qr_factor(100, 50, dtype, A, lda, prec, 0, p, p, rinv, p, wb, p, None)
+    assert call(A=None) == C.CTQR_EINVAL                      # null A
+    assert call(lda=96) == C.CTQR_EINVAL                      # lda < m
+    assert call(lda=102) == C.CTQR_EINVAL                     # lda not a multiple of 4
+    assert call(A=ctypes.c_void_p(4100)) == C.CTQR_EINVAL     # misaligned A
+    assert call(rinv=ctypes.c_void_p(4104)) == C.CTQR_EINVAL  # misaligned Rinv
+    assert call(wb=16) == C.CTQR_ENOMEM                       # workspace too small
+    assert call(prec=C.CTQR_PREC_BF16_MFMA) == C.CTQR_EINVAL  # BF16 path not offered for FP64 storage
+    assert C.ctqr_qr_rinv_bytes(65536, C.CTQR_F32) == 2 * 2048 * 65536 * 4
+    assert C.ctqr_qr_rinv_bytes(100, C.CTQR_F64) == 2 * 2048 * 2048 * 8
 
 
 def test_solve_rejects_before_any_hip_call():
@@ -119,7 +119,7 @@ def test_solve_rejects_before_any_hip_call():
     def call(**kw):
         a = dict(ok)
         a.update(kw)
-        return L.ctqr_qr_solve_slices(a["m"], a["n"], a["dtype"], a["QR"], a["lda"], a["T"], a["tau"], a["nb"],
+        return L.ctqr_qr_solve_slices(a["m"], a["n"], a["dtype"], a["QR"], a["lda"], a["T"], a["tau"], None, a["nb"],
                                       a["B"], a["ldb"], a["S"], a["X"], a["ldx"], a["sp"], a["tol"], a["it"],
                                       a["work"], a["wb"], a["info"], a["st"])
     assert call(S=0) == C.CTQR_EINVAL
