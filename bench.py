@@ -51,6 +51,7 @@ def parse():
     p.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU comparison run")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--no-stream", action="store_true", help="skip the batched request-stream leg")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="only run 3 device-to-device copies of 1 GiB (counter calibration) and exit")
     return p.parse_args()
@@ -121,6 +122,109 @@ def cpu_baseline(workload, target_s):
     return {"value": qr_flops(m, k) / t / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
             "sample": "unblocked FP64 Householder QR of A[:, :%d] (%d x %d) of the %s geometry, %.1f s"
                       % (k, m, k, workload, t)}
+
+
+def request_stream_bench(args, log, F256, sp256, B256):
+    """Batched serving of 200 solve requests (slice counts log-uniform in
+    [1, 512], geometry uniform over 128^2 and 256^2) on two resident factors:
+    128^2 FP64 (plain FP64 path) and 256^2 FP32 (mixed path, CSNE-refined).
+    Right-hand sides are drawn cyclically from each geometry's slice pool.
+    Closed loop (one request in flight): per-request latency, host clock
+    around the call and a stream synchronisation.  All queued: requests of
+    one geometry packed in arrival order into solves of at most 512 slices."""
+    import numpy as np
+    import torch
+    from synthetic import get_workload, phantom_batch, noise_batch, NOISE_REL_LEVEL, request_stream
+    from paper_1907_01891_amd import ctqr as C
+    from paper_1907_01891_amd.device import SystemMatrix, QRFactor, Solver, colmajor, to_colmajor
+    dev = B256.device
+    w128 = get_workload("ct128")
+    s128 = SystemMatrix(w128.geometry(), C.CTQR_F64, dense=True, sparse=True)
+    X128 = to_colmajor(torch.as_tensor(phantom_batch(w128.side, w128.n_slices)), dtype=torch.float64)
+    B128 = s128.spmm(X128)
+    torch.cuda.synchronize()
+    B128.add_(torch.as_tensor(noise_batch(w128.side, w128.m, w128.n_slices), device=dev)
+              * (NOISE_REL_LEVEL * B128.abs().amax(dim=0))[None, :])
+    F128 = QRFactor(s128.A, C.CTQR_PREC_FP64, nb=256).factor()
+    torch.cuda.synchronize()
+    assert F128.info.read().status == 0
+    solvers = {"ct128": Solver(F128, 512),
+               "ct256": Solver(F256, 512, sparse=sp256.sp, tol=args.tol, max_iters=args.max_iters)}
+    pools = {"ct128": B128, "ct256": B256}
+    t0 = time.perf_counter()
+    for sv in solvers.values():
+        sv.tune(reps=1)
+    torch.cuda.synchronize()
+    t_tune = time.perf_counter() - t0
+    reqs = request_stream()
+    cursor = {"ct128": 0, "ct256": 0}
+
+    def cyclic(pool, c0, k):
+        cols = torch.tensor([(c0 + j) % pool.shape[1] for j in range(k)], device=dev)
+        b = colmajor(pool.shape[0], k, torch.float64, dev)
+        b.copy_(pool.index_select(1, cols))
+        return b
+    Bs = []
+    for g, k in reqs:
+        Bs.append(cyclic(pools[g], cursor[g], k))
+        cursor[g] = (cursor[g] + k) % pools[g].shape[1]
+    Xs = [colmajor(solvers[g].qr.n, k, torch.float64, dev) for g, k in reqs]
+    # warm-up: every bucket of both solvers calibrated and captured
+    t0 = time.perf_counter()
+    for g, sv in solvers.items():
+        for b in [1 << i for i in range(10)]:
+            Bw = cyclic(pools[g], 0, b)
+            for _ in range(2):
+                sv.solve(Bw)
+            del Bw
+    torch.cuda.synchronize()
+    t_warm = time.perf_counter() - t0
+    log("stream: tuned in %.1f s, buckets captured in %.1f s" % (t_tune, t_warm))
+
+    lat = []
+    status = 0
+    tc0 = time.perf_counter()
+    for (g, k), b, x in zip(reqs, Bs, Xs):
+        t0 = time.perf_counter()
+        solvers[g].solve(b, X=x)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0)
+        status = max(status, solvers[g].info.read().status)
+    t_closed = time.perf_counter() - tc0
+    total = sum(k for _, k in reqs)
+    lat_ms = np.array(lat) * 1e3
+
+    tq0 = time.perf_counter()
+    for g in solvers:
+        batch, nsl = [], 0
+        idx = [i for i, (gg, _) in enumerate(reqs) if gg == g]
+        for i in idx + [None]:
+            k = reqs[i][1] if i is not None else 0
+            if batch and (i is None or nsl + k > 512):
+                solvers[g].solve_batch([Bs[j] for j in batch], [Xs[j] for j in batch])
+                batch, nsl = [], 0
+            if i is not None:
+                batch.append(i)
+                nsl += k
+    torch.cuda.synchronize()
+    t_queued = time.perf_counter() - tq0
+    per = {}
+    for g in solvers:
+        l = np.array([lat_ms[i] for i, (gg, _) in enumerate(reqs) if gg == g])
+        per[g] = {"requests": int(l.size), "slices": int(sum(k for gg, k in reqs if gg == g)),
+                  "p50_ms": float(np.percentile(l, 50)), "p99_ms": float(np.percentile(l, 99)),
+                  "slice_tiles": {str(1 << i): solvers[g].query(1 << i)[1] for i in range(10)},
+                  "graph_refine_iters": {str(1 << i): solvers[g].query(1 << i)[2] for i in range(10)}}
+    out = {"requests": len(reqs), "slices": int(total),
+           "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
+           "closed_loop_slices_per_s": total / t_closed, "queued_slices_per_s": total / t_queued,
+           "queued_s": t_queued, "worst_status": int(status), "per_geometry": per}
+    log("stream: %d requests, %d slices; closed loop p50 %.1f ms p99 %.1f ms (%.0f slices/s); "
+        "all queued %.0f slices/s" % (len(reqs), total, out["p50_ms"], out["p99_ms"],
+                                     out["closed_loop_slices_per_s"], out["queued_slices_per_s"]))
+    for sv in solvers.values():
+        sv.close()
+    return out
 
 
 def main():
@@ -220,6 +324,10 @@ def main():
     Xmixed = X.clone()
     log("mixed: qr %.2f TFLOP/s, %.0f slices/s, refine iters %d (status %d), recovery err %.2e"
         % (qr_tf, slices_s, sinfo.iters, sinfo.status, rec_err))
+    stream_out = None
+    if not args.no_stream and args.workload == "ct256":
+        stream_out = request_stream_bench(args, log, F, sp, B)
+        torch.cuda.empty_cache()
     del A32, F
     torch.cuda.empty_cache()
 
@@ -307,6 +415,7 @@ def main():
             "flops_per_launch": kern_flops / launches if launches else None,
         },
         "cpu_baseline": cpu,
+        "request_stream": stream_out,
         "wall_s_timed": wall,
     }
     out.update(fp64)

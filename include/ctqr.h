@@ -214,6 +214,94 @@ ctqr_status ctqr_qr_solve_slices(int64_t m, int64_t n, ctqr_dtype dtype,
                                  void *work, size_t work_bytes, ctqr_info *info,
                                  hipStream_t stream);
 
+/* ---- Batched solver ------------------------------------------------------
+ * One stored factorization serves a stream of reconstruction requests: the
+ * factorization does not depend on B, so it is computed once and reused
+ * (Section II-A), and the per-slice cost falls as more slices share one read
+ * of the factor (Section III-B).  A solver holds a stored factor (the
+ * outputs of ctqr_qr_factor, Rinv required) and solves requests of 1 ..
+ * max_slices slices.  A request of S slices runs in the smallest power-of-two
+ * slice bucket >= S (the extra slices are zero and do not change the others'
+ * results).  Each bucket's solve -- Q^T B, the back substitution and, with
+ * refinement, a calibrated number of refinement iterations -- is captured
+ * once into a HIP graph and replayed on the caller's stream.
+ *
+ * Refinement (A64 != NULL, max_iters > 0) follows ctqr_qr_solve_slices.  The
+ * first request of a bucket runs eagerly and counts its iterations; the
+ * bucket's graph then holds that count + 2 (at most max_iters), its kernels
+ * returning at once after convergence.  After each replay the call reads the
+ * convergence flag (it waits on the stream) and, if the refinement has not
+ * ended, continues eagerly up to max_iters and recaptures the bucket with the
+ * larger count on its next use.  The results of a bucket are bitwise
+ * reproducible: a graph replays exactly the kernels of the eager run.
+ *
+ * Memory: the solver owns no device memory; the caller passes a workspace
+ * of ctqr_solver_workspace bytes, which must outlive the solver.  The
+ * factor, T, tau, Rinv and the sparse arrays are referenced, not copied, and
+ * must stay valid and unmodified.  Host memory: the graphs and a capture
+ * stream.  One solve at a time per solver (calls are serialised by a lock);
+ * solvers with different workspaces are independent. */
+typedef struct ctqr_solver_t *ctqr_solver;
+
+typedef struct {
+    int64_t m, n;
+    int32_t dtype;          /* ctqr_dtype of the factor */
+    int32_t nb;             /* the factor's block width (0 = default) */
+    const void *QR;         /* factored A, leading dim lda */
+    int64_t lda;
+    const void *T;          /* nb x n block-reflector factors */
+    const double *tau;
+    const void *Rinv;       /* diagonal-block inverses (required) */
+    const ctqr_sparse *A64; /* FP64 sparse A for the refinement, or NULL */
+    double tol;             /* refinement tolerance */
+    int32_t max_iters;      /* refinement iteration limit (0 = none) */
+    int32_t max_slices;     /* largest request, 1 .. 4096 */
+} ctqr_solver_desc;        /* 88 bytes */
+
+/* Workspace bytes of a solver (host only). */
+ctqr_status ctqr_solver_workspace(const ctqr_solver_desc *desc, size_t *bytes);
+
+/* Creates a solver; *out is NULL on failure. */
+ctqr_status ctqr_solver_create(const ctqr_solver_desc *desc, void *work, size_t work_bytes,
+                               ctqr_solver *out);
+
+/* Autotuner: times Q^T B plus the back substitution of every bucket with the
+ * 32-wide and with the 128-wide slice tile of the MFMA products (reps timed
+ * runs each, after one warm-up) and keeps the faster (untuned buckets use the
+ * 32-wide tile up to 32 slices).  Overwrites the solver's request
+ * buffer; waits on the stream.  Buckets whose choice changed are recalibrated
+ * and recaptured on their next use. */
+ctqr_status ctqr_solver_tune(ctqr_solver solver, int32_t reps, hipStream_t stream);
+
+/* X = R^-1 Q^T B for one request of nslices slices (B m x nslices FP64, ldb;
+ * X n x nslices FP64, ldx; both device, B not modified).  info (device)
+ * receives the request's ctqr_info.  Without refinement the call only
+ * enqueues; with it the call waits on the stream once per request (twice
+ * for a bucket's calibration run, which waits after every iteration). */
+ctqr_status ctqr_solver_solve(ctqr_solver solver, const double *B, int64_t ldb, int32_t nslices,
+                              double *X, int64_t ldx, ctqr_info *info, hipStream_t stream);
+
+/* Several queued requests in one solve: their slices (sum <= max_slices) are
+ * packed side by side into one bucket, so the requests share one pass over
+ * the factor.  Arrays of nreq entries in host memory; B[i], X[i] are device
+ * pointers as in ctqr_solver_solve.  Slices do not interact (the refinement
+ * stops when the slowest slice has converged), so each request's X is its
+ * own least-squares solution; info is that of the batch.  Requests of one
+ * call must not overlap in X. */
+ctqr_status ctqr_solver_solve_batch(ctqr_solver solver, int32_t nreq, const double *const *B,
+                                    const int64_t *ldb, const int32_t *nslices, double *const *X,
+                                    const int64_t *ldx, ctqr_info *info, hipStream_t stream);
+
+/* For a request of nslices: its bucket, the slice-tile width its products use
+ * (32 or 128) and the refinement iterations its captured graph holds (-1: no
+ * graph yet; 0 without refinement).  Host only. */
+ctqr_status ctqr_solver_query(ctqr_solver solver, int32_t nslices, int32_t *bucket,
+                              int32_t *slice_tile, int32_t *graph_iters);
+
+/* Releases the graphs and the capture stream (not the workspace).  NULL is
+ * accepted. */
+ctqr_status ctqr_solver_destroy(ctqr_solver solver);
+
 /* Sinogram synthesis and residual helper: Y = alpha * A X + beta * Y with the
  * FP64 CSR copy of A.  X (n x nslices, ldx) and Y (m x nslices, ldy) are
  * column-major FP64 device arrays.  Eq. 1. */

@@ -86,7 +86,7 @@ struct SolveWS {
 };
 
 template <typename T>
-SolveWS<T> carve_solve(void *work, int64_t m, int64_t n, int nb, int S, bool refine)
+SolveWS<T> carve_solve(void *work, int64_t m, int64_t n, int nb, int S, bool refine, bool with_rinv = true)
 {
     Carve c(work);
     SolveWS<T> w{};
@@ -97,8 +97,10 @@ SolveWS<T> carve_solve(void *work, int64_t m, int64_t n, int nb, int S, bool ref
     w.W2 = c.take<T>((int64_t)nb * S);
     int64_t sp = std::max<int64_t>(SPLIT_PART_ELEMS, 64LL * nb * S);
     w.split = c.take<T>(sp);
-    w.Rinv = c.take<T>(2 * (int64_t)trinv_elems((int)n));     // used when the factor has none
-    w.RinvT = c.take<T>((int64_t)trinv_tmp_elems());   // scratch of the inverse doubling
+    if (with_rinv) {   // used when the factor has no stored inverses
+        w.Rinv = c.take<T>(2 * (int64_t)trinv_elems((int)n));
+        w.RinvT = c.take<T>((int64_t)trinv_tmp_elems());   // scratch of the inverse doubling
+    }
     w.Xw = c.take<T>(w.ldxw * S);
     w.done = c.take<int>(64);
     if (refine) {
@@ -220,6 +222,161 @@ ctqr_status factor_impl(int64_t m64, int64_t n64, T *A, int64_t lda, int nb, T *
     return Rinv ? trinv_blocks<T>(n, A, lda, Rinv, w.rtmp, info, st) : CTQR_OK;
 }
 
+// Sets the slice-tile choice of the GEMMs enqueued by this thread for the
+// lifetime of the scope.
+struct NarrowScope {
+    int old;
+    explicit NarrowScope(int v) : old(gemm_narrow_max()) { gemm_set_narrow_max(v); }
+    ~NarrowScope() { gemm_set_narrow_max(old); }
+};
+
+constexpr int DEFAULT_NARROW = 32;   // slices up to which the 32-wide tile is used
+
+// One multi-slice solve over a carved workspace, in three phases: the first
+// two enqueue no host synchronisation when host_sync is off, so a graph can
+// capture them.
+template <typename T>
+struct SolveRun {
+    int m, n, nb, S;
+    const T *QR;
+    int64_t lda;
+    const T *Tf;
+    const T *Rinv;   // the factor's diagonal-block inverses, or null (built into w.Rinv)
+    const double *B;
+    int64_t ldb;
+    const ctqr_sparse *A64;
+    double tol;
+    int max_iters;
+    int narrow;
+    ctqr_info *info;
+    SolveWS<T> w;
+    int64_t sp_elems;
+    bool refine() const { return A64 != nullptr && max_iters > 0; }
+};
+
+template <typename T>
+SolveRun<T> make_run(int64_t m, int64_t n, const T *QR, int64_t lda, const T *Tf, const T *Rinv, int nb,
+                     const double *B, int64_t ldb, int S, const ctqr_sparse *A64, double tol, int max_iters,
+                     void *work, ctqr_info *info, bool carve_rinv)
+{
+    SolveRun<T> r{};
+    r.m = (int)m; r.n = (int)n; r.nb = nb; r.S = S;
+    r.QR = QR; r.lda = lda; r.Tf = Tf; r.Rinv = Rinv; r.B = B; r.ldb = ldb;
+    r.A64 = A64; r.tol = tol; r.max_iters = max_iters;
+    r.narrow = S <= DEFAULT_NARROW ? DEFAULT_NARROW : 0;
+    r.info = info;
+    r.w = carve_solve<T>(work, m, n, nb, S, r.refine(), carve_rinv);
+    r.sp_elems = std::max<int64_t>(SPLIT_PART_ELEMS, 64LL * nb * S);
+    return r;
+}
+
+// Q^T B and the back substitution (Section II-C), then the set-up of the
+// refinement.
+template <typename T>
+ctqr_status solve_start(SolveRun<T> &r, hipStream_t st)
+{
+    NarrowScope ns(r.narrow);
+    SolveWS<T> &w = r.w;
+    const int m = r.m, n = r.n, nb = r.nb, S = r.S;
+    ctqr_status s;
+    if ((s = info_reset(r.info, st))) return s;
+    if ((s = fill_u32((unsigned *)w.done, 64, 0u, st))) return s;
+    // working copy of B in the factor's precision
+    if ((s = copy_cm<T, double>(m, S, r.B, r.ldb, w.Bw, w.ldbw, st))) return s;
+    // Q^T B, one block reflector at a time: B -= V (T^T (V^T B))
+    for (int k0 = 0; k0 < n; k0 += nb) {
+        const int nbk = std::min(nb, n - k0);
+        const T *V = r.QR + (int64_t)k0 * r.lda + k0;
+        T *Bk = w.Bw + k0;
+        s = gemm_tn<T>(nbk, S, m - k0, V, r.lda, nbk, Bk, w.ldbw, 0, T(1), T(0), w.W, nb, w.split, r.sp_elems,
+                       nullptr, st);
+        if (s) return s;
+        s = gemm_tn<T>(nbk, S, nbk, r.Tf + (int64_t)k0 * nb, nb, 0, w.W, nb, 0, T(1), T(0), w.W2, nb, w.split,
+                       r.sp_elems, nullptr, st);
+        if (s) return s;
+        s = gemm_nn<T>(m - k0, S, nbk, V, r.lda, 1, w.W2, nb, T(-1), Bk, w.ldbw, nullptr, st);
+        if (s) return s;
+    }
+    // back substitution R X = (Q^T B)[0:n], with the factor's diagonal-block
+    // inverses (built here when the factor was stored without them)
+    if (!r.Rinv) {
+        if ((s = trinv_blocks<T>(n, r.QR, r.lda, w.Rinv, w.RinvT, r.info, st))) return s;
+        r.Rinv = w.Rinv;
+    }
+    s = trsm_upper<T>(n, S, r.QR, r.lda, r.Rinv, w.Bw, w.ldbw, w.Xw, w.ldxw, w.split, r.sp_elems, nullptr, st);
+    if (s) return s;
+    if (!r.refine()) return CTQR_OK;
+    if ((s = cm_to_rm<double, T>(n, S, w.Xw, w.ldxw, w.xr, nullptr, st))) return s;
+    if ((s = cm_to_rm<double, double>(m, S, r.B, r.ldb, w.Br, nullptr, st))) return s;
+    if ((s = fill_f64(w.hist, 8, 0.0, st))) return s;
+    if ((s = fill_u32((unsigned *)w.dmax, 2LL * S, 0u, st))) return s;
+    return fill_u32((unsigned *)w.xmax, 2LL * S, 0u, st);
+}
+
+// Reads the device-side end-of-refinement flag (synchronises the stream).
+ctqr_status read_done(const int *done, hipStream_t st, bool &out)
+{
+    int *flag = host_flag();
+    if (!flag) return CTQR_EHIP;
+    HIP_TRY(hipMemcpyAsync(flag, done, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    out = *flag != 0;
+    return CTQR_OK;
+}
+
+// Refinement iterations it0 .. it1-1 of the corrected semi-normal equations:
+// r = B - A x, R^T y = A^T r, R d = y, x += d.  Every kernel of an iteration
+// returns at once after the device-side flag has ended the refinement.  With
+// host_sync the loop stops enqueuing once that flag is set; *ran is then the
+// number of iterations the refinement took.
+template <typename T>
+ctqr_status refine_iters(SolveRun<T> &r, int it0, int it1, bool host_sync, hipStream_t st, int *ran)
+{
+    NarrowScope ns(r.narrow);
+    SolveWS<T> &w = r.w;
+    const int m = r.m, n = r.n, S = r.S;
+    const ctqr_sparse *A = r.A64;
+    ctqr_status s;
+    if (ran) *ran = it1;
+    for (int it = it0; it < it1; ++it) {
+        const int *skip = w.done;
+        s = spmm_rowmajor(m, S, A->rowptr, A->col, A->val, -1.0, w.xr, 1.0, w.Br, w.r, skip, st);
+        if (s) return s;
+        s = spmm_rowmajor(n, S, A->colptr, A->row, A->cval, 1.0, w.r, 0.0, nullptr, w.s, skip, st);
+        if (s) return s;
+        if ((s = rm_to_cm<T, double>(n, S, w.s, w.s32, w.ldxw, skip, st))) return s;
+        s = trsm_upper_trans<T>(n, S, r.QR, r.lda, r.Rinv, w.s32, w.ldxw, w.y32, w.ldxw, w.split, r.sp_elems,
+                                skip, st);
+        if (s) return s;
+        s = trsm_upper<T>(n, S, r.QR, r.lda, r.Rinv, w.y32, w.ldxw, w.d32, w.ldxw, w.split, r.sp_elems, skip,
+                          st);
+        if (s) return s;
+        if ((s = refine_update<T>(n, S, w.xr, w.d32, w.ldxw, w.dmax, w.xmax, skip, st))) return s;
+        if ((s = refine_check(S, w.dmax, w.xmax, r.tol, it, r.max_iters, w.hist, w.done, r.info, st)))
+            return s;
+        if (host_sync) {
+            bool done = false;
+            if ((s = read_done(w.done, st, done))) return s;
+            if (done) {
+                if (ran) *ran = it + 1;
+                break;
+            }
+        }
+    }
+    return CTQR_OK;
+}
+
+// The first S_out slices of the solution into X (FP64, column-major).
+template <typename T>
+ctqr_status solve_finish(SolveRun<T> &r, int S_out, double *X, int64_t ldx, hipStream_t st)
+{
+    SolveWS<T> &w = r.w;
+    if (!r.refine()) return copy_cm<double, T>(r.n, S_out, w.Xw, w.ldxw, X, ldx, st);
+    if (S_out == r.S) return rm_to_cm<double, double>(r.n, r.S, w.xr, X, ldx, nullptr, st);
+    // row-major x holds S slices per row: gather the first S_out of each
+    return rm_to_cm_sub(r.n, r.S, S_out, w.xr, X, ldx, st);
+}
+
 template <typename T>
 ctqr_status solve_impl(int64_t m64, int64_t n64, const T *QR, int64_t lda, const T *Tf,
                        const double *tau, const T *Rinv_in, int nb, const double *B, int64_t ldb, int S,
@@ -227,69 +384,237 @@ ctqr_status solve_impl(int64_t m64, int64_t n64, const T *QR, int64_t lda, const
                        ctqr_info *info, hipStream_t st)
 {
     (void)tau;
-    const int m = (int)m64, n = (int)n64;
-    const bool refine = A64 != nullptr && max_iters > 0;
-    SolveWS<T> w = carve_solve<T>(work, m64, n64, nb, S, refine);
-    const int64_t sp_elems = std::max<int64_t>(SPLIT_PART_ELEMS, 64LL * nb * S);
-    ctqr_status s;
-    if ((s = info_reset(info, st))) return s;
-    if ((s = fill_u32((unsigned *)w.done, 64, 0u, st))) return s;
-    // working copy of B in the factor's precision
-    if ((s = copy_cm<T, double>(m, S, B, ldb, w.Bw, w.ldbw, st))) return s;
-    // Q^T B, one block reflector at a time: B -= V (T^T (V^T B))
-    for (int k0 = 0; k0 < n; k0 += nb) {
-        const int nbk = std::min(nb, n - k0);
-        const T *V = QR + (int64_t)k0 * lda + k0;
-        T *Bk = w.Bw + k0;
-        s = gemm_tn<T>(nbk, S, m - k0, V, lda, nbk, Bk, w.ldbw, 0, T(1), T(0), w.W, nb, w.split, sp_elems,
-                       nullptr, st);
-        if (s) return s;
-        s = gemm_tn<T>(nbk, S, nbk, Tf + (int64_t)k0 * nb, nb, 0, w.W, nb, 0, T(1), T(0), w.W2, nb, w.split,
-                       sp_elems, nullptr, st);
-        if (s) return s;
-        s = gemm_nn<T>(m - k0, S, nbk, V, lda, 1, w.W2, nb, T(-1), Bk, w.ldbw, nullptr, st);
-        if (s) return s;
-    }
-    // back substitution R X = (Q^T B)[0:n], with the factor's diagonal-block
-    // inverses (built here when the factor was stored without them)
-    const T *Rinv = Rinv_in;
-    if (!Rinv) {
-        if ((s = trinv_blocks<T>(n, QR, lda, w.Rinv, w.RinvT, info, st))) return s;
-        Rinv = w.Rinv;
-    }
-    s = trsm_upper<T>(n, S, QR, lda, Rinv, w.Bw, w.ldbw, w.Xw, w.ldxw, w.split, sp_elems, nullptr, st);
+    SolveRun<T> r = make_run<T>(m64, n64, QR, lda, Tf, Rinv_in, nb, B, ldb, S, A64, tol, max_iters, work, info,
+                                true);
+    ctqr_status s = solve_start(r, st);
     if (s) return s;
-    if (!refine) return copy_cm<double, T>(n, S, w.Xw, w.ldxw, X, ldx, st);
+    if (r.refine() && (s = refine_iters(r, 0, max_iters, true, st, nullptr))) return s;
+    return solve_finish(r, S, X, ldx, st);
+}
 
-    // corrected semi-normal equations: r = B - A x, R^T y = A^T r, R d = y, x += d
-    if ((s = cm_to_rm<double, T>(n, S, w.Xw, w.ldxw, w.xr, nullptr, st))) return s;
-    if ((s = cm_to_rm<double, double>(m, S, B, ldb, w.Br, nullptr, st))) return s;
-    if ((s = fill_f64(w.hist, 8, 0.0, st))) return s;
-    if ((s = fill_u32((unsigned *)w.dmax, 2LL * S, 0u, st))) return s;
-    if ((s = fill_u32((unsigned *)w.xmax, 2LL * S, 0u, st))) return s;
-    for (int it = 0; it < max_iters; ++it) {
-        const int *skip = w.done;
-        s = spmm_rowmajor(m, S, A64->rowptr, A64->col, A64->val, -1.0, w.xr, 1.0, w.Br, w.r, skip, st);
-        if (s) return s;
-        s = spmm_rowmajor(n, S, A64->colptr, A64->row, A64->cval, 1.0, w.r, 0.0, nullptr, w.s, skip, st);
-        if (s) return s;
-        if ((s = rm_to_cm<T, double>(n, S, w.s, w.s32, w.ldxw, skip, st))) return s;
-        s = trsm_upper_trans<T>(n, S, QR, lda, Rinv, w.s32, w.ldxw, w.y32, w.ldxw, w.split, sp_elems,
-                                skip, st);
-        if (s) return s;
-        s = trsm_upper<T>(n, S, QR, lda, Rinv, w.y32, w.ldxw, w.d32, w.ldxw, w.split, sp_elems, skip, st);
-        if (s) return s;
-        if ((s = refine_update<T>(n, S, w.xr, w.d32, w.ldxw, w.dmax, w.xmax, skip, st))) return s;
-        if ((s = refine_check(S, w.dmax, w.xmax, tol, it, max_iters, w.hist, w.done, info, st))) return s;
-        // stop enqueuing once the device-side flag says the refinement ended
-        // (the kernels of any extra iteration would return at once anyway)
-        int *flag = host_flag();
-        if (!flag) return CTQR_EHIP;
-        HIP_TRY(hipMemcpyAsync(flag, w.done, sizeof(int), hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
-        if (*flag) break;
+// ---------------------------------------------------------------------------
+// Batched solver: one stored factor serves a stream of requests (the
+// factorization does not depend on B and is computed once, Section II-A; the
+// per-slice cost falls as more slices share one read of the factor,
+// Section III-B).  Requests are padded to a power-of-two slice bucket; each
+// bucket's solve is captured once into a HIP graph and replayed.
+// ---------------------------------------------------------------------------
+constexpr int SOLVER_MAX_SLICES = 4096;
+constexpr int GRAPH_EXTRA_ITERS = 2;   // refinement iterations beyond the calibrated count
+
+struct SolverBucket {
+    int S = 0;
+    int narrow = 0;            // slice-tile threshold of its GEMMs
+    int iters = -1;            // refinement iterations of its calibration run (-1: none yet)
+    int graph_iters = 0;       // refinement iterations the graph holds
+    hipGraphExec_t exec = nullptr;
+};
+
+int next_pow2(int x)
+{
+    int p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+}  // namespace
+
+struct ctqr_solver_t {
+    ctqr_solver_desc d{};
+    ctqr_sparse sp{};
+    bool refine = false;
+    int smax = 0;
+    int64_t ldbp = 0;
+    double *Bpad = nullptr;     // m x smax request buffer the graphs read
+    ctqr_info *info = nullptr;  // device info the graphs write
+    void *swork = nullptr;      // solve workspace of the largest bucket
+    hipStream_t cap = nullptr;  // capture stream (never executes work)
+    std::vector<SolverBucket> buckets;
+    std::mutex mu;
+};
+
+namespace {
+
+struct SolverLayout {
+    ctqr_info *info;
+    double *Bpad;
+    void *swork;
+    size_t bytes;
+};
+
+SolverLayout solver_layout(const ctqr_solver_desc *d, void *work, int smax, int64_t ldbp)
+{
+    Carve c(work);
+    SolverLayout L{};
+    L.info = c.take<ctqr_info>(1);
+    L.Bpad = c.take<double>(ldbp * smax);
+    L.swork = c.take<char>(0);
+    const bool refine = d->A64 != nullptr && d->max_iters > 0;
+    size_t sb = d->dtype == CTQR_F64 ? carve_solve<double>(nullptr, d->m, d->n, d->nb, smax, refine, false).bytes
+                                     : carve_solve<float>(nullptr, d->m, d->n, d->nb, smax, refine, false).bytes;
+    L.bytes = c.off + sb + 256;
+    return L;
+}
+
+template <typename T>
+SolveRun<T> solver_run(ctqr_solver_t *sv, const SolverBucket &bk)
+{
+    const ctqr_solver_desc &d = sv->d;
+    SolveRun<T> r = make_run<T>(d.m, d.n, (const T *)d.QR, d.lda, (const T *)d.T, (const T *)d.Rinv, d.nb,
+                                sv->Bpad, sv->ldbp, bk.S, sv->refine ? &sv->sp : nullptr, d.tol,
+                                sv->refine ? d.max_iters : 0, sv->swork, sv->info, false);
+    r.narrow = bk.narrow;
+    return r;
+}
+
+void drop_graph(SolverBucket &bk)
+{
+    if (bk.exec) (void)hipGraphExecDestroy(bk.exec);
+    bk.exec = nullptr;
+}
+
+// Captures the bucket's solve (Q^T B, the back substitution and graph_iters
+// refinement iterations, no host synchronisation) on the capture stream.
+template <typename T>
+ctqr_status capture_bucket(ctqr_solver_t *sv, SolverBucket &bk)
+{
+    SolveRun<T> r = solver_run<T>(sv, bk);
+    HIP_TRY(hipStreamBeginCapture(sv->cap, hipStreamCaptureModeThreadLocal));
+    ctqr_status s = solve_start(r, sv->cap);
+    if (!s && r.refine()) s = refine_iters(r, 0, bk.graph_iters, false, sv->cap, nullptr);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(sv->cap, &g);
+    if (s || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        if (e != hipSuccess) ctqr_last_hip_error(e, "hipStreamEndCapture", __FILE__, __LINE__);
+        return s ? s : CTQR_EHIP;
     }
-    return rm_to_cm<double, double>(n, S, w.xr, X, ldx, nullptr, st);
+    e = hipGraphInstantiate(&bk.exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        bk.exec = nullptr;
+        ctqr_last_hip_error(e, "hipGraphInstantiate", __FILE__, __LINE__);
+        return CTQR_EHIP;
+    }
+    return CTQR_OK;
+}
+
+// Solves nreq requests together: their slices are packed side by side into
+// the smallest bucket that holds them all (zero slices after them), solved
+// once, and each request's slices copied out to its X.
+template <typename T>
+ctqr_status solver_solve_t(ctqr_solver_t *sv, int nreq, const double *const *B, const int64_t *ldb,
+                           const int32_t *S, double *const *X, const int64_t *ldx, ctqr_info *info_out,
+                           hipStream_t st)
+{
+    const ctqr_solver_desc &d = sv->d;
+    int total = 0;
+    for (int i = 0; i < nreq; ++i) total += S[i];
+    SolverBucket *bp = nullptr;
+    for (auto &b : sv->buckets)
+        if (b.S >= total) { bp = &b; break; }
+    SolverBucket &bk = *bp;
+    ctqr_status s;
+    // the requests into the bucket's buffer, zero slices after them (a zero
+    // right-hand side gives a zero solution and leaves the others unchanged)
+    for (int i = 0, off = 0; i < nreq; off += S[i], ++i)
+        if ((s = copy_cm<double, double>(d.m, S[i], B[i], ldb[i], sv->Bpad + (int64_t)off * sv->ldbp, sv->ldbp,
+                                         st)))
+            return s;
+    if (bk.S > total &&
+        (s = fill_f64(sv->Bpad + (int64_t)total * sv->ldbp, (int64_t)(bk.S - total) * sv->ldbp, 0.0, st)))
+        return s;
+    SolveRun<T> r = solver_run<T>(sv, bk);
+    if (sv->refine && bk.iters < 0) {
+        // calibration: an eager, host-synchronised run that counts the
+        // refinement iterations the graph will hold
+        if ((s = solve_start(r, st))) return s;
+        int ran = 0;
+        if ((s = refine_iters(r, 0, r.max_iters, true, st, &ran))) return s;
+        bk.iters = ran;
+        bk.graph_iters = std::min(r.max_iters, ran + GRAPH_EXTRA_ITERS);
+    } else {
+        if (!bk.exec) {
+            if (!sv->refine) bk.graph_iters = 0;
+            if ((s = capture_bucket<T>(sv, bk))) return s;
+        }
+        HIP_TRY(hipGraphLaunch(bk.exec, st));
+        if (sv->refine && bk.graph_iters < r.max_iters) {
+            // the refinement may need more iterations than the graph holds:
+            // continue eagerly, and recapture with the new count next time
+            bool done = false;
+            if ((s = read_done(r.w.done, st, done))) return s;
+            if (!done) {
+                int ran = 0;
+                if ((s = refine_iters(r, bk.graph_iters, r.max_iters, true, st, &ran))) return s;
+                bk.iters = ran;
+                bk.graph_iters = std::min(r.max_iters, ran + GRAPH_EXTRA_ITERS);
+                drop_graph(bk);
+            }
+        }
+    }
+    for (int i = 0, off = 0; i < nreq; off += S[i], ++i) {
+        if (r.refine())
+            s = rm_to_cm_sub(r.n, bk.S, S[i], r.w.xr + off, X[i], ldx[i], st);
+        else
+            s = copy_cm<double, T>(r.n, S[i], r.w.Xw + (int64_t)off * r.w.ldxw, r.w.ldxw, X[i], ldx[i], st);
+        if (s) return s;
+    }
+    HIP_TRY(hipMemcpyAsync(info_out, sv->info, sizeof(ctqr_info), hipMemcpyDeviceToDevice, st));
+    return CTQR_OK;
+}
+
+// Times Q^T B plus the back substitution of every bucket with the 32-wide
+// and with the 128-wide slice tile and keeps the faster.
+template <typename T>
+ctqr_status solver_tune_t(ctqr_solver_t *sv, hipStream_t st, int reps)
+{
+    const ctqr_solver_desc &d = sv->d;
+    ctqr_status s;
+    if ((s = fill_f64(sv->Bpad, sv->ldbp * sv->smax, 1.0, st))) return s;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    ctqr_status out = CTQR_OK;
+    for (auto &bk : sv->buckets) {
+        const int cands[2] = {bk.S, 0};   // 32-wide, 128-wide slice tile
+        const int ncand = 2;
+        float best = 0.f;
+        int pick = bk.narrow;
+        for (int c = 0; c < ncand && !out; ++c) {
+            SolveRun<T> r = make_run<T>(d.m, d.n, (const T *)d.QR, d.lda, (const T *)d.T, (const T *)d.Rinv,
+                                        d.nb, sv->Bpad, sv->ldbp, bk.S, nullptr, 0.0, 0, sv->swork, sv->info,
+                                        false);
+            r.narrow = cands[c];
+            float tot = 0.f;
+            for (int rep = 0; rep <= reps && !out; ++rep) {
+                hipError_t e = hipEventRecord(e0, st);
+                if (e == hipSuccess && (s = solve_start(r, st))) out = s;
+                if (!out && e == hipSuccess) e = hipEventRecord(e1, st);
+                if (!out && e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (!out && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e != hipSuccess) {
+                    ctqr_last_hip_error(e, "solver tuning", __FILE__, __LINE__);
+                    out = CTQR_EHIP;
+                }
+                if (rep > 0) tot += ms;   // the first run warms up
+            }
+            if (!out && (c == 0 || tot < best)) {
+                best = tot;
+                pick = cands[c];
+            }
+        }
+        if (out) break;
+        if (pick != bk.narrow) {
+            bk.narrow = pick;
+            bk.iters = -1;
+            drop_graph(bk);
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return out;
 }
 
 bool geometry_ok(const ctqr_geometry *g)
@@ -475,6 +800,143 @@ ctqr_status ctqr_qr_solve_slices(int64_t m, int64_t n, ctqr_dtype dtype, const v
     } catch (...) {
         return CTQR_EHIP;
     }
+}
+
+namespace {
+ctqr_status solver_desc_check(const ctqr_solver_desc *d)
+{
+    if (!d) return CTQR_EINVAL;
+    if (d->m < d->n || d->n < 1 || d->m >= INT32_MAX) return CTQR_EINVAL;
+    if (d->dtype != CTQR_F64 && d->dtype != CTQR_F32) return CTQR_EINVAL;
+    if (!nb_ok(resolve_nb(d->nb))) return CTQR_EINVAL;
+    if (!d->QR || !d->T || !d->tau || !d->Rinv) return CTQR_EINVAL;
+    if (!aligned16(d->QR) || !aligned16(d->T) || !aligned16(d->Rinv)) return CTQR_EINVAL;
+    if (d->lda < d->m || d->lda % 4 != 0) return CTQR_EINVAL;
+    if (d->max_slices < 1 || d->max_slices > SOLVER_MAX_SLICES) return CTQR_EINVAL;
+    const ctqr_sparse *A = d->A64;
+    if (A && (A->m != d->m || A->n != d->n || !A->rowptr || !A->col || !A->val || !A->colptr || !A->row ||
+              !A->cval))
+        return CTQR_EINVAL;
+    if (A && (d->max_iters < 0 || !(d->tol >= 0.0))) return CTQR_EINVAL;
+    return CTQR_OK;
+}
+}  // namespace
+
+ctqr_status ctqr_solver_workspace(const ctqr_solver_desc *desc, size_t *bytes)
+{
+    ctqr_status s = solver_desc_check(desc);
+    if (s || !bytes) return s ? s : CTQR_EINVAL;
+    ctqr_solver_desc d = *desc;
+    d.nb = resolve_nb(d.nb);
+    *bytes = solver_layout(&d, nullptr, next_pow2(d.max_slices), round_up(d.m, 64)).bytes;
+    return CTQR_OK;
+}
+
+ctqr_status ctqr_solver_create(const ctqr_solver_desc *desc, void *work, size_t work_bytes, ctqr_solver *out)
+{
+    try {
+        ctqr_status s = solver_desc_check(desc);
+        if (s) return s;
+        if (!out || !work || !aligned16(work)) return CTQR_EINVAL;
+        *out = nullptr;
+        size_t need = 0;
+        ctqr_solver_workspace(desc, &need);
+        if (work_bytes < need) return CTQR_ENOMEM;
+        auto *sv = new ctqr_solver_t;
+        sv->d = *desc;
+        sv->d.nb = resolve_nb(desc->nb);
+        sv->refine = desc->A64 != nullptr && desc->max_iters > 0;
+        if (desc->A64) sv->sp = *desc->A64;
+        sv->d.A64 = desc->A64 ? &sv->sp : nullptr;
+        sv->smax = next_pow2(desc->max_slices);
+        sv->ldbp = round_up(desc->m, 64);
+        SolverLayout L = solver_layout(&sv->d, work, sv->smax, sv->ldbp);
+        sv->info = L.info;
+        sv->Bpad = L.Bpad;
+        sv->swork = L.swork;
+        for (int b = 1; b <= sv->smax; b <<= 1) {
+            SolverBucket bk;
+            bk.S = b;
+            bk.narrow = b <= DEFAULT_NARROW ? DEFAULT_NARROW : 0;
+            sv->buckets.push_back(bk);
+        }
+        hipError_t e = hipStreamCreateWithFlags(&sv->cap, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            ctqr_last_hip_error(e, "hipStreamCreateWithFlags", __FILE__, __LINE__);
+            delete sv;
+            return CTQR_EHIP;
+        }
+        *out = sv;
+        return CTQR_OK;
+    } catch (...) {
+        return CTQR_EHIP;
+    }
+}
+
+ctqr_status ctqr_solver_tune(ctqr_solver sv, int32_t reps, hipStream_t stream)
+{
+    try {
+        if (!sv || reps < 1 || reps > 100) return CTQR_EINVAL;
+        std::lock_guard<std::mutex> lk(sv->mu);
+        if (sv->d.dtype == CTQR_F64) return solver_tune_t<double>(sv, stream, reps);
+        return solver_tune_t<float>(sv, stream, reps);
+    } catch (...) {
+        return CTQR_EHIP;
+    }
+}
+
+ctqr_status ctqr_solver_solve(ctqr_solver sv, const double *B, int64_t ldb, int32_t nslices, double *X,
+                              int64_t ldx, ctqr_info *info, hipStream_t stream)
+{
+    return ctqr_solver_solve_batch(sv, 1, &B, &ldb, &nslices, &X, &ldx, info, stream);
+}
+
+ctqr_status ctqr_solver_solve_batch(ctqr_solver sv, int32_t nreq, const double *const *B, const int64_t *ldb,
+                                    const int32_t *nslices, double *const *X, const int64_t *ldx, ctqr_info *info,
+                                    hipStream_t stream)
+{
+    try {
+        if (!sv || nreq < 1 || !B || !ldb || !nslices || !X || !ldx || !info) return CTQR_EINVAL;
+        int64_t total = 0;
+        for (int i = 0; i < nreq; ++i) {
+            if (!B[i] || !X[i] || nslices[i] < 1 || ldb[i] < sv->d.m || ldx[i] < sv->d.n) return CTQR_EINVAL;
+            total += nslices[i];
+        }
+        if (total > sv->smax) return CTQR_EINVAL;
+        std::lock_guard<std::mutex> lk(sv->mu);
+        if (sv->d.dtype == CTQR_F64)
+            return solver_solve_t<double>(sv, nreq, B, ldb, nslices, X, ldx, info, stream);
+        return solver_solve_t<float>(sv, nreq, B, ldb, nslices, X, ldx, info, stream);
+    } catch (...) {
+        return CTQR_EHIP;
+    }
+}
+
+ctqr_status ctqr_solver_query(ctqr_solver sv, int32_t nslices, int32_t *bucket, int32_t *slice_tile,
+                              int32_t *graph_iters)
+{
+    if (!sv || !bucket || !slice_tile || !graph_iters || nslices < 1 || nslices > sv->smax) return CTQR_EINVAL;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    for (auto &b : sv->buckets)
+        if (b.S >= nslices) {
+            *bucket = b.S;
+            *slice_tile = b.narrow >= b.S ? 32 : 128;
+            *graph_iters = b.exec ? b.graph_iters : -1;
+            return CTQR_OK;
+        }
+    return CTQR_EINVAL;
+}
+
+ctqr_status ctqr_solver_destroy(ctqr_solver sv)
+{
+    if (!sv) return CTQR_OK;
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        for (auto &b : sv->buckets) drop_graph(b);
+        if (sv->cap) (void)hipStreamDestroy(sv->cap);
+    }
+    delete sv;
+    return CTQR_OK;
 }
 
 ctqr_status ctqr_spmm(const ctqr_sparse *A64, int32_t nslices, double alpha, const double *X, int64_t ldx,

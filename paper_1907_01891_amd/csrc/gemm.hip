@@ -19,7 +19,10 @@
 //
 // Tiling (gfx950, 64-wide waves): a 256-thread workgroup owns a 128 x 128
 // output tile, each of its 4 waves a 64 x 64 sub-tile built from MFMA blocks
-// (FP32: v_mfma_f32_32x32x2f32, FP64: v_mfma_f64_16x16x4f64).  The k-step is
+// (FP32: v_mfma_f32_32x32x2f32, FP64: v_mfma_f64_16x16x4f64).  Products with
+// few output columns (a solve with a handful of slices) use a 128 x 32 tile
+// instead, one 32 x 32 sub-tile per wave, so a narrow right-hand side does not
+// pay for 128 columns of MFMA work.  The k-step is
 // 128 bytes of every operand column (32 floats / 16 doubles), staged through
 // double-buffered LDS from 16-byte coalesced global loads.  The MFMA output is
 // computed transposed, so that the 32 (FP32) or 16 (FP64) lanes that share an
@@ -105,19 +108,20 @@ template <typename T> using vec16_t = typename Vec16<T>::type;
 // load latency.
 
 // ---------------------------------------------------------------------------
-// Loader of a 128-column x BK tile whose columns are contiguous in k
+// Loader of a COLS-column x BK tile whose columns are contiguous in k
 // ("[col][k]" LDS layout, padded), used for both TN operands and for the B
 // operand of NN.  Column c of the tile is operand column col0 + c, rows
 // k0 .. k0+BK-1.  mask_cols > 0 marks the first mask_cols operand columns as
 // a Householder block (diagonal at row == column).
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int COLS = TILE>
 struct KcTile {
     static constexpr int BK = Mf<T>::BK;
     static constexpr int LD = BK + Mf<T>::PAD_KC;
     static constexpr int E = 16 / sizeof(T);
     static constexpr int CPC = BK / E;                 // chunks per column (8)
-    static constexpr int PER_THR = TILE * CPC / NTHR;  // 4
+    static constexpr int PER_THR = COLS * CPC / NTHR;  // 4 (1 for a 32-column tile)
+    static_assert(COLS * CPC % NTHR == 0, "tile does not split evenly over the workgroup");
     vec16_t<T> r[PER_THR];
     int col0_, k0_, kmax_, ncols_, mask_;
 
@@ -203,13 +207,13 @@ struct MkTile {
     }
 };
 
-// One BK-deep step of a wave's 64x64 MFMA accumulation from LDS.
+// One BK-deep step of a wave's (NI*MB) x (NJ*MB) MFMA accumulation from LDS.
 // opA: [n][k] tile (MFMA rows = output columns n), opB: [m][k] tile when
 // B_KC (TN) or [k][m] tile otherwise (NN).  Output block (ib, jb) covers
 // output columns wn + ib*MB .. and rows wm + jb*MB ..
-template <typename T, bool B_KC>
+template <typename T, bool B_KC, int NI, int NJ>
 __device__ inline void mfma_step(const T *opA, const T *opB, int wn, int wm,
-                                 typename Mf<T>::acc_t (&acc)[Mf<T>::NBLK][Mf<T>::NBLK])
+                                 typename Mf<T>::acc_t (&acc)[NI][NJ])
 {
     using M = Mf<T>;
     const int lane = threadIdx.x % CTQR_WAVE;
@@ -220,12 +224,12 @@ __device__ inline void mfma_step(const T *opA, const T *opB, int wn, int wm,
         const int kk = 4 * slot;
 #pragma unroll
         for (int sp = 0; sp < 2; ++sp) {
-            doublex2 a[M::NBLK], b[M::NBLK];
+            doublex2 a[NI], b[NJ];
 #pragma unroll
-            for (int ib = 0; ib < M::NBLK; ++ib)
+            for (int ib = 0; ib < NI; ++ib)
                 a[ib] = *reinterpret_cast<const doublex2 *>(opA + (wn + ib * M::MB + li) * KcTile<T>::LD + kk + 2 * sp);
 #pragma unroll
-            for (int jb = 0; jb < M::NBLK; ++jb) {
+            for (int jb = 0; jb < NJ; ++jb) {
                 if constexpr (B_KC) {
                     b[jb] = *reinterpret_cast<const doublex2 *>(opB + (wm + jb * M::MB + li) * KcTile<T>::LD + kk + 2 * sp);
                 } else {
@@ -237,9 +241,9 @@ __device__ inline void mfma_step(const T *opA, const T *opB, int wn, int wm,
 #pragma unroll
             for (int s = 0; s < 2; ++s)
 #pragma unroll
-                for (int ib = 0; ib < M::NBLK; ++ib)
+                for (int ib = 0; ib < NI; ++ib)
 #pragma unroll
-                    for (int jb = 0; jb < M::NBLK; ++jb)
+                    for (int jb = 0; jb < NJ; ++jb)
                         acc[ib][jb] = mfma(a[ib][s], b[jb][s], acc[ib][jb]);
         }
         return;
@@ -247,14 +251,14 @@ __device__ inline void mfma_step(const T *opA, const T *opB, int wn, int wm,
     // FP32: 4 k-groups of 8 per stage; the LDS fragments of k-group g+1 are
     // fetched into the second register set while the 16 MFMAs of group g issue.
     constexpr int NG = M::BK / M::KG;
-    floatx4 a[2][M::NBLK], b[2][M::NBLK];
+    floatx4 a[2][NI], b[2][NJ];
     auto fetch = [&](int g, int buf) {
         const int kk = g * M::KG + 4 * slot;
 #pragma unroll
-        for (int ib = 0; ib < M::NBLK; ++ib)
+        for (int ib = 0; ib < NI; ++ib)
             a[buf][ib] = *reinterpret_cast<const floatx4 *>(opA + (wn + ib * M::MB + li) * KcTile<T>::LD + kk);
 #pragma unroll
-        for (int jb = 0; jb < M::NBLK; ++jb) {
+        for (int jb = 0; jb < NJ; ++jb) {
             if constexpr (B_KC) {
                 b[buf][jb] = *reinterpret_cast<const floatx4 *>(opB + (wm + jb * M::MB + li) * KcTile<T>::LD + kk);
             } else {
@@ -272,9 +276,9 @@ __device__ inline void mfma_step(const T *opA, const T *opB, int wn, int wm,
 #pragma unroll
         for (int s = 0; s < 4; ++s)
 #pragma unroll
-            for (int ib = 0; ib < M::NBLK; ++ib)
+            for (int ib = 0; ib < NI; ++ib)
 #pragma unroll
-                for (int jb = 0; jb < M::NBLK; ++jb)
+                for (int jb = 0; jb < NJ; ++jb)
                     acc[ib][jb] = mfma(a[cb][ib][s], b[cb][jb][s], acc[ib][jb]);
     }
 }
@@ -299,10 +303,22 @@ __device__ inline void acc_coords(int ib, int jb, int r, int &n, int &m)
 
 template <typename T> constexpr int acc_len() { return sizeof(T) == 4 ? 16 : 4; }
 
+// Wave layout of a 128 x TW output tile (TW = 128 or 32 output columns): each
+// wave owns an EDGE x EDGE sub-tile of NI x NJ MFMA blocks at (wn, wm).
+template <typename T, int TW>
+struct WaveTile {
+    static_assert(TW == TILE || TW == 32, "output tile width is 128 or 32");
+    static constexpr int EDGE = TW == TILE ? 64 : 32;
+    static constexpr int NI = EDGE / Mf<T>::MB;   // blocks along output columns
+    static constexpr int NJ = EDGE / Mf<T>::MB;   // blocks along output rows
+    __device__ static inline int wn(int wave) { return TW == TILE ? (wave / 2) * 64 : 0; }
+    __device__ static inline int wm(int wave) { return TW == TILE ? (wave % 2) * 64 : wave * 32; }
+};
+
 // ---------------------------------------------------------------------------
 // TN:  Out = alpha * A^T B + beta * Out   (or split-K partials)
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int TW>
 __global__ __launch_bounds__(NTHR, 2)
 void gemm_tn_kernel(int M, int N, int K,
                     const T *__restrict__ A, int64_t lda, int amask,
@@ -311,27 +327,29 @@ void gemm_tn_kernel(int M, int N, int K,
                     T *__restrict__ part, int kchunk, const int *skip)
 {
     using Mt = Mf<T>;
+    using W = WaveTile<T, TW>;
     if (skip && *skip) return;
     __shared__ __attribute__((aligned(16))) T sA[2][TILE * KcTile<T>::LD];
-    __shared__ __attribute__((aligned(16))) T sB[2][TILE * KcTile<T>::LD];
+    __shared__ __attribute__((aligned(16))) T sB[2][TW * KcTile<T>::LD];
 
     int tm, tn;
-    tile_of_block((M + TILE - 1) / TILE, (N + TILE - 1) / TILE, tm, tn);
-    const int m0 = tm * TILE, n0 = tn * TILE;
+    tile_of_block((M + TILE - 1) / TILE, (N + TW - 1) / TW, tm, tn);
+    const int m0 = tm * TILE, n0 = tn * TW;
     const int kbeg = blockIdx.z * kchunk;
     const int kend = min(K, kbeg + kchunk);
     const int wave = threadIdx.x / CTQR_WAVE;
-    const int wn = (wave / 2) * 64, wm = (wave % 2) * 64;
+    const int wn = W::wn(wave), wm = W::wm(wave);
 
-    typename Mt::acc_t acc[Mt::NBLK][Mt::NBLK];
+    typename Mt::acc_t acc[W::NI][W::NJ];
 #pragma unroll
-    for (int i = 0; i < Mt::NBLK; ++i)
+    for (int i = 0; i < W::NI; ++i)
 #pragma unroll
-        for (int j = 0; j < Mt::NBLK; ++j)
+        for (int j = 0; j < W::NJ; ++j)
 #pragma unroll
             for (int e = 0; e < acc_len<T>(); ++e) acc[i][j][e] = T(0);
 
-    KcTile<T> la, lb;
+    KcTile<T> la;
+    KcTile<T, TW> lb;
     if (kbeg < kend) {
         la.load(A, lda, M, m0, kbeg, kend, amask);
         lb.load(B, ldb, N, n0, kbeg, kend, bmask);
@@ -346,7 +364,7 @@ void gemm_tn_kernel(int M, int N, int K,
             la.load(A, lda, M, m0, k + Mt::BK, kend, amask);
             lb.load(B, ldb, N, n0, k + Mt::BK, kend, bmask);
         }
-        mfma_step<T, true>(sB[cur], sA[cur], wn, wm, acc);
+        mfma_step<T, true, W::NI, W::NJ>(sB[cur], sA[cur], wn, wm, acc);
         if (more) {
             la.store(sA[cur ^ 1]);
             lb.store(sB[cur ^ 1]);
@@ -357,9 +375,9 @@ void gemm_tn_kernel(int M, int N, int K,
 
     const bool split = gridDim.z > 1;
 #pragma unroll
-    for (int ib = 0; ib < Mt::NBLK; ++ib)
+    for (int ib = 0; ib < W::NI; ++ib)
 #pragma unroll
-        for (int jb = 0; jb < Mt::NBLK; ++jb)
+        for (int jb = 0; jb < W::NJ; ++jb)
 #pragma unroll
             for (int r = 0; r < acc_len<T>(); ++r) {
                 int n, m;
@@ -400,7 +418,7 @@ __global__ void splitk_reduce_kernel(int M, int N, int splits, const T *__restri
 // ---------------------------------------------------------------------------
 // KIND only separates the symbols of the launch sites in a profile: 1 is the
 // trailing update of the factorization, 0 every other use.
-template <typename T, int KIND>
+template <typename T, int KIND, int TW>
 __global__ __launch_bounds__(NTHR, 2)
 void gemm_nn_kernel(int M, int N, int K,
                     const T *__restrict__ A, int64_t lda, int amask,
@@ -409,32 +427,33 @@ void gemm_nn_kernel(int M, int N, int K,
 {
     // accum != 0: C += alpha A B;  accum == 0: C = alpha A B (C is not read)
     using Mt = Mf<T>;
+    using W = WaveTile<T, TW>;
     if (skip && *skip) return;
     __shared__ __attribute__((aligned(16))) T sA[2][Mt::BK * MkTile<T>::LD];
-    __shared__ __attribute__((aligned(16))) T sB[2][TILE * KcTile<T>::LD];
+    __shared__ __attribute__((aligned(16))) T sB[2][TW * KcTile<T>::LD];
 
     int tm, tn;
-    tile_of_block((M + TILE - 1) / TILE, (N + TILE - 1) / TILE, tm, tn);
-    const int m0 = tm * TILE, n0 = tn * TILE;
+    tile_of_block((M + TILE - 1) / TILE, (N + TW - 1) / TW, tm, tn);
+    const int m0 = tm * TILE, n0 = tn * TW;
     const int wave = threadIdx.x / CTQR_WAVE;
-    const int wn = (wave / 2) * 64, wm = (wave % 2) * 64;
+    const int wn = W::wn(wave), wm = W::wm(wave);
 
-    typename Mt::acc_t acc[Mt::NBLK][Mt::NBLK];
+    typename Mt::acc_t acc[W::NI][W::NJ];
 #pragma unroll
-    for (int i = 0; i < Mt::NBLK; ++i)
+    for (int i = 0; i < W::NI; ++i)
 #pragma unroll
-        for (int j = 0; j < Mt::NBLK; ++j)
+        for (int j = 0; j < W::NJ; ++j)
 #pragma unroll
             for (int e = 0; e < acc_len<T>(); ++e) acc[i][j][e] = T(0);
 
     // FP32: fetch the C tile now; its HBM latency hides behind the K loop
     constexpr bool PRE = sizeof(T) == 4;
-    T cpre[PRE ? Mt::NBLK : 1][PRE ? Mt::NBLK : 1][PRE ? 16 : 1];
+    T cpre[PRE ? W::NI : 1][PRE ? W::NJ : 1][PRE ? 16 : 1];
     if constexpr (PRE) {
 #pragma unroll
-        for (int ib = 0; ib < Mt::NBLK; ++ib)
+        for (int ib = 0; ib < W::NI; ++ib)
 #pragma unroll
-            for (int jb = 0; jb < Mt::NBLK; ++jb)
+            for (int jb = 0; jb < W::NJ; ++jb)
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     int n, m;
@@ -446,7 +465,7 @@ void gemm_nn_kernel(int M, int N, int K,
     }
 
     MkTile<T> la;
-    KcTile<T> lb;
+    KcTile<T, TW> lb;
     la.load(A, lda, M, m0, 0, K, amask != 0);
     lb.load(B, ldb, N, n0, 0, K, 0);
     la.store(sA[0]);
@@ -459,7 +478,7 @@ void gemm_nn_kernel(int M, int N, int K,
             la.load(A, lda, M, m0, k + Mt::BK, K, amask != 0);
             lb.load(B, ldb, N, n0, k + Mt::BK, K, 0);
         }
-        mfma_step<T, false>(sB[cur], sA[cur], wn, wm, acc);
+        mfma_step<T, false, W::NI, W::NJ>(sB[cur], sA[cur], wn, wm, acc);
         if (more) {
             la.store(sA[cur ^ 1]);
             lb.store(sB[cur ^ 1]);
@@ -469,9 +488,9 @@ void gemm_nn_kernel(int M, int N, int K,
     }
 
 #pragma unroll
-    for (int ib = 0; ib < Mt::NBLK; ++ib)
+    for (int ib = 0; ib < W::NI; ++ib)
 #pragma unroll
-        for (int jb = 0; jb < Mt::NBLK; ++jb)
+        for (int jb = 0; jb < W::NJ; ++jb)
 #pragma unroll
             for (int r = 0; r < acc_len<T>(); ++r) {
                 int n, m;
@@ -508,6 +527,16 @@ int num_cus()
 // ---------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------
+namespace {
+// Products with at most this many output columns use the 128 x 32 tile
+// (per host thread; 0 = always the 128 x 128 tile).
+thread_local int t_narrow_max = 0;
+constexpr int NARROW = 32;
+}  // namespace
+
+int gemm_narrow_max() { return t_narrow_max; }
+void gemm_set_narrow_max(int n) { t_narrow_max = n < 0 ? 0 : n; }
+
 size_t gemm_tn_partial_elems(int M, int N, int K)
 {
     int splits = gemm_tn_splits(M, N, K);
@@ -516,14 +545,18 @@ size_t gemm_tn_partial_elems(int M, int N, int K)
 
 int gemm_tn_splits(int M, int N, int K)
 {
-    int64_t tiles = ceil_div(M, TILE) * ceil_div(N, TILE);
+    const bool narrow = N <= t_narrow_max;
+    int64_t tiles = ceil_div(M, TILE) * ceil_div(N, narrow ? NARROW : TILE);
     int target = 2 * num_cus();
     if (tiles >= target) return 1;
     int64_t splits = ceil_div(target, tiles);
     int64_t max_by_k = K / (4 * 32);   // keep at least 4 k-steps per split
     if (splits > max_by_k) splits = max_by_k;
     if (splits < 1) splits = 1;
-    if (splits > 64) splits = 64;
+    // narrow products read a tall operand through few tiles: allow more
+    // splits so the read still spreads over every CU
+    const int cap = narrow ? 256 : 64;
+    if (splits > cap) splits = cap;
     return (int)splits;
 }
 
@@ -533,14 +566,19 @@ ctqr_status gemm_tn(int M, int N, int K, const T *A, int64_t lda, int amask, con
                     size_t part_elems, const int *skip, hipStream_t st)
 {
     if (M <= 0 || N <= 0) return CTQR_OK;
+    const bool narrow = N <= t_narrow_max;
     int splits = gemm_tn_splits(M, N, K);
     if (splits > 1 && (part == nullptr || part_elems < (size_t)splits * M * N)) splits = 1;
     int kchunk = (int)ceil_div(ceil_div(K, splits), Mf<T>::BK) * Mf<T>::BK;
     if (kchunk <= 0) kchunk = Mf<T>::BK;
     splits = (int)ceil_div(K > 0 ? K : 1, kchunk);
-    dim3 grid((unsigned)(ceil_div(M, TILE) * ceil_div(N, TILE)), 1, (unsigned)splits);
-    LAUNCH_TRY(gemm_tn_kernel<T>, grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B, ldb, bmask,
-               alpha, beta, Out, ldo, part, kchunk, skip);
+    dim3 grid((unsigned)(ceil_div(M, TILE) * ceil_div(N, narrow ? NARROW : TILE)), 1, (unsigned)splits);
+    if (narrow)
+        LAUNCH_TRY((gemm_tn_kernel<T, NARROW>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B, ldb,
+                   bmask, alpha, beta, Out, ldo, part, kchunk, skip);
+    else
+        LAUNCH_TRY((gemm_tn_kernel<T, TILE>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B, ldb,
+                   bmask, alpha, beta, Out, ldo, part, kchunk, skip);
     if (splits > 1) {
         int64_t total = (int64_t)M * N;
         LAUNCH_TRY(splitk_reduce_kernel<T>, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, st,
@@ -559,13 +597,17 @@ ctqr_status gemm_nn(int M, int N, int K, const T *A, int64_t lda, int amask, con
         if (accum) return CTQR_OK;
         K = 0;   // C = 0: the kernel runs with an empty k loop
     }
-    dim3 grid((unsigned)(ceil_div(M, TILE) * ceil_div(N, TILE)));
+    const bool narrow = N <= t_narrow_max;
+    dim3 grid((unsigned)(ceil_div(M, TILE) * ceil_div(N, narrow ? NARROW : TILE)));
     if (kind == 1)
-        LAUNCH_TRY((gemm_nn_kernel<T, 1>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B, ldb, alpha,
-                   C, ldc, accum, skip);
+        LAUNCH_TRY((gemm_nn_kernel<T, 1, TILE>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B, ldb,
+                   alpha, C, ldc, accum, skip);
+    else if (narrow)
+        LAUNCH_TRY((gemm_nn_kernel<T, 0, NARROW>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B, ldb,
+                   alpha, C, ldc, accum, skip);
     else
-        LAUNCH_TRY((gemm_nn_kernel<T, 0>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B, ldb, alpha,
-                   C, ldc, accum, skip);
+        LAUNCH_TRY((gemm_nn_kernel<T, 0, TILE>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B, ldb,
+                   alpha, C, ldc, accum, skip);
     return CTQR_OK;
 }
 

@@ -3,6 +3,10 @@
 #include "common.h"
 
 // ---- gemm.hip --------------------------------------------------------------
+// Products launched from this host thread with at most gemm_narrow_max()
+// output columns use the 128 x 32 output tile (0: never).
+int gemm_narrow_max();
+void gemm_set_narrow_max(int n);
 int gemm_tn_splits(int M, int N, int K);
 size_t gemm_tn_partial_elems(int M, int N, int K);
 template <typename T>
@@ -67,6 +71,9 @@ ctqr_status cm_to_rm(int64_t rows, int S, const TSRC *src, int64_t lds, TD *dst,
 template <typename TD, typename TSRC>
 ctqr_status rm_to_cm(int64_t rows, int S, const TSRC *src, TD *dst, int64_t ldd, const int *skip,
                      hipStream_t st);
+// the first S of the ss slices of a row-major FP64 array, column-major
+ctqr_status rm_to_cm_sub(int64_t rows, int ss, int S, const double *src, double *dst, int64_t ldd,
+                         hipStream_t st);
 template <typename TD, typename TSRC>
 ctqr_status copy_cm(int64_t rows, int S, const TSRC *src, int64_t lds, TD *dst, int64_t ldd,
                     hipStream_t st);

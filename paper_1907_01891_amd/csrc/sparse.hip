@@ -79,9 +79,10 @@ __global__ void cm_to_rm_kernel(int64_t rows, int S, const TSRC *__restrict__ sr
 }
 
 template <typename TD, typename TSRC>
-__global__ void rm_to_cm_kernel(int64_t rows, int S, const TSRC *__restrict__ src,
+__global__ void rm_to_cm_kernel(int64_t rows, int S, int ss, const TSRC *__restrict__ src,
                                 TD *__restrict__ dst, int64_t ldd, const int *skip)
 {
+    // the first S of the ss values of each source row
     if (skip && *skip) return;
     __shared__ double t[32][33];
     const int64_t r0 = (int64_t)blockIdx.x * 32;
@@ -89,7 +90,7 @@ __global__ void rm_to_cm_kernel(int64_t rows, int S, const TSRC *__restrict__ sr
     for (int k = threadIdx.y; k < 32; k += 8) {
         int64_t r = r0 + k;
         int s = s0 + threadIdx.x;
-        t[k][threadIdx.x] = (r < rows && s < S) ? (double)src[r * S + s] : 0.0;
+        t[k][threadIdx.x] = (r < rows && s < S) ? (double)src[r * ss + s] : 0.0;
     }
     __syncthreads();
     for (int k = threadIdx.y; k < 32; k += 8) {
@@ -275,7 +276,16 @@ ctqr_status rm_to_cm(int64_t rows, int S, const TSRC *src, TD *dst, int64_t ldd,
 {
     if (rows <= 0 || S <= 0) return CTQR_OK;
     LAUNCH_TRY((rm_to_cm_kernel<TD, TSRC>), dim3((unsigned)ceil_div(rows, 32), (unsigned)ceil_div(S, 32)),
-               dim3(32, 8), 0, st, rows, S, src, dst, ldd, skip);
+               dim3(32, 8), 0, st, rows, S, S, src, dst, ldd, skip);
+    return CTQR_OK;
+}
+
+ctqr_status rm_to_cm_sub(int64_t rows, int ss, int S, const double *src, double *dst, int64_t ldd,
+                         hipStream_t st)
+{
+    if (rows <= 0 || S <= 0) return CTQR_OK;
+    LAUNCH_TRY((rm_to_cm_kernel<double, double>), dim3((unsigned)ceil_div(rows, 32), (unsigned)ceil_div(S, 32)),
+               dim3(32, 8), 0, st, rows, S, ss, src, dst, ldd, nullptr);
     return CTQR_OK;
 }
 

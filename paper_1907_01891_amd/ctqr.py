@@ -47,6 +47,12 @@ class ctqr_info(ctypes.Structure):
                 ("max_rel_update", c_dbl), ("rdiag_max", c_dbl), ("rdiag_min", c_dbl), ("nnz", c_i64)]
 
 
+class ctqr_solver_desc(ctypes.Structure):
+    _fields_ = [("m", c_i64), ("n", c_i64), ("dtype", c_i32), ("nb", c_i32), ("QR", c_vp), ("lda", c_i64),
+                ("T", c_vp), ("tau", c_vp), ("Rinv", c_vp), ("A64", ctypes.POINTER(ctqr_sparse)),
+                ("tol", c_dbl), ("max_iters", c_i32), ("max_slices", c_i32)]
+
+
 _P = ctypes.POINTER
 _SIGNATURES = {
     "ctqr_status_string": (ctypes.c_char_p, [c_i32]),
@@ -64,6 +70,14 @@ _SIGNATURES = {
     "ctqr_qr_solve_slices": (c_i32, [c_i64, c_i64, c_i32, c_vp, c_i64, c_vp, c_vp, c_vp, c_i32,
                                      c_vp, c_i64, c_i32, c_vp, c_i64, _P(ctqr_sparse), c_dbl, c_i32,
                                      c_vp, c_sz, c_vp, c_vp]),
+    "ctqr_solver_workspace": (c_i32, [_P(ctqr_solver_desc), _P(c_sz)]),
+    "ctqr_solver_create": (c_i32, [_P(ctqr_solver_desc), c_vp, c_sz, _P(c_vp)]),
+    "ctqr_solver_tune": (c_i32, [c_vp, c_i32, c_vp]),
+    "ctqr_solver_solve": (c_i32, [c_vp, c_vp, c_i64, c_i32, c_vp, c_i64, c_vp, c_vp]),
+    "ctqr_solver_solve_batch": (c_i32, [c_vp, c_i32, _P(c_vp), _P(c_i64), _P(c_i32), _P(c_vp), _P(c_i64),
+                                        c_vp, c_vp]),
+    "ctqr_solver_query": (c_i32, [c_vp, c_i32, _P(c_i32), _P(c_i32), _P(c_i32)]),
+    "ctqr_solver_destroy": (c_i32, [c_vp]),
     "ctqr_spmm": (c_i32, [_P(ctqr_sparse), c_i32, c_dbl, c_vp, c_i64, c_dbl, c_vp, c_i64, c_vp]),
     "ctqr_profile_enable": (c_i32, [c_i32]),
     "ctqr_profile_read": (c_i32, [_P(c_i64), _P(c_dbl), _P(c_dbl)]),
@@ -160,6 +174,43 @@ def ctqr_qr_solve_slices(m, n, dtype, QR_ptr, lda, T_ptr, tau_ptr, rinv_ptr, nb,
     return lib().ctqr_qr_solve_slices(m, n, dtype, QR_ptr, lda, T_ptr, tau_ptr, rinv_ptr, nb, B_ptr, ldb, nslices,
                                       X_ptr, ldx, ctypes.byref(sparse) if sparse is not None else None,
                                       tol, max_iters, work_ptr, work_bytes, info_ptr, stream)
+
+
+def ctqr_solver_workspace(desc):
+    b = c_sz()
+    check(lib().ctqr_solver_workspace(ctypes.byref(desc), ctypes.byref(b)), "ctqr_solver_workspace")
+    return b.value
+
+
+def ctqr_solver_create(desc, work_ptr, work_bytes):
+    h = c_vp()
+    check(lib().ctqr_solver_create(ctypes.byref(desc), work_ptr, work_bytes, ctypes.byref(h)), "ctqr_solver_create")
+    return h
+
+
+def ctqr_solver_tune(solver, reps, stream):
+    return lib().ctqr_solver_tune(solver, reps, stream)
+
+
+def ctqr_solver_solve(solver, B_ptr, ldb, nslices, X_ptr, ldx, info_ptr, stream):
+    return lib().ctqr_solver_solve(solver, B_ptr, ldb, nslices, X_ptr, ldx, info_ptr, stream)
+
+
+def ctqr_solver_solve_batch(solver, B_ptrs, ldbs, nslices, X_ptrs, ldxs, info_ptr, stream):
+    k = len(B_ptrs)
+    return lib().ctqr_solver_solve_batch(solver, k, (c_vp * k)(*B_ptrs), (c_i64 * k)(*ldbs), (c_i32 * k)(*nslices),
+                                         (c_vp * k)(*X_ptrs), (c_i64 * k)(*ldxs), info_ptr, stream)
+
+
+def ctqr_solver_query(solver, nslices):
+    b, t, g = c_i32(), c_i32(), c_i32()
+    check(lib().ctqr_solver_query(solver, nslices, ctypes.byref(b), ctypes.byref(t), ctypes.byref(g)),
+          "ctqr_solver_query")
+    return b.value, t.value, g.value
+
+
+def ctqr_solver_destroy(solver):
+    return lib().ctqr_solver_destroy(solver)
 
 
 def ctqr_spmm(sparse, nslices, alpha, X_ptr, ldx, beta, Y_ptr, ldy, stream):

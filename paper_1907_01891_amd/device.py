@@ -174,3 +174,58 @@ class QRFactor:
                                        wp, wb, self.sinfo.ptr, stream_handle(stream)),
                 "ctqr_qr_solve_slices")
         return X
+
+
+class Solver:
+    """Batched solver over a stored factor (ctqr_solver_*): requests of 1 ..
+    max_slices slices, one HIP graph per power-of-two slice bucket."""
+
+    def __init__(self, qr, max_slices, sparse=None, tol=1e-13, max_iters=0, device="cuda"):
+        self.qr = qr
+        self.sparse = sparse    # ctqr_sparse (kept alive: the solver copies the struct only)
+        self.desc = C.ctqr_solver_desc(qr.m, qr.n, qr.dtype, qr.nb, qr.A.data_ptr(), ld_of(qr.A), qr.T.data_ptr(),
+                                       qr.tau.data_ptr(), qr.Rinv.data_ptr(),
+                                       ctypes.pointer(sparse) if sparse is not None else None,
+                                       float(tol), int(max_iters) if sparse is not None else 0, int(max_slices))
+        nbytes = C.ctqr_solver_workspace(self.desc)
+        self.work = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        self.h = C.ctqr_solver_create(self.desc, ctypes.c_void_p(self.work.data_ptr()), self.work.numel())
+        self.info = Info(device)
+        self.device = device
+
+    def tune(self, reps=2, stream=None):
+        C.check(C.ctqr_solver_tune(self.h, reps, stream_handle(stream)), "ctqr_solver_tune")
+
+    def solve(self, B, X=None, stream=None):
+        S = B.shape[1]
+        if X is None:
+            X = colmajor(self.qr.n, S, torch.float64, self.device)
+        C.check(C.ctqr_solver_solve(self.h, ctypes.c_void_p(B.data_ptr()), ld_of(B), S,
+                                    ctypes.c_void_p(X.data_ptr()), ld_of(X), self.info.ptr, stream_handle(stream)),
+                "ctqr_solver_solve")
+        return X
+
+    def solve_batch(self, Bs, Xs=None, stream=None):
+        """Queued requests packed into one bucket (sum of slices <= max_slices)."""
+        if Xs is None:
+            Xs = [colmajor(self.qr.n, b.shape[1], torch.float64, self.device) for b in Bs]
+        C.check(C.ctqr_solver_solve_batch(self.h, [b.data_ptr() for b in Bs], [ld_of(b) for b in Bs],
+                                          [b.shape[1] for b in Bs], [x.data_ptr() for x in Xs],
+                                          [ld_of(x) for x in Xs], self.info.ptr, stream_handle(stream)),
+                "ctqr_solver_solve_batch")
+        return Xs
+
+    def query(self, nslices):
+        """(bucket, slice_tile, graph_iters) for a request of nslices."""
+        return C.ctqr_solver_query(self.h, nslices)
+
+    def close(self):
+        if self.h is not None:
+            C.ctqr_solver_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -146,3 +146,55 @@ def test_build_rejects():
     assert L.ctqr_build_system_matrix(ctypes.byref(g), C.CTQR_F64, p, 3072, None, p, 4, p, None) == C.CTQR_ENOMEM
     # spmm argument checks
     assert L.ctqr_spmm(None, 1, 1.0, p, 10, 0.0, p, 10, None) == C.CTQR_EINVAL
+
+
+def _solver_desc(**kw):
+    p = 4096
+    d = dict(m=3072, n=1024, dtype=C.CTQR_F64, nb=0, QR=p, lda=3072, T=p, tau=p, Rinv=p, A64=None, tol=1e-13,
+             max_iters=0, max_slices=64)
+    d.update(kw)
+    return C.ctqr_solver_desc(d["m"], d["n"], d["dtype"], d["nb"], d["QR"], d["lda"], d["T"], d["tau"], d["Rinv"],
+                              d["A64"], d["tol"], d["max_iters"], d["max_slices"])
+
+
+def test_solver_desc_layout_and_workspace():
+    assert ctypes.sizeof(C.ctqr_solver_desc) == 88
+    b64 = C.ctqr_solver_workspace(_solver_desc(max_slices=64))
+    assert b64 >= 3072 * 64 * 8                               # the padded request buffer at least
+    assert C.ctqr_solver_workspace(_solver_desc(max_slices=40)) == b64     # rounded up to the bucket
+    assert C.ctqr_solver_workspace(_solver_desc(max_slices=65)) > b64
+
+
+@pytest.mark.parametrize("kw", [dict(max_slices=0), dict(max_slices=4097), dict(Rinv=None), dict(QR=None),
+                                dict(lda=3000), dict(lda=3074), dict(m=100), dict(nb=48), dict(dtype=5),
+                                dict(Rinv=4100)])
+def test_solver_rejects(kw):
+    L = C.lib()
+    d = _solver_desc(**kw)
+    assert L.ctqr_solver_workspace(ctypes.byref(d), ctypes.byref(_sz())) == C.CTQR_EINVAL
+    h = ctypes.c_void_p(1)
+    assert L.ctqr_solver_create(ctypes.byref(d), ctypes.c_void_p(4096), 1 << 40, ctypes.byref(h)) == C.CTQR_EINVAL
+
+
+def test_solver_create_and_solve_reject_before_any_hip_call():
+    L = C.lib()
+    d = _solver_desc()
+    h = ctypes.c_void_p(1)
+    assert L.ctqr_solver_create(ctypes.byref(d), ctypes.c_void_p(4096), 64, ctypes.byref(h)) == C.CTQR_ENOMEM
+    assert L.ctqr_solver_create(ctypes.byref(d), None, 1 << 40, ctypes.byref(h)) == C.CTQR_EINVAL
+    bad = C.ctqr_sparse(3071, 1024, 10, 4096, 4096, 4096, 4096, 4096, 4096)
+    d2 = _solver_desc(A64=ctypes.pointer(bad), max_iters=5)
+    assert L.ctqr_solver_workspace(ctypes.byref(d2), ctypes.byref(_sz())) == C.CTQR_EINVAL
+    p = ctypes.c_void_p(4096)
+    assert L.ctqr_solver_solve(None, p, 3072, 1, p, 1024, p, None) == C.CTQR_EINVAL
+    assert L.ctqr_solver_tune(None, 1, None) == C.CTQR_EINVAL
+    assert L.ctqr_solver_destroy(None) == C.CTQR_OK
+
+
+def test_solver_batch_rejects():
+    L = C.lib()
+    p = ctypes.c_void_p(4096)
+    one = (ctypes.c_void_p * 1)(4096)
+    ld = (ctypes.c_int64 * 1)(3072)
+    ns = (ctypes.c_int32 * 1)(1)
+    assert L.ctqr_solver_solve_batch(None, 1, one, ld, ns, one, ld, p, None) == C.CTQR_EINVAL
