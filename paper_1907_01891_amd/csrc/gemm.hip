@@ -397,20 +397,35 @@ void gemm_tn_kernel(int M, int N, int K,
 }
 
 // Deterministic split-K reduction: Out = alpha * sum_z part[z] + beta * Out.
-template <typename T>
-__global__ void splitk_reduce_kernel(int M, int N, int splits, const T *__restrict__ part,
-                                     T alpha, T beta, T *__restrict__ Out, int64_t ldo,
-                                     const int *skip)
+// A workgroup of SG waves owns 64 consecutive outputs: wave w sums the
+// partials of splits w, w + SG, w + 2 SG, ... in order, then the SG wave sums
+// are added in wave order.
+template <typename T, int SG>
+__global__ __launch_bounds__(64 * SG)
+void splitk_reduce_kernel(int M, int N, int splits, const T *__restrict__ part,
+                          T alpha, T beta, T *__restrict__ Out, int64_t ldo,
+                          const int *skip)
 {
     if (skip && *skip) return;
-    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t total = (int64_t)M * N;
-    if (idx >= total) return;
-    int n = (int)(idx / M), m = (int)(idx % M);
-    T s = T(0);
-    for (int z = 0; z < splits; ++z) s += part[(int64_t)z * total + idx];
-    T *o = Out + (int64_t)n * ldo + m;
-    *o = beta == T(0) ? alpha * s : alpha * s + beta * *o;
+    __shared__ T red[SG][64];
+    const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+    const int64_t idx = (int64_t)blockIdx.x * 64 + lane;
+    const int64_t total = (int64_t)M * N;
+    T acc = T(0);
+    if (idx < total) {
+#pragma unroll 4
+        for (int z = w; z < splits; z += SG) acc += part[(int64_t)z * total + idx];
+    }
+    red[w][lane] = acc;
+    __syncthreads();
+    if (w == 0 && idx < total) {
+        T v = red[0][lane];
+#pragma unroll
+        for (int k = 1; k < SG; ++k) v += red[k][lane];
+        const int n = (int)(idx / M), m = (int)(idx % M);
+        T *o = Out + (int64_t)n * ldo + m;
+        *o = beta == T(0) ? alpha * v : alpha * v + beta * *o;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -423,9 +438,12 @@ __global__ __launch_bounds__(NTHR, 2)
 void gemm_nn_kernel(int M, int N, int K,
                     const T *__restrict__ A, int64_t lda, int amask,
                     const T *__restrict__ B, int64_t ldb,
-                    T alpha, T *__restrict__ C, int64_t ldc, int accum, const int *skip)
+                    T alpha, T *__restrict__ C, int64_t ldc, int accum,
+                    T *__restrict__ part, int kchunk, const int *skip)
 {
-    // accum != 0: C += alpha A B;  accum == 0: C = alpha A B (C is not read)
+    // accum != 0: C += alpha A B;  accum == 0: C = alpha A B (C is not read).
+    // With gridDim.z > 1 split z covers k in [z kchunk, (z+1) kchunk) and
+    // writes its raw product to part (reduced by splitk_reduce_kernel).
     using Mt = Mf<T>;
     using W = WaveTile<T, TW>;
     if (skip && *skip) return;
@@ -445,6 +463,11 @@ void gemm_nn_kernel(int M, int N, int K,
         for (int j = 0; j < W::NJ; ++j)
 #pragma unroll
             for (int e = 0; e < acc_len<T>(); ++e) acc[i][j][e] = T(0);
+
+    const bool split = gridDim.z > 1;
+    const int kbeg = blockIdx.z * kchunk;
+    const int kend = min(K, kbeg + kchunk);
+    if (split) accum = 0;
 
     // FP32: fetch the C tile now; its HBM latency hides behind the K loop
     constexpr bool PRE = sizeof(T) == 4;
@@ -466,17 +489,17 @@ void gemm_nn_kernel(int M, int N, int K,
 
     MkTile<T> la;
     KcTile<T, TW> lb;
-    la.load(A, lda, M, m0, 0, K, amask != 0);
-    lb.load(B, ldb, N, n0, 0, K, 0);
+    la.load(A, lda, M, m0, kbeg, kend, amask != 0);
+    lb.load(B, ldb, N, n0, kbeg, kend, 0);
     la.store(sA[0]);
     lb.store(sB[0]);
     __syncthreads();
     int cur = 0;
-    for (int k = 0; k < K; k += Mt::BK) {
-        const bool more = k + Mt::BK < K;
+    for (int k = kbeg; k < kend; k += Mt::BK) {
+        const bool more = k + Mt::BK < kend;
         if (more) {
-            la.load(A, lda, M, m0, k + Mt::BK, K, amask != 0);
-            lb.load(B, ldb, N, n0, k + Mt::BK, K, 0);
+            la.load(A, lda, M, m0, k + Mt::BK, kend, amask != 0);
+            lb.load(B, ldb, N, n0, k + Mt::BK, kend, 0);
         }
         mfma_step<T, false, W::NI, W::NJ>(sB[cur], sA[cur], wn, wm, acc);
         if (more) {
@@ -498,6 +521,10 @@ void gemm_nn_kernel(int M, int N, int K,
                 n += n0 + wn;
                 m += m0 + wm;
                 if (m < M && n < N) {
+                    if (split) {
+                        part[((int64_t)blockIdx.z * N + n) * M + m] = acc[ib][jb][r];
+                        continue;
+                    }
                     T *c = C + (int64_t)n * ldc + m;
                     if constexpr (PRE)
                         *c = cpre[ib][jb][r] + alpha * acc[ib][jb][r];
@@ -560,6 +587,24 @@ int gemm_tn_splits(int M, int N, int K)
     return (int)splits;
 }
 
+// Out = alpha * sum of the split partials + beta * Out.  Many splits (a tall,
+// narrow product): 16 waves share each output group.  The choice depends on
+// the split count only, so products that differ only in their number of
+// columns within one column tile sum every output in the same order.
+template <typename T>
+ctqr_status splitk_reduce(int M, int N, int splits, const T *part, T alpha, T beta, T *Out, int64_t ldo,
+                          const int *skip, hipStream_t st)
+{
+    const int64_t groups = ceil_div((int64_t)M * N, 64);
+    if (splits >= 64)
+        LAUNCH_TRY((splitk_reduce_kernel<T, 16>), dim3((unsigned)groups), dim3(64 * 16), 0, st, M, N, splits,
+                   part, alpha, beta, Out, ldo, skip);
+    else
+        LAUNCH_TRY((splitk_reduce_kernel<T, 4>), dim3((unsigned)groups), dim3(64 * 4), 0, st, M, N, splits,
+                   part, alpha, beta, Out, ldo, skip);
+    return CTQR_OK;
+}
+
 template <typename T>
 ctqr_status gemm_tn(int M, int N, int K, const T *A, int64_t lda, int amask, const T *B,
                     int64_t ldb, int bmask, T alpha, T beta, T *Out, int64_t ldo, T *part,
@@ -579,11 +624,7 @@ ctqr_status gemm_tn(int M, int N, int K, const T *A, int64_t lda, int amask, con
     else
         LAUNCH_TRY((gemm_tn_kernel<T, TILE>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B, ldb,
                    bmask, alpha, beta, Out, ldo, part, kchunk, skip);
-    if (splits > 1) {
-        int64_t total = (int64_t)M * N;
-        LAUNCH_TRY(splitk_reduce_kernel<T>, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, st,
-                   M, N, splits, part, alpha, beta, Out, ldo, skip);
-    }
+    if (splits > 1) return splitk_reduce<T>(M, N, splits, part, alpha, beta, Out, ldo, skip, st);
     return CTQR_OK;
 }
 
@@ -598,17 +639,39 @@ ctqr_status gemm_nn(int M, int N, int K, const T *A, int64_t lda, int amask, con
         K = 0;   // C = 0: the kernel runs with an empty k loop
     }
     const bool narrow = N <= t_narrow_max;
+    const int kchunk = K > 0 ? K : 1;
     dim3 grid((unsigned)(ceil_div(M, TILE) * ceil_div(N, narrow ? NARROW : TILE)));
     if (kind == 1)
         LAUNCH_TRY((gemm_nn_kernel<T, 1, TILE>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B, ldb,
-                   alpha, C, ldc, accum, skip);
+                   alpha, C, ldc, accum, (T *)nullptr, kchunk, skip);
     else if (narrow)
         LAUNCH_TRY((gemm_nn_kernel<T, 0, NARROW>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B, ldb,
-                   alpha, C, ldc, accum, skip);
+                   alpha, C, ldc, accum, (T *)nullptr, kchunk, skip);
     else
         LAUNCH_TRY((gemm_nn_kernel<T, 0, TILE>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B, ldb,
-                   alpha, C, ldc, accum, skip);
+                   alpha, C, ldc, accum, (T *)nullptr, kchunk, skip);
     return CTQR_OK;
+}
+
+template <typename T>
+ctqr_status gemm_nn_split(int M, int N, int K, const T *A, int64_t lda, const T *B, int64_t ldb, T alpha,
+                          T *C, int64_t ldc, T *part, size_t part_elems, const int *skip, hipStream_t st)
+{
+    if (M <= 0 || N <= 0 || K <= 0) return CTQR_OK;
+    const bool narrow = N <= t_narrow_max;
+    int splits = gemm_tn_splits(M, N, K);
+    if (splits > 1 && (part == nullptr || part_elems < (size_t)splits * M * N)) splits = 1;
+    if (splits <= 1) return gemm_nn<T>(M, N, K, A, lda, 0, B, ldb, alpha, C, ldc, skip, st, 0, 1);
+    int kchunk = (int)ceil_div(ceil_div(K, splits), Mf<T>::BK) * Mf<T>::BK;
+    splits = (int)ceil_div(K, kchunk);
+    dim3 grid((unsigned)(ceil_div(M, TILE) * ceil_div(N, narrow ? NARROW : TILE)), 1, (unsigned)splits);
+    if (narrow)
+        LAUNCH_TRY((gemm_nn_kernel<T, 0, NARROW>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, 0, B, ldb, alpha,
+                   C, ldc, 0, part, kchunk, skip);
+    else
+        LAUNCH_TRY((gemm_nn_kernel<T, 0, TILE>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, 0, B, ldb, alpha,
+                   C, ldc, 0, part, kchunk, skip);
+    return splitk_reduce<T>(M, N, splits, part, alpha, T(1), C, ldc, skip, st);
 }
 
 template ctqr_status gemm_tn<float>(int, int, int, const float *, int64_t, int, const float *,
@@ -621,3 +684,7 @@ template ctqr_status gemm_nn<float>(int, int, int, const float *, int64_t, int, 
                                     int64_t, float, float *, int64_t, const int *, hipStream_t, int, int);
 template ctqr_status gemm_nn<double>(int, int, int, const double *, int64_t, int, const double *,
                                      int64_t, double, double *, int64_t, const int *, hipStream_t, int, int);
+template ctqr_status gemm_nn_split<float>(int, int, int, const float *, int64_t, const float *, int64_t, float,
+                                          float *, int64_t, float *, size_t, const int *, hipStream_t);
+template ctqr_status gemm_nn_split<double>(int, int, int, const double *, int64_t, const double *, int64_t,
+                                           double, double *, int64_t, double *, size_t, const int *, hipStream_t);

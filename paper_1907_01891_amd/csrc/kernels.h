@@ -17,6 +17,11 @@ template <typename T>
 ctqr_status gemm_nn(int M, int N, int K, const T *A, int64_t lda, int amask, const T *B,
                     int64_t ldb, T alpha, T *C, int64_t ldc, const int *skip, hipStream_t st,
                     int kind = 0, int accum = 1);
+// C += alpha A B (A not a Householder block), split over K into part when the
+// output has too few tiles to fill the chip.
+template <typename T>
+ctqr_status gemm_nn_split(int M, int N, int K, const T *A, int64_t lda, const T *B, int64_t ldb, T alpha,
+                          T *C, int64_t ldc, T *part, size_t part_elems, const int *skip, hipStream_t st);
 
 // ---- panel_qr.hip ----------------------------------------------------------
 constexpr int PANEL_XCH_STRIDE = 40;   // doubles per workgroup per exchange buffer (two buffers)

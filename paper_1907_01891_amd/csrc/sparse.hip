@@ -12,7 +12,8 @@
 namespace {
 
 // y[i, s] = alpha * sum_k val[k] x[idx[k], s] + beta * y_in[i, s]
-// Workgroup of 256 threads: SW = min(256, S rounded up to 64) threads per row.
+// Wide form (S > 64): SW = min(256, S rounded up to 64) threads per row, one
+// slice per thread.
 __global__ __launch_bounds__(256)
 void spmm_rm_kernel(int64_t rows, int S, int SW, const int64_t *__restrict__ ptr,
                     const int32_t *__restrict__ idx, const double *__restrict__ val, double alpha,
@@ -34,7 +35,43 @@ void spmm_rm_kernel(int64_t rows, int S, int SW, const int64_t *__restrict__ ptr
         const int s = s0 + lane;
         if (s >= S) break;
         double acc = 0.0;
+#pragma unroll 4
         for (int64_t k = b; k < e; ++k) acc += val[k] * x[(int64_t)idx[k] * S + s];
+        double out = alpha * acc;
+        if (beta != 0.0) out += beta * y_in[i * S + s];
+        y[i * S + s] = out;
+    }
+}
+
+// Narrow form (S <= 64): one wave per row, its lanes split into 64 / SP
+// groups of SP slices (SP = S rounded up to a power of two).  Group g sums the
+// row's nonzeros g, g + G, g + 2G, ... in order; the groups' sums are then
+// combined by a fixed butterfly, so the result does not depend on timing.
+template <int SP>
+__global__ __launch_bounds__(256)
+void spmm_rm_narrow_kernel(int64_t rows, int S, const int64_t *__restrict__ ptr,
+                           const int32_t *__restrict__ idx, const double *__restrict__ val, double alpha,
+                           const double *__restrict__ x, double beta, const double *__restrict__ y_in,
+                           double *__restrict__ y, const int *skip)
+{
+    if (skip && *skip) return;
+    constexpr int G = CTQR_WAVE / SP;
+    unsigned blk = blockIdx.x;
+    const unsigned per = gridDim.x / 8;
+    if (blk < per * 8) blk = (blk % 8) * per + blk / 8;
+    const int64_t i = (int64_t)blk * 4 + threadIdx.x / CTQR_WAVE;
+    const int lane = threadIdx.x % CTQR_WAVE;
+    const int g = lane / SP, s = lane % SP;
+    if (i >= rows) return;   // whole waves leave together
+    const int64_t b = ptr[i], e = ptr[i + 1];
+    double acc = 0.0;
+    if (s < S) {
+#pragma unroll 4
+        for (int64_t k = b + g; k < e; k += G) acc += val[k] * x[(int64_t)idx[k] * S + s];
+    }
+#pragma unroll
+    for (int off = SP; off < CTQR_WAVE; off <<= 1) acc += __shfl_xor(acc, off);
+    if (g == 0 && s < S) {
         double out = alpha * acc;
         if (beta != 0.0) out += beta * y_in[i * S + s];
         y[i * S + s] = out;
@@ -150,28 +187,39 @@ __global__ void refine_update_kernel(int64_t n, int S, double *__restrict__ x, c
 {
     if (skip && *skip) return;
     __shared__ double t[32][33];
-    const int64_t r0 = (int64_t)blockIdx.x * 32;
+    __shared__ unsigned long long md[8][32], mx[8][32];
     const int s0 = blockIdx.y * 32;
-    for (int k = threadIdx.y; k < 32; k += 8) {
-        int64_t r = r0 + threadIdx.x;
-        int s = s0 + k;
-        t[k][threadIdx.x] = (r < n && s < S) ? (double)d[(int64_t)s * ldd + r] : 0.0;
-    }
-    __syncthreads();
-    unsigned long long dm = 0, xm = 0;
     const int s = s0 + threadIdx.x;
-    for (int k = threadIdx.y; k < 32; k += 8) {
-        int64_t r = r0 + k;
-        if (r < n && s < S) {
-            double dv = t[threadIdx.x][k];
-            double xv = x[r * S + s] + dv;
-            x[r * S + s] = xv;
-            unsigned long long a = order_bits(dv), b = order_bits(xv);
-            dm = a > dm ? a : dm;
-            xm = b > xm ? b : xm;
+    unsigned long long dm = 0, xm = 0;
+    // 32-row tiles, strided over the grid: few blocks, so few atomics
+    for (int64_t r0 = (int64_t)blockIdx.x * 32; r0 < n; r0 += (int64_t)gridDim.x * 32) {
+        __syncthreads();
+        for (int k = threadIdx.y; k < 32; k += 8) {
+            int64_t r = r0 + threadIdx.x;
+            int sk = s0 + k;
+            t[k][threadIdx.x] = (r < n && sk < S) ? (double)d[(int64_t)sk * ldd + r] : 0.0;
+        }
+        __syncthreads();
+        for (int k = threadIdx.y; k < 32; k += 8) {
+            int64_t r = r0 + k;
+            if (r < n && s < S) {
+                double dv = t[threadIdx.x][k];
+                double xv = x[r * S + s] + dv;
+                x[r * S + s] = xv;
+                unsigned long long a = order_bits(dv), b = order_bits(xv);
+                dm = a > dm ? a : dm;
+                xm = b > xm ? b : xm;
+            }
         }
     }
-    if (s < S) {
+    md[threadIdx.y][threadIdx.x] = dm;
+    mx[threadIdx.y][threadIdx.x] = xm;
+    __syncthreads();
+    if (threadIdx.y == 0 && s < S) {
+        for (int k = 1; k < 8; ++k) {
+            dm = md[k][threadIdx.x] > dm ? md[k][threadIdx.x] : dm;
+            xm = mx[k][threadIdx.x] > xm ? mx[k][threadIdx.x] : xm;
+        }
         atomicMax(&dmax[s], dm);
         atomicMax(&xmax[s], xm);
     }
@@ -242,6 +290,21 @@ ctqr_status spmm_rowmajor(int64_t rows, int S, const int64_t *ptr, const int32_t
                           const double *y_in, double *y, const int *skip, hipStream_t st)
 {
     if (rows <= 0 || S <= 0) return CTQR_OK;
+    if (S <= CTQR_WAVE) {
+        dim3 grid((unsigned)ceil_div(rows, 4));
+#define CTQR_SPMM_NARROW(SPV)                                                                       \
+    LAUNCH_TRY(spmm_rm_narrow_kernel<SPV>, grid, dim3(256), 0, st, rows, S, ptr, idx, val, alpha, x, \
+               beta, y_in, y, skip)
+        if (S == 1) CTQR_SPMM_NARROW(1);
+        else if (S == 2) CTQR_SPMM_NARROW(2);
+        else if (S <= 4) CTQR_SPMM_NARROW(4);
+        else if (S <= 8) CTQR_SPMM_NARROW(8);
+        else if (S <= 16) CTQR_SPMM_NARROW(16);
+        else if (S <= 32) CTQR_SPMM_NARROW(32);
+        else CTQR_SPMM_NARROW(64);
+#undef CTQR_SPMM_NARROW
+        return CTQR_OK;
+    }
     int SW = (int)std::min<int64_t>(256, ceil_div(S, 64) * 64);
     int rpb = 256 / SW;
     LAUNCH_TRY(spmm_rm_kernel, dim3((unsigned)ceil_div(rows, rpb)), dim3(256), 0, st, rows, S, SW, ptr,
@@ -327,7 +390,7 @@ ctqr_status refine_update(int64_t n, int S, double *x, const TD *d, int64_t ldd,
                           unsigned long long *dmax, unsigned long long *xmax, const int *skip,
                           hipStream_t st)
 {
-    LAUNCH_TRY(refine_update_kernel<TD>, dim3((unsigned)ceil_div(n, 32), (unsigned)ceil_div(S, 32)),
+    LAUNCH_TRY(refine_update_kernel<TD>, dim3((unsigned)std::min<int64_t>(ceil_div(n, 32), 512), (unsigned)ceil_div(S, 32)),
                dim3(32, 8), 0, st, n, S, x, d, ldd, dmax, xmax, skip);
     return CTQR_OK;
 }

@@ -239,19 +239,36 @@ ctqr_status rdiag_check(int n, const T *R, int64_t ldr, double *scratch, ctqr_in
     return CTQR_OK;
 }
 
+// Block back substitution R X = C with the stored diagonal-block inverses
+// (Section II-C, "System solving"), C overwritten.  Two orders with the same
+// arithmetic per block:
+//  - right-looking: after X_i, the rows above take its update at once,
+//    C_{0:r0} -= R_{0:r0, i} X_i (products of r0 rows: few tiles early on);
+//  - left-looking: before X_i, block row i takes the updates of every solved
+//    block at once, C_i -= R_{i, i+1:} X_{i+1:} (a 2048-row product with a
+//    long inner dimension, split over it, so every step fills the chip).
+// Narrow right-hand sides (the 32-wide slice tile) use the left-looking order.
 template <typename T>
 ctqr_status trsm_upper(int n, int S, const T *R, int64_t ldr, const T *Rinv, T *C, int64_t ldc,
                        T *X, int64_t ldx, T *part, size_t part_elems, const int *skip, hipStream_t st)
 {
     const T *RinvT = Rinv + trinv_elems(n);
     const int nblk = (int)ceil_div(n, BIG);
+    const bool left = S <= gemm_narrow_max();
     for (int i = nblk - 1; i >= 0; --i) {
         const int r0 = i * BIG, bw = min(BIG, n - r0);
+        ctqr_status s;
+        if (left && r0 + bw < n) {
+            // C_i -= R_{i, i+1:} X_{i+1:}
+            s = gemm_nn_split<T>(bw, S, n - r0 - bw, R + (int64_t)(r0 + bw) * ldr + r0, ldr, X + r0 + bw, ldx,
+                                 T(-1), C + r0, ldc, part, part_elems, skip, st);
+            if (s) return s;
+        }
         // X_i = inv(R_ii) C_i = (inv(R_ii)^T)^T C_i  (split-K TN product)
-        ctqr_status s = gemm_tn<T>(bw, S, bw, RinvT + (int64_t)r0 * BIG, BIG, 0, C + r0, ldc, 0, T(1), T(0),
-                                   X + r0, ldx, part, part_elems, skip, st);
+        s = gemm_tn<T>(bw, S, bw, RinvT + (int64_t)r0 * BIG, BIG, 0, C + r0, ldc, 0, T(1), T(0), X + r0, ldx,
+                       part, part_elems, skip, st);
         if (s) return s;
-        if (r0 > 0) {
+        if (!left && r0 > 0) {
             // C_{0:r0} -= R_{0:r0, i} X_i
             s = gemm_nn<T>(r0, S, bw, R + (int64_t)r0 * ldr, ldr, 0, X + r0, ldx, T(-1), C, ldc, skip, st);
             if (s) return s;
@@ -260,20 +277,31 @@ ctqr_status trsm_upper(int n, int S, const T *R, int64_t ldr, const T *Rinv, T *
     return CTQR_OK;
 }
 
+// Block forward substitution R^T Y = C, C overwritten; right-looking
+// (C_{i+1:} -= R_{i, i+1:}^T Y_i after Y_i) or, for narrow right-hand
+// sides, left-looking (C_i -= R_{0:r0, i}^T Y_{0:r0} before Y_i).
 template <typename T>
 ctqr_status trsm_upper_trans(int n, int S, const T *R, int64_t ldr, const T *Rinv, T *C, int64_t ldc,
                              T *Y, int64_t ldy, T *part, size_t part_elems, const int *skip,
                              hipStream_t st)
 {
     const int nblk = (int)ceil_div(n, BIG);
+    const bool left = S <= gemm_narrow_max();
     for (int i = 0; i < nblk; ++i) {
         const int r0 = i * BIG, bw = min(BIG, n - r0);
+        ctqr_status s;
+        if (left && r0 > 0) {
+            // C_i -= (R_{0:r0, i})^T Y_{0:r0}
+            s = gemm_tn<T>(bw, S, r0, R + (int64_t)r0 * ldr, ldr, 0, Y, ldy, 0, T(-1), T(1), C + r0, ldc, part,
+                           part_elems, skip, st);
+            if (s) return s;
+        }
         // Y_i = inv(R_ii)^T C_i
-        ctqr_status s = gemm_tn<T>(bw, S, bw, Rinv + (int64_t)r0 * BIG, BIG, 0, C + r0, ldc, 0,
-                                   T(1), T(0), Y + r0, ldy, part, part_elems, skip, st);
+        s = gemm_tn<T>(bw, S, bw, Rinv + (int64_t)r0 * BIG, BIG, 0, C + r0, ldc, 0, T(1), T(0), Y + r0, ldy,
+                       part, part_elems, skip, st);
         if (s) return s;
         const int rest = n - r0 - bw;
-        if (rest > 0) {
+        if (!left && rest > 0) {
             // C_{i+1:} -= (R_{i, i+1:})^T Y_i
             s = gemm_tn<T>(rest, S, bw, R + (int64_t)(r0 + bw) * ldr + r0, ldr, 0, Y + r0, ldy, 0,
                            T(-1), T(1), C + r0 + bw, ldc, part, part_elems, skip, st);

@@ -185,3 +185,31 @@ def test_solver_batch_of_requests(gpu):
         else:
             assert all((x == y).all() for x, y in zip(Xs, first))
     sv.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_two_block_substitution_orders(gpu, dtype):
+    # n = 2304: two diagonal blocks of the block substitution (2048 + a ragged
+    # 256).  Few slices take the left-looking order, 40 slices the
+    # right-looking one; both must reach the oracle's solution.
+    name = "ct48"
+    g, A, X, B = oracle_problem(name, n_slices=40)
+    QRo, tauo = oracle_factor(name)
+    Xo = hh.backsub(QRo, hh.apply_qt(QRo, tauo, B))
+    if dtype == "f64":
+        F = _factor(A, torch.float64, C.CTQR_PREC_FP64, nb=256)
+        kw = {}
+    else:
+        F = _factor(A, torch.float32, C.CTQR_PREC_FP32_MFMA, nb=256)
+        spA = DeviceSparse(A)
+        kw = dict(sparse=spA.sp, tol=1e-14, max_iters=30)
+    for S in (4, 40):
+        _print_case("two-block trsm", dtype, "S", S)
+        Bd = to_colmajor(torch.as_tensor(B[:, :S]), dtype=torch.float64)
+        Xg = download(F.solve(Bd, **kw))
+        torch.cuda.synchronize()
+        si = F.sinfo.read()
+        assert si.status == 0, (C.status_string(si.status), si.iters)
+        err = lsq.rel_err(Xg, Xo[:, :S]).max()
+        print("%s S %d err %.3e iters %d" % (dtype, S, err, si.iters))
+        assert err <= 1e-10
