@@ -177,6 +177,36 @@ ctqr_status ctqr_qr_factor(int64_t m, int64_t n, ctqr_dtype dtype, void *A, int6
                            void *work, size_t work_bytes, ctqr_info *info,
                            hipStream_t stream);
 
+/* ---- Out-of-core factorization --------------------------------------------
+ * For an A larger than device memory (the paper's out-of-core setting,
+ * Section II-B, with HBM in the role of main memory and pinned host memory in
+ * the role of the disk).  Columns [0, n_dev) of A are in device memory
+ * (A_dev, leading dim lda); columns [n_dev, n) are in pinned host memory
+ * (A_host, allocated with hipHostMalloc; column j at A_host + (j - n_dev) *
+ * lda, same lda).  The resident columns are factored first, with their
+ * trailing updates kept inside them; each host tile of tile_cols columns is
+ * then uploaded, takes the block-reflector updates of every factored block
+ * column to its left (left-looking: resident blocks from HBM, earlier host
+ * tiles uploaded again one at a time), is factored, and written back.  The
+ * factor, T, tau and Rinv are bit-identical to ctqr_qr_factor's on the same
+ * matrix (every reduction keeps the split of the all-in-HBM run).
+ *   n_dev, tile_cols  multiples of 2048 and of nb; 0 <= n_dev <= n.
+ *   A_dev   device, m x n_dev (may be NULL when n_dev = 0).
+ *   A_host  pinned host, m x (n - n_dev) (may be NULL when n_dev = n); on
+ *           exit it holds its columns of the factor.  CTQR_EINVAL if it is
+ *           not pinned host memory.
+ *   T, tau, Rinv, info  as ctqr_qr_factor (T, tau and Rinv in device memory).
+ *   work    device, ctqr_qr_factor_ooc_workspace bytes (two tile buffers
+ *           of lda * tile_cols elements plus the factorization workspace).
+ * Copies and kernels are enqueued on `stream` in order; the call returns
+ * once everything is enqueued. */
+ctqr_status ctqr_qr_factor_ooc_workspace(int64_t m, int64_t n, ctqr_dtype dtype, ctqr_prec prec,
+                                         int32_t nb, int64_t lda, int64_t tile_cols, size_t *bytes);
+ctqr_status ctqr_qr_factor_ooc(int64_t m, int64_t n, ctqr_dtype dtype, void *A_dev, void *A_host,
+                               int64_t lda, int64_t n_dev, int64_t tile_cols, ctqr_prec prec,
+                               int32_t nb, void *T, double *tau, void *Rinv, void *work,
+                               size_t work_bytes, ctqr_info *info, hipStream_t stream);
+
 /* Bytes of the Rinv array of ctqr_qr_factor / ctqr_qr_solve_slices (host only). */
 ctqr_status ctqr_qr_rinv_bytes(int64_t n, ctqr_dtype dtype, size_t *bytes);
 

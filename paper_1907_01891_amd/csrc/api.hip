@@ -148,28 +148,66 @@ ctqr_status ensure_setup()
     return st;
 }
 
+// Profiled launch of the trailing update C -= V W' (the dominant kernel).
 template <typename T>
-ctqr_status factor_impl(int64_t m64, int64_t n64, T *A, int64_t lda, int nb, T *Tout, double *tau, T *Rinv,
-                        void *work, ctqr_info *info, hipStream_t st)
+ctqr_status trailing_update(int mk, int nc, int nbk, const T *V, int64_t lda, const T *W2, int nb, T *C,
+                            hipStream_t st)
 {
-    const int m = (int)m64, n = (int)n64;
-    FactorWS<T> w = carve_factor<T>(work, m64, n64, nb);
-    const int ncu = std::min(device_cus(), MAX_PANEL_WG);
-    if (panel_rows_per_wg(m, ncu) > panel_max_rows_per_wg()) return CTQR_EUNSUPPORTED;
+    bool prof;
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        prof = g_prof_on;
+    }
+    ProfRec rec{};
+    if (prof) {
+        HIP_TRY(hipEventCreate(&rec.a));
+        HIP_TRY(hipEventCreate(&rec.b));
+        HIP_TRY(hipEventRecord(rec.a, st));
+    }
+    ctqr_status s = gemm_nn<T>(mk, nc, nbk, V, lda, 1, W2, nb, T(-1), C, lda, nullptr, st, 1);
+    if (s) return s;
+    if (prof) {
+        HIP_TRY(hipEventRecord(rec.b, st));
+        rec.flops = 2.0 * (double)mk * (double)nc * (double)nbk;
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        g_prof.push_back(rec);
+    }
+    return CTQR_OK;
+}
+
+// Split counts of the two reductions of block k0 in the all-in-HBM
+// factorization of an m x n matrix ([G | W] = V^T [V | C] and W' = T^T W).
+// Every other caller that touches block k0's columns forces the same counts,
+// so a column gets bit-identical updates whatever range it is processed in.
+struct BlockSplits {
+    int gw, tw;
+};
+BlockSplits block_splits(int m, int n, int nb, int k0)
+{
+    const int nbk = std::min(nb, n - k0), nc = n - (k0 + nbk);
+    return {gemm_tn_splits(nbk, nbk + nc, m - k0), nc > 0 ? gemm_tn_splits(nbk, nc, nbk) : 1};
+}
+
+// Right-looking blocked Householder QR of the block columns [kb, ke) of an
+// m x n matrix whose columns [kb, ce) are addressable through A (column k at
+// A + k lda; ke <= ce), with every trailing update restricted to columns
+// < ce.  kb, ke: multiples of nb (ke may be n).  With kb = 0, ke = ce = n it
+// is the whole factorization.
+template <typename T>
+ctqr_status factor_blocks(int m, int n, T *A, int64_t lda, int nb, int kb, int ke, int ce, T *Tout, double *tau,
+                          FactorWS<T> &w, unsigned *bars, ctqr_info *info, int ncu, hipStream_t st)
+{
     ctqr_status s;
-    if ((s = info_reset(info, st))) return s;
-    if ((s = fill_u32(w.bars, (ceil_div(n, PANEL_W) + 1) * GB_WORDS, 0u, st))) return s;
-    int ipanel = 0;
-    for (int k0 = 0; k0 < n; k0 += nb) {
+    for (int k0 = kb; k0 < ke; k0 += nb) {
         const int nbk = std::min(nb, n - k0);
+        const BlockSplits sp = block_splits(m, n, nb, k0);
         // inner panels of the block column, each followed by its update of
         // the rest of the block column
         for (int c0 = k0; c0 < k0 + nbk; c0 += PANEL_W) {
             const int wdt = std::min(PANEL_W, k0 + nbk - c0);
             s = panel_qr<T>(A, lda, m, c0, wdt, tau + c0, w.part, w.part2, w.gram_part, w.gram,
-                            w.bars + (int64_t)ipanel * GB_WORDS, info, ncu, st);
+                            bars + (int64_t)(c0 / PANEL_W) * GB_WORDS, info, ncu, st);
             if (s) return s;
-            ++ipanel;
             const int ncr = k0 + nbk - (c0 + wdt);
             if (ncr <= 0) continue;
             if ((s = tbuild<double, T>(wdt, w.gram, PANEL_W, tau + c0, w.Tin, PANEL_W, w.Tw, st))) return s;
@@ -185,41 +223,147 @@ ctqr_status factor_impl(int64_t m64, int64_t n64, T *A, int64_t lda, int nb, T *
             if (s) return s;
         }
         // block reflector of the whole block column: [G | W] = V^T [V | C]
-        const int nc = n - (k0 + nbk);
+        const int nc = std::max(0, ce - (k0 + nbk));
         const T *V = A + (int64_t)k0 * lda + k0;
         s = gemm_tn<T>(nbk, nbk + nc, m - k0, V, lda, nbk, V, lda, nbk, T(1), T(0), w.GW, nb, w.split,
-                       SPLIT_PART_ELEMS, nullptr, st);
+                       SPLIT_PART_ELEMS, nullptr, st, sp.gw);
         if (s) return s;
         T *Tk = Tout + (int64_t)k0 * nb;
         if ((s = tbuild<T, T>(nbk, w.GW, nb, tau + k0, Tk, nb, w.Tw, st))) return s;
         if (nc <= 0) continue;
         // W' = T^T W;  C -= V W'
         s = gemm_tn<T>(nbk, nc, nbk, Tk, nb, 0, w.GW + (int64_t)nbk * nb, nb, 0, T(1), T(0), w.W2, nb,
-                       w.split, SPLIT_PART_ELEMS, nullptr, st);
+                       w.split, SPLIT_PART_ELEMS, nullptr, st, sp.tw);
         if (s) return s;
-        T *C = A + (int64_t)(k0 + nbk) * lda + k0;
-        bool prof;
-        {
-            std::lock_guard<std::mutex> lk(g_prof_mu);
-            prof = g_prof_on;
-        }
-        ProfRec rec{};
-        if (prof) {
-            HIP_TRY(hipEventCreate(&rec.a));
-            HIP_TRY(hipEventCreate(&rec.b));
-            HIP_TRY(hipEventRecord(rec.a, st));
-        }
-        s = gemm_nn<T>(m - k0, nc, nbk, V, lda, 1, w.W2, nb, T(-1), C, lda, nullptr, st, 1);
-        if (s) return s;
-        if (prof) {
-            HIP_TRY(hipEventRecord(rec.b, st));
-            rec.flops = 2.0 * (double)(m - k0) * (double)nc * (double)nbk;
-            std::lock_guard<std::mutex> lk(g_prof_mu);
-            g_prof.push_back(rec);
-        }
+        if ((s = trailing_update<T>(m - k0, nc, nbk, V, lda, w.W2, nb, A + (int64_t)(k0 + nbk) * lda + k0, st)))
+            return s;
     }
+    return CTQR_OK;
+}
+
+// Left-looking application of the factored block columns [kb, ke) (their
+// Householder blocks read through V: column k at V + k lda) to the columns
+// [c0, c1) addressed through C (column k at C + k lda): for each block in
+// order, W = V_k^T C, W' = T_k^T W, C -= V_k W', with the reductions split as
+// in the all-in-HBM factorization.
+template <typename T>
+ctqr_status apply_blocks(int m, int n, const T *V, int64_t lda, const T *Tf, int nb, int kb, int ke, T *C, int c0,
+                         int c1, FactorWS<T> &w, hipStream_t st)
+{
+    ctqr_status s;
+    const int nc = c1 - c0;
+    if (nc <= 0) return CTQR_OK;
+    for (int k0 = kb; k0 < ke; k0 += nb) {
+        const int nbk = std::min(nb, n - k0);
+        const BlockSplits sp = block_splits(m, n, nb, k0);
+        const T *Vk = V + (int64_t)k0 * lda + k0;
+        T *Ck = C + (int64_t)c0 * lda + k0;
+        // the in-HBM call forms [G | W] at once: its split count applies
+        s = gemm_tn<T>(nbk, nc, m - k0, Vk, lda, nbk, Ck, lda, 0, T(1), T(0), w.GW, nb, w.split,
+                       SPLIT_PART_ELEMS, nullptr, st, sp.gw);
+        if (s) return s;
+        s = gemm_tn<T>(nbk, nc, nbk, Tf + (int64_t)k0 * nb, nb, 0, w.GW, nb, 0, T(1), T(0), w.W2, nb, w.split,
+                       SPLIT_PART_ELEMS, nullptr, st, sp.tw);
+        if (s) return s;
+        if ((s = trailing_update<T>(m - k0, nc, nbk, Vk, lda, w.W2, nb, Ck, st))) return s;
+    }
+    return CTQR_OK;
+}
+
+template <typename T>
+ctqr_status factor_impl(int64_t m64, int64_t n64, T *A, int64_t lda, int nb, T *Tout, double *tau, T *Rinv,
+                        void *work, ctqr_info *info, hipStream_t st)
+{
+    const int m = (int)m64, n = (int)n64;
+    FactorWS<T> w = carve_factor<T>(work, m64, n64, nb);
+    const int ncu = std::min(device_cus(), MAX_PANEL_WG);
+    ctqr_status s;
+    if ((s = info_reset(info, st))) return s;
+    if ((s = fill_u32(w.bars, (ceil_div(n, PANEL_W) + 1) * GB_WORDS, 0u, st))) return s;
+    if ((s = factor_blocks<T>(m, n, A, lda, nb, 0, n, n, Tout, tau, w, w.bars, info, ncu, st))) return s;
     if ((s = rdiag_check<T>(n, A, lda, nullptr, info, st))) return s;
     return Rinv ? trinv_blocks<T>(n, A, lda, Rinv, w.rtmp, info, st) : CTQR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Out-of-core factorization (Section II-B): the leading n_dev columns stay in
+// HBM, the rest lives in pinned host memory and passes through HBM one tile of
+// columns at a time.  The resident columns are factored right-looking with
+// their trailing updates kept inside them; each host tile is then uploaded,
+// takes the updates of every factored block to its left (left-looking: the
+// resident blocks, then the earlier host tiles re-uploaded one by one), is
+// factored, and is written back.  Every reduction uses the split count of
+// the all-in-HBM factorization, so the factor is bit-identical to it.
+// ---------------------------------------------------------------------------
+template <typename T>
+T *shift_cols(T *base, int64_t c0, int64_t lda)
+{
+    // column k of the returned pointer is column k - c0 of base (only
+    // columns >= c0 are ever addressed through it)
+    return reinterpret_cast<T *>(reinterpret_cast<uintptr_t>(base) - (uintptr_t)(c0 * lda * (int64_t)sizeof(T)));
+}
+
+template <typename T>
+struct OocWS {
+    FactorWS<T> f;
+    T *D, *E, *diag;
+    size_t bytes;
+};
+
+template <typename T>
+OocWS<T> carve_ooc(void *work, int64_t m, int64_t n, int nb, int64_t lda, int64_t tile_cols)
+{
+    OocWS<T> o{};
+    o.f = carve_factor<T>(work, m, n, nb);
+    Carve c(work);
+    c.off = o.f.bytes;
+    o.D = c.take<T>(lda * tile_cols);
+    o.E = c.take<T>(lda * tile_cols);
+    o.diag = c.take<T>(n);
+    o.bytes = c.off + 256;
+    return o;
+}
+
+template <typename T>
+ctqr_status factor_ooc_impl(int64_t m64, int64_t n64, T *A_dev, T *A_host, int64_t lda, int64_t n_dev64,
+                            int64_t tile64, int nb, T *Tout, double *tau, T *Rinv, void *work, ctqr_info *info,
+                            hipStream_t st)
+{
+    const int m = (int)m64, n = (int)n64, n_dev = (int)n_dev64, tile = (int)tile64;
+    OocWS<T> o = carve_ooc<T>(work, m64, n64, nb, lda, tile64);
+    FactorWS<T> &w = o.f;
+    const int ncu = std::min(device_cus(), MAX_PANEL_WG);
+    const size_t col_bytes = (size_t)lda * sizeof(T);
+    ctqr_status s;
+    if ((s = info_reset(info, st))) return s;
+    if ((s = fill_u32(w.bars, (ceil_div(n, PANEL_W) + 1) * GB_WORDS, 0u, st))) return s;
+    if (n_dev > 0) {
+        if ((s = factor_blocks<T>(m, n, A_dev, lda, nb, 0, n_dev, n_dev, Tout, tau, w, w.bars, info, ncu, st)))
+            return s;
+        if ((s = diag_copy<T>(0, n_dev, A_dev, lda, o.diag, st))) return s;
+        if (Rinv && (s = trinv_blocks_range<T>(n, 0, n_dev, A_dev, lda, Rinv, w.rtmp, st))) return s;
+    }
+    for (int c0 = n_dev; c0 < n; c0 += tile) {
+        const int c1 = std::min(n, c0 + tile);
+        HIP_TRY(hipMemcpyAsync(o.D, A_host + (int64_t)(c0 - n_dev) * lda, (size_t)(c1 - c0) * col_bytes,
+                               hipMemcpyHostToDevice, st));
+        T *Dv = shift_cols(o.D, c0, lda);
+        if (n_dev > 0 && (s = apply_blocks<T>(m, n, A_dev, lda, Tout, nb, 0, n_dev, Dv, c0, c1, w, st))) return s;
+        for (int e0 = n_dev; e0 < c0; e0 += tile) {
+            const int e1 = std::min(n, e0 + tile);
+            HIP_TRY(hipMemcpyAsync(o.E, A_host + (int64_t)(e0 - n_dev) * lda, (size_t)(e1 - e0) * col_bytes,
+                                   hipMemcpyHostToDevice, st));
+            T *Ev = shift_cols(o.E, e0, lda);
+            if ((s = apply_blocks<T>(m, n, Ev, lda, Tout, nb, e0, e1, Dv, c0, c1, w, st))) return s;
+        }
+        if ((s = factor_blocks<T>(m, n, Dv, lda, nb, c0, c1, c1, Tout, tau, w, w.bars, info, ncu, st))) return s;
+        if ((s = diag_copy<T>(c0, c1, Dv, lda, o.diag, st))) return s;
+        if (Rinv && (s = trinv_blocks_range<T>(n, c0, c1, Dv, lda, Rinv, w.rtmp, st))) return s;
+        HIP_TRY(hipMemcpyAsync(A_host + (int64_t)(c0 - n_dev) * lda, o.D, (size_t)(c1 - c0) * col_bytes,
+                               hipMemcpyDeviceToHost, st));
+    }
+    // rank check over the diagonal collected above (stride 0: diag[k])
+    return rdiag_check<T>(n, o.diag, 0, nullptr, info, st);
 }
 
 // Sets the slice-tile choice of the GEMMs enqueued by this thread for the
@@ -637,6 +781,14 @@ bool prec_ok(ctqr_dtype dtype, ctqr_prec prec)
 }
 
 int resolve_nb(int nb) { return nb == 0 ? DEFAULT_NB : nb; }
+
+// The panel's row slabs of an m-row matrix fit in LDS (checked for a
+// 256-CU device before any HIP call).
+bool panel_fits(int m, ctqr_dtype dtype)
+{
+    const int rows = panel_rows_per_wg(m, 256);
+    return rows <= (dtype == CTQR_F32 ? panel_max_rows_per_wg_f32() : panel_max_rows_per_wg());
+}
 bool nb_ok(int nb) { return nb >= 32 && nb <= 256 && nb % 32 == 0; }
 
 }  // namespace
@@ -724,6 +876,61 @@ ctqr_status ctqr_qr_workspace(int64_t m, int64_t n, ctqr_dtype dtype, ctqr_prec 
     return CTQR_OK;
 }
 
+ctqr_status ctqr_qr_factor_ooc_workspace(int64_t m, int64_t n, ctqr_dtype dtype, ctqr_prec prec, int32_t nb,
+                                         int64_t lda, int64_t tile_cols, size_t *bytes)
+{
+    if (!bytes || m < n || n < 1 || m >= INT32_MAX || lda < m || tile_cols < 1) return CTQR_EINVAL;
+    if (!prec_ok(dtype, prec)) return (dtype == CTQR_F32 && prec == CTQR_PREC_BF16_MFMA) ? CTQR_EUNSUPPORTED : CTQR_EINVAL;
+    nb = resolve_nb(nb);
+    if (!nb_ok(nb)) return CTQR_EINVAL;
+    *bytes = dtype == CTQR_F64 ? carve_ooc<double>(nullptr, m, n, nb, lda, tile_cols).bytes
+                               : carve_ooc<float>(nullptr, m, n, nb, lda, tile_cols).bytes;
+    return CTQR_OK;
+}
+
+ctqr_status ctqr_qr_factor_ooc(int64_t m, int64_t n, ctqr_dtype dtype, void *A_dev, void *A_host, int64_t lda,
+                               int64_t n_dev, int64_t tile_cols, ctqr_prec prec, int32_t nb, void *T, double *tau,
+                               void *Rinv, void *work, size_t work_bytes, ctqr_info *info, hipStream_t stream)
+{
+    try {
+        if (m < n || n < 1 || m >= INT32_MAX || !T || !tau || !work || !info) return CTQR_EINVAL;
+        if (lda < m || lda % 4 != 0 || !aligned16(T) || !aligned16(work)) return CTQR_EINVAL;
+        if (Rinv && !aligned16(Rinv)) return CTQR_EINVAL;
+        if (!prec_ok(dtype, prec))
+            return (dtype == CTQR_F32 && prec == CTQR_PREC_BF16_MFMA) ? CTQR_EUNSUPPORTED : CTQR_EINVAL;
+        nb = resolve_nb(nb);
+        if (!nb_ok(nb)) return CTQR_EINVAL;
+        // block boundaries: resident part and tiles are whole 2048-column
+        // diagonal blocks of the substitution and whole nb-column blocks
+        if (n_dev < 0 || n_dev > n || tile_cols < 1) return CTQR_EINVAL;
+        if (n_dev % TRSM_BIG != 0 || n_dev % nb != 0 || tile_cols % TRSM_BIG != 0 || tile_cols % nb != 0)
+            return CTQR_EINVAL;
+        if (n_dev > 0 && (!A_dev || !aligned16(A_dev))) return CTQR_EINVAL;
+        if (n_dev < n && (!A_host || !aligned16(A_host))) return CTQR_EINVAL;
+        size_t need = 0;
+        ctqr_qr_factor_ooc_workspace(m, n, dtype, prec, nb, lda, tile_cols, &need);
+        if (work_bytes < need) return CTQR_ENOMEM;
+        if (!panel_fits((int)m, dtype)) return CTQR_EUNSUPPORTED;
+        if (n_dev < n) {
+            // the host part must be pinned (page-locked) host memory
+            hipPointerAttribute_t at{};
+            if (hipPointerGetAttributes(&at, A_host) != hipSuccess || at.type != hipMemoryTypeHost) {
+                (void)hipGetLastError();
+                return CTQR_EINVAL;
+            }
+        }
+        ctqr_status s = ensure_setup();
+        if (s) return s;
+        if (dtype == CTQR_F64)
+            return factor_ooc_impl<double>(m, n, (double *)A_dev, (double *)A_host, lda, n_dev, tile_cols, nb,
+                                           (double *)T, tau, (double *)Rinv, work, info, stream);
+        return factor_ooc_impl<float>(m, n, (float *)A_dev, (float *)A_host, lda, n_dev, tile_cols, nb, (float *)T,
+                                      tau, (float *)Rinv, work, info, stream);
+    } catch (...) {
+        return CTQR_EHIP;
+    }
+}
+
 ctqr_status ctqr_qr_rinv_bytes(int64_t n, ctqr_dtype dtype, size_t *bytes)
 {
     if (!bytes || n < 1 || n >= INT32_MAX || (dtype != CTQR_F64 && dtype != CTQR_F32)) return CTQR_EINVAL;
@@ -746,7 +953,7 @@ ctqr_status ctqr_qr_factor(int64_t m, int64_t n, ctqr_dtype dtype, void *A, int6
         size_t need = 0;
         ctqr_qr_workspace(m, n, dtype, prec, nb, &need);
         if (work_bytes < need || !aligned16(work)) return work_bytes < need ? CTQR_ENOMEM : CTQR_EINVAL;
-        if (panel_rows_per_wg((int)m, 256) > panel_max_rows_per_wg()) return CTQR_EUNSUPPORTED;
+        if (!panel_fits((int)m, dtype)) return CTQR_EUNSUPPORTED;
         ctqr_status s = ensure_setup();
         if (s) return s;
         if (dtype == CTQR_F64)

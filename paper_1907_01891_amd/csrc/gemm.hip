@@ -608,12 +608,15 @@ ctqr_status splitk_reduce(int M, int N, int splits, const T *part, T alpha, T be
 template <typename T>
 ctqr_status gemm_tn(int M, int N, int K, const T *A, int64_t lda, int amask, const T *B,
                     int64_t ldb, int bmask, T alpha, T beta, T *Out, int64_t ldo, T *part,
-                    size_t part_elems, const int *skip, hipStream_t st)
+                    size_t part_elems, const int *skip, hipStream_t st, int force_splits)
 {
     if (M <= 0 || N <= 0) return CTQR_OK;
     const bool narrow = N <= t_narrow_max;
-    int splits = gemm_tn_splits(M, N, K);
-    if (splits > 1 && (part == nullptr || part_elems < (size_t)splits * M * N)) splits = 1;
+    int splits = force_splits > 0 ? force_splits : gemm_tn_splits(M, N, K);
+    if (splits > 1 && (part == nullptr || part_elems < (size_t)splits * M * N)) {
+        if (force_splits > 0) return CTQR_ENOMEM;   // a forced split must not silently change
+        splits = 1;
+    }
     int kchunk = (int)ceil_div(ceil_div(K, splits), Mf<T>::BK) * Mf<T>::BK;
     if (kchunk <= 0) kchunk = Mf<T>::BK;
     splits = (int)ceil_div(K > 0 ? K : 1, kchunk);
@@ -676,10 +679,10 @@ ctqr_status gemm_nn_split(int M, int N, int K, const T *A, int64_t lda, const T 
 
 template ctqr_status gemm_tn<float>(int, int, int, const float *, int64_t, int, const float *,
                                     int64_t, int, float, float, float *, int64_t, float *, size_t,
-                                    const int *, hipStream_t);
+                                    const int *, hipStream_t, int);
 template ctqr_status gemm_tn<double>(int, int, int, const double *, int64_t, int, const double *,
                                      int64_t, int, double, double, double *, int64_t, double *,
-                                     size_t, const int *, hipStream_t);
+                                     size_t, const int *, hipStream_t, int);
 template ctqr_status gemm_nn<float>(int, int, int, const float *, int64_t, int, const float *,
                                     int64_t, float, float *, int64_t, const int *, hipStream_t, int, int);
 template ctqr_status gemm_nn<double>(int, int, int, const double *, int64_t, int, const double *,

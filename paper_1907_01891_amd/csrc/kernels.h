@@ -9,10 +9,13 @@ int gemm_narrow_max();
 void gemm_set_narrow_max(int n);
 int gemm_tn_splits(int M, int N, int K);
 size_t gemm_tn_partial_elems(int M, int N, int K);
+// force_splits > 0 fixes the number of K splits (the partial buffer must hold
+// them, else CTQR_ENOMEM): products over different column ranges of one
+// matrix then sum every output in the same order.
 template <typename T>
 ctqr_status gemm_tn(int M, int N, int K, const T *A, int64_t lda, int amask, const T *B,
                     int64_t ldb, int bmask, T alpha, T beta, T *Out, int64_t ldo, T *part,
-                    size_t part_elems, const int *skip, hipStream_t st);
+                    size_t part_elems, const int *skip, hipStream_t st, int force_splits = 0);
 template <typename T>
 ctqr_status gemm_nn(int M, int N, int K, const T *A, int64_t lda, int amask, const T *B,
                     int64_t ldb, T alpha, T *C, int64_t ldc, const int *skip, hipStream_t st,
@@ -26,7 +29,8 @@ ctqr_status gemm_nn_split(int M, int N, int K, const T *A, int64_t lda, const T 
 // ---- panel_qr.hip ----------------------------------------------------------
 constexpr int PANEL_XCH_STRIDE = 40;   // doubles per workgroup per exchange buffer (two buffers)
 int panel_rows_per_wg(int mrem, int ncu);
-int panel_max_rows_per_wg();
+int panel_max_rows_per_wg();       // FP64 slab
+int panel_max_rows_per_wg_f32();   // FP32 slab (FP32 storage only)
 ctqr_status panel_setup(int max_rows);
 template <typename TS>
 ctqr_status panel_qr(TS *A, int64_t lda, int m, int r0, int w, double *tau, double *part,
@@ -44,6 +48,10 @@ size_t trinv_tmp_elems();
 template <typename T>
 ctqr_status trinv_blocks(int n, const T *R, int64_t ldr, T *Rinv, T *tmp, ctqr_info *info,
                          hipStream_t st);
+// the diagonal blocks starting in columns [c0, c1) only (block-size multiples)
+template <typename T>
+ctqr_status trinv_blocks_range(int n, int c0, int c1, const T *R, int64_t ldr, T *Rinv, T *tmp,
+                               hipStream_t st);
 template <typename T>
 ctqr_status trsm_upper(int n, int S, const T *R, int64_t ldr, const T *Rinv, T *C, int64_t ldc,
                        T *X, int64_t ldx, T *part, size_t part_elems, const int *skip, hipStream_t st);
@@ -51,6 +59,9 @@ template <typename T>
 ctqr_status trsm_upper_trans(int n, int S, const T *R, int64_t ldr, const T *Rinv, T *C, int64_t ldc,
                              T *Y, int64_t ldy, T *part, size_t part_elems, const int *skip,
                              hipStream_t st);
+// out[k] = A(k, k) for k in [c0, c1)
+template <typename T>
+ctqr_status diag_copy(int c0, int c1, const T *A, int64_t lda, T *out, hipStream_t st);
 template <typename T>
 ctqr_status rdiag_check(int n, const T *R, int64_t ldr, double *scratch, ctqr_info *info,
                         hipStream_t st);

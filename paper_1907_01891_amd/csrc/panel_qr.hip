@@ -56,13 +56,17 @@ __device__ inline double block_sum(double v, double *red)
     return r;
 }
 
-template <typename TS>
+// SL: element type of the slab.  FP64 whenever it fits in LDS; for very tall
+// FP32 panels (more rows per workgroup than an FP64 slab can hold) an FP32
+// slab, with every sum, norm and reflector scalar still formed in FP64.
+template <typename TS, typename SL>
 __global__ __launch_bounds__(PNT)
 void panel_qr_kernel(TS *__restrict__ A, int64_t lda, int m, int r0, int w, int rows_per_wg,
                      double *__restrict__ tau_out, double *part, double *part2,
                      double *__restrict__ gram_part, unsigned *bar, ctqr_info *info)
 {
-    extern __shared__ double slab[];              // rows_per_wg x SLD
+    extern __shared__ __attribute__((aligned(16))) unsigned char slab_raw[];
+    SL *slab = reinterpret_cast<SL *>(slab_raw);  // rows_per_wg x SLD
     __shared__ double red[PNT / CTQR_WAVE];
     __shared__ double wred[PNT / PW][PS];
     __shared__ double red4[PNT / CTQR_WAVE][CTQR_WAVE];
@@ -76,7 +80,7 @@ void panel_qr_kernel(TS *__restrict__ A, int64_t lda, int m, int r0, int w, int 
 
     for (int idx = tid; idx < nrows * w; idx += PNT) {
         int c = idx / nrows, rr = idx % nrows;
-        slab[rr * SLD + c] = (double)A[(int64_t)(r0 + c) * lda + row0 + rr];
+        slab[rr * SLD + c] = (SL)A[(int64_t)(r0 + c) * lda + row0 + rr];
     }
     __syncthreads();
 
@@ -205,7 +209,7 @@ void panel_qr_kernel(TS *__restrict__ A, int64_t lda, int m, int r0, int w, int 
                 alpha = xch[X_A1] - tw * xch[X_V1];
             }
         }
-        if (wg == 0 && tid == 0) slab[(p - row0) * SLD + j] = beta;
+        if (wg == 0 && tid == 0) slab[(p - row0) * SLD + j] = (SL)beta;
         __syncthreads();
     }
 
@@ -366,9 +370,13 @@ int panel_rows_per_wg(int mrem, int ncu)
     return rows;
 }
 
-size_t panel_lds_bytes(int rows_per_wg) { return (size_t)rows_per_wg * SLD * sizeof(double); }
+// LDS of a slab of rows_per_wg rows (element size esz).  FP64 slabs keep to
+// 144 KiB; the FP32 slab of very tall panels may take 152 KiB (the kernel's
+// static LDS adds about 5 KiB; gfx950 offers 160 KiB per workgroup).
+size_t panel_lds_bytes(int rows_per_wg, size_t esz) { return (size_t)rows_per_wg * SLD * esz; }
 
 int panel_max_rows_per_wg() { return (int)((144 * 1024) / (SLD * sizeof(double))); }
+int panel_max_rows_per_wg_f32() { return (int)((152 * 1024) / (SLD * sizeof(float))); }
 
 template <typename TS>
 ctqr_status panel_qr(TS *A, int64_t lda, int m, int r0, int w, double *tau, double *part,
@@ -377,22 +385,31 @@ ctqr_status panel_qr(TS *A, int64_t lda, int m, int r0, int w, double *tau, doub
 {
     const int mrem = m - r0;
     const int rows = panel_rows_per_wg(mrem, ncu);
-    if (rows > panel_max_rows_per_wg()) return CTQR_EUNSUPPORTED;
+    const bool f32slab = sizeof(TS) == 4 && rows > panel_max_rows_per_wg();
+    if (rows > (f32slab ? panel_max_rows_per_wg_f32() : panel_max_rows_per_wg())) return CTQR_EUNSUPPORTED;
     const int G = (int)ceil_div(mrem, rows);
-    const size_t lds = panel_lds_bytes(rows);
+    const size_t lds = panel_lds_bytes(rows, f32slab ? sizeof(float) : sizeof(double));
     void *args[] = {&A, (void *)&lda, &m, &r0, &w, (void *)&rows, &tau, &part, &part2, &gram_part, &bar, &info};
-    HIP_TRY(hipLaunchCooperativeKernel((const void *)panel_qr_kernel<TS>, dim3(G), dim3(PNT), args, lds, st));
+    if (f32slab)
+        HIP_TRY(hipLaunchCooperativeKernel((const void *)panel_qr_kernel<TS, float>, dim3(G), dim3(PNT), args, lds,
+                                           st));
+    else
+        HIP_TRY(hipLaunchCooperativeKernel((const void *)panel_qr_kernel<TS, double>, dim3(G), dim3(PNT), args,
+                                           lds, st));
     LAUNCH_TRY(gram_reduce_kernel, dim3(PW * PW / 16), dim3(256), 0, st, G, (const double *)gram_part, gram);
     return CTQR_OK;
 }
 
 ctqr_status panel_setup(int max_rows)
 {
-    size_t lds = panel_lds_bytes(max_rows);
-    HIP_TRY(hipFuncSetAttribute((const void *)panel_qr_kernel<float>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    HIP_TRY(hipFuncSetAttribute((const void *)panel_qr_kernel<double>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    const int l64 = (int)panel_lds_bytes(max_rows, sizeof(double));
+    const int l32 = (int)panel_lds_bytes(panel_max_rows_per_wg_f32(), sizeof(float));
+    HIP_TRY(hipFuncSetAttribute((const void *)panel_qr_kernel<float, double>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, l64));
+    HIP_TRY(hipFuncSetAttribute((const void *)panel_qr_kernel<double, double>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, l64));
+    HIP_TRY(hipFuncSetAttribute((const void *)panel_qr_kernel<float, float>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, l32));
     return CTQR_OK;
 }
 

@@ -70,13 +70,13 @@ __device__ inline void inv32(const double (*Rs)[33], double (*Xq)[33], int valid
 // (j's block offset inside its BIG block) + i).
 template <typename T>
 __global__ __launch_bounds__(256)
-void trinv_kernel(int n, const T *__restrict__ R, int64_t ldr, T *__restrict__ Rinv)
+void trinv_kernel(int n, const T *__restrict__ R, int64_t ldr, T *__restrict__ Rinv, int blk0)
 {
     __shared__ double Xrow[RB][XLD];
     __shared__ double Rs[32][33];
     __shared__ double Xq[32][33];
     __shared__ double Y[32][33];
-    const int blk = blockIdx.x, p = blockIdx.y, tid = threadIdx.x;
+    const int blk = blk0 + (int)blockIdx.x, p = blockIdx.y, tid = threadIdx.x;
     const int base = blk * BT;
     const int nbk = min(BT, n - base);
     const int nq = (nbk + RB - 1) / RB;
@@ -170,6 +170,14 @@ void rdiag_kernel(int n, const T *__restrict__ R, int64_t ldr, ctqr_info *info)
     }
 }
 
+// out[k] = A(k, k) for k in [c0, c1)
+template <typename T>
+__global__ void diag_copy_kernel(int c0, int c1, const T *__restrict__ A, int64_t lda, T *__restrict__ out)
+{
+    const int k = c0 + (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (k < c1) out[k] = A[(int64_t)k * lda + k];
+}
+
 template <typename T>
 __global__ void zero_kernel(T *__restrict__ p, int64_t count)
 {
@@ -180,10 +188,10 @@ __global__ void zero_kernel(T *__restrict__ p, int64_t count)
 
 // RinvT block i = transpose of Rinv block i (each BIG x BIG, ld BIG)
 template <typename T>
-__global__ void block_transpose_kernel(const T *__restrict__ Rinv, T *__restrict__ RinvT)
+__global__ void block_transpose_kernel(const T *__restrict__ Rinv, T *__restrict__ RinvT, int z0)
 {
     __shared__ T t[32][33];
-    const int64_t base = (int64_t)blockIdx.z * BIG * BIG;
+    const int64_t base = (int64_t)(z0 + (int)blockIdx.z) * BIG * BIG;
     const int r0 = blockIdx.x * 32, c0 = blockIdx.y * 32;
     for (int k = threadIdx.y; k < 32; k += 8)
         t[k][threadIdx.x] = Rinv[base + (int64_t)(c0 + k) * BIG + r0 + threadIdx.x];
@@ -200,18 +208,24 @@ size_t trinv_elems(int n) { return (size_t)BIG * (size_t)ceil_div(n, BIG) * BIG;
 size_t trinv_tmp_elems() { return (size_t)(BIG / 2) * (BIG / 2); }
 
 template <typename T>
-ctqr_status trinv_blocks(int n, const T *R, int64_t ldr, T *Rinv, T *tmp, ctqr_info *info, hipStream_t st)
+ctqr_status trinv_blocks_range(int n, int c0, int c1, const T *R, int64_t ldr, T *Rinv, T *tmp, hipStream_t st)
 {
-    // Rinv holds the inverses, Rinv + trinv_elems(n) their block transposes
-    (void)info;
+    // Rinv holds the inverses, Rinv + trinv_elems(n) their block transposes;
+    // this call fills the diagonal blocks whose columns start in [c0, c1)
+    // (multiples of the block size) and reads R only inside them.
     const int64_t total = (int64_t)trinv_elems(n);
-    LAUNCH_TRY(zero_kernel<T>, dim3((unsigned)std::min<int64_t>(ceil_div(total, 256), 8192)), dim3(256), 0, st,
-               Rinv, total);
-    LAUNCH_TRY(trinv_kernel<T>, dim3((unsigned)ceil_div(n, BT), NQ), dim3(256), 0, st, n, R, ldr, Rinv);
+    c1 = std::min(c1, n);
+    if (c0 >= c1) return CTQR_OK;
+    const int64_t z0 = c0 / BIG, z1 = ceil_div(c1, BIG);
+    const int64_t span = (z1 - z0) * BIG * BIG;
+    LAUNCH_TRY(zero_kernel<T>, dim3((unsigned)std::min<int64_t>(ceil_div(span, 256), 8192)), dim3(256), 0, st,
+               Rinv + z0 * BIG * BIG, span);
+    LAUNCH_TRY(trinv_kernel<T>, dim3((unsigned)ceil_div(c1 - c0, BT), NQ), dim3(256), 0, st, n, R, ldr, Rinv,
+               c0 / BT);
     // doubling inside every BIG block: [A B; 0 D] -> X12 = -inv(A) (B inv(D))
     const int64_t ldy = BIG / 2;
     for (int s = BT; s < BIG; s *= 2) {
-        for (int g0 = 0; g0 < n; g0 += 2 * s) {
+        for (int g0 = c0; g0 < c1; g0 += 2 * s) {
             const int d = std::min(s, n - (g0 + s));
             if (d <= 0) continue;
             const int off = g0 % BIG;
@@ -225,8 +239,23 @@ ctqr_status trinv_blocks(int n, const T *R, int64_t ldr, T *Rinv, T *tmp, ctqr_i
             if (e) return e;
         }
     }
-    LAUNCH_TRY(block_transpose_kernel<T>, dim3(BIG / 32, BIG / 32, (unsigned)ceil_div(n, BIG)), dim3(32, 8), 0,
-               st, (const T *)Rinv, Rinv + total);
+    LAUNCH_TRY(block_transpose_kernel<T>, dim3(BIG / 32, BIG / 32, (unsigned)(z1 - z0)), dim3(32, 8), 0, st,
+               (const T *)Rinv, Rinv + total, (int)z0);
+    return CTQR_OK;
+}
+
+template <typename T>
+ctqr_status trinv_blocks(int n, const T *R, int64_t ldr, T *Rinv, T *tmp, ctqr_info *info, hipStream_t st)
+{
+    (void)info;
+    return trinv_blocks_range<T>(n, 0, (int)(ceil_div(n, BIG) * BIG), R, ldr, Rinv, tmp, st);
+}
+
+template <typename T>
+ctqr_status diag_copy(int c0, int c1, const T *A, int64_t lda, T *out, hipStream_t st)
+{
+    if (c1 <= c0) return CTQR_OK;
+    LAUNCH_TRY(diag_copy_kernel<T>, dim3((unsigned)ceil_div(c1 - c0, 256)), dim3(256), 0, st, c0, c1, A, lda, out);
     return CTQR_OK;
 }
 
@@ -313,7 +342,9 @@ ctqr_status trsm_upper_trans(int n, int S, const T *R, int64_t ldr, const T *Rin
 
 #define INST(T)                                                                                        \
     template ctqr_status trinv_blocks<T>(int, const T *, int64_t, T *, T *, ctqr_info *, hipStream_t);  \
+    template ctqr_status trinv_blocks_range<T>(int, int, int, const T *, int64_t, T *, T *, hipStream_t); \
     template ctqr_status rdiag_check<T>(int, const T *, int64_t, double *, ctqr_info *, hipStream_t);   \
+    template ctqr_status diag_copy<T>(int, int, const T *, int64_t, T *, hipStream_t);                  \
     template ctqr_status trsm_upper<T>(int, int, const T *, int64_t, const T *, T *, int64_t, T *,       \
                                        int64_t, T *, size_t, const int *, hipStream_t);                 \
     template ctqr_status trsm_upper_trans<T>(int, int, const T *, int64_t, const T *, T *, int64_t,     \

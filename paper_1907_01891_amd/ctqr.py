@@ -65,6 +65,9 @@ _SIGNATURES = {
     "ctqr_qr_workspace": (c_i32, [c_i64, c_i64, c_i32, c_i32, c_i32, _P(c_sz)]),
     "ctqr_qr_factor": (c_i32, [c_i64, c_i64, c_i32, c_vp, c_i64, c_i32, c_i32, c_vp, c_vp, c_vp,
                                c_vp, c_sz, c_vp, c_vp]),
+    "ctqr_qr_factor_ooc_workspace": (c_i32, [c_i64, c_i64, c_i32, c_i32, c_i32, c_i64, c_i64, _P(c_sz)]),
+    "ctqr_qr_factor_ooc": (c_i32, [c_i64, c_i64, c_i32, c_vp, c_vp, c_i64, c_i64, c_i64, c_i32, c_i32, c_vp, c_vp,
+                                   c_vp, c_vp, c_sz, c_vp, c_vp]),
     "ctqr_qr_rinv_bytes": (c_i32, [c_i64, c_i32, _P(c_sz)]),
     "ctqr_solve_workspace": (c_i32, [c_i64, c_i64, c_i32, c_i32, c_i32, c_i32, _P(c_sz)]),
     "ctqr_qr_solve_slices": (c_i32, [c_i64, c_i64, c_i32, c_vp, c_i64, c_vp, c_vp, c_vp, c_i32,
@@ -155,6 +158,19 @@ def ctqr_qr_factor(m, n, dtype, A_ptr, lda, prec, nb, T_ptr, tau_ptr, rinv_ptr, 
                    stream):
     return lib().ctqr_qr_factor(m, n, dtype, A_ptr, lda, prec, nb, T_ptr, tau_ptr, rinv_ptr, work_ptr, work_bytes,
                                 info_ptr, stream)
+
+
+def ctqr_qr_factor_ooc_workspace(m, n, dtype, prec, nb, lda, tile_cols):
+    b = c_sz()
+    check(lib().ctqr_qr_factor_ooc_workspace(m, n, dtype, prec, nb, lda, tile_cols, ctypes.byref(b)),
+          "ctqr_qr_factor_ooc_workspace")
+    return b.value
+
+
+def ctqr_qr_factor_ooc(m, n, dtype, A_dev, A_host, lda, n_dev, tile_cols, prec, nb, T_ptr, tau_ptr, rinv_ptr,
+                       work_ptr, work_bytes, info_ptr, stream):
+    return lib().ctqr_qr_factor_ooc(m, n, dtype, A_dev, A_host, lda, n_dev, tile_cols, prec, nb, T_ptr, tau_ptr,
+                                    rinv_ptr, work_ptr, work_bytes, info_ptr, stream)
 
 
 def ctqr_qr_rinv_bytes(n, dtype):

@@ -176,6 +176,52 @@ class QRFactor:
         return X
 
 
+class OocFactor:
+    """Out-of-core factor (ctqr_qr_factor_ooc): columns [0, n_dev) of A in
+    device memory, the rest in pinned host memory, streamed in tiles."""
+
+    def __init__(self, m, n, dtype, prec, n_dev, tile_cols, nb=0, device="cuda"):
+        tdt = _DT[dtype]
+        self.m, self.n, self.dtype, self.prec = m, n, dtype, prec
+        self.nb = nb or 256
+        self.lda = round_up(m, 64)
+        self.n_dev, self.tile_cols = n_dev, tile_cols
+        self.A_dev = colmajor(m, n_dev, tdt, device, ld=self.lda) if n_dev > 0 else None
+        self.A_host = (torch.empty((n - n_dev, self.lda), dtype=tdt, pin_memory=True).t()[:m, :]
+                       if n_dev < n else None)
+        self.T = colmajor(self.nb, n, tdt, device, ld=self.nb)
+        self.tau = torch.zeros(n, dtype=torch.float64, device=device)
+        self.Rinv = torch.empty(C.ctqr_qr_rinv_bytes(n, dtype) // self.T.element_size(), dtype=tdt, device=device)
+        self.info = Info(device)
+        self.work = Workspace(device)
+
+    def load(self, A):
+        """Copy a column-major (m x n) matrix (host or device tensor) into the two parts."""
+        if self.A_dev is not None:
+            self.A_dev.copy_(A[:, :self.n_dev])
+        if self.A_host is not None:
+            self.A_host.copy_(A[:, self.n_dev:])
+
+    def factor(self, stream=None):
+        wp, wb = self.work.get(C.ctqr_qr_factor_ooc_workspace(self.m, self.n, self.dtype, self.prec, self.nb,
+                                                              self.lda, self.tile_cols))
+        ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
+        C.check(C.ctqr_qr_factor_ooc(self.m, self.n, self.dtype, ptr(self.A_dev), ptr(self.A_host), self.lda,
+                                     self.n_dev, self.tile_cols, self.prec, self.nb, ptr(self.T), ptr(self.tau),
+                                     ptr(self.Rinv), wp, wb, self.info.ptr, stream_handle(stream)),
+                "ctqr_qr_factor_ooc")
+        return self
+
+    def factor_matrix(self):
+        """The whole factored matrix as one host tensor (m x n, column-major)."""
+        out = torch.empty((self.n, self.lda), dtype=self.T.dtype).t()[:self.m, :]
+        if self.A_dev is not None:
+            out[:, :self.n_dev].copy_(self.A_dev.cpu())
+        if self.A_host is not None:
+            out[:, self.n_dev:].copy_(self.A_host)
+        return out
+
+
 class Solver:
     """Batched solver over a stored factor (ctqr_solver_*): requests of 1 ..
     max_slices slices, one HIP graph per power-of-two slice bucket."""

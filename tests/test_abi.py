@@ -198,3 +198,23 @@ def test_solver_batch_rejects():
     ld = (ctypes.c_int64 * 1)(3072)
     ns = (ctypes.c_int32 * 1)(1)
     assert L.ctqr_solver_solve_batch(None, 1, one, ld, ns, one, ld, p, None) == C.CTQR_EINVAL
+
+
+def test_ooc_factor_rejects_before_any_hip_call():
+    L = C.lib()
+    p = ctypes.c_void_p(4096)
+
+    def call(m=8192, n=6144, A_dev=p, A_host=p, lda=8192, n_dev=2048, tile=2048, nb=256, wb=1 << 40,
+             prec=C.CTQR_PREC_FP32_MFMA, dtype=C.CTQR_F32):
+        return L.ctqr_qr_factor_ooc(m, n, dtype, A_dev, A_host, lda, n_dev, tile, prec, nb, p, p, p, p, wb, p, None)
+    assert call(n_dev=1024) == C.CTQR_EINVAL          # not a multiple of the 2048-column block
+    assert call(tile=3072) == C.CTQR_EINVAL
+    assert call(n_dev=8192) == C.CTQR_EINVAL          # n_dev > n
+    assert call(lda=8190) == C.CTQR_EINVAL
+    assert call(A_dev=None) == C.CTQR_EINVAL          # resident part missing
+    assert call(n_dev=0, A_host=None) == C.CTQR_EINVAL
+    assert call(wb=64) == C.CTQR_ENOMEM
+    assert call(nb=96) == C.CTQR_EINVAL               # 2048 is not a multiple of 96
+    w1 = C.ctqr_qr_factor_ooc_workspace(8192, 6144, C.CTQR_F32, C.CTQR_PREC_FP32_MFMA, 256, 8192, 2048)
+    w2 = C.ctqr_qr_factor_ooc_workspace(8192, 6144, C.CTQR_F32, C.CTQR_PREC_FP32_MFMA, 256, 8192, 4096)
+    assert w2 - w1 >= 2 * 8192 * 2048 * 4             # two tile buffers
