@@ -177,6 +177,15 @@ ctqr_status ctqr_qr_factor(int64_t m, int64_t n, ctqr_dtype dtype, void *A, int6
                            void *work, size_t work_bytes, ctqr_info *info,
                            hipStream_t stream);
 
+/* Columns [c0, c1) of the dense A, rebuilt from the CSC half of a sparse copy
+ * made by ctqr_build_system_matrix: column c0 + q goes to A + q * lda
+ * (device, `dtype`, every entry of the lda x (c1 - c0) block written).  The
+ * same values as the dense output of the build (each a_ij rounded once to
+ * `dtype`), for matrices whose dense form is produced a tile at a time
+ * (Section II-A, Eq. 1). */
+ctqr_status ctqr_sparse_to_dense(const ctqr_sparse *sp, ctqr_dtype dtype, int64_t c0, int64_t c1,
+                                 void *A, int64_t lda, hipStream_t stream);
+
 /* ---- Out-of-core factorization --------------------------------------------
  * For an A larger than device memory (the paper's out-of-core setting,
  * Section II-B, with HBM in the role of main memory and pinned host memory in
@@ -206,6 +215,27 @@ ctqr_status ctqr_qr_factor_ooc(int64_t m, int64_t n, ctqr_dtype dtype, void *A_d
                                int64_t lda, int64_t n_dev, int64_t tile_cols, ctqr_prec prec,
                                int32_t nb, void *T, double *tau, void *Rinv, void *work,
                                size_t work_bytes, ctqr_info *info, hipStream_t stream);
+
+/* Solve with an out-of-core factor (the outputs of ctqr_qr_factor_ooc, same
+ * n_dev, tile_cols, lda and nb; Rinv required): X = R^-1 Q^T B with the
+ * refinement of ctqr_qr_solve_slices.  Q^T B applies the resident blocks and
+ * then each host tile uploaded in turn; R X = C runs from the last host tile
+ * back to the resident columns (right-looking) and R^T Y = C from the
+ * resident columns forward (left-looking), so each substitution uploads
+ * every host tile once and never writes host memory.  B, X, the sparse A and
+ * the work space are device memory; the workspace holds one tile buffer
+ * (ctqr_solve_ooc_workspace).  With refinement the call waits on the stream
+ * after each iteration, as ctqr_qr_solve_slices does.  Section II-B (one
+ * read of the stored factor per pass serves every slice). */
+ctqr_status ctqr_solve_ooc_workspace(int64_t m, int64_t n, ctqr_dtype dtype, int32_t nb,
+                                     int32_t nslices, int32_t refine, int64_t lda,
+                                     int64_t tile_cols, size_t *bytes);
+ctqr_status ctqr_qr_solve_ooc(int64_t m, int64_t n, ctqr_dtype dtype, const void *QR_dev,
+                              const void *QR_host, int64_t lda, int64_t n_dev, int64_t tile_cols,
+                              const void *T, const double *tau, const void *Rinv, int32_t nb,
+                              const double *B, int64_t ldb, int32_t nslices, double *X,
+                              int64_t ldx, const ctqr_sparse *A64, double tol, int32_t max_iters,
+                              void *work, size_t work_bytes, ctqr_info *info, hipStream_t stream);
 
 /* Bytes of the Rinv array of ctqr_qr_factor / ctqr_qr_solve_slices (host only). */
 ctqr_status ctqr_qr_rinv_bytes(int64_t n, ctqr_dtype dtype, size_t *bytes);

@@ -414,6 +414,30 @@ SolveRun<T> make_run(int64_t m, int64_t n, const T *QR, int64_t lda, const T *Tf
     return r;
 }
 
+// Q^T B over the block reflectors [kb, ke) (Householder blocks read through
+// V: column k at V + k lda), one block at a time: B -= V (T^T (V^T B)).
+template <typename T>
+ctqr_status apply_qt_range(SolveRun<T> &r, const T *QRv, int kb, int ke, hipStream_t st)
+{
+    SolveWS<T> &w = r.w;
+    const int m = r.m, n = r.n, nb = r.nb, S = r.S;
+    ctqr_status s;
+    for (int k0 = kb; k0 < ke; k0 += nb) {
+        const int nbk = std::min(nb, n - k0);
+        const T *V = QRv + (int64_t)k0 * r.lda + k0;
+        T *Bk = w.Bw + k0;
+        s = gemm_tn<T>(nbk, S, m - k0, V, r.lda, nbk, Bk, w.ldbw, 0, T(1), T(0), w.W, nb, w.split, r.sp_elems,
+                       nullptr, st);
+        if (s) return s;
+        s = gemm_tn<T>(nbk, S, nbk, r.Tf + (int64_t)k0 * nb, nb, 0, w.W, nb, 0, T(1), T(0), w.W2, nb, w.split,
+                       r.sp_elems, nullptr, st);
+        if (s) return s;
+        s = gemm_nn<T>(m - k0, S, nbk, V, r.lda, 1, w.W2, nb, T(-1), Bk, w.ldbw, nullptr, st);
+        if (s) return s;
+    }
+    return CTQR_OK;
+}
+
 // Q^T B and the back substitution (Section II-C), then the set-up of the
 // refinement.
 template <typename T>
@@ -427,20 +451,7 @@ ctqr_status solve_start(SolveRun<T> &r, hipStream_t st)
     if ((s = fill_u32((unsigned *)w.done, 64, 0u, st))) return s;
     // working copy of B in the factor's precision
     if ((s = copy_cm<T, double>(m, S, r.B, r.ldb, w.Bw, w.ldbw, st))) return s;
-    // Q^T B, one block reflector at a time: B -= V (T^T (V^T B))
-    for (int k0 = 0; k0 < n; k0 += nb) {
-        const int nbk = std::min(nb, n - k0);
-        const T *V = r.QR + (int64_t)k0 * r.lda + k0;
-        T *Bk = w.Bw + k0;
-        s = gemm_tn<T>(nbk, S, m - k0, V, r.lda, nbk, Bk, w.ldbw, 0, T(1), T(0), w.W, nb, w.split, r.sp_elems,
-                       nullptr, st);
-        if (s) return s;
-        s = gemm_tn<T>(nbk, S, nbk, r.Tf + (int64_t)k0 * nb, nb, 0, w.W, nb, 0, T(1), T(0), w.W2, nb, w.split,
-                       r.sp_elems, nullptr, st);
-        if (s) return s;
-        s = gemm_nn<T>(m - k0, S, nbk, V, r.lda, 1, w.W2, nb, T(-1), Bk, w.ldbw, nullptr, st);
-        if (s) return s;
-    }
+    if ((s = apply_qt_range(r, r.QR, 0, n, st))) return s;
     // back substitution R X = (Q^T B)[0:n], with the factor's diagonal-block
     // inverses (built here when the factor was stored without them)
     if (!r.Rinv) {
@@ -534,6 +545,127 @@ ctqr_status solve_impl(int64_t m64, int64_t n64, const T *QR, int64_t lda, const
     if (s) return s;
     if (r.refine() && (s = refine_iters(r, 0, max_iters, true, st, nullptr))) return s;
     return solve_finish(r, S, X, ldx, st);
+}
+
+// ---------------------------------------------------------------------------
+// Out-of-core solve: the factor of ctqr_qr_factor_ooc, resident columns in
+// HBM and the rest in pinned host memory.  Q^T B takes the resident blocks,
+// then each host tile uploaded in turn; R X = C runs right-looking from the
+// last tile back to the resident part and R^T Y = C left-looking from the
+// resident part forward, so every step reads only its own column block and
+// every pass uploads each tile once.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct TileCache {
+    const T *host;
+    T *buf;
+    int64_t lda;
+    int n_dev, tile, n;
+    int loaded = -1;   // first column of the tile the buffer holds
+    // the tile starting at column c0, uploaded unless the buffer holds it;
+    // returns the column-shifted pointer (column k at + k lda)
+    ctqr_status get(int c0, hipStream_t st, const T **out)
+    {
+        if (loaded != c0) {
+            const int c1 = std::min(n, c0 + tile);
+            HIP_TRY(hipMemcpyAsync(buf, host + (int64_t)(c0 - n_dev) * lda, (size_t)(c1 - c0) * lda * sizeof(T),
+                                   hipMemcpyHostToDevice, st));
+            loaded = c0;
+        }
+        *out = shift_cols(buf, c0, lda);
+        return CTQR_OK;
+    }
+};
+
+template <typename T>
+ctqr_status ooc_upper(SolveRun<T> &r, TileCache<T> &tc, const T *QRdev, T *C, int64_t ldc, T *X, int64_t ldx,
+                      const int *skip, hipStream_t st)
+{
+    ctqr_status s;
+    const int n = r.n;
+    int last = tc.n_dev + (int)((n - tc.n_dev - 1) / tc.tile) * tc.tile;
+    for (int c0 = last; c0 >= tc.n_dev && c0 < n; c0 -= tc.tile) {
+        const T *Rv;
+        if ((s = tc.get(c0, st, &Rv))) return s;
+        s = trsm_upper_cols<T>(n, r.S, Rv, r.lda, r.Rinv, C, ldc, X, ldx, c0, std::min(n, c0 + tc.tile),
+                               r.w.split, r.sp_elems, skip, st);
+        if (s) return s;
+    }
+    if (tc.n_dev > 0)
+        return trsm_upper_cols<T>(n, r.S, QRdev, r.lda, r.Rinv, C, ldc, X, ldx, 0, tc.n_dev, r.w.split,
+                                  r.sp_elems, skip, st);
+    return CTQR_OK;
+}
+
+template <typename T>
+ctqr_status ooc_upper_trans(SolveRun<T> &r, TileCache<T> &tc, const T *QRdev, T *C, T *Y, const int *skip,
+                            hipStream_t st)
+{
+    ctqr_status s;
+    const int n = r.n;
+    if (tc.n_dev > 0) {
+        s = trsm_upper_trans_cols<T>(n, r.S, QRdev, r.lda, r.Rinv, C, r.w.ldxw, Y, r.w.ldxw, 0, tc.n_dev,
+                                     r.w.split, r.sp_elems, skip, st);
+        if (s) return s;
+    }
+    for (int c0 = tc.n_dev; c0 < n; c0 += tc.tile) {
+        const T *Rv;
+        if ((s = tc.get(c0, st, &Rv))) return s;
+        s = trsm_upper_trans_cols<T>(n, r.S, Rv, r.lda, r.Rinv, C, r.w.ldxw, Y, r.w.ldxw, c0,
+                                     std::min(n, c0 + tc.tile), r.w.split, r.sp_elems, skip, st);
+        if (s) return s;
+    }
+    return CTQR_OK;
+}
+
+template <typename T>
+ctqr_status solve_ooc_impl(int64_t m64, int64_t n64, const T *QR_dev, const T *QR_host, int64_t lda, int n_dev,
+                           int tile, const T *Tf, const T *Rinv, int nb, const double *B, int64_t ldb, int S,
+                           double *X, int64_t ldx, const ctqr_sparse *A64, double tol, int max_iters, void *work,
+                           ctqr_info *info, hipStream_t st)
+{
+    SolveRun<T> r = make_run<T>(m64, n64, QR_dev, lda, Tf, Rinv, nb, B, ldb, S, A64, tol, max_iters, work, info,
+                                false);
+    Carve c(work);
+    c.off = r.w.bytes;
+    TileCache<T> tc{QR_host, c.take<T>(lda * (int64_t)tile), lda, n_dev, tile, (int)n64};
+    NarrowScope ns(r.narrow);
+    SolveWS<T> &w = r.w;
+    const int m = r.m, n = r.n;
+    ctqr_status s;
+    if ((s = info_reset(info, st))) return s;
+    if ((s = fill_u32((unsigned *)w.done, 64, 0u, st))) return s;
+    if ((s = copy_cm<T, double>(m, S, B, ldb, w.Bw, w.ldbw, st))) return s;
+    if (n_dev > 0 && (s = apply_qt_range(r, QR_dev, 0, n_dev, st))) return s;
+    for (int c0 = n_dev; c0 < n; c0 += tile) {
+        const T *Vv;
+        if ((s = tc.get(c0, st, &Vv))) return s;
+        if ((s = apply_qt_range(r, Vv, c0, std::min(n, c0 + tile), st))) return s;
+    }
+    // R X = (Q^T B)[0:n], substituting in the working copy
+    if ((s = ooc_upper(r, tc, QR_dev, w.Bw, w.ldbw, w.Xw, w.ldxw, nullptr, st))) return s;
+    if (!r.refine()) return copy_cm<double, T>(n, S, w.Xw, w.ldxw, X, ldx, st);
+    if ((s = cm_to_rm<double, T>(n, S, w.Xw, w.ldxw, w.xr, nullptr, st))) return s;
+    if ((s = cm_to_rm<double, double>(m, S, B, ldb, w.Br, nullptr, st))) return s;
+    if ((s = fill_f64(w.hist, 8, 0.0, st))) return s;
+    if ((s = fill_u32((unsigned *)w.dmax, 2LL * S, 0u, st))) return s;
+    if ((s = fill_u32((unsigned *)w.xmax, 2LL * S, 0u, st))) return s;
+    for (int it = 0; it < max_iters; ++it) {
+        const int *skip = w.done;
+        s = spmm_rowmajor(m, S, A64->rowptr, A64->col, A64->val, -1.0, w.xr, 1.0, w.Br, w.r, skip, st);
+        if (s) return s;
+        s = spmm_rowmajor(n, S, A64->colptr, A64->row, A64->cval, 1.0, w.r, 0.0, nullptr, w.s, skip, st);
+        if (s) return s;
+        if ((s = rm_to_cm<T, double>(n, S, w.s, w.s32, w.ldxw, skip, st))) return s;
+        if ((s = ooc_upper_trans(r, tc, QR_dev, w.s32, w.y32, skip, st))) return s;
+        if ((s = ooc_upper(r, tc, QR_dev, w.y32, w.ldxw, w.d32, w.ldxw, skip, st))) return s;
+        if ((s = refine_update<T>(n, S, w.xr, w.d32, w.ldxw, w.dmax, w.xmax, skip, st))) return s;
+        if ((s = refine_check(S, w.dmax, w.xmax, tol, it, max_iters, w.hist, w.done, info, st))) return s;
+        bool done = false;
+        if ((s = read_done(w.done, st, done))) return s;
+        if (done) break;
+    }
+    return rm_to_cm<double, double>(n, S, w.xr, X, ldx, nullptr, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -876,6 +1008,15 @@ ctqr_status ctqr_qr_workspace(int64_t m, int64_t n, ctqr_dtype dtype, ctqr_prec 
     return CTQR_OK;
 }
 
+ctqr_status ctqr_sparse_to_dense(const ctqr_sparse *sp, ctqr_dtype dtype, int64_t c0, int64_t c1, void *A,
+                                 int64_t lda, hipStream_t stream)
+{
+    if (!sp || !sp->colptr || !sp->row || !sp->cval || !A || !aligned16(A)) return CTQR_EINVAL;
+    if (dtype != CTQR_F64 && dtype != CTQR_F32) return CTQR_EINVAL;
+    if (c0 < 0 || c1 < c0 || c1 > sp->n || lda < sp->m || sp->n >= INT32_MAX) return CTQR_EINVAL;
+    return sparse_to_dense_cols(sp, dtype, (int)c0, (int)c1, A, lda, stream);
+}
+
 ctqr_status ctqr_qr_factor_ooc_workspace(int64_t m, int64_t n, ctqr_dtype dtype, ctqr_prec prec, int32_t nb,
                                          int64_t lda, int64_t tile_cols, size_t *bytes)
 {
@@ -1144,6 +1285,65 @@ ctqr_status ctqr_solver_destroy(ctqr_solver sv)
     }
     delete sv;
     return CTQR_OK;
+}
+
+ctqr_status ctqr_solve_ooc_workspace(int64_t m, int64_t n, ctqr_dtype dtype, int32_t nb, int32_t nslices,
+                                     int32_t refine, int64_t lda, int64_t tile_cols, size_t *bytes)
+{
+    if (!bytes || m < n || n < 1 || m >= INT32_MAX || nslices < 1 || lda < m || tile_cols < 1) return CTQR_EINVAL;
+    if (dtype != CTQR_F64 && dtype != CTQR_F32) return CTQR_EINVAL;
+    nb = resolve_nb(nb);
+    if (!nb_ok(nb)) return CTQR_EINVAL;
+    const size_t esz = dtype == CTQR_F64 ? sizeof(double) : sizeof(float);
+    const size_t sb = dtype == CTQR_F64 ? carve_solve<double>(nullptr, m, n, nb, nslices, refine != 0, false).bytes
+                                        : carve_solve<float>(nullptr, m, n, nb, nslices, refine != 0, false).bytes;
+    *bytes = sb + 256 + (size_t)lda * (size_t)tile_cols * esz + 256;
+    return CTQR_OK;
+}
+
+ctqr_status ctqr_qr_solve_ooc(int64_t m, int64_t n, ctqr_dtype dtype, const void *QR_dev, const void *QR_host,
+                              int64_t lda, int64_t n_dev, int64_t tile_cols, const void *T, const double *tau,
+                              const void *Rinv, int32_t nb, const double *B, int64_t ldb, int32_t nslices, double *X,
+                              int64_t ldx, const ctqr_sparse *A64, double tol, int32_t max_iters, void *work,
+                              size_t work_bytes, ctqr_info *info, hipStream_t stream)
+{
+    try {
+        if (m < n || n < 1 || m >= INT32_MAX || nslices < 1) return CTQR_EINVAL;
+        if (!T || !tau || !Rinv || !B || !X || !work || !info) return CTQR_EINVAL;
+        if (dtype != CTQR_F64 && dtype != CTQR_F32) return CTQR_EINVAL;
+        if (lda < m || lda % 4 != 0 || ldb < m || ldx < n) return CTQR_EINVAL;
+        if (!aligned16(T) || !aligned16(Rinv) || !aligned16(work)) return CTQR_EINVAL;
+        nb = resolve_nb(nb);
+        if (!nb_ok(nb)) return CTQR_EINVAL;
+        if (n_dev < 0 || n_dev > n || tile_cols < 1) return CTQR_EINVAL;
+        if (n_dev % TRSM_BIG != 0 || n_dev % nb != 0 || tile_cols % TRSM_BIG != 0 || tile_cols % nb != 0)
+            return CTQR_EINVAL;
+        if (n_dev > 0 && (!QR_dev || !aligned16(QR_dev))) return CTQR_EINVAL;
+        if (n_dev < n && (!QR_host || !aligned16(QR_host))) return CTQR_EINVAL;
+        if (A64 && (A64->m != m || A64->n != n || !A64->rowptr || !A64->col || !A64->val || !A64->colptr ||
+                    !A64->row || !A64->cval))
+            return CTQR_EINVAL;
+        if (A64 && (max_iters < 0 || !(tol >= 0.0))) return CTQR_EINVAL;
+        size_t need = 0;
+        ctqr_solve_ooc_workspace(m, n, dtype, nb, nslices, A64 != nullptr && max_iters > 0, lda, tile_cols, &need);
+        if (work_bytes < need) return CTQR_ENOMEM;
+        if (n_dev < n) {
+            hipPointerAttribute_t at{};
+            if (hipPointerGetAttributes(&at, QR_host) != hipSuccess || at.type != hipMemoryTypeHost) {
+                (void)hipGetLastError();
+                return CTQR_EINVAL;
+            }
+        }
+        if (dtype == CTQR_F64)
+            return solve_ooc_impl<double>(m, n, (const double *)QR_dev, (const double *)QR_host, lda, (int)n_dev,
+                                          (int)tile_cols, (const double *)T, (const double *)Rinv, nb, B, ldb, nslices,
+                                          X, ldx, A64, tol, max_iters, work, info, stream);
+        return solve_ooc_impl<float>(m, n, (const float *)QR_dev, (const float *)QR_host, lda, (int)n_dev,
+                                     (int)tile_cols, (const float *)T, (const float *)Rinv, nb, B, ldb, nslices, X,
+                                     ldx, A64, tol, max_iters, work, info, stream);
+    } catch (...) {
+        return CTQR_EHIP;
+    }
 }
 
 ctqr_status ctqr_spmm(const ctqr_sparse *A64, int32_t nslices, double alpha, const double *X, int64_t ldx,

@@ -62,6 +62,17 @@ ctqr_status trsm_upper_trans(int n, int S, const T *R, int64_t ldr, const T *Rin
 // out[k] = A(k, k) for k in [c0, c1)
 template <typename T>
 ctqr_status diag_copy(int c0, int c1, const T *A, int64_t lda, T *out, hipStream_t st);
+// column-block ranges of the substitutions (right-looking R X = C over the
+// blocks starting in [c_lo, c_hi), last first; left-looking R^T Y = C, first
+// first); each step reads only its own column block of R
+template <typename T>
+ctqr_status trsm_upper_cols(int n, int S, const T *R, int64_t ldr, const T *Rinv, T *C, int64_t ldc, T *X,
+                            int64_t ldx, int c_lo, int c_hi, T *part, size_t part_elems, const int *skip,
+                            hipStream_t st);
+template <typename T>
+ctqr_status trsm_upper_trans_cols(int n, int S, const T *R, int64_t ldr, const T *Rinv, T *C, int64_t ldc, T *Y,
+                                  int64_t ldy, int c_lo, int c_hi, T *part, size_t part_elems, const int *skip,
+                                  hipStream_t st);
 template <typename T>
 ctqr_status rdiag_check(int n, const T *R, int64_t ldr, double *scratch, ctqr_info *info,
                         hipStream_t st);
@@ -70,6 +81,9 @@ ctqr_status rdiag_check(int n, const T *R, int64_t ldr, double *scratch, ctqr_in
 ctqr_status siddon_build(const ctqr_geometry *g, int dtype, void *A, int64_t lda, ctqr_sparse *sp,
                          void *work, size_t work_bytes, ctqr_info *info, hipStream_t st);
 size_t siddon_workspace(const ctqr_geometry *g);
+// columns [c0, c1) of the dense A (FP64 or FP32) from the CSC copy
+ctqr_status sparse_to_dense_cols(const ctqr_sparse *sp, int dtype, int c0, int c1, void *A, int64_t lda,
+                                 hipStream_t st);
 
 // ---- sparse.hip / util ------------------------------------------------------
 // y[i, :] = alpha * sum_k val[k] x[idx[k], :] + beta * y[i, :] for rows i of a

@@ -285,6 +285,19 @@ __global__ void zero_i32_kernel(int32_t *__restrict__ p, int64_t n)
         p[e] = 0;
 }
 
+// Columns [c0, c1) of the dense A from the CSC copy: column c0 + q of A goes
+// to out + q ldo (zeros elsewhere).  One wave per column.
+template <typename TA>
+__global__ __launch_bounds__(256)
+void csc_to_dense_kernel(int c0, int c1, const int64_t *__restrict__ colptr, const int32_t *__restrict__ row,
+                         const double *__restrict__ cval, TA *__restrict__ out, int64_t ldo)
+{
+    const int j = c0 + (int)blockIdx.x * 4 + (int)threadIdx.x / 64;
+    if (j >= c1) return;
+    TA *o = out + (int64_t)(j - c0) * ldo;
+    for (int64_t k = colptr[j] + threadIdx.x % 64; k < colptr[j + 1]; k += 64) o[row[k]] = (TA)cval[k];
+}
+
 }  // namespace
 
 size_t siddon_workspace(const ctqr_geometry *g)
@@ -344,6 +357,25 @@ ctqr_status siddon_build(const ctqr_geometry *gp, int dtype, void *A, int64_t ld
                    (const double *)sp->val, cap, (const int64_t *)sp->colptr, colfill, sp->row, sp->cval);
         LAUNCH_TRY(csc_sort_kernel, dim3((unsigned)n), dim3(256), 0, st, (int)n,
                    (const int64_t *)sp->colptr, cap, sp->row, sp->cval, info);
+    }
+    return CTQR_OK;
+}
+
+ctqr_status sparse_to_dense_cols(const ctqr_sparse *sp, int dtype, int c0, int c1, void *A, int64_t lda,
+                                 hipStream_t st)
+{
+    const int64_t cols = c1 - c0;
+    if (cols <= 0) return CTQR_OK;
+    unsigned blocks = (unsigned)std::min<int64_t>(ceil_div(lda * cols, 256), 1 << 20);
+    const dim3 g((unsigned)ceil_div(cols, 4)), b(256);
+    if (dtype == CTQR_F64) {
+        LAUNCH_TRY(zero_dense_kernel<double>, dim3(blocks), dim3(256), 0, st, (double *)A, lda, lda, cols);
+        LAUNCH_TRY(csc_to_dense_kernel<double>, g, b, 0, st, c0, c1, (const int64_t *)sp->colptr,
+                   (const int32_t *)sp->row, (const double *)sp->cval, (double *)A, lda);
+    } else {
+        LAUNCH_TRY(zero_dense_kernel<float>, dim3(blocks), dim3(256), 0, st, (float *)A, lda, lda, cols);
+        LAUNCH_TRY(csc_to_dense_kernel<float>, g, b, 0, st, c0, c1, (const int64_t *)sp->colptr,
+                   (const int32_t *)sp->row, (const double *)sp->cval, (float *)A, lda);
     }
     return CTQR_OK;
 }

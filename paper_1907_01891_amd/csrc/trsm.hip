@@ -340,6 +340,52 @@ ctqr_status trsm_upper_trans(int n, int S, const T *R, int64_t ldr, const T *Rin
     return CTQR_OK;
 }
 
+// Column-block ranges of the two substitutions, for a factor whose columns
+// are not all addressable at once (R: column k at R + k ldr for the columns
+// of the range only).  trsm_upper_cols runs the right-looking steps of the
+// diagonal blocks starting in [c_lo, c_hi), last block first: each step reads
+// only its own column block of R, so the ranges are taken from the last to
+// the first.  trsm_upper_trans_cols runs the left-looking steps of the blocks
+// in the range, first block first, also reading only column block i.
+template <typename T>
+ctqr_status trsm_upper_cols(int n, int S, const T *R, int64_t ldr, const T *Rinv, T *C, int64_t ldc, T *X,
+                            int64_t ldx, int c_lo, int c_hi, T *part, size_t part_elems, const int *skip,
+                            hipStream_t st)
+{
+    const T *RinvT = Rinv + trinv_elems(n);
+    for (int r0 = (int)(ceil_div(std::min(c_hi, n), BIG) - 1) * BIG; r0 >= c_lo; r0 -= BIG) {
+        const int bw = min(BIG, n - r0);
+        ctqr_status s = gemm_tn<T>(bw, S, bw, RinvT + (int64_t)r0 * BIG, BIG, 0, C + r0, ldc, 0, T(1), T(0),
+                                   X + r0, ldx, part, part_elems, skip, st);
+        if (s) return s;
+        if (r0 > 0) {
+            s = gemm_nn<T>(r0, S, bw, R + (int64_t)r0 * ldr, ldr, 0, X + r0, ldx, T(-1), C, ldc, skip, st);
+            if (s) return s;
+        }
+    }
+    return CTQR_OK;
+}
+
+template <typename T>
+ctqr_status trsm_upper_trans_cols(int n, int S, const T *R, int64_t ldr, const T *Rinv, T *C, int64_t ldc, T *Y,
+                                  int64_t ldy, int c_lo, int c_hi, T *part, size_t part_elems, const int *skip,
+                                  hipStream_t st)
+{
+    for (int r0 = c_lo; r0 < std::min(c_hi, n); r0 += BIG) {
+        const int bw = min(BIG, n - r0);
+        ctqr_status s;
+        if (r0 > 0) {
+            s = gemm_tn<T>(bw, S, r0, R + (int64_t)r0 * ldr, ldr, 0, Y, ldy, 0, T(-1), T(1), C + r0, ldc, part,
+                           part_elems, skip, st);
+            if (s) return s;
+        }
+        s = gemm_tn<T>(bw, S, bw, Rinv + (int64_t)r0 * BIG, BIG, 0, C + r0, ldc, 0, T(1), T(0), Y + r0, ldy,
+                       part, part_elems, skip, st);
+        if (s) return s;
+    }
+    return CTQR_OK;
+}
+
 #define INST(T)                                                                                        \
     template ctqr_status trinv_blocks<T>(int, const T *, int64_t, T *, T *, ctqr_info *, hipStream_t);  \
     template ctqr_status trinv_blocks_range<T>(int, int, int, const T *, int64_t, T *, T *, hipStream_t); \
@@ -348,6 +394,11 @@ ctqr_status trsm_upper_trans(int n, int S, const T *R, int64_t ldr, const T *Rin
     template ctqr_status trsm_upper<T>(int, int, const T *, int64_t, const T *, T *, int64_t, T *,       \
                                        int64_t, T *, size_t, const int *, hipStream_t);                 \
     template ctqr_status trsm_upper_trans<T>(int, int, const T *, int64_t, const T *, T *, int64_t,     \
-                                             T *, int64_t, T *, size_t, const int *, hipStream_t);
+                                             T *, int64_t, T *, size_t, const int *, hipStream_t);      \
+    template ctqr_status trsm_upper_cols<T>(int, int, const T *, int64_t, const T *, T *, int64_t, T *,  \
+                                            int64_t, int, int, T *, size_t, const int *, hipStream_t);  \
+    template ctqr_status trsm_upper_trans_cols<T>(int, int, const T *, int64_t, const T *, T *, int64_t, \
+                                                  T *, int64_t, int, int, T *, size_t, const int *,    \
+                                                  hipStream_t);
 INST(float)
 INST(double)

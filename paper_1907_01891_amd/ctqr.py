@@ -65,9 +65,14 @@ _SIGNATURES = {
     "ctqr_qr_workspace": (c_i32, [c_i64, c_i64, c_i32, c_i32, c_i32, _P(c_sz)]),
     "ctqr_qr_factor": (c_i32, [c_i64, c_i64, c_i32, c_vp, c_i64, c_i32, c_i32, c_vp, c_vp, c_vp,
                                c_vp, c_sz, c_vp, c_vp]),
+    "ctqr_sparse_to_dense": (c_i32, [_P(ctqr_sparse), c_i32, c_i64, c_i64, c_vp, c_i64, c_vp]),
     "ctqr_qr_factor_ooc_workspace": (c_i32, [c_i64, c_i64, c_i32, c_i32, c_i32, c_i64, c_i64, _P(c_sz)]),
     "ctqr_qr_factor_ooc": (c_i32, [c_i64, c_i64, c_i32, c_vp, c_vp, c_i64, c_i64, c_i64, c_i32, c_i32, c_vp, c_vp,
                                    c_vp, c_vp, c_sz, c_vp, c_vp]),
+    "ctqr_solve_ooc_workspace": (c_i32, [c_i64, c_i64, c_i32, c_i32, c_i32, c_i32, c_i64, c_i64, _P(c_sz)]),
+    "ctqr_qr_solve_ooc": (c_i32, [c_i64, c_i64, c_i32, c_vp, c_vp, c_i64, c_i64, c_i64, c_vp, c_vp, c_vp, c_i32,
+                                  c_vp, c_i64, c_i32, c_vp, c_i64, _P(ctqr_sparse), c_dbl, c_i32, c_vp, c_sz, c_vp,
+                                  c_vp]),
     "ctqr_qr_rinv_bytes": (c_i32, [c_i64, c_i32, _P(c_sz)]),
     "ctqr_solve_workspace": (c_i32, [c_i64, c_i64, c_i32, c_i32, c_i32, c_i32, _P(c_sz)]),
     "ctqr_qr_solve_slices": (c_i32, [c_i64, c_i64, c_i32, c_vp, c_i64, c_vp, c_vp, c_vp, c_i32,
@@ -160,6 +165,10 @@ def ctqr_qr_factor(m, n, dtype, A_ptr, lda, prec, nb, T_ptr, tau_ptr, rinv_ptr, 
                                 info_ptr, stream)
 
 
+def ctqr_sparse_to_dense(sparse, dtype, c0, c1, A_ptr, lda, stream):
+    return lib().ctqr_sparse_to_dense(ctypes.byref(sparse), dtype, c0, c1, A_ptr, lda, stream)
+
+
 def ctqr_qr_factor_ooc_workspace(m, n, dtype, prec, nb, lda, tile_cols):
     b = c_sz()
     check(lib().ctqr_qr_factor_ooc_workspace(m, n, dtype, prec, nb, lda, tile_cols, ctypes.byref(b)),
@@ -171,6 +180,20 @@ def ctqr_qr_factor_ooc(m, n, dtype, A_dev, A_host, lda, n_dev, tile_cols, prec, 
                        work_ptr, work_bytes, info_ptr, stream):
     return lib().ctqr_qr_factor_ooc(m, n, dtype, A_dev, A_host, lda, n_dev, tile_cols, prec, nb, T_ptr, tau_ptr,
                                     rinv_ptr, work_ptr, work_bytes, info_ptr, stream)
+
+
+def ctqr_solve_ooc_workspace(m, n, dtype, nb, nslices, refine, lda, tile_cols):
+    b = c_sz()
+    check(lib().ctqr_solve_ooc_workspace(m, n, dtype, nb, nslices, refine, lda, tile_cols, ctypes.byref(b)),
+          "ctqr_solve_ooc_workspace")
+    return b.value
+
+
+def ctqr_qr_solve_ooc(m, n, dtype, QR_dev, QR_host, lda, n_dev, tile_cols, T_ptr, tau_ptr, rinv_ptr, nb, B_ptr, ldb,
+                      nslices, X_ptr, ldx, sparse, tol, max_iters, work_ptr, work_bytes, info_ptr, stream):
+    return lib().ctqr_qr_solve_ooc(m, n, dtype, QR_dev, QR_host, lda, n_dev, tile_cols, T_ptr, tau_ptr, rinv_ptr, nb,
+                                   B_ptr, ldb, nslices, X_ptr, ldx, ctypes.byref(sparse) if sparse is not None else None,
+                                   tol, max_iters, work_ptr, work_bytes, info_ptr, stream)
 
 
 def ctqr_qr_rinv_bytes(n, dtype):

@@ -121,6 +121,12 @@ class SystemMatrix:
     def nnz(self):
         return int(self.info.read().nnz)
 
+    def dense_cols(self, c0, c1, out, dtype=C.CTQR_F32, stream=None):
+        """Columns [c0, c1) of the dense A into the column-major device tensor out."""
+        C.check(C.ctqr_sparse_to_dense(self.sp, dtype, c0, c1, ctypes.c_void_p(out.data_ptr()), ld_of(out),
+                                       stream_handle(stream)), "ctqr_sparse_to_dense")
+        return out
+
     def spmm(self, X, alpha=1.0, beta=0.0, Y=None, stream=None):
         """Y = alpha A X + beta Y (FP64, column-major), with the sparse copy."""
         S = X.shape[1]
@@ -211,6 +217,23 @@ class OocFactor:
                                      ptr(self.Rinv), wp, wb, self.info.ptr, stream_handle(stream)),
                 "ctqr_qr_factor_ooc")
         return self
+
+    def solve(self, B, X=None, sparse=None, tol=1e-13, max_iters=0, stream=None):
+        """X = R^-1 Q^T B with the out-of-core factor (ctqr_qr_solve_ooc)."""
+        S = B.shape[1]
+        if X is None:
+            X = colmajor(self.n, S, torch.float64, B.device)
+        refine = 1 if (sparse is not None and max_iters > 0) else 0
+        if not hasattr(self, "swork"):
+            self.swork, self.sinfo = Workspace(self.T.device), Info(self.T.device)
+        wp, wb = self.swork.get(C.ctqr_solve_ooc_workspace(self.m, self.n, self.dtype, self.nb, S, refine, self.lda,
+                                                           self.tile_cols))
+        ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
+        C.check(C.ctqr_qr_solve_ooc(self.m, self.n, self.dtype, ptr(self.A_dev), ptr(self.A_host), self.lda,
+                                    self.n_dev, self.tile_cols, ptr(self.T), ptr(self.tau), ptr(self.Rinv), self.nb,
+                                    ptr(B), ld_of(B), S, ptr(X), ld_of(X), sparse, tol, max_iters, wp, wb,
+                                    self.sinfo.ptr, stream_handle(stream)), "ctqr_qr_solve_ooc")
+        return X
 
     def factor_matrix(self):
         """The whole factored matrix as one host tensor (m x n, column-major)."""

@@ -76,3 +76,49 @@ def test_tall_fp32_panel_matches_oracle(gpu, oracle_lib):
     print("tall panel R rel err %.2e" % err)
     assert err <= 2e-5
     assert np.abs(F.tau.cpu().numpy() - tau_o).max() <= 1e-5
+
+
+def test_sparse_to_dense_matches_build(gpu):
+    from synthetic import get_workload
+    from paper_1907_01891_amd.device import SystemMatrix, colmajor
+    g = get_workload("ct32").geometry()
+    S = SystemMatrix(g, C.CTQR_F32, dense=True, sparse=True)
+    out = colmajor(S.m, S.n, torch.float32)
+    S.dense_cols(0, S.n, out, C.CTQR_F32)
+    part = colmajor(S.m, 600, torch.float32)
+    S.dense_cols(100, 700, part, C.CTQR_F32)
+    torch.cuda.synchronize()
+    assert torch.equal(out.cpu(), S.A.cpu())
+    assert torch.equal(part.cpu(), S.A[:, 100:700].cpu())
+
+
+@pytest.mark.parametrize("name,n_dev,dt", [("ct48", 0, "f64"), ("ct48", 0, "f32"), ("ct64", 2048, "f32")])
+def test_ooc_solve_matches_in_core_and_oracle(gpu, name, n_dev, dt):
+    from gpu_helpers import oracle_problem, oracle_factor, DeviceSparse
+    from oracle import lsq
+    g, A, X, B = oracle_problem(name, n_slices=40)
+    QRo, tauo = oracle_factor(name)
+    Xo = hh.backsub(QRo, hh.apply_qt(QRo, tauo, B))
+    m, n = A.shape
+    dtype = torch.float64 if dt == "f64" else torch.float32
+    cd = C.CTQR_F64 if dt == "f64" else C.CTQR_F32
+    prec = C.CTQR_PREC_FP64 if dt == "f64" else C.CTQR_PREC_FP32_MFMA
+    Ad = torch.as_tensor(A.toarray(), dtype=dtype)
+    F = QRFactor(to_colmajor(Ad, dtype=dtype), prec, nb=256).factor()
+    O = OocFactor(m, n, cd, prec, n_dev, 2048, nb=256)
+    O.load(to_colmajor(Ad, dtype=dtype, device="cpu"))
+    O.factor()
+    spA = DeviceSparse(A)
+    kw = {} if dt == "f64" else dict(sparse=spA.sp, tol=1e-14, max_iters=30)
+    for S in (4, 40):
+        _print_case("ooc solve", name, n_dev, dt, "S", S)
+        Bd = to_colmajor(torch.as_tensor(B[:, :S]), dtype=torch.float64)
+        Xg = O.solve(Bd, **kw).cpu().numpy()
+        Xi = F.solve(Bd, **kw).cpu().numpy()
+        torch.cuda.synchronize()
+        si = O.sinfo.read()
+        assert si.status == 0, (C.status_string(si.status), si.iters)
+        e_in, e_or = lsq.rel_err(Xg, Xi).max(), lsq.rel_err(Xg, Xo[:, :S]).max()
+        print("%s S %d vs in-core %.2e vs oracle %.2e iters %d" % (dt, S, e_in, e_or, si.iters))
+        assert e_or <= 1e-10
+        assert e_in <= (1e-12 if dt == "f64" else 1e-10)
