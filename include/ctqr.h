@@ -369,6 +369,20 @@ ctqr_status ctqr_spmm(const ctqr_sparse *A64, int32_t nslices, double alpha,
                       const double *X, int64_t ldx, double beta, double *Y, int64_t ldy,
                       hipStream_t stream);
 
+/* Progress of the long out-of-core calls.  When a hook is set,
+ * ctqr_qr_factor_ooc reports (CTQR_PROGRESS_FACTOR, columns factored, n)
+ * after every 8192 resident columns and after every host tile, and
+ * ctqr_qr_solve_ooc reports (CTQR_PROGRESS_SOLVE, iterations done, max_iters)
+ * after Q^T B and after each refinement iteration.  Each report is a host
+ * function enqueued on the call's stream (hipLaunchHostFunc), so it runs on a
+ * HIP runtime thread once the GPU has finished the work before it; the hook
+ * must return quickly and must not call HIP.  NULL removes the hook.  The
+ * hook is process-wide. */
+#define CTQR_PROGRESS_FACTOR 1
+#define CTQR_PROGRESS_SOLVE  2
+typedef void (*ctqr_progress_fn)(int32_t stage, int64_t done, int64_t total, void *user);
+ctqr_status ctqr_set_progress(ctqr_progress_fn fn, void *user);
+
 /* Kernel-level timing of the dominant kernel (the trailing-update GEMM
  * C -= V W of ctqr_qr_factor).  While enabled, every launch of it is
  * bracketed by HIP events on the stream it runs on; ctqr_profile_read returns

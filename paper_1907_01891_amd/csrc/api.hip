@@ -28,6 +28,48 @@ bool g_prof_on = false;
 std::vector<ProfRec> g_prof;
 
 bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+// Progress hook of the long out-of-core calls: a host function enqueued on
+// the stream, so it runs when the GPU has finished the work before it.
+std::mutex g_progress_mu;
+ctqr_progress_fn g_progress = nullptr;
+void *g_progress_user = nullptr;
+
+struct ProgressMsg {
+    ctqr_progress_fn fn;
+    void *user;
+    int32_t stage;
+    int64_t done, total;
+};
+
+void progress_trampoline(void *p)
+{
+    ProgressMsg *msg = static_cast<ProgressMsg *>(p);
+    msg->fn(msg->stage, msg->done, msg->total, msg->user);
+    delete msg;
+}
+
+ctqr_status progress_mark(hipStream_t st, int32_t stage, int64_t done, int64_t total)
+{
+    ctqr_progress_fn fn;
+    void *user;
+    {
+        std::lock_guard<std::mutex> lk(g_progress_mu);
+        fn = g_progress;
+        user = g_progress_user;
+    }
+    if (!fn) return CTQR_OK;
+    ProgressMsg *msg = new ProgressMsg{fn, user, stage, done, total};
+    hipError_t e = hipLaunchHostFunc(st, progress_trampoline, msg);
+    if (e != hipSuccess) {
+        delete msg;
+        ctqr_last_hip_error(e, "hipLaunchHostFunc", __FILE__, __LINE__);
+        return CTQR_EHIP;
+    }
+    return CTQR_OK;
+}
+
+
 int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
 
 // Bump allocator over the caller's workspace (256-byte aligned pieces).
@@ -338,8 +380,14 @@ ctqr_status factor_ooc_impl(int64_t m64, int64_t n64, T *A_dev, T *A_host, int64
     if ((s = info_reset(info, st))) return s;
     if ((s = fill_u32(w.bars, (ceil_div(n, PANEL_W) + 1) * GB_WORDS, 0u, st))) return s;
     if (n_dev > 0) {
-        if ((s = factor_blocks<T>(m, n, A_dev, lda, nb, 0, n_dev, n_dev, Tout, tau, w, w.bars, info, ncu, st)))
-            return s;
+        // in pieces of 8192 columns (the same arithmetic as one call), each
+        // followed by a progress mark
+        for (int k0 = 0; k0 < n_dev; k0 += 8192) {
+            const int k1 = std::min(n_dev, k0 + 8192);
+            if ((s = factor_blocks<T>(m, n, A_dev, lda, nb, k0, k1, n_dev, Tout, tau, w, w.bars, info, ncu, st)))
+                return s;
+            if ((s = progress_mark(st, CTQR_PROGRESS_FACTOR, k1, n))) return s;
+        }
         if ((s = diag_copy<T>(0, n_dev, A_dev, lda, o.diag, st))) return s;
         if (Rinv && (s = trinv_blocks_range<T>(n, 0, n_dev, A_dev, lda, Rinv, w.rtmp, st))) return s;
     }
@@ -361,6 +409,7 @@ ctqr_status factor_ooc_impl(int64_t m64, int64_t n64, T *A_dev, T *A_host, int64
         if (Rinv && (s = trinv_blocks_range<T>(n, c0, c1, Dv, lda, Rinv, w.rtmp, st))) return s;
         HIP_TRY(hipMemcpyAsync(A_host + (int64_t)(c0 - n_dev) * lda, o.D, (size_t)(c1 - c0) * col_bytes,
                                hipMemcpyDeviceToHost, st));
+        if ((s = progress_mark(st, CTQR_PROGRESS_FACTOR, c1, n))) return s;
     }
     // rank check over the diagonal collected above (stride 0: diag[k])
     return rdiag_check<T>(n, o.diag, 0, nullptr, info, st);
@@ -642,6 +691,7 @@ ctqr_status solve_ooc_impl(int64_t m64, int64_t n64, const T *QR_dev, const T *Q
         if ((s = tc.get(c0, st, &Vv))) return s;
         if ((s = apply_qt_range(r, Vv, c0, std::min(n, c0 + tile), st))) return s;
     }
+    if ((s = progress_mark(st, CTQR_PROGRESS_SOLVE, 0, max_iters))) return s;
     // R X = (Q^T B)[0:n], substituting in the working copy
     if ((s = ooc_upper(r, tc, QR_dev, w.Bw, w.ldbw, w.Xw, w.ldxw, nullptr, st))) return s;
     if (!r.refine()) return copy_cm<double, T>(n, S, w.Xw, w.ldxw, X, ldx, st);
@@ -661,6 +711,7 @@ ctqr_status solve_ooc_impl(int64_t m64, int64_t n64, const T *QR_dev, const T *Q
         if ((s = ooc_upper(r, tc, QR_dev, w.y32, w.ldxw, w.d32, w.ldxw, skip, st))) return s;
         if ((s = refine_update<T>(n, S, w.xr, w.d32, w.ldxw, w.dmax, w.xmax, skip, st))) return s;
         if ((s = refine_check(S, w.dmax, w.xmax, tol, it, max_iters, w.hist, w.done, info, st))) return s;
+        if ((s = progress_mark(st, CTQR_PROGRESS_SOLVE, it + 1, max_iters))) return s;
         bool done = false;
         if ((s = read_done(w.done, st, done))) return s;
         if (done) break;
@@ -1353,6 +1404,14 @@ ctqr_status ctqr_spmm(const ctqr_sparse *A64, int32_t nslices, double alpha, con
     if (ldx < A64->n || ldy < A64->m) return CTQR_EINVAL;
     return spmm_colmajor(A64->m, A64->n, nslices, A64->rowptr, A64->col, A64->val, alpha, X, ldx, beta, Y,
                          ldy, stream);
+}
+
+ctqr_status ctqr_set_progress(ctqr_progress_fn fn, void *user)
+{
+    std::lock_guard<std::mutex> lk(g_progress_mu);
+    g_progress = fn;
+    g_progress_user = user;
+    return CTQR_OK;
 }
 
 ctqr_status ctqr_profile_enable(int32_t on)

@@ -53,6 +53,10 @@ class ctqr_solver_desc(ctypes.Structure):
                 ("tol", c_dbl), ("max_iters", c_i32), ("max_slices", c_i32)]
 
 
+CTQR_PROGRESS_FACTOR = 1
+CTQR_PROGRESS_SOLVE = 2
+ctqr_progress_fn = ctypes.CFUNCTYPE(None, c_i32, c_i64, c_i64, c_vp)
+
 _P = ctypes.POINTER
 _SIGNATURES = {
     "ctqr_status_string": (ctypes.c_char_p, [c_i32]),
@@ -87,6 +91,7 @@ _SIGNATURES = {
     "ctqr_solver_query": (c_i32, [c_vp, c_i32, _P(c_i32), _P(c_i32), _P(c_i32)]),
     "ctqr_solver_destroy": (c_i32, [c_vp]),
     "ctqr_spmm": (c_i32, [_P(ctqr_sparse), c_i32, c_dbl, c_vp, c_i64, c_dbl, c_vp, c_i64, c_vp]),
+    "ctqr_set_progress": (c_i32, [ctqr_progress_fn, c_vp]),
     "ctqr_profile_enable": (c_i32, [c_i32]),
     "ctqr_profile_read": (c_i32, [_P(c_i64), _P(c_dbl), _P(c_dbl)]),
 }
@@ -254,6 +259,17 @@ def ctqr_solver_destroy(solver):
 
 def ctqr_spmm(sparse, nslices, alpha, X_ptr, ldx, beta, Y_ptr, ldy, stream):
     return lib().ctqr_spmm(ctypes.byref(sparse), nslices, alpha, X_ptr, ldx, beta, Y_ptr, ldy, stream)
+
+
+_progress_keep = None
+
+
+def ctqr_set_progress(fn):
+    """Install a Python hook fn(stage, done, total) (None removes it)."""
+    global _progress_keep
+    cb = ctqr_progress_fn(lambda st, d, t, u: fn(st, d, t)) if fn is not None else ctqr_progress_fn()
+    _progress_keep = cb
+    return lib().ctqr_set_progress(cb, None)
 
 
 def ctqr_profile_enable(on):

@@ -193,8 +193,9 @@ class OocFactor:
         self.lda = round_up(m, 64)
         self.n_dev, self.tile_cols = n_dev, tile_cols
         self.A_dev = colmajor(m, n_dev, tdt, device, ld=self.lda) if n_dev > 0 else None
-        self.A_host = (torch.empty((n - n_dev, self.lda), dtype=tdt, pin_memory=True).t()[:m, :]
-                       if n_dev < n else None)
+        # host part: pinned (hipHostMalloc) rows of lda elements, one per column
+        self.host_base = torch.empty((n - n_dev, self.lda), dtype=tdt, pin_memory=True) if n_dev < n else None
+        self.A_host = self.host_base.t()[:m, :] if n_dev < n else None
         self.T = colmajor(self.nb, n, tdt, device, ld=self.nb)
         self.tau = torch.zeros(n, dtype=torch.float64, device=device)
         self.Rinv = torch.empty(C.ctqr_qr_rinv_bytes(n, dtype) // self.T.element_size(), dtype=tdt, device=device)
