@@ -433,7 +433,7 @@ void splitk_reduce_kernel(int M, int N, int splits, const T *__restrict__ part,
 // ---------------------------------------------------------------------------
 // KIND only separates the symbols of the launch sites in a profile: 1 is the
 // trailing update of the factorization, 0 every other use.
-template <typename T, int KIND, int TW>
+template <typename T, int KIND, int TW, bool SPLIT>
 __global__ __launch_bounds__(NTHR, 2)
 void gemm_nn_kernel(int M, int N, int K,
                     const T *__restrict__ A, int64_t lda, int amask,
@@ -442,8 +442,9 @@ void gemm_nn_kernel(int M, int N, int K,
                     T *__restrict__ part, int kchunk, const int *skip)
 {
     // accum != 0: C += alpha A B;  accum == 0: C = alpha A B (C is not read).
-    // With gridDim.z > 1 split z covers k in [z kchunk, (z+1) kchunk) and
-    // writes its raw product to part (reduced by splitk_reduce_kernel).
+    // SPLIT: split blockIdx.z covers k in [z kchunk, (z+1) kchunk) and writes
+    // its raw product to part (reduced by splitk_reduce_kernel).  A
+    // compile-time switch: the unsplit kernels carry none of its registers.
     using Mt = Mf<T>;
     using W = WaveTile<T, TW>;
     if (skip && *skip) return;
@@ -464,10 +465,12 @@ void gemm_nn_kernel(int M, int N, int K,
 #pragma unroll
             for (int e = 0; e < acc_len<T>(); ++e) acc[i][j][e] = T(0);
 
-    const bool split = gridDim.z > 1;
-    const int kbeg = blockIdx.z * kchunk;
-    const int kend = min(K, kbeg + kchunk);
-    if (split) accum = 0;
+    constexpr bool split = SPLIT;
+    const int kbeg = SPLIT ? (int)blockIdx.z * kchunk : 0;
+    const int kend = SPLIT ? min(K, kbeg + kchunk) : K;
+    if (SPLIT) accum = 0;
+    (void)part;
+    (void)kchunk;
 
     // FP32: fetch the C tile now; its HBM latency hides behind the K loop
     constexpr bool PRE = sizeof(T) == 4;
@@ -521,7 +524,7 @@ void gemm_nn_kernel(int M, int N, int K,
                 n += n0 + wn;
                 m += m0 + wm;
                 if (m < M && n < N) {
-                    if (split) {
+                    if constexpr (split) {
                         part[((int64_t)blockIdx.z * N + n) * M + m] = acc[ib][jb][r];
                         continue;
                     }
@@ -645,14 +648,14 @@ ctqr_status gemm_nn(int M, int N, int K, const T *A, int64_t lda, int amask, con
     const int kchunk = K > 0 ? K : 1;
     dim3 grid((unsigned)(ceil_div(M, TILE) * ceil_div(N, narrow ? NARROW : TILE)));
     if (kind == 1)
-        LAUNCH_TRY((gemm_nn_kernel<T, 1, TILE>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B, ldb,
-                   alpha, C, ldc, accum, (T *)nullptr, kchunk, skip);
+        LAUNCH_TRY((gemm_nn_kernel<T, 1, TILE, false>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B,
+                   ldb, alpha, C, ldc, accum, (T *)nullptr, kchunk, skip);
     else if (narrow)
-        LAUNCH_TRY((gemm_nn_kernel<T, 0, NARROW>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B, ldb,
-                   alpha, C, ldc, accum, (T *)nullptr, kchunk, skip);
+        LAUNCH_TRY((gemm_nn_kernel<T, 0, NARROW, false>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B,
+                   ldb, alpha, C, ldc, accum, (T *)nullptr, kchunk, skip);
     else
-        LAUNCH_TRY((gemm_nn_kernel<T, 0, TILE>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B, ldb,
-                   alpha, C, ldc, accum, (T *)nullptr, kchunk, skip);
+        LAUNCH_TRY((gemm_nn_kernel<T, 0, TILE, false>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B,
+                   ldb, alpha, C, ldc, accum, (T *)nullptr, kchunk, skip);
     return CTQR_OK;
 }
 
@@ -669,11 +672,11 @@ ctqr_status gemm_nn_split(int M, int N, int K, const T *A, int64_t lda, const T 
     splits = (int)ceil_div(K, kchunk);
     dim3 grid((unsigned)(ceil_div(M, TILE) * ceil_div(N, narrow ? NARROW : TILE)), 1, (unsigned)splits);
     if (narrow)
-        LAUNCH_TRY((gemm_nn_kernel<T, 0, NARROW>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, 0, B, ldb, alpha,
-                   C, ldc, 0, part, kchunk, skip);
+        LAUNCH_TRY((gemm_nn_kernel<T, 0, NARROW, true>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, 0, B, ldb,
+                   alpha, C, ldc, 0, part, kchunk, skip);
     else
-        LAUNCH_TRY((gemm_nn_kernel<T, 0, TILE>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, 0, B, ldb, alpha,
-                   C, ldc, 0, part, kchunk, skip);
+        LAUNCH_TRY((gemm_nn_kernel<T, 0, TILE, true>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, 0, B, ldb,
+                   alpha, C, ldc, 0, part, kchunk, skip);
     return splitk_reduce<T>(M, N, splits, part, alpha, T(1), C, ldc, skip, st);
 }
 
