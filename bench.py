@@ -53,6 +53,7 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--no-stream", action="store_true", help="skip the batched request-stream leg")
+    p.add_argument("--no-bf16", action="store_true", help="skip the BF16-MFMA factorization leg")
     p.add_argument("--ooc", action="store_true",
                    help="out-of-core factorization (default for workloads whose dense FP32 A exceeds HBM)")
     p.add_argument("--ooc-tile", type=int, default=8192, help="columns per streamed host tile")
@@ -454,6 +455,33 @@ def main():
     if not args.no_stream and args.workload == "ct256":
         stream_out = request_stream_bench(args, log, F, sp, B)
         torch.cuda.empty_cache()
+    bf16 = {}
+    if not args.no_bf16:
+        # BF16 MFMA for the block-column products of the same factorization;
+        # its error is reported against the refined mixed solution
+        build_dense(A32, C.CTQR_F32)
+        F16 = QRFactor(A32, C.CTQR_PREC_BF16_MFMA, nb=args.nb)
+        torch.cuda.synchronize()
+        e0, e1 = ev(), ev()
+        e0.record()
+        F16.factor()
+        e1.record()
+        torch.cuda.synchronize()
+        t16 = e0.elapsed_time(e1)
+        Xu = F16.solve(B)
+        torch.cuda.synchronize()
+        e_unref = ((Xu - Xmixed).norm(dim=0) / Xmixed.norm(dim=0)).max().item()
+        Xr = F16.solve(B, sparse=sp.sp, tol=args.tol, max_iters=args.max_iters)
+        torch.cuda.synchronize()
+        si16 = F16.sinfo.read()
+        e_ref = ((Xr - Xmixed).norm(dim=0) / Xmixed.norm(dim=0)).max().item()
+        bf16 = {"bf16_qr_tflops": qr_flops(m, n) / (t16 * 1e-3) / 1e12, "bf16_qr_ms": t16,
+                "bf16_unrefined_rel_err_vs_mixed": e_unref, "bf16_refined_rel_err_vs_mixed": e_ref,
+                "bf16_refine_status": int(si16.status), "bf16_refine_iters": int(si16.iters),
+                "bf16_qr_info_status": int(F16.info.read().status)}
+        log("bf16: qr %.2f TFLOP/s (%.0f ms); error vs mixed: unrefined %.2e, refined %.2e (status %d, %d iters)"
+            % (bf16["bf16_qr_tflops"], t16, e_unref, e_ref, si16.status, si16.iters))
+        del F16, Xu, Xr
     del A32, F
     torch.cuda.empty_cache()
 
@@ -545,6 +573,7 @@ def main():
         "wall_s_timed": wall,
     }
     out.update(fp64)
+    out.update(bf16)
     print(json.dumps(out))
 
 

@@ -93,6 +93,7 @@ struct FactorWS {
     double *part, *part2, *gram_part, *gram, *Tw;
     T *Tin, *GW, *W2, *split, *rtmp;
     size_t bytes;
+    bool bf16 = false;   // block-column GEMMs ([G | W] and the trailing update) on BF16 MFMA
 };
 
 template <typename T>
@@ -193,7 +194,7 @@ ctqr_status ensure_setup()
 // Profiled launch of the trailing update C -= V W' (the dominant kernel).
 template <typename T>
 ctqr_status trailing_update(int mk, int nc, int nbk, const T *V, int64_t lda, const T *W2, int nb, T *C,
-                            hipStream_t st)
+                            hipStream_t st, bool bf16)
 {
     bool prof;
     {
@@ -206,7 +207,7 @@ ctqr_status trailing_update(int mk, int nc, int nbk, const T *V, int64_t lda, co
         HIP_TRY(hipEventCreate(&rec.b));
         HIP_TRY(hipEventRecord(rec.a, st));
     }
-    ctqr_status s = gemm_nn<T>(mk, nc, nbk, V, lda, 1, W2, nb, T(-1), C, lda, nullptr, st, 1);
+    ctqr_status s = gemm_nn<T>(mk, nc, nbk, V, lda, 1, W2, nb, T(-1), C, lda, nullptr, st, 1, 1, bf16);
     if (s) return s;
     if (prof) {
         HIP_TRY(hipEventRecord(rec.b, st));
@@ -268,7 +269,7 @@ ctqr_status factor_blocks(int m, int n, T *A, int64_t lda, int nb, int kb, int k
         const int nc = std::max(0, ce - (k0 + nbk));
         const T *V = A + (int64_t)k0 * lda + k0;
         s = gemm_tn<T>(nbk, nbk + nc, m - k0, V, lda, nbk, V, lda, nbk, T(1), T(0), w.GW, nb, w.split,
-                       SPLIT_PART_ELEMS, nullptr, st, sp.gw);
+                       SPLIT_PART_ELEMS, nullptr, st, sp.gw, w.bf16);
         if (s) return s;
         T *Tk = Tout + (int64_t)k0 * nb;
         if ((s = tbuild<T, T>(nbk, w.GW, nb, tau + k0, Tk, nb, w.Tw, st))) return s;
@@ -277,7 +278,8 @@ ctqr_status factor_blocks(int m, int n, T *A, int64_t lda, int nb, int kb, int k
         s = gemm_tn<T>(nbk, nc, nbk, Tk, nb, 0, w.GW + (int64_t)nbk * nb, nb, 0, T(1), T(0), w.W2, nb,
                        w.split, SPLIT_PART_ELEMS, nullptr, st, sp.tw);
         if (s) return s;
-        if ((s = trailing_update<T>(m - k0, nc, nbk, V, lda, w.W2, nb, A + (int64_t)(k0 + nbk) * lda + k0, st)))
+        if ((s = trailing_update<T>(m - k0, nc, nbk, V, lda, w.W2, nb, A + (int64_t)(k0 + nbk) * lda + k0, st,
+                                    w.bf16)))
             return s;
     }
     return CTQR_OK;
@@ -302,22 +304,23 @@ ctqr_status apply_blocks(int m, int n, const T *V, int64_t lda, const T *Tf, int
         T *Ck = C + (int64_t)c0 * lda + k0;
         // the in-HBM call forms [G | W] at once: its split count applies
         s = gemm_tn<T>(nbk, nc, m - k0, Vk, lda, nbk, Ck, lda, 0, T(1), T(0), w.GW, nb, w.split,
-                       SPLIT_PART_ELEMS, nullptr, st, sp.gw);
+                       SPLIT_PART_ELEMS, nullptr, st, sp.gw, w.bf16);
         if (s) return s;
         s = gemm_tn<T>(nbk, nc, nbk, Tf + (int64_t)k0 * nb, nb, 0, w.GW, nb, 0, T(1), T(0), w.W2, nb, w.split,
                        SPLIT_PART_ELEMS, nullptr, st, sp.tw);
         if (s) return s;
-        if ((s = trailing_update<T>(m - k0, nc, nbk, Vk, lda, w.W2, nb, Ck, st))) return s;
+        if ((s = trailing_update<T>(m - k0, nc, nbk, Vk, lda, w.W2, nb, Ck, st, w.bf16))) return s;
     }
     return CTQR_OK;
 }
 
 template <typename T>
 ctqr_status factor_impl(int64_t m64, int64_t n64, T *A, int64_t lda, int nb, T *Tout, double *tau, T *Rinv,
-                        void *work, ctqr_info *info, hipStream_t st)
+                        void *work, ctqr_info *info, hipStream_t st, bool bf16)
 {
     const int m = (int)m64, n = (int)n64;
     FactorWS<T> w = carve_factor<T>(work, m64, n64, nb);
+    w.bf16 = bf16;
     const int ncu = std::min(device_cus(), MAX_PANEL_WG);
     ctqr_status s;
     if ((s = info_reset(info, st))) return s;
@@ -369,11 +372,12 @@ OocWS<T> carve_ooc(void *work, int64_t m, int64_t n, int nb, int64_t lda, int64_
 template <typename T>
 ctqr_status factor_ooc_impl(int64_t m64, int64_t n64, T *A_dev, T *A_host, int64_t lda, int64_t n_dev64,
                             int64_t tile64, int nb, T *Tout, double *tau, T *Rinv, void *work, ctqr_info *info,
-                            hipStream_t st)
+                            hipStream_t st, bool bf16)
 {
     const int m = (int)m64, n = (int)n64, n_dev = (int)n_dev64, tile = (int)tile64;
     OocWS<T> o = carve_ooc<T>(work, m64, n64, nb, lda, tile64);
     FactorWS<T> &w = o.f;
+    w.bf16 = bf16;
     const int ncu = std::min(device_cus(), MAX_PANEL_WG);
     const size_t col_bytes = (size_t)lda * sizeof(T);
     ctqr_status s;
@@ -959,7 +963,7 @@ bool geometry_ok(const ctqr_geometry *g)
 bool prec_ok(ctqr_dtype dtype, ctqr_prec prec)
 {
     if (dtype == CTQR_F64) return prec == CTQR_PREC_FP64;
-    if (dtype == CTQR_F32) return prec == CTQR_PREC_FP32_MFMA;
+    if (dtype == CTQR_F32) return prec == CTQR_PREC_FP32_MFMA || prec == CTQR_PREC_BF16_MFMA;
     return false;
 }
 
@@ -1051,7 +1055,7 @@ ctqr_status ctqr_qr_workspace(int64_t m, int64_t n, ctqr_dtype dtype, ctqr_prec 
                               size_t *bytes)
 {
     if (!bytes || m < n || n < 1 || m >= INT32_MAX) return CTQR_EINVAL;
-    if (!prec_ok(dtype, prec)) return (dtype == CTQR_F32 && prec == CTQR_PREC_BF16_MFMA) ? CTQR_EUNSUPPORTED : CTQR_EINVAL;
+    if (!prec_ok(dtype, prec)) return CTQR_EINVAL;
     nb = resolve_nb(nb);
     if (!nb_ok(nb)) return CTQR_EINVAL;
     *bytes = dtype == CTQR_F64 ? carve_factor<double>(nullptr, m, n, nb).bytes
@@ -1072,7 +1076,7 @@ ctqr_status ctqr_qr_factor_ooc_workspace(int64_t m, int64_t n, ctqr_dtype dtype,
                                          int64_t lda, int64_t tile_cols, size_t *bytes)
 {
     if (!bytes || m < n || n < 1 || m >= INT32_MAX || lda < m || tile_cols < 1) return CTQR_EINVAL;
-    if (!prec_ok(dtype, prec)) return (dtype == CTQR_F32 && prec == CTQR_PREC_BF16_MFMA) ? CTQR_EUNSUPPORTED : CTQR_EINVAL;
+    if (!prec_ok(dtype, prec)) return CTQR_EINVAL;
     nb = resolve_nb(nb);
     if (!nb_ok(nb)) return CTQR_EINVAL;
     *bytes = dtype == CTQR_F64 ? carve_ooc<double>(nullptr, m, n, nb, lda, tile_cols).bytes
@@ -1089,7 +1093,7 @@ ctqr_status ctqr_qr_factor_ooc(int64_t m, int64_t n, ctqr_dtype dtype, void *A_d
         if (lda < m || lda % 4 != 0 || !aligned16(T) || !aligned16(work)) return CTQR_EINVAL;
         if (Rinv && !aligned16(Rinv)) return CTQR_EINVAL;
         if (!prec_ok(dtype, prec))
-            return (dtype == CTQR_F32 && prec == CTQR_PREC_BF16_MFMA) ? CTQR_EUNSUPPORTED : CTQR_EINVAL;
+            return CTQR_EINVAL;
         nb = resolve_nb(nb);
         if (!nb_ok(nb)) return CTQR_EINVAL;
         // block boundaries: resident part and tiles are whole 2048-column
@@ -1115,9 +1119,9 @@ ctqr_status ctqr_qr_factor_ooc(int64_t m, int64_t n, ctqr_dtype dtype, void *A_d
         if (s) return s;
         if (dtype == CTQR_F64)
             return factor_ooc_impl<double>(m, n, (double *)A_dev, (double *)A_host, lda, n_dev, tile_cols, nb,
-                                           (double *)T, tau, (double *)Rinv, work, info, stream);
+                                           (double *)T, tau, (double *)Rinv, work, info, stream, false);
         return factor_ooc_impl<float>(m, n, (float *)A_dev, (float *)A_host, lda, n_dev, tile_cols, nb, (float *)T,
-                                      tau, (float *)Rinv, work, info, stream);
+                                      tau, (float *)Rinv, work, info, stream, prec == CTQR_PREC_BF16_MFMA);
     } catch (...) {
         return CTQR_EHIP;
     }
@@ -1139,7 +1143,7 @@ ctqr_status ctqr_qr_factor(int64_t m, int64_t n, ctqr_dtype dtype, void *A, int6
         if (lda < m || lda % 4 != 0 || !aligned16(A) || !aligned16(T)) return CTQR_EINVAL;
         if (Rinv && !aligned16(Rinv)) return CTQR_EINVAL;
         if (!prec_ok(dtype, prec))
-            return (dtype == CTQR_F32 && prec == CTQR_PREC_BF16_MFMA) ? CTQR_EUNSUPPORTED : CTQR_EINVAL;
+            return CTQR_EINVAL;
         nb = resolve_nb(nb);
         if (!nb_ok(nb)) return CTQR_EINVAL;
         size_t need = 0;
@@ -1150,8 +1154,9 @@ ctqr_status ctqr_qr_factor(int64_t m, int64_t n, ctqr_dtype dtype, void *A, int6
         if (s) return s;
         if (dtype == CTQR_F64)
             return factor_impl<double>(m, n, (double *)A, lda, nb, (double *)T, tau, (double *)Rinv, work, info,
-                                       stream);
-        return factor_impl<float>(m, n, (float *)A, lda, nb, (float *)T, tau, (float *)Rinv, work, info, stream);
+                                       stream, false);
+        return factor_impl<float>(m, n, (float *)A, lda, nb, (float *)T, tau, (float *)Rinv, work, info, stream,
+                                  prec == CTQR_PREC_BF16_MFMA);
     } catch (...) {
         return CTQR_EHIP;
     }

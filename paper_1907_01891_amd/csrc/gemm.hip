@@ -31,6 +31,8 @@
 // MFMAs is permuted (k = 4*slot + s) so each lane fetches 4 consecutive k
 // values with one LDS read; the sum over k is unchanged.  Workgroup ids are
 // remapped so the tiles one XCD runs are neighbours (shared L2 lines).
+#include <type_traits>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -100,6 +102,8 @@ template <typename T> struct Vec16;
 template <> struct Vec16<float> { using type = floatx4; };
 template <> struct Vec16<double> { using type = doublex2; };
 template <typename T> using vec16_t = typename Vec16<T>::type;
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 // Loads are issued unconditionally (an out-of-range chunk reads the operand's
 // first chunk instead), so every load of a stage is in flight at once; the
@@ -139,22 +143,47 @@ struct KcTile {
             r[q] = *reinterpret_cast<const vec16_t<T> *>(p);
         }
     }
+    // register chunk q with the bounds and the Householder structure applied;
+    // c, h: its column and chunk within the tile
+    __device__ inline vec16_t<T> masked(int q, int &c, int &h) const
+    {
+        int f = threadIdx.x + NTHR * q;
+        c = f / CPC;
+        h = f % CPC;
+        int col = col0_ + c, k = k0_ + h * E;
+        vec16_t<T> v = r[q];
+        if (col >= ncols_ || k + E > kmax_ || (col < mask_ && k <= col)) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                T x = (col < ncols_ && k + e < kmax_) ? v[e] : T(0);
+                v[e] = col < mask_ ? vmask(x, k + e, col) : x;
+            }
+        }
+        return v;
+    }
     __device__ inline void store(T *lds) const
     {
 #pragma unroll
         for (int q = 0; q < PER_THR; ++q) {
-            int f = threadIdx.x + NTHR * q;
-            int c = f / CPC, h = f % CPC;
-            int col = col0_ + c, k = k0_ + h * E;
-            vec16_t<T> v = r[q];
-            if (col >= ncols_ || k + E > kmax_ || (col < mask_ && k <= col)) {
-#pragma unroll
-                for (int e = 0; e < E; ++e) {
-                    T x = (col < ncols_ && k + e < kmax_) ? v[e] : T(0);
-                    v[e] = col < mask_ ? vmask(x, k + e, col) : x;
-                }
-            }
+            int c, h;
+            vec16_t<T> v = masked(q, c, h);
             *reinterpret_cast<vec16_t<T> *>(lds + c * LD + h * E) = v;
+        }
+    }
+    // BF16 staging (FP32 operands): the same values rounded to bf16 (nearest
+    // even), [col][k] layout with row stride LDB
+    static constexpr int LDB = BK + 8;
+    __device__ inline void store_bf(__bf16 *lds) const
+    {
+        static_assert(sizeof(T) == 4, "bf16 staging of FP32 operands only");
+#pragma unroll
+        for (int q = 0; q < PER_THR; ++q) {
+            int c, h;
+            vec16_t<T> v = masked(q, c, h);
+            bf16x4 o;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) o[e] = (__bf16)v[e];
+            *reinterpret_cast<bf16x4 *>(lds + c * LDB + h * E) = o;
         }
     }
 };
@@ -187,22 +216,43 @@ struct MkTile {
             r[q] = *reinterpret_cast<const vec16_t<T> *>(p);
         }
     }
+    __device__ inline vec16_t<T> masked(int q, int &kk, int &h) const
+    {
+        int f = threadIdx.x + NTHR * q;
+        kk = f / CPC;
+        h = f % CPC;
+        int k = k0_ + kk, row = row0_ + h * E;
+        vec16_t<T> v = r[q];
+        if (k >= kmax_ || row + E > mrows_ || (mask_ && row <= k)) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                T x = (k < kmax_ && row + e < mrows_) ? v[e] : T(0);
+                v[e] = mask_ ? vmask(x, row + e, k) : x;
+            }
+        }
+        return v;
+    }
     __device__ inline void store(T *lds) const
     {
 #pragma unroll
         for (int q = 0; q < PER_THR; ++q) {
-            int f = threadIdx.x + NTHR * q;
-            int kk = f / CPC, h = f % CPC;
-            int k = k0_ + kk, row = row0_ + h * E;
-            vec16_t<T> v = r[q];
-            if (k >= kmax_ || row + E > mrows_ || (mask_ && row <= k)) {
-#pragma unroll
-                for (int e = 0; e < E; ++e) {
-                    T x = (k < kmax_ && row + e < mrows_) ? v[e] : T(0);
-                    v[e] = mask_ ? vmask(x, row + e, k) : x;
-                }
-            }
+            int kk, h;
+            vec16_t<T> v = masked(q, kk, h);
             *reinterpret_cast<vec16_t<T> *>(lds + kk * LD + h * E) = v;
+        }
+    }
+    // BF16 staging, transposed to the [row][k] layout (k contiguous, row
+    // stride LDB) so both MFMA operands are read as 8 consecutive k
+    static constexpr int LDB = BK + 8;
+    __device__ inline void store_bf_t(__bf16 *lds) const
+    {
+        static_assert(sizeof(T) == 4, "bf16 staging of FP32 operands only");
+#pragma unroll
+        for (int q = 0; q < PER_THR; ++q) {
+            int kk, h;
+            vec16_t<T> v = masked(q, kk, h);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) lds[(h * E + e) * LDB + kk] = (__bf16)v[e];
         }
     }
 };
@@ -283,6 +333,35 @@ __device__ inline void mfma_step(const T *opA, const T *opB, int wn, int wm,
     }
 }
 
+// One BK-deep step of a wave's MFMA accumulation from bf16 LDS tiles (both
+// [col][k], row stride LDB): v_mfma_f32_32x32x16_bf16, FP32 accumulation.
+// Each lane feeds 8 consecutive k of its row (k = 16 g + 8 slot + e) to both
+// operands, so the sum covers every k once.
+template <int NI, int NJ>
+__device__ inline void mfma_step_bf(const __bf16 *opA, const __bf16 *opB, int wn, int wm,
+                                    floatx16 (&acc)[NI][NJ])
+{
+    constexpr int LDB = KcTile<float>::LDB;
+    const int lane = threadIdx.x % CTQR_WAVE;
+    const int li = lane % 32, slot = lane / 32;
+#pragma unroll
+    for (int g = 0; g < Mf<float>::BK / 16; ++g) {
+        const int kk = 16 * g + 8 * slot;
+        bf16x8 a[NI], b[NJ];
+#pragma unroll
+        for (int ib = 0; ib < NI; ++ib)
+            a[ib] = *reinterpret_cast<const bf16x8 *>(opA + (wn + ib * 32 + li) * LDB + kk);
+#pragma unroll
+        for (int jb = 0; jb < NJ; ++jb)
+            b[jb] = *reinterpret_cast<const bf16x8 *>(opB + (wm + jb * 32 + li) * LDB + kk);
+#pragma unroll
+        for (int ib = 0; ib < NI; ++ib)
+#pragma unroll
+            for (int jb = 0; jb < NJ; ++jb)
+                acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[ib], b[jb], acc[ib][jb], 0, 0, 0);
+    }
+}
+
 // Output coordinates of accumulator element r of block (ib, jb) for this lane:
 // output column (n) and row (m) offsets inside the wave's 64x64 sub-tile.
 template <typename T>
@@ -318,7 +397,7 @@ struct WaveTile {
 // ---------------------------------------------------------------------------
 // TN:  Out = alpha * A^T B + beta * Out   (or split-K partials)
 // ---------------------------------------------------------------------------
-template <typename T, int TW>
+template <typename T, int TW, bool BF>
 __global__ __launch_bounds__(NTHR, 2)
 void gemm_tn_kernel(int M, int N, int K,
                     const T *__restrict__ A, int64_t lda, int amask,
@@ -329,8 +408,12 @@ void gemm_tn_kernel(int M, int N, int K,
     using Mt = Mf<T>;
     using W = WaveTile<T, TW>;
     if (skip && *skip) return;
-    __shared__ __attribute__((aligned(16))) T sA[2][TILE * KcTile<T>::LD];
-    __shared__ __attribute__((aligned(16))) T sB[2][TW * KcTile<T>::LD];
+    // BF: FP32 operands staged as bf16 (BF16 MFMA, FP32 accumulation)
+    static_assert(!BF || (sizeof(T) == 4 && TW == TILE), "bf16 path: FP32, 128-wide tiles");
+    using LT = typename std::conditional<BF, __bf16, T>::type;
+    constexpr int LDX = BF ? KcTile<T>::LDB : KcTile<T>::LD;
+    __shared__ __attribute__((aligned(16))) LT sA[2][TILE * LDX];
+    __shared__ __attribute__((aligned(16))) LT sB[2][TW * LDX];
 
     int tm, tn;
     tile_of_block((M + TILE - 1) / TILE, (N + TW - 1) / TW, tm, tn);
@@ -350,11 +433,19 @@ void gemm_tn_kernel(int M, int N, int K,
 
     KcTile<T> la;
     KcTile<T, TW> lb;
+    auto stage = [](const KcTile<T> &a, const KcTile<T, TW> &b, LT *da, LT *db) {
+        if constexpr (BF) {
+            a.store_bf(da);
+            b.store_bf(db);
+        } else {
+            a.store(da);
+            b.store(db);
+        }
+    };
     if (kbeg < kend) {
         la.load(A, lda, M, m0, kbeg, kend, amask);
         lb.load(B, ldb, N, n0, kbeg, kend, bmask);
-        la.store(sA[0]);
-        lb.store(sB[0]);
+        stage(la, lb, sA[0], sB[0]);
     }
     __syncthreads();
     int cur = 0;
@@ -364,11 +455,11 @@ void gemm_tn_kernel(int M, int N, int K,
             la.load(A, lda, M, m0, k + Mt::BK, kend, amask);
             lb.load(B, ldb, N, n0, k + Mt::BK, kend, bmask);
         }
-        mfma_step<T, true, W::NI, W::NJ>(sB[cur], sA[cur], wn, wm, acc);
-        if (more) {
-            la.store(sA[cur ^ 1]);
-            lb.store(sB[cur ^ 1]);
-        }
+        if constexpr (BF)
+            mfma_step_bf<W::NI, W::NJ>(sB[cur], sA[cur], wn, wm, acc);
+        else
+            mfma_step<T, true, W::NI, W::NJ>(sB[cur], sA[cur], wn, wm, acc);
+        if (more) stage(la, lb, sA[cur ^ 1], sB[cur ^ 1]);
         __syncthreads();
         cur ^= 1;
     }
@@ -433,7 +524,7 @@ void splitk_reduce_kernel(int M, int N, int splits, const T *__restrict__ part,
 // ---------------------------------------------------------------------------
 // KIND only separates the symbols of the launch sites in a profile: 1 is the
 // trailing update of the factorization, 0 every other use.
-template <typename T, int KIND, int TW, bool SPLIT>
+template <typename T, int KIND, int TW, bool SPLIT, bool BF>
 __global__ __launch_bounds__(NTHR, 2)
 void gemm_nn_kernel(int M, int N, int K,
                     const T *__restrict__ A, int64_t lda, int amask,
@@ -448,8 +539,12 @@ void gemm_nn_kernel(int M, int N, int K,
     using Mt = Mf<T>;
     using W = WaveTile<T, TW>;
     if (skip && *skip) return;
-    __shared__ __attribute__((aligned(16))) T sA[2][Mt::BK * MkTile<T>::LD];
-    __shared__ __attribute__((aligned(16))) T sB[2][TW * KcTile<T>::LD];
+    // BF: FP32 operands staged as bf16 (BF16 MFMA, FP32 accumulation); the
+    // A tile is then stored [row][k]
+    static_assert(!BF || (sizeof(T) == 4 && TW == TILE && !SPLIT), "bf16 path: FP32, 128-wide, unsplit");
+    using LT = typename std::conditional<BF, __bf16, T>::type;
+    __shared__ __attribute__((aligned(16))) LT sA[2][BF ? TILE * MkTile<T>::LDB : Mt::BK * MkTile<T>::LD];
+    __shared__ __attribute__((aligned(16))) LT sB[2][TW * (BF ? KcTile<T>::LDB : KcTile<T>::LD)];
 
     int tm, tn;
     tile_of_block((M + TILE - 1) / TILE, (N + TW - 1) / TW, tm, tn);
@@ -492,10 +587,18 @@ void gemm_nn_kernel(int M, int N, int K,
 
     MkTile<T> la;
     KcTile<T, TW> lb;
+    auto stage = [](const MkTile<T> &a, const KcTile<T, TW> &b, LT *da, LT *db) {
+        if constexpr (BF) {
+            a.store_bf_t(da);
+            b.store_bf(db);
+        } else {
+            a.store(da);
+            b.store(db);
+        }
+    };
     la.load(A, lda, M, m0, kbeg, kend, amask != 0);
     lb.load(B, ldb, N, n0, kbeg, kend, 0);
-    la.store(sA[0]);
-    lb.store(sB[0]);
+    stage(la, lb, sA[0], sB[0]);
     __syncthreads();
     int cur = 0;
     for (int k = kbeg; k < kend; k += Mt::BK) {
@@ -504,11 +607,11 @@ void gemm_nn_kernel(int M, int N, int K,
             la.load(A, lda, M, m0, k + Mt::BK, kend, amask != 0);
             lb.load(B, ldb, N, n0, k + Mt::BK, kend, 0);
         }
-        mfma_step<T, false, W::NI, W::NJ>(sB[cur], sA[cur], wn, wm, acc);
-        if (more) {
-            la.store(sA[cur ^ 1]);
-            lb.store(sB[cur ^ 1]);
-        }
+        if constexpr (BF)
+            mfma_step_bf<W::NI, W::NJ>(sB[cur], sA[cur], wn, wm, acc);
+        else
+            mfma_step<T, false, W::NI, W::NJ>(sB[cur], sA[cur], wn, wm, acc);
+        if (more) stage(la, lb, sA[cur ^ 1], sB[cur ^ 1]);
         __syncthreads();
         cur ^= 1;
     }
@@ -611,7 +714,7 @@ ctqr_status splitk_reduce(int M, int N, int splits, const T *part, T alpha, T be
 template <typename T>
 ctqr_status gemm_tn(int M, int N, int K, const T *A, int64_t lda, int amask, const T *B,
                     int64_t ldb, int bmask, T alpha, T beta, T *Out, int64_t ldo, T *part,
-                    size_t part_elems, const int *skip, hipStream_t st, int force_splits)
+                    size_t part_elems, const int *skip, hipStream_t st, int force_splits, bool bf16)
 {
     if (M <= 0 || N <= 0) return CTQR_OK;
     const bool narrow = N <= t_narrow_max;
@@ -624,12 +727,22 @@ ctqr_status gemm_tn(int M, int N, int K, const T *A, int64_t lda, int amask, con
     if (kchunk <= 0) kchunk = Mf<T>::BK;
     splits = (int)ceil_div(K > 0 ? K : 1, kchunk);
     dim3 grid((unsigned)(ceil_div(M, TILE) * ceil_div(N, narrow ? NARROW : TILE)), 1, (unsigned)splits);
-    if (narrow)
-        LAUNCH_TRY((gemm_tn_kernel<T, NARROW>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B, ldb,
+    bool done = false;
+    if constexpr (sizeof(T) == 4) {
+        if (bf16 && !narrow) {
+            LAUNCH_TRY((gemm_tn_kernel<T, TILE, true>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B, ldb,
+                       bmask, alpha, beta, Out, ldo, part, kchunk, skip);
+            done = true;
+        }
+    }
+    if (done) {
+    } else if (narrow) {
+        LAUNCH_TRY((gemm_tn_kernel<T, NARROW, false>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B, ldb,
                    bmask, alpha, beta, Out, ldo, part, kchunk, skip);
-    else
-        LAUNCH_TRY((gemm_tn_kernel<T, TILE>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B, ldb,
+    } else {
+        LAUNCH_TRY((gemm_tn_kernel<T, TILE, false>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B, ldb,
                    bmask, alpha, beta, Out, ldo, part, kchunk, skip);
+    }
     if (splits > 1) return splitk_reduce<T>(M, N, splits, part, alpha, beta, Out, ldo, skip, st);
     return CTQR_OK;
 }
@@ -637,7 +750,7 @@ ctqr_status gemm_tn(int M, int N, int K, const T *A, int64_t lda, int amask, con
 template <typename T>
 ctqr_status gemm_nn(int M, int N, int K, const T *A, int64_t lda, int amask, const T *B,
                     int64_t ldb, T alpha, T *C, int64_t ldc, const int *skip, hipStream_t st, int kind,
-                    int accum)
+                    int accum, bool bf16)
 {
     if (M <= 0 || N <= 0) return CTQR_OK;
     if (K <= 0) {
@@ -647,15 +760,22 @@ ctqr_status gemm_nn(int M, int N, int K, const T *A, int64_t lda, int amask, con
     const bool narrow = N <= t_narrow_max;
     const int kchunk = K > 0 ? K : 1;
     dim3 grid((unsigned)(ceil_div(M, TILE) * ceil_div(N, narrow ? NARROW : TILE)));
+    if constexpr (sizeof(T) == 4) {
+        if (kind == 1 && bf16) {
+            LAUNCH_TRY((gemm_nn_kernel<T, 1, TILE, false, true>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask,
+                       B, ldb, alpha, C, ldc, accum, (T *)nullptr, kchunk, skip);
+            return CTQR_OK;
+        }
+    }
     if (kind == 1)
-        LAUNCH_TRY((gemm_nn_kernel<T, 1, TILE, false>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B,
+        LAUNCH_TRY((gemm_nn_kernel<T, 1, TILE, false, false>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B,
                    ldb, alpha, C, ldc, accum, (T *)nullptr, kchunk, skip);
     else if (narrow)
-        LAUNCH_TRY((gemm_nn_kernel<T, 0, NARROW, false>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B,
-                   ldb, alpha, C, ldc, accum, (T *)nullptr, kchunk, skip);
+        LAUNCH_TRY((gemm_nn_kernel<T, 0, NARROW, false, false>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask,
+                   B, ldb, alpha, C, ldc, accum, (T *)nullptr, kchunk, skip);
     else
-        LAUNCH_TRY((gemm_nn_kernel<T, 0, TILE, false>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B,
-                   ldb, alpha, C, ldc, accum, (T *)nullptr, kchunk, skip);
+        LAUNCH_TRY((gemm_nn_kernel<T, 0, TILE, false, false>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask,
+                   B, ldb, alpha, C, ldc, accum, (T *)nullptr, kchunk, skip);
     return CTQR_OK;
 }
 
@@ -667,29 +787,29 @@ ctqr_status gemm_nn_split(int M, int N, int K, const T *A, int64_t lda, const T 
     const bool narrow = N <= t_narrow_max;
     int splits = gemm_tn_splits(M, N, K);
     if (splits > 1 && (part == nullptr || part_elems < (size_t)splits * M * N)) splits = 1;
-    if (splits <= 1) return gemm_nn<T>(M, N, K, A, lda, 0, B, ldb, alpha, C, ldc, skip, st, 0, 1);
+    if (splits <= 1) return gemm_nn<T>(M, N, K, A, lda, 0, B, ldb, alpha, C, ldc, skip, st, 0, 1, false);
     int kchunk = (int)ceil_div(ceil_div(K, splits), Mf<T>::BK) * Mf<T>::BK;
     splits = (int)ceil_div(K, kchunk);
     dim3 grid((unsigned)(ceil_div(M, TILE) * ceil_div(N, narrow ? NARROW : TILE)), 1, (unsigned)splits);
     if (narrow)
-        LAUNCH_TRY((gemm_nn_kernel<T, 0, NARROW, true>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, 0, B, ldb,
-                   alpha, C, ldc, 0, part, kchunk, skip);
+        LAUNCH_TRY((gemm_nn_kernel<T, 0, NARROW, true, false>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, 0, B,
+                   ldb, alpha, C, ldc, 0, part, kchunk, skip);
     else
-        LAUNCH_TRY((gemm_nn_kernel<T, 0, TILE, true>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, 0, B, ldb,
-                   alpha, C, ldc, 0, part, kchunk, skip);
+        LAUNCH_TRY((gemm_nn_kernel<T, 0, TILE, true, false>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, 0, B,
+                   ldb, alpha, C, ldc, 0, part, kchunk, skip);
     return splitk_reduce<T>(M, N, splits, part, alpha, T(1), C, ldc, skip, st);
 }
 
 template ctqr_status gemm_tn<float>(int, int, int, const float *, int64_t, int, const float *,
                                     int64_t, int, float, float, float *, int64_t, float *, size_t,
-                                    const int *, hipStream_t, int);
+                                    const int *, hipStream_t, int, bool);
 template ctqr_status gemm_tn<double>(int, int, int, const double *, int64_t, int, const double *,
                                      int64_t, int, double, double, double *, int64_t, double *,
-                                     size_t, const int *, hipStream_t, int);
+                                     size_t, const int *, hipStream_t, int, bool);
 template ctqr_status gemm_nn<float>(int, int, int, const float *, int64_t, int, const float *,
-                                    int64_t, float, float *, int64_t, const int *, hipStream_t, int, int);
+                                    int64_t, float, float *, int64_t, const int *, hipStream_t, int, int, bool);
 template ctqr_status gemm_nn<double>(int, int, int, const double *, int64_t, int, const double *,
-                                     int64_t, double, double *, int64_t, const int *, hipStream_t, int, int);
+                                     int64_t, double, double *, int64_t, const int *, hipStream_t, int, int, bool);
 template ctqr_status gemm_nn_split<float>(int, int, int, const float *, int64_t, const float *, int64_t, float,
                                           float *, int64_t, float *, size_t, const int *, hipStream_t);
 template ctqr_status gemm_nn_split<double>(int, int, int, const double *, int64_t, const double *, int64_t,

@@ -11,15 +11,18 @@ int gemm_tn_splits(int M, int N, int K);
 size_t gemm_tn_partial_elems(int M, int N, int K);
 // force_splits > 0 fixes the number of K splits (the partial buffer must hold
 // them, else CTQR_ENOMEM): products over different column ranges of one
-// matrix then sum every output in the same order.
+// matrix then sum every output in the same order.  bf16 (FP32 operands,
+// 128-wide tiles): operands rounded to bf16 while staged, BF16 MFMA with FP32
+// accumulation; gemm_nn honours it for the trailing update (kind 1) only.
 template <typename T>
 ctqr_status gemm_tn(int M, int N, int K, const T *A, int64_t lda, int amask, const T *B,
                     int64_t ldb, int bmask, T alpha, T beta, T *Out, int64_t ldo, T *part,
-                    size_t part_elems, const int *skip, hipStream_t st, int force_splits = 0);
+                    size_t part_elems, const int *skip, hipStream_t st, int force_splits = 0,
+                    bool bf16 = false);
 template <typename T>
 ctqr_status gemm_nn(int M, int N, int K, const T *A, int64_t lda, int amask, const T *B,
                     int64_t ldb, T alpha, T *C, int64_t ldc, const int *skip, hipStream_t st,
-                    int kind = 0, int accum = 1);
+                    int kind = 0, int accum = 1, bool bf16 = false);
 // C += alpha A B (A not a Householder block), split over K into part when the
 // output has too few tiles to fill the chip.
 template <typename T>

@@ -201,3 +201,42 @@ def test_rank_deficient_reported(gpu):
     F, info = _gpu_factor(Ad, torch.float64, C.CTQR_PREC_FP64, 32)
     assert info.status == C.CTQR_RANK_DEFICIENT
     assert info.first_bad_col == 57
+
+
+@pytest.mark.parametrize("name", ["ct24", "ct40"])
+def test_bf16_trailing_update_factor(gpu, name):
+    # BF16 MFMA for the block-column products (operands rounded to bf16, FP32
+    # accumulation): R agrees with the oracle's to BF16 accuracy -- visibly
+    # worse than the FP32 path, which shows the BF16 kernels ran -- and the
+    # refined solve either converges or reports that it did not.
+    _print_case("bf16 factor", name)
+    g, A, X, B = oracle_problem(name)
+    QRo, tauo = oracle_factor(name)
+    n = A.shape[1]
+    Ro = np.triu(QRo[:n, :n])
+    F16, info = _gpu_factor(A.toarray().astype(np.float32), torch.float32, C.CTQR_PREC_BF16_MFMA, 64)
+    F32, info32 = _gpu_factor(A.toarray().astype(np.float32), torch.float32, C.CTQR_PREC_FP32_MFMA, 64)
+    assert info.status in (0, C.CTQR_RANK_DEFICIENT), C.status_string(info.status)
+    # R is unique up to the signs of its rows: a pivot that BF16 rounding
+    # moves across zero flips the reflector's sign choice, so compare
+    # diag(sign R_ii) R
+    sn = lambda R: np.sign(np.diag(R))[:, None] * R
+    R16 = sn(np.triu(download(F16.A)[:n, :n]).astype(np.float64))
+    R32 = sn(np.triu(download(F32.A)[:n, :n]).astype(np.float64))
+    Ron = sn(Ro)
+    e16 = np.abs(R16 - Ron).max() / np.abs(Ron).max()
+    e32 = np.abs(R32 - Ron).max() / np.abs(Ron).max()
+    print("R rel err: bf16 %.2e, fp32 %.2e" % (e16, e32))
+    assert e16 <= 5e-2
+    assert e16 > 10 * e32
+    Bd = to_colmajor(torch.as_tensor(B), dtype=torch.float64)
+    Xo = hh.backsub(QRo, hh.apply_qt(QRo, tauo, B))
+    spA = DeviceSparse(A)
+    Xg = download(F16.solve(Bd, sparse=spA.sp, tol=1e-14, max_iters=30))
+    torch.cuda.synchronize()
+    si = F16.sinfo.read()
+    err = lsq.rel_err(Xg, Xo).max()
+    print("bf16 refined: status %d iters %d err %.2e" % (si.status, si.iters, err))
+    assert si.status in (0, C.CTQR_NOT_CONVERGED)
+    if si.status == 0:
+        assert err <= 1e-10
