@@ -207,8 +207,12 @@ ctqr_status ctqr_sparse_to_dense(const ctqr_sparse *sp, ctqr_dtype dtype, int64_
  *   T, tau, Rinv, info  as ctqr_qr_factor (T, tau and Rinv in device memory).
  *   work    device, ctqr_qr_factor_ooc_workspace bytes (two tile buffers
  *           of lda * tile_cols elements plus the factorization workspace).
- * Copies and kernels are enqueued on `stream` in order; the call returns
- * once everything is enqueued. */
+ * Kernels run on `stream`; the tile copies run on a copy stream of the call,
+ * ordered by events, so the next tile uploads while the current one is
+ * factored, the first while the resident columns are factored, and each
+ * factored tile is written back while the next takes its updates.  The call
+ * returns once every copy has finished (host memory then holds the factor);
+ * the kernels enqueued on `stream` are complete when it synchronises. */
 ctqr_status ctqr_qr_factor_ooc_workspace(int64_t m, int64_t n, ctqr_dtype dtype, ctqr_prec prec,
                                          int32_t nb, int64_t lda, int64_t tile_cols, size_t *bytes);
 ctqr_status ctqr_qr_factor_ooc(int64_t m, int64_t n, ctqr_dtype dtype, void *A_dev, void *A_host,

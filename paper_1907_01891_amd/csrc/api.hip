@@ -369,6 +369,39 @@ OocWS<T> carve_ooc(void *work, int64_t m, int64_t n, int nb, int64_t lda, int64_
     return o;
 }
 
+// Events and the copy stream of one out-of-core call; the compute stream
+// waits for the copy stream's last work before the call returns, so the
+// caller sees one stream-ordered operation.
+struct CopyLane {
+    hipStream_t cs = nullptr;
+    std::vector<hipEvent_t> evs;
+    ~CopyLane()
+    {
+        for (auto e : evs) (void)hipEventDestroy(e);
+        if (cs) (void)hipStreamDestroy(cs);
+    }
+    ctqr_status init()
+    {
+        HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        return CTQR_OK;
+    }
+    // records a fresh event on stream s
+    ctqr_status mark(hipStream_t s, hipEvent_t *out)
+    {
+        hipEvent_t e;
+        HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        evs.push_back(e);
+        HIP_TRY(hipEventRecord(e, s));
+        *out = e;
+        return CTQR_OK;
+    }
+    ctqr_status wait(hipStream_t s, hipEvent_t e)
+    {
+        if (e) HIP_TRY(hipStreamWaitEvent(s, e, 0));
+        return CTQR_OK;
+    }
+};
+
 template <typename T>
 ctqr_status factor_ooc_impl(int64_t m64, int64_t n64, T *A_dev, T *A_host, int64_t lda, int64_t n_dev64,
                             int64_t tile64, int nb, T *Tout, double *tau, T *Rinv, void *work, ctqr_info *info,
@@ -380,9 +413,25 @@ ctqr_status factor_ooc_impl(int64_t m64, int64_t n64, T *A_dev, T *A_host, int64
     w.bf16 = bf16;
     const int ncu = std::min(device_cus(), MAX_PANEL_WG);
     const size_t col_bytes = (size_t)lda * sizeof(T);
+    auto host_cols = [&](int c0) { return A_host + (int64_t)(c0 - n_dev) * lda; };
+    auto tile_bytes = [&](int c0) { return (size_t)(std::min(n, c0 + tile) - c0) * col_bytes; };
     ctqr_status s;
     if ((s = info_reset(info, st))) return s;
     if ((s = fill_u32(w.bars, (ceil_div(n, PANEL_W) + 1) * GB_WORDS, 0u, st))) return s;
+    // Two tile buffers: X holds the tile being updated and factored, Y the
+    // earlier tiles re-uploaded for their updates, then the next tile
+    // (prefetched while X is factored); they swap roles every tile.  All
+    // copies go through the copy stream.
+    CopyLane cl;
+    if ((s = cl.init())) return s;
+    T *buf[2] = {o.D, o.E};
+    int x = 0;
+    hipEvent_t loaded_x = nullptr, free_y = nullptr, last_copy = nullptr;
+    if (n_dev < n) {   // the first host tile streams in while the resident columns are factored
+        HIP_TRY(hipMemcpyAsync(buf[x], host_cols(n_dev), tile_bytes(n_dev), hipMemcpyHostToDevice, cl.cs));
+        if ((s = cl.mark(cl.cs, &loaded_x))) return s;
+        last_copy = loaded_x;
+    }
     if (n_dev > 0) {
         // in pieces of 8192 columns (the same arithmetic as one call), each
         // followed by a progress mark
@@ -397,26 +446,51 @@ ctqr_status factor_ooc_impl(int64_t m64, int64_t n64, T *A_dev, T *A_host, int64
     }
     for (int c0 = n_dev; c0 < n; c0 += tile) {
         const int c1 = std::min(n, c0 + tile);
-        HIP_TRY(hipMemcpyAsync(o.D, A_host + (int64_t)(c0 - n_dev) * lda, (size_t)(c1 - c0) * col_bytes,
-                               hipMemcpyHostToDevice, st));
-        T *Dv = shift_cols(o.D, c0, lda);
+        const int y = x ^ 1;
+        if ((s = cl.wait(st, loaded_x))) return s;
+        T *Dv = shift_cols(buf[x], c0, lda);
         if (n_dev > 0 && (s = apply_blocks<T>(m, n, A_dev, lda, Tout, nb, 0, n_dev, Dv, c0, c1, w, st))) return s;
         for (int e0 = n_dev; e0 < c0; e0 += tile) {
             const int e1 = std::min(n, e0 + tile);
-            HIP_TRY(hipMemcpyAsync(o.E, A_host + (int64_t)(e0 - n_dev) * lda, (size_t)(e1 - e0) * col_bytes,
-                                   hipMemcpyHostToDevice, st));
-            T *Ev = shift_cols(o.E, e0, lda);
+            if ((s = cl.wait(cl.cs, free_y))) return s;
+            HIP_TRY(hipMemcpyAsync(buf[y], host_cols(e0), tile_bytes(e0), hipMemcpyHostToDevice, cl.cs));
+            hipEvent_t ready;
+            if ((s = cl.mark(cl.cs, &ready))) return s;
+            last_copy = ready;
+            if ((s = cl.wait(st, ready))) return s;
+            T *Ev = shift_cols(buf[y], e0, lda);
             if ((s = apply_blocks<T>(m, n, Ev, lda, Tout, nb, e0, e1, Dv, c0, c1, w, st))) return s;
+            if ((s = cl.mark(st, &free_y))) return s;
         }
         if ((s = factor_blocks<T>(m, n, Dv, lda, nb, c0, c1, c1, Tout, tau, w, w.bars, info, ncu, st))) return s;
         if ((s = diag_copy<T>(c0, c1, Dv, lda, o.diag, st))) return s;
         if (Rinv && (s = trinv_blocks_range<T>(n, c0, c1, Dv, lda, Rinv, w.rtmp, st))) return s;
-        HIP_TRY(hipMemcpyAsync(A_host + (int64_t)(c0 - n_dev) * lda, o.D, (size_t)(c1 - c0) * col_bytes,
-                               hipMemcpyDeviceToHost, st));
+        hipEvent_t factored;
+        if ((s = cl.mark(st, &factored))) return s;
         if ((s = progress_mark(st, CTQR_PROGRESS_FACTOR, c1, n))) return s;
+        // next tile into Y (after Y's last update read), then this tile back
+        hipEvent_t loaded_next = nullptr;
+        if (c1 < n) {
+            if ((s = cl.wait(cl.cs, free_y))) return s;
+            HIP_TRY(hipMemcpyAsync(buf[y], host_cols(c1), tile_bytes(c1), hipMemcpyHostToDevice, cl.cs));
+            if ((s = cl.mark(cl.cs, &loaded_next))) return s;
+        }
+        if ((s = cl.wait(cl.cs, factored))) return s;
+        HIP_TRY(hipMemcpyAsync(host_cols(c0), buf[x], (size_t)(c1 - c0) * col_bytes, hipMemcpyDeviceToHost, cl.cs));
+        hipEvent_t written;
+        if ((s = cl.mark(cl.cs, &written))) return s;
+        last_copy = written;
+        // swap: the written-back buffer takes the re-uploads of the next tile
+        x = y;
+        loaded_x = loaded_next;
+        free_y = written;
     }
+    if ((s = cl.wait(st, last_copy))) return s;
     // rank check over the diagonal collected above (stride 0: diag[k])
-    return rdiag_check<T>(n, o.diag, 0, nullptr, info, st);
+    if ((s = rdiag_check<T>(n, o.diag, 0, nullptr, info, st))) return s;
+    // the copy stream and its events are released only once idle
+    HIP_TRY(hipStreamSynchronize(cl.cs));
+    return CTQR_OK;
 }
 
 // Sets the slice-tile choice of the GEMMs enqueued by this thread for the
