@@ -29,6 +29,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
+REFINE = {"csne": 0, "pcg": 1}
 HBM_PEAK_GBS = 8000.0
 
 
@@ -49,6 +50,8 @@ def parse():
     p.add_argument("--nb", type=int, default=256)
     p.add_argument("--max-iters", type=int, default=30)
     p.add_argument("--tol", type=float, default=1e-12)
+    p.add_argument("--refine", choices=["csne", "pcg"], default="csne",
+                   help="refinement form: corrected semi-normal equations or their conjugate-gradient form")
     p.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU comparison run")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -308,7 +311,7 @@ def ooc_bench(args, log):
     torch.cuda.empty_cache()
     e2, e3 = ev(), ev()
     e2.record()
-    X = O.solve(B, sparse=sp.sp, tol=args.tol, max_iters=args.max_iters)
+    X = O.solve(B, sparse=sp.sp, tol=args.tol, max_iters=args.max_iters, method=REFINE[args.refine])
     e3.record()
     torch.cuda.synchronize()
     t_solve = e2.elapsed_time(e3)
@@ -344,7 +347,7 @@ def ooc_bench(args, log):
                    "nb": args.nb, "slices": S, "parallelism": "single GPU"},
         "qr_ms": t_qr, "solve_ms": t_solve, "slices_per_s": S / (t_solve * 1e-3), "fill_s": t_fill,
         "qr_info_status": int(finfo.status), "rdiag_min_max": [finfo.rdiag_min, finfo.rdiag_max],
-        "refine_iters": int(sinfo.iters), "refine_status": int(sinfo.status),
+        "refine_method": args.refine, "refine_iters": int(sinfo.iters), "refine_status": int(sinfo.status),
         "ls_optimality_max": opt, "recovery_rel_err_max": rec, "nnz": nnz,
         "resident_columns": int(n_dev), "host_columns": int(n - n_dev), "host_gb": host_gb,
     }
@@ -417,7 +420,7 @@ def main():
             C.ctqr_profile_enable(True)
         F.factor()
         e2.record()
-        F.solve(B, X=X, sparse=sp.sp, tol=args.tol, max_iters=args.max_iters)
+        F.solve(B, X=X, sparse=sp.sp, tol=args.tol, max_iters=args.max_iters, method=REFINE[args.refine])
         e3.record()
         torch.cuda.synchronize()
         return e0.elapsed_time(e1), e1.elapsed_time(e2), e2.elapsed_time(e3)
@@ -445,7 +448,7 @@ def main():
 
     # accuracy: exact recovery on noise-free slices (the least-squares solution
     # of consistent data is the phantom itself)
-    Xc = F.solve(Bclean, sparse=sp.sp, tol=args.tol, max_iters=args.max_iters)
+    Xc = F.solve(Bclean, sparse=sp.sp, tol=args.tol, max_iters=args.max_iters, method=REFINE[args.refine])
     torch.cuda.synchronize()
     rec_err = ((Xc - Xtrue[:, :n_clean]).norm(dim=0) / Xtrue[:, :n_clean].norm(dim=0)).max().item()
     Xmixed = X.clone()
@@ -471,7 +474,7 @@ def main():
         Xu = F16.solve(B)
         torch.cuda.synchronize()
         e_unref = ((Xu - Xmixed).norm(dim=0) / Xmixed.norm(dim=0)).max().item()
-        Xr = F16.solve(B, sparse=sp.sp, tol=args.tol, max_iters=args.max_iters)
+        Xr = F16.solve(B, sparse=sp.sp, tol=args.tol, max_iters=args.max_iters, method=REFINE[args.refine])
         torch.cuda.synchronize()
         si16 = F16.sinfo.read()
         e_ref = ((Xr - Xmixed).norm(dim=0) / Xmixed.norm(dim=0)).max().item()
@@ -552,6 +555,7 @@ def main():
         "slices_per_s": slices_s,
         "qr_ms": t_qr, "solve_ms": t_solve, "build_ms": t_build,
         "solve_tflops": S * solve_flops(m, n) / (t_solve * 1e-3) / 1e12,
+        "refine_method": args.refine,
         "refine_iters": int(sinfo.iters), "refine_status": int(sinfo.status),
         "refine_last_rel_update": sinfo.max_rel_update,
         "recovery_rel_err_max": rec_err,

@@ -74,6 +74,21 @@ typedef int32_t ctqr_prec;
 #define CTQR_PREC_FP32_MFMA 1
 #define CTQR_PREC_BF16_MFMA 2
 
+/* Refinement of a solve with the FP64 sparse A (both forms use FP64
+ * residuals r = B - A X, s = A^T r and the preconditioner (R^T R)^-1 applied
+ * by the two triangular solves with the factor's R; both converge to the
+ * least-squares solution of the FP64 A):
+ *   CTQR_REFINE_CSNE  corrected semi-normal equations: X += (R^T R)^-1 s.
+ *   CTQR_REFINE_PCG   the same corrections combined as conjugate directions
+ *                     (preconditioned conjugate gradients on the normal
+ *                     equations, Polak-Ribiere coefficient, per slice): fewer
+ *                     iterations, and convergence where the plain corrections
+ *                     stop contracting (A ill-conditioned for the factor's
+ *                     precision). */
+typedef int32_t ctqr_refine;
+#define CTQR_REFINE_CSNE 0
+#define CTQR_REFINE_PCG  1
+
 /* Fan-beam scanner (Section II-A, Table I) and reconstruction grid.
  * Rays: one per (view, bin), row index view * n_bins + bin.  The source turns
  * on a circle of radius src_iso_cm; the flat detector, src_det_cm from the
@@ -239,13 +254,15 @@ ctqr_status ctqr_qr_solve_ooc(int64_t m, int64_t n, ctqr_dtype dtype, const void
                               const void *T, const double *tau, const void *Rinv, int32_t nb,
                               const double *B, int64_t ldb, int32_t nslices, double *X,
                               int64_t ldx, const ctqr_sparse *A64, double tol, int32_t max_iters,
-                              void *work, size_t work_bytes, ctqr_info *info, hipStream_t stream);
+                              int32_t refine_method, void *work, size_t work_bytes, ctqr_info *info,
+                              hipStream_t stream);
 
 /* Bytes of the Rinv array of ctqr_qr_factor / ctqr_qr_solve_slices (host only). */
 ctqr_status ctqr_qr_rinv_bytes(int64_t n, ctqr_dtype dtype, size_t *bytes);
 
 /* Workspace (device bytes) for ctqr_qr_solve_slices with up to nslices
- * right-hand sides; refine != 0 reserves the refinement vectors. */
+ * right-hand sides; refine: 0 none, 1 the refinement vectors, 2 also the
+ * conjugate-gradient vectors (CTQR_REFINE_PCG). */
 ctqr_status ctqr_solve_workspace(int64_t m, int64_t n, ctqr_dtype dtype, int32_t nb,
                                  int32_t nslices, int32_t refine, size_t *bytes);
 
@@ -267,6 +284,9 @@ ctqr_status ctqr_solve_workspace(int64_t m, int64_t n, ctqr_dtype dtype, int32_t
  *          With refinement the call waits on the stream after each
  *          iteration (it reads the convergence flag back) and returns once
  *          the refinement has ended; without it the call only enqueues.
+ *   refine_method  CTQR_REFINE_CSNE or CTQR_REFINE_PCG (both converge by the
+ *          rule above; the conjugate-gradient form allows a longer run of
+ *          non-shrinking updates, 6, before it stops).
  *   info   device: iterations, last relative update, CTQR_NOT_CONVERGED /
  *          CTQR_NONFINITE. */
 ctqr_status ctqr_qr_solve_slices(int64_t m, int64_t n, ctqr_dtype dtype,
@@ -275,8 +295,8 @@ ctqr_status ctqr_qr_solve_slices(int64_t m, int64_t n, ctqr_dtype dtype,
                                  const double *B, int64_t ldb, int32_t nslices,
                                  double *X, int64_t ldx,
                                  const ctqr_sparse *A64, double tol, int32_t max_iters,
-                                 void *work, size_t work_bytes, ctqr_info *info,
-                                 hipStream_t stream);
+                                 int32_t refine_method, void *work, size_t work_bytes,
+                                 ctqr_info *info, hipStream_t stream);
 
 /* ---- Batched solver ------------------------------------------------------
  * One stored factorization serves a stream of reconstruction requests: the
@@ -320,7 +340,9 @@ typedef struct {
     double tol;             /* refinement tolerance */
     int32_t max_iters;      /* refinement iteration limit (0 = none) */
     int32_t max_slices;     /* largest request, 1 .. 4096 */
-} ctqr_solver_desc;        /* 88 bytes */
+    int32_t refine_method;  /* CTQR_REFINE_CSNE or CTQR_REFINE_PCG */
+    int32_t pad;
+} ctqr_solver_desc;        /* 96 bytes */
 
 /* Workspace bytes of a solver (host only). */
 ctqr_status ctqr_solver_workspace(const ctqr_solver_desc *desc, size_t *bytes);

@@ -121,6 +121,8 @@ template <typename T>
 struct SolveWS {
     T *Bw, *W, *W2, *split, *Rinv, *RinvT, *Xw;
     double *xr, *Br, *r, *s, *hist;
+    // conjugate-gradient form: z (two, by iteration parity), p, q, dot partials, per-slice scalars
+    double *z0, *z1, *p, *q, *dpart, *sz, *szp, *qq, *gamma, *beta, *alpha;
     T *s32, *y32, *d32;
     unsigned long long *dmax, *xmax;
     int *done;
@@ -129,7 +131,9 @@ struct SolveWS {
 };
 
 template <typename T>
-SolveWS<T> carve_solve(void *work, int64_t m, int64_t n, int nb, int S, bool refine, bool with_rinv = true)
+// refine: 0 none, 1 semi-normal-equations corrections, 2 also the
+// conjugate-gradient vectors
+SolveWS<T> carve_solve(void *work, int64_t m, int64_t n, int nb, int S, int refine, bool with_rinv = true)
 {
     Carve c(work);
     SolveWS<T> w{};
@@ -157,6 +161,19 @@ SolveWS<T> carve_solve(void *work, int64_t m, int64_t n, int nb, int S, bool ref
         w.dmax = c.take<unsigned long long>(S);
         w.xmax = c.take<unsigned long long>(S);
         w.hist = c.take<double>(8);
+    }
+    if (refine >= 2) {
+        w.z0 = c.take<double>(n * S);
+        w.z1 = c.take<double>(n * S);
+        w.p = c.take<double>(n * S);
+        w.q = c.take<double>(m * S);
+        w.dpart = c.take<double>((int64_t)slice_dot_partial_elems(S));
+        w.sz = c.take<double>(S);
+        w.szp = c.take<double>(S);
+        w.qq = c.take<double>(S);
+        w.gamma = c.take<double>(S);
+        w.beta = c.take<double>(S);
+        w.alpha = c.take<double>(S);
     }
     w.bytes = c.off + 256;
     return w;
@@ -518,6 +535,8 @@ struct SolveRun {
     const ctqr_sparse *A64;
     double tol;
     int max_iters;
+    int method;      // CTQR_REFINE_CSNE or CTQR_REFINE_PCG
+    bool progress;   // report each refinement iteration to the progress hook
     int narrow;
     ctqr_info *info;
     SolveWS<T> w;
@@ -528,15 +547,15 @@ struct SolveRun {
 template <typename T>
 SolveRun<T> make_run(int64_t m, int64_t n, const T *QR, int64_t lda, const T *Tf, const T *Rinv, int nb,
                      const double *B, int64_t ldb, int S, const ctqr_sparse *A64, double tol, int max_iters,
-                     void *work, ctqr_info *info, bool carve_rinv)
+                     void *work, ctqr_info *info, bool carve_rinv, int method = CTQR_REFINE_CSNE)
 {
     SolveRun<T> r{};
     r.m = (int)m; r.n = (int)n; r.nb = nb; r.S = S;
     r.QR = QR; r.lda = lda; r.Tf = Tf; r.Rinv = Rinv; r.B = B; r.ldb = ldb;
-    r.A64 = A64; r.tol = tol; r.max_iters = max_iters;
+    r.A64 = A64; r.tol = tol; r.max_iters = max_iters; r.method = method;
     r.narrow = S <= DEFAULT_NARROW ? DEFAULT_NARROW : 0;
     r.info = info;
-    r.w = carve_solve<T>(work, m, n, nb, S, r.refine(), carve_rinv);
+    r.w = carve_solve<T>(work, m, n, nb, S, r.refine() ? (method == CTQR_REFINE_PCG ? 2 : 1) : 0, carve_rinv);
     r.sp_elems = std::max<int64_t>(SPLIT_PART_ELEMS, 64LL * nb * S);
     return r;
 }
@@ -565,6 +584,22 @@ ctqr_status apply_qt_range(SolveRun<T> &r, const T *QRv, int kb, int ke, hipStre
     return CTQR_OK;
 }
 
+// Clears the refinement's history, norms and (conjugate-gradient form) the
+// search direction and per-slice scalars.
+template <typename T>
+ctqr_status refine_setup(SolveRun<T> &r, hipStream_t st)
+{
+    SolveWS<T> &w = r.w;
+    const int S = r.S;
+    ctqr_status s;
+    if ((s = fill_f64(w.hist, 8, 0.0, st))) return s;
+    if ((s = fill_u32((unsigned *)w.dmax, 2LL * S, 0u, st))) return s;
+    if ((s = fill_u32((unsigned *)w.xmax, 2LL * S, 0u, st))) return s;
+    if (r.method != CTQR_REFINE_PCG) return CTQR_OK;
+    if ((s = fill_f64(w.p, (int64_t)r.n * S, 0.0, st))) return s;
+    return fill_f64(w.gamma, S, 0.0, st);
+}
+
 // Q^T B and the back substitution (Section II-C), then the set-up of the
 // refinement.
 template <typename T>
@@ -590,9 +625,7 @@ ctqr_status solve_start(SolveRun<T> &r, hipStream_t st)
     if (!r.refine()) return CTQR_OK;
     if ((s = cm_to_rm<double, T>(n, S, w.Xw, w.ldxw, w.xr, nullptr, st))) return s;
     if ((s = cm_to_rm<double, double>(m, S, r.B, r.ldb, w.Br, nullptr, st))) return s;
-    if ((s = fill_f64(w.hist, 8, 0.0, st))) return s;
-    if ((s = fill_u32((unsigned *)w.dmax, 2LL * S, 0u, st))) return s;
-    return fill_u32((unsigned *)w.xmax, 2LL * S, 0u, st);
+    return refine_setup(r, st);
 }
 
 // Reads the device-side end-of-refinement flag (synchronises the stream).
@@ -606,18 +639,23 @@ ctqr_status read_done(const int *done, hipStream_t st, bool &out)
     return CTQR_OK;
 }
 
-// Refinement iterations it0 .. it1-1 of the corrected semi-normal equations:
-// r = B - A x, R^T y = A^T r, R d = y, x += d.  Every kernel of an iteration
-// returns at once after the device-side flag has ended the refinement.  With
-// host_sync the loop stops enqueuing once that flag is set; *ran is then the
-// number of iterations the refinement took.
-template <typename T>
-ctqr_status refine_iters(SolveRun<T> &r, int it0, int it1, bool host_sync, hipStream_t st, int *ran)
+// Refinement iterations it0 .. it1-1 with FP64 residuals against the sparse A
+// (r = B - A x, s = A^T r) and the preconditioner (R^T R)^-1, applied by
+// minv (s32 -> d32 through y32: R^T y = s, R d = y, in the factor's
+// precision).  CTQR_REFINE_CSNE adds the correction, x += d (corrected
+// semi-normal equations); CTQR_REFINE_PCG combines the corrections as
+// conjugate directions (refine.hip).  Every kernel of an iteration returns at
+// once after the device-side flag has ended the refinement.  With host_sync
+// the loop stops enqueuing once that flag is set; *ran is then the number of
+// iterations the refinement took.
+template <typename T, typename MInv>
+ctqr_status refine_iters_with(SolveRun<T> &r, int it0, int it1, bool host_sync, hipStream_t st, int *ran, MInv minv)
 {
     NarrowScope ns(r.narrow);
     SolveWS<T> &w = r.w;
     const int m = r.m, n = r.n, S = r.S;
     const ctqr_sparse *A = r.A64;
+    const bool pcg = r.method == CTQR_REFINE_PCG;
     ctqr_status s;
     if (ran) *ran = it1;
     for (int it = it0; it < it1; ++it) {
@@ -627,15 +665,27 @@ ctqr_status refine_iters(SolveRun<T> &r, int it0, int it1, bool host_sync, hipSt
         s = spmm_rowmajor(n, S, A->colptr, A->row, A->cval, 1.0, w.r, 0.0, nullptr, w.s, skip, st);
         if (s) return s;
         if ((s = rm_to_cm<T, double>(n, S, w.s, w.s32, w.ldxw, skip, st))) return s;
-        s = trsm_upper_trans<T>(n, S, r.QR, r.lda, r.Rinv, w.s32, w.ldxw, w.y32, w.ldxw, w.split, r.sp_elems,
-                                skip, st);
+        if ((s = minv(skip))) return s;
+        if (!pcg) {
+            if ((s = refine_update<T>(n, S, w.xr, w.d32, w.ldxw, w.dmax, w.xmax, skip, st))) return s;
+        } else {
+            double *z = (it & 1) ? w.z1 : w.z0, *zp = (it & 1) ? w.z0 : w.z1;
+            if ((s = cm_to_rm<double, T>(n, S, w.d32, w.ldxw, z, skip, st))) return s;
+            if ((s = slice_dot(n, S, w.s, z, w.dpart, w.sz, skip, st))) return s;
+            if (it > 0 && (s = slice_dot(n, S, w.s, zp, w.dpart, w.szp, skip, st))) return s;
+            if ((s = pcg_beta(S, it == 0, w.sz, w.szp, w.gamma, w.beta, skip, st))) return s;
+            if ((s = pcg_direction(n, S, z, w.beta, w.p, skip, st))) return s;
+            s = spmm_rowmajor(m, S, A->rowptr, A->col, A->val, 1.0, w.p, 0.0, nullptr, w.q, skip, st);
+            if (s) return s;
+            if ((s = slice_dot(m, S, w.q, w.q, w.dpart, w.qq, skip, st))) return s;
+            if ((s = pcg_alpha(S, w.gamma, w.qq, w.alpha, skip, st))) return s;
+            if ((s = pcg_step(n, S, w.xr, w.p, w.alpha, w.dmax, w.xmax, skip, st))) return s;
+        }
+        // conjugate-gradient steps need not shrink monotonically: a longer
+        // run of non-contracting steps ends that form
+        s = refine_check(S, w.dmax, w.xmax, r.tol, it, r.max_iters, pcg ? 6 : 2, w.hist, w.done, r.info, st);
         if (s) return s;
-        s = trsm_upper<T>(n, S, r.QR, r.lda, r.Rinv, w.y32, w.ldxw, w.d32, w.ldxw, w.split, r.sp_elems, skip,
-                          st);
-        if (s) return s;
-        if ((s = refine_update<T>(n, S, w.xr, w.d32, w.ldxw, w.dmax, w.xmax, skip, st))) return s;
-        if ((s = refine_check(S, w.dmax, w.xmax, r.tol, it, r.max_iters, w.hist, w.done, r.info, st)))
-            return s;
+        if (r.progress && (s = progress_mark(st, CTQR_PROGRESS_SOLVE, it + 1, r.max_iters))) return s;
         if (host_sync) {
             bool done = false;
             if ((s = read_done(w.done, st, done))) return s;
@@ -646,6 +696,21 @@ ctqr_status refine_iters(SolveRun<T> &r, int it0, int it1, bool host_sync, hipSt
         }
     }
     return CTQR_OK;
+}
+
+// In-HBM factor: the two block substitutions of trsm.hip
+template <typename T>
+ctqr_status refine_iters(SolveRun<T> &r, int it0, int it1, bool host_sync, hipStream_t st, int *ran)
+{
+    SolveWS<T> &w = r.w;
+    auto minv = [&](const int *skip) -> ctqr_status {
+        ctqr_status s = trsm_upper_trans<T>(r.n, r.S, r.QR, r.lda, r.Rinv, w.s32, w.ldxw, w.y32, w.ldxw, w.split,
+                                            r.sp_elems, skip, st);
+        if (s) return s;
+        return trsm_upper<T>(r.n, r.S, r.QR, r.lda, r.Rinv, w.y32, w.ldxw, w.d32, w.ldxw, w.split, r.sp_elems, skip,
+                             st);
+    };
+    return refine_iters_with(r, it0, it1, host_sync, st, ran, minv);
 }
 
 // The first S_out slices of the solution into X (FP64, column-major).
@@ -662,12 +727,12 @@ ctqr_status solve_finish(SolveRun<T> &r, int S_out, double *X, int64_t ldx, hipS
 template <typename T>
 ctqr_status solve_impl(int64_t m64, int64_t n64, const T *QR, int64_t lda, const T *Tf,
                        const double *tau, const T *Rinv_in, int nb, const double *B, int64_t ldb, int S,
-                       double *X, int64_t ldx, const ctqr_sparse *A64, double tol, int max_iters, void *work,
-                       ctqr_info *info, hipStream_t st)
+                       double *X, int64_t ldx, const ctqr_sparse *A64, double tol, int max_iters, int method,
+                       void *work, ctqr_info *info, hipStream_t st)
 {
     (void)tau;
     SolveRun<T> r = make_run<T>(m64, n64, QR, lda, Tf, Rinv_in, nb, B, ldb, S, A64, tol, max_iters, work, info,
-                                true);
+                                true, method);
     ctqr_status s = solve_start(r, st);
     if (s) return s;
     if (r.refine() && (s = refine_iters(r, 0, max_iters, true, st, nullptr))) return s;
@@ -748,11 +813,12 @@ ctqr_status ooc_upper_trans(SolveRun<T> &r, TileCache<T> &tc, const T *QRdev, T 
 template <typename T>
 ctqr_status solve_ooc_impl(int64_t m64, int64_t n64, const T *QR_dev, const T *QR_host, int64_t lda, int n_dev,
                            int tile, const T *Tf, const T *Rinv, int nb, const double *B, int64_t ldb, int S,
-                           double *X, int64_t ldx, const ctqr_sparse *A64, double tol, int max_iters, void *work,
-                           ctqr_info *info, hipStream_t st)
+                           double *X, int64_t ldx, const ctqr_sparse *A64, double tol, int max_iters, int method,
+                           void *work, ctqr_info *info, hipStream_t st)
 {
     SolveRun<T> r = make_run<T>(m64, n64, QR_dev, lda, Tf, Rinv, nb, B, ldb, S, A64, tol, max_iters, work, info,
-                                false);
+                                false, method);
+    r.progress = true;
     Carve c(work);
     c.off = r.w.bytes;
     TileCache<T> tc{QR_host, c.take<T>(lda * (int64_t)tile), lda, n_dev, tile, (int)n64};
@@ -775,25 +841,13 @@ ctqr_status solve_ooc_impl(int64_t m64, int64_t n64, const T *QR_dev, const T *Q
     if (!r.refine()) return copy_cm<double, T>(n, S, w.Xw, w.ldxw, X, ldx, st);
     if ((s = cm_to_rm<double, T>(n, S, w.Xw, w.ldxw, w.xr, nullptr, st))) return s;
     if ((s = cm_to_rm<double, double>(m, S, B, ldb, w.Br, nullptr, st))) return s;
-    if ((s = fill_f64(w.hist, 8, 0.0, st))) return s;
-    if ((s = fill_u32((unsigned *)w.dmax, 2LL * S, 0u, st))) return s;
-    if ((s = fill_u32((unsigned *)w.xmax, 2LL * S, 0u, st))) return s;
-    for (int it = 0; it < max_iters; ++it) {
-        const int *skip = w.done;
-        s = spmm_rowmajor(m, S, A64->rowptr, A64->col, A64->val, -1.0, w.xr, 1.0, w.Br, w.r, skip, st);
-        if (s) return s;
-        s = spmm_rowmajor(n, S, A64->colptr, A64->row, A64->cval, 1.0, w.r, 0.0, nullptr, w.s, skip, st);
-        if (s) return s;
-        if ((s = rm_to_cm<T, double>(n, S, w.s, w.s32, w.ldxw, skip, st))) return s;
-        if ((s = ooc_upper_trans(r, tc, QR_dev, w.s32, w.y32, skip, st))) return s;
-        if ((s = ooc_upper(r, tc, QR_dev, w.y32, w.ldxw, w.d32, w.ldxw, skip, st))) return s;
-        if ((s = refine_update<T>(n, S, w.xr, w.d32, w.ldxw, w.dmax, w.xmax, skip, st))) return s;
-        if ((s = refine_check(S, w.dmax, w.xmax, tol, it, max_iters, w.hist, w.done, info, st))) return s;
-        if ((s = progress_mark(st, CTQR_PROGRESS_SOLVE, it + 1, max_iters))) return s;
-        bool done = false;
-        if ((s = read_done(w.done, st, done))) return s;
-        if (done) break;
-    }
+    if ((s = refine_setup(r, st))) return s;
+    auto minv = [&](const int *skip) -> ctqr_status {
+        ctqr_status e = ooc_upper_trans(r, tc, QR_dev, w.s32, w.y32, skip, st);
+        if (e) return e;
+        return ooc_upper(r, tc, QR_dev, w.y32, w.ldxw, w.d32, w.ldxw, skip, st);
+    };
+    if ((s = refine_iters_with(r, 0, max_iters, true, st, nullptr, minv))) return s;
     return rm_to_cm<double, double>(n, S, w.xr, X, ldx, nullptr, st);
 }
 
@@ -854,7 +908,7 @@ SolverLayout solver_layout(const ctqr_solver_desc *d, void *work, int smax, int6
     L.info = c.take<ctqr_info>(1);
     L.Bpad = c.take<double>(ldbp * smax);
     L.swork = c.take<char>(0);
-    const bool refine = d->A64 != nullptr && d->max_iters > 0;
+    const int refine = d->A64 != nullptr && d->max_iters > 0 ? (d->refine_method == CTQR_REFINE_PCG ? 2 : 1) : 0;
     size_t sb = d->dtype == CTQR_F64 ? carve_solve<double>(nullptr, d->m, d->n, d->nb, smax, refine, false).bytes
                                      : carve_solve<float>(nullptr, d->m, d->n, d->nb, smax, refine, false).bytes;
     L.bytes = c.off + sb + 256;
@@ -867,7 +921,7 @@ SolveRun<T> solver_run(ctqr_solver_t *sv, const SolverBucket &bk)
     const ctqr_solver_desc &d = sv->d;
     SolveRun<T> r = make_run<T>(d.m, d.n, (const T *)d.QR, d.lda, (const T *)d.T, (const T *)d.Rinv, d.nb,
                                 sv->Bpad, sv->ldbp, bk.S, sv->refine ? &sv->sp : nullptr, d.tol,
-                                sv->refine ? d.max_iters : 0, sv->swork, sv->info, false);
+                                sv->refine ? d.max_iters : 0, sv->swork, sv->info, false, d.refine_method);
     r.narrow = bk.narrow;
     return r;
 }
@@ -1243,20 +1297,22 @@ ctqr_status ctqr_solve_workspace(int64_t m, int64_t n, ctqr_dtype dtype, int32_t
     if (dtype != CTQR_F64 && dtype != CTQR_F32) return CTQR_EINVAL;
     nb = resolve_nb(nb);
     if (!nb_ok(nb)) return CTQR_EINVAL;
-    *bytes = dtype == CTQR_F64 ? carve_solve<double>(nullptr, m, n, nb, nslices, refine != 0).bytes
-                               : carve_solve<float>(nullptr, m, n, nb, nslices, refine != 0).bytes;
+    if (refine < 0 || refine > 2) return CTQR_EINVAL;
+    *bytes = dtype == CTQR_F64 ? carve_solve<double>(nullptr, m, n, nb, nslices, refine).bytes
+                               : carve_solve<float>(nullptr, m, n, nb, nslices, refine).bytes;
     return CTQR_OK;
 }
 
 ctqr_status ctqr_qr_solve_slices(int64_t m, int64_t n, ctqr_dtype dtype, const void *QR, int64_t lda,
                                  const void *T, const double *tau, const void *Rinv, int32_t nb, const double *B,
                                  int64_t ldb, int32_t nslices, double *X, int64_t ldx,
-                                 const ctqr_sparse *A64, double tol, int32_t max_iters, void *work,
-                                 size_t work_bytes, ctqr_info *info, hipStream_t stream)
+                                 const ctqr_sparse *A64, double tol, int32_t max_iters, int32_t refine_method,
+                                 void *work, size_t work_bytes, ctqr_info *info, hipStream_t stream)
 {
     try {
         if (m < n || n < 1 || m >= INT32_MAX || nslices < 1) return CTQR_EINVAL;
         if (!QR || !T || !tau || !B || !X || !work || !info) return CTQR_EINVAL;
+        if (refine_method != CTQR_REFINE_CSNE && refine_method != CTQR_REFINE_PCG) return CTQR_EINVAL;
         if (dtype != CTQR_F64 && dtype != CTQR_F32) return CTQR_EINVAL;
         if (lda < m || lda % 4 != 0 || ldb < m || ldx < n) return CTQR_EINVAL;
         if (!aligned16(QR) || !aligned16(T) || !aligned16(work)) return CTQR_EINVAL;
@@ -1267,14 +1323,16 @@ ctqr_status ctqr_qr_solve_slices(int64_t m, int64_t n, ctqr_dtype dtype, const v
             return CTQR_EINVAL;
         if (A64 && (max_iters < 0 || !(tol >= 0.0))) return CTQR_EINVAL;
         size_t need = 0;
-        ctqr_solve_workspace(m, n, dtype, nb, nslices, A64 != nullptr && max_iters > 0, &need);
+        const int refine = A64 != nullptr && max_iters > 0 ? (refine_method == CTQR_REFINE_PCG ? 2 : 1) : 0;
+        ctqr_solve_workspace(m, n, dtype, nb, nslices, refine, &need);
         if (work_bytes < need) return CTQR_ENOMEM;
         if (Rinv && !aligned16(Rinv)) return CTQR_EINVAL;
         if (dtype == CTQR_F64)
             return solve_impl<double>(m, n, (const double *)QR, lda, (const double *)T, tau, (const double *)Rinv,
-                                      nb, B, ldb, nslices, X, ldx, A64, tol, max_iters, work, info, stream);
+                                      nb, B, ldb, nslices, X, ldx, A64, tol, max_iters, refine_method, work, info,
+                                      stream);
         return solve_impl<float>(m, n, (const float *)QR, lda, (const float *)T, tau, (const float *)Rinv, nb, B,
-                                 ldb, nslices, X, ldx, A64, tol, max_iters, work, info, stream);
+                                 ldb, nslices, X, ldx, A64, tol, max_iters, refine_method, work, info, stream);
     } catch (...) {
         return CTQR_EHIP;
     }
@@ -1296,6 +1354,7 @@ ctqr_status solver_desc_check(const ctqr_solver_desc *d)
               !A->cval))
         return CTQR_EINVAL;
     if (A && (d->max_iters < 0 || !(d->tol >= 0.0))) return CTQR_EINVAL;
+    if (d->refine_method != CTQR_REFINE_CSNE && d->refine_method != CTQR_REFINE_PCG) return CTQR_EINVAL;
     return CTQR_OK;
 }
 }  // namespace
@@ -1425,8 +1484,9 @@ ctqr_status ctqr_solve_ooc_workspace(int64_t m, int64_t n, ctqr_dtype dtype, int
     nb = resolve_nb(nb);
     if (!nb_ok(nb)) return CTQR_EINVAL;
     const size_t esz = dtype == CTQR_F64 ? sizeof(double) : sizeof(float);
-    const size_t sb = dtype == CTQR_F64 ? carve_solve<double>(nullptr, m, n, nb, nslices, refine != 0, false).bytes
-                                        : carve_solve<float>(nullptr, m, n, nb, nslices, refine != 0, false).bytes;
+    if (refine < 0 || refine > 2) return CTQR_EINVAL;
+    const size_t sb = dtype == CTQR_F64 ? carve_solve<double>(nullptr, m, n, nb, nslices, refine, false).bytes
+                                        : carve_solve<float>(nullptr, m, n, nb, nslices, refine, false).bytes;
     *bytes = sb + 256 + (size_t)lda * (size_t)tile_cols * esz + 256;
     return CTQR_OK;
 }
@@ -1434,12 +1494,14 @@ ctqr_status ctqr_solve_ooc_workspace(int64_t m, int64_t n, ctqr_dtype dtype, int
 ctqr_status ctqr_qr_solve_ooc(int64_t m, int64_t n, ctqr_dtype dtype, const void *QR_dev, const void *QR_host,
                               int64_t lda, int64_t n_dev, int64_t tile_cols, const void *T, const double *tau,
                               const void *Rinv, int32_t nb, const double *B, int64_t ldb, int32_t nslices, double *X,
-                              int64_t ldx, const ctqr_sparse *A64, double tol, int32_t max_iters, void *work,
-                              size_t work_bytes, ctqr_info *info, hipStream_t stream)
+                              int64_t ldx, const ctqr_sparse *A64, double tol, int32_t max_iters,
+                              int32_t refine_method, void *work, size_t work_bytes, ctqr_info *info,
+                              hipStream_t stream)
 {
     try {
         if (m < n || n < 1 || m >= INT32_MAX || nslices < 1) return CTQR_EINVAL;
         if (!T || !tau || !Rinv || !B || !X || !work || !info) return CTQR_EINVAL;
+        if (refine_method != CTQR_REFINE_CSNE && refine_method != CTQR_REFINE_PCG) return CTQR_EINVAL;
         if (dtype != CTQR_F64 && dtype != CTQR_F32) return CTQR_EINVAL;
         if (lda < m || lda % 4 != 0 || ldb < m || ldx < n) return CTQR_EINVAL;
         if (!aligned16(T) || !aligned16(Rinv) || !aligned16(work)) return CTQR_EINVAL;
@@ -1455,7 +1517,8 @@ ctqr_status ctqr_qr_solve_ooc(int64_t m, int64_t n, ctqr_dtype dtype, const void
             return CTQR_EINVAL;
         if (A64 && (max_iters < 0 || !(tol >= 0.0))) return CTQR_EINVAL;
         size_t need = 0;
-        ctqr_solve_ooc_workspace(m, n, dtype, nb, nslices, A64 != nullptr && max_iters > 0, lda, tile_cols, &need);
+        const int refine = A64 != nullptr && max_iters > 0 ? (refine_method == CTQR_REFINE_PCG ? 2 : 1) : 0;
+        ctqr_solve_ooc_workspace(m, n, dtype, nb, nslices, refine, lda, tile_cols, &need);
         if (work_bytes < need) return CTQR_ENOMEM;
         if (n_dev < n) {
             hipPointerAttribute_t at{};
@@ -1467,10 +1530,10 @@ ctqr_status ctqr_qr_solve_ooc(int64_t m, int64_t n, ctqr_dtype dtype, const void
         if (dtype == CTQR_F64)
             return solve_ooc_impl<double>(m, n, (const double *)QR_dev, (const double *)QR_host, lda, (int)n_dev,
                                           (int)tile_cols, (const double *)T, (const double *)Rinv, nb, B, ldb, nslices,
-                                          X, ldx, A64, tol, max_iters, work, info, stream);
+                                          X, ldx, A64, tol, max_iters, refine_method, work, info, stream);
         return solve_ooc_impl<float>(m, n, (const float *)QR_dev, (const float *)QR_host, lda, (int)n_dev,
                                      (int)tile_cols, (const float *)T, (const float *)Rinv, nb, B, ldb, nslices, X,
-                                     ldx, A64, tol, max_iters, work, info, stream);
+                                     ldx, A64, tol, max_iters, refine_method, work, info, stream);
     } catch (...) {
         return CTQR_EHIP;
     }

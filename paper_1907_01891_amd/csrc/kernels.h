@@ -119,6 +119,23 @@ template <typename TD>
 ctqr_status refine_update(int64_t n, int S, double *x, const TD *d, int64_t ldd,
                           unsigned long long *dmax, unsigned long long *xmax, const int *skip,
                           hipStream_t st);
+// stall_limit: consecutive non-contracting iterations that end the
+// refinement (converged at the FP64 floor, else CTQR_NOT_CONVERGED)
 ctqr_status refine_check(int S, unsigned long long *dmax, unsigned long long *xmax, double tol,
-                         int it, int max_iters, double *hist, int *done, ctqr_info *info,
+                         int it, int max_iters, int stall_limit, double *hist, int *done, ctqr_info *info,
                          hipStream_t st);
+
+// ---- refine.hip (conjugate-gradient form of the refinement) -----------------
+constexpr int PCG_DOT_BLOCKS = 256;
+size_t slice_dot_partial_elems(int S);
+// out[s] = sum_i x[i, s] y[i, s] (row-major, deterministic two-pass sum)
+ctqr_status slice_dot(int64_t rows, int S, const double *x, const double *y, double *partial, double *out,
+                      const int *skip, hipStream_t st);
+ctqr_status pcg_beta(int S, int first, const double *sz, const double *szp, double *gamma, double *beta,
+                     const int *skip, hipStream_t st);
+ctqr_status pcg_alpha(int S, const double *gamma, const double *qq, double *alpha, const int *skip,
+                      hipStream_t st);
+ctqr_status pcg_direction(int64_t rows, int S, const double *z, const double *beta, double *p, const int *skip,
+                          hipStream_t st);
+ctqr_status pcg_step(int64_t rows, int S, double *x, const double *p, const double *alpha,
+                     unsigned long long *dmax, unsigned long long *xmax, const int *skip, hipStream_t st);

@@ -230,7 +230,7 @@ __global__ void refine_update_kernel(int64_t n, int S, double *__restrict__ x, c
 // update, hist[1] the number of consecutive non-contracting iterations.
 __global__ __launch_bounds__(256)
 void refine_check_kernel(int S, unsigned long long *dmax, unsigned long long *xmax, double tol, int it,
-                         int max_iters, double *hist, int *done, ctqr_info *info)
+                         int max_iters, int stall_limit, double *hist, int *done, ctqr_info *info)
 {
     if (*done) return;
     __shared__ double red[256];
@@ -273,9 +273,9 @@ void refine_check_kernel(int S, unsigned long long *dmax, unsigned long long *xm
             int stalls = (it > 0 && rel > 0.9 * prev) ? (int)hist[1] + 1 : 0;
             hist[0] = rel;
             hist[1] = stalls;
-            if (stalls >= 2 && rel <= STALL_FLOOR) {
+            if (stalls >= stall_limit && rel <= STALL_FLOOR) {
                 *done = 1;
-            } else if (stalls >= 2 || it + 1 >= max_iters) {
+            } else if (stalls >= stall_limit || it + 1 >= max_iters) {
                 info_event(info, CTQR_NOT_CONVERGED, -1);
                 *done = 1;
             }
@@ -396,11 +396,11 @@ ctqr_status refine_update(int64_t n, int S, double *x, const TD *d, int64_t ldd,
 }
 
 ctqr_status refine_check(int S, unsigned long long *dmax, unsigned long long *xmax, double tol,
-                         int it, int max_iters, double *hist, int *done, ctqr_info *info,
+                         int it, int max_iters, int stall_limit, double *hist, int *done, ctqr_info *info,
                          hipStream_t st)
 {
-    LAUNCH_TRY(refine_check_kernel, dim3(1), dim3(256), 0, st, S, dmax, xmax, tol, it, max_iters, hist,
-               done, info);
+    LAUNCH_TRY(refine_check_kernel, dim3(1), dim3(256), 0, st, S, dmax, xmax, tol, it, max_iters, stall_limit,
+               hist, done, info);
     return CTQR_OK;
 }
 

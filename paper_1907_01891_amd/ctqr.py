@@ -29,6 +29,8 @@ CTQR_F32 = 1
 CTQR_PREC_FP64 = 0
 CTQR_PREC_FP32_MFMA = 1
 CTQR_PREC_BF16_MFMA = 2
+CTQR_REFINE_CSNE = 0
+CTQR_REFINE_PCG = 1
 
 
 class ctqr_geometry(ctypes.Structure):
@@ -50,7 +52,8 @@ class ctqr_info(ctypes.Structure):
 class ctqr_solver_desc(ctypes.Structure):
     _fields_ = [("m", c_i64), ("n", c_i64), ("dtype", c_i32), ("nb", c_i32), ("QR", c_vp), ("lda", c_i64),
                 ("T", c_vp), ("tau", c_vp), ("Rinv", c_vp), ("A64", ctypes.POINTER(ctqr_sparse)),
-                ("tol", c_dbl), ("max_iters", c_i32), ("max_slices", c_i32)]
+                ("tol", c_dbl), ("max_iters", c_i32), ("max_slices", c_i32), ("refine_method", c_i32),
+                ("pad", c_i32)]
 
 
 CTQR_PROGRESS_FACTOR = 1
@@ -75,12 +78,12 @@ _SIGNATURES = {
                                    c_vp, c_vp, c_sz, c_vp, c_vp]),
     "ctqr_solve_ooc_workspace": (c_i32, [c_i64, c_i64, c_i32, c_i32, c_i32, c_i32, c_i64, c_i64, _P(c_sz)]),
     "ctqr_qr_solve_ooc": (c_i32, [c_i64, c_i64, c_i32, c_vp, c_vp, c_i64, c_i64, c_i64, c_vp, c_vp, c_vp, c_i32,
-                                  c_vp, c_i64, c_i32, c_vp, c_i64, _P(ctqr_sparse), c_dbl, c_i32, c_vp, c_sz, c_vp,
-                                  c_vp]),
+                                  c_vp, c_i64, c_i32, c_vp, c_i64, _P(ctqr_sparse), c_dbl, c_i32, c_i32, c_vp, c_sz,
+                                  c_vp, c_vp]),
     "ctqr_qr_rinv_bytes": (c_i32, [c_i64, c_i32, _P(c_sz)]),
     "ctqr_solve_workspace": (c_i32, [c_i64, c_i64, c_i32, c_i32, c_i32, c_i32, _P(c_sz)]),
     "ctqr_qr_solve_slices": (c_i32, [c_i64, c_i64, c_i32, c_vp, c_i64, c_vp, c_vp, c_vp, c_i32,
-                                     c_vp, c_i64, c_i32, c_vp, c_i64, _P(ctqr_sparse), c_dbl, c_i32,
+                                     c_vp, c_i64, c_i32, c_vp, c_i64, _P(ctqr_sparse), c_dbl, c_i32, c_i32,
                                      c_vp, c_sz, c_vp, c_vp]),
     "ctqr_solver_workspace": (c_i32, [_P(ctqr_solver_desc), _P(c_sz)]),
     "ctqr_solver_create": (c_i32, [_P(ctqr_solver_desc), c_vp, c_sz, _P(c_vp)]),
@@ -195,10 +198,11 @@ def ctqr_solve_ooc_workspace(m, n, dtype, nb, nslices, refine, lda, tile_cols):
 
 
 def ctqr_qr_solve_ooc(m, n, dtype, QR_dev, QR_host, lda, n_dev, tile_cols, T_ptr, tau_ptr, rinv_ptr, nb, B_ptr, ldb,
-                      nslices, X_ptr, ldx, sparse, tol, max_iters, work_ptr, work_bytes, info_ptr, stream):
+                      nslices, X_ptr, ldx, sparse, tol, max_iters, refine_method, work_ptr, work_bytes, info_ptr,
+                      stream):
     return lib().ctqr_qr_solve_ooc(m, n, dtype, QR_dev, QR_host, lda, n_dev, tile_cols, T_ptr, tau_ptr, rinv_ptr, nb,
                                    B_ptr, ldb, nslices, X_ptr, ldx, ctypes.byref(sparse) if sparse is not None else None,
-                                   tol, max_iters, work_ptr, work_bytes, info_ptr, stream)
+                                   tol, max_iters, refine_method, work_ptr, work_bytes, info_ptr, stream)
 
 
 def ctqr_qr_rinv_bytes(n, dtype):
@@ -214,10 +218,10 @@ def ctqr_solve_workspace(m, n, dtype, nb, nslices, refine):
 
 
 def ctqr_qr_solve_slices(m, n, dtype, QR_ptr, lda, T_ptr, tau_ptr, rinv_ptr, nb, B_ptr, ldb, nslices, X_ptr, ldx,
-                         sparse, tol, max_iters, work_ptr, work_bytes, info_ptr, stream):
+                         sparse, tol, max_iters, refine_method, work_ptr, work_bytes, info_ptr, stream):
     return lib().ctqr_qr_solve_slices(m, n, dtype, QR_ptr, lda, T_ptr, tau_ptr, rinv_ptr, nb, B_ptr, ldb, nslices,
                                       X_ptr, ldx, ctypes.byref(sparse) if sparse is not None else None,
-                                      tol, max_iters, work_ptr, work_bytes, info_ptr, stream)
+                                      tol, max_iters, refine_method, work_ptr, work_bytes, info_ptr, stream)
 
 
 def ctqr_solver_workspace(desc):

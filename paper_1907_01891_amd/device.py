@@ -164,19 +164,19 @@ class QRFactor:
                                  wp, wb, self.info.ptr, stream_handle(stream)), "ctqr_qr_factor")
         return self
 
-    def solve(self, B, X=None, sparse=None, tol=1e-13, max_iters=0, stream=None):
+    def solve(self, B, X=None, sparse=None, tol=1e-13, max_iters=0, method=C.CTQR_REFINE_CSNE, stream=None):
         """X = R^-1 Q^T B (FP64, column-major), refined with the sparse A if given."""
         S = B.shape[1]
         if X is None:
             X = colmajor(self.n, S, torch.float64, B.device)
-        refine = 1 if (sparse is not None and max_iters > 0) else 0
+        refine = (2 if method == C.CTQR_REFINE_PCG else 1) if (sparse is not None and max_iters > 0) else 0
         wp, wb = self.swork.get(C.ctqr_solve_workspace(self.m, self.n, self.dtype, self.nb, S, refine))
         C.check(C.ctqr_qr_solve_slices(self.m, self.n, self.dtype, ctypes.c_void_p(self.A.data_ptr()),
                                        ld_of(self.A), ctypes.c_void_p(self.T.data_ptr()),
                                        ctypes.c_void_p(self.tau.data_ptr()),
                                        ctypes.c_void_p(self.Rinv.data_ptr()), self.nb,
                                        ctypes.c_void_p(B.data_ptr()), ld_of(B), S,
-                                       ctypes.c_void_p(X.data_ptr()), ld_of(X), sparse, tol, max_iters,
+                                       ctypes.c_void_p(X.data_ptr()), ld_of(X), sparse, tol, max_iters, method,
                                        wp, wb, self.sinfo.ptr, stream_handle(stream)),
                 "ctqr_qr_solve_slices")
         return X
@@ -219,12 +219,12 @@ class OocFactor:
                 "ctqr_qr_factor_ooc")
         return self
 
-    def solve(self, B, X=None, sparse=None, tol=1e-13, max_iters=0, stream=None):
+    def solve(self, B, X=None, sparse=None, tol=1e-13, max_iters=0, method=C.CTQR_REFINE_CSNE, stream=None):
         """X = R^-1 Q^T B with the out-of-core factor (ctqr_qr_solve_ooc)."""
         S = B.shape[1]
         if X is None:
             X = colmajor(self.n, S, torch.float64, B.device)
-        refine = 1 if (sparse is not None and max_iters > 0) else 0
+        refine = (2 if method == C.CTQR_REFINE_PCG else 1) if (sparse is not None and max_iters > 0) else 0
         if not hasattr(self, "swork"):
             self.swork, self.sinfo = Workspace(self.T.device), Info(self.T.device)
         wp, wb = self.swork.get(C.ctqr_solve_ooc_workspace(self.m, self.n, self.dtype, self.nb, S, refine, self.lda,
@@ -232,7 +232,7 @@ class OocFactor:
         ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
         C.check(C.ctqr_qr_solve_ooc(self.m, self.n, self.dtype, ptr(self.A_dev), ptr(self.A_host), self.lda,
                                     self.n_dev, self.tile_cols, ptr(self.T), ptr(self.tau), ptr(self.Rinv), self.nb,
-                                    ptr(B), ld_of(B), S, ptr(X), ld_of(X), sparse, tol, max_iters, wp, wb,
+                                    ptr(B), ld_of(B), S, ptr(X), ld_of(X), sparse, tol, max_iters, method, wp, wb,
                                     self.sinfo.ptr, stream_handle(stream)), "ctqr_qr_solve_ooc")
         return X
 
@@ -250,13 +250,15 @@ class Solver:
     """Batched solver over a stored factor (ctqr_solver_*): requests of 1 ..
     max_slices slices, one HIP graph per power-of-two slice bucket."""
 
-    def __init__(self, qr, max_slices, sparse=None, tol=1e-13, max_iters=0, device="cuda"):
+    def __init__(self, qr, max_slices, sparse=None, tol=1e-13, max_iters=0, method=C.CTQR_REFINE_CSNE,
+                 device="cuda"):
         self.qr = qr
         self.sparse = sparse    # ctqr_sparse (kept alive: the solver copies the struct only)
         self.desc = C.ctqr_solver_desc(qr.m, qr.n, qr.dtype, qr.nb, qr.A.data_ptr(), ld_of(qr.A), qr.T.data_ptr(),
                                        qr.tau.data_ptr(), qr.Rinv.data_ptr(),
                                        ctypes.pointer(sparse) if sparse is not None else None,
-                                       float(tol), int(max_iters) if sparse is not None else 0, int(max_slices))
+                                       float(tol), int(max_iters) if sparse is not None else 0, int(max_slices),
+                                       int(method), 0)
         nbytes = C.ctqr_solver_workspace(self.desc)
         self.work = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
         self.h = C.ctqr_solver_create(self.desc, ctypes.c_void_p(self.work.data_ptr()), self.work.numel())

@@ -73,7 +73,8 @@ def test_workspace_queries():
     assert a > 0 and b > 0 and a > b
     s0 = C.ctqr_solve_workspace(3072, 1024, C.CTQR_F64, 0, 4, 0)
     s1 = C.ctqr_solve_workspace(3072, 1024, C.CTQR_F64, 0, 4, 1)
-    assert 0 < s0 < s1
+    s2 = C.ctqr_solve_workspace(3072, 1024, C.CTQR_F64, 0, 4, 2)
+    assert 0 < s0 < s1 < s2
     assert C.ctqr_build_workspace(_geom()) > 0
 
 
@@ -121,12 +122,13 @@ def test_solve_rejects_before_any_hip_call():
         a.update(kw)
         return L.ctqr_qr_solve_slices(a["m"], a["n"], a["dtype"], a["QR"], a["lda"], a["T"], a["tau"], None, a["nb"],
                                       a["B"], a["ldb"], a["S"], a["X"], a["ldx"], a["sp"], a["tol"], a["it"],
-                                      a["work"], a["wb"], a["info"], a["st"])
+                                      a.get("method", 0), a["work"], a["wb"], a["info"], a["st"])
     assert call(S=0) == C.CTQR_EINVAL
     assert call(ldb=99) == C.CTQR_EINVAL
     assert call(ldx=49) == C.CTQR_EINVAL
     assert call(B=None) == C.CTQR_EINVAL
     assert call(wb=8) == C.CTQR_ENOMEM
+    assert call(method=7) == C.CTQR_EINVAL
     bad = C.ctqr_sparse(99, 50, 10, 4096, 4096, 4096, 4096, 4096, 4096)
     assert call(sp=ctypes.byref(bad), it=3) == C.CTQR_EINVAL
 
@@ -151,21 +153,21 @@ def test_build_rejects():
 def _solver_desc(**kw):
     p = 4096
     d = dict(m=3072, n=1024, dtype=C.CTQR_F64, nb=0, QR=p, lda=3072, T=p, tau=p, Rinv=p, A64=None, tol=1e-13,
-             max_iters=0, max_slices=64)
+             max_iters=0, max_slices=64, method=0)
     d.update(kw)
     return C.ctqr_solver_desc(d["m"], d["n"], d["dtype"], d["nb"], d["QR"], d["lda"], d["T"], d["tau"], d["Rinv"],
-                              d["A64"], d["tol"], d["max_iters"], d["max_slices"])
+                              d["A64"], d["tol"], d["max_iters"], d["max_slices"], d["method"], 0)
 
 
 def test_solver_desc_layout_and_workspace():
-    assert ctypes.sizeof(C.ctqr_solver_desc) == 88
+    assert ctypes.sizeof(C.ctqr_solver_desc) == 96
     b64 = C.ctqr_solver_workspace(_solver_desc(max_slices=64))
     assert b64 >= 3072 * 64 * 8                               # the padded request buffer at least
     assert C.ctqr_solver_workspace(_solver_desc(max_slices=40)) == b64     # rounded up to the bucket
     assert C.ctqr_solver_workspace(_solver_desc(max_slices=65)) > b64
 
 
-@pytest.mark.parametrize("kw", [dict(max_slices=0), dict(max_slices=4097), dict(Rinv=None), dict(QR=None),
+@pytest.mark.parametrize("kw", [dict(max_slices=0), dict(max_slices=4097), dict(Rinv=None), dict(QR=None), dict(method=3),
                                 dict(lda=3000), dict(lda=3074), dict(m=100), dict(nb=48), dict(dtype=5),
                                 dict(Rinv=4100)])
 def test_solver_rejects(kw):

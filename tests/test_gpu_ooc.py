@@ -93,8 +93,9 @@ def test_sparse_to_dense_matches_build(gpu):
     assert torch.equal(part.cpu(), S.A[:, 100:700].cpu())
 
 
-@pytest.mark.parametrize("name,n_dev,dt", [("ct48", 0, "f64"), ("ct48", 0, "f32"), ("ct64", 2048, "f32")])
-def test_ooc_solve_matches_in_core_and_oracle(gpu, name, n_dev, dt):
+@pytest.mark.parametrize("name,n_dev,dt,method", [("ct48", 0, "f64", 0), ("ct48", 0, "f32", 0),
+                                                  ("ct64", 2048, "f32", 0), ("ct64", 2048, "f32", 1)])
+def test_ooc_solve_matches_in_core_and_oracle(gpu, name, n_dev, dt, method):
     from gpu_helpers import oracle_problem, oracle_factor, DeviceSparse
     from oracle import lsq
     g, A, X, B = oracle_problem(name, n_slices=40)
@@ -110,7 +111,7 @@ def test_ooc_solve_matches_in_core_and_oracle(gpu, name, n_dev, dt):
     O.load(to_colmajor(Ad, dtype=dtype, device="cpu"))
     O.factor()
     spA = DeviceSparse(A)
-    kw = {} if dt == "f64" else dict(sparse=spA.sp, tol=1e-14, max_iters=30)
+    kw = {} if dt == "f64" else dict(sparse=spA.sp, tol=1e-14, max_iters=30, method=method)
     for S in (4, 40):
         _print_case("ooc solve", name, n_dev, dt, "S", S)
         Bd = to_colmajor(torch.as_tensor(B[:, :S]), dtype=torch.float64)

@@ -155,9 +155,10 @@ def test_exact_recovery_fp64(gpu, name):
     assert lsq.rel_err(Xg, X).max() <= 1e-11
 
 
+@pytest.mark.parametrize("method", [C.CTQR_REFINE_CSNE, C.CTQR_REFINE_PCG])
 @pytest.mark.parametrize("name,nb", [("ct24", 64), ("ct32", 256), ("ct40", 128)])
-def test_mixed_fp32_refined_matches_oracle(gpu, name, nb):
-    _print_case("mixed fp32", name, nb)
+def test_mixed_fp32_refined_matches_oracle(gpu, name, nb, method):
+    _print_case("mixed fp32", name, nb, "method", method)
     g, A, X, B = oracle_problem(name)
     QRo, tauo = oracle_factor(name)
     Xo = hh.backsub(QRo, hh.apply_qt(QRo, tauo, B))
@@ -170,7 +171,7 @@ def test_mixed_fp32_refined_matches_oracle(gpu, name, nb):
     Bd = to_colmajor(torch.as_tensor(B), dtype=torch.float64)
     Xu = download(F.solve(Bd))                   # unrefined FP32 solve
     spA = DeviceSparse(A)
-    Xg = download(F.solve(Bd, sparse=spA.sp, tol=1e-14, max_iters=30))
+    Xg = download(F.solve(Bd, sparse=spA.sp, tol=1e-14, max_iters=30, method=method))
     torch.cuda.synchronize()
     si = F.sinfo.read()
     assert si.status == 0, (C.status_string(si.status), si.iters, si.max_rel_update)
@@ -232,11 +233,12 @@ def test_bf16_trailing_update_factor(gpu, name):
     Bd = to_colmajor(torch.as_tensor(B), dtype=torch.float64)
     Xo = hh.backsub(QRo, hh.apply_qt(QRo, tauo, B))
     spA = DeviceSparse(A)
-    Xg = download(F16.solve(Bd, sparse=spA.sp, tol=1e-14, max_iters=30))
-    torch.cuda.synchronize()
-    si = F16.sinfo.read()
-    err = lsq.rel_err(Xg, Xo).max()
-    print("bf16 refined: status %d iters %d err %.2e" % (si.status, si.iters, err))
-    assert si.status in (0, C.CTQR_NOT_CONVERGED)
-    if si.status == 0:
-        assert err <= 1e-10
+    for method in (C.CTQR_REFINE_CSNE, C.CTQR_REFINE_PCG):
+        Xg = download(F16.solve(Bd, sparse=spA.sp, tol=1e-14, max_iters=30, method=method))
+        torch.cuda.synchronize()
+        si = F16.sinfo.read()
+        err = lsq.rel_err(Xg, Xo).max()
+        print("bf16 refined (method %d): status %d iters %d err %.2e" % (method, si.status, si.iters, err))
+        assert si.status in (0, C.CTQR_NOT_CONVERGED)
+        if si.status == 0:
+            assert err <= 1e-10

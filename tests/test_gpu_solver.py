@@ -97,16 +97,17 @@ def test_solver_replays_bitwise(gpu):
     sv.close()
 
 
-def test_solver_mixed_refined(gpu):
+@pytest.mark.parametrize("method", [C.CTQR_REFINE_CSNE, C.CTQR_REFINE_PCG])
+def test_solver_mixed_refined(gpu, method):
     A, B, Xo = _problem()
     F = _factor(A, torch.float32, C.CTQR_PREC_FP32_MFMA)
     spA = DeviceSparse(A)
-    sv = Solver(F, max_slices=64, sparse=spA.sp, tol=1e-14, max_iters=30)
+    sv = Solver(F, max_slices=64, sparse=spA.sp, tol=1e-14, max_iters=30, method=method)
     for S in (5, 40):
         Bd = to_colmajor(torch.as_tensor(B[:, :S]), dtype=torch.float64)
         outs = []
         for rep in range(3):
-            _print_case("solver mixed", NAME, "S", S, "rep", rep)
+            _print_case("solver mixed", NAME, "method", method, "S", S, "rep", rep)
             outs.append(download(sv.solve(Bd)))
             torch.cuda.synchronize()
             info = sv.info.read()
@@ -124,7 +125,7 @@ def test_solver_mixed_refined(gpu):
         print("S %d iters %d err %.3e" % (S, calib, err.max()))
         assert err.max() <= 1e-10
         # the direct refined solve converges to the same least-squares solution
-        Xd = download(F.solve(Bd, sparse=spA.sp, tol=1e-14, max_iters=30))
+        Xd = download(F.solve(Bd, sparse=spA.sp, tol=1e-14, max_iters=30, method=method))
         assert lsq.rel_err(outs[0], Xd).max() <= 1e-10
     sv.close()
 
