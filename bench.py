@@ -562,7 +562,7 @@ def main():
         "qr_info_status": int(finfo.status),
         "rdiag_min_max": [finfo.rdiag_min, finfo.rdiag_max],
         "roofline": {
-            "bound": "mfma", "kernel": "gemm_nn_kernel<float> (trailing update C -= V W')",
+            "bound": "mfma", "kernel": "gemm_nn_kernel<float, 1, 128, false, false> (trailing update C -= V W')",
             "achieved": achieved, "peak": PEAK_TFLOPS["f32"], "unit": "TFLOP/s",
             "frac": (achieved / PEAK_TFLOPS["f32"]) if achieved else None,
             "traffic": measured_traffic(args.workload) if args.nb == 256 else None,
