@@ -190,13 +190,18 @@ void panel_qr_kernel(TS *__restrict__ A, int64_t lda, int m, int r0, int w, int 
                 __syncthreads();
             }
             if (tau != 0.0) {
-                const int nc = w - j - 1;
-                for (int idx = tid; idx < nrows * nc; idx += PNT) {
-                    int rr = idx / nc, cc = j + 1 + idx % nc;
-                    int g = row0 + rr;
-                    if (g >= p) {
-                        double v = g == p ? 1.0 : slab[rr * SLD + j];
-                        slab[rr * SLD + cc] -= (tau * xch[cc - j - 1]) * v;
+                // a_c -= (tau w_c) v: thread (cl, rg) takes column j+1+cl on
+                // rows rg, rg + 8, ... (as in the products above)
+                const int cl = tid % PW, rg = tid / PW;
+                const int c = j + 1 + cl;
+                if (c < w) {
+                    const double f = tau * xch[cl];
+                    for (int rr = rg; rr < nrows; rr += PNT / PW) {
+                        const int g = row0 + rr;
+                        if (g >= p) {
+                            const double v = g == p ? 1.0 : slab[rr * SLD + j];
+                            slab[rr * SLD + c] -= f * v;
+                        }
                     }
                 }
             }
