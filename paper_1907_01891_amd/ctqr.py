@@ -108,7 +108,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise RuntimeError("libctqr.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+            raise RuntimeError("libctqr.so is not built (%s); run paper_1907_01891_amd.build.build()" % LIB_PATH)
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGNATURES.items():
             f = getattr(L, name)
