@@ -182,8 +182,8 @@ ctqr_status ctqr_qr_workspace(int64_t m, int64_t n, ctqr_dtype dtype, ctqr_prec 
  *   Rinv   device, ctqr_qr_rinv_bytes(n, dtype) bytes in `dtype`, or NULL: the
  *          inverses of the 2048 x 2048 diagonal blocks of R and their
  *          transposes, stored with the factor so every later solve's block
- *          back substitution is a chain of MFMA products (the factorization
- *          "is computed just once and stored", Section II-A).  NULL skips them;
+ *          back substitution is a chain of MFMA products (the factorization is
+ *          done once and kept for every later solve, Section II-A).  NULL skips them;
  *          the solve then builds them in its workspace each call.
  *   info   device: rank deficiency / non-finite / barrier time-out.
  * Sections II-C ("QR factorization"), Eq. 3. */
