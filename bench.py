@@ -180,9 +180,10 @@ def request_stream_bench(args, log, F256, sp256, B256):
         cursor[g] = (cursor[g] + k) % pools[g].shape[1]
     Xs = [colmajor(solvers[g].qr.n, k, torch.float64, dev) for g, k in reqs]
     # warm-up: every bucket of both solvers calibrated and captured
+    buckets = {g: sorted({sv.query(k)[0] for k in range(1, 513)}) for g, sv in solvers.items()}
     t0 = time.perf_counter()
     for g, sv in solvers.items():
-        for b in [1 << i for i in range(10)]:
+        for b in buckets[g]:
             Bw = cyclic(pools[g], 0, b)
             for _ in range(2):
                 sv.solve(Bw)
@@ -223,8 +224,8 @@ def request_stream_bench(args, log, F256, sp256, B256):
         l = np.array([lat_ms[i] for i, (gg, _) in enumerate(reqs) if gg == g])
         per[g] = {"requests": int(l.size), "slices": int(sum(k for gg, k in reqs if gg == g)),
                   "p50_ms": float(np.percentile(l, 50)), "p99_ms": float(np.percentile(l, 99)),
-                  "slice_tiles": {str(1 << i): solvers[g].query(1 << i)[1] for i in range(10)},
-                  "graph_refine_iters": {str(1 << i): solvers[g].query(1 << i)[2] for i in range(10)}}
+                  "slice_tiles": {str(b): solvers[g].query(b)[1] for b in buckets[g]},
+                  "graph_refine_iters": {str(b): solvers[g].query(b)[2] for b in buckets[g]}}
     out = {"requests": len(reqs), "slices": int(total),
            "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
            "closed_loop_slices_per_s": total / t_closed, "queued_slices_per_s": total / t_queued,

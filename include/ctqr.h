@@ -304,9 +304,9 @@ ctqr_status ctqr_qr_solve_slices(int64_t m, int64_t n, ctqr_dtype dtype,
  * (Section II-A), and the per-slice cost falls as more slices share one read
  * of the factor (Section III-B).  A solver holds a stored factor (the
  * outputs of ctqr_qr_factor, Rinv required) and solves requests of 1 ..
- * max_slices slices.  A request of S slices runs in the smallest power-of-two
- * slice bucket >= S (the extra slices are zero and do not change the others'
- * results).  Each bucket's solve -- Q^T B, the back substitution and, with
+ * max_slices slices.  A request of S slices runs in the smallest slice
+ * bucket >= S -- the powers of two up to 64, then the multiples of 64 (the
+ * extra slices are zero and do not change the others' results).  Each bucket's solve -- Q^T B, the back substitution and, with
  * refinement, a calibrated number of refinement iterations -- is captured
  * once into a HIP graph and replayed on the caller's stream.
  *

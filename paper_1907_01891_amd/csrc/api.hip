@@ -855,8 +855,9 @@ ctqr_status solve_ooc_impl(int64_t m64, int64_t n64, const T *QR_dev, const T *Q
 // Batched solver: one stored factor serves a stream of requests (the
 // factorization does not depend on B and is computed once, Section II-A; the
 // per-slice cost falls as more slices share one read of the factor,
-// Section III-B).  Requests are padded to a power-of-two slice bucket; each
-// bucket's solve is captured once into a HIP graph and replayed.
+// Section III-B).  Requests are padded to a slice bucket (powers of two up to
+// 64, multiples of 64 above); each bucket's solve is captured once into a HIP
+// graph and replayed.
 // ---------------------------------------------------------------------------
 constexpr int SOLVER_MAX_SLICES = 4096;
 constexpr int GRAPH_EXTRA_ITERS = 2;   // refinement iterations beyond the calibrated count
@@ -874,6 +875,21 @@ int next_pow2(int x)
     int p = 1;
     while (p < x) p <<= 1;
     return p;
+}
+
+// Slice buckets: powers of two up to 64, then multiples of 64 (a request is
+// padded by less than 64 slices beyond 64).
+constexpr int BUCKET_STEP = 64;
+int bucket_cap(int max_slices)
+{
+    return max_slices <= BUCKET_STEP ? next_pow2(max_slices) : (int)round_up(max_slices, BUCKET_STEP);
+}
+std::vector<int> bucket_sizes(int cap)
+{
+    std::vector<int> v;
+    for (int b = 1; b <= std::min(cap, BUCKET_STEP); b <<= 1) v.push_back(b);
+    for (int b = 2 * BUCKET_STEP; b <= cap; b += BUCKET_STEP) v.push_back(b);
+    return v;
 }
 
 }  // namespace
@@ -1365,7 +1381,7 @@ ctqr_status ctqr_solver_workspace(const ctqr_solver_desc *desc, size_t *bytes)
     if (s || !bytes) return s ? s : CTQR_EINVAL;
     ctqr_solver_desc d = *desc;
     d.nb = resolve_nb(d.nb);
-    *bytes = solver_layout(&d, nullptr, next_pow2(d.max_slices), round_up(d.m, 64)).bytes;
+    *bytes = solver_layout(&d, nullptr, bucket_cap(d.max_slices), round_up(d.m, 64)).bytes;
     return CTQR_OK;
 }
 
@@ -1385,13 +1401,13 @@ ctqr_status ctqr_solver_create(const ctqr_solver_desc *desc, void *work, size_t 
         sv->refine = desc->A64 != nullptr && desc->max_iters > 0;
         if (desc->A64) sv->sp = *desc->A64;
         sv->d.A64 = desc->A64 ? &sv->sp : nullptr;
-        sv->smax = next_pow2(desc->max_slices);
+        sv->smax = bucket_cap(desc->max_slices);
         sv->ldbp = round_up(desc->m, 64);
         SolverLayout L = solver_layout(&sv->d, work, sv->smax, sv->ldbp);
         sv->info = L.info;
         sv->Bpad = L.Bpad;
         sv->swork = L.swork;
-        for (int b = 1; b <= sv->smax; b <<= 1) {
+        for (int b : bucket_sizes(sv->smax)) {
             SolverBucket bk;
             bk.S = b;
             bk.narrow = b <= DEFAULT_NARROW ? DEFAULT_NARROW : 0;

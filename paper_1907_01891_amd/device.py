@@ -248,7 +248,7 @@ class OocFactor:
 
 class Solver:
     """Batched solver over a stored factor (ctqr_solver_*): requests of 1 ..
-    max_slices slices, one HIP graph per power-of-two slice bucket."""
+    max_slices slices, one HIP graph per slice bucket (powers of two up to 64, multiples of 64 above)."""
 
     def __init__(self, qr, max_slices, sparse=None, tol=1e-13, max_iters=0, method=C.CTQR_REFINE_CSNE,
                  device="cuda"):

@@ -22,7 +22,7 @@ from gpu_helpers import oracle_problem, oracle_factor, DeviceSparse, upload_dens
 pytestmark = pytest.mark.gpu
 
 NAME = "ct40"          # m = 3744, n = 1600: 13 block columns at nb = 128, ragged edges
-N_SLICES = 40
+N_SLICES = 130
 
 
 def _print_case(*a):
@@ -57,8 +57,8 @@ def _other_gpu_work():
 def test_solver_fp64_matches_direct_and_oracle(gpu):
     A, B, Xo = _problem()
     F = _factor(A, torch.float64, C.CTQR_PREC_FP64)
-    sv = Solver(F, max_slices=64)
-    for S in (1, 3, 5, 8, 17, 32, 40):
+    sv = Solver(F, max_slices=130)             # buckets 1 .. 64, 128, 192
+    for S in (1, 3, 5, 8, 17, 32, 40, 70, 130):
         _print_case("solver fp64", NAME, "S", S)
         Bd = to_colmajor(torch.as_tensor(B[:, :S]), dtype=torch.float64)
         Xd = download(F.solve(Bd))
@@ -66,7 +66,10 @@ def test_solver_fp64_matches_direct_and_oracle(gpu):
         torch.cuda.synchronize()
         assert sv.info.read().status == 0
         bucket, tile, giters = sv.query(S)
-        assert bucket >= S and bucket & (bucket - 1) == 0
+        if S <= 64:
+            assert bucket >= S and bucket & (bucket - 1) == 0 and bucket < 2 * S
+        else:
+            assert bucket % 64 == 0 and S <= bucket < S + 64
         assert giters == 0                      # captured, no refinement
         if S <= 32:
             assert tile == 32
