@@ -9,8 +9,11 @@ the other workloads change only the image side and the view/bin counts.
 Readings taken where the paper is silent (each is listed in the design doc):
   * the detector is flat and its bins are equispaced over the fan's width;
   * the square image is centred on the rotation axis with side
-    0.98 * sqrt(2) * R * sin(fan/2), i.e. just inside the circle every view's
-    fan covers, so every pixel is seen from every view.
+    2 R sin(fan/2): it circumscribes the circle that every view's fan covers,
+    so every ray crosses the image.  The paper factors its 266,500 x 262,144
+    system by QR, which needs full column rank and so at least as many rays
+    crossing the image as pixels; a smaller square would leave the paper's own
+    case with fewer crossing rays than unknowns.
 """
 from dataclasses import dataclass
 import math
@@ -24,9 +27,9 @@ SCANNER = {
 
 
 def image_side_cm(src_iso_cm=SCANNER["src_iso_cm"], fan_deg=SCANNER["fan_deg"]):
-    """Side of the square image region (cm): 98% of the square inscribed in
-    the circle of radius R*sin(fan/2) that every view's fan covers."""
-    return 0.98 * math.sqrt(2.0) * src_iso_cm * math.sin(math.radians(fan_deg / 2.0))
+    """Side of the square image region (cm): the square circumscribing the
+    circle of radius R*sin(fan/2) that every view's fan covers."""
+    return 2.0 * src_iso_cm * math.sin(math.radians(fan_deg / 2.0))
 
 
 @dataclass(frozen=True)

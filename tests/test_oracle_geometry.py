@@ -28,9 +28,32 @@ def test_paper_sizes():
 
 def test_table1_scanner():
     assert SCANNER == {"src_iso_cm": 75.0, "src_det_cm": 150.0, "fan_deg": 30.0}
-    # image square inscribed (at 98%) in the circle R sin(15 deg) every fan covers
+    # image square circumscribing the circle R sin(15 deg) every fan covers
     L = image_side_cm()
-    assert abs(L * math.sqrt(2) / 2 / 0.98 - 75.0 * math.sin(math.radians(15.0))) < 1e-12
+    assert abs(L / 2 - 75.0 * math.sin(math.radians(15.0))) < 1e-12
+
+
+@pytest.mark.parametrize("name", ["paper512", "ct512", "ct256"])
+def test_every_ray_crosses_the_image(name):
+    # QR of A needs full column rank, so at least n rays must cross the image:
+    # the paper factors its 266,500 x 262,144 case (Section III-B), which only
+    # holds if (nearly) all of its rays are informative
+    w = get_workload(name)
+    c = image_chord_lengths(w.geometry())
+    assert (c > 0).all()
+    assert w.m >= w.n
+    # no chord is longer than the square's diagonal
+    assert c.max() <= w.side * math.sqrt(2) + 1e-9
+
+
+def test_undersampled_512_ratio_is_full_rank_small():
+    # the 512^2 view/bin density (288 views, 2 bins per pixel across) at 32^2:
+    # more crossing rays than pixels and a moderate condition number
+    g = dict(get_workload("ct32").geometry(), n_views=18, n_bins=64)
+    A = system_matrix_csr(g).toarray()
+    assert A.shape == (1152, 1024)
+    sv = np.linalg.svd(A, compute_uv=False)
+    assert sv[-1] > 0 and sv[0] / sv[-1] < 1e5
 
 
 def test_eq2_worked_values_v260():

@@ -176,4 +176,4 @@ def test_condition_ct32(ct32):
     _, d, QR, tau = ct32
     s = np.linalg.svd(d, compute_uv=False)
     kappa = s[0] / s[-1]
-    assert 50 < kappa < 1e3     # measured 234; full column rank
+    assert 10 < kappa < 1e2     # measured 32.3; full column rank
