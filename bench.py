@@ -5,14 +5,18 @@ of Table I with 120 views x 736 bins (m = 88,320 rays), A stored in FP32 for
 the factorization, 256 seeded ellipse-phantom sinograms with 1e-3 relative
 Gaussian noise.  One step is the whole hot path on resident inputs:
   1. build the dense FP32 system matrix A on the GPU (Siddon),
-  2. blocked Householder QR with FP32-MFMA trailing updates (A = QR, Eq. 3),
+  2. blocked Householder QR (A = QR, Eq. 3) whose block-column products run
+     on split-BF16 MFMA (each FP32 operand as a high and a low bf16 part,
+     three products, FP32 accumulation; --prec fp32 for FP32 MFMA), panel
+     norms and reflectors in FP64,
   3. X = R^-1 Q^T B for all 256 slices (Eq. 4), refined by corrected
      semi-normal equations with FP64 residuals against the FP64 sparse A.
 value = QR TFLOP/s of step 2 ((2 m n^2 - 2 n^3 / 3) / t_QR); slices/s of
 step 3 are reported beside it, as are the same two figures for the plain FP64
-GPU path (FP64 A, FP64 MFMA, no refinement), timed once after the K steps.
+GPU path (FP64 A, FP64 MFMA, no refinement) and for the other FP32-storage
+product modes (FP32 MFMA, one-part BF16), each timed once after the K steps.
 
-The "roofline" object covers the dominant kernel (the trailing-update GEMM
+The "roofline" object covers the dominant kernel (the trailing-update product
 C -= V W'), timed per launch with HIP events on the stream it runs on.  The
 "cpu_baseline" leg times the CPU oracle (unblocked FP64 Householder QR) on a
 bounded column sample of the same A.
@@ -28,8 +32,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
+PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6, "bf16": 2500.0}
 REFINE = {"csne": 0, "pcg": 1}
+
+
+def prec_codes(C):
+    """Product mode name -> ctqr_prec of an FP32-storage factorization."""
+    return {"bf16x3": C.CTQR_PREC_BF16X3_MFMA, "fp32": C.CTQR_PREC_FP32_MFMA, "bf16": C.CTQR_PREC_BF16_MFMA}
 HBM_PEAK_GBS = 8000.0
 
 
@@ -50,6 +59,8 @@ def parse():
     p.add_argument("--nb", type=int, default=256)
     p.add_argument("--max-iters", type=int, default=30)
     p.add_argument("--tol", type=float, default=1e-12)
+    p.add_argument("--prec", choices=["bf16x3", "fp32"], default="bf16x3",
+                   help="block-column products of the mixed path: split-BF16 MFMA or FP32 MFMA")
     p.add_argument("--refine", choices=["csne", "pcg"], default="csne",
                    help="refinement form: corrected semi-normal equations or their conjugate-gradient form")
     p.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU comparison run")
@@ -67,7 +78,12 @@ def parse():
     return p.parse_args()
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_nn_trailing_update_ct256_traffic.txt")
+# committed HBM-counter summaries of the trailing-update kernel, per product mode
+TRAFFIC_FILES = {"fp32": os.path.join(ROOT, "profiles", "gemm_nn_trailing_update_ct256_traffic.txt"),
+                 "bf16x3": os.path.join(ROOT, "profiles", "gemm_nn_bf16x3_trailing_update_ct256_traffic.txt")}
+# the trailing-update kernel of each mode, as rocprofv3 names it
+TRAILING_KERNEL = {"fp32": "gemm_nn_kernel<float, 1, 128, false, 0>",
+                   "bf16x3": "gemm_nn_bf16x3_kernel"}
 
 
 def gemm_source_hash():
@@ -76,12 +92,12 @@ def gemm_source_hash():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(workload):
-    """HBM bytes per launch of the trailing-update GEMM from the committed
+def measured_traffic(workload, prec):
+    """HBM bytes per launch of the trailing-update kernel from the committed
     counter summary (FETCH_SIZE + WRITE_SIZE scaled by a copy kernel), or None
     if there is none for this workload or the kernel source changed since."""
     try:
-        kv = dict(l.strip().split("=", 1) for l in open(TRAFFIC_FILE)
+        kv = dict(l.strip().split("=", 1) for l in open(TRAFFIC_FILES[prec])
                   if "=" in l and not l.lstrip().startswith("#"))
     except OSError:
         return None
@@ -283,7 +299,7 @@ def ooc_bench(args, log):
     host_gb = (n - n_dev) * col_bytes / 1e9
     log("HBM free %.1f GB of %.1f: %d resident columns (%.1f GB), %d host columns (%.1f GB pinned), tiles of %d"
         % (free / 1e9, total / 1e9, n_dev, n_dev * col_bytes / 1e9, n - n_dev, host_gb, tile))
-    O = OocFactor(m, n, C.CTQR_F32, C.CTQR_PREC_FP32_MFMA, n_dev, tile, nb=args.nb)
+    O = OocFactor(m, n, C.CTQR_F32, prec_codes(C)[args.prec], n_dev, tile, nb=args.nb)
     t0 = time.perf_counter()
     if n_dev > 0:
         sp.dense_cols(0, n_dev, O.A_dev, C.CTQR_F32)
@@ -408,7 +424,7 @@ def main():
     from paper_1907_01891_amd.device import Workspace
     build_dense.ws = Workspace()
 
-    F = QRFactor(A32, C.CTQR_PREC_FP32_MFMA, nb=args.nb)
+    F = QRFactor(A32, prec_codes(C)[args.prec], nb=args.nb)
     X = colmajor(n, S, torch.float64, dev)
     ev = lambda: torch.cuda.Event(enable_timing=True)
 
@@ -453,39 +469,56 @@ def main():
     torch.cuda.synchronize()
     rec_err = ((Xc - Xtrue[:, :n_clean]).norm(dim=0) / Xtrue[:, :n_clean].norm(dim=0)).max().item()
     Xmixed = X.clone()
-    log("mixed: qr %.2f TFLOP/s, %.0f slices/s, refine iters %d (status %d), recovery err %.2e"
-        % (qr_tf, slices_s, sinfo.iters, sinfo.status, rec_err))
+    log("mixed (%s products): qr %.2f TFLOP/s, %.0f slices/s, refine iters %d (status %d), recovery err %.2e"
+        % (args.prec, qr_tf, slices_s, sinfo.iters, sinfo.status, rec_err))
     stream_out = None
     if not args.no_stream and args.workload == "ct256":
         stream_out = request_stream_bench(args, log, F, sp, B)
         torch.cuda.empty_cache()
     bf16 = {}
     if not args.no_bf16:
-        # BF16 MFMA for the block-column products of the same factorization;
-        # its error is reported against the refined mixed solution
-        build_dense(A32, C.CTQR_F32)
-        F16 = QRFactor(A32, C.CTQR_PREC_BF16_MFMA, nb=args.nb)
-        torch.cuda.synchronize()
-        e0, e1 = ev(), ev()
-        e0.record()
-        F16.factor()
-        e1.record()
-        torch.cuda.synchronize()
-        t16 = e0.elapsed_time(e1)
-        Xu = F16.solve(B)
-        torch.cuda.synchronize()
-        e_unref = ((Xu - Xmixed).norm(dim=0) / Xmixed.norm(dim=0)).max().item()
-        Xr = F16.solve(B, sparse=sp.sp, tol=args.tol, max_iters=args.max_iters, method=REFINE[args.refine])
-        torch.cuda.synchronize()
-        si16 = F16.sinfo.read()
-        e_ref = ((Xr - Xmixed).norm(dim=0) / Xmixed.norm(dim=0)).max().item()
-        bf16 = {"bf16_qr_tflops": qr_flops(m, n) / (t16 * 1e-3) / 1e12, "bf16_qr_ms": t16,
-                "bf16_unrefined_rel_err_vs_mixed": e_unref, "bf16_refined_rel_err_vs_mixed": e_ref,
-                "bf16_refine_status": int(si16.status), "bf16_refine_iters": int(si16.iters),
-                "bf16_qr_info_status": int(F16.info.read().status)}
-        log("bf16: qr %.2f TFLOP/s (%.0f ms); error vs mixed: unrefined %.2e, refined %.2e (status %d, %d iters)"
-            % (bf16["bf16_qr_tflops"], t16, e_unref, e_ref, si16.status, si16.iters))
-        del F16, Xu, Xr
+        # the other product modes of the FP32-storage factorization (FP32
+        # MFMA, one-part BF16, split BF16), each factored once; errors are
+        # reported against the refined solution of the headline mode
+        for key in [k for k in ("fp32", "bf16", "bf16x3") if k != args.prec]:
+            build_dense(A32, C.CTQR_F32)
+            F16 = QRFactor(A32, prec_codes(C)[key], nb=args.nb)
+            torch.cuda.synchronize()
+            e0, e1 = ev(), ev()
+            C.ctqr_profile_enable(True)
+            e0.record()
+            F16.factor()
+            e1.record()
+            torch.cuda.synchronize()
+            t16 = e0.elapsed_time(e1)
+            tl, tms, tfl = C.ctqr_profile_read()
+            C.ctqr_profile_enable(False)
+            if tl:
+                bf16[key + "_trailing_update_avg_ms"] = tms / tl
+                bf16[key + "_trailing_update_tflops"] = tfl / (tms * 1e-3) / 1e12
+                if key == "fp32":
+                    bf16["fp32_trailing_update_frac_of_fp32_mfma_peak"] = tfl / (tms * 1e-3) / 1e12 / PEAK_TFLOPS["f32"]
+            Xu = F16.solve(B)
+            torch.cuda.synchronize()
+            e_unref = ((Xu - Xmixed).norm(dim=0) / Xmixed.norm(dim=0)).max().item()
+            e0.record()
+            Xr = F16.solve(B, sparse=sp.sp, tol=args.tol, max_iters=args.max_iters, method=REFINE[args.refine])
+            e1.record()
+            torch.cuda.synchronize()
+            ts16 = e0.elapsed_time(e1)
+            si16 = F16.sinfo.read()
+            e_ref = ((Xr - Xmixed).norm(dim=0) / Xmixed.norm(dim=0)).max().item()
+            bf16.update({key + "_qr_tflops": qr_flops(m, n) / (t16 * 1e-3) / 1e12, key + "_qr_ms": t16,
+                         key + "_unrefined_rel_err_vs_headline": e_unref, key + "_refined_rel_err_vs_headline": e_ref,
+                         key + "_refine_status": int(si16.status), key + "_refine_iters": int(si16.iters),
+                         key + "_refined_slices_per_s": S / (ts16 * 1e-3),
+                         key + "_qr_info_status": int(F16.info.read().status)})
+            log("%s: qr %.2f TFLOP/s (%.0f ms; trailing update %.2f ms per launch); error vs headline: unrefined "
+                "%.2e, refined %.2e (status %d, %d iters, %.0f slices/s)"
+                % (key, bf16[key + "_qr_tflops"], t16, bf16.get(key + "_trailing_update_avg_ms", 0.0), e_unref,
+                   e_ref, si16.status, si16.iters, S / (ts16 * 1e-3)))
+            del F16, Xu, Xr
+            torch.cuda.empty_cache()
     del A32, F
     torch.cuda.empty_cache()
 
@@ -533,6 +566,34 @@ def main():
             alg += 8.0 * (m - k0) * nc + 4.0 * nbk * ((m - k0) + nc)
             nl += 1
     alg_bytes = alg / nl if nl else None
+    avg_ms = kern_ms / launches if launches else None
+    if args.prec == "fp32":
+        roof = {"bound": "mfma", "kernel": TRAILING_KERNEL["fp32"] + " (trailing update C -= V W', FP32 MFMA)",
+                "achieved": achieved, "peak": PEAK_TFLOPS["f32"], "unit": "TFLOP/s",
+                "frac": (achieved / PEAK_TFLOPS["f32"]) if achieved else None}
+    else:
+        # at BF16 MFMA rates the update is bound by HBM: its FP32-equivalent
+        # intensity (2 m_k n_k nb flops over the C read + write, nb / 4 = 64
+        # flop/B at nb = 256; 192 counting the three products) is below the
+        # 2500 TFLOP/s / 8 TB/s = 312 flop/B ridge
+        gbs = alg_bytes / (avg_ms * 1e-3) / 1e9 if avg_ms else None
+        roof = {"bound": "hbm", "kernel": TRAILING_KERNEL["bf16x3"] + " (split-BF16 trailing update C -= V W')",
+                "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": gbs / HBM_PEAK_GBS if gbs else None,
+                "mfma_tflops_fp32_equivalent": achieved,
+                "mfma_tflops_executed_bf16": 3 * achieved if achieved else None,
+                "mfma_peak_bf16_tflops": PEAK_TFLOPS["bf16"]}
+    roof.update({
+        "traffic": measured_traffic(args.workload, args.prec) if args.nb == 256 else None,
+        "traffic_unit": "bytes per launch (HBM, FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+        "algorithmic_bytes_per_launch": alg_bytes,
+        "launches": launches,
+        "avg_launch_ms": avg_ms,
+        "flops_per_launch": kern_flops / launches if launches else None,
+    })
+    products = {"bf16x3": "split-BF16 MFMA block-column products (high + low bf16 parts, three products, FP32 "
+                          "accumulation)",
+                "fp32": "FP32-MFMA block-column products"}[args.prec]
     out = {
         "metric": "QR TFLOP/s + slices/s at 256^2 (mixed vs FP64 GPU, rel err <= 1e-10)",
         "value": qr_tf,
@@ -548,10 +609,10 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": "%s: %dx%d image, %d views x %d bins (m=%d, n=%d), %d ellipse-phantom slices, "
-                        "1e-3 relative noise; FP32 A, FP32-MFMA trailing updates, FP64 panel, "
-                        "CSNE refinement with FP64 sparse residuals" % (w.name, w.side, w.side, w.n_views,
-                                                                       w.n_bins, m, n, S),
-            "nb": args.nb, "slices": S, "parallelism": "single GPU",
+                        "1e-3 relative noise; FP32 A, %s, FP64 panel, %s refinement with FP64 sparse "
+                        "residuals" % (w.name, w.side, w.side, w.n_views, w.n_bins, m, n, S, products,
+                                       args.refine.upper()),
+            "nb": args.nb, "slices": S, "products": args.prec, "parallelism": "single GPU",
         },
         "slices_per_s": slices_s,
         "qr_ms": t_qr, "solve_ms": t_solve, "build_ms": t_build,
@@ -562,17 +623,7 @@ def main():
         "recovery_rel_err_max": rec_err,
         "qr_info_status": int(finfo.status),
         "rdiag_min_max": [finfo.rdiag_min, finfo.rdiag_max],
-        "roofline": {
-            "bound": "mfma", "kernel": "gemm_nn_kernel<float, 1, 128, false, false> (trailing update C -= V W')",
-            "achieved": achieved, "peak": PEAK_TFLOPS["f32"], "unit": "TFLOP/s",
-            "frac": (achieved / PEAK_TFLOPS["f32"]) if achieved else None,
-            "traffic": measured_traffic(args.workload) if args.nb == 256 else None,
-            "traffic_unit": "bytes per launch (HBM, FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-            "algorithmic_bytes_per_launch": alg_bytes,
-            "launches": launches,
-            "avg_launch_ms": kern_ms / launches if launches else None,
-            "flops_per_launch": kern_flops / launches if launches else None,
-        },
+        "roofline": roof,
         "cpu_baseline": cpu,
         "request_stream": stream_out,
         "wall_s_timed": wall,

@@ -68,11 +68,20 @@ typedef int32_t ctqr_dtype;
  *   CTQR_PREC_FP32_MFMA  FP32 storage, FP32 MFMA with FP32 accumulation; panel
  *                        norms and reflectors in FP64.
  *   CTQR_PREC_BF16_MFMA  FP32 storage, operands rounded to BF16 for MFMA with
- *                        FP32 accumulation; panel in FP64. */
+ *                        FP32 accumulation; panel in FP64.
+ *   CTQR_PREC_BF16X3_MFMA FP32 storage, each operand split into a BF16 high
+ *                        part and a BF16 low part (its rounding remainder);
+ *                        three BF16 MFMA products (high-high, high-low,
+ *                        low-high) with FP32 accumulation, about 16 bits of
+ *                        operand precision; panel in FP64.
+ * The two BF16 modes apply to the block-column products ([G | W] = V^T [V | C]
+ * and the trailing update C -= V W'); the inner panel updates and Q^T B stay
+ * FP32. */
 typedef int32_t ctqr_prec;
-#define CTQR_PREC_FP64      0
-#define CTQR_PREC_FP32_MFMA 1
-#define CTQR_PREC_BF16_MFMA 2
+#define CTQR_PREC_FP64        0
+#define CTQR_PREC_FP32_MFMA   1
+#define CTQR_PREC_BF16_MFMA   2
+#define CTQR_PREC_BF16X3_MFMA 3
 
 /* Refinement of a solve with the FP64 sparse A (both forms use FP64
  * residuals r = B - A X, s = A^T r and the preconditioner (R^T R)^-1 applied

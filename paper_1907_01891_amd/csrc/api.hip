@@ -92,14 +92,15 @@ struct FactorWS {
     unsigned *bars;
     double *part, *part2, *gram_part, *gram, *Tw;
     T *Tin, *GW, *W2, *split, *rtmp;
+    __bf16 *bsplit;          // split-BF16 parts of V and W' (FP32 factor only)
+    size_t bsplit_elems;
     size_t bytes;
-    bool bf16 = false;   // block-column GEMMs ([G | W] and the trailing update) on BF16 MFMA
+    int bf16 = 0;   // block-column GEMMs ([G | W], trailing update): bf16 parts per operand (0: none)
 };
 
 template <typename T>
 FactorWS<T> carve_factor(void *work, int64_t m, int64_t n, int nb)
 {
-    (void)m;
     Carve c(work);
     FactorWS<T> w;
     w.bars = c.take<unsigned>((ceil_div(n, PANEL_W) + 1) * GB_WORDS);
@@ -113,6 +114,8 @@ FactorWS<T> carve_factor(void *work, int64_t m, int64_t n, int nb)
     w.W2 = c.take<T>((int64_t)nb * n);
     w.split = c.take<T>(SPLIT_PART_ELEMS);
     w.rtmp = c.take<T>((int64_t)trinv_tmp_elems());
+    w.bsplit_elems = sizeof(T) == 4 ? bf16x3_split_elems(m, n, nb) : 0;
+    w.bsplit = c.take<__bf16>((int64_t)w.bsplit_elems);
     w.bytes = c.off + 256;
     return w;
 }
@@ -211,8 +214,15 @@ ctqr_status ensure_setup()
 // Profiled launch of the trailing update C -= V W' (the dominant kernel).
 template <typename T>
 ctqr_status trailing_update(int mk, int nc, int nbk, const T *V, int64_t lda, const T *W2, int nb, T *C,
-                            hipStream_t st, bool bf16)
+                            hipStream_t st, int bf16, __bf16 *bsplit, size_t bsplit_elems)
 {
+    if constexpr (sizeof(T) == 4) {
+        // split-BF16: both operands split once, outside the timed product
+        if (bf16 == 2) {
+            ctqr_status s = bf16x3_split(mk, nc, nbk, V, lda, W2, nb, bsplit, bsplit_elems, st);
+            if (s) return s;
+        }
+    }
     bool prof;
     {
         std::lock_guard<std::mutex> lk(g_prof_mu);
@@ -224,7 +234,17 @@ ctqr_status trailing_update(int mk, int nc, int nbk, const T *V, int64_t lda, co
         HIP_TRY(hipEventCreate(&rec.b));
         HIP_TRY(hipEventRecord(rec.a, st));
     }
-    ctqr_status s = gemm_nn<T>(mk, nc, nbk, V, lda, 1, W2, nb, T(-1), C, lda, nullptr, st, 1, 1, bf16);
+    ctqr_status s;
+    if constexpr (sizeof(T) == 4) {
+        if (bf16 == 2)
+            s = gemm_nn_bf16x3(mk, nc, nbk, -1.0f, C, lda, bsplit, bsplit_elems, st);
+        else
+            s = gemm_nn<T>(mk, nc, nbk, V, lda, 1, W2, nb, T(-1), C, lda, nullptr, st, 1, 1, bf16);
+    } else {
+        (void)bsplit;
+        (void)bsplit_elems;
+        s = gemm_nn<T>(mk, nc, nbk, V, lda, 1, W2, nb, T(-1), C, lda, nullptr, st, 1, 1, 0);
+    }
     if (s) return s;
     if (prof) {
         HIP_TRY(hipEventRecord(rec.b, st));
@@ -296,7 +316,7 @@ ctqr_status factor_blocks(int m, int n, T *A, int64_t lda, int nb, int kb, int k
                        w.split, SPLIT_PART_ELEMS, nullptr, st, sp.tw);
         if (s) return s;
         if ((s = trailing_update<T>(m - k0, nc, nbk, V, lda, w.W2, nb, A + (int64_t)(k0 + nbk) * lda + k0, st,
-                                    w.bf16)))
+                                    w.bf16, w.bsplit, w.bsplit_elems)))
             return s;
     }
     return CTQR_OK;
@@ -326,14 +346,15 @@ ctqr_status apply_blocks(int m, int n, const T *V, int64_t lda, const T *Tf, int
         s = gemm_tn<T>(nbk, nc, nbk, Tf + (int64_t)k0 * nb, nb, 0, w.GW, nb, 0, T(1), T(0), w.W2, nb, w.split,
                        SPLIT_PART_ELEMS, nullptr, st, sp.tw);
         if (s) return s;
-        if ((s = trailing_update<T>(m - k0, nc, nbk, Vk, lda, w.W2, nb, Ck, st, w.bf16))) return s;
+        if ((s = trailing_update<T>(m - k0, nc, nbk, Vk, lda, w.W2, nb, Ck, st, w.bf16, w.bsplit, w.bsplit_elems)))
+            return s;
     }
     return CTQR_OK;
 }
 
 template <typename T>
 ctqr_status factor_impl(int64_t m64, int64_t n64, T *A, int64_t lda, int nb, T *Tout, double *tau, T *Rinv,
-                        void *work, ctqr_info *info, hipStream_t st, bool bf16)
+                        void *work, ctqr_info *info, hipStream_t st, int bf16)
 {
     const int m = (int)m64, n = (int)n64;
     FactorWS<T> w = carve_factor<T>(work, m64, n64, nb);
@@ -422,7 +443,7 @@ struct CopyLane {
 template <typename T>
 ctqr_status factor_ooc_impl(int64_t m64, int64_t n64, T *A_dev, T *A_host, int64_t lda, int64_t n_dev64,
                             int64_t tile64, int nb, T *Tout, double *tau, T *Rinv, void *work, ctqr_info *info,
-                            hipStream_t st, bool bf16)
+                            hipStream_t st, int bf16)
 {
     const int m = (int)m64, n = (int)n64, n_dev = (int)n_dev64, tile = (int)tile64;
     OocWS<T> o = carve_ooc<T>(work, m64, n64, nb, lda, tile64);
@@ -1104,10 +1125,17 @@ bool geometry_ok(const ctqr_geometry *g)
     return m < INT32_MAX && n < INT32_MAX;
 }
 
+// bf16 parts each block-column GEMM operand is staged as (0: FP32 MFMA)
+int bf16_parts(ctqr_prec prec)
+{
+    return prec == CTQR_PREC_BF16_MFMA ? 1 : prec == CTQR_PREC_BF16X3_MFMA ? 2 : 0;
+}
+
 bool prec_ok(ctqr_dtype dtype, ctqr_prec prec)
 {
     if (dtype == CTQR_F64) return prec == CTQR_PREC_FP64;
-    if (dtype == CTQR_F32) return prec == CTQR_PREC_FP32_MFMA || prec == CTQR_PREC_BF16_MFMA;
+    if (dtype == CTQR_F32)
+        return prec == CTQR_PREC_FP32_MFMA || prec == CTQR_PREC_BF16_MFMA || prec == CTQR_PREC_BF16X3_MFMA;
     return false;
 }
 
@@ -1263,9 +1291,9 @@ ctqr_status ctqr_qr_factor_ooc(int64_t m, int64_t n, ctqr_dtype dtype, void *A_d
         if (s) return s;
         if (dtype == CTQR_F64)
             return factor_ooc_impl<double>(m, n, (double *)A_dev, (double *)A_host, lda, n_dev, tile_cols, nb,
-                                           (double *)T, tau, (double *)Rinv, work, info, stream, false);
+                                           (double *)T, tau, (double *)Rinv, work, info, stream, 0);
         return factor_ooc_impl<float>(m, n, (float *)A_dev, (float *)A_host, lda, n_dev, tile_cols, nb, (float *)T,
-                                      tau, (float *)Rinv, work, info, stream, prec == CTQR_PREC_BF16_MFMA);
+                                      tau, (float *)Rinv, work, info, stream, bf16_parts(prec));
     } catch (...) {
         return CTQR_EHIP;
     }
@@ -1298,9 +1326,9 @@ ctqr_status ctqr_qr_factor(int64_t m, int64_t n, ctqr_dtype dtype, void *A, int6
         if (s) return s;
         if (dtype == CTQR_F64)
             return factor_impl<double>(m, n, (double *)A, lda, nb, (double *)T, tau, (double *)Rinv, work, info,
-                                       stream, false);
+                                       stream, 0);
         return factor_impl<float>(m, n, (float *)A, lda, nb, (float *)T, tau, (float *)Rinv, work, info, stream,
-                                  prec == CTQR_PREC_BF16_MFMA);
+                                  bf16_parts(prec));
     } catch (...) {
         return CTQR_EHIP;
     }

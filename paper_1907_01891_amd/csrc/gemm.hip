@@ -31,6 +31,13 @@
 // MFMAs is permuted (k = 4*slot + s) so each lane fetches 4 consecutive k
 // values with one LDS read; the sum over k is unchanged.  Workgroup ids are
 // remapped so the tiles one XCD runs are neighbours (shared L2 lines).
+//
+// BF16 products of FP32 operands (the template parameter BF counts the bf16
+// parts each operand is staged as): BF = 1 rounds every operand to bf16 (one
+// v_mfma_f32_32x32x16_bf16 product); BF = 2 splits it into a high part
+// h = bf16(x) and a low part l = bf16(x - h), exact to about 16 bits, and sums
+// the three products l h', h l', h h' (the l l' term is below the FP32
+// accumulation's own rounding for most sums).  Both accumulate in FP32.
 #include <type_traits>
 
 #include "common.h"
@@ -186,6 +193,25 @@ struct KcTile {
             *reinterpret_cast<bf16x4 *>(lds + c * LDB + h * E) = o;
         }
     }
+    // split staging: high parts to hi, the bf16-rounded remainders to lo
+    __device__ inline void store_bf2(__bf16 *hi, __bf16 *lo) const
+    {
+        static_assert(sizeof(T) == 4, "bf16 staging of FP32 operands only");
+#pragma unroll
+        for (int q = 0; q < PER_THR; ++q) {
+            int c, h;
+            vec16_t<T> v = masked(q, c, h);
+            bf16x4 oh, ol;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const __bf16 t = (__bf16)v[e];
+                oh[e] = t;
+                ol[e] = (__bf16)(v[e] - (float)t);
+            }
+            *reinterpret_cast<bf16x4 *>(hi + c * LDB + h * E) = oh;
+            *reinterpret_cast<bf16x4 *>(lo + c * LDB + h * E) = ol;
+        }
+    }
 };
 
 // Loader of a BK-column x 128-row tile of a column-major M x K operand
@@ -241,18 +267,65 @@ struct MkTile {
             *reinterpret_cast<vec16_t<T> *>(lds + kk * LD + h * E) = v;
         }
     }
-    // BF16 staging, transposed to the [row][k] layout (k contiguous, row
-    // stride LDB) so both MFMA operands are read as 8 consecutive k
+};
+
+// BF16 loader of the same BK-column x 128-row tile (FP32, column-major
+// M x K): each thread takes one row and four groups of 4 consecutive k, so
+// it can write the row's bf16 values for those k as one 8-byte LDS store in
+// the [row][k] layout the BF16 MFMA reads.  The global loads are single
+// floats, still coalesced: the 64 lanes of a wave read 64 consecutive rows of
+// one column.
+template <typename T>
+struct MkTileBf {
+    static_assert(sizeof(T) == 4, "bf16 staging of FP32 operands only");
+    static constexpr int BK = Mf<T>::BK;
     static constexpr int LDB = BK + 8;
-    __device__ inline void store_bf_t(__bf16 *lds) const
+    static constexpr int QUADS = BK / 4;                   // k groups per row (8)
+    static constexpr int PER_THR = TILE * QUADS / NTHR;    // groups per thread (4)
+    static constexpr int QSTEP = NTHR / TILE;              // 2
+    T r[PER_THR][4];
+    int row0_, k0_, kmax_, mrows_;
+    bool mask_;
+
+    __device__ inline void load(const T *P, int64_t ld, int mrows, int row0, int k0, int kmax, bool mask)
     {
-        static_assert(sizeof(T) == 4, "bf16 staging of FP32 operands only");
+        row0_ = row0; k0_ = k0; kmax_ = kmax; mrows_ = mrows; mask_ = mask;
+        const int row = row0 + (int)threadIdx.x % TILE;
 #pragma unroll
-        for (int q = 0; q < PER_THR; ++q) {
-            int kk, h;
-            vec16_t<T> v = masked(q, kk, h);
+        for (int j = 0; j < PER_THR; ++j) {
+            const int q = (int)threadIdx.x / TILE + QSTEP * j;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) lds[(h * E + e) * LDB + kk] = (__bf16)v[e];
+            for (int e = 0; e < 4; ++e) {
+                const int k = k0 + 4 * q + e;
+                const bool ok = k < kmax && row < mrows;
+                r[j][e] = *(ok ? P + (int64_t)k * ld + row : P);
+            }
+        }
+    }
+    // the 4 values of group j with the bounds and the Householder structure
+    __device__ inline void masked(int j, int &rr, int &q, T (&v)[4]) const
+    {
+        rr = (int)threadIdx.x % TILE;
+        q = (int)threadIdx.x / TILE + QSTEP * j;
+        const int row = row0_ + rr;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int k = k0_ + 4 * q + e;
+            const T x = (k < kmax_ && row < mrows_) ? r[j][e] : T(0);
+            v[e] = mask_ ? vmask(x, row, k) : x;
+        }
+    }
+    __device__ inline void store_bf(__bf16 *lds) const
+    {
+#pragma unroll
+        for (int j = 0; j < PER_THR; ++j) {
+            int rr, q;
+            T v[4];
+            masked(j, rr, q, v);
+            bf16x4 o;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) o[e] = (__bf16)v[e];
+            *reinterpret_cast<bf16x4 *>(lds + rr * LDB + 4 * q) = o;
         }
     }
 };
@@ -362,6 +435,38 @@ __device__ inline void mfma_step_bf(const __bf16 *opA, const __bf16 *opB, int wn
     }
 }
 
+// The same step from split operands (high and low bf16 parts, same layout):
+// per block the low-part products first, then the high-high product.
+template <int NI, int NJ>
+__device__ inline void mfma_step_bf2(const __bf16 *opAh, const __bf16 *opAl, const __bf16 *opBh,
+                                     const __bf16 *opBl, int wn, int wm, floatx16 (&acc)[NI][NJ])
+{
+    constexpr int LDB = KcTile<float>::LDB;
+    const int lane = threadIdx.x % CTQR_WAVE;
+    const int li = lane % 32, slot = lane / 32;
+#pragma unroll
+    for (int g = 0; g < Mf<float>::BK / 16; ++g) {
+        const int kk = 16 * g + 8 * slot;
+        bf16x8 bh[NJ], bl[NJ];
+#pragma unroll
+        for (int jb = 0; jb < NJ; ++jb) {
+            bh[jb] = *reinterpret_cast<const bf16x8 *>(opBh + (wm + jb * 32 + li) * LDB + kk);
+            bl[jb] = *reinterpret_cast<const bf16x8 *>(opBl + (wm + jb * 32 + li) * LDB + kk);
+        }
+#pragma unroll
+        for (int ib = 0; ib < NI; ++ib) {
+            const bf16x8 ah = *reinterpret_cast<const bf16x8 *>(opAh + (wn + ib * 32 + li) * LDB + kk);
+            const bf16x8 al = *reinterpret_cast<const bf16x8 *>(opAl + (wn + ib * 32 + li) * LDB + kk);
+#pragma unroll
+            for (int jb = 0; jb < NJ; ++jb) {
+                acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[jb], acc[ib][jb], 0, 0, 0);
+                acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[jb], acc[ib][jb], 0, 0, 0);
+                acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[jb], acc[ib][jb], 0, 0, 0);
+            }
+        }
+    }
+}
+
 // Output coordinates of accumulator element r of block (ib, jb) for this lane:
 // output column (n) and row (m) offsets inside the wave's 64x64 sub-tile.
 template <typename T>
@@ -397,7 +502,7 @@ struct WaveTile {
 // ---------------------------------------------------------------------------
 // TN:  Out = alpha * A^T B + beta * Out   (or split-K partials)
 // ---------------------------------------------------------------------------
-template <typename T, int TW, bool BF>
+template <typename T, int TW, int BF>
 __global__ __launch_bounds__(NTHR, 2)
 void gemm_tn_kernel(int M, int N, int K,
                     const T *__restrict__ A, int64_t lda, int amask,
@@ -408,12 +513,14 @@ void gemm_tn_kernel(int M, int N, int K,
     using Mt = Mf<T>;
     using W = WaveTile<T, TW>;
     if (skip && *skip) return;
-    // BF: FP32 operands staged as bf16 (BF16 MFMA, FP32 accumulation)
-    static_assert(!BF || (sizeof(T) == 4 && TW == TILE), "bf16 path: FP32, 128-wide tiles");
-    using LT = typename std::conditional<BF, __bf16, T>::type;
+    // BF > 0: FP32 operands staged as BF bf16 parts (BF16 MFMA, FP32
+    // accumulation)
+    static_assert(BF == 0 || (sizeof(T) == 4 && TW == TILE && BF <= 2), "bf16 path: FP32, 128-wide tiles");
+    using LT = typename std::conditional<(BF > 0), __bf16, T>::type;
+    constexpr int NP = BF == 2 ? 2 : 1;
     constexpr int LDX = BF ? KcTile<T>::LDB : KcTile<T>::LD;
-    __shared__ __attribute__((aligned(16))) LT sA[2][TILE * LDX];
-    __shared__ __attribute__((aligned(16))) LT sB[2][TW * LDX];
+    __shared__ __attribute__((aligned(16))) LT sA[2][NP][TILE * LDX];
+    __shared__ __attribute__((aligned(16))) LT sB[2][NP][TW * LDX];
 
     int tm, tn;
     tile_of_block((M + TILE - 1) / TILE, (N + TW - 1) / TW, tm, tn);
@@ -433,13 +540,16 @@ void gemm_tn_kernel(int M, int N, int K,
 
     KcTile<T> la;
     KcTile<T, TW> lb;
-    auto stage = [](const KcTile<T> &a, const KcTile<T, TW> &b, LT *da, LT *db) {
-        if constexpr (BF) {
-            a.store_bf(da);
-            b.store_bf(db);
+    auto stage = [](const KcTile<T> &a, const KcTile<T, TW> &b, LT (*da)[TILE * LDX], LT (*db)[TW * LDX]) {
+        if constexpr (BF == 2) {
+            a.store_bf2(da[0], da[NP - 1]);
+            b.store_bf2(db[0], db[NP - 1]);
+        } else if constexpr (BF == 1) {
+            a.store_bf(da[0]);
+            b.store_bf(db[0]);
         } else {
-            a.store(da);
-            b.store(db);
+            a.store(da[0]);
+            b.store(db[0]);
         }
     };
     if (kbeg < kend) {
@@ -455,10 +565,12 @@ void gemm_tn_kernel(int M, int N, int K,
             la.load(A, lda, M, m0, k + Mt::BK, kend, amask);
             lb.load(B, ldb, N, n0, k + Mt::BK, kend, bmask);
         }
-        if constexpr (BF)
-            mfma_step_bf<W::NI, W::NJ>(sB[cur], sA[cur], wn, wm, acc);
+        if constexpr (BF == 2)
+            mfma_step_bf2<W::NI, W::NJ>(sB[cur][0], sB[cur][NP - 1], sA[cur][0], sA[cur][NP - 1], wn, wm, acc);
+        else if constexpr (BF == 1)
+            mfma_step_bf<W::NI, W::NJ>(sB[cur][0], sA[cur][0], wn, wm, acc);
         else
-            mfma_step<T, true, W::NI, W::NJ>(sB[cur], sA[cur], wn, wm, acc);
+            mfma_step<T, true, W::NI, W::NJ>(sB[cur][0], sA[cur][0], wn, wm, acc);
         if (more) stage(la, lb, sA[cur ^ 1], sB[cur ^ 1]);
         __syncthreads();
         cur ^= 1;
@@ -524,7 +636,7 @@ void splitk_reduce_kernel(int M, int N, int splits, const T *__restrict__ part,
 // ---------------------------------------------------------------------------
 // KIND only separates the symbols of the launch sites in a profile: 1 is the
 // trailing update of the factorization, 0 every other use.
-template <typename T, int KIND, int TW, bool SPLIT, bool BF>
+template <typename T, int KIND, int TW, bool SPLIT, int BF>
 __global__ __launch_bounds__(NTHR, 2)
 void gemm_nn_kernel(int M, int N, int K,
                     const T *__restrict__ A, int64_t lda, int amask,
@@ -539,12 +651,16 @@ void gemm_nn_kernel(int M, int N, int K,
     using Mt = Mf<T>;
     using W = WaveTile<T, TW>;
     if (skip && *skip) return;
-    // BF: FP32 operands staged as bf16 (BF16 MFMA, FP32 accumulation); the
-    // A tile is then stored [row][k]
-    static_assert(!BF || (sizeof(T) == 4 && TW == TILE && !SPLIT), "bf16 path: FP32, 128-wide, unsplit");
-    using LT = typename std::conditional<BF, __bf16, T>::type;
-    __shared__ __attribute__((aligned(16))) LT sA[2][BF ? TILE * MkTile<T>::LDB : Mt::BK * MkTile<T>::LD];
-    __shared__ __attribute__((aligned(16))) LT sB[2][TW * (BF ? KcTile<T>::LDB : KcTile<T>::LD)];
+    // BF > 0: FP32 operands staged as BF bf16 parts (BF16 MFMA, FP32
+    // accumulation); the A tile is then stored [row][k]
+    static_assert(BF == 0 || (sizeof(T) == 4 && TW == TILE && !SPLIT && BF == 1),
+                  "bf16 path: FP32, 128-wide, unsplit, one part (split parts: gemm_nn_bf16x3_kernel)");
+    using LT = typename std::conditional<(BF > 0), __bf16, T>::type;
+    constexpr int NP = BF == 2 ? 2 : 1;
+    constexpr int SA = BF ? TILE * (Mt::BK + 8) : Mt::BK * MkTile<T>::LD;
+    constexpr int SB = TW * (BF ? KcTile<T>::LDB : KcTile<T>::LD);
+    __shared__ __attribute__((aligned(16))) LT sA[2][NP][SA];
+    __shared__ __attribute__((aligned(16))) LT sB[2][NP][SB];
 
     int tm, tn;
     tile_of_block((M + TILE - 1) / TILE, (N + TW - 1) / TW, tm, tn);
@@ -585,15 +701,19 @@ void gemm_nn_kernel(int M, int N, int K,
                 }
     }
 
-    MkTile<T> la;
+    using ATile = typename std::conditional<(BF > 0), MkTileBf<T>, MkTile<T>>::type;
+    ATile la;
     KcTile<T, TW> lb;
-    auto stage = [](const MkTile<T> &a, const KcTile<T, TW> &b, LT *da, LT *db) {
-        if constexpr (BF) {
-            a.store_bf_t(da);
-            b.store_bf(db);
+    auto stage = [](const ATile &a, const KcTile<T, TW> &b, LT (*da)[SA], LT (*db)[SB]) {
+        if constexpr (BF == 2) {
+            a.store_bf2(da[0], da[NP - 1]);
+            b.store_bf2(db[0], db[NP - 1]);
+        } else if constexpr (BF == 1) {
+            a.store_bf(da[0]);
+            b.store_bf(db[0]);
         } else {
-            a.store(da);
-            b.store(db);
+            a.store(da[0]);
+            b.store(db[0]);
         }
     };
     la.load(A, lda, M, m0, kbeg, kend, amask != 0);
@@ -607,10 +727,12 @@ void gemm_nn_kernel(int M, int N, int K,
             la.load(A, lda, M, m0, k + Mt::BK, kend, amask != 0);
             lb.load(B, ldb, N, n0, k + Mt::BK, kend, 0);
         }
-        if constexpr (BF)
-            mfma_step_bf<W::NI, W::NJ>(sB[cur], sA[cur], wn, wm, acc);
+        if constexpr (BF == 2)
+            mfma_step_bf2<W::NI, W::NJ>(sB[cur][0], sB[cur][NP - 1], sA[cur][0], sA[cur][NP - 1], wn, wm, acc);
+        else if constexpr (BF == 1)
+            mfma_step_bf<W::NI, W::NJ>(sB[cur][0], sA[cur][0], wn, wm, acc);
         else
-            mfma_step<T, false, W::NI, W::NJ>(sB[cur], sA[cur], wn, wm, acc);
+            mfma_step<T, false, W::NI, W::NJ>(sB[cur][0], sA[cur][0], wn, wm, acc);
         if (more) stage(la, lb, sA[cur ^ 1], sB[cur ^ 1]);
         __syncthreads();
         cur ^= 1;
@@ -637,6 +759,161 @@ void gemm_nn_kernel(int M, int N, int K,
                     else
                         *c = accum ? *c + alpha * acc[ib][jb][r] : alpha * acc[ib][jb][r];
                 }
+            }
+}
+
+// ---------------------------------------------------------------------------
+// Split-BF16 trailing update from operands split once per block column
+// ---------------------------------------------------------------------------
+// C -= V W' re-stages every V tile for each column tile and every W' tile for
+// each row tile.  Splitting both once into high and low bf16 parts -- V into
+// a [row][k] layout, W' in its own [col][k] layout, both zero-padded to whole
+// tiles and k stages -- leaves the product kernel no conversion and no
+// masking: a stage is four 16-byte copies per thread into LDS.
+
+// V (rows x kc Householder block: unit lower trapezoidal, column-major) to
+// high / low bf16 parts, row-major with row stride ldv (k contiguous); rows up
+// to rows_pad and k up to ldv are zero.  Thread: one row, 8 consecutive k
+// (the 64 lanes of a wave read 64 consecutive rows of each column).
+__global__ __launch_bounds__(256)
+void split_v_kernel(int rows, int kc, const float *__restrict__ V, int64_t lda, int rows_pad, int ldv,
+                    __bf16 *__restrict__ hi, __bf16 *__restrict__ lo)
+{
+    const int r = (int)blockIdx.x * 256 + (int)threadIdx.x;
+    const int k0 = 8 * (int)blockIdx.y;
+    if (r >= rows_pad) return;
+    bf16x8 oh, ol;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int k = k0 + e;
+        const float x = (r < rows && k < kc) ? vmask(V[(int64_t)k * lda + r], r, k) : 0.0f;
+        const __bf16 t = (__bf16)x;
+        oh[e] = t;
+        ol[e] = (__bf16)(x - (float)t);
+    }
+    *reinterpret_cast<bf16x8 *>(hi + (int64_t)r * ldv + k0) = oh;
+    *reinterpret_cast<bf16x8 *>(lo + (int64_t)r * ldv + k0) = ol;
+}
+
+// W' (kc x cols, column-major, leading dimension ldw_in) to high / low bf16
+// parts with leading dimension ldw; columns up to cols_pad and k up to ldw are
+// zero.  Thread: one column, 8 consecutive k.
+__global__ __launch_bounds__(256)
+void split_w_kernel(int kc, int cols, const float *__restrict__ W, int64_t ldw_in, int cols_pad, int ldw,
+                    __bf16 *__restrict__ hi, __bf16 *__restrict__ lo)
+{
+    const int groups = ldw / 8;
+    const int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (f >= (int64_t)cols_pad * groups) return;
+    const int c = (int)(f / groups), k0 = 8 * (int)(f % groups);
+    bf16x8 oh, ol;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int k = k0 + e;
+        const float x = (c < cols && k < kc) ? W[(int64_t)c * ldw_in + k] : 0.0f;
+        const __bf16 t = (__bf16)x;
+        oh[e] = t;
+        ol[e] = (__bf16)(x - (float)t);
+    }
+    *reinterpret_cast<bf16x8 *>(hi + (int64_t)c * ldw + k0) = oh;
+    *reinterpret_cast<bf16x8 *>(lo + (int64_t)c * ldw + k0) = ol;
+}
+
+// C += alpha V W' from the split parts: 128 x 128 output tiles, three BF16
+// products per operand pair (as in the BF = 2 kernels), FP32 accumulation, C
+// prefetched at the start as in the FP32 trailing update.  Ah/Al: rows padded
+// to whole tiles, row stride lda; Bh/Bl: columns padded to whole tiles,
+// column stride ldb; both cover k up to K rounded up to a stage.
+__global__ __launch_bounds__(NTHR, 2)
+void gemm_nn_bf16x3_kernel(int M, int N, int K, const __bf16 *__restrict__ Ah, const __bf16 *__restrict__ Al,
+                           int64_t lda, const __bf16 *__restrict__ Bh, const __bf16 *__restrict__ Bl,
+                           int64_t ldb, float alpha, float *__restrict__ C, int64_t ldc, const int *skip)
+{
+    using W = WaveTile<float, TILE>;
+    constexpr int BK = Mf<float>::BK;
+    constexpr int LDB = KcTile<float>::LDB;
+    constexpr int CH = BK / 8;                     // 16-byte chunks per row and stage (4)
+    constexpr int PER = TILE * CH / NTHR;          // chunks per thread, per part and operand (2)
+    if (skip && *skip) return;
+    __shared__ __attribute__((aligned(16))) __bf16 sA[2][2][TILE * LDB];
+    __shared__ __attribute__((aligned(16))) __bf16 sB[2][2][TILE * LDB];
+
+    int tm, tn;
+    tile_of_block((M + TILE - 1) / TILE, (N + TILE - 1) / TILE, tm, tn);
+    const int m0 = tm * TILE, n0 = tn * TILE;
+    const int wave = threadIdx.x / CTQR_WAVE;
+    const int wn = W::wn(wave), wm = W::wm(wave);
+
+    floatx16 acc[W::NI][W::NJ];
+#pragma unroll
+    for (int i = 0; i < W::NI; ++i)
+#pragma unroll
+        for (int j = 0; j < W::NJ; ++j)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
+
+    float cpre[W::NI][W::NJ][16];
+#pragma unroll
+    for (int ib = 0; ib < W::NI; ++ib)
+#pragma unroll
+        for (int jb = 0; jb < W::NJ; ++jb)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                int n, m;
+                acc_coords<float>(ib, jb, r, n, m);
+                n += n0 + wn;
+                m += m0 + wm;
+                cpre[ib][jb][r] = (m < M && n < N) ? C[(int64_t)n * ldc + m] : 0.0f;
+            }
+
+    bf16x8 ra[2][PER], rb[2][PER];
+    auto load = [&](int k) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int f = (int)threadIdx.x + NTHR * q, r = f / CH, c = f % CH;
+            const int64_t oa = (int64_t)(m0 + r) * lda + k + 8 * c;
+            const int64_t ob = (int64_t)(n0 + r) * ldb + k + 8 * c;
+            ra[0][q] = *reinterpret_cast<const bf16x8 *>(Ah + oa);
+            ra[1][q] = *reinterpret_cast<const bf16x8 *>(Al + oa);
+            rb[0][q] = *reinterpret_cast<const bf16x8 *>(Bh + ob);
+            rb[1][q] = *reinterpret_cast<const bf16x8 *>(Bl + ob);
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int f = (int)threadIdx.x + NTHR * q, r = f / CH, c = f % CH;
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                *reinterpret_cast<bf16x8 *>(&sA[buf][p][r * LDB + 8 * c]) = ra[p][q];
+                *reinterpret_cast<bf16x8 *>(&sB[buf][p][r * LDB + 8 * c]) = rb[p][q];
+            }
+        }
+    };
+    load(0);
+    store(0);
+    __syncthreads();
+    int cur = 0;
+    for (int k = 0; k < K; k += BK) {
+        const bool more = k + BK < K;
+        if (more) load(k + BK);
+        mfma_step_bf2<W::NI, W::NJ>(sB[cur][0], sB[cur][1], sA[cur][0], sA[cur][1], wn, wm, acc);
+        if (more) store(cur ^ 1);
+        __syncthreads();
+        cur ^= 1;
+    }
+
+#pragma unroll
+    for (int ib = 0; ib < W::NI; ++ib)
+#pragma unroll
+        for (int jb = 0; jb < W::NJ; ++jb)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                int n, m;
+                acc_coords<float>(ib, jb, r, n, m);
+                n += n0 + wn;
+                m += m0 + wm;
+                if (m < M && n < N) C[(int64_t)n * ldc + m] = cpre[ib][jb][r] + alpha * acc[ib][jb][r];
             }
 }
 
@@ -714,7 +991,7 @@ ctqr_status splitk_reduce(int M, int N, int splits, const T *part, T alpha, T be
 template <typename T>
 ctqr_status gemm_tn(int M, int N, int K, const T *A, int64_t lda, int amask, const T *B,
                     int64_t ldb, int bmask, T alpha, T beta, T *Out, int64_t ldo, T *part,
-                    size_t part_elems, const int *skip, hipStream_t st, int force_splits, bool bf16)
+                    size_t part_elems, const int *skip, hipStream_t st, int force_splits, int bf16)
 {
     if (M <= 0 || N <= 0) return CTQR_OK;
     const bool narrow = N <= t_narrow_max;
@@ -729,18 +1006,22 @@ ctqr_status gemm_tn(int M, int N, int K, const T *A, int64_t lda, int amask, con
     dim3 grid((unsigned)(ceil_div(M, TILE) * ceil_div(N, narrow ? NARROW : TILE)), 1, (unsigned)splits);
     bool done = false;
     if constexpr (sizeof(T) == 4) {
-        if (bf16 && !narrow) {
-            LAUNCH_TRY((gemm_tn_kernel<T, TILE, true>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B, ldb,
+        if (bf16 == 1 && !narrow) {
+            LAUNCH_TRY((gemm_tn_kernel<T, TILE, 1>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B, ldb,
+                       bmask, alpha, beta, Out, ldo, part, kchunk, skip);
+            done = true;
+        } else if (bf16 == 2 && !narrow) {
+            LAUNCH_TRY((gemm_tn_kernel<T, TILE, 2>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B, ldb,
                        bmask, alpha, beta, Out, ldo, part, kchunk, skip);
             done = true;
         }
     }
     if (done) {
     } else if (narrow) {
-        LAUNCH_TRY((gemm_tn_kernel<T, NARROW, false>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B, ldb,
+        LAUNCH_TRY((gemm_tn_kernel<T, NARROW, 0>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B, ldb,
                    bmask, alpha, beta, Out, ldo, part, kchunk, skip);
     } else {
-        LAUNCH_TRY((gemm_tn_kernel<T, TILE, false>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B, ldb,
+        LAUNCH_TRY((gemm_tn_kernel<T, TILE, 0>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B, ldb,
                    bmask, alpha, beta, Out, ldo, part, kchunk, skip);
     }
     if (splits > 1) return splitk_reduce<T>(M, N, splits, part, alpha, beta, Out, ldo, skip, st);
@@ -750,9 +1031,10 @@ ctqr_status gemm_tn(int M, int N, int K, const T *A, int64_t lda, int amask, con
 template <typename T>
 ctqr_status gemm_nn(int M, int N, int K, const T *A, int64_t lda, int amask, const T *B,
                     int64_t ldb, T alpha, T *C, int64_t ldc, const int *skip, hipStream_t st, int kind,
-                    int accum, bool bf16)
+                    int accum, int bf16)
 {
     if (M <= 0 || N <= 0) return CTQR_OK;
+    if (bf16 == 2) return CTQR_EINVAL;   // split operands: gemm_nn_bf16x3
     if (K <= 0) {
         if (accum) return CTQR_OK;
         K = 0;   // C = 0: the kernel runs with an empty k loop
@@ -761,20 +1043,21 @@ ctqr_status gemm_nn(int M, int N, int K, const T *A, int64_t lda, int amask, con
     const int kchunk = K > 0 ? K : 1;
     dim3 grid((unsigned)(ceil_div(M, TILE) * ceil_div(N, narrow ? NARROW : TILE)));
     if constexpr (sizeof(T) == 4) {
-        if (kind == 1 && bf16) {
-            LAUNCH_TRY((gemm_nn_kernel<T, 1, TILE, false, true>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask,
+        if (kind == 1 && bf16 == 1) {
+            LAUNCH_TRY((gemm_nn_kernel<T, 1, TILE, false, 1>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask,
                        B, ldb, alpha, C, ldc, accum, (T *)nullptr, kchunk, skip);
             return CTQR_OK;
         }
+
     }
     if (kind == 1)
-        LAUNCH_TRY((gemm_nn_kernel<T, 1, TILE, false, false>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B,
+        LAUNCH_TRY((gemm_nn_kernel<T, 1, TILE, false, 0>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B,
                    ldb, alpha, C, ldc, accum, (T *)nullptr, kchunk, skip);
     else if (narrow)
-        LAUNCH_TRY((gemm_nn_kernel<T, 0, NARROW, false, false>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask,
+        LAUNCH_TRY((gemm_nn_kernel<T, 0, NARROW, false, 0>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask,
                    B, ldb, alpha, C, ldc, accum, (T *)nullptr, kchunk, skip);
     else
-        LAUNCH_TRY((gemm_nn_kernel<T, 0, TILE, false, false>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask,
+        LAUNCH_TRY((gemm_nn_kernel<T, 0, TILE, false, 0>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask,
                    B, ldb, alpha, C, ldc, accum, (T *)nullptr, kchunk, skip);
     return CTQR_OK;
 }
@@ -787,29 +1070,85 @@ ctqr_status gemm_nn_split(int M, int N, int K, const T *A, int64_t lda, const T 
     const bool narrow = N <= t_narrow_max;
     int splits = gemm_tn_splits(M, N, K);
     if (splits > 1 && (part == nullptr || part_elems < (size_t)splits * M * N)) splits = 1;
-    if (splits <= 1) return gemm_nn<T>(M, N, K, A, lda, 0, B, ldb, alpha, C, ldc, skip, st, 0, 1, false);
+    if (splits <= 1) return gemm_nn<T>(M, N, K, A, lda, 0, B, ldb, alpha, C, ldc, skip, st, 0, 1, 0);
     int kchunk = (int)ceil_div(ceil_div(K, splits), Mf<T>::BK) * Mf<T>::BK;
     splits = (int)ceil_div(K, kchunk);
     dim3 grid((unsigned)(ceil_div(M, TILE) * ceil_div(N, narrow ? NARROW : TILE)), 1, (unsigned)splits);
     if (narrow)
-        LAUNCH_TRY((gemm_nn_kernel<T, 0, NARROW, true, false>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, 0, B,
+        LAUNCH_TRY((gemm_nn_kernel<T, 0, NARROW, true, 0>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, 0, B,
                    ldb, alpha, C, ldc, 0, part, kchunk, skip);
     else
-        LAUNCH_TRY((gemm_nn_kernel<T, 0, TILE, true, false>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, 0, B,
+        LAUNCH_TRY((gemm_nn_kernel<T, 0, TILE, true, 0>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, 0, B,
                    ldb, alpha, C, ldc, 0, part, kchunk, skip);
     return splitk_reduce<T>(M, N, splits, part, alpha, T(1), C, ldc, skip, st);
 }
 
+namespace {
+int64_t up_to(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
+}  // namespace
+
+size_t bf16x3_split_elems(int64_t m, int64_t n, int nb)
+{
+    const int64_t kp = up_to(nb, 32);
+    return (size_t)(2 * up_to(m, TILE) * kp + 2 * up_to(n, TILE) * kp);
+}
+
+namespace {
+struct SplitParts {
+    int kp, rows_pad, cols_pad;
+    __bf16 *vh, *vl, *wh, *wl;
+};
+bool split_parts(int M, int N, int K, __bf16 *split, size_t split_elems, SplitParts &p)
+{
+    p.kp = (int)up_to(K, 32);
+    p.rows_pad = (int)up_to(M, TILE);
+    p.cols_pad = (int)up_to(N, TILE);
+    const size_t need = 2 * (size_t)p.rows_pad * p.kp + 2 * (size_t)p.cols_pad * p.kp;
+    if (split == nullptr || need > split_elems) return false;
+    p.vh = split;
+    p.vl = p.vh + (size_t)p.rows_pad * p.kp;
+    p.wh = p.vl + (size_t)p.rows_pad * p.kp;
+    p.wl = p.wh + (size_t)p.cols_pad * p.kp;
+    return true;
+}
+}  // namespace
+
+ctqr_status bf16x3_split(int M, int N, int K, const float *V, int64_t lda, const float *W, int64_t ldw,
+                         __bf16 *split, size_t split_elems, hipStream_t st)
+{
+    if (M <= 0 || N <= 0 || K <= 0) return CTQR_OK;
+    SplitParts p;
+    if (!split_parts(M, N, K, split, split_elems, p)) return CTQR_ENOMEM;
+    LAUNCH_TRY(split_v_kernel, dim3((unsigned)ceil_div(p.rows_pad, 256), (unsigned)(p.kp / 8)), dim3(256), 0, st, M,
+               K, V, lda, p.rows_pad, p.kp, p.vh, p.vl);
+    LAUNCH_TRY(split_w_kernel, dim3((unsigned)ceil_div((int64_t)p.cols_pad * (p.kp / 8), 256)), dim3(256), 0, st, K,
+               N, W, ldw, p.cols_pad, p.kp, p.wh, p.wl);
+    return CTQR_OK;
+}
+
+ctqr_status gemm_nn_bf16x3(int M, int N, int K, float alpha, float *C, int64_t ldc, const __bf16 *split,
+                           size_t split_elems, hipStream_t st)
+{
+    if (M <= 0 || N <= 0 || K <= 0) return CTQR_OK;
+    SplitParts p;
+    if (!split_parts(M, N, K, const_cast<__bf16 *>(split), split_elems, p)) return CTQR_ENOMEM;
+    dim3 grid((unsigned)(ceil_div(M, TILE) * ceil_div(N, TILE)));
+    LAUNCH_TRY(gemm_nn_bf16x3_kernel, grid, dim3(NTHR), 0, st, M, N, K, (const __bf16 *)p.vh, (const __bf16 *)p.vl,
+               (int64_t)p.kp, (const __bf16 *)p.wh, (const __bf16 *)p.wl, (int64_t)p.kp, alpha, C, ldc,
+               (const int *)nullptr);
+    return CTQR_OK;
+}
+
 template ctqr_status gemm_tn<float>(int, int, int, const float *, int64_t, int, const float *,
                                     int64_t, int, float, float, float *, int64_t, float *, size_t,
-                                    const int *, hipStream_t, int, bool);
+                                    const int *, hipStream_t, int, int);
 template ctqr_status gemm_tn<double>(int, int, int, const double *, int64_t, int, const double *,
                                      int64_t, int, double, double, double *, int64_t, double *,
-                                     size_t, const int *, hipStream_t, int, bool);
+                                     size_t, const int *, hipStream_t, int, int);
 template ctqr_status gemm_nn<float>(int, int, int, const float *, int64_t, int, const float *,
-                                    int64_t, float, float *, int64_t, const int *, hipStream_t, int, int, bool);
+                                    int64_t, float, float *, int64_t, const int *, hipStream_t, int, int, int);
 template ctqr_status gemm_nn<double>(int, int, int, const double *, int64_t, int, const double *,
-                                     int64_t, double, double *, int64_t, const int *, hipStream_t, int, int, bool);
+                                     int64_t, double, double *, int64_t, const int *, hipStream_t, int, int, int);
 template ctqr_status gemm_nn_split<float>(int, int, int, const float *, int64_t, const float *, int64_t, float,
                                           float *, int64_t, float *, size_t, const int *, hipStream_t);
 template ctqr_status gemm_nn_split<double>(int, int, int, const double *, int64_t, const double *, int64_t,

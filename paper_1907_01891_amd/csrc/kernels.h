@@ -12,22 +12,35 @@ size_t gemm_tn_partial_elems(int M, int N, int K);
 // force_splits > 0 fixes the number of K splits (the partial buffer must hold
 // them, else CTQR_ENOMEM): products over different column ranges of one
 // matrix then sum every output in the same order.  bf16 (FP32 operands,
-// 128-wide tiles): operands rounded to bf16 while staged, BF16 MFMA with FP32
-// accumulation; gemm_nn honours it for the trailing update (kind 1) only.
+// 128-wide tiles), the bf16 parts each operand is staged as: 1 = rounded to
+// bf16, 2 = split into high and low bf16 parts with three products; BF16 MFMA
+// with FP32 accumulation.  gemm_nn honours it for the trailing update (kind
+// 1) only.
 template <typename T>
 ctqr_status gemm_tn(int M, int N, int K, const T *A, int64_t lda, int amask, const T *B,
                     int64_t ldb, int bmask, T alpha, T beta, T *Out, int64_t ldo, T *part,
                     size_t part_elems, const int *skip, hipStream_t st, int force_splits = 0,
-                    bool bf16 = false);
+                    int bf16 = 0);
 template <typename T>
 ctqr_status gemm_nn(int M, int N, int K, const T *A, int64_t lda, int amask, const T *B,
                     int64_t ldb, T alpha, T *C, int64_t ldc, const int *skip, hipStream_t st,
-                    int kind = 0, int accum = 1, bool bf16 = false);
+                    int kind = 0, int accum = 1, int bf16 = 0);
 // C += alpha A B (A not a Householder block), split over K into part when the
 // output has too few tiles to fill the chip.
 template <typename T>
 ctqr_status gemm_nn_split(int M, int N, int K, const T *A, int64_t lda, const T *B, int64_t ldb, T alpha,
                           T *C, int64_t ldc, T *part, size_t part_elems, const int *skip, hipStream_t st);
+
+// Split-BF16 trailing update C += alpha V W' (V: M x K Householder block,
+// column-major lda; W': K x N, column-major ldw).  bf16x3_split writes both
+// operands' high and low bf16 parts to `split` (bf16x3_split_elems(m, n, nb)
+// elements cover any M <= m, N <= n, K <= nb); gemm_nn_bf16x3 then forms the
+// product from them, three BF16 products per pair with FP32 accumulation.
+size_t bf16x3_split_elems(int64_t m, int64_t n, int nb);
+ctqr_status bf16x3_split(int M, int N, int K, const float *V, int64_t lda, const float *W, int64_t ldw,
+                         __bf16 *split, size_t split_elems, hipStream_t st);
+ctqr_status gemm_nn_bf16x3(int M, int N, int K, float alpha, float *C, int64_t ldc, const __bf16 *split,
+                           size_t split_elems, hipStream_t st);
 
 // ---- panel_qr.hip ----------------------------------------------------------
 constexpr int PANEL_XCH_STRIDE = 40;   // doubles per workgroup per exchange buffer (two buffers)

@@ -29,6 +29,7 @@ CTQR_F32 = 1
 CTQR_PREC_FP64 = 0
 CTQR_PREC_FP32_MFMA = 1
 CTQR_PREC_BF16_MFMA = 2
+CTQR_PREC_BF16X3_MFMA = 3
 CTQR_REFINE_CSNE = 0
 CTQR_REFINE_PCG = 1
 

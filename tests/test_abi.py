@@ -107,6 +107,8 @@ def test_factor_rejects_before_any_hip_call():
     assert call(rinv=ctypes.c_void_p(4104)) == C.CTQR_EINVAL  # misaligned Rinv
     assert call(wb=16) == C.CTQR_ENOMEM                       # workspace too small
     assert call(prec=C.CTQR_PREC_BF16_MFMA) == C.CTQR_EINVAL  # BF16 path not offered for FP64 storage
+    assert call(prec=C.CTQR_PREC_BF16X3_MFMA) == C.CTQR_EINVAL
+    assert call(prec=4) == C.CTQR_EINVAL                       # unknown precision
     assert C.ctqr_qr_rinv_bytes(65536, C.CTQR_F32) == 2 * 2048 * 65536 * 4
     assert C.ctqr_qr_rinv_bytes(100, C.CTQR_F64) == 2 * 2048 * 2048 * 8
 

@@ -34,12 +34,14 @@ def _random(m, n, seed, dtype):
     (6000, 5000, 256, 0, 2048, "f32"),        # everything streamed: three tiles, re-uploads
     (4500, 4096, 256, 2048, 4096, "f32"),     # one tile wider than the rest of the matrix
     (6000, 5000, 256, 2048, 2048, "bf16"),    # BF16 block-column products
+    (6000, 5000, 256, 2048, 2048, "bf16x3"),  # split-BF16 block-column products
 ])
 def test_ooc_factor_bitwise_equals_in_core(gpu, m, n, nb, n_dev, tile, dt):
     _print_case("ooc", m, n, nb, n_dev, tile, dt)
     dtype = torch.float64 if dt == "f64" else torch.float32
     cd = C.CTQR_F64 if dt == "f64" else C.CTQR_F32
-    prec = {"f64": C.CTQR_PREC_FP64, "f32": C.CTQR_PREC_FP32_MFMA, "bf16": C.CTQR_PREC_BF16_MFMA}[dt]
+    prec = {"f64": C.CTQR_PREC_FP64, "f32": C.CTQR_PREC_FP32_MFMA, "bf16": C.CTQR_PREC_BF16_MFMA,
+            "bf16x3": C.CTQR_PREC_BF16X3_MFMA}[dt]
     A = _random(m, n, 11, dtype)
     Ad = to_colmajor(A, dtype=dtype)
     F = QRFactor(Ad, prec, nb=nb).factor()

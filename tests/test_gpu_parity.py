@@ -242,3 +242,40 @@ def test_bf16_trailing_update_factor(gpu, name):
         assert si.status in (0, C.CTQR_NOT_CONVERGED)
         if si.status == 0:
             assert err <= 1e-10
+
+
+@pytest.mark.parametrize("name", ["ct24", "ct40"])
+def test_bf16x3_trailing_update_factor(gpu, name):
+    # Split BF16 (high and low bf16 parts, three products, FP32 accumulation)
+    # for the block-column products: R agrees with the oracle's far better
+    # than the one-part BF16 path and close to the FP32 path, and the refined
+    # solve reaches the oracle's solution with both refinement forms.
+    _print_case("bf16x3 factor", name)
+    g, A, X, B = oracle_problem(name)
+    QRo, tauo = oracle_factor(name)
+    n = A.shape[1]
+    Ad = A.toarray().astype(np.float32)
+    F3, info = _gpu_factor(Ad, torch.float32, C.CTQR_PREC_BF16X3_MFMA, 64)
+    F16, _ = _gpu_factor(Ad, torch.float32, C.CTQR_PREC_BF16_MFMA, 64)
+    F32, _ = _gpu_factor(Ad, torch.float32, C.CTQR_PREC_FP32_MFMA, 64)
+    assert info.status == 0, C.status_string(info.status)
+    sn = lambda R: np.sign(np.diag(R))[:, None] * R
+    Ron = sn(np.triu(QRo[:n, :n]))
+    err = {}
+    for key, F in (("x3", F3), ("bf16", F16), ("fp32", F32)):
+        R = sn(np.triu(download(F.A)[:n, :n]).astype(np.float64))
+        err[key] = np.abs(R - Ron).max() / np.abs(Ron).max()
+    print("R rel err: bf16x3 %.2e, bf16 %.2e, fp32 %.2e" % (err["x3"], err["bf16"], err["fp32"]))
+    assert err["x3"] <= 1e-4
+    assert err["x3"] * 30 < err["bf16"]
+    Bd = to_colmajor(torch.as_tensor(B), dtype=torch.float64)
+    Xo = hh.backsub(QRo, hh.apply_qt(QRo, tauo, B))
+    spA = DeviceSparse(A)
+    for method in (C.CTQR_REFINE_CSNE, C.CTQR_REFINE_PCG):
+        Xg = download(F3.solve(Bd, sparse=spA.sp, tol=1e-14, max_iters=30, method=method))
+        torch.cuda.synchronize()
+        si = F3.sinfo.read()
+        e = lsq.rel_err(Xg, Xo).max()
+        print("bf16x3 refined (method %d): status %d iters %d err %.2e" % (method, si.status, si.iters, e))
+        assert si.status == 0
+        assert e <= 1e-10
