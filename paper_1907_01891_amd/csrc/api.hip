@@ -94,6 +94,8 @@ struct FactorWS {
     T *Tin, *GW, *W2, *split, *rtmp;
     __bf16 *bsplit;          // split-BF16 parts of V and W' (FP32 factor only)
     size_t bsplit_elems;
+    __bf16 *vtsplit;         // split-BF16 parts of V, column-major, for [G | W]
+    size_t vtsplit_elems;
     size_t bytes;
     int bf16 = 0;   // block-column GEMMs ([G | W], trailing update): bf16 parts per operand (0: none)
 };
@@ -116,6 +118,8 @@ FactorWS<T> carve_factor(void *work, int64_t m, int64_t n, int nb)
     w.rtmp = c.take<T>((int64_t)trinv_tmp_elems());
     w.bsplit_elems = sizeof(T) == 4 ? bf16x3_split_elems(m, n, nb) : 0;
     w.bsplit = c.take<__bf16>((int64_t)w.bsplit_elems);
+    w.vtsplit_elems = sizeof(T) == 4 ? bf16x3_vt_elems(m, nb) : 0;
+    w.vtsplit = c.take<__bf16>((int64_t)w.vtsplit_elems);
     w.bytes = c.off + 256;
     return w;
 }
@@ -255,6 +259,25 @@ ctqr_status trailing_update(int mk, int nc, int nbk, const T *V, int64_t lda, co
     return CTQR_OK;
 }
 
+// [G | W] = V^T B of one block column (V: K x M Householder block, the first
+// bmask columns of B too), into w.GW.  Split BF16 splits V once for all the
+// column tiles.
+template <typename T>
+ctqr_status block_reduction(int M, int N, int K, const T *V, int64_t lda, const T *B, int64_t ldb, int bmask,
+                            FactorWS<T> &w, int nb, int force_splits, hipStream_t st)
+{
+    if constexpr (sizeof(T) == 4) {
+        if (w.bf16 == 2) {
+            ctqr_status s = bf16x3_split_vt(K, M, V, lda, w.vtsplit, w.vtsplit_elems, st);
+            if (s) return s;
+            return gemm_tn_bf16x3(M, N, K, w.vtsplit, w.vtsplit_elems, B, ldb, bmask, 1.0f, 0.0f, w.GW, nb, w.split,
+                                  SPLIT_PART_ELEMS, nullptr, st, force_splits);
+        }
+    }
+    return gemm_tn<T>(M, N, K, V, lda, M, B, ldb, bmask, T(1), T(0), w.GW, nb, w.split, SPLIT_PART_ELEMS, nullptr,
+                      st, force_splits, w.bf16);
+}
+
 // Split counts of the two reductions of block k0 in the all-in-HBM
 // factorization of an m x n matrix ([G | W] = V^T [V | C] and W' = T^T W).
 // Every other caller that touches block k0's columns forces the same counts,
@@ -305,8 +328,7 @@ ctqr_status factor_blocks(int m, int n, T *A, int64_t lda, int nb, int kb, int k
         // block reflector of the whole block column: [G | W] = V^T [V | C]
         const int nc = std::max(0, ce - (k0 + nbk));
         const T *V = A + (int64_t)k0 * lda + k0;
-        s = gemm_tn<T>(nbk, nbk + nc, m - k0, V, lda, nbk, V, lda, nbk, T(1), T(0), w.GW, nb, w.split,
-                       SPLIT_PART_ELEMS, nullptr, st, sp.gw, w.bf16);
+        s = block_reduction<T>(nbk, nbk + nc, m - k0, V, lda, V, lda, nbk, w, nb, sp.gw, st);
         if (s) return s;
         T *Tk = Tout + (int64_t)k0 * nb;
         if ((s = tbuild<T, T>(nbk, w.GW, nb, tau + k0, Tk, nb, w.Tw, st))) return s;
@@ -340,8 +362,7 @@ ctqr_status apply_blocks(int m, int n, const T *V, int64_t lda, const T *Tf, int
         const T *Vk = V + (int64_t)k0 * lda + k0;
         T *Ck = C + (int64_t)c0 * lda + k0;
         // the in-HBM call forms [G | W] at once: its split count applies
-        s = gemm_tn<T>(nbk, nc, m - k0, Vk, lda, nbk, Ck, lda, 0, T(1), T(0), w.GW, nb, w.split,
-                       SPLIT_PART_ELEMS, nullptr, st, sp.gw, w.bf16);
+        s = block_reduction<T>(nbk, nc, m - k0, Vk, lda, Ck, lda, 0, w, nb, sp.gw, st);
         if (s) return s;
         s = gemm_tn<T>(nbk, nc, nbk, Tf + (int64_t)k0 * nb, nb, 0, w.GW, nb, 0, T(1), T(0), w.W2, nb, w.split,
                        SPLIT_PART_ELEMS, nullptr, st, sp.tw);

@@ -32,12 +32,14 @@
 // values with one LDS read; the sum over k is unchanged.  Workgroup ids are
 // remapped so the tiles one XCD runs are neighbours (shared L2 lines).
 //
-// BF16 products of FP32 operands (the template parameter BF counts the bf16
-// parts each operand is staged as): BF = 1 rounds every operand to bf16 (one
-// v_mfma_f32_32x32x16_bf16 product); BF = 2 splits it into a high part
-// h = bf16(x) and a low part l = bf16(x - h), exact to about 16 bits, and sums
-// the three products l h', h l', h h' (the l l' term is below the FP32
-// accumulation's own rounding for most sums).  Both accumulate in FP32.
+// BF16 products of FP32 operands, accumulated in FP32.  One part (template
+// parameter BF = 1): every operand rounded to bf16, one
+// v_mfma_f32_32x32x16_bf16 product.  Split (the *_bf16x3 kernels): each
+// operand as a high part h = bf16(x) and a low part l = bf16(x - h), exact to
+// about 16 bits, and the three products l h', h l', h h' (the l l' term lies
+// below the FP32 accumulation's own rounding for most sums).  The Householder
+// block V is split once per block column, in the layout each product reads;
+// C, read by only two tiles of [G | W], is split while staged.
 #include <type_traits>
 
 #include "common.h"
@@ -513,14 +515,13 @@ void gemm_tn_kernel(int M, int N, int K,
     using Mt = Mf<T>;
     using W = WaveTile<T, TW>;
     if (skip && *skip) return;
-    // BF > 0: FP32 operands staged as BF bf16 parts (BF16 MFMA, FP32
-    // accumulation)
-    static_assert(BF == 0 || (sizeof(T) == 4 && TW == TILE && BF <= 2), "bf16 path: FP32, 128-wide tiles");
+    // BF = 1: FP32 operands rounded to bf16 while staged (BF16 MFMA, FP32
+    // accumulation; split operands: gemm_tn_bf16x3_kernel)
+    static_assert(BF == 0 || (sizeof(T) == 4 && TW == TILE && BF == 1), "bf16 path: FP32, 128-wide tiles");
     using LT = typename std::conditional<(BF > 0), __bf16, T>::type;
-    constexpr int NP = BF == 2 ? 2 : 1;
     constexpr int LDX = BF ? KcTile<T>::LDB : KcTile<T>::LD;
-    __shared__ __attribute__((aligned(16))) LT sA[2][NP][TILE * LDX];
-    __shared__ __attribute__((aligned(16))) LT sB[2][NP][TW * LDX];
+    __shared__ __attribute__((aligned(16))) LT sA[2][TILE * LDX];
+    __shared__ __attribute__((aligned(16))) LT sB[2][TW * LDX];
 
     int tm, tn;
     tile_of_block((M + TILE - 1) / TILE, (N + TW - 1) / TW, tm, tn);
@@ -540,16 +541,13 @@ void gemm_tn_kernel(int M, int N, int K,
 
     KcTile<T> la;
     KcTile<T, TW> lb;
-    auto stage = [](const KcTile<T> &a, const KcTile<T, TW> &b, LT (*da)[TILE * LDX], LT (*db)[TW * LDX]) {
-        if constexpr (BF == 2) {
-            a.store_bf2(da[0], da[NP - 1]);
-            b.store_bf2(db[0], db[NP - 1]);
-        } else if constexpr (BF == 1) {
-            a.store_bf(da[0]);
-            b.store_bf(db[0]);
+    auto stage = [](const KcTile<T> &a, const KcTile<T, TW> &b, LT *da, LT *db) {
+        if constexpr (BF == 1) {
+            a.store_bf(da);
+            b.store_bf(db);
         } else {
-            a.store(da[0]);
-            b.store(db[0]);
+            a.store(da);
+            b.store(db);
         }
     };
     if (kbeg < kend) {
@@ -565,12 +563,10 @@ void gemm_tn_kernel(int M, int N, int K,
             la.load(A, lda, M, m0, k + Mt::BK, kend, amask);
             lb.load(B, ldb, N, n0, k + Mt::BK, kend, bmask);
         }
-        if constexpr (BF == 2)
-            mfma_step_bf2<W::NI, W::NJ>(sB[cur][0], sB[cur][NP - 1], sA[cur][0], sA[cur][NP - 1], wn, wm, acc);
-        else if constexpr (BF == 1)
-            mfma_step_bf<W::NI, W::NJ>(sB[cur][0], sA[cur][0], wn, wm, acc);
+        if constexpr (BF == 1)
+            mfma_step_bf<W::NI, W::NJ>(sB[cur], sA[cur], wn, wm, acc);
         else
-            mfma_step<T, true, W::NI, W::NJ>(sB[cur][0], sA[cur][0], wn, wm, acc);
+            mfma_step<T, true, W::NI, W::NJ>(sB[cur], sA[cur], wn, wm, acc);
         if (more) stage(la, lb, sA[cur ^ 1], sB[cur ^ 1]);
         __syncthreads();
         cur ^= 1;
@@ -656,11 +652,10 @@ void gemm_nn_kernel(int M, int N, int K,
     static_assert(BF == 0 || (sizeof(T) == 4 && TW == TILE && !SPLIT && BF == 1),
                   "bf16 path: FP32, 128-wide, unsplit, one part (split parts: gemm_nn_bf16x3_kernel)");
     using LT = typename std::conditional<(BF > 0), __bf16, T>::type;
-    constexpr int NP = BF == 2 ? 2 : 1;
     constexpr int SA = BF ? TILE * (Mt::BK + 8) : Mt::BK * MkTile<T>::LD;
     constexpr int SB = TW * (BF ? KcTile<T>::LDB : KcTile<T>::LD);
-    __shared__ __attribute__((aligned(16))) LT sA[2][NP][SA];
-    __shared__ __attribute__((aligned(16))) LT sB[2][NP][SB];
+    __shared__ __attribute__((aligned(16))) LT sA[2][SA];
+    __shared__ __attribute__((aligned(16))) LT sB[2][SB];
 
     int tm, tn;
     tile_of_block((M + TILE - 1) / TILE, (N + TW - 1) / TW, tm, tn);
@@ -704,16 +699,13 @@ void gemm_nn_kernel(int M, int N, int K,
     using ATile = typename std::conditional<(BF > 0), MkTileBf<T>, MkTile<T>>::type;
     ATile la;
     KcTile<T, TW> lb;
-    auto stage = [](const ATile &a, const KcTile<T, TW> &b, LT (*da)[SA], LT (*db)[SB]) {
-        if constexpr (BF == 2) {
-            a.store_bf2(da[0], da[NP - 1]);
-            b.store_bf2(db[0], db[NP - 1]);
-        } else if constexpr (BF == 1) {
-            a.store_bf(da[0]);
-            b.store_bf(db[0]);
+    auto stage = [](const ATile &a, const KcTile<T, TW> &b, LT *da, LT *db) {
+        if constexpr (BF == 1) {
+            a.store_bf(da);
+            b.store_bf(db);
         } else {
-            a.store(da[0]);
-            b.store(db[0]);
+            a.store(da);
+            b.store(db);
         }
     };
     la.load(A, lda, M, m0, kbeg, kend, amask != 0);
@@ -727,12 +719,10 @@ void gemm_nn_kernel(int M, int N, int K,
             la.load(A, lda, M, m0, k + Mt::BK, kend, amask != 0);
             lb.load(B, ldb, N, n0, k + Mt::BK, kend, 0);
         }
-        if constexpr (BF == 2)
-            mfma_step_bf2<W::NI, W::NJ>(sB[cur][0], sB[cur][NP - 1], sA[cur][0], sA[cur][NP - 1], wn, wm, acc);
-        else if constexpr (BF == 1)
-            mfma_step_bf<W::NI, W::NJ>(sB[cur][0], sA[cur][0], wn, wm, acc);
+        if constexpr (BF == 1)
+            mfma_step_bf<W::NI, W::NJ>(sB[cur], sA[cur], wn, wm, acc);
         else
-            mfma_step<T, false, W::NI, W::NJ>(sB[cur][0], sA[cur][0], wn, wm, acc);
+            mfma_step<T, false, W::NI, W::NJ>(sB[cur], sA[cur], wn, wm, acc);
         if (more) stage(la, lb, sA[cur ^ 1], sB[cur ^ 1]);
         __syncthreads();
         cur ^= 1;
@@ -917,6 +907,125 @@ void gemm_nn_bf16x3_kernel(int M, int N, int K, const __bf16 *__restrict__ Ah, c
             }
 }
 
+// V (rows x kc Householder block, column-major) to high / low bf16 parts in
+// its own column-major layout (k = row contiguous), column stride ldk; rows
+// up to ldk and columns up to cols_pad are zero.  These are the A operand of
+// the split-BF16 reduction [G | W] = V^T [V | C].  Thread: one column, 8
+// consecutive rows.
+__global__ __launch_bounds__(256)
+void split_vt_kernel(int rows, int kc, const float *__restrict__ V, int64_t lda, int ldk, int cols_pad,
+                     __bf16 *__restrict__ hi, __bf16 *__restrict__ lo)
+{
+    const int groups = ldk / 8;
+    const int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (f >= (int64_t)cols_pad * groups) return;
+    const int c = (int)(f / groups), r0 = 8 * (int)(f % groups);
+    bf16x8 oh, ol;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int r = r0 + e;
+        const float x = (r < rows && c < kc) ? vmask(V[(int64_t)c * lda + r], r, c) : 0.0f;
+        const __bf16 t = (__bf16)x;
+        oh[e] = t;
+        ol[e] = (__bf16)(x - (float)t);
+    }
+    *reinterpret_cast<bf16x8 *>(hi + (int64_t)c * ldk + r0) = oh;
+    *reinterpret_cast<bf16x8 *>(lo + (int64_t)c * ldk + r0) = ol;
+}
+
+// Out = alpha A^T B + beta Out (or split-K partials) with A given as split
+// parts (Ah / Al, [col][k], column stride ldk, zero-padded) and B an FP32
+// operand split while staged, as gemm_tn_kernel<float, 128, 2>: the same
+// products in the same order, without re-splitting A in every column tile.
+__global__ __launch_bounds__(NTHR, 2)
+void gemm_tn_bf16x3_kernel(int M, int N, int K, const __bf16 *__restrict__ Ah, const __bf16 *__restrict__ Al,
+                           int64_t ldk, const float *__restrict__ B, int64_t ldb, int bmask, float alpha, float beta,
+                           float *__restrict__ Out, int64_t ldo, float *__restrict__ part, int kchunk, const int *skip)
+{
+    using W = WaveTile<float, TILE>;
+    constexpr int BK = Mf<float>::BK;
+    constexpr int LDB = KcTile<float>::LDB;
+    constexpr int CH = BK / 8;
+    constexpr int PER = TILE * CH / NTHR;
+    if (skip && *skip) return;
+    __shared__ __attribute__((aligned(16))) __bf16 sA[2][2][TILE * LDB];
+    __shared__ __attribute__((aligned(16))) __bf16 sB[2][2][TILE * LDB];
+
+    int tm, tn;
+    tile_of_block((M + TILE - 1) / TILE, (N + TILE - 1) / TILE, tm, tn);
+    const int m0 = tm * TILE, n0 = tn * TILE;
+    const int kbeg = blockIdx.z * kchunk;
+    const int kend = min(K, kbeg + kchunk);
+    const int wave = threadIdx.x / CTQR_WAVE;
+    const int wn = W::wn(wave), wm = W::wm(wave);
+
+    floatx16 acc[W::NI][W::NJ];
+#pragma unroll
+    for (int i = 0; i < W::NI; ++i)
+#pragma unroll
+        for (int j = 0; j < W::NJ; ++j)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
+
+    bf16x8 ra[2][PER];
+    KcTile<float> lb;
+    auto load = [&](int k) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int f = (int)threadIdx.x + NTHR * q, c = f / CH, h = f % CH;
+            const int64_t o = (int64_t)(m0 + c) * ldk + k + 8 * h;
+            ra[0][q] = *reinterpret_cast<const bf16x8 *>(Ah + o);
+            ra[1][q] = *reinterpret_cast<const bf16x8 *>(Al + o);
+        }
+        lb.load(B, ldb, N, n0, k, kend, bmask);
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int f = (int)threadIdx.x + NTHR * q, c = f / CH, h = f % CH;
+            *reinterpret_cast<bf16x8 *>(&sA[buf][0][c * LDB + 8 * h]) = ra[0][q];
+            *reinterpret_cast<bf16x8 *>(&sA[buf][1][c * LDB + 8 * h]) = ra[1][q];
+        }
+        lb.store_bf2(sB[buf][0], sB[buf][1]);
+    };
+    if (kbeg < kend) {
+        load(kbeg);
+        store(0);
+    }
+    __syncthreads();
+    int cur = 0;
+    for (int k = kbeg; k < kend; k += BK) {
+        const bool more = k + BK < kend;
+        if (more) load(k + BK);
+        mfma_step_bf2<W::NI, W::NJ>(sB[cur][0], sB[cur][1], sA[cur][0], sA[cur][1], wn, wm, acc);
+        if (more) store(cur ^ 1);
+        __syncthreads();
+        cur ^= 1;
+    }
+
+    const bool split = gridDim.z > 1;
+#pragma unroll
+    for (int ib = 0; ib < W::NI; ++ib)
+#pragma unroll
+        for (int jb = 0; jb < W::NJ; ++jb)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                int n, m;
+                acc_coords<float>(ib, jb, r, n, m);
+                n += n0 + wn;
+                m += m0 + wm;
+                if (m < M && n < N) {
+                    const float v = acc[ib][jb][r];
+                    if (split) {
+                        part[((int64_t)blockIdx.z * N + n) * M + m] = v;
+                    } else {
+                        float *o = Out + (int64_t)n * ldo + m;
+                        *o = beta == 0.0f ? alpha * v : alpha * v + beta * *o;
+                    }
+                }
+            }
+}
+
 int g_num_cus = 0;
 
 int num_cus()
@@ -994,6 +1103,7 @@ ctqr_status gemm_tn(int M, int N, int K, const T *A, int64_t lda, int amask, con
                     size_t part_elems, const int *skip, hipStream_t st, int force_splits, int bf16)
 {
     if (M <= 0 || N <= 0) return CTQR_OK;
+    if (bf16 == 2) return CTQR_EINVAL;   // split operands: gemm_tn_bf16x3
     const bool narrow = N <= t_narrow_max;
     int splits = force_splits > 0 ? force_splits : gemm_tn_splits(M, N, K);
     if (splits > 1 && (part == nullptr || part_elems < (size_t)splits * M * N)) {
@@ -1008,10 +1118,6 @@ ctqr_status gemm_tn(int M, int N, int K, const T *A, int64_t lda, int amask, con
     if constexpr (sizeof(T) == 4) {
         if (bf16 == 1 && !narrow) {
             LAUNCH_TRY((gemm_tn_kernel<T, TILE, 1>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B, ldb,
-                       bmask, alpha, beta, Out, ldo, part, kchunk, skip);
-            done = true;
-        } else if (bf16 == 2 && !narrow) {
-            LAUNCH_TRY((gemm_tn_kernel<T, TILE, 2>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B, ldb,
                        bmask, alpha, beta, Out, ldo, part, kchunk, skip);
             done = true;
         }
@@ -1123,6 +1229,49 @@ ctqr_status bf16x3_split(int M, int N, int K, const float *V, int64_t lda, const
                K, V, lda, p.rows_pad, p.kp, p.vh, p.vl);
     LAUNCH_TRY(split_w_kernel, dim3((unsigned)ceil_div((int64_t)p.cols_pad * (p.kp / 8), 256)), dim3(256), 0, st, K,
                N, W, ldw, p.cols_pad, p.kp, p.wh, p.wl);
+    return CTQR_OK;
+}
+
+size_t bf16x3_vt_elems(int64_t m, int nb)
+{
+    return (size_t)(2 * up_to(m, 32) * up_to(nb, TILE));
+}
+
+ctqr_status bf16x3_split_vt(int rows, int kc, const float *V, int64_t lda, __bf16 *vt, size_t vt_elems,
+                            hipStream_t st)
+{
+    if (rows <= 0 || kc <= 0) return CTQR_OK;
+    const int ldk = (int)up_to(rows, 32), cols_pad = (int)up_to(kc, TILE);
+    if (vt == nullptr || 2 * (size_t)ldk * cols_pad > vt_elems) return CTQR_ENOMEM;
+    LAUNCH_TRY(split_vt_kernel, dim3((unsigned)ceil_div((int64_t)cols_pad * (ldk / 8), 256)), dim3(256), 0, st, rows,
+               kc, V, lda, ldk, cols_pad, vt, vt + (size_t)ldk * cols_pad);
+    return CTQR_OK;
+}
+
+ctqr_status gemm_tn_bf16x3(int M, int N, int K, const __bf16 *vt, size_t vt_elems, const float *B, int64_t ldb,
+                           int bmask, float alpha, float beta, float *Out, int64_t ldo, float *part,
+                           size_t part_elems, const int *skip, hipStream_t st, int force_splits)
+{
+    if (M <= 0 || N <= 0) return CTQR_OK;
+    const int ldk = (int)up_to(K, 32), cols_pad = (int)up_to(M, TILE);
+    if (vt == nullptr || 2 * (size_t)ldk * cols_pad > vt_elems) return CTQR_ENOMEM;
+    // the same split rule as gemm_tn (128-wide tiles), so a forced split count
+    // sums every output in the same order as there
+    const int narrow_saved = t_narrow_max;
+    t_narrow_max = 0;
+    int splits = force_splits > 0 ? force_splits : gemm_tn_splits(M, N, K);
+    t_narrow_max = narrow_saved;
+    if (splits > 1 && (part == nullptr || part_elems < (size_t)splits * M * N)) {
+        if (force_splits > 0) return CTQR_ENOMEM;
+        splits = 1;
+    }
+    int kchunk = (int)ceil_div(ceil_div(K, splits), Mf<float>::BK) * Mf<float>::BK;
+    if (kchunk <= 0) kchunk = Mf<float>::BK;
+    splits = (int)ceil_div(K > 0 ? K : 1, kchunk);
+    dim3 grid((unsigned)(ceil_div(M, TILE) * ceil_div(N, TILE)), 1, (unsigned)splits);
+    LAUNCH_TRY(gemm_tn_bf16x3_kernel, grid, dim3(NTHR), 0, st, M, N, K, vt, vt + (size_t)ldk * cols_pad,
+               (int64_t)ldk, B, ldb, bmask, alpha, beta, Out, ldo, part, kchunk, skip);
+    if (splits > 1) return splitk_reduce<float>(M, N, splits, part, alpha, beta, Out, ldo, skip, st);
     return CTQR_OK;
 }
 

@@ -12,10 +12,9 @@ size_t gemm_tn_partial_elems(int M, int N, int K);
 // force_splits > 0 fixes the number of K splits (the partial buffer must hold
 // them, else CTQR_ENOMEM): products over different column ranges of one
 // matrix then sum every output in the same order.  bf16 (FP32 operands,
-// 128-wide tiles), the bf16 parts each operand is staged as: 1 = rounded to
-// bf16, 2 = split into high and low bf16 parts with three products; BF16 MFMA
-// with FP32 accumulation.  gemm_nn honours it for the trailing update (kind
-// 1) only.
+// 128-wide tiles): 1 = operands rounded to bf16 while staged, BF16 MFMA with
+// FP32 accumulation (gemm_nn: the trailing update, kind 1, only); 2 (split
+// parts) is refused with CTQR_EINVAL: gemm_tn_bf16x3 / gemm_nn_bf16x3 below.
 template <typename T>
 ctqr_status gemm_tn(int M, int N, int K, const T *A, int64_t lda, int amask, const T *B,
                     int64_t ldb, int bmask, T alpha, T beta, T *Out, int64_t ldo, T *part,
@@ -41,6 +40,18 @@ ctqr_status bf16x3_split(int M, int N, int K, const float *V, int64_t lda, const
                          __bf16 *split, size_t split_elems, hipStream_t st);
 ctqr_status gemm_nn_bf16x3(int M, int N, int K, float alpha, float *C, int64_t ldc, const __bf16 *split,
                            size_t split_elems, hipStream_t st);
+
+// Split-BF16 reduction Out = alpha V^T B + beta Out (V: K x M Householder
+// block, M <= 256): bf16x3_split_vt writes V's high and low bf16 parts once to
+// `vt` (bf16x3_vt_elems(m, nb) elements cover any K <= m, M <= nb);
+// gemm_tn_bf16x3 then forms the products with B split while staged, split
+// over K by the same rule as gemm_tn.
+size_t bf16x3_vt_elems(int64_t m, int nb);
+ctqr_status bf16x3_split_vt(int rows, int kc, const float *V, int64_t lda, __bf16 *vt, size_t vt_elems,
+                            hipStream_t st);
+ctqr_status gemm_tn_bf16x3(int M, int N, int K, const __bf16 *vt, size_t vt_elems, const float *B, int64_t ldb,
+                           int bmask, float alpha, float beta, float *Out, int64_t ldo, float *part,
+                           size_t part_elems, const int *skip, hipStream_t st, int force_splits);
 
 // ---- panel_qr.hip ----------------------------------------------------------
 constexpr int PANEL_XCH_STRIDE = 40;   // doubles per workgroup per exchange buffer (two buffers)
