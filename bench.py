@@ -56,7 +56,8 @@ def parse():
     p.add_argument("--steps", type=int, default=2)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--workload", default="ct256")
-    p.add_argument("--nb", type=int, default=256)
+    p.add_argument("--nb", type=int, default=0,
+                   help="outer block width; 0 = picked by ctqr_qr_tune_nb on the benchmark's own A (untimed)")
     p.add_argument("--max-iters", type=int, default=30)
     p.add_argument("--tol", type=float, default=1e-12)
     p.add_argument("--prec", choices=["bf16x3", "fp32"], default="bf16x3",
@@ -272,6 +273,7 @@ def ooc_bench(args, log):
     w = get_workload(args.workload)
     m, n, S = w.m, w.n, w.n_slices
     dev = torch.device("cuda:0")
+    args.nb = args.nb or 256   # the out-of-core factorization is not tuned (tiles are multiples of 256)
     log("workload %s m=%d n=%d slices=%d (out of core)" % (w.name, m, n, S))
     C.ctqr_set_progress(lambda st, d, t: log("%s %d/%d" % ("factor columns" if st == 1 else "solve iterations",
                                                           d, t)))
@@ -424,6 +426,17 @@ def main():
     from paper_1907_01891_amd.device import Workspace
     build_dense.ws = Workspace()
 
+    tuned = None
+    if args.nb == 0:
+        # block width by timing on this A (overwrites it; every step rebuilds A)
+        build_dense(A32, C.CTQR_F32)
+        Ft = QRFactor(A32, prec_codes(C)[args.prec], nb=256)
+        nb_t, ms_col = Ft.tune_nb()
+        torch.cuda.synchronize()
+        del Ft
+        args.nb = nb_t
+        tuned = {"nb": nb_t, "ms_per_column": {"64": ms_col[0], "128": ms_col[1], "256": ms_col[2]}}
+        log("tuned nb = %d (ms per column: 64: %.3f, 128: %.3f, 256: %.3f)" % (nb_t, *ms_col))
     F = QRFactor(A32, prec_codes(C)[args.prec], nb=args.nb)
     X = colmajor(n, S, torch.float64, dev)
     ev = lambda: torch.cuda.Event(enable_timing=True)
@@ -612,7 +625,7 @@ def main():
                         "1e-3 relative noise; FP32 A, %s, FP64 panel, %s refinement with FP64 sparse "
                         "residuals" % (w.name, w.side, w.side, w.n_views, w.n_bins, m, n, S, products,
                                        args.refine.upper()),
-            "nb": args.nb, "slices": S, "products": args.prec, "parallelism": "single GPU",
+            "nb": args.nb, "nb_tuning": tuned, "slices": S, "products": args.prec, "parallelism": "single GPU",
         },
         "slices_per_s": slices_s,
         "qr_ms": t_qr, "solve_ms": t_solve, "build_ms": t_build,

@@ -201,6 +201,25 @@ ctqr_status ctqr_qr_factor(int64_t m, int64_t n, ctqr_dtype dtype, void *A, int6
                            void *work, size_t work_bytes, ctqr_info *info,
                            hipStream_t stream);
 
+/* Outer block width nb for ctqr_qr_factor, picked by timing on the caller's
+ * own matrix: each candidate nb in {64, 128, 256} factors the leading
+ * min(n, 1024) columns (rounded down to a multiple of 256, or all n columns
+ * when n < 256) with the trailing updates over all n columns, on `stream`,
+ * and the candidate with the least time per factored column wins.
+ * A is OVERWRITTEN (each candidate factors it further in place): rebuild it
+ * before the real factorization.  The stream is synchronised (the timing is
+ * read on the host).
+ *   A, lda, dtype, prec, T, tau, info   as ctqr_qr_factor.
+ *   work        ctqr_qr_workspace(m, n, dtype, prec, 256) bytes.
+ *   nb_best     host: the chosen nb.
+ *   ms_per_col  host, 3 floats or NULL: milliseconds per factored column of
+ *               each candidate, in the order 64, 128, 256.
+ * The tuned outer block width of the batched path's parameters. */
+ctqr_status ctqr_qr_tune_nb(int64_t m, int64_t n, ctqr_dtype dtype, void *A, int64_t lda,
+                            ctqr_prec prec, void *T, double *tau, void *work, size_t work_bytes,
+                            ctqr_info *info, int32_t *nb_best, float *ms_per_col,
+                            hipStream_t stream);
+
 /* Columns [c0, c1) of the dense A, rebuilt from the CSC half of a sparse copy
  * made by ctqr_build_system_matrix: column c0 + q goes to A + q * lda
  * (device, `dtype`, every entry of the lda x (c1 - c0) block written).  The

@@ -389,6 +389,55 @@ ctqr_status factor_impl(int64_t m64, int64_t n64, T *A, int64_t lda, int nb, T *
     return Rinv ? trinv_blocks<T>(n, A, lda, Rinv, w.rtmp, info, st) : CTQR_OK;
 }
 
+// Outer block width by timing: each candidate factors the leading columns of
+// A (a multiple of every candidate, with the trailing updates over all n
+// columns) and the fastest per factored column wins.  A is overwritten.
+constexpr int TUNE_NB[3] = {64, 128, 256};
+constexpr int TUNE_COLS = 1024;
+
+template <typename T>
+ctqr_status tune_nb_impl(int64_t m64, int64_t n64, T *A, int64_t lda, T *Tout, double *tau, void *work,
+                         ctqr_info *info, hipStream_t st, int bf16, int32_t *nb_best, float *ms_per_col)
+{
+    const int m = (int)m64, n = (int)n64;
+    const int cols = n < 256 ? n : std::min(n, TUNE_COLS) / 256 * 256;
+    const int ncu = std::min(device_cus(), MAX_PANEL_WG);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ctqr_status s = CTQR_OK;
+    float best = 0.0f;
+    int best_nb = TUNE_NB[2];
+    HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return CTQR_EHIP;
+    }
+    for (int i = 0; i < 3 && !s; ++i) {
+        const int nb = TUNE_NB[i];
+        FactorWS<T> w = carve_factor<T>(work, m64, n64, nb);
+        w.bf16 = bf16;
+        if ((s = info_reset(info, st))) break;
+        if ((s = fill_u32(w.bars, (ceil_div(n, PANEL_W) + 1) * GB_WORDS, 0u, st))) break;
+        if (hipEventRecord(e0, st) != hipSuccess) { s = CTQR_EHIP; break; }
+        if ((s = factor_blocks<T>(m, n, A, lda, nb, 0, cols, n, Tout, tau, w, w.bars, info, ncu, st))) break;
+        float ms = 0.0f;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            s = CTQR_EHIP;
+            break;
+        }
+        const float per = ms / (float)cols;
+        if (ms_per_col) ms_per_col[i] = per;
+        if (i == 0 || per < best) {
+            best = per;
+            best_nb = nb;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (!s) *nb_best = best_nb;
+    return s;
+}
+
 // ---------------------------------------------------------------------------
 // Out-of-core factorization (Section II-B): the leading n_dev columns stay in
 // HBM, the rest lives in pinned host memory and passes through HBM one tile of
@@ -1350,6 +1399,30 @@ ctqr_status ctqr_qr_factor(int64_t m, int64_t n, ctqr_dtype dtype, void *A, int6
                                        stream, 0);
         return factor_impl<float>(m, n, (float *)A, lda, nb, (float *)T, tau, (float *)Rinv, work, info, stream,
                                   bf16_parts(prec));
+    } catch (...) {
+        return CTQR_EHIP;
+    }
+}
+
+ctqr_status ctqr_qr_tune_nb(int64_t m, int64_t n, ctqr_dtype dtype, void *A, int64_t lda, ctqr_prec prec, void *T,
+                           double *tau, void *work, size_t work_bytes, ctqr_info *info, int32_t *nb_best,
+                           float *ms_per_col, hipStream_t stream)
+{
+    try {
+        if (m < n || n < 1 || m >= INT32_MAX || !A || !T || !tau || !work || !info || !nb_best) return CTQR_EINVAL;
+        if (lda < m || lda % 4 != 0 || !aligned16(A) || !aligned16(T)) return CTQR_EINVAL;
+        if (!prec_ok(dtype, prec)) return CTQR_EINVAL;
+        size_t need = 0;
+        ctqr_qr_workspace(m, n, dtype, prec, TUNE_NB[2], &need);
+        if (work_bytes < need || !aligned16(work)) return work_bytes < need ? CTQR_ENOMEM : CTQR_EINVAL;
+        if (!panel_fits((int)m, dtype)) return CTQR_EUNSUPPORTED;
+        ctqr_status s = ensure_setup();
+        if (s) return s;
+        if (dtype == CTQR_F64)
+            return tune_nb_impl<double>(m, n, (double *)A, lda, (double *)T, tau, work, info, stream, 0, nb_best,
+                                        ms_per_col);
+        return tune_nb_impl<float>(m, n, (float *)A, lda, (float *)T, tau, work, info, stream, bf16_parts(prec),
+                                   nb_best, ms_per_col);
     } catch (...) {
         return CTQR_EHIP;
     }

@@ -73,6 +73,8 @@ _SIGNATURES = {
     "ctqr_qr_workspace": (c_i32, [c_i64, c_i64, c_i32, c_i32, c_i32, _P(c_sz)]),
     "ctqr_qr_factor": (c_i32, [c_i64, c_i64, c_i32, c_vp, c_i64, c_i32, c_i32, c_vp, c_vp, c_vp,
                                c_vp, c_sz, c_vp, c_vp]),
+    "ctqr_qr_tune_nb": (c_i32, [c_i64, c_i64, c_i32, c_vp, c_i64, c_i32, c_vp, c_vp, c_vp, c_sz, c_vp,
+                                _P(c_i32), _P(ctypes.c_float), c_vp]),
     "ctqr_sparse_to_dense": (c_i32, [_P(ctqr_sparse), c_i32, c_i64, c_i64, c_vp, c_i64, c_vp]),
     "ctqr_qr_factor_ooc_workspace": (c_i32, [c_i64, c_i64, c_i32, c_i32, c_i32, c_i64, c_i64, _P(c_sz)]),
     "ctqr_qr_factor_ooc": (c_i32, [c_i64, c_i64, c_i32, c_vp, c_vp, c_i64, c_i64, c_i64, c_i32, c_i32, c_vp, c_vp,
@@ -172,6 +174,15 @@ def ctqr_qr_factor(m, n, dtype, A_ptr, lda, prec, nb, T_ptr, tau_ptr, rinv_ptr, 
                    stream):
     return lib().ctqr_qr_factor(m, n, dtype, A_ptr, lda, prec, nb, T_ptr, tau_ptr, rinv_ptr, work_ptr, work_bytes,
                                 info_ptr, stream)
+
+
+def ctqr_qr_tune_nb(m, n, dtype, A_ptr, lda, prec, T_ptr, tau_ptr, work_ptr, work_bytes, info_ptr, stream):
+    """(status, nb_best, [ms per column for nb = 64, 128, 256]); overwrites A."""
+    nb = c_i32()
+    ms = (ctypes.c_float * 3)()
+    st = lib().ctqr_qr_tune_nb(m, n, dtype, A_ptr, lda, prec, T_ptr, tau_ptr, work_ptr, work_bytes, info_ptr,
+                               ctypes.byref(nb), ms, stream)
+    return st, nb.value, list(ms)
 
 
 def ctqr_sparse_to_dense(sparse, dtype, c0, c1, A_ptr, lda, stream):

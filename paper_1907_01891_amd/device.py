@@ -164,6 +164,23 @@ class QRFactor:
                                  wp, wb, self.info.ptr, stream_handle(stream)), "ctqr_qr_factor")
         return self
 
+    def tune_nb(self, stream=None):
+        """Pick the outer block width by timing on this A (ctqr_qr_tune_nb);
+        A is overwritten and must be rebuilt before factor().  Sets self.nb
+        and returns (nb, ms per column for 64, 128, 256)."""
+        wp, wb = self.work.get(C.ctqr_qr_workspace(self.m, self.n, self.dtype, self.prec, 256))
+        Tt = colmajor(256, self.n, self.A.dtype, self.A.device, ld=256)
+        st, nb, ms = C.ctqr_qr_tune_nb(self.m, self.n, self.dtype, ctypes.c_void_p(self.A.data_ptr()),
+                                       ld_of(self.A), self.prec, ctypes.c_void_p(Tt.data_ptr()),
+                                       ctypes.c_void_p(self.tau.data_ptr()), wp, wb, self.info.ptr,
+                                       stream_handle(stream))
+        C.check(st, "ctqr_qr_tune_nb")
+        del Tt
+        if nb != self.nb:
+            self.nb = nb
+            self.T = colmajor(self.nb, self.n, self.A.dtype, self.A.device, ld=self.nb)
+        return nb, ms
+
     def solve(self, B, X=None, sparse=None, tol=1e-13, max_iters=0, method=C.CTQR_REFINE_CSNE, stream=None):
         """X = R^-1 Q^T B (FP64, column-major), refined with the sparse A if given."""
         S = B.shape[1]

@@ -113,6 +113,23 @@ def test_factor_rejects_before_any_hip_call():
     assert C.ctqr_qr_rinv_bytes(100, C.CTQR_F64) == 2 * 2048 * 2048 * 8
 
 
+def test_tune_nb_rejects_before_any_hip_call():
+    L = C.lib()
+    p = ctypes.c_void_p(1 << 20)
+    nb = ctypes.c_int32(-1)
+
+    def call(A=p, lda=100, prec=C.CTQR_PREC_FP64, wb=1 << 40, nbp=True, m=100, n=50):
+        return L.ctqr_qr_tune_nb(m, n, C.CTQR_F64, A, lda, prec, p, p, p, wb, p,
+                                 ctypes.byref(nb) if nbp else None, None, None)
+    assert call(A=None) == C.CTQR_EINVAL                      # null A
+    assert call(nbp=False) == C.CTQR_EINVAL                   # nowhere to put the answer
+    assert call(m=40) == C.CTQR_EINVAL                        # m < n
+    assert call(lda=102) == C.CTQR_EINVAL                     # lda not a multiple of 4
+    assert call(prec=C.CTQR_PREC_BF16X3_MFMA) == C.CTQR_EINVAL
+    assert call(wb=16) == C.CTQR_ENOMEM                       # workspace below the nb = 256 size
+    assert nb.value == -1                                     # untouched on every reject
+
+
 def test_solve_rejects_before_any_hip_call():
     L = C.lib()
     p = ctypes.c_void_p(4096)

@@ -279,3 +279,31 @@ def test_bf16x3_trailing_update_factor(gpu, name):
         print("bf16x3 refined (method %d): status %d iters %d err %.2e" % (method, si.status, si.iters, e))
         assert si.status == 0
         assert e <= 1e-10
+
+
+def test_tune_nb_then_factor(gpu):
+    # the block-width tuner times every candidate on the caller's matrix
+    # (overwriting it); the matrix rebuilt and factored with the chosen width
+    # meets the oracle
+    name = "ct48"                       # n = 2304: the tuner factors 1024 columns per candidate
+    _print_case("tune nb", name)
+    g, A, X, B = oracle_problem(name)
+    QRo, tauo = oracle_factor(name)
+    Ad = A.toarray()
+    F = QRFactor(upload_dense(Ad, torch.float64), C.CTQR_PREC_FP64, nb=256)
+    nb, ms = F.tune_nb()
+    torch.cuda.synchronize()
+    print("tuned nb %d, ms per column %s" % (nb, ms))
+    assert nb in (64, 128, 256) and F.nb == nb
+    assert all(t > 0 for t in ms)
+    F.A.copy_(upload_dense(Ad, torch.float64))
+    F.factor()
+    torch.cuda.synchronize()
+    assert F.info.read().status == 0
+    n = A.shape[1]
+    sn = lambda R: np.sign(np.diag(R))[:, None] * R
+    R = np.triu(download(F.A)[:n, :n])
+    assert np.abs(sn(R) - sn(np.triu(QRo[:n, :n]))).max() <= 1e-11 * np.abs(QRo[:n, :n]).max()
+    Xg = download(F.solve(to_colmajor(torch.as_tensor(B), dtype=torch.float64)))
+    Xo = hh.backsub(QRo, hh.apply_qt(QRo, tauo, B))
+    assert lsq.rel_err(Xg, Xo).max() <= 1e-10
