@@ -35,7 +35,6 @@ namespace {
 
 constexpr int PNT = 256;          // threads per panel workgroup
 constexpr int PW = 32;            // max panel width
-constexpr int SLD = PW + 1;       // slab LDS row stride (doubles)
 constexpr int PS = PANEL_XCH_STRIDE;   // per-workgroup exchange slots (see below)
 // exchange slots: [0, 32) partial w_c for c = j+1+slot; 32: S_aa; 33: S_av;
 // 34: S_vv; 35, 36: a(p+1, j+1) and v(p+1) before the update (workgroup 0)
@@ -56,31 +55,51 @@ __device__ inline double block_sum(double v, double *red)
     return r;
 }
 
+// Rows of a slab per lane (a wave covers a column, 64 rows at a time): the
+// slab capacities below keep every slab within these many rows per lane.
+template <typename SL> constexpr int rows_per_lane() { return sizeof(SL) == 8 ? 9 : 19; }
+
+__device__ inline double wave_sum(double v)
+{
+    // deterministic butterfly over the 64 lanes (every lane gets the total)
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
 // SL: element type of the slab.  FP64 whenever it fits in LDS; for very tall
 // FP32 panels (more rows per workgroup than an FP64 slab can hold) an FP32
 // slab, with every sum, norm and reflector scalar still formed in FP64.
+// The slab is column-major (column c of the workgroup's rows at
+// slab + c * rows_per_wg): the per-column products and updates give one wave
+// to a column, its 64 lanes on consecutive rows, and each lane keeps the
+// current reflector's values of its rows in registers.
 template <typename TS, typename SL>
 __global__ __launch_bounds__(PNT)
 void panel_qr_kernel(TS *__restrict__ A, int64_t lda, int m, int r0, int w, int rows_per_wg,
                      double *__restrict__ tau_out, double *part, double *part2,
                      double *__restrict__ gram_part, unsigned *bar, ctqr_info *info)
 {
+    constexpr int NW = PNT / CTQR_WAVE;
+    constexpr int RPL = rows_per_lane<SL>();
     extern __shared__ __attribute__((aligned(16))) unsigned char slab_raw[];
-    SL *slab = reinterpret_cast<SL *>(slab_raw);  // rows_per_wg x SLD
-    __shared__ double red[PNT / CTQR_WAVE];
-    __shared__ double wred[PNT / PW][PS];
-    __shared__ double red4[PNT / CTQR_WAVE][CTQR_WAVE];
+    SL *slab = reinterpret_cast<SL *>(slab_raw);  // column-major, column stride ldsl
+    __shared__ double red[NW];
+    __shared__ double wsum[PS];
+    __shared__ double red4[NW][CTQR_WAVE];
     __shared__ double xch[PS];
     __shared__ double tau_s[PW];
 
     const int G = gridDim.x, wg = blockIdx.x, tid = threadIdx.x;
+    const int lane = tid % CTQR_WAVE, wave = tid / CTQR_WAVE;
+    const int ldsl = rows_per_wg;
     const int row0 = r0 + wg * rows_per_wg;
     const int nrows = max(0, min(rows_per_wg, m - row0));
     unsigned epoch = 0;
 
     for (int idx = tid; idx < nrows * w; idx += PNT) {
         int c = idx / nrows, rr = idx % nrows;
-        slab[rr * SLD + c] = (SL)A[(int64_t)(r0 + c) * lda + row0 + rr];
+        slab[c * ldsl + rr] = (SL)A[(int64_t)(r0 + c) * lda + row0 + rr];
     }
     __syncthreads();
 
@@ -90,17 +109,18 @@ void panel_qr_kernel(TS *__restrict__ A, int64_t lda, int m, int r0, int w, int 
     bool nonfinite = false;
     for (int j = 0; j < w; ++j) {
         const int p = r0 + j;                     // pivot row
+        SL *colj = slab + (int64_t)j * ldsl;
         if (!have) {
             double s = 0.0;
             for (int rr = tid; rr < nrows; rr += PNT)
                 if (row0 + rr > p) {
-                    double x = slab[rr * SLD + j];
+                    double x = colj[rr];
                     s += x * x;
                 }
             s = block_sum(s, red);
             if (tid == 0) {
                 store_coherent(&part[wg], s);
-                if (wg == 0) store_coherent(&part[G], slab[(p - row0) * SLD + j]);
+                if (wg == 0) store_coherent(&part[G], colj[p - row0]);
             }
             grid_barrier(bar, epoch, info);
             double t = 0.0;
@@ -120,60 +140,90 @@ void panel_qr_kernel(TS *__restrict__ A, int64_t lda, int m, int r0, int w, int 
         if (tid == 0) tau_s[j] = tau;
         if (tau != 0.0)
             for (int rr = tid; rr < nrows; rr += PNT)
-                if (row0 + rr > p) slab[rr * SLD + j] *= scale;
+                if (row0 + rr > p) colj[rr] *= scale;
         __syncthreads();
 
         have = false;
         if (j + 1 < w) {
             double *x2 = part2 + (int64_t)(j & 1) * G * PS;    // alternate buffers by column
-            const int cl = tid % PW, rg = tid / PW;
-            const int c = j + 1 + cl;
-            double acc = 0.0, saa = 0.0, sav = 0.0, svv = 0.0;
-            if (c < w)
-                for (int rr = rg; rr < nrows; rr += PNT / PW) {
-                    const int g = row0 + rr;
-                    if (g >= p) {
-                        const double v = g == p ? 1.0 : slab[rr * SLD + j];
-                        const double a = slab[rr * SLD + c];
-                        acc += v * a;
-                        if (cl == 0 && g >= p + 2) {
-                            saa += a * a;
-                            sav += a * v;
-                            svv += v * v;
-                        }
-                    }
+            // v on this lane's rows: 1 at the pivot, 0 above it and past the
+            // slab.  Every slab read below is unconditional, with its row
+            // clamped to the slab's last row (weight 0 there) and its column to
+            // the panel's last, so the reads issue back to back instead of one
+            // per branch.  nrows >= 1 in every launched workgroup.
+            double vr[RPL];
+#pragma unroll
+            for (int k = 0; k < RPL; ++k) {
+                const int rr = lane + CTQR_WAVE * k;
+                const int g = row0 + rr;
+                const double x = (double)colj[min(rr, nrows - 1)];
+                vr[k] = (rr < nrows && g >= p) ? (g == p ? 1.0 : x) : 0.0;
+            }
+            // w_c = v^T a_c over this slab: wave wv takes columns j+1+wv+NW q,
+            // q < PW / NW; all its products first, then all its wave sums
+            constexpr int CPW = PW / NW;
+            double acc[CPW];
+#pragma unroll
+            for (int q = 0; q < CPW; ++q) {
+                const SL *col = slab + (int64_t)min(j + 1 + wave + NW * q, w - 1) * ldsl;
+                acc[q] = 0.0;
+#pragma unroll
+                for (int k = 0; k < RPL; ++k) acc[q] += vr[k] * (double)col[min(lane + CTQR_WAVE * k, nrows - 1)];
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+                for (int q = 0; q < CPW; ++q) acc[q] += __shfl_xor(acc[q], o);
+            if (lane == 0)
+#pragma unroll
+                for (int q = 0; q < CPW; ++q) {
+                    const int c = j + 1 + wave + NW * q;
+                    if (c < w) wsum[c - (j + 1)] = acc[q];
                 }
-            wred[rg][cl] = acc;
-            if (cl == 0) {
-                wred[rg][X_SAA] = saa;
-                wred[rg][X_SAV] = sav;
-                wred[rg][X_SVV] = svv;
+            // column j+1 below the next pivot: S_aa, S_av, S_vv (the last wave)
+            if (wave == NW - 1) {
+                const SL *col = slab + (int64_t)(j + 1) * ldsl;
+                double saa = 0.0, sav = 0.0, svv = 0.0;
+#pragma unroll
+                for (int k = 0; k < RPL; ++k) {
+                    const int rr = lane + CTQR_WAVE * k;
+                    const double a0 = col[min(rr, nrows - 1)];
+                    const bool in = rr < nrows && row0 + rr >= p + 2;
+                    const double a = in ? a0 : 0.0, v = in ? vr[k] : 0.0;
+                    saa += a * a;
+                    sav += a * v;
+                    svv += v * v;
+                }
+                saa = wave_sum(saa);
+                sav = wave_sum(sav);
+                svv = wave_sum(svv);
+                if (lane == 0) {
+                    wsum[X_SAA] = saa;
+                    wsum[X_SAV] = sav;
+                    wsum[X_SVV] = svv;
+                }
             }
             __syncthreads();
-            if (tid < X_A1) {
-                double s = 0.0;
-                for (int q = 0; q < PNT / PW; ++q) s += wred[q][tid];
-                if (tid >= PW || j + 1 + tid < w) store_coherent(&x2[(int64_t)wg * PS + tid], s);
-            }
+            if (tid < X_A1 && (tid >= PW || j + 1 + tid < w)) store_coherent(&x2[(int64_t)wg * PS + tid], wsum[tid]);
             if (wg == 0 && tid == 0) {
                 const int rr = p + 1 - row0;
-                store_coherent(&x2[X_A1], slab[rr * SLD + j + 1]);
-                store_coherent(&x2[X_V1], slab[rr * SLD + j]);
+                store_coherent(&x2[X_A1], slab[(int64_t)(j + 1) * ldsl + rr]);
+                store_coherent(&x2[X_V1], colj[rr]);
             }
             grid_barrier(bar, epoch, info);
 
             // totals over the workgroups, in workgroup order
             {
                 const int e = tid % CTQR_WAVE, grp = tid / CTQR_WAVE;
-                constexpr int NG = PNT / CTQR_WAVE, BATCH = 16;
+                constexpr int BATCH = 64;   // every load of up to 256 workgroups in flight
                 double s = 0.0;
                 if (e < X_A1 && (e >= PW || j + 1 + e < w))
-                    for (int q0 = grp; q0 < G; q0 += NG * BATCH) {
+                    for (int q0 = grp; q0 < G; q0 += NW * BATCH) {
                         // BATCH loads in flight, then summed in workgroup order
                         double v[BATCH];
 #pragma unroll
                         for (int u = 0; u < BATCH; ++u) {
-                            const int q = q0 + NG * u;
+                            const int q = q0 + NW * u;
                             v[u] = q < G ? load_coherent(&x2[(int64_t)q * PS + e]) : 0.0;
                         }
 #pragma unroll
@@ -183,24 +233,30 @@ void panel_qr_kernel(TS *__restrict__ A, int64_t lda, int m, int r0, int w, int 
                 __syncthreads();
                 if (tid < X_A1) {
                     double t = red4[0][tid];
-                    for (int q = 1; q < PNT / CTQR_WAVE; ++q) t += red4[q][tid];
+                    for (int q = 1; q < NW; ++q) t += red4[q][tid];
                     xch[tid] = t;
                 }
                 if (tid == X_A1 || tid == X_V1) xch[tid] = load_coherent(&x2[tid]);
                 __syncthreads();
             }
             if (tau != 0.0) {
-                // a_c -= (tau w_c) v: thread (cl, rg) takes column j+1+cl on
-                // rows rg, rg + 8, ... (as in the products above)
-                const int cl = tid % PW, rg = tid / PW;
-                const int c = j + 1 + cl;
-                if (c < w) {
-                    const double f = tau * xch[cl];
-                    for (int rr = rg; rr < nrows; rr += PNT / PW) {
-                        const int g = row0 + rr;
-                        if (g >= p) {
-                            const double v = g == p ? 1.0 : slab[rr * SLD + j];
-                            slab[rr * SLD + c] -= f * v;
+                // a_c -= (tau w_c) v, the columns of each wave as above
+#pragma unroll
+                for (int q = 0; q < CPW; ++q) {
+                    const int c = j + 1 + wave + NW * q;
+                    if (c < w) {
+                        SL *col = slab + (int64_t)c * ldsl;
+                        const double f = tau * xch[c - (j + 1)];
+                        // every read first, then the stores of the lane's own rows
+                        // (v = 0 above the pivot leaves those rows unchanged)
+                        double nv[RPL];
+#pragma unroll
+                        for (int k = 0; k < RPL; ++k)
+                            nv[k] = (double)col[min(lane + CTQR_WAVE * k, nrows - 1)] - f * vr[k];
+#pragma unroll
+                        for (int k = 0; k < RPL; ++k) {
+                            const int rr = lane + CTQR_WAVE * k;
+                            if (rr < nrows) col[rr] = (SL)nv[k];
                         }
                     }
                 }
@@ -214,31 +270,41 @@ void panel_qr_kernel(TS *__restrict__ A, int64_t lda, int m, int r0, int w, int 
                 alpha = xch[X_A1] - tw * xch[X_V1];
             }
         }
-        if (wg == 0 && tid == 0) slab[(p - row0) * SLD + j] = (SL)beta;
+        if (wg == 0 && tid == 0) colj[p - row0] = (SL)beta;
         __syncthreads();
     }
 
     // write the factored slab back in storage precision
     for (int idx = tid; idx < nrows * w; idx += PNT) {
         int c = idx / nrows, rr = idx % nrows;
-        A[(int64_t)(r0 + c) * lda + row0 + rr] = (TS)slab[rr * SLD + c];
+        A[(int64_t)(r0 + c) * lda + row0 + rr] = (TS)slab[c * ldsl + rr];
     }
     if (wg == 0 && tid < w) tau_out[tid] = tau_s[tid];
     if (nonfinite && tid == 0 && wg == 0) info_event(info, CTQR_NONFINITE, r0);
 
     // partial Gram V^T V over this slab (V unit lower trapezoidal), rounded to
-    // storage precision first so it describes the stored vectors
-    for (int e = tid; e < PW * PW; e += PNT) {
-        int c1 = e % PW, c2 = e / PW;
-        double s = 0.0;
-        if (c1 < w && c2 < w)
-            for (int rr = 0; rr < nrows; ++rr) {
-                int g = row0 + rr;
-                double v1 = g == r0 + c1 ? 1.0 : (g > r0 + c1 ? (double)(TS)slab[rr * SLD + c1] : 0.0);
-                double v2 = g == r0 + c2 ? 1.0 : (g > r0 + c2 ? (double)(TS)slab[rr * SLD + c2] : 0.0);
-                s += v1 * v2;
-            }
-        gram_part[(int64_t)wg * PW * PW + e] = s;
+    // storage precision first so it describes the stored vectors: a 32 x 32
+    // product over the slab's rows on FP64 MFMA (v_mfma_f64_16x16x4f64), one
+    // 16 x 16 block per wave.  Lane l feeds row k0 + l/16 of columns
+    // bi + l%16 and bj + l%16; output register r of lane l holds
+    // G(bi + 4r + l/16, bj + l%16).
+    __syncthreads();
+    {
+        const int bi = 16 * (wave / 2), bj = 16 * (wave % 2);
+        const int li = lane % 16, kq = lane / 16;
+        auto vval = [&](int rr, int c) -> double {
+            if (rr >= nrows || c >= w) return 0.0;
+            const int g = row0 + rr;
+            return g == r0 + c ? 1.0 : (g > r0 + c ? (double)(TS)slab[c * ldsl + rr] : 0.0);
+        };
+        doublex4 g4 = {0.0, 0.0, 0.0, 0.0};
+        for (int k0 = 0; k0 < nrows; k0 += 4) {
+            const double a = vval(k0 + kq, bi + li), b = vval(k0 + kq, bj + li);
+            g4 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, g4, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            gram_part[(int64_t)wg * PW * PW + (bi + 4 * r + kq) + PW * (bj + li)] = g4[r];
     }
 }
 
@@ -378,10 +444,11 @@ int panel_rows_per_wg(int mrem, int ncu)
 // LDS of a slab of rows_per_wg rows (element size esz).  FP64 slabs keep to
 // 144 KiB; the FP32 slab of very tall panels may take 152 KiB (the kernel's
 // static LDS adds about 5 KiB; gfx950 offers 160 KiB per workgroup).
-size_t panel_lds_bytes(int rows_per_wg, size_t esz) { return (size_t)rows_per_wg * SLD * esz; }
+size_t panel_lds_bytes(int rows_per_wg, size_t esz) { return (size_t)rows_per_wg * PW * esz; }
 
-int panel_max_rows_per_wg() { return (int)((144 * 1024) / (SLD * sizeof(double))); }
-int panel_max_rows_per_wg_f32() { return (int)((152 * 1024) / (SLD * sizeof(float))); }
+// at most 64 rows_per_lane rows per slab, the register tile of the per-column steps
+int panel_max_rows_per_wg() { return std::min((int)((144 * 1024) / (PW * sizeof(double))), 64 * rows_per_lane<double>()); }
+int panel_max_rows_per_wg_f32() { return std::min((int)((152 * 1024) / (PW * sizeof(float))), 64 * rows_per_lane<float>()); }
 
 template <typename TS>
 ctqr_status panel_qr(TS *A, int64_t lda, int m, int r0, int w, double *tau, double *part,
