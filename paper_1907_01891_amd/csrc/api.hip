@@ -131,16 +131,29 @@ struct SolveWS {
     // conjugate-gradient form: z (two, by iteration parity), p, q, dot partials, per-slice scalars
     double *z0, *z1, *p, *q, *dpart, *sz, *szp, *qq, *gamma, *beta, *alpha;
     T *s32, *y32, *d32;
+    __bf16 *bsplit;          // split-BF16 parts for the refinement's wide substitutions (or null)
+    size_t bsplit_elems;
     unsigned long long *dmax, *xmax;
     int *done;
     int64_t ldbw, ldxw;
     size_t bytes;
 };
 
+// The wide substitutions of the corrected semi-normal-equations refinement
+// take split-BF16 products (all-in-HBM FP32 factor, at least 128 slices):
+// each correction only has to contract the error, which an inexact
+// (R^T R)^-1 does.  The conjugate-gradient form (refine 2) keeps FP32
+// products: it needs the preconditioner to be the same symmetric operator
+// in every iteration, and the split products' rounding erodes conjugacy
+// before its tolerance is met.
 template <typename T>
+bool refine_split_trsm(int S, int refine) { return sizeof(T) == 4 && refine == 1 && S >= 128; }
+
 // refine: 0 none, 1 semi-normal-equations corrections, 2 also the
-// conjugate-gradient vectors
-SolveWS<T> carve_solve(void *work, int64_t m, int64_t n, int nb, int S, int refine, bool with_rinv = true)
+// conjugate-gradient vectors; trsm_split: room for those split products.
+template <typename T>
+SolveWS<T> carve_solve(void *work, int64_t m, int64_t n, int nb, int S, int refine, bool with_rinv = true,
+                       bool trsm_split = false)
 {
     Carve c(work);
     SolveWS<T> w{};
@@ -168,6 +181,8 @@ SolveWS<T> carve_solve(void *work, int64_t m, int64_t n, int nb, int S, int refi
         w.dmax = c.take<unsigned long long>(S);
         w.xmax = c.take<unsigned long long>(S);
         w.hist = c.take<double>(8);
+        w.bsplit_elems = trsm_split && refine_split_trsm<T>(S, refine) ? trsm_bf16x3_elems(n, S) : 0;
+        w.bsplit = w.bsplit_elems ? c.take<__bf16>((int64_t)w.bsplit_elems) : nullptr;
     }
     if (refine >= 2) {
         w.z0 = c.take<double>(n * S);
@@ -638,7 +653,8 @@ struct SolveRun {
 template <typename T>
 SolveRun<T> make_run(int64_t m, int64_t n, const T *QR, int64_t lda, const T *Tf, const T *Rinv, int nb,
                      const double *B, int64_t ldb, int S, const ctqr_sparse *A64, double tol, int max_iters,
-                     void *work, ctqr_info *info, bool carve_rinv, int method = CTQR_REFINE_CSNE)
+                     void *work, ctqr_info *info, bool carve_rinv, int method = CTQR_REFINE_CSNE,
+                     bool trsm_split = false)
 {
     SolveRun<T> r{};
     r.m = (int)m; r.n = (int)n; r.nb = nb; r.S = S;
@@ -646,7 +662,8 @@ SolveRun<T> make_run(int64_t m, int64_t n, const T *QR, int64_t lda, const T *Tf
     r.A64 = A64; r.tol = tol; r.max_iters = max_iters; r.method = method;
     r.narrow = S <= DEFAULT_NARROW ? DEFAULT_NARROW : 0;
     r.info = info;
-    r.w = carve_solve<T>(work, m, n, nb, S, r.refine() ? (method == CTQR_REFINE_PCG ? 2 : 1) : 0, carve_rinv);
+    r.w = carve_solve<T>(work, m, n, nb, S, r.refine() ? (method == CTQR_REFINE_PCG ? 2 : 1) : 0, carve_rinv,
+                         trsm_split);
     r.sp_elems = std::max<int64_t>(SPLIT_PART_ELEMS, 64LL * nb * S);
     return r;
 }
@@ -796,10 +813,10 @@ ctqr_status refine_iters(SolveRun<T> &r, int it0, int it1, bool host_sync, hipSt
     SolveWS<T> &w = r.w;
     auto minv = [&](const int *skip) -> ctqr_status {
         ctqr_status s = trsm_upper_trans<T>(r.n, r.S, r.QR, r.lda, r.Rinv, w.s32, w.ldxw, w.y32, w.ldxw, w.split,
-                                            r.sp_elems, skip, st);
+                                            r.sp_elems, skip, st, w.bsplit, w.bsplit_elems);
         if (s) return s;
         return trsm_upper<T>(r.n, r.S, r.QR, r.lda, r.Rinv, w.y32, w.ldxw, w.d32, w.ldxw, w.split, r.sp_elems, skip,
-                             st);
+                             st, w.bsplit, w.bsplit_elems);
     };
     return refine_iters_with(r, it0, it1, host_sync, st, ran, minv);
 }
@@ -823,7 +840,7 @@ ctqr_status solve_impl(int64_t m64, int64_t n64, const T *QR, int64_t lda, const
 {
     (void)tau;
     SolveRun<T> r = make_run<T>(m64, n64, QR, lda, Tf, Rinv_in, nb, B, ldb, S, A64, tol, max_iters, work, info,
-                                true, method);
+                                true, method, true);
     ctqr_status s = solve_start(r, st);
     if (s) return s;
     if (r.refine() && (s = refine_iters(r, 0, max_iters, true, st, nullptr))) return s;
@@ -1016,8 +1033,8 @@ SolverLayout solver_layout(const ctqr_solver_desc *d, void *work, int smax, int6
     L.Bpad = c.take<double>(ldbp * smax);
     L.swork = c.take<char>(0);
     const int refine = d->A64 != nullptr && d->max_iters > 0 ? (d->refine_method == CTQR_REFINE_PCG ? 2 : 1) : 0;
-    size_t sb = d->dtype == CTQR_F64 ? carve_solve<double>(nullptr, d->m, d->n, d->nb, smax, refine, false).bytes
-                                     : carve_solve<float>(nullptr, d->m, d->n, d->nb, smax, refine, false).bytes;
+    size_t sb = d->dtype == CTQR_F64 ? carve_solve<double>(nullptr, d->m, d->n, d->nb, smax, refine, false, true).bytes
+                                     : carve_solve<float>(nullptr, d->m, d->n, d->nb, smax, refine, false, true).bytes;
     L.bytes = c.off + sb + 256;
     return L;
 }
@@ -1028,7 +1045,7 @@ SolveRun<T> solver_run(ctqr_solver_t *sv, const SolverBucket &bk)
     const ctqr_solver_desc &d = sv->d;
     SolveRun<T> r = make_run<T>(d.m, d.n, (const T *)d.QR, d.lda, (const T *)d.T, (const T *)d.Rinv, d.nb,
                                 sv->Bpad, sv->ldbp, bk.S, sv->refine ? &sv->sp : nullptr, d.tol,
-                                sv->refine ? d.max_iters : 0, sv->swork, sv->info, false, d.refine_method);
+                                sv->refine ? d.max_iters : 0, sv->swork, sv->info, false, d.refine_method, true);
     r.narrow = bk.narrow;
     return r;
 }
@@ -1436,8 +1453,8 @@ ctqr_status ctqr_solve_workspace(int64_t m, int64_t n, ctqr_dtype dtype, int32_t
     nb = resolve_nb(nb);
     if (!nb_ok(nb)) return CTQR_EINVAL;
     if (refine < 0 || refine > 2) return CTQR_EINVAL;
-    *bytes = dtype == CTQR_F64 ? carve_solve<double>(nullptr, m, n, nb, nslices, refine).bytes
-                               : carve_solve<float>(nullptr, m, n, nb, nslices, refine).bytes;
+    *bytes = dtype == CTQR_F64 ? carve_solve<double>(nullptr, m, n, nb, nslices, refine, true, true).bytes
+                               : carve_solve<float>(nullptr, m, n, nb, nslices, refine, true, true).bytes;
     return CTQR_OK;
 }
 

@@ -767,8 +767,9 @@ void gemm_nn_kernel(int M, int N, int K,
 // (the 64 lanes of a wave read 64 consecutive rows of each column).
 __global__ __launch_bounds__(256)
 void split_v_kernel(int rows, int kc, const float *__restrict__ V, int64_t lda, int rows_pad, int ldv,
-                    __bf16 *__restrict__ hi, __bf16 *__restrict__ lo)
+                    __bf16 *__restrict__ hi, __bf16 *__restrict__ lo, int mask, const int *skip)
 {
+    if (skip && *skip) return;
     const int r = (int)blockIdx.x * 256 + (int)threadIdx.x;
     const int k0 = 8 * (int)blockIdx.y;
     if (r >= rows_pad) return;
@@ -776,7 +777,11 @@ void split_v_kernel(int rows, int kc, const float *__restrict__ V, int64_t lda, 
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
         const int k = k0 + e;
-        const float x = (r < rows && k < kc) ? vmask(V[(int64_t)k * lda + r], r, k) : 0.0f;
+        float x = 0.0f;
+        if (r < rows && k < kc) {
+            const float a = V[(int64_t)k * lda + r];
+            x = mask ? vmask(a, r, k) : a;
+        }
         const __bf16 t = (__bf16)x;
         oh[e] = t;
         ol[e] = (__bf16)(x - (float)t);
@@ -790,8 +795,9 @@ void split_v_kernel(int rows, int kc, const float *__restrict__ V, int64_t lda, 
 // zero.  Thread: one column, 8 consecutive k.
 __global__ __launch_bounds__(256)
 void split_w_kernel(int kc, int cols, const float *__restrict__ W, int64_t ldw_in, int cols_pad, int ldw,
-                    __bf16 *__restrict__ hi, __bf16 *__restrict__ lo)
+                    __bf16 *__restrict__ hi, __bf16 *__restrict__ lo, const int *skip)
 {
+    if (skip && *skip) return;
     const int groups = ldw / 8;
     const int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (f >= (int64_t)cols_pad * groups) return;
@@ -914,8 +920,9 @@ void gemm_nn_bf16x3_kernel(int M, int N, int K, const __bf16 *__restrict__ Ah, c
 // consecutive rows.
 __global__ __launch_bounds__(256)
 void split_vt_kernel(int rows, int kc, const float *__restrict__ V, int64_t lda, int ldk, int cols_pad,
-                     __bf16 *__restrict__ hi, __bf16 *__restrict__ lo)
+                     __bf16 *__restrict__ hi, __bf16 *__restrict__ lo, int mask, const int *skip)
 {
+    if (skip && *skip) return;
     const int groups = ldk / 8;
     const int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (f >= (int64_t)cols_pad * groups) return;
@@ -924,7 +931,11 @@ void split_vt_kernel(int rows, int kc, const float *__restrict__ V, int64_t lda,
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
         const int r = r0 + e;
-        const float x = (r < rows && c < kc) ? vmask(V[(int64_t)c * lda + r], r, c) : 0.0f;
+        float x = 0.0f;
+        if (r < rows && c < kc) {
+            const float a = V[(int64_t)c * lda + r];
+            x = mask ? vmask(a, r, c) : a;
+        }
         const __bf16 t = (__bf16)x;
         oh[e] = t;
         ol[e] = (__bf16)(x - (float)t);
@@ -1220,15 +1231,15 @@ bool split_parts(int M, int N, int K, __bf16 *split, size_t split_elems, SplitPa
 }  // namespace
 
 ctqr_status bf16x3_split(int M, int N, int K, const float *V, int64_t lda, const float *W, int64_t ldw,
-                         __bf16 *split, size_t split_elems, hipStream_t st)
+                         __bf16 *split, size_t split_elems, hipStream_t st, bool householder, const int *skip)
 {
     if (M <= 0 || N <= 0 || K <= 0) return CTQR_OK;
     SplitParts p;
     if (!split_parts(M, N, K, split, split_elems, p)) return CTQR_ENOMEM;
     LAUNCH_TRY(split_v_kernel, dim3((unsigned)ceil_div(p.rows_pad, 256), (unsigned)(p.kp / 8)), dim3(256), 0, st, M,
-               K, V, lda, p.rows_pad, p.kp, p.vh, p.vl);
+               K, V, lda, p.rows_pad, p.kp, p.vh, p.vl, householder ? 1 : 0, skip);
     LAUNCH_TRY(split_w_kernel, dim3((unsigned)ceil_div((int64_t)p.cols_pad * (p.kp / 8), 256)), dim3(256), 0, st, K,
-               N, W, ldw, p.cols_pad, p.kp, p.wh, p.wl);
+               N, W, ldw, p.cols_pad, p.kp, p.wh, p.wl, skip);
     return CTQR_OK;
 }
 
@@ -1238,13 +1249,13 @@ size_t bf16x3_vt_elems(int64_t m, int nb)
 }
 
 ctqr_status bf16x3_split_vt(int rows, int kc, const float *V, int64_t lda, __bf16 *vt, size_t vt_elems,
-                            hipStream_t st)
+                            hipStream_t st, bool householder, const int *skip)
 {
     if (rows <= 0 || kc <= 0) return CTQR_OK;
     const int ldk = (int)up_to(rows, 32), cols_pad = (int)up_to(kc, TILE);
     if (vt == nullptr || 2 * (size_t)ldk * cols_pad > vt_elems) return CTQR_ENOMEM;
     LAUNCH_TRY(split_vt_kernel, dim3((unsigned)ceil_div((int64_t)cols_pad * (ldk / 8), 256)), dim3(256), 0, st, rows,
-               kc, V, lda, ldk, cols_pad, vt, vt + (size_t)ldk * cols_pad);
+               kc, V, lda, ldk, cols_pad, vt, vt + (size_t)ldk * cols_pad, householder ? 1 : 0, skip);
     return CTQR_OK;
 }
 
@@ -1276,15 +1287,14 @@ ctqr_status gemm_tn_bf16x3(int M, int N, int K, const __bf16 *vt, size_t vt_elem
 }
 
 ctqr_status gemm_nn_bf16x3(int M, int N, int K, float alpha, float *C, int64_t ldc, const __bf16 *split,
-                           size_t split_elems, hipStream_t st)
+                           size_t split_elems, hipStream_t st, const int *skip)
 {
     if (M <= 0 || N <= 0 || K <= 0) return CTQR_OK;
     SplitParts p;
     if (!split_parts(M, N, K, const_cast<__bf16 *>(split), split_elems, p)) return CTQR_ENOMEM;
     dim3 grid((unsigned)(ceil_div(M, TILE) * ceil_div(N, TILE)));
     LAUNCH_TRY(gemm_nn_bf16x3_kernel, grid, dim3(NTHR), 0, st, M, N, K, (const __bf16 *)p.vh, (const __bf16 *)p.vl,
-               (int64_t)p.kp, (const __bf16 *)p.wh, (const __bf16 *)p.wl, (int64_t)p.kp, alpha, C, ldc,
-               (const int *)nullptr);
+               (int64_t)p.kp, (const __bf16 *)p.wh, (const __bf16 *)p.wl, (int64_t)p.kp, alpha, C, ldc, skip);
     return CTQR_OK;
 }
 

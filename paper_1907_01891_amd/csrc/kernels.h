@@ -36,10 +36,12 @@ ctqr_status gemm_nn_split(int M, int N, int K, const T *A, int64_t lda, const T 
 // elements cover any M <= m, N <= n, K <= nb); gemm_nn_bf16x3 then forms the
 // product from them, three BF16 products per pair with FP32 accumulation.
 size_t bf16x3_split_elems(int64_t m, int64_t n, int nb);
+// householder = false splits a plain M x K operand (a block of R).
 ctqr_status bf16x3_split(int M, int N, int K, const float *V, int64_t lda, const float *W, int64_t ldw,
-                         __bf16 *split, size_t split_elems, hipStream_t st);
+                         __bf16 *split, size_t split_elems, hipStream_t st, bool householder = true,
+                         const int *skip = nullptr);
 ctqr_status gemm_nn_bf16x3(int M, int N, int K, float alpha, float *C, int64_t ldc, const __bf16 *split,
-                           size_t split_elems, hipStream_t st);
+                           size_t split_elems, hipStream_t st, const int *skip = nullptr);
 
 // Split-BF16 reduction Out = alpha V^T B + beta Out (V: K x M Householder
 // block, M <= 256): bf16x3_split_vt writes V's high and low bf16 parts once to
@@ -48,7 +50,7 @@ ctqr_status gemm_nn_bf16x3(int M, int N, int K, float alpha, float *C, int64_t l
 // over K by the same rule as gemm_tn.
 size_t bf16x3_vt_elems(int64_t m, int nb);
 ctqr_status bf16x3_split_vt(int rows, int kc, const float *V, int64_t lda, __bf16 *vt, size_t vt_elems,
-                            hipStream_t st);
+                            hipStream_t st, bool householder = true, const int *skip = nullptr);
 ctqr_status gemm_tn_bf16x3(int M, int N, int K, const __bf16 *vt, size_t vt_elems, const float *B, int64_t ldb,
                            int bmask, float alpha, float beta, float *Out, int64_t ldo, float *part,
                            size_t part_elems, const int *skip, hipStream_t st, int force_splits);
@@ -79,13 +81,18 @@ ctqr_status trinv_blocks(int n, const T *R, int64_t ldr, T *Rinv, T *tmp, ctqr_i
 template <typename T>
 ctqr_status trinv_blocks_range(int n, int c0, int c1, const T *R, int64_t ldr, T *Rinv, T *tmp,
                                hipStream_t st);
+// bsplit: trsm_bf16x3_elems(n, S) bf16 elements, or null.  Given (FP32 R and
+// at least 128 slices), the off-diagonal block products of the wide
+// (right-looking) substitution run on split-BF16 MFMA.
+size_t trsm_bf16x3_elems(int64_t n, int S);
 template <typename T>
 ctqr_status trsm_upper(int n, int S, const T *R, int64_t ldr, const T *Rinv, T *C, int64_t ldc,
-                       T *X, int64_t ldx, T *part, size_t part_elems, const int *skip, hipStream_t st);
+                       T *X, int64_t ldx, T *part, size_t part_elems, const int *skip, hipStream_t st,
+                       __bf16 *bsplit = nullptr, size_t bsplit_elems = 0);
 template <typename T>
 ctqr_status trsm_upper_trans(int n, int S, const T *R, int64_t ldr, const T *Rinv, T *C, int64_t ldc,
                              T *Y, int64_t ldy, T *part, size_t part_elems, const int *skip,
-                             hipStream_t st);
+                             hipStream_t st, __bf16 *bsplit = nullptr, size_t bsplit_elems = 0);
 // out[k] = A(k, k) for k in [c0, c1)
 template <typename T>
 ctqr_status diag_copy(int c0, int c1, const T *A, int64_t lda, T *out, hipStream_t st);

@@ -277,10 +277,25 @@ ctqr_status rdiag_check(int n, const T *R, int64_t ldr, double *scratch, ctqr_in
 //    block at once, C_i -= R_{i, i+1:} X_{i+1:} (a 2048-row product with a
 //    long inner dimension, split over it, so every step fills the chip).
 // Narrow right-hand sides (the 32-wide slice tile) use the left-looking order.
+// Split-BF16 products for the off-diagonal blocks of a wide substitution
+// (FP32 factor, at least one 128-wide slice tile, `bsplit` given): the
+// refinement applies (R^T R)^-1 only as a preconditioner, which needs the
+// accuracy of the factor itself (about 16 bits for a split-BF16 factor), not
+// FP32's.  The diagonal-block products with the stored inverses stay FP32.
+constexpr int BF16X3_MIN_SLICES = 128;
+
+size_t trsm_bf16x3_elems(int64_t n, int S)
+{
+    const int64_t np = ceil_div(n, 128) * 128, sp = ceil_div(S, 128) * 128;
+    return (size_t)(2 * np * BIG + 2 * sp * BIG);
+}
+
 template <typename T>
 ctqr_status trsm_upper(int n, int S, const T *R, int64_t ldr, const T *Rinv, T *C, int64_t ldc,
-                       T *X, int64_t ldx, T *part, size_t part_elems, const int *skip, hipStream_t st)
+                       T *X, int64_t ldx, T *part, size_t part_elems, const int *skip, hipStream_t st,
+                       __bf16 *bsplit, size_t bsplit_elems)
 {
+    const bool bf = sizeof(T) == 4 && bsplit && S >= BF16X3_MIN_SLICES;
     const T *RinvT = Rinv + trinv_elems(n);
     const int nblk = (int)ceil_div(n, BIG);
     const bool left = S <= gemm_narrow_max();
@@ -299,6 +314,15 @@ ctqr_status trsm_upper(int n, int S, const T *R, int64_t ldr, const T *Rinv, T *
         if (s) return s;
         if (!left && r0 > 0) {
             // C_{0:r0} -= R_{0:r0, i} X_i
+            if constexpr (sizeof(T) == 4) {
+                if (bf) {
+                    s = bf16x3_split(r0, S, bw, R + (int64_t)r0 * ldr, ldr, X + r0, ldx, bsplit, bsplit_elems, st,
+                                     false, skip);
+                    if (!s) s = gemm_nn_bf16x3(r0, S, bw, -1.0f, C, ldc, bsplit, bsplit_elems, st, skip);
+                    if (s) return s;
+                    continue;
+                }
+            }
             s = gemm_nn<T>(r0, S, bw, R + (int64_t)r0 * ldr, ldr, 0, X + r0, ldx, T(-1), C, ldc, skip, st);
             if (s) return s;
         }
@@ -312,8 +336,9 @@ ctqr_status trsm_upper(int n, int S, const T *R, int64_t ldr, const T *Rinv, T *
 template <typename T>
 ctqr_status trsm_upper_trans(int n, int S, const T *R, int64_t ldr, const T *Rinv, T *C, int64_t ldc,
                              T *Y, int64_t ldy, T *part, size_t part_elems, const int *skip,
-                             hipStream_t st)
+                             hipStream_t st, __bf16 *bsplit, size_t bsplit_elems)
 {
+    const bool bf = sizeof(T) == 4 && bsplit && S >= BF16X3_MIN_SLICES;
     const int nblk = (int)ceil_div(n, BIG);
     const bool left = S <= gemm_narrow_max();
     for (int i = 0; i < nblk; ++i) {
@@ -332,6 +357,17 @@ ctqr_status trsm_upper_trans(int n, int S, const T *R, int64_t ldr, const T *Rin
         const int rest = n - r0 - bw;
         if (!left && rest > 0) {
             // C_{i+1:} -= (R_{i, i+1:})^T Y_i
+            if constexpr (sizeof(T) == 4) {
+                if (bf) {
+                    s = bf16x3_split_vt(bw, rest, R + (int64_t)(r0 + bw) * ldr + r0, ldr, bsplit, bsplit_elems, st,
+                                        false, skip);
+                    if (!s)
+                        s = gemm_tn_bf16x3(rest, S, bw, bsplit, bsplit_elems, Y + r0, ldy, 0, -1.0f, 1.0f,
+                                           C + r0 + bw, ldc, part, part_elems, skip, st, 0);
+                    if (s) return s;
+                    continue;
+                }
+            }
             s = gemm_tn<T>(rest, S, bw, R + (int64_t)(r0 + bw) * ldr + r0, ldr, 0, Y + r0, ldy, 0,
                            T(-1), T(1), C + r0 + bw, ldc, part, part_elems, skip, st);
             if (s) return s;
@@ -392,9 +428,10 @@ ctqr_status trsm_upper_trans_cols(int n, int S, const T *R, int64_t ldr, const T
     template ctqr_status rdiag_check<T>(int, const T *, int64_t, double *, ctqr_info *, hipStream_t);   \
     template ctqr_status diag_copy<T>(int, int, const T *, int64_t, T *, hipStream_t);                  \
     template ctqr_status trsm_upper<T>(int, int, const T *, int64_t, const T *, T *, int64_t, T *,       \
-                                       int64_t, T *, size_t, const int *, hipStream_t);                 \
+                                       int64_t, T *, size_t, const int *, hipStream_t, __bf16 *, size_t); \
     template ctqr_status trsm_upper_trans<T>(int, int, const T *, int64_t, const T *, T *, int64_t,     \
-                                             T *, int64_t, T *, size_t, const int *, hipStream_t);      \
+                                             T *, int64_t, T *, size_t, const int *, hipStream_t,       \
+                                             __bf16 *, size_t);                                          \
     template ctqr_status trsm_upper_cols<T>(int, int, const T *, int64_t, const T *, T *, int64_t, T *,  \
                                             int64_t, int, int, T *, size_t, const int *, hipStream_t);  \
     template ctqr_status trsm_upper_trans_cols<T>(int, int, const T *, int64_t, const T *, T *, int64_t, \

@@ -217,3 +217,38 @@ def test_two_block_substitution_orders(gpu, dtype):
         err = lsq.rel_err(Xg, Xo[:, :S]).max()
         print("%s S %d err %.3e iters %d" % (dtype, S, err, si.iters))
         assert err <= 1e-10
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("method", [C.CTQR_REFINE_CSNE, C.CTQR_REFINE_PCG])
+def test_wide_refinement_with_split_substitutions(gpu, prec, method):
+    # 130 slices (>= 128) of an n = 2304 problem (two diagonal blocks): the
+    # corrected semi-normal-equations refinement's right-looking
+    # substitutions take split-BF16 off-diagonal products (the
+    # conjugate-gradient form keeps FP32 ones), directly and through the
+    # batched solver (bucket 192); the refined solution meets the oracle
+    name = "ct48"
+    g, A, X, B = oracle_problem(name, n_slices=130)
+    QRo, tauo = oracle_factor(name)
+    Xo = hh.backsub(QRo, hh.apply_qt(QRo, tauo, B))
+    code = {"fp32": C.CTQR_PREC_FP32_MFMA, "bf16x3": C.CTQR_PREC_BF16X3_MFMA}[prec]
+    F = _factor(A, torch.float32, code, nb=128)
+    spA = DeviceSparse(A)
+    Bd = to_colmajor(torch.as_tensor(B), dtype=torch.float64)
+    _print_case("wide refinement", name, prec, "method", method)
+    Xg = download(F.solve(Bd, sparse=spA.sp, tol=1e-14, max_iters=40, method=method))
+    torch.cuda.synchronize()
+    si = F.sinfo.read()
+    err = lsq.rel_err(Xg, Xo).max()
+    print("direct: status %d iters %d err %.2e" % (si.status, si.iters, err))
+    assert si.status == 0 and err <= 1e-10
+    sv = Solver(F, max_slices=130, sparse=spA.sp, tol=1e-14, max_iters=40, method=method)
+    for rep in range(2):
+        _print_case("wide refinement solver", prec, method, rep)
+        Xs = download(sv.solve(Bd))
+        torch.cuda.synchronize()
+        info = sv.info.read()
+        assert info.status == 0, (C.status_string(info.status), info.iters)
+        assert lsq.rel_err(Xs, Xo).max() <= 1e-10
+    assert sv.query(130)[0] == 192
+    sv.close()
