@@ -131,8 +131,8 @@ struct SolveWS {
     // conjugate-gradient form: z (two, by iteration parity), p, q, dot partials, per-slice scalars
     double *z0, *z1, *p, *q, *dpart, *sz, *szp, *qq, *gamma, *beta, *alpha;
     T *s32, *y32, *d32;
-    __bf16 *bsplit;          // split-BF16 parts for the refinement's wide substitutions (or null)
-    size_t bsplit_elems;
+    __bf16 *rparts;          // split-BF16 parts of R for the refinement's wide substitutions (or null)
+    __bf16 *xparts;          // and of their right-hand sides (or null)
     unsigned long long *dmax, *xmax;
     int *done;
     int64_t ldbw, ldxw;
@@ -150,10 +150,13 @@ template <typename T>
 bool refine_split_trsm(int S, int refine) { return sizeof(T) == 4 && refine == 1 && S >= 128; }
 
 // refine: 0 none, 1 semi-normal-equations corrections, 2 also the
-// conjugate-gradient vectors; trsm_split: room for those split products.
+// conjugate-gradient vectors; trsm_split: room for those split products
+// (TRSM_PARTS_X: the right-hand sides' parts only, R's are elsewhere;
+// TRSM_PARTS_ALL: R's parts too).
+constexpr int TRSM_PARTS_NONE = 0, TRSM_PARTS_X = 1, TRSM_PARTS_ALL = 2;
 template <typename T>
 SolveWS<T> carve_solve(void *work, int64_t m, int64_t n, int nb, int S, int refine, bool with_rinv = true,
-                       bool trsm_split = false)
+                       int trsm_split = TRSM_PARTS_NONE)
 {
     Carve c(work);
     SolveWS<T> w{};
@@ -181,8 +184,9 @@ SolveWS<T> carve_solve(void *work, int64_t m, int64_t n, int nb, int S, int refi
         w.dmax = c.take<unsigned long long>(S);
         w.xmax = c.take<unsigned long long>(S);
         w.hist = c.take<double>(8);
-        w.bsplit_elems = trsm_split && refine_split_trsm<T>(S, refine) ? trsm_bf16x3_elems(n, S) : 0;
-        w.bsplit = w.bsplit_elems ? c.take<__bf16>((int64_t)w.bsplit_elems) : nullptr;
+        const bool parts = trsm_split != TRSM_PARTS_NONE && refine_split_trsm<T>(S, refine);
+        w.xparts = parts ? c.take<__bf16>((int64_t)trsm_xparts_elems(S)) : nullptr;
+        w.rparts = parts && trsm_split == TRSM_PARTS_ALL ? c.take<__bf16>((int64_t)trsm_rparts_elems(n)) : nullptr;
     }
     if (refine >= 2) {
         w.z0 = c.take<double>(n * S);
@@ -647,14 +651,17 @@ struct SolveRun {
     ctqr_info *info;
     SolveWS<T> w;
     int64_t sp_elems;
+    TrsmParts tp{};  // split-BF16 parts of the refinement's substitutions (tp.x null: none)
+    bool split_r;    // R's parts are made by this run (refine_setup), not kept by a solver
     bool refine() const { return A64 != nullptr && max_iters > 0; }
+    const TrsmParts *parts() const { return tp.x ? &tp : nullptr; }
 };
 
 template <typename T>
 SolveRun<T> make_run(int64_t m, int64_t n, const T *QR, int64_t lda, const T *Tf, const T *Rinv, int nb,
                      const double *B, int64_t ldb, int S, const ctqr_sparse *A64, double tol, int max_iters,
                      void *work, ctqr_info *info, bool carve_rinv, int method = CTQR_REFINE_CSNE,
-                     bool trsm_split = false)
+                     int trsm_split = TRSM_PARTS_NONE)
 {
     SolveRun<T> r{};
     r.m = (int)m; r.n = (int)n; r.nb = nb; r.S = S;
@@ -665,6 +672,9 @@ SolveRun<T> make_run(int64_t m, int64_t n, const T *QR, int64_t lda, const T *Tf
     r.w = carve_solve<T>(work, m, n, nb, S, r.refine() ? (method == CTQR_REFINE_PCG ? 2 : 1) : 0, carve_rinv,
                          trsm_split);
     r.sp_elems = std::max<int64_t>(SPLIT_PART_ELEMS, 64LL * nb * S);
+    r.tp.x = r.w.xparts;
+    r.tp.r = r.w.rparts;
+    r.split_r = r.w.rparts != nullptr;
     return r;
 }
 
@@ -703,6 +713,9 @@ ctqr_status refine_setup(SolveRun<T> &r, hipStream_t st)
     if ((s = fill_f64(w.hist, 8, 0.0, st))) return s;
     if ((s = fill_u32((unsigned *)w.dmax, 2LL * S, 0u, st))) return s;
     if ((s = fill_u32((unsigned *)w.xmax, 2LL * S, 0u, st))) return s;
+    if constexpr (sizeof(T) == 4) {
+        if (r.split_r && (s = trsm_split_r(r.n, r.QR, r.lda, w.rparts, st))) return s;
+    }
     if (r.method != CTQR_REFINE_PCG) return CTQR_OK;
     if ((s = fill_f64(w.p, (int64_t)r.n * S, 0.0, st))) return s;
     return fill_f64(w.gamma, S, 0.0, st);
@@ -813,10 +826,10 @@ ctqr_status refine_iters(SolveRun<T> &r, int it0, int it1, bool host_sync, hipSt
     SolveWS<T> &w = r.w;
     auto minv = [&](const int *skip) -> ctqr_status {
         ctqr_status s = trsm_upper_trans<T>(r.n, r.S, r.QR, r.lda, r.Rinv, w.s32, w.ldxw, w.y32, w.ldxw, w.split,
-                                            r.sp_elems, skip, st, w.bsplit, w.bsplit_elems);
+                                            r.sp_elems, skip, st, r.parts());
         if (s) return s;
         return trsm_upper<T>(r.n, r.S, r.QR, r.lda, r.Rinv, w.y32, w.ldxw, w.d32, w.ldxw, w.split, r.sp_elems, skip,
-                             st, w.bsplit, w.bsplit_elems);
+                             st, r.parts());
     };
     return refine_iters_with(r, it0, it1, host_sync, st, ran, minv);
 }
@@ -840,7 +853,7 @@ ctqr_status solve_impl(int64_t m64, int64_t n64, const T *QR, int64_t lda, const
 {
     (void)tau;
     SolveRun<T> r = make_run<T>(m64, n64, QR, lda, Tf, Rinv_in, nb, B, ldb, S, A64, tol, max_iters, work, info,
-                                true, method, true);
+                                true, method, TRSM_PARTS_ALL);
     ctqr_status s = solve_start(r, st);
     if (s) return s;
     if (r.refine() && (s = refine_iters(r, 0, max_iters, true, st, nullptr))) return s;
@@ -1011,6 +1024,8 @@ struct ctqr_solver_t {
     double *Bpad = nullptr;     // m x smax request buffer the graphs read
     ctqr_info *info = nullptr;  // device info the graphs write
     void *swork = nullptr;      // solve workspace of the largest bucket
+    __bf16 *rparts = nullptr;   // R's split-BF16 parts (wide refined buckets), made once
+    bool rparts_ready = false;
     hipStream_t cap = nullptr;  // capture stream (never executes work)
     std::vector<SolverBucket> buckets;
     std::mutex mu;
@@ -1021,6 +1036,7 @@ namespace {
 struct SolverLayout {
     ctqr_info *info;
     double *Bpad;
+    __bf16 *rparts;   // R's split-BF16 parts for the wide refined buckets, or null
     void *swork;
     size_t bytes;
 };
@@ -1031,10 +1047,13 @@ SolverLayout solver_layout(const ctqr_solver_desc *d, void *work, int smax, int6
     SolverLayout L{};
     L.info = c.take<ctqr_info>(1);
     L.Bpad = c.take<double>(ldbp * smax);
-    L.swork = c.take<char>(0);
     const int refine = d->A64 != nullptr && d->max_iters > 0 ? (d->refine_method == CTQR_REFINE_PCG ? 2 : 1) : 0;
-    size_t sb = d->dtype == CTQR_F64 ? carve_solve<double>(nullptr, d->m, d->n, d->nb, smax, refine, false, true).bytes
-                                     : carve_solve<float>(nullptr, d->m, d->n, d->nb, smax, refine, false, true).bytes;
+    const bool parts = d->dtype == CTQR_F32 && refine_split_trsm<float>(smax, refine);
+    L.rparts = parts ? c.take<__bf16>((int64_t)trsm_rparts_elems(d->n)) : nullptr;
+    L.swork = c.take<char>(0);
+    size_t sb = d->dtype == CTQR_F64
+                    ? carve_solve<double>(nullptr, d->m, d->n, d->nb, smax, refine, false, TRSM_PARTS_X).bytes
+                    : carve_solve<float>(nullptr, d->m, d->n, d->nb, smax, refine, false, TRSM_PARTS_X).bytes;
     L.bytes = c.off + sb + 256;
     return L;
 }
@@ -1045,8 +1064,11 @@ SolveRun<T> solver_run(ctqr_solver_t *sv, const SolverBucket &bk)
     const ctqr_solver_desc &d = sv->d;
     SolveRun<T> r = make_run<T>(d.m, d.n, (const T *)d.QR, d.lda, (const T *)d.T, (const T *)d.Rinv, d.nb,
                                 sv->Bpad, sv->ldbp, bk.S, sv->refine ? &sv->sp : nullptr, d.tol,
-                                sv->refine ? d.max_iters : 0, sv->swork, sv->info, false, d.refine_method, true);
+                                sv->refine ? d.max_iters : 0, sv->swork, sv->info, false, d.refine_method,
+                                TRSM_PARTS_X);
     r.narrow = bk.narrow;
+    r.tp.r = sv->rparts;     // split once for the solver (solver_solve_t)
+    if (!r.tp.r) r.tp.x = nullptr;
     return r;
 }
 
@@ -1108,6 +1130,14 @@ ctqr_status solver_solve_t(ctqr_solver_t *sv, int nreq, const double *const *B, 
         (s = fill_f64(sv->Bpad + (int64_t)total * sv->ldbp, (int64_t)(bk.S - total) * sv->ldbp, 0.0, st)))
         return s;
     SolveRun<T> r = solver_run<T>(sv, bk);
+    if constexpr (sizeof(T) == 4) {
+        // R's parts for the wide substitutions, once for the solver's life
+        // (before any graph that reads them is captured or replayed)
+        if (r.parts() && !sv->rparts_ready) {
+            if ((s = trsm_split_r(r.n, r.QR, r.lda, sv->rparts, st))) return s;
+            sv->rparts_ready = true;
+        }
+    }
     if (sv->refine && bk.iters < 0) {
         // calibration: an eager, host-synchronised run that counts the
         // refinement iterations the graph will hold
@@ -1453,8 +1483,8 @@ ctqr_status ctqr_solve_workspace(int64_t m, int64_t n, ctqr_dtype dtype, int32_t
     nb = resolve_nb(nb);
     if (!nb_ok(nb)) return CTQR_EINVAL;
     if (refine < 0 || refine > 2) return CTQR_EINVAL;
-    *bytes = dtype == CTQR_F64 ? carve_solve<double>(nullptr, m, n, nb, nslices, refine, true, true).bytes
-                               : carve_solve<float>(nullptr, m, n, nb, nslices, refine, true, true).bytes;
+    *bytes = dtype == CTQR_F64 ? carve_solve<double>(nullptr, m, n, nb, nslices, refine, true, TRSM_PARTS_ALL).bytes
+                               : carve_solve<float>(nullptr, m, n, nb, nslices, refine, true, TRSM_PARTS_ALL).bytes;
     return CTQR_OK;
 }
 
@@ -1545,6 +1575,7 @@ ctqr_status ctqr_solver_create(const ctqr_solver_desc *desc, void *work, size_t 
         SolverLayout L = solver_layout(&sv->d, work, sv->smax, sv->ldbp);
         sv->info = L.info;
         sv->Bpad = L.Bpad;
+        sv->rparts = L.rparts;
         sv->swork = L.swork;
         for (int b : bucket_sizes(sv->smax)) {
             SolverBucket bk;

@@ -1286,6 +1286,38 @@ ctqr_status gemm_tn_bf16x3(int M, int N, int K, const __bf16 *vt, size_t vt_elem
     return CTQR_OK;
 }
 
+ctqr_status bf16x3_split_rows(int M, int K, const float *V, int64_t lda, bool householder, __bf16 *hi, __bf16 *lo,
+                              int ldp, int rows_pad, hipStream_t st, const int *skip)
+{
+    if (M <= 0 || K <= 0) return CTQR_OK;
+    if (ldp < K || ldp % 8 != 0 || rows_pad < M || rows_pad % TILE != 0) return CTQR_EINVAL;
+    LAUNCH_TRY(split_v_kernel, dim3((unsigned)ceil_div(rows_pad, 256), (unsigned)(ldp / 8)), dim3(256), 0, st, M, K,
+               V, lda, rows_pad, ldp, hi, lo, householder ? 1 : 0, skip);
+    return CTQR_OK;
+}
+
+ctqr_status bf16x3_split_cols(int K, int N, const float *W, int64_t ldw, __bf16 *hi, __bf16 *lo, int ldp,
+                              int cols_pad, hipStream_t st, const int *skip)
+{
+    if (N <= 0 || K <= 0) return CTQR_OK;
+    if (ldp < K || ldp % 8 != 0 || cols_pad < N || cols_pad % TILE != 0) return CTQR_EINVAL;
+    LAUNCH_TRY(split_w_kernel, dim3((unsigned)ceil_div((int64_t)cols_pad * (ldp / 8), 256)), dim3(256), 0, st, K, N,
+               W, ldw, cols_pad, ldp, hi, lo, skip);
+    return CTQR_OK;
+}
+
+ctqr_status gemm_nn_bf16x3_parts(int M, int N, int K, float alpha, float *C, int64_t ldc, const __bf16 *ah,
+                                 const __bf16 *al, int64_t lda_p, const __bf16 *bh, const __bf16 *bl, int64_t ldb_p,
+                                 hipStream_t st, const int *skip)
+{
+    if (M <= 0 || N <= 0 || K <= 0) return CTQR_OK;
+    if (lda_p < up_to(K, 32) || ldb_p < up_to(K, 32)) return CTQR_EINVAL;
+    dim3 grid((unsigned)(ceil_div(M, TILE) * ceil_div(N, TILE)));
+    LAUNCH_TRY(gemm_nn_bf16x3_kernel, grid, dim3(NTHR), 0, st, M, N, K, ah, al, lda_p, bh, bl, ldb_p, alpha, C, ldc,
+               skip);
+    return CTQR_OK;
+}
+
 ctqr_status gemm_nn_bf16x3(int M, int N, int K, float alpha, float *C, int64_t ldc, const __bf16 *split,
                            size_t split_elems, hipStream_t st, const int *skip)
 {

@@ -42,6 +42,18 @@ ctqr_status bf16x3_split(int M, int N, int K, const float *V, int64_t lda, const
                          const int *skip = nullptr);
 ctqr_status gemm_nn_bf16x3(int M, int N, int K, float alpha, float *C, int64_t ldc, const __bf16 *split,
                            size_t split_elems, hipStream_t st, const int *skip = nullptr);
+// The same pieces with caller-placed parts: an M x K operand to row-major
+// parts (row stride ldp, rows up to rows_pad, a multiple of 128, zero), a
+// K x N operand to column-major parts (column stride ldp, columns up to
+// cols_pad, a multiple of 128, zero), both zero for k in [K, ldp); and the
+// product C += alpha A B from such parts.
+ctqr_status bf16x3_split_rows(int M, int K, const float *V, int64_t lda, bool householder, __bf16 *hi, __bf16 *lo,
+                              int ldp, int rows_pad, hipStream_t st, const int *skip = nullptr);
+ctqr_status bf16x3_split_cols(int K, int N, const float *W, int64_t ldw, __bf16 *hi, __bf16 *lo, int ldp,
+                              int cols_pad, hipStream_t st, const int *skip = nullptr);
+ctqr_status gemm_nn_bf16x3_parts(int M, int N, int K, float alpha, float *C, int64_t ldc, const __bf16 *ah,
+                                 const __bf16 *al, int64_t lda_p, const __bf16 *bh, const __bf16 *bl, int64_t ldb_p,
+                                 hipStream_t st, const int *skip = nullptr);
 
 // Split-BF16 reduction Out = alpha V^T B + beta Out (V: K x M Householder
 // block, M <= 256): bf16x3_split_vt writes V's high and low bf16 parts once to
@@ -81,18 +93,27 @@ ctqr_status trinv_blocks(int n, const T *R, int64_t ldr, T *Rinv, T *tmp, ctqr_i
 template <typename T>
 ctqr_status trinv_blocks_range(int n, int c0, int c1, const T *R, int64_t ldr, T *Rinv, T *tmp,
                                hipStream_t st);
-// bsplit: trsm_bf16x3_elems(n, S) bf16 elements, or null.  Given (FP32 R and
-// at least 128 slices), the off-diagonal block products of the wide
-// (right-looking) substitution run on split-BF16 MFMA.
-size_t trsm_bf16x3_elems(int64_t n, int S);
+// Split-BF16 parts for the wide substitutions: r holds R's off-diagonal
+// blocks split once by trsm_split_r (trsm_rparts_elems(n) elements), x the
+// right-hand side's parts of one product (trsm_xparts_elems(S)).  Given
+// (FP32 R, at least TRSM_SPLIT_MIN_SLICES slices), the off-diagonal block
+// products of the right-looking substitutions run on split-BF16 MFMA.
+constexpr int TRSM_SPLIT_MIN_SLICES = 128;
+struct TrsmParts {
+    const __bf16 *r;
+    __bf16 *x;
+};
+size_t trsm_rparts_elems(int64_t n);
+size_t trsm_xparts_elems(int S);
+ctqr_status trsm_split_r(int n, const float *R, int64_t ldr, __bf16 *parts, hipStream_t st);
 template <typename T>
 ctqr_status trsm_upper(int n, int S, const T *R, int64_t ldr, const T *Rinv, T *C, int64_t ldc,
                        T *X, int64_t ldx, T *part, size_t part_elems, const int *skip, hipStream_t st,
-                       __bf16 *bsplit = nullptr, size_t bsplit_elems = 0);
+                       const TrsmParts *rp = nullptr);
 template <typename T>
 ctqr_status trsm_upper_trans(int n, int S, const T *R, int64_t ldr, const T *Rinv, T *C, int64_t ldc,
                              T *Y, int64_t ldy, T *part, size_t part_elems, const int *skip,
-                             hipStream_t st, __bf16 *bsplit = nullptr, size_t bsplit_elems = 0);
+                             hipStream_t st, const TrsmParts *rp = nullptr);
 // out[k] = A(k, k) for k in [c0, c1)
 template <typename T>
 ctqr_status diag_copy(int c0, int c1, const T *A, int64_t lda, T *out, hipStream_t st);

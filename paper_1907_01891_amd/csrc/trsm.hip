@@ -278,24 +278,63 @@ ctqr_status rdiag_check(int n, const T *R, int64_t ldr, double *scratch, ctqr_in
 //    long inner dimension, split over it, so every step fills the chip).
 // Narrow right-hand sides (the 32-wide slice tile) use the left-looking order.
 // Split-BF16 products for the off-diagonal blocks of a wide substitution
-// (FP32 factor, at least one 128-wide slice tile, `bsplit` given): the
-// refinement applies (R^T R)^-1 only as a preconditioner, which needs the
+// (FP32 factor, at least one 128-wide slice tile, parts of R given): the
+// refinement applies (R^T R)^-1 only to contract its error, which needs the
 // accuracy of the factor itself (about 16 bits for a split-BF16 factor), not
 // FP32's.  The diagonal-block products with the stored inverses stay FP32.
-constexpr int BF16X3_MIN_SLICES = 128;
-
-size_t trsm_bf16x3_elems(int64_t n, int S)
+// R's off-diagonal blocks are split once (trsm_split_r) into the two layouts
+// the products read:
+//   nn: block column R_{0:r0, i} (i >= 1) as row-major high / low parts,
+//       row stride BIG, at nn_off(i); the high part's r0 rows, then the low's.
+//   tn: block row R_{i, i+1:} (i before the last) as column-major parts,
+//       column stride BIG, columns padded to 128, at tn_off(i).
+// The right-hand side X_i (Y_i) of each product is split per call into x.
+namespace {
+int64_t up128(int64_t v) { return ceil_div(v, 128) * 128; }
+int64_t nn_off(int i) { return (int64_t)BIG * BIG * i * (i - 1); }
+int64_t tn_off(int n, int i)
 {
-    const int64_t np = ceil_div(n, 128) * 128, sp = ceil_div(S, 128) * 128;
-    return (size_t)(2 * np * BIG + 2 * sp * BIG);
+    int64_t off = 0;
+    for (int j = 0; j < i; ++j) off += 2LL * BIG * up128(n - (int64_t)(j + 1) * BIG);
+    return off;
+}
+}  // namespace
+
+size_t trsm_rparts_elems(int64_t n)
+{
+    const int nblk = (int)ceil_div(n, BIG);
+    return (size_t)(nn_off(nblk) + tn_off((int)n, std::max(0, nblk - 1)));
+}
+
+size_t trsm_xparts_elems(int S) { return (size_t)(2 * up128(S) * BIG); }
+
+ctqr_status trsm_split_r(int n, const float *R, int64_t ldr, __bf16 *parts, hipStream_t st)
+{
+    const int nblk = (int)ceil_div(n, BIG);
+    __bf16 *nn = parts, *tn = parts + nn_off(nblk);
+    ctqr_status s;
+    for (int i = 1; i < nblk; ++i) {
+        const int r0 = i * BIG, bw = std::min(BIG, n - r0);
+        __bf16 *hi = nn + nn_off(i);
+        if ((s = bf16x3_split_rows(r0, bw, R + (int64_t)r0 * ldr, ldr, false, hi, hi + (int64_t)r0 * BIG, BIG, r0,
+                                   st)))
+            return s;
+    }
+    for (int i = 0; i + 1 < nblk; ++i) {
+        const int r0 = i * BIG, rest = n - r0 - BIG;
+        if ((s = bf16x3_split_vt(BIG, rest, R + (int64_t)(r0 + BIG) * ldr + r0, ldr, tn + tn_off(n, i),
+                                 2 * (size_t)BIG * up128(rest), st, false)))
+            return s;
+    }
+    return CTQR_OK;
 }
 
 template <typename T>
 ctqr_status trsm_upper(int n, int S, const T *R, int64_t ldr, const T *Rinv, T *C, int64_t ldc,
                        T *X, int64_t ldx, T *part, size_t part_elems, const int *skip, hipStream_t st,
-                       __bf16 *bsplit, size_t bsplit_elems)
+                       const TrsmParts *rp)
 {
-    const bool bf = sizeof(T) == 4 && bsplit && S >= BF16X3_MIN_SLICES;
+    const bool bf = sizeof(T) == 4 && rp && S >= TRSM_SPLIT_MIN_SLICES;
     const T *RinvT = Rinv + trinv_elems(n);
     const int nblk = (int)ceil_div(n, BIG);
     const bool left = S <= gemm_narrow_max();
@@ -316,9 +355,11 @@ ctqr_status trsm_upper(int n, int S, const T *R, int64_t ldr, const T *Rinv, T *
             // C_{0:r0} -= R_{0:r0, i} X_i
             if constexpr (sizeof(T) == 4) {
                 if (bf) {
-                    s = bf16x3_split(r0, S, bw, R + (int64_t)r0 * ldr, ldr, X + r0, ldx, bsplit, bsplit_elems, st,
-                                     false, skip);
-                    if (!s) s = gemm_nn_bf16x3(r0, S, bw, -1.0f, C, ldc, bsplit, bsplit_elems, st, skip);
+                    const __bf16 *ah = rp->r + nn_off(i), *al = ah + (int64_t)r0 * BIG;
+                    const int cp = (int)up128(S);
+                    __bf16 *xh = rp->x, *xl = rp->x + (int64_t)cp * BIG;
+                    s = bf16x3_split_cols(bw, S, X + r0, ldx, xh, xl, BIG, cp, st, skip);
+                    if (!s) s = gemm_nn_bf16x3_parts(r0, S, bw, -1.0f, C, ldc, ah, al, BIG, xh, xl, BIG, st, skip);
                     if (s) return s;
                     continue;
                 }
@@ -336,9 +377,9 @@ ctqr_status trsm_upper(int n, int S, const T *R, int64_t ldr, const T *Rinv, T *
 template <typename T>
 ctqr_status trsm_upper_trans(int n, int S, const T *R, int64_t ldr, const T *Rinv, T *C, int64_t ldc,
                              T *Y, int64_t ldy, T *part, size_t part_elems, const int *skip,
-                             hipStream_t st, __bf16 *bsplit, size_t bsplit_elems)
+                             hipStream_t st, const TrsmParts *rp)
 {
-    const bool bf = sizeof(T) == 4 && bsplit && S >= BF16X3_MIN_SLICES;
+    const bool bf = sizeof(T) == 4 && rp && S >= TRSM_SPLIT_MIN_SLICES;
     const int nblk = (int)ceil_div(n, BIG);
     const bool left = S <= gemm_narrow_max();
     for (int i = 0; i < nblk; ++i) {
@@ -359,11 +400,10 @@ ctqr_status trsm_upper_trans(int n, int S, const T *R, int64_t ldr, const T *Rin
             // C_{i+1:} -= (R_{i, i+1:})^T Y_i
             if constexpr (sizeof(T) == 4) {
                 if (bf) {
-                    s = bf16x3_split_vt(bw, rest, R + (int64_t)(r0 + bw) * ldr + r0, ldr, bsplit, bsplit_elems, st,
-                                        false, skip);
-                    if (!s)
-                        s = gemm_tn_bf16x3(rest, S, bw, bsplit, bsplit_elems, Y + r0, ldy, 0, -1.0f, 1.0f,
-                                           C + r0 + bw, ldc, part, part_elems, skip, st, 0);
+                    const int nblk = (int)ceil_div(n, BIG);
+                    const __bf16 *vt = rp->r + nn_off(nblk) + tn_off(n, i);
+                    s = gemm_tn_bf16x3(rest, S, bw, vt, 2 * (size_t)BIG * up128(rest), Y + r0, ldy, 0, -1.0f, 1.0f,
+                                       C + r0 + bw, ldc, part, part_elems, skip, st, 0);
                     if (s) return s;
                     continue;
                 }
@@ -428,10 +468,10 @@ ctqr_status trsm_upper_trans_cols(int n, int S, const T *R, int64_t ldr, const T
     template ctqr_status rdiag_check<T>(int, const T *, int64_t, double *, ctqr_info *, hipStream_t);   \
     template ctqr_status diag_copy<T>(int, int, const T *, int64_t, T *, hipStream_t);                  \
     template ctqr_status trsm_upper<T>(int, int, const T *, int64_t, const T *, T *, int64_t, T *,       \
-                                       int64_t, T *, size_t, const int *, hipStream_t, __bf16 *, size_t); \
+                                       int64_t, T *, size_t, const int *, hipStream_t, const TrsmParts *); \
     template ctqr_status trsm_upper_trans<T>(int, int, const T *, int64_t, const T *, T *, int64_t,     \
                                              T *, int64_t, T *, size_t, const int *, hipStream_t,       \
-                                             __bf16 *, size_t);                                          \
+                                             const TrsmParts *);                                         \
     template ctqr_status trsm_upper_cols<T>(int, int, const T *, int64_t, const T *, T *, int64_t, T *,  \
                                             int64_t, int, int, T *, size_t, const int *, hipStream_t);  \
     template ctqr_status trsm_upper_trans_cols<T>(int, int, const T *, int64_t, const T *, T *, int64_t, \
