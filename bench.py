@@ -84,7 +84,7 @@ TRAFFIC_FILES = {"fp32": os.path.join(ROOT, "profiles", "gemm_nn_trailing_update
                  "bf16x3": os.path.join(ROOT, "profiles", "gemm_nn_bf16x3_trailing_update_ct256_traffic.txt")}
 # the trailing-update kernel of each mode, as rocprofv3 names it
 TRAILING_KERNEL = {"fp32": "gemm_nn_kernel<float, 1, 128, false, 0>",
-                   "bf16x3": "gemm_nn_bf16x3_kernel"}
+                   "bf16x3": "gemm_nn_bf16x3_kernel<1>"}
 
 
 def gemm_source_hash():

@@ -816,10 +816,13 @@ void split_w_kernel(int kc, int cols, const float *__restrict__ W, int64_t ldw_i
 }
 
 // C += alpha V W' from the split parts: 128 x 128 output tiles, three BF16
-// products per operand pair (as in the BF = 2 kernels), FP32 accumulation, C
-// prefetched at the start as in the FP32 trailing update.  Ah/Al: rows padded
-// to whole tiles, row stride lda; Bh/Bl: columns padded to whole tiles,
-// column stride ldb; both cover k up to K rounded up to a stage.
+// products per operand pair (mfma_step_bf2), FP32 accumulation, C prefetched
+// at the start as in the FP32 trailing update.  Ah/Al: rows padded to whole
+// tiles, row stride lda; Bh/Bl: columns padded to whole tiles, column stride
+// ldb; both cover k up to K rounded up to a stage.  KIND only separates the
+// launch sites in a profile: 1 is the factorization's trailing update, 0 the
+// substitutions.
+template <int KIND>
 __global__ __launch_bounds__(NTHR, 2)
 void gemm_nn_bf16x3_kernel(int M, int N, int K, const __bf16 *__restrict__ Ah, const __bf16 *__restrict__ Al,
                            int64_t lda, const __bf16 *__restrict__ Bh, const __bf16 *__restrict__ Bl,
@@ -1313,8 +1316,8 @@ ctqr_status gemm_nn_bf16x3_parts(int M, int N, int K, float alpha, float *C, int
     if (M <= 0 || N <= 0 || K <= 0) return CTQR_OK;
     if (lda_p < up_to(K, 32) || ldb_p < up_to(K, 32)) return CTQR_EINVAL;
     dim3 grid((unsigned)(ceil_div(M, TILE) * ceil_div(N, TILE)));
-    LAUNCH_TRY(gemm_nn_bf16x3_kernel, grid, dim3(NTHR), 0, st, M, N, K, ah, al, lda_p, bh, bl, ldb_p, alpha, C, ldc,
-               skip);
+    LAUNCH_TRY(gemm_nn_bf16x3_kernel<0>, grid, dim3(NTHR), 0, st, M, N, K, ah, al, lda_p, bh, bl, ldb_p, alpha, C,
+               ldc, skip);
     return CTQR_OK;
 }
 
@@ -1325,7 +1328,7 @@ ctqr_status gemm_nn_bf16x3(int M, int N, int K, float alpha, float *C, int64_t l
     SplitParts p;
     if (!split_parts(M, N, K, const_cast<__bf16 *>(split), split_elems, p)) return CTQR_ENOMEM;
     dim3 grid((unsigned)(ceil_div(M, TILE) * ceil_div(N, TILE)));
-    LAUNCH_TRY(gemm_nn_bf16x3_kernel, grid, dim3(NTHR), 0, st, M, N, K, (const __bf16 *)p.vh, (const __bf16 *)p.vl,
+    LAUNCH_TRY(gemm_nn_bf16x3_kernel<1>, grid, dim3(NTHR), 0, st, M, N, K, (const __bf16 *)p.vh, (const __bf16 *)p.vl,
                (int64_t)p.kp, (const __bf16 *)p.wh, (const __bf16 *)p.wl, (int64_t)p.kp, alpha, C, ldc, skip);
     return CTQR_OK;
 }
