@@ -6,6 +6,7 @@ an independent brute-force clipping derivation of A, and exact chord
 lengths of rays through the image square.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -17,17 +18,38 @@ from oracle.siddon import system_matrix_csr, siddon_ray
 from oracle.clip import system_matrix_bruteforce, image_chord_lengths, chord_length
 
 
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "table1_scanner.txt")
+
+
+def _golden():
+    kv = {}
+    for line in open(GOLDEN):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            k, v = (t.strip() for t in line.split("=", 1))
+            kv[k] = float(v)
+    return kv
+
+
 def test_paper_sizes():
-    # Section III-B: 1025 detectors x 260 views = 266,500 rays, 512^2 pixels;
-    # the dense FP64 A is "about 560 GB".
-    g = get_workload("paper512").geometry()
+    # Section III-B: detectors x projections rays, 512^2 pixels; the dense
+    # FP64 A is about 560 GB (values as the paper prints them, golden file)
+    t = _golden()
+    w = get_workload("paper512")
+    g = w.geometry()
     m, n = sizes(g)
-    assert (m, n) == (266500, 262144)
-    assert abs(m * n * 8 / 1e9 - 558.9) < 0.1
+    assert (w.n_bins, w.n_views, w.side) == (t["detectors"], t["projections"], t["image_side"])
+    assert (m, n) == (t["A_rows"], t["A_cols"])
+    assert abs(m * n * 8 / 1e9 - t["A_fp64_storage_gb_about"]) < 2.0
 
 
 def test_table1_scanner():
-    assert SCANNER == {"src_iso_cm": 75.0, "src_det_cm": 150.0, "fan_deg": 30.0}
+    t = _golden()
+    assert SCANNER == {"src_iso_cm": t["scan_radius_cm"], "src_det_cm": t["source_to_detector_cm"],
+                       "fan_deg": t["fan_angle_deg"]}
+    # a full turn: the uniform schedule spans 360 degrees in equal steps
+    th = projection_angles_deg(int(t["projections"]), schedule=0)
+    assert abs(th[1] - th[0] - t["trajectory_deg"] / t["projections"]) < 1e-12
     # image square circumscribing the circle R sin(15 deg) every fan covers
     L = image_side_cm()
     assert abs(L / 2 - 75.0 * math.sin(math.radians(15.0))) < 1e-12
