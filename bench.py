@@ -392,7 +392,15 @@ def main():
     w = get_workload(args.workload)
     log = lambda *a: print("[bench]", *a, file=sys.stderr, flush=True)
     free, _ = torch.cuda.mem_get_info()
-    if args.ooc or w.m * w.n * 4 > free:
+    # out of core unless the dense FP32 A, its factorization and the refined
+    # solve of all slices (workspaces as the library reports them) fit in HBM
+    from paper_1907_01891_amd.device import round_up
+    nb_q, refine_q = args.nb or 256, REFINE[args.refine] + 1
+    need = (round_up(w.m, 64) * w.n * 4 + nb_q * w.n * 4 + C.ctqr_qr_rinv_bytes(w.n, C.CTQR_F32)
+            + C.ctqr_qr_workspace(w.m, w.n, C.CTQR_F32, prec_codes(C)[args.prec], nb_q)
+            + C.ctqr_solve_workspace(w.m, w.n, C.CTQR_F32, nb_q, w.n_slices, refine_q)
+            + 24 * w.m * (2 * w.side - 1) + 4 * 8 * w.m * w.n_slices)   # sparse copies, B / X
+    if args.ooc or need > 0.95 * free:
         print(json.dumps(ooc_bench(args, log)))
         return
     g = w.geometry()

@@ -140,14 +140,22 @@ struct SolveWS {
 };
 
 // The wide substitutions of the corrected semi-normal-equations refinement
-// take split-BF16 products (all-in-HBM FP32 factor, at least 128 slices):
+// take split-BF16 products (all-in-HBM FP32 factor, at least 128 slices, R's
+// parts within TRSM_SPLIT_MAX_BYTES):
 // each correction only has to contract the error, which an inexact
 // (R^T R)^-1 does.  The conjugate-gradient form (refine 2) keeps FP32
 // products: it needs the preconditioner to be the same symmetric operator
 // in every iteration, and the split products' rounding erodes conjugacy
 // before its tolerance is met.
+// R's parts take about 4 n^2 bytes (both layouts), so they are used up to a
+// fixed size: 32 GiB, n up to about 92,000 (16.6 GB at 256^2).
+constexpr size_t TRSM_SPLIT_MAX_BYTES = (size_t)32 << 30;
 template <typename T>
-bool refine_split_trsm(int S, int refine) { return sizeof(T) == 4 && refine == 1 && S >= 128; }
+bool refine_split_trsm(int64_t n, int S, int refine)
+{
+    return sizeof(T) == 4 && refine == 1 && S >= TRSM_SPLIT_MIN_SLICES &&
+           trsm_rparts_elems(n) * sizeof(__bf16) <= TRSM_SPLIT_MAX_BYTES;
+}
 
 // refine: 0 none, 1 semi-normal-equations corrections, 2 also the
 // conjugate-gradient vectors; trsm_split: room for those split products
@@ -184,7 +192,7 @@ SolveWS<T> carve_solve(void *work, int64_t m, int64_t n, int nb, int S, int refi
         w.dmax = c.take<unsigned long long>(S);
         w.xmax = c.take<unsigned long long>(S);
         w.hist = c.take<double>(8);
-        const bool parts = trsm_split != TRSM_PARTS_NONE && refine_split_trsm<T>(S, refine);
+        const bool parts = trsm_split != TRSM_PARTS_NONE && refine_split_trsm<T>(n, S, refine);
         w.xparts = parts ? c.take<__bf16>((int64_t)trsm_xparts_elems(S)) : nullptr;
         w.rparts = parts && trsm_split == TRSM_PARTS_ALL ? c.take<__bf16>((int64_t)trsm_rparts_elems(n)) : nullptr;
     }
@@ -1048,7 +1056,7 @@ SolverLayout solver_layout(const ctqr_solver_desc *d, void *work, int smax, int6
     L.info = c.take<ctqr_info>(1);
     L.Bpad = c.take<double>(ldbp * smax);
     const int refine = d->A64 != nullptr && d->max_iters > 0 ? (d->refine_method == CTQR_REFINE_PCG ? 2 : 1) : 0;
-    const bool parts = d->dtype == CTQR_F32 && refine_split_trsm<float>(smax, refine);
+    const bool parts = d->dtype == CTQR_F32 && refine_split_trsm<float>(d->n, smax, refine);
     L.rparts = parts ? c.take<__bf16>((int64_t)trsm_rparts_elems(d->n)) : nullptr;
     L.swork = c.take<char>(0);
     size_t sb = d->dtype == CTQR_F64
