@@ -87,6 +87,23 @@ TRAILING_KERNEL = {"fp32": "gemm_nn_kernel<float, 1, 128, false, 0>",
                    "bf16x3": "gemm_nn_bf16x3_kernel<1>"}
 
 
+def trailing_launches(m, n, nb):
+    """(rows, columns, inner dimension) of every trailing-update launch of the
+    factorization.  With nb dividing 1024, block columns (2j, 2j+1) are
+    paired: the first block's reflector updates only its partner, and the
+    pair's 2nb-wide block reflector updates the rest in one launch."""
+    out, k0 = [], 0
+    paired = 1024 % nb == 0
+    while k0 < n:
+        w = min(nb, n - k0)
+        if paired and k0 + nb < n:
+            w = nb + min(nb, n - k0 - nb)
+        if n - k0 - w > 0:
+            out.append((m - k0, n - k0 - w, w))
+        k0 += w
+    return out
+
+
 def gemm_source_hash():
     import hashlib
     with open(os.path.join(ROOT, "paper_1907_01891_amd", "csrc", "gemm.hip"), "rb") as f:
@@ -578,15 +595,10 @@ def main():
 
     achieved = kern_flops / (kern_ms * 1e-3) / 1e12 if kern_ms > 0 else None
     # algorithmic HBM bytes of one trailing update C -= V W' (FP32): read and
-    # write C (m_k x n_k), read V (m_k x nb) and W' (nb x n_k) once
-    alg, nl = 0.0, 0
-    for k0 in range(0, n, args.nb):
-        nbk = min(args.nb, n - k0)
-        nc = n - k0 - nbk
-        if nc > 0:
-            alg += 8.0 * (m - k0) * nc + 4.0 * nbk * ((m - k0) + nc)
-            nl += 1
-    alg_bytes = alg / nl if nl else None
+    # write C (m_k x n_k), read V (m_k x K) and W' (K x n_k) once
+    launches_k = trailing_launches(m, n, args.nb)
+    alg = sum(8.0 * mk * nc + 4.0 * kk * (mk + nc) for mk, nc, kk in launches_k)
+    alg_bytes = alg / len(launches_k) if launches_k else None
     avg_ms = kern_ms / launches if launches else None
     if args.prec == "fp32":
         roof = {"bound": "mfma", "kernel": TRAILING_KERNEL["fp32"] + " (trailing update C -= V W', FP32 MFMA)",

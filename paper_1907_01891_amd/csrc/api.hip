@@ -87,11 +87,23 @@ struct Carve {
     }
 };
 
+// Consecutive block columns (2j, 2j+1) are paired: the first block's
+// reflector updates only its partner, and the two compact-WY reflectors then
+// act on the rest of the matrix as one 2nb-wide block reflector (Schreiber and
+// Van Loan, the product form of Householder blocks), so the trailing update
+// sweeps the remaining columns once per pair instead of once per block, with
+// an inner dimension of 2nb.  Only for nb dividing 1024: every range boundary
+// of the out-of-core factorization (a multiple of 2048, or n) then falls
+// between pairs.
+bool paired(int nb) { return 1024 % nb == 0; }
+int gw_rows(int nb) { return paired(nb) ? 2 * nb : nb; }   // rows of [G | W] and W'
+
 template <typename T>
 struct FactorWS {
     unsigned *bars;
     double *part, *part2, *gram_part, *gram, *Tw;
     T *Tin, *GW, *W2, *split, *rtmp;
+    T *g21;                  // per pair: V2^T V1 (nb x nb), for the pair's later applications
     __bf16 *bsplit;          // split-BF16 parts of V and W' (FP32 factor only)
     size_t bsplit_elems;
     __bf16 *vtsplit;         // split-BF16 parts of V, column-major, for [G | W]
@@ -112,13 +124,15 @@ FactorWS<T> carve_factor(void *work, int64_t m, int64_t n, int nb)
     w.gram = c.take<double>(PANEL_W * PANEL_W);
     w.Tw = c.take<double>((int64_t)nb * nb);
     w.Tin = c.take<T>(PANEL_W * PANEL_W);
-    w.GW = c.take<T>((int64_t)nb * n);
-    w.W2 = c.take<T>((int64_t)nb * n);
+    const int g = gw_rows(nb);
+    w.GW = c.take<T>((int64_t)g * n);
+    w.W2 = c.take<T>((int64_t)g * n);
+    w.g21 = c.take<T>(paired(nb) ? ceil_div(n, 2 * nb) * nb * nb : 0);
     w.split = c.take<T>(SPLIT_PART_ELEMS);
     w.rtmp = c.take<T>((int64_t)trinv_tmp_elems());
-    w.bsplit_elems = sizeof(T) == 4 ? bf16x3_split_elems(m, n, nb) : 0;
+    w.bsplit_elems = sizeof(T) == 4 ? bf16x3_split_elems(m, n, g) : 0;
     w.bsplit = c.take<__bf16>((int64_t)w.bsplit_elems);
-    w.vtsplit_elems = sizeof(T) == 4 ? bf16x3_vt_elems(m, nb) : 0;
+    w.vtsplit_elems = sizeof(T) == 4 ? bf16x3_vt_elems(m, g) : 0;
     w.vtsplit = c.take<__bf16>((int64_t)w.vtsplit_elems);
     w.bytes = c.off + 256;
     return w;
@@ -243,9 +257,13 @@ ctqr_status ensure_setup()
 }
 
 // Profiled launch of the trailing update C -= V W' (the dominant kernel).
+// C -= V W' (V: mk x nbk Householder block, W': nbk x nc, column stride nb).
+// partner: the update of a pair's second block column by the first block,
+// launched as its own kernel instance (FP32 MFMA in the one-part BF16 mode)
+// and left out of the profile records, which hold the trailing updates only.
 template <typename T>
 ctqr_status trailing_update(int mk, int nc, int nbk, const T *V, int64_t lda, const T *W2, int nb, T *C,
-                            hipStream_t st, int bf16, __bf16 *bsplit, size_t bsplit_elems)
+                            hipStream_t st, int bf16, __bf16 *bsplit, size_t bsplit_elems, bool partner = false)
 {
     if constexpr (sizeof(T) == 4) {
         // split-BF16: both operands split once, outside the timed product
@@ -254,8 +272,8 @@ ctqr_status trailing_update(int mk, int nc, int nbk, const T *V, int64_t lda, co
             if (s) return s;
         }
     }
-    bool prof;
-    {
+    bool prof = false;
+    if (!partner) {
         std::lock_guard<std::mutex> lk(g_prof_mu);
         prof = g_prof_on;
     }
@@ -268,13 +286,13 @@ ctqr_status trailing_update(int mk, int nc, int nbk, const T *V, int64_t lda, co
     ctqr_status s;
     if constexpr (sizeof(T) == 4) {
         if (bf16 == 2)
-            s = gemm_nn_bf16x3(mk, nc, nbk, -1.0f, C, lda, bsplit, bsplit_elems, st);
+            s = gemm_nn_bf16x3(mk, nc, nbk, -1.0f, C, lda, bsplit, bsplit_elems, st, nullptr, partner ? 2 : 1);
         else
-            s = gemm_nn<T>(mk, nc, nbk, V, lda, 1, W2, nb, T(-1), C, lda, nullptr, st, 1, 1, bf16);
+            s = gemm_nn<T>(mk, nc, nbk, V, lda, 1, W2, nb, T(-1), C, lda, nullptr, st, partner ? 0 : 1, 1, bf16);
     } else {
         (void)bsplit;
         (void)bsplit_elems;
-        s = gemm_nn<T>(mk, nc, nbk, V, lda, 1, W2, nb, T(-1), C, lda, nullptr, st, 1, 1, 0);
+        s = gemm_nn<T>(mk, nc, nbk, V, lda, 1, W2, nb, T(-1), C, lda, nullptr, st, partner ? 0 : 1, 1, 0);
     }
     if (s) return s;
     if (prof) {
@@ -286,22 +304,22 @@ ctqr_status trailing_update(int mk, int nc, int nbk, const T *V, int64_t lda, co
     return CTQR_OK;
 }
 
-// [G | W] = V^T B of one block column (V: K x M Householder block, the first
-// bmask columns of B too), into w.GW.  Split BF16 splits V once for all the
-// column tiles.
+// [G | W] = V^T B of one block column or pair (V: K x M Householder block,
+// the first bmask columns of B too), into w.GW (column stride ldg).  Split
+// BF16 splits V once for all the column tiles.
 template <typename T>
 ctqr_status block_reduction(int M, int N, int K, const T *V, int64_t lda, const T *B, int64_t ldb, int bmask,
-                            FactorWS<T> &w, int nb, int force_splits, hipStream_t st)
+                            FactorWS<T> &w, int ldg, int force_splits, hipStream_t st)
 {
     if constexpr (sizeof(T) == 4) {
         if (w.bf16 == 2) {
             ctqr_status s = bf16x3_split_vt(K, M, V, lda, w.vtsplit, w.vtsplit_elems, st);
             if (s) return s;
-            return gemm_tn_bf16x3(M, N, K, w.vtsplit, w.vtsplit_elems, B, ldb, bmask, 1.0f, 0.0f, w.GW, nb, w.split,
+            return gemm_tn_bf16x3(M, N, K, w.vtsplit, w.vtsplit_elems, B, ldb, bmask, 1.0f, 0.0f, w.GW, ldg, w.split,
                                   SPLIT_PART_ELEMS, nullptr, st, force_splits);
         }
     }
-    return gemm_tn<T>(M, N, K, V, lda, M, B, ldb, bmask, T(1), T(0), w.GW, nb, w.split, SPLIT_PART_ELEMS, nullptr,
+    return gemm_tn<T>(M, N, K, V, lda, M, B, ldb, bmask, T(1), T(0), w.GW, ldg, w.split, SPLIT_PART_ELEMS, nullptr,
                       st, force_splits, w.bf16);
 }
 
@@ -316,6 +334,39 @@ BlockSplits block_splits(int m, int n, int nb, int k0)
 {
     const int nbk = std::min(nb, n - k0), nc = n - (k0 + nbk);
     return {gemm_tn_splits(nbk, nbk + nc, m - k0), nc > 0 ? gemm_tn_splits(nbk, nc, nbk) : 1};
+}
+
+// The same for the pair whose first block starts at kp (its second block is
+// nb2 wide): [G | W] over both blocks, then Ta^T Wa and Tb^T (Wb - G21 W'a).
+struct PairSplits {
+    int gw, ta, tb;
+};
+PairSplits pair_splits(int m, int n, int nb, int kp)
+{
+    const int nb2 = std::min(nb, n - (kp + nb)), nbp = nb + nb2, nc = n - (kp + nbp);
+    if (nc <= 0) return {gemm_tn_splits(nbp, nbp, m - kp), 1, 1};
+    return {gemm_tn_splits(nbp, nbp + nc, m - kp), gemm_tn_splits(nb, nc, nb), gemm_tn_splits(nb2, nc, nb2)};
+}
+
+// Two-block compact-WY update of nc columns C (rows from kp) by the pair at
+// kp: with T = [Ta, -Ta G12 Tb; 0, Tb] and W = [Wa; Wb] = V^T C (in Wg,
+// column stride ldg), W' = T^T W is W'a = Ta^T Wa and W'b = Tb^T (Wb - G21 W'a)
+// (G21 = V2^T V1 = G12^T), and C -= V W' with the 2nb-wide V.
+template <typename T>
+ctqr_status pair_update(int m, int nb, int kp, int nb2, int nc, const T *Vp, int64_t lda, const T *Tf,
+                        const T *g21, T *Wg, int ldg, T *C, const PairSplits &sp, FactorWS<T> &w, hipStream_t st)
+{
+    ctqr_status s;
+    const T *Ta = Tf + (int64_t)kp * nb, *Tb = Tf + (int64_t)(kp + nb) * nb;
+    s = gemm_tn<T>(nb, nc, nb, Ta, nb, 0, Wg, ldg, 0, T(1), T(0), w.W2, ldg, w.split, SPLIT_PART_ELEMS, nullptr, st,
+                   sp.ta);
+    if (s) return s;
+    s = gemm_nn<T>(nb2, nc, nb, g21, nb, 0, w.W2, ldg, T(-1), Wg + nb, ldg, nullptr, st);
+    if (s) return s;
+    s = gemm_tn<T>(nb2, nc, nb2, Tb, nb, 0, Wg + nb, ldg, 0, T(1), T(0), w.W2 + nb, ldg, w.split, SPLIT_PART_ELEMS,
+                   nullptr, st, sp.tb);
+    if (s) return s;
+    return trailing_update<T>(m - kp, nc, nb + nb2, Vp, lda, w.W2, ldg, C, st, w.bf16, w.bsplit, w.bsplit_elems);
 }
 
 // Right-looking blocked Householder QR of the block columns [kb, ke) of an
@@ -352,12 +403,53 @@ ctqr_status factor_blocks(int m, int n, T *A, int64_t lda, int nb, int kb, int k
             s = gemm_nn<T>(m - c0, ncr, wdt, Vp, lda, 1, w.W2, PANEL_W, T(-1), Cp, lda, nullptr, st);
             if (s) return s;
         }
+        const T *V = A + (int64_t)k0 * lda + k0;
+        T *Tk = Tout + (int64_t)k0 * nb;
+        if (paired(nb) && (k0 / nb) % 2 == 0 && k0 + nb < n) {
+            // first block of a pair: its reflector updates the partner block
+            // column only
+            if (k0 + nb >= ke) return CTQR_EINVAL;   // ranges hold whole pairs
+            const int nb2 = std::min(nb, n - (k0 + nb));
+            s = block_reduction<T>(nbk, nbk + nb2, m - k0, V, lda, V, lda, nbk, w, nb,
+                                   gemm_tn_splits(nbk, nbk + nb2, m - k0), st);
+            if (s) return s;
+            if ((s = tbuild<T, T>(nbk, w.GW, nb, tau + k0, Tk, nb, w.Tw, st))) return s;
+            s = gemm_tn<T>(nbk, nb2, nbk, Tk, nb, 0, w.GW + (int64_t)nbk * nb, nb, 0, T(1), T(0), w.W2, nb,
+                           w.split, SPLIT_PART_ELEMS, nullptr, st, gemm_tn_splits(nbk, nb2, nbk));
+            if (s) return s;
+            if ((s = trailing_update<T>(m - k0, nb2, nbk, V, lda, w.W2, nb, A + (int64_t)(k0 + nbk) * lda + k0, st,
+                                        w.bf16, w.bsplit, w.bsplit_elems, true)))
+                return s;
+            continue;
+        }
+        if (paired(nb) && (k0 / nb) % 2 == 1) {
+            // second block of a pair: [G | W] = V^T [V | C] over both blocks,
+            // this block's T from the Gram's lower-right block, then the
+            // two-block update of the rest
+            const int kp = k0 - nb, nbp = nb + nbk, ldg = 2 * nb;
+            if (kp < kb) return CTQR_EINVAL;   // ranges hold whole pairs
+            const int nc = std::max(0, ce - (k0 + nbk));
+            const PairSplits ps = pair_splits(m, n, nb, kp);
+            const T *Vp = A + (int64_t)kp * lda + kp;
+            s = block_reduction<T>(nbp, nbp + nc, m - kp, Vp, lda, Vp, lda, nbp, w, ldg, ps.gw, st);
+            if (s) return s;
+            if ((s = tbuild<T, T>(nbk, w.GW + (int64_t)nb * ldg + nb, ldg, tau + k0, Tk, nb, w.Tw, st))) return s;
+            // G21 is kept for every pair with columns to its right, also those
+            // beyond this range (applied to them later)
+            T *g21 = w.g21 + (int64_t)(kp / (2 * nb)) * nb * nb;
+            if (k0 + nbk < n)
+                HIP_TRY(hipMemcpy2DAsync(g21, (size_t)nb * sizeof(T), w.GW + nb, (size_t)ldg * sizeof(T),
+                                         (size_t)nbk * sizeof(T), nb, hipMemcpyDeviceToDevice, st));
+            if (nc <= 0) continue;
+            if ((s = pair_update<T>(m, nb, kp, nbk, nc, Vp, lda, Tout, g21, w.GW + (int64_t)nbp * ldg, ldg,
+                                    A + (int64_t)(k0 + nbk) * lda + kp, ps, w, st)))
+                return s;
+            continue;
+        }
         // block reflector of the whole block column: [G | W] = V^T [V | C]
         const int nc = std::max(0, ce - (k0 + nbk));
-        const T *V = A + (int64_t)k0 * lda + k0;
         s = block_reduction<T>(nbk, nbk + nc, m - k0, V, lda, V, lda, nbk, w, nb, sp.gw, st);
         if (s) return s;
-        T *Tk = Tout + (int64_t)k0 * nb;
         if ((s = tbuild<T, T>(nbk, w.GW, nb, tau + k0, Tk, nb, w.Tw, st))) return s;
         if (nc <= 0) continue;
         // W' = T^T W;  C -= V W'
@@ -385,9 +477,22 @@ ctqr_status apply_blocks(int m, int n, const T *V, int64_t lda, const T *Tf, int
     if (nc <= 0) return CTQR_OK;
     for (int k0 = kb; k0 < ke; k0 += nb) {
         const int nbk = std::min(nb, n - k0);
-        const BlockSplits sp = block_splits(m, n, nb, k0);
         const T *Vk = V + (int64_t)k0 * lda + k0;
         T *Ck = C + (int64_t)c0 * lda + k0;
+        if (paired(nb) && k0 + nb < n) {
+            // the pair (k0, k0 + nb), as the in-range update applies it
+            if ((k0 / nb) % 2 != 0 || k0 + nb >= ke) return CTQR_EINVAL;   // ranges hold whole pairs
+            const int nb2 = std::min(nb, n - (k0 + nb)), ldg = 2 * nb;
+            const PairSplits ps = pair_splits(m, n, nb, k0);
+            s = block_reduction<T>(nb + nb2, nc, m - k0, Vk, lda, Ck, lda, 0, w, ldg, ps.gw, st);
+            if (s) return s;
+            if ((s = pair_update<T>(m, nb, k0, nb2, nc, Vk, lda, Tf, w.g21 + (int64_t)(k0 / (2 * nb)) * nb * nb,
+                                    w.GW, ldg, Ck, ps, w, st)))
+                return s;
+            k0 += nb;
+            continue;
+        }
+        const BlockSplits sp = block_splits(m, n, nb, k0);
         // the in-HBM call forms [G | W] at once: its split count applies
         s = block_reduction<T>(nbk, nc, m - k0, Vk, lda, Ck, lda, 0, w, nb, sp.gw, st);
         if (s) return s;

@@ -1322,14 +1322,21 @@ ctqr_status gemm_nn_bf16x3_parts(int M, int N, int K, float alpha, float *C, int
 }
 
 ctqr_status gemm_nn_bf16x3(int M, int N, int K, float alpha, float *C, int64_t ldc, const __bf16 *split,
-                           size_t split_elems, hipStream_t st, const int *skip)
+                           size_t split_elems, hipStream_t st, const int *skip, int kind)
 {
     if (M <= 0 || N <= 0 || K <= 0) return CTQR_OK;
+    if (kind != 1 && kind != 2) return CTQR_EINVAL;
     SplitParts p;
     if (!split_parts(M, N, K, const_cast<__bf16 *>(split), split_elems, p)) return CTQR_ENOMEM;
     dim3 grid((unsigned)(ceil_div(M, TILE) * ceil_div(N, TILE)));
-    LAUNCH_TRY(gemm_nn_bf16x3_kernel<1>, grid, dim3(NTHR), 0, st, M, N, K, (const __bf16 *)p.vh, (const __bf16 *)p.vl,
-               (int64_t)p.kp, (const __bf16 *)p.wh, (const __bf16 *)p.wl, (int64_t)p.kp, alpha, C, ldc, skip);
+    if (kind == 1)
+        LAUNCH_TRY(gemm_nn_bf16x3_kernel<1>, grid, dim3(NTHR), 0, st, M, N, K, (const __bf16 *)p.vh,
+                   (const __bf16 *)p.vl, (int64_t)p.kp, (const __bf16 *)p.wh, (const __bf16 *)p.wl, (int64_t)p.kp,
+                   alpha, C, ldc, skip);
+    else
+        LAUNCH_TRY(gemm_nn_bf16x3_kernel<2>, grid, dim3(NTHR), 0, st, M, N, K, (const __bf16 *)p.vh,
+                   (const __bf16 *)p.vl, (int64_t)p.kp, (const __bf16 *)p.wh, (const __bf16 *)p.wl, (int64_t)p.kp,
+                   alpha, C, ldc, skip);
     return CTQR_OK;
 }
 

@@ -35,13 +35,15 @@ ctqr_status gemm_nn_split(int M, int N, int K, const T *A, int64_t lda, const T 
 // operands' high and low bf16 parts to `split` (bf16x3_split_elems(m, n, nb)
 // elements cover any M <= m, N <= n, K <= nb); gemm_nn_bf16x3 then forms the
 // product from them, three BF16 products per pair with FP32 accumulation.
+// kind (1 or 2) only selects the kernel instance, so that profiles tell the
+// trailing update (1) from the update of a pair's second block column (2).
 size_t bf16x3_split_elems(int64_t m, int64_t n, int nb);
 // householder = false splits a plain M x K operand (a block of R).
 ctqr_status bf16x3_split(int M, int N, int K, const float *V, int64_t lda, const float *W, int64_t ldw,
                          __bf16 *split, size_t split_elems, hipStream_t st, bool householder = true,
                          const int *skip = nullptr);
 ctqr_status gemm_nn_bf16x3(int M, int N, int K, float alpha, float *C, int64_t ldc, const __bf16 *split,
-                           size_t split_elems, hipStream_t st, const int *skip = nullptr);
+                           size_t split_elems, hipStream_t st, const int *skip = nullptr, int kind = 1);
 // The same pieces with caller-placed parts: an M x K operand to row-major
 // parts (row stride ldp, rows up to rows_pad, a multiple of 128, zero), a
 // K x N operand to column-major parts (column stride ldp, columns up to
