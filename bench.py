@@ -605,17 +605,27 @@ def main():
                 "achieved": achieved, "peak": PEAK_TFLOPS["f32"], "unit": "TFLOP/s",
                 "frac": (achieved / PEAK_TFLOPS["f32"]) if achieved else None}
     else:
-        # at BF16 MFMA rates the update is bound by HBM: its FP32-equivalent
-        # intensity (2 m_k n_k nb flops over the C read + write, nb / 4 = 64
-        # flop/B at nb = 256; 192 counting the three products) is below the
-        # 2500 TFLOP/s / 8 TB/s = 312 flop/B ridge
+        # The split-BF16 update executes three BF16 products per FP32 product:
+        # 6 m_k n_k K BF16 flops over 8 m_k n_k (+ 4 K (m_k + n_k)) bytes.  At
+        # K = 512 (paired block columns) that is 384 flop/B, above the
+        # 2500 TFLOP/s / 8 TB/s = 312 flop/B ridge: bound by the MFMA rate.  At
+        # K = 256 (unpaired nb = 256) it is 192 flop/B: bound by HBM.
         gbs = alg_bytes / (avg_ms * 1e-3) / 1e9 if avg_ms else None
-        roof = {"bound": "hbm", "kernel": TRAILING_KERNEL["bf16x3"] + " (split-BF16 trailing update C -= V W')",
-                "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": gbs / HBM_PEAK_GBS if gbs else None,
-                "mfma_tflops_fp32_equivalent": achieved,
-                "mfma_tflops_executed_bf16": 3 * achieved if achieved else None,
-                "mfma_peak_bf16_tflops": PEAK_TFLOPS["bf16"]}
+        exec_tf = 3 * achieved if achieved else None
+        flops_exec = sum(6.0 * mk * nc * kk for mk, nc, kk in launches_k)
+        intensity = flops_exec / alg if alg else 0.0
+        ridge = PEAK_TFLOPS["bf16"] * 1e12 / (HBM_PEAK_GBS * 1e9)
+        common = {"kernel": TRAILING_KERNEL["bf16x3"] + " (split-BF16 trailing update C -= V W')",
+                  "executed_bf16_flop_per_byte": intensity, "ridge_flop_per_byte": ridge,
+                  "mfma_tflops_fp32_equivalent": achieved,
+                  "mfma_tflops_executed_bf16": exec_tf, "mfma_peak_bf16_tflops": PEAK_TFLOPS["bf16"],
+                  "hbm_gbs_algorithmic": gbs, "hbm_frac": gbs / HBM_PEAK_GBS if gbs else None}
+        if intensity > ridge:
+            roof = {"bound": "mfma", "achieved": exec_tf, "peak": PEAK_TFLOPS["bf16"], "unit": "TFLOP/s",
+                    "frac": exec_tf / PEAK_TFLOPS["bf16"] if exec_tf else None, **common}
+        else:
+            roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": gbs / HBM_PEAK_GBS if gbs else None, **common}
     roof.update({
         "traffic": measured_traffic(args.workload, args.prec) if args.nb == 256 else None,
         "traffic_unit": "bytes per launch (HBM, FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
@@ -623,6 +633,8 @@ def main():
         "launches": launches,
         "avg_launch_ms": avg_ms,
         "flops_per_launch": kern_flops / launches if launches else None,
+        "flops_per_launch_counts": "2 rows cols K (one FP32-equivalent product; the split-BF16 "
+                                   "update executes three BF16 products of this size)",
     })
     products = {"bf16x3": "split-BF16 MFMA block-column products (high + low bf16 parts, three products, FP32 "
                           "accumulation)",
