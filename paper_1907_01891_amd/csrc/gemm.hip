@@ -817,11 +817,13 @@ void split_w_kernel(int kc, int cols, const float *__restrict__ W, int64_t ldw_i
 
 // C += alpha V W' from the split parts: 128 x 128 output tiles, three BF16
 // products per operand pair (mfma_step_bf2), FP32 accumulation, C prefetched
-// at the start as in the FP32 trailing update.  Ah/Al: rows padded to whole
-// tiles, row stride lda; Bh/Bl: columns padded to whole tiles, column stride
-// ldb; both cover k up to K rounded up to a stage.  KIND only separates the
-// launch sites in a profile: 1 is the factorization's trailing update, 0 the
-// substitutions.
+// at the start as in the FP32 trailing update.  C is read and written once,
+// with non-temporal accesses, so the streaming tiles do not push the operand
+// panels that neighbouring tiles re-read out of the L2.  Ah/Al: rows padded to
+// whole tiles, row stride lda; Bh/Bl: columns padded to whole tiles, column
+// stride ldb; both cover k up to K rounded up to a stage.  KIND only separates
+// the launch sites in a profile: 1 is the factorization's trailing update, 2
+// the update of a pair's second block column, 0 the substitutions.
 template <int KIND>
 __global__ __launch_bounds__(NTHR, 2)
 void gemm_nn_bf16x3_kernel(int M, int N, int K, const __bf16 *__restrict__ Ah, const __bf16 *__restrict__ Al,
@@ -862,7 +864,7 @@ void gemm_nn_bf16x3_kernel(int M, int N, int K, const __bf16 *__restrict__ Ah, c
                 acc_coords<float>(ib, jb, r, n, m);
                 n += n0 + wn;
                 m += m0 + wm;
-                cpre[ib][jb][r] = (m < M && n < N) ? C[(int64_t)n * ldc + m] : 0.0f;
+                cpre[ib][jb][r] = (m < M && n < N) ? __builtin_nontemporal_load(C + (int64_t)n * ldc + m) : 0.0f;
             }
 
     bf16x8 ra[2][PER], rb[2][PER];
@@ -912,7 +914,8 @@ void gemm_nn_bf16x3_kernel(int M, int N, int K, const __bf16 *__restrict__ Ah, c
                 acc_coords<float>(ib, jb, r, n, m);
                 n += n0 + wn;
                 m += m0 + wm;
-                if (m < M && n < N) C[(int64_t)n * ldc + m] = cpre[ib][jb][r] + alpha * acc[ib][jb][r];
+                if (m < M && n < N)
+                    __builtin_nontemporal_store(cpre[ib][jb][r] + alpha * acc[ib][jb][r], C + (int64_t)n * ldc + m);
             }
 }
 
