@@ -1089,10 +1089,10 @@ int gemm_tn_splits(int M, int N, int K)
     int64_t max_by_k = K / (4 * 32);   // keep at least 4 k-steps per split
     if (splits > max_by_k) splits = max_by_k;
     if (splits < 1) splits = 1;
-    // narrow products read a tall operand through few tiles: allow more
-    // splits so the read still spreads over every CU
-    const int cap = narrow ? 256 : 64;
-    if (splits > cap) splits = cap;
+    // products with few output tiles read tall operands (the inner-panel
+    // reductions V^T C of a 32-wide panel, Q^T B of few slices): up to 256
+    // splits, so the read still spreads over every CU
+    if (splits > 256) splits = 256;
     return (int)splits;
 }
 
