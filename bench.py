@@ -105,27 +105,32 @@ def trailing_launches(m, n, nb):
 
 
 def gemm_source_hash():
-    """Hash of gemm.hip without the host-side split-count rule of the TN
-    products (gemm_tn_splits), which the trailing-update kernels and their
-    launchers do not use: the key of the committed HBM-counter summaries."""
+    """Hash of the code of gemm.hip (comments removed) without the host-side
+    split-count rule of the TN products (gemm_tn_splits), which the
+    trailing-update kernels and their launchers do not use: the key of the
+    committed HBM-counter summaries."""
     import hashlib
     import re
     with open(os.path.join(ROOT, "paper_1907_01891_amd", "csrc", "gemm.hip")) as f:
         src = f.read()
     src = re.sub(r"\nint gemm_tn_splits\(int M, int N, int K\)\n\{.*?\n\}\n", "\n", src, count=1, flags=re.S)
+    src = re.sub(r"[ \t]*//[^\n]*", "", src)
     return hashlib.sha256(src.encode()).hexdigest()[:16]
 
 
-def measured_traffic(workload, prec):
+def measured_traffic(workload, prec, launches):
     """HBM bytes per launch of the trailing-update kernel from the committed
     counter summary (FETCH_SIZE + WRITE_SIZE scaled by a copy kernel), or None
-    if there is none for this workload or the kernel source changed since."""
+    if there is none for this workload and launch count (the factorization's
+    schedule) or the kernel source changed since."""
     try:
         kv = dict(l.strip().split("=", 1) for l in open(TRAFFIC_FILES[prec])
                   if "=" in l and not l.lstrip().startswith("#"))
     except OSError:
         return None
     if kv.get("workload") != workload or kv.get("gemm_hip_sha256") != gemm_source_hash():
+        return None
+    if kv.get("launches") != str(launches):
         return None
     return float(kv["bytes_per_launch"])
 
@@ -633,7 +638,7 @@ def main():
             roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": gbs / HBM_PEAK_GBS if gbs else None, **common}
     roof.update({
-        "traffic": measured_traffic(args.workload, args.prec) if args.nb == 256 else None,
+        "traffic": measured_traffic(args.workload, args.prec, launches) if args.nb == 256 else None,
         "traffic_unit": "bytes per launch (HBM, FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
         "algorithmic_bytes_per_launch": alg_bytes,
         "launches": launches,
