@@ -89,15 +89,14 @@ TRAILING_KERNEL = {"fp32": "gemm_nn_kernel<float, 1, 128, false, 0>",
 
 def trailing_launches(m, n, nb):
     """(rows, columns, inner dimension) of every trailing-update launch of the
-    factorization.  With nb dividing 1024, block columns (2j, 2j+1) are
-    paired: the first block's reflector updates only its partner, and the
-    pair's 2nb-wide block reflector updates the rest in one launch."""
+    factorization.  With nb dividing 512, groups of four block columns share
+    one update: each block's reflector updates only the rest of its group, and
+    the group's block reflector (up to 4 nb wide) updates the remaining columns
+    in one launch."""
     out, k0 = [], 0
-    paired = 1024 % nb == 0
+    g = 4 if 512 % nb == 0 else 1
     while k0 < n:
-        w = min(nb, n - k0)
-        if paired and k0 + nb < n:
-            w = nb + min(nb, n - k0 - nb)
+        w = min(g * nb, n - k0)
         if n - k0 - w > 0:
             out.append((m - k0, n - k0 - w, w))
         k0 += w
@@ -618,9 +617,9 @@ def main():
     else:
         # The split-BF16 update executes three BF16 products per FP32 product:
         # 6 m_k n_k K BF16 flops over 8 m_k n_k (+ 4 K (m_k + n_k)) bytes.  At
-        # K = 512 (paired block columns) that is 384 flop/B, above the
-        # 2500 TFLOP/s / 8 TB/s = 312 flop/B ridge: bound by the MFMA rate.  At
-        # K = 256 (unpaired nb = 256) it is 192 flop/B: bound by HBM.
+        # K = 1024 (groups of four 256-wide block columns) that is 768 flop/B,
+        # above the 2500 TFLOP/s / 8 TB/s = 312 flop/B ridge: bound by the MFMA
+        # rate.  At K = 256 (ungrouped nb = 256) it is 192 flop/B: bound by HBM.
         gbs = alg_bytes / (avg_ms * 1e-3) / 1e9 if avg_ms else None
         exec_tf = 3 * achieved if achieved else None
         flops_exec = sum(6.0 * mk * nc * kk for mk, nc, kk in launches_k)

@@ -183,12 +183,13 @@ ctqr_status ctqr_qr_workspace(int64_t m, int64_t n, ctqr_dtype dtype, ctqr_prec 
  *   prec   CTQR_PREC_FP64 requires dtype CTQR_F64; the two MFMA modes require
  *          CTQR_F32.
  *   nb     outer block width (multiple of 32, <= 256), 0 = default.  The same
- *          nb must be passed to the solve.  When nb divides 1024, block
- *          columns (2j, 2j+1) are paired: the first block's reflector updates
- *          only its partner, and the two reflectors together update the rest
- *          of the matrix as one 2nb-wide block reflector
- *          I - [V1 V2] [T1, -T1 V1^T V2 T2; 0, T2] [V1 V2]^T, one pass over the
- *          trailing columns per pair.  T still holds each block's own T.
+ *          nb must be passed to the solve.  When nb divides 512, groups
+ *          of four block columns share one trailing update: each block's
+ *          reflector updates only the rest of its group, and the group's
+ *          reflectors together update the remaining columns as one block
+ *          reflector up to 4 nb wide, I - V T V^T with
+ *          T = [T_0, -T_0 V_0^T V_1 T_1, ...; 0, T_1, ...], one pass over the
+ *          trailing columns per group.  T still holds each block's own T.
  *   T      device, nb x n in `dtype` (leading dim nb): the nb x nb upper
  *          triangular T of each block column (the paper's "S factors").
  *   tau    device, n doubles: the reflector scalars (LAPACK larfg convention:
@@ -447,9 +448,8 @@ ctqr_status ctqr_set_progress(ctqr_progress_fn fn, void *user);
  * bracketed by HIP events on the stream it runs on; ctqr_profile_read returns
  * the number of launches, their summed duration (ms, resolved after the
  * caller has synchronised the stream) and their summed algorithmic flops
- * (2 * rows * cols * K per launch, K = nb, or the pair's width for paired
- * block columns; the updates of a pair's second block column by the first
- * block are not counted).  Host-side bookkeeping only; enabling it
+ * (2 * rows * cols * K per launch, K = nb, or the group's width for grouped
+ * block columns; the updates inside a group by its blocks are not counted).  Host-side bookkeeping only; enabling it
  * clears the previous record. */
 ctqr_status ctqr_profile_enable(int32_t on);
 ctqr_status ctqr_profile_read(int64_t *launches, double *total_ms, double *total_flops);

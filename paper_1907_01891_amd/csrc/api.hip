@@ -87,23 +87,24 @@ struct Carve {
     }
 };
 
-// Consecutive block columns (2j, 2j+1) are paired: the first block's
-// reflector updates only its partner, and the two compact-WY reflectors then
-// act on the rest of the matrix as one 2nb-wide block reflector (Schreiber and
-// Van Loan, the product form of Householder blocks), so the trailing update
-// sweeps the remaining columns once per pair instead of once per block, with
-// an inner dimension of 2nb.  Only for nb dividing 1024: every range boundary
-// of the out-of-core factorization (a multiple of 2048, or n) then falls
-// between pairs.
-bool paired(int nb) { return 1024 % nb == 0; }
-int gw_rows(int nb) { return paired(nb) ? 2 * nb : nb; }   // rows of [G | W] and W'
+// Groups of GROUP consecutive block columns share one trailing update: each
+// block's reflector updates only the rest of its group, and the group's
+// compact-WY reflectors then act on the remaining columns as one block
+// reflector of up to GROUP nb columns (Schreiber and Van Loan, the product form
+// of Householder blocks), so the trailing update sweeps the remaining columns
+// once per group instead of once per block, with an inner dimension of
+// GROUP nb.  Only for nb dividing 512: every range boundary of the out-of-core
+// factorization (a multiple of 2048, or n) then falls between groups.
+constexpr int GROUP = 4;
+int group_blocks(int nb) { return 512 % nb == 0 ? GROUP : 1; }
+int gw_rows(int nb) { return group_blocks(nb) * nb; }   // rows of [G | W] and W'
 
 template <typename T>
 struct FactorWS {
     unsigned *bars;
     double *part, *part2, *gram_part, *gram, *Tw;
     T *Tin, *GW, *W2, *split, *rtmp;
-    T *g21;                  // per pair: V2^T V1 (nb x nb), for the pair's later applications
+    T *gstore;               // per group: its Gram V^T V (gw_rows square), for its later applications
     __bf16 *bsplit;          // split-BF16 parts of V and W' (FP32 factor only)
     size_t bsplit_elems;
     __bf16 *vtsplit;         // split-BF16 parts of V, column-major, for [G | W]
@@ -127,7 +128,7 @@ FactorWS<T> carve_factor(void *work, int64_t m, int64_t n, int nb)
     const int g = gw_rows(nb);
     w.GW = c.take<T>((int64_t)g * n);
     w.W2 = c.take<T>((int64_t)g * n);
-    w.g21 = c.take<T>(paired(nb) ? ceil_div(n, 2 * nb) * nb * nb : 0);
+    w.gstore = c.take<T>(group_blocks(nb) > 1 ? ceil_div(n, g) * g * g : 0);
     w.split = c.take<T>(SPLIT_PART_ELEMS);
     w.rtmp = c.take<T>((int64_t)trinv_tmp_elems());
     w.bsplit_elems = sizeof(T) == 4 ? bf16x3_split_elems(m, n, g) : 0;
@@ -258,9 +259,10 @@ ctqr_status ensure_setup()
 
 // Profiled launch of the trailing update C -= V W' (the dominant kernel).
 // C -= V W' (V: mk x nbk Householder block, W': nbk x nc, column stride nb).
-// partner: the update of a pair's second block column by the first block,
-// launched as its own kernel instance (FP32 MFMA in the one-part BF16 mode)
-// and left out of the profile records, which hold the trailing updates only.
+// partner: the update of the rest of a group of block columns by one of its
+// blocks, launched as its own kernel instance (FP32 MFMA in the one-part BF16
+// mode) and left out of the profile records, which hold the trailing updates
+// only.
 template <typename T>
 ctqr_status trailing_update(int mk, int nc, int nbk, const T *V, int64_t lda, const T *W2, int nb, T *C,
                             hipStream_t st, int bf16, __bf16 *bsplit, size_t bsplit_elems, bool partner = false)
@@ -336,37 +338,45 @@ BlockSplits block_splits(int m, int n, int nb, int k0)
     return {gemm_tn_splits(nbk, nbk + nc, m - k0), nc > 0 ? gemm_tn_splits(nbk, nc, nbk) : 1};
 }
 
-// The same for the pair whose first block starts at kp (its second block is
-// nb2 wide): [G | W] over both blocks, then Ta^T Wa and Tb^T (Wb - G21 W'a).
-struct PairSplits {
-    int gw, ta, tb;
+// The same for the group of block columns starting at kg: [G | W] over the
+// group, then T_j^T (W_j - G_{j,<j} W'_{<j}) for each block j of the group.
+struct GroupSplits {
+    int gw;
+    int t[GROUP];
 };
-PairSplits pair_splits(int m, int n, int nb, int kp)
+GroupSplits group_splits(int m, int n, int nb, int kg)
 {
-    const int nb2 = std::min(nb, n - (kp + nb)), nbp = nb + nb2, nc = n - (kp + nbp);
-    if (nc <= 0) return {gemm_tn_splits(nbp, nbp, m - kp), 1, 1};
-    return {gemm_tn_splits(nbp, nbp + nc, m - kp), gemm_tn_splits(nb, nc, nb), gemm_tn_splits(nb2, nc, nb2)};
+    const int nbg = std::min(group_blocks(nb) * nb, n - kg), nc = n - (kg + nbg);
+    GroupSplits s{};
+    s.gw = gemm_tn_splits(nbg, nbg + std::max(nc, 0), m - kg);
+    for (int j = 0; j * nb < nbg; ++j) {
+        const int wj = std::min(nb, nbg - j * nb);
+        s.t[j] = nc > 0 ? gemm_tn_splits(wj, nc, wj) : 1;
+    }
+    return s;
 }
 
-// Two-block compact-WY update of nc columns C (rows from kp) by the pair at
-// kp: with T = [Ta, -Ta G12 Tb; 0, Tb] and W = [Wa; Wb] = V^T C (in Wg,
-// column stride ldg), W' = T^T W is W'a = Ta^T Wa and W'b = Tb^T (Wb - G21 W'a)
-// (G21 = V2^T V1 = G12^T), and C -= V W' with the 2nb-wide V.
+// Compact-WY update of nc columns C (rows from kg) by the group of block
+// columns at kg (nbg Householder vectors Vg with Gram G = Vg^T Vg in Gs,
+// column stride ldg).  With W = Vg^T C in Wg (column stride ldg), the rows of
+// W' = T^T W for the group's factor T = [T_0, -T_0 G_01 T_1, ...; 0, T_1, ...]
+// are, block by block, W'_j = T_j^T (W_j - G_{j,<j} W'_{<j}); then C -= Vg W'.
 template <typename T>
-ctqr_status pair_update(int m, int nb, int kp, int nb2, int nc, const T *Vp, int64_t lda, const T *Tf,
-                        const T *g21, T *Wg, int ldg, T *C, const PairSplits &sp, FactorWS<T> &w, hipStream_t st)
+ctqr_status group_update(int m, int nb, int kg, int nbg, int nc, const T *Vg, int64_t lda, const T *Tf,
+                         const T *Gs, T *Wg, int ldg, T *C, const GroupSplits &sp, FactorWS<T> &w, hipStream_t st)
 {
     ctqr_status s;
-    const T *Ta = Tf + (int64_t)kp * nb, *Tb = Tf + (int64_t)(kp + nb) * nb;
-    s = gemm_tn<T>(nb, nc, nb, Ta, nb, 0, Wg, ldg, 0, T(1), T(0), w.W2, ldg, w.split, SPLIT_PART_ELEMS, nullptr, st,
-                   sp.ta);
-    if (s) return s;
-    s = gemm_nn<T>(nb2, nc, nb, g21, nb, 0, w.W2, ldg, T(-1), Wg + nb, ldg, nullptr, st);
-    if (s) return s;
-    s = gemm_tn<T>(nb2, nc, nb2, Tb, nb, 0, Wg + nb, ldg, 0, T(1), T(0), w.W2 + nb, ldg, w.split, SPLIT_PART_ELEMS,
-                   nullptr, st, sp.tb);
-    if (s) return s;
-    return trailing_update<T>(m - kp, nc, nb + nb2, Vp, lda, w.W2, ldg, C, st, w.bf16, w.bsplit, w.bsplit_elems);
+    for (int j = 0, r0 = 0; r0 < nbg; ++j, r0 += nb) {
+        const int wj = std::min(nb, nbg - r0);
+        if (r0 > 0) {
+            s = gemm_nn<T>(wj, nc, r0, Gs + r0, ldg, 0, w.W2, ldg, T(-1), Wg + r0, ldg, nullptr, st);
+            if (s) return s;
+        }
+        s = gemm_tn<T>(wj, nc, wj, Tf + (int64_t)(kg + r0) * nb, nb, 0, Wg + r0, ldg, 0, T(1), T(0), w.W2 + r0, ldg,
+                       w.split, SPLIT_PART_ELEMS, nullptr, st, sp.t[j]);
+        if (s) return s;
+    }
+    return trailing_update<T>(m - kg, nc, nbg, Vg, lda, w.W2, ldg, C, st, w.bf16, w.bsplit, w.bsplit_elems);
 }
 
 // Right-looking blocked Householder QR of the block columns [kb, ke) of an
@@ -405,44 +415,45 @@ ctqr_status factor_blocks(int m, int n, T *A, int64_t lda, int nb, int kb, int k
         }
         const T *V = A + (int64_t)k0 * lda + k0;
         T *Tk = Tout + (int64_t)k0 * nb;
-        if (paired(nb) && (k0 / nb) % 2 == 0 && k0 + nb < n) {
-            // first block of a pair: its reflector updates the partner block
-            // column only
-            if (k0 + nb >= ke) return CTQR_EINVAL;   // ranges hold whole pairs
-            const int nb2 = std::min(nb, n - (k0 + nb));
-            s = block_reduction<T>(nbk, nbk + nb2, m - k0, V, lda, V, lda, nbk, w, nb,
-                                   gemm_tn_splits(nbk, nbk + nb2, m - k0), st);
+        const int g = group_blocks(nb), bi = (k0 / nb) % g, kg = k0 - bi * nb, ge = std::min(n, kg + g * nb);
+        if (g > 1 && k0 + nbk < ge) {
+            // not the last block of its group: its reflector updates the rest
+            // of the group only
+            if (kg < kb || ge > ke) return CTQR_EINVAL;   // ranges hold whole groups
+            const int nr = ge - (k0 + nbk);
+            s = block_reduction<T>(nbk, nbk + nr, m - k0, V, lda, V, lda, nbk, w, nb,
+                                   gemm_tn_splits(nbk, nbk + nr, m - k0), st);
             if (s) return s;
             if ((s = tbuild<T, T>(nbk, w.GW, nb, tau + k0, Tk, nb, w.Tw, st))) return s;
-            s = gemm_tn<T>(nbk, nb2, nbk, Tk, nb, 0, w.GW + (int64_t)nbk * nb, nb, 0, T(1), T(0), w.W2, nb,
-                           w.split, SPLIT_PART_ELEMS, nullptr, st, gemm_tn_splits(nbk, nb2, nbk));
+            s = gemm_tn<T>(nbk, nr, nbk, Tk, nb, 0, w.GW + (int64_t)nbk * nb, nb, 0, T(1), T(0), w.W2, nb,
+                           w.split, SPLIT_PART_ELEMS, nullptr, st, gemm_tn_splits(nbk, nr, nbk));
             if (s) return s;
-            if ((s = trailing_update<T>(m - k0, nb2, nbk, V, lda, w.W2, nb, A + (int64_t)(k0 + nbk) * lda + k0, st,
+            if ((s = trailing_update<T>(m - k0, nr, nbk, V, lda, w.W2, nb, A + (int64_t)(k0 + nbk) * lda + k0, st,
                                         w.bf16, w.bsplit, w.bsplit_elems, true)))
                 return s;
             continue;
         }
-        if (paired(nb) && (k0 / nb) % 2 == 1) {
-            // second block of a pair: [G | W] = V^T [V | C] over both blocks,
-            // this block's T from the Gram's lower-right block, then the
-            // two-block update of the rest
-            const int kp = k0 - nb, nbp = nb + nbk, ldg = 2 * nb;
-            if (kp < kb) return CTQR_EINVAL;   // ranges hold whole pairs
-            const int nc = std::max(0, ce - (k0 + nbk));
-            const PairSplits ps = pair_splits(m, n, nb, kp);
-            const T *Vp = A + (int64_t)kp * lda + kp;
-            s = block_reduction<T>(nbp, nbp + nc, m - kp, Vp, lda, Vp, lda, nbp, w, ldg, ps.gw, st);
+        if (g > 1 && bi > 0) {
+            // last block of a group: [G | W] = Vg^T [Vg | C] over the group,
+            // this block's T from the Gram's diagonal block, then the group's
+            // update of the rest
+            const int nbg = ge - kg, ldg = g * nb;
+            if (kg < kb) return CTQR_EINVAL;   // ranges hold whole groups
+            const int nc = std::max(0, ce - ge);
+            const GroupSplits gs = group_splits(m, n, nb, kg);
+            const T *Vg = A + (int64_t)kg * lda + kg;
+            s = block_reduction<T>(nbg, nbg + nc, m - kg, Vg, lda, Vg, lda, nbg, w, ldg, gs.gw, st);
             if (s) return s;
-            if ((s = tbuild<T, T>(nbk, w.GW + (int64_t)nb * ldg + nb, ldg, tau + k0, Tk, nb, w.Tw, st))) return s;
-            // G21 is kept for every pair with columns to its right, also those
-            // beyond this range (applied to them later)
-            T *g21 = w.g21 + (int64_t)(kp / (2 * nb)) * nb * nb;
-            if (k0 + nbk < n)
-                HIP_TRY(hipMemcpy2DAsync(g21, (size_t)nb * sizeof(T), w.GW + nb, (size_t)ldg * sizeof(T),
-                                         (size_t)nbk * sizeof(T), nb, hipMemcpyDeviceToDevice, st));
+            if ((s = tbuild<T, T>(nbk, w.GW + (int64_t)(bi * nb) * ldg + bi * nb, ldg, tau + k0, Tk, nb, w.Tw, st)))
+                return s;
+            // the Gram is kept for every group with columns to its right, also
+            // those beyond this range (applied to them later)
+            T *Gs = w.gstore + (int64_t)(kg / ldg) * ldg * ldg;
+            if (ge < n)
+                HIP_TRY(hipMemcpyAsync(Gs, w.GW, (size_t)ldg * nbg * sizeof(T), hipMemcpyDeviceToDevice, st));
             if (nc <= 0) continue;
-            if ((s = pair_update<T>(m, nb, kp, nbk, nc, Vp, lda, Tout, g21, w.GW + (int64_t)nbp * ldg, ldg,
-                                    A + (int64_t)(k0 + nbk) * lda + kp, ps, w, st)))
+            if ((s = group_update<T>(m, nb, kg, nbg, nc, Vg, lda, Tout, Gs, w.GW + (int64_t)nbg * ldg, ldg,
+                                     A + (int64_t)ge * lda + kg, gs, w, st)))
                 return s;
             continue;
         }
@@ -475,21 +486,22 @@ ctqr_status apply_blocks(int m, int n, const T *V, int64_t lda, const T *Tf, int
     ctqr_status s;
     const int nc = c1 - c0;
     if (nc <= 0) return CTQR_OK;
+    const int g = group_blocks(nb);
     for (int k0 = kb; k0 < ke; k0 += nb) {
         const int nbk = std::min(nb, n - k0);
         const T *Vk = V + (int64_t)k0 * lda + k0;
         T *Ck = C + (int64_t)c0 * lda + k0;
-        if (paired(nb) && k0 + nb < n) {
-            // the pair (k0, k0 + nb), as the in-range update applies it
-            if ((k0 / nb) % 2 != 0 || k0 + nb >= ke) return CTQR_EINVAL;   // ranges hold whole pairs
-            const int nb2 = std::min(nb, n - (k0 + nb)), ldg = 2 * nb;
-            const PairSplits ps = pair_splits(m, n, nb, k0);
-            s = block_reduction<T>(nb + nb2, nc, m - k0, Vk, lda, Ck, lda, 0, w, ldg, ps.gw, st);
+        if (g > 1 && k0 + nb < n) {
+            // a group of two or more blocks, as the in-range update applies it
+            const int nbg = std::min(g * nb, n - k0), ldg = g * nb;
+            if ((k0 / nb) % g != 0 || k0 + nbg > ke) return CTQR_EINVAL;   // ranges hold whole groups
+            const GroupSplits gs = group_splits(m, n, nb, k0);
+            s = block_reduction<T>(nbg, nc, m - k0, Vk, lda, Ck, lda, 0, w, ldg, gs.gw, st);
             if (s) return s;
-            if ((s = pair_update<T>(m, nb, k0, nb2, nc, Vk, lda, Tf, w.g21 + (int64_t)(k0 / (2 * nb)) * nb * nb,
-                                    w.GW, ldg, Ck, ps, w, st)))
+            if ((s = group_update<T>(m, nb, k0, nbg, nc, Vk, lda, Tf, w.gstore + (int64_t)(k0 / ldg) * ldg * ldg,
+                                     w.GW, ldg, Ck, gs, w, st)))
                 return s;
-            k0 += nb;
+            k0 += nbg - nb;
             continue;
         }
         const BlockSplits sp = block_splits(m, n, nb, k0);
