@@ -6,7 +6,7 @@ source-to-detector distance of 150 cm and a 30 degree fan.  The paper's own
 case (512^2 pixels, 260 views, 1025 detector bins) is kept as ``paper512``;
 the other workloads change only the image side and the view/bin counts.
 
-Readings taken where the paper is silent (each is listed in the design doc):
+Readings taken where the paper is silent:
   * the detector is flat and its bins are equispaced over the fan's width;
   * the square image is centred on the rotation axis with side
     2 R sin(fan/2): it circumscribes the circle that every view's fan covers,
