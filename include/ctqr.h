@@ -209,8 +209,7 @@ ctqr_status ctqr_qr_factor(int64_t m, int64_t n, ctqr_dtype dtype, void *A, int6
 
 /* Outer block width nb for ctqr_qr_factor, picked by timing on the caller's
  * own matrix: each candidate nb in {64, 128, 256} factors the leading
- * min(n, 1024) columns (rounded down to a multiple of 256, or all n columns
- * when n < 256) with the trailing updates over all n columns, on `stream`,
+ * min(n, 1024) columns with the trailing updates over all n columns, on `stream`,
  * and the candidate with the least time per factored column wins.
  * A is OVERWRITTEN (each candidate factors it further in place): rebuild it
  * before the real factorization.  The stream is synchronised (the timing is

@@ -544,7 +544,9 @@ ctqr_status tune_nb_impl(int64_t m64, int64_t n64, T *A, int64_t lda, T *Tout, d
                          ctqr_info *info, hipStream_t st, int bf16, int32_t *nb_best, float *ms_per_col)
 {
     const int m = (int)m64, n = (int)n64;
-    const int cols = n < 256 ? n : std::min(n, TUNE_COLS) / 256 * 256;
+    // whole groups of block columns for every candidate (TUNE_COLS is a
+    // multiple of each candidate's group width), or all n columns
+    const int cols = std::min(n, TUNE_COLS);
     const int ncu = std::min(device_cus(), MAX_PANEL_WG);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     ctqr_status s = CTQR_OK;

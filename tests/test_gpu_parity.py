@@ -281,6 +281,23 @@ def test_bf16x3_trailing_update_factor(gpu, name):
         assert e <= 1e-10
 
 
+def test_tune_nb_small_matrix(gpu):
+    # n = 576 (fewer than 1024 columns, not a multiple of 256): every candidate
+    # factors all columns, whole groups of block columns included
+    name = "ct24"
+    _print_case("tune nb small", name)
+    g, A, X, B = oracle_problem(name)
+    QRo, tauo = oracle_factor(name)
+    Ad = A.toarray()
+    F = QRFactor(upload_dense(Ad, torch.float64), C.CTQR_PREC_FP64, nb=256)
+    nb, ms = F.tune_nb()
+    torch.cuda.synchronize()
+    assert nb in (64, 128, 256) and F.nb == nb and all(t > 0 for t in ms)
+    F2, info = _gpu_factor(Ad, torch.float64, C.CTQR_PREC_FP64, nb)
+    assert info.status == 0, C.status_string(info.status)
+    assert np.abs(download(F2.A) - QRo).max() <= 1e-11 * np.abs(QRo).max()
+
+
 def test_tune_nb_then_factor(gpu):
     # the block-width tuner times every candidate on the caller's matrix
     # (overwriting it); the matrix rebuilt and factored with the chosen width
