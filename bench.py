@@ -50,6 +50,42 @@ def solve_flops(m, n):
     return 4.0 * m * n - 2.0 * n * n + n * n
 
 
+def solve_phase_model(m, n, S, nnz, iters, store_bytes, split_refine, mfma_tflops=PEAK_TFLOPS["f32"]):
+    """Per-phase algorithmic work of one refined solve of S slices: flops and
+    HBM bytes, and the floor time max(flops / peak, bytes / HBM) of each phase.
+      qtb          Q^T B: 4 m n S - 2 n^2 S flops; reads V (the factor below
+                   the diagonal, m n - n^2 / 2 elements) and T, B in FP64,
+                   the working copy written and read back.
+      trsm         R X = C: n^2 S flops; reads R (n^2 / 2 elements) and the
+                   stored diagonal-block inverses (2 x 2048 n elements).
+      residual     per iteration r = B - A x, s = A^T r: 4 nnz S flops; the CSR
+                   and CSC values and indices (12 B per nonzero each) and the
+                   FP64 vectors.
+      refine_trsm  per iteration R^T y = s, R d = y: 2 n^2 S flops; R read twice.
+    MFMA phases are priced at the MFMA peak of the factor's precision
+    (mfma_tflops), or at a third of the BF16 peak for the refinement's
+    split-BF16 products (three BF16 products each); the sparse products at the
+    HBM rate only (FP64 gathers, no MFMA)."""
+    b = store_bytes
+    bw = HBM_PEAK_GBS * 1e9
+    f32 = mfma_tflops * 1e12
+    ph = {}
+    fl = S * (4.0 * m * n - 2.0 * n * n)
+    by = (m * n - n * n / 2.0) * b + 256.0 * n * b + 8.0 * m * S + 2 * 4.0 * m * S
+    ph["qtb"] = (fl, by, max(fl / f32, by / bw))
+    fl = S * float(n) * n
+    by = (n * n / 2.0 + 2 * 2048.0 * n) * b + 2 * 4.0 * n * S
+    ph["trsm"] = (fl, by, max(fl / f32, by / bw))
+    fl = iters * 4.0 * nnz * S
+    by = iters * (24.0 * nnz + 8.0 * S * (3 * m + 2 * n))
+    ph["residual"] = (fl, by, by / bw)
+    fl = iters * 2.0 * n * n * S
+    by = iters * (2 * (n * n / 2.0 + 2 * 2048.0 * n) * b + 4 * 4.0 * n * S)
+    peak = PEAK_TFLOPS["bf16"] * 1e12 / 3.0 if split_refine else f32
+    ph["refine_trsm"] = (fl, by, max(fl / peak, by / bw))
+    return ph
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -170,12 +206,29 @@ def cpu_baseline(workload, target_s):
     k = max(128, k // 32 * 32)
     Ad = A[:, :k].toarray()
     t0 = time.perf_counter()
-    hh.geqr2(Ad)
+    QR, tau = hh.geqr2(Ad)
     t = time.perf_counter() - t0
+    # the oracle's solve of the sample (Q^T B and back substitution) for a few
+    # slices, and LAPACK's blocked dgeqrf on the same columns as the tuned
+    # CPU library reference
+    import numpy as np
+    import scipy.linalg as sl
+    S = 16
+    Bs = np.asfortranarray(np.random.default_rng(0).standard_normal((m, S)))
+    t1 = time.perf_counter()
+    hh.backsub(QR, hh.apply_qt(QR, tau, Bs))
+    ts = time.perf_counter() - t1
+    t2 = time.perf_counter()
+    sl.lapack.dgeqrf(np.asfortranarray(Ad))
+    tl = time.perf_counter() - t2
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": qr_flops(m, k) / t / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
             "sample": "unblocked FP64 Householder QR of A[:, :%d] (%d x %d) of the %s geometry, %.1f s"
-                      % (k, m, k, workload, t)}
+                      % (k, m, k, workload, t),
+            "solve": {"value": S / ts, "unit": "slices/s (of the %d-column sample)" % k,
+                      "tflops": S * solve_flops(m, k) / ts / 1e12, "slices": S, "seconds": ts},
+            "lapack_dgeqrf": {"value": qr_flops(m, k) / tl / 1e12, "unit": "TFLOP/s", "seconds": tl,
+                              "note": "SciPy LAPACK dgeqrf (blocked, multithreaded BLAS) on the same sample"}}
 
 
 def request_stream_bench(args, log, F256, sp256, B256):
@@ -264,12 +317,34 @@ def request_stream_bench(args, log, F256, sp256, B256):
     torch.cuda.synchronize()
     t_queued = time.perf_counter() - tq0
     per = {}
+    nnz256 = sp256.nnz()
     for g in solvers:
         l = np.array([lat_ms[i] for i, (gg, _) in enumerate(reqs) if gg == g])
         per[g] = {"requests": int(l.size), "slices": int(sum(k for gg, k in reqs if gg == g)),
                   "p50_ms": float(np.percentile(l, 50)), "p99_ms": float(np.percentile(l, 99)),
                   "slice_tiles": {str(b): solvers[g].query(b)[1] for b in buckets[g]},
                   "graph_refine_iters": {str(b): solvers[g].query(b)[2] for b in buckets[g]}}
+        # closed-loop latency of each bucket against the floor of its work
+        # (the phase model of solve_phase_model at the bucket's width and its
+        # graph's refinement count): factor and sparse reads for narrow
+        # buckets, MFMA work for wide ones
+        sv = solvers[g]
+        qr = sv.qr
+        fl = {}
+        for b in buckets[g]:
+            li = [lat_ms[i] for i, (gg, k) in enumerate(reqs) if gg == g and sv.query(k)[0] == b]
+            if not li:
+                continue
+            gi = sv.query(b)[2]
+            it = max(0, gi - 2) if gi > 0 else 0   # the graph holds the calibrated count + 2
+            if g == "ct128":
+                mod = solve_phase_model(qr.m, qr.n, b, 0, 0, 8, False, PEAK_TFLOPS["f64"])
+            else:
+                mod = solve_phase_model(qr.m, qr.n, b, nnz256, it, 4, args.prec == "bf16x3" and b >= 128)
+            floor = sum(v[2] for v in mod.values()) * 1e3
+            med = float(np.median(li))
+            fl[str(b)] = {"requests": len(li), "median_ms": med, "floor_ms": floor, "frac": floor / med}
+        per[g]["bucket_floor"] = fl
     out = {"requests": len(reqs), "slices": int(total),
            "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
            "closed_loop_slices_per_s": total / t_closed, "queued_slices_per_s": total / t_queued,
@@ -519,6 +594,49 @@ def main():
     Xmixed = X.clone()
     log("mixed (%s products): qr %.2f TFLOP/s, %.0f slices/s, refine iters %d (status %d), recovery err %.2e"
         % (args.prec, qr_tf, slices_s, sinfo.iters, sinfo.status, rec_err))
+
+    # ---- untimed: phase breakdown of one factorization and refined solve
+    build_dense(A32, C.CTQR_F32)
+    torch.cuda.synchronize()
+    C.ctqr_profile_enable(C.CTQR_PROFILE_PHASES)
+    F.factor()
+    Xp = F.solve(B, sparse=sp.sp, tol=args.tol, max_iters=args.max_iters, method=REFINE[args.refine])
+    torch.cuda.synchronize()
+    phases = C.ctqr_profile_phases()
+    C.ctqr_profile_enable(False)
+    del Xp
+    phase_ms = {k: v[0] for k, v in phases.items()}
+    log("phases (ms): " + ", ".join("%s %.1f" % (k, v) for k, v in phase_ms.items()))
+
+    # ---- condition estimate and the least-squares perturbation bound
+    smax, smin, kappa = F.cond_estimate(sp.sp, nvec=8, iters=30)
+    Rr = colmajor(m, S, torch.float64, dev)
+    Rr.copy_(B)
+    sp.spmm(Xmixed, alpha=-1.0, beta=1.0, Y=Rr)
+    AX = sp.spmm(Xmixed)
+    torch.cuda.synchronize()
+    tan_theta = (Rr.norm(dim=0) / AX.norm(dim=0)).max().item()
+    del Rr, AX
+    u64, u32 = 2.0 ** -53, 2.0 ** -24
+    ls_bound64 = u64 * (2.0 * kappa + kappa ** 2 * tan_theta)
+    log("kappa estimate %.4e (sigma_max %.4e, sigma_min %.4e); tan(theta) %.3e; LS bound u64 (2k + k^2 tan) %.2e; "
+        "contraction %.3e (u32 kappa^2 %.3e)" % (kappa, smax, smin, tan_theta, ls_bound64, sinfo.contraction,
+                                                 u32 * kappa ** 2))
+    nnz = sp.nnz()
+    split_refine = args.prec == "bf16x3" and S >= 128
+    model = solve_phase_model(m, n, S, nnz, int(sinfo.iters), 4, split_refine)
+    floor_ms = sum(v[2] for v in model.values()) * 1e3
+    solve_roof = {
+        "bound": "per phase: MFMA (Q^T B, substitutions) and HBM (sparse residuals)",
+        "floor_ms": floor_ms, "measured_ms": t_solve, "frac": floor_ms / t_solve,
+        "refine_iters": int(sinfo.iters),
+        "phases": {k: {"flops": v[0], "bytes": v[1], "floor_ms": v[2] * 1e3,
+                       "measured_ms": phase_ms[k]} for k, v in model.items()},
+        "refine_other_ms": phase_ms["refine_other"],
+        "model": "floor = sum over phases of max(flops / MFMA peak, bytes / 8 TB/s); FP32 MFMA peak, a third of "
+                 "the BF16 peak for split-BF16 substitution products; per-phase measured = HIP events of an "
+                 "untimed profiled solve",
+    }
     stream_out = None
     if not args.no_stream and args.workload == "ct256":
         stream_out = request_stream_bench(args, log, F, sp, B)
@@ -615,27 +733,23 @@ def main():
                 "achieved": achieved, "peak": PEAK_TFLOPS["f32"], "unit": "TFLOP/s",
                 "frac": (achieved / PEAK_TFLOPS["f32"]) if achieved else None}
     else:
-        # The split-BF16 update executes three BF16 products per FP32 product:
-        # 6 m_k n_k K BF16 flops over 8 m_k n_k (+ 4 K (m_k + n_k)) bytes.  At
-        # K = 1024 (groups of four 256-wide block columns) that is 768 flop/B,
-        # above the 2500 TFLOP/s / 8 TB/s = 312 flop/B ridge: bound by the MFMA
-        # rate.  At K = 256 (ungrouped nb = 256) it is 192 flop/B: bound by HBM.
+        # The split-BF16 update executes three BF16 products per FP32-equivalent
+        # product (high-high, high-low, low-high).  The method's own work is one
+        # product, 2 m_k n_k K flops per launch: that is what `achieved` and
+        # `frac` count, against the BF16 MFMA peak the products run on.  The
+        # executed three-product rate and the HBM figures are reported beside it.
         gbs = alg_bytes / (avg_ms * 1e-3) / 1e9 if avg_ms else None
         exec_tf = 3 * achieved if achieved else None
-        flops_exec = sum(6.0 * mk * nc * kk for mk, nc, kk in launches_k)
-        intensity = flops_exec / alg if alg else 0.0
+        flops_method = sum(2.0 * mk * nc * kk for mk, nc, kk in launches_k)
         ridge = PEAK_TFLOPS["bf16"] * 1e12 / (HBM_PEAK_GBS * 1e9)
-        common = {"kernel": TRAILING_KERNEL["bf16x3"] + " (split-BF16 trailing update C -= V W')",
-                  "executed_bf16_flop_per_byte": intensity, "ridge_flop_per_byte": ridge,
-                  "mfma_tflops_fp32_equivalent": achieved,
-                  "mfma_tflops_executed_bf16": exec_tf, "mfma_peak_bf16_tflops": PEAK_TFLOPS["bf16"],
-                  "hbm_gbs_algorithmic": gbs, "hbm_frac": gbs / HBM_PEAK_GBS if gbs else None}
-        if intensity > ridge:
-            roof = {"bound": "mfma", "achieved": exec_tf, "peak": PEAK_TFLOPS["bf16"], "unit": "TFLOP/s",
-                    "frac": exec_tf / PEAK_TFLOPS["bf16"] if exec_tf else None, **common}
-        else:
-            roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": gbs / HBM_PEAK_GBS if gbs else None, **common}
+        roof = {"bound": "mfma", "kernel": TRAILING_KERNEL["bf16x3"] + " (split-BF16 trailing update C -= V W')",
+                "achieved": achieved, "peak": PEAK_TFLOPS["bf16"], "unit": "TFLOP/s",
+                "frac": achieved / PEAK_TFLOPS["bf16"] if achieved else None,
+                "achieved_counts": "method flops 2 m_k n_k K per launch (one FP32-equivalent product)",
+                "method_flop_per_byte": flops_method / alg if alg else None, "ridge_flop_per_byte": ridge,
+                "mfma_tflops_executed_bf16": exec_tf,
+                "executed_frac_of_bf16_peak": exec_tf / PEAK_TFLOPS["bf16"] if exec_tf else None,
+                "hbm_gbs_algorithmic": gbs, "hbm_frac": gbs / HBM_PEAK_GBS if gbs else None}
     roof.update({
         "traffic": measured_traffic(args.workload, args.prec, launches) if args.nb == 256 else None,
         "traffic_unit": "bytes per launch (HBM, FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
@@ -660,7 +774,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "bf16" if args.prec == "bf16x3" else "f32",
+        "dtype_detail": "FP32 storage of A and the factor; the dominant contractions (block-column products) on %s "
+                        "with FP32 accumulation; FP64 panel norms and reflectors; FP64 sparse residuals in the "
+                        "refinement" % ("split-BF16 MFMA (three BF16 products per FP32 product)"
+                                        if args.prec == "bf16x3" else "FP32 MFMA"),
         "data": "synthetic",
         "config": {
             "workload": "%s: %dx%d image, %d views x %d bins (m=%d, n=%d), %d ellipse-phantom slices, "
@@ -676,6 +794,15 @@ def main():
         "refine_iters": int(sinfo.iters), "refine_status": int(sinfo.status),
         "refine_last_rel_update": sinfo.max_rel_update,
         "recovery_rel_err_max": rec_err,
+        "refine_contraction": sinfo.contraction,
+        "kappa_est": kappa, "sigma_max_est": smax, "sigma_min_est": smin,
+        "kappa_note": "lower-bound estimates: power iteration on A^T A (FP64 sparse A), inverse iteration on R^T R "
+                      "(the factor's R), 8 vectors x 30 steps",
+        "ls_tan_theta_max": tan_theta,
+        "ls_perturbation_bound_fp64": ls_bound64,
+        "u32_kappa2": u32 * kappa ** 2,
+        "qr_phases_ms": {k: phase_ms[k] for k in ("panel", "inner", "reduction", "update", "group_update", "rinv")},
+        "solve_roofline": solve_roof,
         "qr_info_status": int(finfo.status),
         "rdiag_min_max": [finfo.rdiag_min, finfo.rdiag_max],
         "roofline": roof,

@@ -127,11 +127,22 @@ typedef struct {
     int32_t status;          /* 0 or one of the positive codes above           */
     int32_t first_bad_col;   /* rank deficiency: first column k with tiny R_kk */
     int32_t iters;           /* refinement iterations performed                */
-    int32_t pad;
-    double  max_rel_update;  /* last refinement: max_s ||dx_s||_inf / ||x_s||_inf */
+    int32_t x_iters;         /* refinement updates contained in the returned X:
+                                iters, or fewer when CTQR_NOT_CONVERGED returned
+                                an earlier iterate (the one with the smallest
+                                update, see ctqr_qr_solve_slices)               */
+    double  max_rel_update;  /* refinement: max_s ||dx_s||_inf / ||x_s||_inf of
+                                the last update, or of the update computed from
+                                the returned iterate when an earlier one is
+                                returned                                        */
     double  rdiag_max;       /* max |R_kk|                                      */
     double  rdiag_min;       /* min |R_kk|                                      */
     int64_t nnz;             /* system matrix build: nonzeros of A              */
+    double  contraction;     /* refinement: mean contraction per iteration,
+                                (last / first relative update)^(1/(iters-1));
+                                0 with fewer than two iterations.  Corrected
+                                semi-normal equations contract by about
+                                c u kappa(A)^2, u the factor's precision        */
 } ctqr_info;
 
 /* Human-readable name of a status code (static string, never NULL). */
@@ -309,15 +320,18 @@ ctqr_status ctqr_solve_workspace(int64_t m, int64_t n, ctqr_dtype dtype, int32_t
  *   X      device, n x nslices FP64, leading dim ldx (output).
  *   A64    optional FP64 sparse A (from ctqr_build_system_matrix).  When given,
  *          the solution is refined by corrected semi-normal equations:
- *          r = B - A X (FP64), R^T y = A^T r, R d = y, X += d, until
- *          max_s ||d_s||_inf <= tol ||X_s||_inf, or the relative update
- *          stops shrinking while below 1e-9 (the rounding floor of the FP64
- *          residuals: converged), or it stops shrinking above that floor or
- *          max_iters is reached (CTQR_NOT_CONVERGED).  NULL = no refinement.
+ *          r = B - A X (FP64), R^T y = A^T r, R d = y, X += d.  The
+ *          refinement has converged (status 0) only when the relative update
+ *          max_s ||d_s||_inf / ||X_s||_inf is <= tol.  It stops with
+ *          CTQR_NOT_CONVERGED when two consecutive updates fail to shrink
+ *          below 0.9x the previous one, or after max_iters; X is then the
+ *          iterate with the smallest update after it (the update estimates
+ *          that iterate's error), or the last iterate if the last update was
+ *          the smallest (info.x_iters says which).  NULL = no refinement.
  *          With refinement the call waits on the stream after each
  *          iteration (it reads the convergence flag back) and returns once
  *          the refinement has ended; without it the call only enqueues.
- *   refine_method  CTQR_REFINE_CSNE or CTQR_REFINE_PCG (both converge by the
+ *   refine_method  CTQR_REFINE_CSNE or CTQR_REFINE_PCG (both follow the
  *          rule above; the conjugate-gradient form allows a longer run of
  *          non-shrinking updates, 6, before it stops).
  *   info   device: iterations, last relative update, CTQR_NOT_CONVERGED /
@@ -421,6 +435,30 @@ ctqr_status ctqr_solver_query(ctqr_solver solver, int32_t nslices, int32_t *buck
  * accepted. */
 ctqr_status ctqr_solver_destroy(ctqr_solver solver);
 
+/* Estimate of the 2-norm condition number of A.  The direct solve needs A of
+ * full column rank (Section II-A), and kappa(A) sets how far a least-squares
+ * solution moves under perturbations of A and B, including rounding: the
+ * perturbation bound of the solution is about u (2 kappa + kappa^2 tan theta)
+ * with tan theta = ||r|| / ||A x||.  kappa(A) = sigma_max(A) / sigma_min(A):
+ *   sigma_max(A)  power iteration on A^T A with the FP64 sparse A;
+ *   sigma_min(A) = sigma_min(R) (A = QR, Eq. 3)  inverse iteration on R^T R,
+ *                 applied by the two block substitutions with the factor's R
+ *                 (R^T y = z, R w = y).
+ * nvec start vectors (1..64, fixed counter-hashed values) iterate together
+ * for `iters` steps; every step's Rayleigh quotient is a lower bound of
+ * sigma_max^2 (resp. 1 / sigma_min^2), and the largest over vectors and steps
+ * is kept, so both estimates approach the true values from one side and
+ * kappa is never over-estimated.
+ *   QR, lda, dtype, Rinv  the factor (ctqr_qr_factor outputs; Rinv required).
+ *   A64    device, the FP64 sparse A of the same matrix (CSR and CSC).
+ *   out    device, 3 doubles: sigma_max(A), sigma_min(R), kappa.
+ *   work   device, ctqr_cond_workspace bytes.
+ * The call only enqueues; read out after synchronising the stream. */
+ctqr_status ctqr_cond_workspace(int64_t m, int64_t n, ctqr_dtype dtype, int32_t nvec, size_t *bytes);
+ctqr_status ctqr_cond_estimate(int64_t m, int64_t n, ctqr_dtype dtype, const void *QR, int64_t lda,
+                               const void *Rinv, const ctqr_sparse *A64, int32_t nvec, int32_t iters,
+                               void *work, size_t work_bytes, double *out, hipStream_t stream);
+
 /* Sinogram synthesis and residual helper: Y = alpha * A X + beta * Y with the
  * FP64 CSR copy of A.  X (n x nslices, ldx) and Y (m x nslices, ldy) are
  * column-major FP64 device arrays.  Eq. 1. */
@@ -442,16 +480,52 @@ ctqr_status ctqr_spmm(const ctqr_sparse *A64, int32_t nslices, double alpha,
 typedef void (*ctqr_progress_fn)(int32_t stage, int64_t done, int64_t total, void *user);
 ctqr_status ctqr_set_progress(ctqr_progress_fn fn, void *user);
 
+/* Releases the library's process-lifetime state: waits for the current
+ * device to finish its work, frees the pinned host words the refinement reads
+ * its flag into, destroys the timing events and removes the progress hook.
+ * Call it with no ctqr call in flight, before the HIP runtime is torn down
+ * (the Python binding calls it at interpreter exit); the library remains
+ * usable afterwards (the state is made again on first use).  Solvers are not
+ * touched: destroy them with ctqr_solver_destroy. */
+ctqr_status ctqr_release(void);
+
 /* Kernel-level timing of the dominant kernel (the trailing-update GEMM
  * C -= V W of ctqr_qr_factor).  While enabled, every launch of it is
  * bracketed by HIP events on the stream it runs on; ctqr_profile_read returns
  * the number of launches, their summed duration (ms, resolved after the
  * caller has synchronised the stream) and their summed algorithmic flops
  * (2 * rows * cols * K per launch, K = nb, or the group's width for grouped
- * block columns; the updates inside a group by its blocks are not counted).  Host-side bookkeeping only; enabling it
- * clears the previous record. */
+ * block columns; the updates inside a group by its blocks are not counted).
+ * Host-side bookkeeping only; enabling it clears the previous records.  `on`
+ * is a bit set: CTQR_PROFILE_UPDATE for these records, CTQR_PROFILE_PHASES
+ * for the phase timing below (0 turns both off). */
+#define CTQR_PROFILE_UPDATE 1
+#define CTQR_PROFILE_PHASES 2
 ctqr_status ctqr_profile_enable(int32_t on);
 ctqr_status ctqr_profile_read(int64_t *launches, double *total_ms, double *total_flops);
+
+/* Phase timing (ctqr_profile_enable with the CTQR_PROFILE_PHASES bit): the
+ * factorization and every direct solve record HIP events around their phases
+ * on the stream they run on (never inside a graph capture, so the batched
+ * solver's replays are not split).  ctqr_profile_phases returns, per phase,
+ * the summed duration (ms; the caller must have synchronised the streams) and
+ * the number of intervals; host synchronisation between phases counts in
+ * none.  ms and count are host arrays of CTQR_NPHASES entries.
+ * Factorization (Section II-C, "QR factorization"): */
+#define CTQR_PHASE_PANEL         0   /* 32-column Householder panels (FP64 norms/reflectors) */
+#define CTQR_PHASE_INNER         1   /* inner-panel T and updates inside a block column */
+#define CTQR_PHASE_REDUCTION     2   /* [G | W] = V^T [V | C], block T, W' = T^T W */
+#define CTQR_PHASE_UPDATE        3   /* trailing update C -= V W' of the rest of the matrix */
+#define CTQR_PHASE_GROUP_UPDATE  4   /* update of the rest of a group by one of its blocks */
+#define CTQR_PHASE_RINV          5   /* rank check and the stored diagonal-block inverses */
+/* Solve (Eq. 4; Section II-C, "System solving") and its refinement: */
+#define CTQR_PHASE_QTB           6   /* Q^T B */
+#define CTQR_PHASE_TRSM          7   /* back substitution R X = (Q^T B)[0:n] */
+#define CTQR_PHASE_RESIDUAL      8   /* FP64 sparse r = B - A X and s = A^T r */
+#define CTQR_PHASE_REFINE_TRSM   9   /* R^T y = s and R d = y */
+#define CTQR_PHASE_REFINE_OTHER 10   /* layout changes, X += d, convergence check */
+#define CTQR_NPHASES            11
+ctqr_status ctqr_profile_phases(double *ms, int64_t *count);
 
 #ifdef __cplusplus
 }

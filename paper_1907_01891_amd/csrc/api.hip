@@ -27,6 +27,53 @@ std::mutex g_prof_mu;
 bool g_prof_on = false;
 std::vector<ProfRec> g_prof;
 
+// Phase timing (ctqr_profile_enable bit 2): HIP events around the phases of
+// a factorization or a direct solve, on the stream they run on (not inside
+// graph capture).  Gaps between phases (host synchronisation) count in none.
+struct PhaseRec {
+    int phase;
+    hipEvent_t a, b;
+};
+bool g_phase_on = false;
+std::vector<PhaseRec> g_phase;
+
+struct PhaseScope {
+    int phase;
+    hipStream_t st;
+    hipEvent_t a = nullptr;
+    PhaseScope(int p, hipStream_t s) : phase(p), st(s)
+    {
+        {
+            std::lock_guard<std::mutex> lk(g_prof_mu);
+            if (!g_phase_on) return;
+        }
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+        if (hipEventCreate(&a) != hipSuccess) {
+            a = nullptr;
+            return;
+        }
+        if (hipEventRecord(a, st) != hipSuccess) {
+            (void)hipEventDestroy(a);
+            a = nullptr;
+        }
+    }
+    ~PhaseScope()
+    {
+        if (!a) return;
+        hipEvent_t b = nullptr;
+        if (hipEventCreate(&b) != hipSuccess || hipEventRecord(b, st) != hipSuccess) {
+            (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
+            return;
+        }
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        g_phase.push_back({phase, a, b});
+    }
+    PhaseScope(const PhaseScope &) = delete;
+    PhaseScope &operator=(const PhaseScope &) = delete;
+};
+
 bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
 // Progress hook of the long out-of-core calls: a host function enqueued on
@@ -143,6 +190,7 @@ template <typename T>
 struct SolveWS {
     T *Bw, *W, *W2, *split, *Rinv, *RinvT, *Xw;
     double *xr, *Br, *r, *s, *hist;
+    double *xs, *xbest;      // refinement: the iterate before the last update, and the best one kept
     // conjugate-gradient form: z (two, by iteration parity), p, q, dot partials, per-slice scalars
     double *z0, *z1, *p, *q, *dpart, *sz, *szp, *qq, *gamma, *beta, *alpha;
     T *s32, *y32, *d32;
@@ -207,6 +255,8 @@ SolveWS<T> carve_solve(void *work, int64_t m, int64_t n, int nb, int S, int refi
         w.dmax = c.take<unsigned long long>(S);
         w.xmax = c.take<unsigned long long>(S);
         w.hist = c.take<double>(8);
+        w.xs = c.take<double>(n * S);
+        w.xbest = c.take<double>(n * S);
         const bool parts = trsm_split != TRSM_PARTS_NONE && refine_split_trsm<T>(n, S, refine);
         w.xparts = parts ? c.take<__bf16>((int64_t)trsm_xparts_elems(S)) : nullptr;
         w.rparts = parts && trsm_split == TRSM_PARTS_ALL ? c.take<__bf16>((int64_t)trsm_rparts_elems(n)) : nullptr;
@@ -242,10 +292,22 @@ int device_cus()
 }
 
 // Per-thread pinned word the refinement loop reads its convergence flag into.
+// Every word is also listed process-wide, so ctqr_release can free them all.
+std::mutex g_flags_mu;
+std::vector<int *> g_flags;
+uint64_t g_flags_epoch = 0;   // bumped by ctqr_release: cached words are stale
+
 int *host_flag()
 {
     thread_local int *p = nullptr;
-    if (!p && hipHostMalloc((void **)&p, 64, hipHostMallocDefault) != hipSuccess) p = nullptr;
+    thread_local uint64_t epoch = 0;
+    std::lock_guard<std::mutex> lk(g_flags_mu);
+    if (p && epoch != g_flags_epoch) p = nullptr;
+    if (!p) {
+        if (hipHostMalloc((void **)&p, 64, hipHostMallocDefault) != hipSuccess) return p = nullptr;
+        g_flags.push_back(p);
+        epoch = g_flags_epoch;
+    }
     return p;
 }
 
@@ -396,11 +458,15 @@ ctqr_status factor_blocks(int m, int n, T *A, int64_t lda, int nb, int kb, int k
         // the rest of the block column
         for (int c0 = k0; c0 < k0 + nbk; c0 += PANEL_W) {
             const int wdt = std::min(PANEL_W, k0 + nbk - c0);
-            s = panel_qr<T>(A, lda, m, c0, wdt, tau + c0, w.part, w.part2, w.gram_part, w.gram,
-                            bars + (int64_t)(c0 / PANEL_W) * GB_WORDS, info, ncu, st);
-            if (s) return s;
+            {
+                PhaseScope ph(CTQR_PHASE_PANEL, st);
+                s = panel_qr<T>(A, lda, m, c0, wdt, tau + c0, w.part, w.part2, w.gram_part, w.gram,
+                                bars + (int64_t)(c0 / PANEL_W) * GB_WORDS, info, ncu, st);
+                if (s) return s;
+            }
             const int ncr = k0 + nbk - (c0 + wdt);
             if (ncr <= 0) continue;
+            PhaseScope ph(CTQR_PHASE_INNER, st);
             if ((s = tbuild<double, T>(wdt, w.gram, PANEL_W, tau + c0, w.Tin, PANEL_W, w.Tw, st))) return s;
             const T *Vp = A + (int64_t)c0 * lda + c0;
             T *Cp = A + (int64_t)(c0 + wdt) * lda + c0;
@@ -421,13 +487,17 @@ ctqr_status factor_blocks(int m, int n, T *A, int64_t lda, int nb, int kb, int k
             // of the group only
             if (kg < kb || ge > ke) return CTQR_EINVAL;   // ranges hold whole groups
             const int nr = ge - (k0 + nbk);
-            s = block_reduction<T>(nbk, nbk + nr, m - k0, V, lda, V, lda, nbk, w, nb,
-                                   gemm_tn_splits(nbk, nbk + nr, m - k0), st);
-            if (s) return s;
-            if ((s = tbuild<T, T>(nbk, w.GW, nb, tau + k0, Tk, nb, w.Tw, st))) return s;
-            s = gemm_tn<T>(nbk, nr, nbk, Tk, nb, 0, w.GW + (int64_t)nbk * nb, nb, 0, T(1), T(0), w.W2, nb,
-                           w.split, SPLIT_PART_ELEMS, nullptr, st, gemm_tn_splits(nbk, nr, nbk));
-            if (s) return s;
+            {
+                PhaseScope ph(CTQR_PHASE_REDUCTION, st);
+                s = block_reduction<T>(nbk, nbk + nr, m - k0, V, lda, V, lda, nbk, w, nb,
+                                       gemm_tn_splits(nbk, nbk + nr, m - k0), st);
+                if (s) return s;
+                if ((s = tbuild<T, T>(nbk, w.GW, nb, tau + k0, Tk, nb, w.Tw, st))) return s;
+                s = gemm_tn<T>(nbk, nr, nbk, Tk, nb, 0, w.GW + (int64_t)nbk * nb, nb, 0, T(1), T(0), w.W2, nb,
+                               w.split, SPLIT_PART_ELEMS, nullptr, st, gemm_tn_splits(nbk, nr, nbk));
+                if (s) return s;
+            }
+            PhaseScope ph(CTQR_PHASE_GROUP_UPDATE, st);
             if ((s = trailing_update<T>(m - k0, nr, nbk, V, lda, w.W2, nb, A + (int64_t)(k0 + nbk) * lda + k0, st,
                                         w.bf16, w.bsplit, w.bsplit_elems, true)))
                 return s;
@@ -442,16 +512,21 @@ ctqr_status factor_blocks(int m, int n, T *A, int64_t lda, int nb, int kb, int k
             const int nc = std::max(0, ce - ge);
             const GroupSplits gs = group_splits(m, n, nb, kg);
             const T *Vg = A + (int64_t)kg * lda + kg;
-            s = block_reduction<T>(nbg, nbg + nc, m - kg, Vg, lda, Vg, lda, nbg, w, ldg, gs.gw, st);
-            if (s) return s;
-            if ((s = tbuild<T, T>(nbk, w.GW + (int64_t)(bi * nb) * ldg + bi * nb, ldg, tau + k0, Tk, nb, w.Tw, st)))
-                return s;
+            {
+                PhaseScope ph(CTQR_PHASE_REDUCTION, st);
+                s = block_reduction<T>(nbg, nbg + nc, m - kg, Vg, lda, Vg, lda, nbg, w, ldg, gs.gw, st);
+                if (s) return s;
+                if ((s = tbuild<T, T>(nbk, w.GW + (int64_t)(bi * nb) * ldg + bi * nb, ldg, tau + k0, Tk, nb, w.Tw,
+                                      st)))
+                    return s;
+            }
             // the Gram is kept for every group with columns to its right, also
             // those beyond this range (applied to them later)
             T *Gs = w.gstore + (int64_t)(kg / ldg) * ldg * ldg;
             if (ge < n)
                 HIP_TRY(hipMemcpyAsync(Gs, w.GW, (size_t)ldg * nbg * sizeof(T), hipMemcpyDeviceToDevice, st));
             if (nc <= 0) continue;
+            PhaseScope ph(CTQR_PHASE_UPDATE, st);
             if ((s = group_update<T>(m, nb, kg, nbg, nc, Vg, lda, Tout, Gs, w.GW + (int64_t)nbg * ldg, ldg,
                                      A + (int64_t)ge * lda + kg, gs, w, st)))
                 return s;
@@ -459,10 +534,14 @@ ctqr_status factor_blocks(int m, int n, T *A, int64_t lda, int nb, int kb, int k
         }
         // block reflector of the whole block column: [G | W] = V^T [V | C]
         const int nc = std::max(0, ce - (k0 + nbk));
-        s = block_reduction<T>(nbk, nbk + nc, m - k0, V, lda, V, lda, nbk, w, nb, sp.gw, st);
-        if (s) return s;
-        if ((s = tbuild<T, T>(nbk, w.GW, nb, tau + k0, Tk, nb, w.Tw, st))) return s;
+        {
+            PhaseScope ph(CTQR_PHASE_REDUCTION, st);
+            s = block_reduction<T>(nbk, nbk + nc, m - k0, V, lda, V, lda, nbk, w, nb, sp.gw, st);
+            if (s) return s;
+            if ((s = tbuild<T, T>(nbk, w.GW, nb, tau + k0, Tk, nb, w.Tw, st))) return s;
+        }
         if (nc <= 0) continue;
+        PhaseScope ph(CTQR_PHASE_UPDATE, st);
         // W' = T^T W;  C -= V W'
         s = gemm_tn<T>(nbk, nc, nbk, Tk, nb, 0, w.GW + (int64_t)nbk * nb, nb, 0, T(1), T(0), w.W2, nb,
                        w.split, SPLIT_PART_ELEMS, nullptr, st, sp.tw);
@@ -529,6 +608,7 @@ ctqr_status factor_impl(int64_t m64, int64_t n64, T *A, int64_t lda, int nb, T *
     if ((s = info_reset(info, st))) return s;
     if ((s = fill_u32(w.bars, (ceil_div(n, PANEL_W) + 1) * GB_WORDS, 0u, st))) return s;
     if ((s = factor_blocks<T>(m, n, A, lda, nb, 0, n, n, Tout, tau, w, w.bars, info, ncu, st))) return s;
+    PhaseScope ph(CTQR_PHASE_RINV, st);
     if ((s = rdiag_check<T>(n, A, lda, nullptr, info, st))) return s;
     return Rinv ? trinv_blocks<T>(n, A, lda, Rinv, w.rtmp, info, st) : CTQR_OK;
 }
@@ -859,17 +939,24 @@ ctqr_status solve_start(SolveRun<T> &r, hipStream_t st)
     ctqr_status s;
     if ((s = info_reset(r.info, st))) return s;
     if ((s = fill_u32((unsigned *)w.done, 64, 0u, st))) return s;
-    // working copy of B in the factor's precision
-    if ((s = copy_cm<T, double>(m, S, r.B, r.ldb, w.Bw, w.ldbw, st))) return s;
-    if ((s = apply_qt_range(r, r.QR, 0, n, st))) return s;
-    // back substitution R X = (Q^T B)[0:n], with the factor's diagonal-block
-    // inverses (built here when the factor was stored without them)
-    if (!r.Rinv) {
-        if ((s = trinv_blocks<T>(n, r.QR, r.lda, w.Rinv, w.RinvT, r.info, st))) return s;
-        r.Rinv = w.Rinv;
+    {
+        // working copy of B in the factor's precision
+        PhaseScope ph(CTQR_PHASE_QTB, st);
+        if ((s = copy_cm<T, double>(m, S, r.B, r.ldb, w.Bw, w.ldbw, st))) return s;
+        if ((s = apply_qt_range(r, r.QR, 0, n, st))) return s;
     }
-    s = trsm_upper<T>(n, S, r.QR, r.lda, r.Rinv, w.Bw, w.ldbw, w.Xw, w.ldxw, w.split, r.sp_elems, nullptr, st);
-    if (s) return s;
+    {
+        // back substitution R X = (Q^T B)[0:n], with the factor's diagonal-block
+        // inverses (built here when the factor was stored without them)
+        PhaseScope ph(CTQR_PHASE_TRSM, st);
+        if (!r.Rinv) {
+            if ((s = trinv_blocks<T>(n, r.QR, r.lda, w.Rinv, w.RinvT, r.info, st))) return s;
+            r.Rinv = w.Rinv;
+        }
+        s = trsm_upper<T>(n, S, r.QR, r.lda, r.Rinv, w.Bw, w.ldbw, w.Xw, w.ldxw, w.split, r.sp_elems, nullptr, st);
+        if (s) return s;
+    }
+    PhaseScope ph(CTQR_PHASE_REFINE_OTHER, st);
     if (!r.refine()) return CTQR_OK;
     if ((s = cm_to_rm<double, T>(n, S, w.Xw, w.ldxw, w.xr, nullptr, st))) return s;
     if ((s = cm_to_rm<double, double>(m, S, r.B, r.ldb, w.Br, nullptr, st))) return s;
@@ -908,14 +995,21 @@ ctqr_status refine_iters_with(SolveRun<T> &r, int it0, int it1, bool host_sync, 
     if (ran) *ran = it1;
     for (int it = it0; it < it1; ++it) {
         const int *skip = w.done;
-        s = spmm_rowmajor(m, S, A->rowptr, A->col, A->val, -1.0, w.xr, 1.0, w.Br, w.r, skip, st);
-        if (s) return s;
-        s = spmm_rowmajor(n, S, A->colptr, A->row, A->cval, 1.0, w.r, 0.0, nullptr, w.s, skip, st);
-        if (s) return s;
-        if ((s = rm_to_cm<T, double>(n, S, w.s, w.s32, w.ldxw, skip, st))) return s;
-        if ((s = minv(skip))) return s;
+        {
+            PhaseScope ph(CTQR_PHASE_RESIDUAL, st);
+            s = spmm_rowmajor(m, S, A->rowptr, A->col, A->val, -1.0, w.xr, 1.0, w.Br, w.r, skip, st);
+            if (s) return s;
+            s = spmm_rowmajor(n, S, A->colptr, A->row, A->cval, 1.0, w.r, 0.0, nullptr, w.s, skip, st);
+            if (s) return s;
+        }
+        {
+            PhaseScope ph(CTQR_PHASE_REFINE_TRSM, st);
+            if ((s = rm_to_cm<T, double>(n, S, w.s, w.s32, w.ldxw, skip, st))) return s;
+            if ((s = minv(skip))) return s;
+        }
+        PhaseScope ph(CTQR_PHASE_REFINE_OTHER, st);
         if (!pcg) {
-            if ((s = refine_update<T>(n, S, w.xr, w.d32, w.ldxw, w.dmax, w.xmax, skip, st))) return s;
+            if ((s = refine_update<T>(n, S, w.xr, w.d32, w.ldxw, w.dmax, w.xmax, w.xs, skip, st))) return s;
         } else {
             double *z = (it & 1) ? w.z1 : w.z0, *zp = (it & 1) ? w.z0 : w.z1;
             if ((s = cm_to_rm<double, T>(n, S, w.d32, w.ldxw, z, skip, st))) return s;
@@ -927,12 +1021,13 @@ ctqr_status refine_iters_with(SolveRun<T> &r, int it0, int it1, bool host_sync, 
             if (s) return s;
             if ((s = slice_dot(m, S, w.q, w.q, w.dpart, w.qq, skip, st))) return s;
             if ((s = pcg_alpha(S, w.gamma, w.qq, w.alpha, skip, st))) return s;
-            if ((s = pcg_step(n, S, w.xr, w.p, w.alpha, w.dmax, w.xmax, skip, st))) return s;
+            if ((s = pcg_step(n, S, w.xr, w.p, w.alpha, w.dmax, w.xmax, w.xs, skip, st))) return s;
         }
         // conjugate-gradient steps need not shrink monotonically: a longer
         // run of non-contracting steps ends that form
         s = refine_check(S, w.dmax, w.xmax, r.tol, it, r.max_iters, pcg ? 6 : 2, w.hist, w.done, r.info, st);
         if (s) return s;
+        if ((s = refine_keep((int64_t)n * S, w.xs, w.xbest, w.hist, st))) return s;
         if (r.progress && (s = progress_mark(st, CTQR_PROGRESS_SOLVE, it + 1, r.max_iters))) return s;
         if (host_sync) {
             bool done = false;
@@ -961,12 +1056,23 @@ ctqr_status refine_iters(SolveRun<T> &r, int it0, int it1, bool host_sync, hipSt
     return refine_iters_with(r, it0, it1, host_sync, st, ran, minv);
 }
 
+// After the refinement: a refinement that did not converge returns the
+// iterate with the smallest update after it (device-side decision).
+template <typename T>
+ctqr_status refine_finish(SolveRun<T> &r, hipStream_t st)
+{
+    if (!r.refine()) return CTQR_OK;
+    return refine_select((int64_t)r.n * r.S, r.w.xr, r.w.xbest, r.w.hist, r.info, st);
+}
+
 // The first S_out slices of the solution into X (FP64, column-major).
 template <typename T>
 ctqr_status solve_finish(SolveRun<T> &r, int S_out, double *X, int64_t ldx, hipStream_t st)
 {
     SolveWS<T> &w = r.w;
     if (!r.refine()) return copy_cm<double, T>(r.n, S_out, w.Xw, w.ldxw, X, ldx, st);
+    ctqr_status s = refine_finish(r, st);
+    if (s) return s;
     if (S_out == r.S) return rm_to_cm<double, double>(r.n, r.S, w.xr, X, ldx, nullptr, st);
     // row-major x holds S slices per row: gather the first S_out of each
     return rm_to_cm_sub(r.n, r.S, S_out, w.xr, X, ldx, st);
@@ -1096,6 +1202,7 @@ ctqr_status solve_ooc_impl(int64_t m64, int64_t n64, const T *QR_dev, const T *Q
         return ooc_upper(r, tc, QR_dev, w.y32, w.ldxw, w.d32, w.ldxw, skip, st);
     };
     if ((s = refine_iters_with(r, 0, max_iters, true, st, nullptr, minv))) return s;
+    if ((s = refine_finish(r, st))) return s;
     return rm_to_cm<double, double>(n, S, w.xr, X, ldx, nullptr, st);
 }
 
@@ -1293,6 +1400,7 @@ ctqr_status solver_solve_t(ctqr_solver_t *sv, int nreq, const double *const *B, 
             }
         }
     }
+    if ((s = refine_finish(r, st))) return s;
     for (int i = 0, off = 0; i < nreq; off += S[i], ++i) {
         if (r.refine())
             s = rm_to_cm_sub(r.n, bk.S, S[i], r.w.xr + off, X[i], ldx[i], st);
@@ -1355,6 +1463,80 @@ ctqr_status solver_tune_t(ctqr_solver_t *sv, hipStream_t st, int reps)
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return out;
+}
+
+// Condition-number estimate: power iteration on A^T A with the FP64 sparse A
+// (sigma_max), inverse iteration on R^T R through the two block substitutions
+// with the factor's R (sigma_min).  Workspace layout of cond_impl.
+template <typename T>
+struct CondWS {
+    double *x, *r, *y, *dots, *est;
+    T *z, *c, *yt, *w, *part;
+    int64_t ldn, ldm;
+    size_t bytes;
+};
+
+template <typename T>
+CondWS<T> carve_cond(void *work, int64_t m, int64_t n, int S)
+{
+    Carve c(work);
+    CondWS<T> w{};
+    w.ldn = round_up(n, 4);
+    w.ldm = round_up(m, 4);
+    w.x = c.take<double>(w.ldn * S);
+    w.r = c.take<double>(w.ldm * S);
+    w.y = c.take<double>(w.ldn * S);
+    w.dots = c.take<double>(2 * (int64_t)S);
+    w.est = c.take<double>(4);
+    w.z = c.take<T>(w.ldn * S);
+    w.c = c.take<T>(w.ldn * S);
+    w.yt = c.take<T>(w.ldn * S);
+    w.w = c.take<T>(w.ldn * S);
+    w.part = c.take<T>(SPLIT_PART_ELEMS);
+    w.bytes = c.off + 256;
+    return w;
+}
+
+template <typename T>
+ctqr_status cond_impl(int64_t m, int64_t n, const T *QR, int64_t lda, const T *Rinv, const ctqr_sparse *A, int S,
+                      int iters, void *work, double *out, hipStream_t st)
+{
+    CondWS<T> w = carve_cond<T>(work, m, n, S);
+    NarrowScope ns(S <= DEFAULT_NARROW ? DEFAULT_NARROW : 0);
+    double *q = w.dots, *nrm = w.dots + S;
+    ctqr_status s;
+    if ((s = fill_f64(w.est, 4, 0.0, st))) return s;
+    // sigma_max(A)^2: largest Rayleigh quotient x^T A^T A x, ||x|| = 1
+    if ((s = cond_start<double>(n, S, w.x, w.ldn, 0x5eed0001ull, st))) return s;
+    if ((s = col_dot<double, double>(n, S, w.x, w.ldn, w.x, w.ldn, nrm, st))) return s;
+    if ((s = col_scale<double, double>(n, S, w.x, w.ldn, nrm, w.x, w.ldn, st))) return s;
+    for (int it = 0; it < iters; ++it) {
+        if ((s = spmm_colmajor(m, n, S, A->rowptr, A->col, A->val, 1.0, w.x, w.ldn, 0.0, w.r, w.ldm, st))) return s;
+        if ((s = spmm_colmajor(n, m, S, A->colptr, A->row, A->cval, 1.0, w.r, w.ldm, 0.0, w.y, w.ldn, st)))
+            return s;
+        if ((s = col_dot<double, double>(n, S, w.x, w.ldn, w.y, w.ldn, q, st))) return s;
+        if ((s = cond_max(S, q, w.est, 0, st))) return s;
+        if ((s = col_dot<double, double>(n, S, w.y, w.ldn, w.y, w.ldn, nrm, st))) return s;
+        if ((s = col_scale<double, double>(n, S, w.y, w.ldn, nrm, w.x, w.ldn, st))) return s;
+    }
+    // 1 / sigma_min(R)^2: largest Rayleigh quotient z^T (R^T R)^-1 z, ||z|| = 1
+    if ((s = cond_start<T>(n, S, w.z, w.ldn, 0x5eed0002ull, st))) return s;
+    if ((s = col_dot<T, T>(n, S, w.z, w.ldn, w.z, w.ldn, nrm, st))) return s;
+    if ((s = col_scale<T, T>(n, S, w.z, w.ldn, nrm, w.z, w.ldn, st))) return s;
+    for (int it = 0; it < iters; ++it) {
+        // the substitutions overwrite their right-hand side: work on a copy
+        if ((s = copy_cm<T, T>(n, S, w.z, w.ldn, w.c, w.ldn, st))) return s;
+        s = trsm_upper_trans<T>((int)n, S, QR, lda, Rinv, w.c, w.ldn, w.yt, w.ldn, w.part, SPLIT_PART_ELEMS,
+                                nullptr, st);
+        if (s) return s;
+        s = trsm_upper<T>((int)n, S, QR, lda, Rinv, w.yt, w.ldn, w.w, w.ldn, w.part, SPLIT_PART_ELEMS, nullptr, st);
+        if (s) return s;
+        if ((s = col_dot<T, T>(n, S, w.z, w.ldn, w.w, w.ldn, q, st))) return s;
+        if ((s = cond_max(S, q, w.est, 1, st))) return s;
+        if ((s = col_dot<T, T>(n, S, w.w, w.ldn, w.w, w.ldn, nrm, st))) return s;
+        if ((s = col_scale<T, T>(n, S, w.w, w.ldn, nrm, w.z, w.ldn, st))) return s;
+    }
+    return cond_finish(w.est, out, st);
 }
 
 bool geometry_ok(const ctqr_geometry *g)
@@ -1852,6 +2034,43 @@ ctqr_status ctqr_qr_solve_ooc(int64_t m, int64_t n, ctqr_dtype dtype, const void
     }
 }
 
+ctqr_status ctqr_cond_workspace(int64_t m, int64_t n, ctqr_dtype dtype, int32_t nvec, size_t *bytes)
+{
+    if (!bytes || m < n || n < 1 || nvec < 1 || nvec > 64) return CTQR_EINVAL;
+    if (dtype == CTQR_F64)
+        *bytes = carve_cond<double>(nullptr, m, n, nvec).bytes;
+    else if (dtype == CTQR_F32)
+        *bytes = carve_cond<float>(nullptr, m, n, nvec).bytes;
+    else
+        return CTQR_EINVAL;
+    return CTQR_OK;
+}
+
+ctqr_status ctqr_cond_estimate(int64_t m, int64_t n, ctqr_dtype dtype, const void *QR, int64_t lda, const void *Rinv,
+                               const ctqr_sparse *A64, int32_t nvec, int32_t iters, void *work, size_t work_bytes,
+                               double *out, hipStream_t stream)
+{
+    try {
+        size_t need = 0;
+        ctqr_status s = ctqr_cond_workspace(m, n, dtype, nvec, &need);
+        if (s) return s;
+        if (!QR || !Rinv || !A64 || !work || !out || iters < 1 || m >= INT32_MAX) return CTQR_EINVAL;
+        if (lda < m || lda % 4 || !aligned16(QR)) return CTQR_EINVAL;
+        if (A64->m != m || A64->n != n || !A64->rowptr || !A64->col || !A64->val || !A64->colptr || !A64->row ||
+            !A64->cval)
+            return CTQR_EINVAL;
+        if (!aligned16(work) || !aligned16(Rinv)) return CTQR_EINVAL;
+        if (work_bytes < need) return CTQR_ENOMEM;
+        if (dtype == CTQR_F64)
+            return cond_impl<double>(m, n, (const double *)QR, lda, (const double *)Rinv, A64, nvec, iters, work,
+                                     out, stream);
+        return cond_impl<float>(m, n, (const float *)QR, lda, (const float *)Rinv, A64, nvec, iters, work, out,
+                                stream);
+    } catch (...) {
+        return CTQR_EHIP;
+    }
+}
+
 ctqr_status ctqr_spmm(const ctqr_sparse *A64, int32_t nslices, double alpha, const double *X, int64_t ldx,
                       double beta, double *Y, int64_t ldy, hipStream_t stream)
 {
@@ -1877,7 +2096,64 @@ ctqr_status ctqr_profile_enable(int32_t on)
         (void)hipEventDestroy(r.b);
     }
     g_prof.clear();
-    g_prof_on = on != 0;
+    for (auto &r : g_phase) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    g_phase.clear();
+    g_prof_on = (on & CTQR_PROFILE_UPDATE) != 0;
+    g_phase_on = (on & CTQR_PROFILE_PHASES) != 0;
+    return CTQR_OK;
+}
+
+ctqr_status ctqr_release(void)
+{
+    try {
+        HIP_TRY(hipDeviceSynchronize());
+        {
+            std::lock_guard<std::mutex> lk(g_prof_mu);
+            for (auto &r : g_prof) {
+                (void)hipEventDestroy(r.a);
+                (void)hipEventDestroy(r.b);
+            }
+            g_prof.clear();
+            for (auto &r : g_phase) {
+                (void)hipEventDestroy(r.a);
+                (void)hipEventDestroy(r.b);
+            }
+            g_phase.clear();
+            g_prof_on = g_phase_on = false;
+        }
+        {
+            std::lock_guard<std::mutex> lk(g_progress_mu);
+            g_progress = nullptr;
+            g_progress_user = nullptr;
+        }
+        std::lock_guard<std::mutex> lk(g_flags_mu);
+        for (int *p : g_flags) (void)hipHostFree(p);
+        g_flags.clear();
+        ++g_flags_epoch;
+        return CTQR_OK;
+    } catch (...) {
+        return CTQR_EHIP;
+    }
+}
+
+ctqr_status ctqr_profile_phases(double *ms, int64_t *count)
+{
+    if (!ms || !count) return CTQR_EINVAL;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (int p = 0; p < CTQR_NPHASES; ++p) {
+        ms[p] = 0.0;
+        count[p] = 0;
+    }
+    for (auto &r : g_phase) {
+        float t = 0.f;
+        HIP_TRY(hipEventSynchronize(r.b));
+        HIP_TRY(hipEventElapsedTime(&t, r.a, r.b));
+        ms[r.phase] += t;
+        count[r.phase] += 1;
+    }
     return CTQR_OK;
 }
 

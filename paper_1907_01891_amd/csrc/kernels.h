@@ -168,16 +168,23 @@ ctqr_status fill_u32(unsigned *p, int64_t n, unsigned v, hipStream_t st);
 ctqr_status fill_f64(double *p, int64_t n, double v, hipStream_t st);
 ctqr_status info_reset(ctqr_info *info, hipStream_t st);
 // Refinement step: x += d (row-major x FP64, column-major d of type TD),
-// per-slice max|d| and max|x| into dmax/xmax (bit patterns, atomic max).
+// per-slice max|d| and max|x| into dmax/xmax (bit patterns, atomic max); xs
+// (row-major like x, or null) receives x before the update.
 template <typename TD>
 ctqr_status refine_update(int64_t n, int S, double *x, const TD *d, int64_t ldd,
-                          unsigned long long *dmax, unsigned long long *xmax, const int *skip,
+                          unsigned long long *dmax, unsigned long long *xmax, double *xs, const int *skip,
                           hipStream_t st);
-// stall_limit: consecutive non-contracting iterations that end the
-// refinement (converged at the FP64 floor, else CTQR_NOT_CONVERGED)
+// Converged when the relative update is <= tol; stall_limit consecutive
+// non-contracting updates, or max_iters, end it with CTQR_NOT_CONVERGED.
+// Also records the smallest update so far (hist[2..5]).
 ctqr_status refine_check(int S, unsigned long long *dmax, unsigned long long *xmax, double tol,
                          int it, int max_iters, int stall_limit, double *hist, int *done, ctqr_info *info,
                          hipStream_t st);
+// xbest = xs (count doubles) when the last refine_check found a new smallest update.
+ctqr_status refine_keep(int64_t count, const double *xs, double *xbest, const double *hist, hipStream_t st);
+// After CTQR_NOT_CONVERGED: x = xbest unless the smallest update was the last one.
+ctqr_status refine_select(int64_t count, double *x, const double *xbest, const double *hist, ctqr_info *info,
+                          hipStream_t st);
 
 // ---- refine.hip (conjugate-gradient form of the refinement) -----------------
 constexpr int PCG_DOT_BLOCKS = 256;
@@ -192,4 +199,21 @@ ctqr_status pcg_alpha(int S, const double *gamma, const double *qq, double *alph
 ctqr_status pcg_direction(int64_t rows, int S, const double *z, const double *beta, double *p, const int *skip,
                           hipStream_t st);
 ctqr_status pcg_step(int64_t rows, int S, double *x, const double *p, const double *alpha,
-                     unsigned long long *dmax, unsigned long long *xmax, const int *skip, hipStream_t st);
+                     unsigned long long *dmax, unsigned long long *xmax, double *xs, const int *skip,
+                     hipStream_t st);
+
+// ---- cond.hip (condition-number estimate) ------------------------------------
+// Column-major rows x S vectors: counter-hashed start values in [-1, 1),
+// FP64 column dot products (deterministic), scaling to unit norm, and the
+// running maximum of Rayleigh quotients (est[slot]); cond_finish writes
+// [sigma_max, sigma_min, kappa] from est[0] (A^T A) and est[1] ((R^T R)^-1).
+template <typename T>
+ctqr_status cond_start(int64_t rows, int S, T *x, int64_t ldx, uint64_t seed, hipStream_t st);
+template <typename TX, typename TY>
+ctqr_status col_dot(int64_t rows, int S, const TX *x, int64_t ldx, const TY *y, int64_t ldy, double *out,
+                    hipStream_t st);
+template <typename TD, typename TS>
+ctqr_status col_scale(int64_t rows, int S, const TS *src, int64_t lds, const double *dots, TD *dst, int64_t ldd,
+                      hipStream_t st);
+ctqr_status cond_max(int S, const double *q, double *est, int slot, hipStream_t st);
+ctqr_status cond_finish(const double *est, double *out, hipStream_t st);

@@ -108,7 +108,7 @@ __device__ inline unsigned long long abs_bits(double v)
 __global__ __launch_bounds__(256)
 void pcg_step_kernel(int64_t rows, int S, double *__restrict__ x, const double *__restrict__ p,
                      const double *__restrict__ alpha, unsigned long long *dmax, unsigned long long *xmax,
-                     const int *skip)
+                     double *__restrict__ xs, const int *skip)
 {
     if (skip && *skip) return;
     __shared__ unsigned long long md[256], mx[256];
@@ -120,7 +120,9 @@ void pcg_step_kernel(int64_t rows, int S, double *__restrict__ x, const double *
             const double a = alpha[s];
             for (int64_t i = (int64_t)blockIdx.x * rt + ro; i < rows; i += (int64_t)gridDim.x * rt) {
                 const double d = a * p[i * S + s];
-                const double xv = x[i * S + s] + d;
+                const double xo = x[i * S + s];
+                if (xs) xs[i * S + s] = xo;
+                const double xv = xo + d;
                 x[i * S + s] = xv;
                 const unsigned long long bd = abs_bits(d), bx = abs_bits(xv);
                 dm = bd > dm ? bd : dm;
@@ -181,10 +183,10 @@ ctqr_status pcg_direction(int64_t rows, int S, const double *z, const double *be
 }
 
 ctqr_status pcg_step(int64_t rows, int S, double *x, const double *p, const double *alpha, unsigned long long *dmax,
-                     unsigned long long *xmax, const int *skip, hipStream_t st)
+                     unsigned long long *xmax, double *xs, const int *skip, hipStream_t st)
 {
     const int rt = 256 / std::min(256, S);
     const unsigned blocks = (unsigned)std::min<int64_t>(ceil_div(rows, rt), 512);
-    LAUNCH_TRY(pcg_step_kernel, dim3(blocks), dim3(256), 0, st, rows, S, x, p, alpha, dmax, xmax, skip);
+    LAUNCH_TRY(pcg_step_kernel, dim3(blocks), dim3(256), 0, st, rows, S, x, p, alpha, dmax, xmax, xs, skip);
     return CTQR_OK;
 }

@@ -166,11 +166,12 @@ __global__ void info_reset_kernel(ctqr_info *info)
     info->status = 0;
     info->first_bad_col = -1;
     info->iters = 0;
-    info->pad = 0;
+    info->x_iters = 0;
     info->max_rel_update = 0.0;
     info->rdiag_max = 0.0;
     info->rdiag_min = 0.0;
     info->nnz = 0;
+    info->contraction = 0.0;
 }
 
 // Non-negative doubles order like their bit patterns; NaN maps to all ones.
@@ -180,10 +181,12 @@ __device__ inline unsigned long long order_bits(double v)
     return v == v ? (unsigned long long)__double_as_longlong(v) : ~0ull;
 }
 
+// x += d; xs (when given) receives x before the update, the iterate whose
+// error this update estimates.
 template <typename TD>
 __global__ void refine_update_kernel(int64_t n, int S, double *__restrict__ x, const TD *__restrict__ d,
                                      int64_t ldd, unsigned long long *dmax, unsigned long long *xmax,
-                                     const int *skip)
+                                     double *__restrict__ xs, const int *skip)
 {
     if (skip && *skip) return;
     __shared__ double t[32][33];
@@ -204,7 +207,9 @@ __global__ void refine_update_kernel(int64_t n, int S, double *__restrict__ x, c
             int64_t r = r0 + k;
             if (r < n && s < S) {
                 double dv = t[threadIdx.x][k];
-                double xv = x[r * S + s] + dv;
+                const double xo = x[r * S + s];
+                if (xs) xs[r * S + s] = xo;
+                double xv = xo + dv;
                 x[r * S + s] = xv;
                 unsigned long long a = order_bits(dv), b = order_bits(xv);
                 dm = a > dm ? a : dm;
@@ -226,13 +231,22 @@ __global__ void refine_update_kernel(int64_t n, int S, double *__restrict__ x, c
 }
 
 // Decide convergence after refinement iteration `it` (0-based) and reset the
-// per-slice maxima for the next one.  hist[0] keeps the previous relative
-// update, hist[1] the number of consecutive non-contracting iterations.
+// per-slice maxima for the next one.  The refinement has converged when
+// rel = max_s ||d_s||_inf / ||x_s||_inf <= tol.  It ends without converging
+// (CTQR_NOT_CONVERGED) after stall_limit consecutive updates that are no
+// smaller than 0.9x the previous one, or after max_iters.
+// hist: [0] previous rel, [1] consecutive non-contracting updates, [2] the
+// smallest rel so far, [3] 1 once [2] is set, [4] 1 if this iteration set a
+// new smallest rel (the iterate before this update is the best one so far;
+// refine_keep copies it), [5] the iteration that set [2], [6] the first rel.
 __global__ __launch_bounds__(256)
 void refine_check_kernel(int S, unsigned long long *dmax, unsigned long long *xmax, double tol, int it,
                          int max_iters, int stall_limit, double *hist, int *done, ctqr_info *info)
 {
-    if (*done) return;
+    if (*done) {
+        if (threadIdx.x == 0) hist[4] = 0.0;
+        return;
+    }
     __shared__ double red[256];
     double worst = 0.0;
     bool bad = false;
@@ -256,30 +270,62 @@ void refine_check_kernel(int S, unsigned long long *dmax, unsigned long long *xm
     if (threadIdx.x == 0) {
         double rel = red[0];
         info->iters = it + 1;
+        info->x_iters = it + 1;
         info->max_rel_update = rel;
+        if (it == 0) hist[6] = rel;
+        info->contraction = (it > 0 && hist[6] > 0.0 && rel <= 1e300) ? pow(rel / hist[6], 1.0 / it) : 0.0;
+        const bool better = rel <= 1e300 && (hist[3] == 0.0 || rel < hist[2]);
+        hist[4] = better ? 1.0 : 0.0;
+        if (better) {
+            hist[2] = rel;
+            hist[3] = 1.0;
+            hist[5] = it;
+        }
         if (!(rel <= 1e300)) {
             info_event(info, CTQR_NONFINITE, -1);
             *done = 1;
         } else if (rel <= tol) {
             *done = 1;
         } else {
-            // Updates that stop shrinking (twice no better than 0.9x the
-            // previous one) have met the rounding floor of the FP64 residuals
-            // when they are already tiny (<= STALL_FLOOR): that is the
-            // attainable accuracy, so it ends the refinement normally.  A
-            // stall above that floor means the iteration does not contract.
-            const double STALL_FLOOR = 1e-9;
             double prev = hist[0];
             int stalls = (it > 0 && rel > 0.9 * prev) ? (int)hist[1] + 1 : 0;
             hist[0] = rel;
             hist[1] = stalls;
-            if (stalls >= stall_limit && rel <= STALL_FLOOR) {
-                *done = 1;
-            } else if (stalls >= stall_limit || it + 1 >= max_iters) {
+            if (stalls >= stall_limit || it + 1 >= max_iters) {
                 info_event(info, CTQR_NOT_CONVERGED, -1);
                 *done = 1;
             }
         }
+    }
+}
+
+// xbest = xs when the last check found a new smallest update (hist[4]).
+__global__ void refine_keep_kernel(int64_t count, const double *__restrict__ xs, double *__restrict__ xbest,
+                                   const double *hist)
+{
+    if (hist[4] == 0.0) return;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+         e += (int64_t)gridDim.x * blockDim.x)
+        xbest[e] = xs[e];
+}
+
+// After a refinement that did not converge: x = xbest, the iterate before the
+// smallest update, unless that update was the last one (the iteration was
+// still contracting, so the last iterate is the better one).  The info then
+// reports that iterate: x_iters updates, max_rel_update its own update.
+__global__ void refine_select_kernel(int64_t count, double *__restrict__ x, const double *__restrict__ xbest,
+                                     const double *hist, ctqr_info *info)
+{
+    if (info->status != CTQR_NOT_CONVERGED || hist[3] == 0.0) return;
+    const int best = (int)hist[5];
+    if (best >= info->iters - 1) return;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+         e += (int64_t)gridDim.x * blockDim.x)
+        x[e] = xbest[e];
+    __syncthreads();
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        info->x_iters = best;
+        info->max_rel_update = hist[2];
     }
 }
 
@@ -387,11 +433,28 @@ ctqr_status info_reset(ctqr_info *info, hipStream_t st)
 
 template <typename TD>
 ctqr_status refine_update(int64_t n, int S, double *x, const TD *d, int64_t ldd,
-                          unsigned long long *dmax, unsigned long long *xmax, const int *skip,
+                          unsigned long long *dmax, unsigned long long *xmax, double *xs, const int *skip,
                           hipStream_t st)
 {
     LAUNCH_TRY(refine_update_kernel<TD>, dim3((unsigned)std::min<int64_t>(ceil_div(n, 32), 512), (unsigned)ceil_div(S, 32)),
-               dim3(32, 8), 0, st, n, S, x, d, ldd, dmax, xmax, skip);
+               dim3(32, 8), 0, st, n, S, x, d, ldd, dmax, xmax, xs, skip);
+    return CTQR_OK;
+}
+
+ctqr_status refine_keep(int64_t count, const double *xs, double *xbest, const double *hist, hipStream_t st)
+{
+    if (count <= 0) return CTQR_OK;
+    unsigned g = (unsigned)std::min<int64_t>(ceil_div(count, 256), 4096);
+    LAUNCH_TRY(refine_keep_kernel, dim3(g), dim3(256), 0, st, count, xs, xbest, hist);
+    return CTQR_OK;
+}
+
+ctqr_status refine_select(int64_t count, double *x, const double *xbest, const double *hist, ctqr_info *info,
+                          hipStream_t st)
+{
+    if (count <= 0) return CTQR_OK;
+    unsigned g = (unsigned)std::min<int64_t>(ceil_div(count, 256), 4096);
+    LAUNCH_TRY(refine_select_kernel, dim3(g), dim3(256), 0, st, count, x, xbest, hist, info);
     return CTQR_OK;
 }
 
@@ -414,13 +477,14 @@ template ctqr_status rm_to_cm<float, double>(int64_t, int, const double *, float
                                              const int *, hipStream_t);
 template ctqr_status copy_cm<double, double>(int64_t, int, const double *, int64_t, double *, int64_t,
                                              hipStream_t);
+template ctqr_status copy_cm<float, float>(int64_t, int, const float *, int64_t, float *, int64_t, hipStream_t);
 template ctqr_status copy_cm<float, double>(int64_t, int, const double *, int64_t, float *, int64_t,
                                             hipStream_t);
 template ctqr_status copy_cm<double, float>(int64_t, int, const float *, int64_t, double *, int64_t,
                                             hipStream_t);
 template ctqr_status refine_update<float>(int64_t, int, double *, const float *, int64_t,
-                                          unsigned long long *, unsigned long long *, const int *,
+                                          unsigned long long *, unsigned long long *, double *, const int *,
                                           hipStream_t);
 template ctqr_status refine_update<double>(int64_t, int, double *, const double *, int64_t,
-                                           unsigned long long *, unsigned long long *, const int *,
+                                           unsigned long long *, unsigned long long *, double *, const int *,
                                            hipStream_t);

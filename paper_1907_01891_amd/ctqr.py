@@ -46,8 +46,9 @@ class ctqr_sparse(ctypes.Structure):
 
 
 class ctqr_info(ctypes.Structure):
-    _fields_ = [("status", c_i32), ("first_bad_col", c_i32), ("iters", c_i32), ("pad", c_i32),
-                ("max_rel_update", c_dbl), ("rdiag_max", c_dbl), ("rdiag_min", c_dbl), ("nnz", c_i64)]
+    _fields_ = [("status", c_i32), ("first_bad_col", c_i32), ("iters", c_i32), ("x_iters", c_i32),
+                ("max_rel_update", c_dbl), ("rdiag_max", c_dbl), ("rdiag_min", c_dbl), ("nnz", c_i64),
+                ("contraction", c_dbl)]
 
 
 class ctqr_solver_desc(ctypes.Structure):
@@ -96,10 +97,15 @@ _SIGNATURES = {
                                         c_vp, c_vp]),
     "ctqr_solver_query": (c_i32, [c_vp, c_i32, _P(c_i32), _P(c_i32), _P(c_i32)]),
     "ctqr_solver_destroy": (c_i32, [c_vp]),
+    "ctqr_cond_workspace": (c_i32, [c_i64, c_i64, c_i32, c_i32, _P(c_sz)]),
+    "ctqr_cond_estimate": (c_i32, [c_i64, c_i64, c_i32, c_vp, c_i64, c_vp, _P(ctqr_sparse), c_i32, c_i32, c_vp,
+                                   c_sz, c_vp, c_vp]),
     "ctqr_spmm": (c_i32, [_P(ctqr_sparse), c_i32, c_dbl, c_vp, c_i64, c_dbl, c_vp, c_i64, c_vp]),
     "ctqr_set_progress": (c_i32, [ctqr_progress_fn, c_vp]),
     "ctqr_profile_enable": (c_i32, [c_i32]),
     "ctqr_profile_read": (c_i32, [_P(c_i64), _P(c_dbl), _P(c_dbl)]),
+    "ctqr_profile_phases": (c_i32, [_P(c_dbl), _P(c_i64)]),
+    "ctqr_release": (c_i32, []),
 }
 EXPORTS = tuple(_SIGNATURES)
 
@@ -129,6 +135,12 @@ class CtqrError(RuntimeError):
             msg += ": " + last.decode()
         super().__init__(msg)
         self.code = code
+
+
+def ctqr_release():
+    """ctqr_release: the library's process-lifetime state (pinned flag words,
+    timing events, progress hook) freed after the device has finished."""
+    return lib().ctqr_release()
 
 
 def check(code, where):
@@ -273,6 +285,18 @@ def ctqr_solver_destroy(solver):
     return lib().ctqr_solver_destroy(solver)
 
 
+def ctqr_cond_workspace(m, n, dtype, nvec):
+    b = c_sz()
+    check(lib().ctqr_cond_workspace(m, n, dtype, nvec, ctypes.byref(b)), "ctqr_cond_workspace")
+    return b.value
+
+
+def ctqr_cond_estimate(m, n, dtype, QR_ptr, lda, rinv_ptr, sparse, nvec, iters, work_ptr, work_bytes, out_ptr,
+                       stream):
+    return lib().ctqr_cond_estimate(m, n, dtype, QR_ptr, lda, rinv_ptr, ctypes.byref(sparse), nvec, iters, work_ptr,
+                                    work_bytes, out_ptr, stream)
+
+
 def ctqr_spmm(sparse, nslices, alpha, X_ptr, ldx, beta, Y_ptr, ldy, stream):
     return lib().ctqr_spmm(ctypes.byref(sparse), nslices, alpha, X_ptr, ldx, beta, Y_ptr, ldy, stream)
 
@@ -288,8 +312,24 @@ def ctqr_set_progress(fn):
     return lib().ctqr_set_progress(cb, None)
 
 
+CTQR_PROFILE_UPDATE = 1
+CTQR_PROFILE_PHASES = 2
+PHASES = ("panel", "inner", "reduction", "update", "group_update", "rinv",
+          "qtb", "trsm", "residual", "refine_trsm", "refine_other")
+CTQR_NPHASES = len(PHASES)
+
+
 def ctqr_profile_enable(on):
-    return lib().ctqr_profile_enable(1 if on else 0)
+    """on: True (= CTQR_PROFILE_UPDATE), False, or a bit set of the CTQR_PROFILE_* flags."""
+    return lib().ctqr_profile_enable(int(on))
+
+
+def ctqr_profile_phases():
+    """{phase name: (total ms, intervals)} of the phase timing."""
+    ms = (c_dbl * CTQR_NPHASES)()
+    cnt = (c_i64 * CTQR_NPHASES)()
+    check(lib().ctqr_profile_phases(ms, cnt), "ctqr_profile_phases")
+    return {PHASES[i]: (ms[i], cnt[i]) for i in range(CTQR_NPHASES)}
 
 
 def ctqr_profile_read():

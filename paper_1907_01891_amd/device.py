@@ -5,11 +5,34 @@ a libctqr call (ctqr.py).  Matrices are column-major: an m x n matrix with
 leading dimension ld is a torch tensor of shape (m, n) and strides (1, ld),
 carved from a (n, ld) row-major allocation.
 """
+import atexit
 import ctypes
+import weakref
 
 import torch
 
 from . import ctqr as C
+
+_live_solvers = weakref.WeakSet()
+
+
+@atexit.register
+def _release_at_exit():
+    """At interpreter exit, before torch's own exit handlers (registered
+    earlier, so run later): destroy the solvers still alive (their graphs and
+    capture streams) and release the library's process-lifetime HIP state,
+    so nothing of libctqr is left for the HIP runtime's teardown."""
+    if not torch.cuda.is_initialized():
+        return
+    for sv in list(_live_solvers):
+        try:
+            sv.close()
+        except Exception:
+            pass
+    try:
+        C.ctqr_release()
+    except Exception:
+        pass
 
 _DT = {C.CTQR_F64: torch.float64, C.CTQR_F32: torch.float32}
 
@@ -89,9 +112,12 @@ class SystemMatrix:
     """A for one geometry: dense (optional, FP64 or FP32) and the FP64 sparse
     copy (CSR + CSC, optional), built on the GPU by ctqr_build_system_matrix."""
 
-    def __init__(self, geom_dict, dtype=C.CTQR_F64, dense=True, sparse=True, device="cuda", stream=None):
+    def __init__(self, geom_dict, dtype=C.CTQR_F64, dense=True, sparse=True, device="cuda", stream=None,
+                 nnz_cap=None):
         self.geom = geometry(geom_dict)
         self.m, self.n, self.nnz_cap = C.ctqr_geometry_sizes(self.geom)
+        if nnz_cap is not None:          # a smaller capacity than the geometry's upper bound
+            self.nnz_cap = int(nnz_cap)
         self.dtype = dtype
         self.device = device
         self.A = colmajor(self.m, self.n, _DT[dtype], device) if dense else None
@@ -181,7 +207,7 @@ class QRFactor:
             self.T = colmajor(self.nb, self.n, self.A.dtype, self.A.device, ld=self.nb)
         return nb, ms
 
-    def solve(self, B, X=None, sparse=None, tol=1e-13, max_iters=0, method=C.CTQR_REFINE_CSNE, stream=None):
+    def solve(self, B, X=None, sparse=None, tol=1e-12, max_iters=0, method=C.CTQR_REFINE_CSNE, stream=None):
         """X = R^-1 Q^T B (FP64, column-major), refined with the sparse A if given."""
         S = B.shape[1]
         if X is None:
@@ -197,6 +223,18 @@ class QRFactor:
                                        wp, wb, self.sinfo.ptr, stream_handle(stream)),
                 "ctqr_qr_solve_slices")
         return X
+
+
+    def cond_estimate(self, sparse, nvec=8, iters=30, stream=None):
+        """(sigma_max(A), sigma_min(R), kappa) by ctqr_cond_estimate: power and
+        inverse iteration, lower bounds of the true values."""
+        ws = Workspace(self.A.device)
+        wp, wb = ws.get(C.ctqr_cond_workspace(self.m, self.n, self.dtype, nvec))
+        out = torch.zeros(3, dtype=torch.float64, device=self.A.device)
+        C.check(C.ctqr_cond_estimate(self.m, self.n, self.dtype, ctypes.c_void_p(self.A.data_ptr()), ld_of(self.A),
+                                     ctypes.c_void_p(self.Rinv.data_ptr()), sparse, nvec, iters, wp, wb,
+                                     ctypes.c_void_p(out.data_ptr()), stream_handle(stream)), "ctqr_cond_estimate")
+        return tuple(float(v) for v in out.cpu().tolist())
 
 
 class OocFactor:
@@ -236,7 +274,7 @@ class OocFactor:
                 "ctqr_qr_factor_ooc")
         return self
 
-    def solve(self, B, X=None, sparse=None, tol=1e-13, max_iters=0, method=C.CTQR_REFINE_CSNE, stream=None):
+    def solve(self, B, X=None, sparse=None, tol=1e-12, max_iters=0, method=C.CTQR_REFINE_CSNE, stream=None):
         """X = R^-1 Q^T B with the out-of-core factor (ctqr_qr_solve_ooc)."""
         S = B.shape[1]
         if X is None:
@@ -267,7 +305,7 @@ class Solver:
     """Batched solver over a stored factor (ctqr_solver_*): requests of 1 ..
     max_slices slices, one HIP graph per slice bucket (powers of two up to 64, multiples of 64 above)."""
 
-    def __init__(self, qr, max_slices, sparse=None, tol=1e-13, max_iters=0, method=C.CTQR_REFINE_CSNE,
+    def __init__(self, qr, max_slices, sparse=None, tol=1e-12, max_iters=0, method=C.CTQR_REFINE_CSNE,
                  device="cuda"):
         self.qr = qr
         self.sparse = sparse    # ctqr_sparse (kept alive: the solver copies the struct only)
@@ -281,6 +319,7 @@ class Solver:
         self.h = C.ctqr_solver_create(self.desc, ctypes.c_void_p(self.work.data_ptr()), self.work.numel())
         self.info = Info(device)
         self.device = device
+        _live_solvers.add(self)
 
     def tune(self, reps=2, stream=None):
         C.check(C.ctqr_solver_tune(self.h, reps, stream_handle(stream)), "ctqr_solver_tune")

@@ -40,7 +40,7 @@ def test_status_strings():
 def test_struct_layouts():
     assert ctypes.sizeof(C.ctqr_geometry) == 48
     assert ctypes.sizeof(C.ctqr_sparse) == 72
-    assert ctypes.sizeof(C.ctqr_info) == 48
+    assert ctypes.sizeof(C.ctqr_info) == 56
 
 
 def _geom(**kw):

@@ -123,7 +123,12 @@ def _check_leading_columns(F, A, tol):
 def _check_gram(F, A, u):
     # Householder QR's backward error on a column grows like sqrt(m) u in
     # practice (the worst-case bound is O(m n u)); allow 2 sqrt(m) u.
-    u = 2.0 * np.sqrt(A.shape[0]) * u / 50.0
+    worst = _gram_worst(F, A)
+    assert worst <= 2.0 * np.sqrt(A.shape[0]) * u, worst
+
+
+def _gram_worst(F, A):
+    """max |r_a^T r_b - a_a^T a_b| / (||a_a|| ||a_b||) over sampled column pairs."""
     Acsc = A.tocsc()
     rng = np.random.default_rng(11)
     n = A.shape[1]
@@ -141,7 +146,7 @@ def _check_gram(F, A, u):
             rr = R[a] @ R[b][:a + 1]
             aa = (Acsc[:, a].T @ Acsc[:, b]).toarray()[0, 0]
             worst = max(worst, abs(rr - aa) / (norms[a] * norms[b]))
-    assert worst <= 50 * u, worst
+    return worst
 
 
 def _check_optimality(A, X, B):
@@ -174,6 +179,52 @@ def test_fp32_refined_solutions(factor32, gpu_sparse, oracle_A, rhs):
     Xn = factor32.solve(to_colmajor(torch.as_tensor(B), dtype=torch.float64), sparse=gpu_sparse.sp,
                         tol=1e-12, max_iters=30).cpu().numpy()
     assert factor32.sinfo.read().status == 0
+    _check_optimality(oracle_A, Xn, B)
+
+
+@pytest.fixture(scope="module")
+def factorx3(gpu_sparse):
+    _case("factor split-bf16 ct256")
+    return _factor(gpu_sparse, torch.float32, C.CTQR_PREC_BF16X3_MFMA)
+
+
+# Split-BF16 products: each FP32 operand as a bf16 high part plus a bf16 low
+# part (about 16 significant bits), the low-low product dropped, so one product
+# term is exact to about 3 * 2^-16 relative.  A column's backward error then
+# grows with the number of block-reflector applications it receives (64 group
+# updates at nb = 256 with groups of four), each contributing two products
+# ([G | W] and C -= V W'): |r_a^T r_b - a_a^T a_b| <= 2 * 2 sqrt(64) u_split
+# ||a_a|| ||a_b||.
+U_SPLIT = 3.0 * 2.0 ** -16
+
+
+def test_bf16x3_factor_leading_columns(factorx3, oracle_A):
+    # the leading 64 columns sit inside the first block column: panel (FP64
+    # arithmetic, FP32 storage) and FP32 inner updates only
+    _case("split-bf16 leading columns")
+    assert factorx3.info.read().status == 0
+    _check_leading_columns(factorx3, oracle_A, 1e-4)
+
+
+def test_bf16x3_factor_gram(factorx3, oracle_A):
+    _case("split-bf16 gram")
+    worst = _gram_worst(factorx3, oracle_A)
+    bound = 2.0 * 2.0 * np.sqrt(get_workload(NAME).n / (4 * NB)) * U_SPLIT
+    print("split-bf16 R^T R vs A^T A: %.2e (bound %.2e)" % (worst, bound))
+    assert worst <= bound
+
+
+def test_bf16x3_refined_solutions(factorx3, gpu_sparse, oracle_A, rhs):
+    _case("split-bf16 refined solve")
+    X, B0, B = rhs
+    Xc = factorx3.solve(to_colmajor(torch.as_tensor(B0), dtype=torch.float64), sparse=gpu_sparse.sp,
+                        tol=1e-12, max_iters=30).cpu().numpy()
+    si = factorx3.sinfo.read()
+    assert si.status == 0, (si.status, si.iters, si.max_rel_update)
+    assert lsq.rel_err(Xc, X).max() <= 1e-10
+    Xn = factorx3.solve(to_colmajor(torch.as_tensor(B), dtype=torch.float64), sparse=gpu_sparse.sp,
+                        tol=1e-12, max_iters=30).cpu().numpy()
+    assert factorx3.sinfo.read().status == 0
     _check_optimality(oracle_A, Xn, B)
 
 

@@ -171,7 +171,7 @@ def test_mixed_fp32_refined_matches_oracle(gpu, name, nb, method):
     Bd = to_colmajor(torch.as_tensor(B), dtype=torch.float64)
     Xu = download(F.solve(Bd))                   # unrefined FP32 solve
     spA = DeviceSparse(A)
-    Xg = download(F.solve(Bd, sparse=spA.sp, tol=1e-14, max_iters=30, method=method))
+    Xg = download(F.solve(Bd, sparse=spA.sp, tol=1e-12, max_iters=30, method=method))
     torch.cuda.synchronize()
     si = F.sinfo.read()
     assert si.status == 0, (C.status_string(si.status), si.iters, si.max_rel_update)
@@ -234,7 +234,7 @@ def test_bf16_trailing_update_factor(gpu, name):
     Xo = hh.backsub(QRo, hh.apply_qt(QRo, tauo, B))
     spA = DeviceSparse(A)
     for method in (C.CTQR_REFINE_CSNE, C.CTQR_REFINE_PCG):
-        Xg = download(F16.solve(Bd, sparse=spA.sp, tol=1e-14, max_iters=30, method=method))
+        Xg = download(F16.solve(Bd, sparse=spA.sp, tol=1e-12, max_iters=30, method=method))
         torch.cuda.synchronize()
         si = F16.sinfo.read()
         err = lsq.rel_err(Xg, Xo).max()
@@ -272,7 +272,7 @@ def test_bf16x3_trailing_update_factor(gpu, name):
     Xo = hh.backsub(QRo, hh.apply_qt(QRo, tauo, B))
     spA = DeviceSparse(A)
     for method in (C.CTQR_REFINE_CSNE, C.CTQR_REFINE_PCG):
-        Xg = download(F3.solve(Bd, sparse=spA.sp, tol=1e-14, max_iters=30, method=method))
+        Xg = download(F3.solve(Bd, sparse=spA.sp, tol=1e-12, max_iters=30, method=method))
         torch.cuda.synchronize()
         si = F3.sinfo.read()
         e = lsq.rel_err(Xg, Xo).max()

@@ -177,3 +177,68 @@ def test_condition_ct32(ct32):
     s = np.linalg.svd(d, compute_uv=False)
     kappa = s[0] / s[-1]
     assert 10 < kappa < 1e2     # measured 32.3; full column rank
+
+
+def _tiny_ls():
+    """A 3 x 2 system whose least-squares solution and residual are known in
+    closed form: A^T A = [[2, 1], [1, 2]], A^T b = [5, 6], x* = [4/3, 7/3],
+    r* = b - A x* = [-1/3, -1/3, 1/3]."""
+    import scipy.sparse as sps
+    A = sps.csr_matrix(np.array([[1.0, 0.0], [0.0, 1.0], [1.0, 1.0]]))
+    b = np.array([[1.0], [2.0], [4.0]])
+    return A, b, np.array([[4.0 / 3.0], [7.0 / 3.0]])
+
+
+def test_ls_optimality_closed_form():
+    A, b, xs = _tiny_ls()
+    # zero (to rounding) at the least-squares solution
+    assert lsq.ls_optimality(A, xs, b)[0] <= 1e-15
+    # x = [1, 2]: r = [0, 0, 1], A^T r = [1, 1], ||A||_F = 2, ||r|| = 1
+    assert abs(lsq.ls_optimality(A, np.array([[1.0], [2.0]]), b)[0] - np.sqrt(2.0) / 2.0) <= 1e-15
+
+
+def test_ls_optimality_rejects_perturbed_solution(ct32):
+    # the metric separates the least-squares solution from a solution moved
+    # by 1e-6 relative: the check on noisy full-size solutions (bound of order
+    # 1e-14) would fail for such an x
+    A, d, QR, tau = ct32
+    X, B = lsq.sinograms(A, 32, 2)
+    x = hh.backsub(QR, hh.apply_qt(QR, tau, B))
+    good = lsq.ls_optimality(A, x, B)
+    rng = np.random.default_rng(5)
+    xp = x * (1.0 + 1e-6 * rng.standard_normal(x.shape))
+    bad = lsq.ls_optimality(A, xp, B)
+    assert good.max() <= 1e-13
+    assert bad.min() >= 1e-9, bad
+    assert (bad > 1e4 * good).all()
+
+
+def test_relative_residual_closed_form():
+    # ||A x* - b||_F / ||A||_F = (1/sqrt(3)) / 2 for the tiny system
+    A, b, xs = _tiny_ls()
+    assert abs(lsq.relative_residual(A, xs, b) - 1.0 / (2.0 * np.sqrt(3.0))) <= 1e-15
+    # dense input takes the same path
+    assert abs(lsq.relative_residual(A.toarray(), xs, b) - 1.0 / (2.0 * np.sqrt(3.0))) <= 1e-15
+
+
+def test_psnr_closed_form():
+    # Eq. 5-6: a constant error of 0.1 on an image whose maximum is 1 gives
+    # MSE = 0.01 and PSNR = 10 log10(1 / 0.01) = 20 dB; an exact image gives inf
+    ref = np.array([[0.0, 1.0], [0.5, 0.25]])
+    assert abs(lsq.psnr(ref, ref + 0.1) - 20.0) <= 1e-12
+    assert abs(lsq.psnr(2.0 * ref, 2.0 * ref - 0.2) - 20.0) <= 1e-12   # scales with max(I0)
+    assert lsq.psnr(ref, ref) == np.inf
+
+
+@pytest.mark.parametrize("name", ["ct24", "ct32"])
+def test_cgls_matches_qr_solve(name, oracle_lib):
+    # the matrix-free CGLS used for sizes the dense oracle cannot hold reaches
+    # the same least-squares solution as the Householder route (Eq. 4)
+    g = get_workload(name).geometry()
+    A = system_matrix_csr(g)
+    X, B = lsq.sinograms(A, g["side"], 2)
+    x_qr = lsq.reconstruct(A.toarray(), B)[0]
+    x_cg, iters = lsq.cgls(A, B, tol=1e-14)
+    assert lsq.rel_err(x_cg, x_qr).max() <= 1e-10
+    assert lsq.ls_optimality(A, x_cg, B).max() <= 1e-13
+    assert (iters < A.shape[1]).all()
