@@ -110,6 +110,8 @@ def parse():
     p.add_argument("--ooc-tile", type=int, default=8192, help="columns per streamed host tile")
     p.add_argument("--ooc-dev-cols", type=int, default=0,
                    help="cap on the HBM-resident columns (0: as many as fit)")
+    p.add_argument("--no-phases", action="store_true",
+                   help="skip the untimed phase breakdown, condition estimate and solve roofline (profiled runs)")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="only run 3 device-to-device copies of 1 GiB (counter calibration) and exit")
     return p.parse_args()
@@ -474,6 +476,67 @@ def ooc_bench(args, log):
     }
 
 
+def phase_and_conditioning(args, log, C, F, A32, B, sp, Xmixed, sinfo, t_solve, build_dense, m, n, S, dev):
+    """Untimed extras of the mixed path: the phase breakdown of one more
+    factorization and refined solve (HIP events per phase), the condition
+    estimate kappa(A) with the least-squares perturbation bound, and the solve
+    roofline from the per-phase work model."""
+    import torch
+    from paper_1907_01891_amd.device import colmajor
+    build_dense(A32, C.CTQR_F32)
+    torch.cuda.synchronize()
+    C.ctqr_profile_enable(C.CTQR_PROFILE_PHASES)
+    F.factor()
+    Xp = F.solve(B, sparse=sp.sp, tol=args.tol, max_iters=args.max_iters, method=REFINE[args.refine])
+    torch.cuda.synchronize()
+    phases = C.ctqr_profile_phases()
+    C.ctqr_profile_enable(False)
+    del Xp
+    phase_ms = {k: v[0] for k, v in phases.items()}
+    log("phases (ms): " + ", ".join("%s %.1f" % (k, v) for k, v in phase_ms.items()))
+
+    # ---- condition estimate and the least-squares perturbation bound
+    smax, smin, kappa = F.cond_estimate(sp.sp, nvec=8, iters=30)
+    Rr = colmajor(m, S, torch.float64, dev)
+    Rr.copy_(B)
+    sp.spmm(Xmixed, alpha=-1.0, beta=1.0, Y=Rr)
+    AX = sp.spmm(Xmixed)
+    torch.cuda.synchronize()
+    tan_theta = (Rr.norm(dim=0) / AX.norm(dim=0)).max().item()
+    del Rr, AX
+    u64, u32 = 2.0 ** -53, 2.0 ** -24
+    ls_bound64 = u64 * (2.0 * kappa + kappa ** 2 * tan_theta)
+    log("kappa estimate %.4e (sigma_max %.4e, sigma_min %.4e); tan(theta) %.3e; LS bound u64 (2k + k^2 tan) %.2e; "
+        "contraction %.3e (u32 kappa^2 %.3e)" % (kappa, smax, smin, tan_theta, ls_bound64, sinfo.contraction,
+                                                 u32 * kappa ** 2))
+    nnz = sp.nnz()
+    split_refine = args.prec == "bf16x3" and S >= 128
+    model = solve_phase_model(m, n, S, nnz, int(sinfo.iters), 4, split_refine)
+    floor_ms = sum(v[2] for v in model.values()) * 1e3
+    solve_roof = {
+        "bound": "per phase: MFMA (Q^T B, substitutions) and HBM (sparse residuals)",
+        "floor_ms": floor_ms, "measured_ms": t_solve, "frac": floor_ms / t_solve,
+        "refine_iters": int(sinfo.iters),
+        "phases": {k: {"flops": v[0], "bytes": v[1], "floor_ms": v[2] * 1e3,
+                       "measured_ms": phase_ms[k]} for k, v in model.items()},
+        "refine_other_ms": phase_ms["refine_other"],
+        "model": "floor = sum over phases of max(flops / MFMA peak, bytes / 8 TB/s); FP32 MFMA peak, a third of "
+                 "the BF16 peak for split-BF16 substitution products; per-phase measured = HIP events of an "
+                 "untimed profiled solve",
+    }
+    return {
+        "refine_contraction": sinfo.contraction,
+        "kappa_est": kappa, "sigma_max_est": smax, "sigma_min_est": smin,
+        "kappa_note": "lower-bound estimates: power iteration on A^T A (FP64 sparse A), inverse iteration on R^T R "
+                      "(the factor's R), 8 vectors x 30 steps",
+        "ls_tan_theta_max": tan_theta,
+        "ls_perturbation_bound_fp64": ls_bound64,
+        "u32_kappa2": u32 * kappa ** 2,
+        "qr_phases_ms": {k: phase_ms[k] for k in ("panel", "inner", "reduction", "update", "group_update", "rinv")},
+        "solve_roofline": solve_roof,
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -595,48 +658,12 @@ def main():
     log("mixed (%s products): qr %.2f TFLOP/s, %.0f slices/s, refine iters %d (status %d), recovery err %.2e"
         % (args.prec, qr_tf, slices_s, sinfo.iters, sinfo.status, rec_err))
 
-    # ---- untimed: phase breakdown of one factorization and refined solve
-    build_dense(A32, C.CTQR_F32)
-    torch.cuda.synchronize()
-    C.ctqr_profile_enable(C.CTQR_PROFILE_PHASES)
-    F.factor()
-    Xp = F.solve(B, sparse=sp.sp, tol=args.tol, max_iters=args.max_iters, method=REFINE[args.refine])
-    torch.cuda.synchronize()
-    phases = C.ctqr_profile_phases()
-    C.ctqr_profile_enable(False)
-    del Xp
-    phase_ms = {k: v[0] for k, v in phases.items()}
-    log("phases (ms): " + ", ".join("%s %.1f" % (k, v) for k, v in phase_ms.items()))
+    extras = {}
+    if not args.no_phases:
+        extras = phase_and_conditioning(args, log, C, F, A32, B, sp, Xmixed, sinfo, t_solve, build_dense,
+                                        m, n, S, dev)
+    log("mixed path done")
 
-    # ---- condition estimate and the least-squares perturbation bound
-    smax, smin, kappa = F.cond_estimate(sp.sp, nvec=8, iters=30)
-    Rr = colmajor(m, S, torch.float64, dev)
-    Rr.copy_(B)
-    sp.spmm(Xmixed, alpha=-1.0, beta=1.0, Y=Rr)
-    AX = sp.spmm(Xmixed)
-    torch.cuda.synchronize()
-    tan_theta = (Rr.norm(dim=0) / AX.norm(dim=0)).max().item()
-    del Rr, AX
-    u64, u32 = 2.0 ** -53, 2.0 ** -24
-    ls_bound64 = u64 * (2.0 * kappa + kappa ** 2 * tan_theta)
-    log("kappa estimate %.4e (sigma_max %.4e, sigma_min %.4e); tan(theta) %.3e; LS bound u64 (2k + k^2 tan) %.2e; "
-        "contraction %.3e (u32 kappa^2 %.3e)" % (kappa, smax, smin, tan_theta, ls_bound64, sinfo.contraction,
-                                                 u32 * kappa ** 2))
-    nnz = sp.nnz()
-    split_refine = args.prec == "bf16x3" and S >= 128
-    model = solve_phase_model(m, n, S, nnz, int(sinfo.iters), 4, split_refine)
-    floor_ms = sum(v[2] for v in model.values()) * 1e3
-    solve_roof = {
-        "bound": "per phase: MFMA (Q^T B, substitutions) and HBM (sparse residuals)",
-        "floor_ms": floor_ms, "measured_ms": t_solve, "frac": floor_ms / t_solve,
-        "refine_iters": int(sinfo.iters),
-        "phases": {k: {"flops": v[0], "bytes": v[1], "floor_ms": v[2] * 1e3,
-                       "measured_ms": phase_ms[k]} for k, v in model.items()},
-        "refine_other_ms": phase_ms["refine_other"],
-        "model": "floor = sum over phases of max(flops / MFMA peak, bytes / 8 TB/s); FP32 MFMA peak, a third of "
-                 "the BF16 peak for split-BF16 substitution products; per-phase measured = HIP events of an "
-                 "untimed profiled solve",
-    }
     stream_out = None
     if not args.no_stream and args.workload == "ct256":
         stream_out = request_stream_bench(args, log, F, sp, B)
@@ -795,14 +822,7 @@ def main():
         "refine_last_rel_update": sinfo.max_rel_update,
         "recovery_rel_err_max": rec_err,
         "refine_contraction": sinfo.contraction,
-        "kappa_est": kappa, "sigma_max_est": smax, "sigma_min_est": smin,
-        "kappa_note": "lower-bound estimates: power iteration on A^T A (FP64 sparse A), inverse iteration on R^T R "
-                      "(the factor's R), 8 vectors x 30 steps",
-        "ls_tan_theta_max": tan_theta,
-        "ls_perturbation_bound_fp64": ls_bound64,
-        "u32_kappa2": u32 * kappa ** 2,
-        "qr_phases_ms": {k: phase_ms[k] for k in ("panel", "inner", "reduction", "update", "group_update", "rinv")},
-        "solve_roofline": solve_roof,
+        **extras,
         "qr_info_status": int(finfo.status),
         "rdiag_min_max": [finfo.rdiag_min, finfo.rdiag_max],
         "roofline": roof,

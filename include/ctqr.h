@@ -130,7 +130,8 @@ typedef struct {
     int32_t x_iters;         /* refinement updates contained in the returned X:
                                 iters, or fewer when CTQR_NOT_CONVERGED returned
                                 an earlier iterate (the one with the smallest
-                                update, see ctqr_qr_solve_slices)               */
+                                normal-equation residual, see
+                                ctqr_qr_solve_slices)                           */
     double  max_rel_update;  /* refinement: max_s ||dx_s||_inf / ||x_s||_inf of
                                 the last update, or of the update computed from
                                 the returned iterate when an earlier one is
@@ -325,9 +326,12 @@ ctqr_status ctqr_solve_workspace(int64_t m, int64_t n, ctqr_dtype dtype, int32_t
  *          max_s ||d_s||_inf / ||X_s||_inf is <= tol.  It stops with
  *          CTQR_NOT_CONVERGED when two consecutive updates fail to shrink
  *          below 0.9x the previous one, or after max_iters; X is then the
- *          iterate with the smallest update after it (the update estimates
- *          that iterate's error), or the last iterate if the last update was
- *          the smallest (info.x_iters says which).  NULL = no refinement.
+ *          iterate with the smallest normal-equation residual
+ *          max_s ||A^T (B_s - A X_s)||_inf / ||A^T (B_s - A X0_s)||_inf (X0 the
+ *          unrefined solution; A^T r = A^T A e measures the error e whatever
+ *          the preconditioner's quality), or the last iterate if the residual
+ *          was still falling at the last iteration (info.x_iters says which).
+ *          NULL = no refinement.
  *          With refinement the call waits on the stream after each
  *          iteration (it reads the convergence flag back) and returns once
  *          the refinement has ended; without it the call only enqueues.
@@ -458,6 +462,37 @@ ctqr_status ctqr_cond_workspace(int64_t m, int64_t n, ctqr_dtype dtype, int32_t 
 ctqr_status ctqr_cond_estimate(int64_t m, int64_t n, ctqr_dtype dtype, const void *QR, int64_t lda,
                                const void *Rinv, const ctqr_sparse *A64, int32_t nvec, int32_t iters,
                                void *work, size_t work_bytes, double *out, hipStream_t stream);
+
+/* View-count search: the smallest number of views for which A has full
+ * column rank.  The direct method needs full rank (Section II-A, Section IV),
+ * and the number of views that gives it depends on the resolution; Eq. 2
+ * places the views with per-quarter angle shifts that break the symmetry of
+ * the projection data to raise the rank.  For v = v_min, v_min + v_step, ...
+ * up to v_max (geometry g with n_views = v; its other fields, the angle
+ * schedule included, as given), the call builds the FP64 A (dense and sparse),
+ * factors it (FP64 QR, nb = 256) and estimates kappa(A) (ctqr_cond_estimate
+ * with 8 vectors and `iters` steps).  A view count passes when the
+ * factorization raises no rank flag (|R_kk| > n u max|R_ii| for every k) and
+ * kappa <= kappa_max; the search stops at the first that passes.  Counts with
+ * fewer rays than pixels (v n_bins < side^2) fail without any GPU work.
+ *   trials    host, up to max_trials entries, one per count tried, in order:
+ *             views, status (CTQR_OK = full rank, CTQR_RANK_DEFICIENT
+ *             otherwise), kappa estimate (INFINITY when not factored),
+ *             min and max |R_kk|.
+ *   n_trials  host: entries written.   v_best  host: the passing count, or 0.
+ *   work      device, ctqr_view_search_workspace(g, v_max) bytes.
+ * The call waits on the stream after every step (it reads the outcomes). */
+typedef struct {
+    int32_t views;
+    int32_t status;
+    double kappa;
+    double rdiag_min, rdiag_max;
+} ctqr_view_trial;
+ctqr_status ctqr_view_search_workspace(const ctqr_geometry *g, int32_t v_max, size_t *bytes);
+ctqr_status ctqr_view_search(const ctqr_geometry *g, int32_t v_min, int32_t v_max, int32_t v_step,
+                             double kappa_max, int32_t iters, void *work, size_t work_bytes,
+                             ctqr_view_trial *trials, int32_t max_trials, int32_t *n_trials,
+                             int32_t *v_best, hipStream_t stream);
 
 /* Sinogram synthesis and residual helper: Y = alpha * A X + beta * Y with the
  * FP64 CSR copy of A.  X (n x nslices, ldx) and Y (m x nslices, ldy) are

@@ -15,4 +15,6 @@ Everything is plain FP64 and follows the paper's definitions:
                 (Eq. 3, Eq. 4; Section II-C "System solving")
   lsq.py        the reconstruction X = R^-1 (Q^T B), residual metrics, CGLS,
                 PSNR (Eq. 5-6)
+  views.py      the smallest view count giving A full column rank (Section
+                II-A, Eq. 2), by SVD condition numbers
 """

@@ -196,7 +196,8 @@ struct SolveWS {
     T *s32, *y32, *d32;
     __bf16 *rparts;          // split-BF16 parts of R for the refinement's wide substitutions (or null)
     __bf16 *xparts;          // and of their right-hand sides (or null)
-    unsigned long long *dmax, *xmax;
+    unsigned long long *dmax, *xmax, *smax;
+    double *s0;
     int *done;
     int64_t ldbw, ldxw;
     size_t bytes;
@@ -254,6 +255,8 @@ SolveWS<T> carve_solve(void *work, int64_t m, int64_t n, int nb, int S, int refi
         w.d32 = c.take<T>(w.ldxw * S);
         w.dmax = c.take<unsigned long long>(S);
         w.xmax = c.take<unsigned long long>(S);
+        w.smax = c.take<unsigned long long>(S);
+        w.s0 = c.take<double>(S);
         w.hist = c.take<double>(8);
         w.xs = c.take<double>(n * S);
         w.xbest = c.take<double>(n * S);
@@ -854,6 +857,7 @@ struct SolveRun {
     int max_iters;
     int method;      // CTQR_REFINE_CSNE or CTQR_REFINE_PCG
     bool progress;   // report each refinement iteration to the progress hook
+    bool pageable;   // read the end-of-refinement flag into ordinary host memory (no pinned word)
     int narrow;
     ctqr_info *info;
     SolveWS<T> w;
@@ -920,6 +924,7 @@ ctqr_status refine_setup(SolveRun<T> &r, hipStream_t st)
     if ((s = fill_f64(w.hist, 8, 0.0, st))) return s;
     if ((s = fill_u32((unsigned *)w.dmax, 2LL * S, 0u, st))) return s;
     if ((s = fill_u32((unsigned *)w.xmax, 2LL * S, 0u, st))) return s;
+    if ((s = fill_u32((unsigned *)w.smax, 2LL * S, 0u, st))) return s;
     if constexpr (sizeof(T) == 4) {
         if (r.split_r && (s = trsm_split_r(r.n, r.QR, r.lda, w.rparts, st))) return s;
     }
@@ -964,8 +969,15 @@ ctqr_status solve_start(SolveRun<T> &r, hipStream_t st)
 }
 
 // Reads the device-side end-of-refinement flag (synchronises the stream).
-ctqr_status read_done(const int *done, hipStream_t st, bool &out)
+ctqr_status read_done(const int *done, hipStream_t st, bool &out, bool pageable = false)
 {
+    if (pageable) {
+        int v = 0;
+        HIP_TRY(hipMemcpyAsync(&v, done, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        out = v != 0;
+        return CTQR_OK;
+    }
     int *flag = host_flag();
     if (!flag) return CTQR_EHIP;
     HIP_TRY(hipMemcpyAsync(flag, done, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -1001,6 +1013,7 @@ ctqr_status refine_iters_with(SolveRun<T> &r, int it0, int it1, bool host_sync, 
             if (s) return s;
             s = spmm_rowmajor(n, S, A->colptr, A->row, A->cval, 1.0, w.r, 0.0, nullptr, w.s, skip, st);
             if (s) return s;
+            if ((s = slice_absmax(n, S, w.s, w.smax, skip, st))) return s;
         }
         {
             PhaseScope ph(CTQR_PHASE_REFINE_TRSM, st);
@@ -1025,13 +1038,14 @@ ctqr_status refine_iters_with(SolveRun<T> &r, int it0, int it1, bool host_sync, 
         }
         // conjugate-gradient steps need not shrink monotonically: a longer
         // run of non-contracting steps ends that form
-        s = refine_check(S, w.dmax, w.xmax, r.tol, it, r.max_iters, pcg ? 6 : 2, w.hist, w.done, r.info, st);
+        s = refine_check(S, w.dmax, w.xmax, w.smax, w.s0, r.tol, it, r.max_iters, pcg ? 6 : 2, w.hist, w.done,
+                         r.info, st);
         if (s) return s;
         if ((s = refine_keep((int64_t)n * S, w.xs, w.xbest, w.hist, st))) return s;
         if (r.progress && (s = progress_mark(st, CTQR_PROGRESS_SOLVE, it + 1, r.max_iters))) return s;
         if (host_sync) {
             bool done = false;
-            if ((s = read_done(w.done, st, done))) return s;
+            if ((s = read_done(w.done, st, done, r.pageable))) return s;
             if (done) {
                 if (ran) *ran = it + 1;
                 break;
@@ -1082,11 +1096,12 @@ template <typename T>
 ctqr_status solve_impl(int64_t m64, int64_t n64, const T *QR, int64_t lda, const T *Tf,
                        const double *tau, const T *Rinv_in, int nb, const double *B, int64_t ldb, int S,
                        double *X, int64_t ldx, const ctqr_sparse *A64, double tol, int max_iters, int method,
-                       void *work, ctqr_info *info, hipStream_t st)
+                       void *work, ctqr_info *info, hipStream_t st, bool pageable = false)
 {
     (void)tau;
     SolveRun<T> r = make_run<T>(m64, n64, QR, lda, Tf, Rinv_in, nb, B, ldb, S, A64, tol, max_iters, work, info,
                                 true, method, TRSM_PARTS_ALL);
+    r.pageable = pageable;
     ctqr_status s = solve_start(r, st);
     if (s) return s;
     if (r.refine() && (s = refine_iters(r, 0, max_iters, true, st, nullptr))) return s;
@@ -2066,6 +2081,129 @@ ctqr_status ctqr_cond_estimate(int64_t m, int64_t n, ctqr_dtype dtype, const voi
                                      out, stream);
         return cond_impl<float>(m, n, (const float *)QR, lda, (const float *)Rinv, A64, nvec, iters, work, out,
                                 stream);
+    } catch (...) {
+        return CTQR_EHIP;
+    }
+}
+
+// ---- View-count search -------------------------------------------------------
+namespace {
+struct ViewSearchWS {
+    ctqr_info *info;
+    double *out, *A, *T, *tau, *Rinv, *val, *cval;
+    int64_t *rowptr, *colptr;
+    int32_t *col, *row;
+    void *qrwork, *bwork, *cwork;
+    size_t qrbytes, bbytes, cbytes, bytes;
+    int64_t lda, cap;
+};
+
+constexpr int VIEW_NB = 256;
+constexpr int VIEW_NVEC = 8;
+
+ViewSearchWS carve_view_search(void *work, const ctqr_geometry *g, int v_max)
+{
+    ctqr_geometry gm = *g;
+    gm.n_views = v_max;
+    const int64_t m = (int64_t)v_max * g->n_bins, n = (int64_t)g->side * g->side;
+    Carve c(work);
+    ViewSearchWS w{};
+    w.lda = round_up(m, 64);
+    w.cap = m * (2LL * g->side - 1);
+    w.info = c.take<ctqr_info>(1);
+    w.out = c.take<double>(4);
+    w.A = c.take<double>(w.lda * n);
+    w.T = c.take<double>((int64_t)VIEW_NB * n);
+    w.tau = c.take<double>(n);
+    w.Rinv = c.take<double>(2 * (int64_t)trinv_elems((int)n));
+    w.rowptr = c.take<int64_t>(m + 1);
+    w.col = c.take<int32_t>(w.cap);
+    w.val = c.take<double>(w.cap);
+    w.colptr = c.take<int64_t>(n + 1);
+    w.row = c.take<int32_t>(w.cap);
+    w.cval = c.take<double>(w.cap);
+    w.qrbytes = 0;
+    if (m >= n) (void)ctqr_qr_workspace(m, n, CTQR_F64, CTQR_PREC_FP64, VIEW_NB, &w.qrbytes);
+    w.qrwork = c.take<char>((int64_t)w.qrbytes);
+    w.bbytes = siddon_workspace(&gm);
+    w.bwork = c.take<char>((int64_t)w.bbytes);
+    w.cbytes = 0;
+    if (m >= n) (void)ctqr_cond_workspace(m, n, CTQR_F64, VIEW_NVEC, &w.cbytes);
+    w.cwork = c.take<char>((int64_t)w.cbytes);
+    w.bytes = c.off + 256;
+    return w;
+}
+}  // namespace
+
+ctqr_status ctqr_view_search_workspace(const ctqr_geometry *g, int32_t v_max, size_t *bytes)
+{
+    if (!bytes || !g || v_max < 1) return CTQR_EINVAL;
+    ctqr_geometry gm = *g;
+    gm.n_views = v_max;
+    if (!geometry_ok(&gm)) return CTQR_EINVAL;
+    *bytes = carve_view_search(nullptr, g, v_max).bytes;
+    return CTQR_OK;
+}
+
+ctqr_status ctqr_view_search(const ctqr_geometry *g, int32_t v_min, int32_t v_max, int32_t v_step, double kappa_max,
+                             int32_t iters, void *work, size_t work_bytes, ctqr_view_trial *trials,
+                             int32_t max_trials, int32_t *n_trials, int32_t *v_best, hipStream_t stream)
+{
+    try {
+        if (!g || !work || !trials || !n_trials || !v_best || v_min < 1 || v_max < v_min || v_step < 1 ||
+            max_trials < 1 || iters < 1 || !(kappa_max > 1.0))
+            return CTQR_EINVAL;
+        size_t need = 0;
+        ctqr_status s = ctqr_view_search_workspace(g, v_max, &need);
+        if (s) return s;
+        if (work_bytes < need || !aligned16(work)) return work_bytes < need ? CTQR_ENOMEM : CTQR_EINVAL;
+        ViewSearchWS w = carve_view_search(work, g, v_max);
+        const int64_t n = (int64_t)g->side * g->side;
+        *n_trials = 0;
+        *v_best = 0;
+        for (int v = v_min; v <= v_max && *n_trials < max_trials; v += v_step) {
+            ctqr_geometry gv = *g;
+            gv.n_views = v;
+            const int64_t m = (int64_t)v * g->n_bins;
+            ctqr_view_trial &t = trials[(*n_trials)++];
+            t.views = v;
+            t.status = CTQR_RANK_DEFICIENT;
+            t.kappa = INFINITY;
+            t.rdiag_min = t.rdiag_max = 0.0;
+            if (m < n) continue;   // fewer rays than pixels: never full column rank
+            if (!panel_fits((int)m, CTQR_F64)) return CTQR_EUNSUPPORTED;
+            ctqr_sparse sp{m, n, w.cap, w.rowptr, w.col, w.val, w.colptr, w.row, w.cval};
+            if ((s = ctqr_build_system_matrix(&gv, CTQR_F64, w.A, w.lda, &sp, w.bwork, w.bbytes, w.info, stream)))
+                return s;
+            ctqr_info bi{};
+            HIP_TRY(hipMemcpyAsync(&bi, w.info, sizeof(bi), hipMemcpyDeviceToHost, stream));
+            HIP_TRY(hipStreamSynchronize(stream));
+            if (bi.status) return CTQR_ENOMEM;   // sparse capacity: cannot happen with the upper bound
+            size_t qb = 0;
+            if ((s = ctqr_qr_workspace(m, n, CTQR_F64, CTQR_PREC_FP64, VIEW_NB, &qb))) return s;
+            if ((s = ctqr_qr_factor(m, n, CTQR_F64, w.A, w.lda, CTQR_PREC_FP64, VIEW_NB, w.T, w.tau, w.Rinv,
+                                    w.qrwork, w.qrbytes, w.info, stream)))
+                return s;
+            ctqr_info fi{};
+            HIP_TRY(hipMemcpyAsync(&fi, w.info, sizeof(fi), hipMemcpyDeviceToHost, stream));
+            HIP_TRY(hipStreamSynchronize(stream));
+            t.rdiag_min = fi.rdiag_min;
+            t.rdiag_max = fi.rdiag_max;
+            if (fi.status == CTQR_NONFINITE || fi.status == CTQR_BARRIER_TIMEOUT) return CTQR_EHIP;
+            if ((s = ctqr_cond_estimate(m, n, CTQR_F64, w.A, w.lda, w.Rinv, &sp, VIEW_NVEC, iters, w.cwork, w.cbytes,
+                                        w.out, stream)))
+                return s;
+            double est[3] = {0, 0, 0};
+            HIP_TRY(hipMemcpyAsync(est, w.out, sizeof(est), hipMemcpyDeviceToHost, stream));
+            HIP_TRY(hipStreamSynchronize(stream));
+            t.kappa = est[2];
+            if (fi.status == 0 && est[2] <= kappa_max) {
+                t.status = CTQR_OK;
+                *v_best = v;
+                break;
+            }
+        }
+        return CTQR_OK;
     } catch (...) {
         return CTQR_EHIP;
     }

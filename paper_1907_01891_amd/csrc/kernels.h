@@ -176,9 +176,15 @@ ctqr_status refine_update(int64_t n, int S, double *x, const TD *d, int64_t ldd,
                           hipStream_t st);
 // Converged when the relative update is <= tol; stall_limit consecutive
 // non-contracting updates, or max_iters, end it with CTQR_NOT_CONVERGED.
-// Also records the smallest update so far (hist[2..5]).
-ctqr_status refine_check(int S, unsigned long long *dmax, unsigned long long *xmax, double tol,
-                         int it, int max_iters, int stall_limit, double *hist, int *done, ctqr_info *info,
+// Also records the best iterate so far (hist[2..7]).
+// The best iterate is judged by smax (per-slice max |A^T (b - A x)| of the
+// iteration's starting iterate, from slice_absmax) relative to s0, the first
+// iteration's values (written at it = 0).
+ctqr_status refine_check(int S, unsigned long long *dmax, unsigned long long *xmax, unsigned long long *smax,
+                         double *s0, double tol, int it, int max_iters, int stall_limit, double *hist, int *done,
+                         ctqr_info *info, hipStream_t st);
+// smax[s] = max(smax[s], max_r |x[r, s]|) for a row-major rows x S array
+ctqr_status slice_absmax(int64_t rows, int S, const double *x, unsigned long long *smax, const int *skip,
                          hipStream_t st);
 // xbest = xs (count doubles) when the last refine_check found a new smallest update.
 ctqr_status refine_keep(int64_t count, const double *xs, double *xbest, const double *hist, hipStream_t st);

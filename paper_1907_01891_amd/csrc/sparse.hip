@@ -230,18 +230,49 @@ __global__ void refine_update_kernel(int64_t n, int S, double *__restrict__ x, c
     }
 }
 
+// smax[s] = max over rows of |x[r, s]| (row-major rows x S; bit patterns,
+// atomic max).  Block: 4 row groups x 64 slices.
+__global__ __launch_bounds__(256)
+void slice_absmax_kernel(int64_t rows, int S, const double *__restrict__ x, unsigned long long *smax,
+                         const int *skip)
+{
+    if (skip && *skip) return;
+    __shared__ unsigned long long red[4][64];
+    const int lane = threadIdx.x % 64, grp = threadIdx.x / 64;
+    const int s = blockIdx.y * 64 + lane;
+    unsigned long long m = 0;
+    if (s < S)
+        for (int64_t r = (int64_t)blockIdx.x * 4 + grp; r < rows; r += (int64_t)gridDim.x * 4) {
+            const unsigned long long b = order_bits(x[r * S + s]);
+            m = b > m ? b : m;
+        }
+    red[grp][lane] = m;
+    __syncthreads();
+    if (grp == 0 && s < S) {
+        for (int k = 1; k < 4; ++k) m = red[k][lane] > m ? red[k][lane] : m;
+        atomicMax(&smax[s], m);
+    }
+}
+
 // Decide convergence after refinement iteration `it` (0-based) and reset the
 // per-slice maxima for the next one.  The refinement has converged when
 // rel = max_s ||d_s||_inf / ||x_s||_inf <= tol.  It ends without converging
 // (CTQR_NOT_CONVERGED) after stall_limit consecutive updates that are no
 // smaller than 0.9x the previous one, or after max_iters.
+// Which iterate is best is judged by the normal-equation residual
+// s = A^T (b - A x) of the iterate before this iteration's update,
+// g = max_s ||s_s||_inf / ||s_s^(0)||_inf: s = A^T A e for the error e of that
+// iterate, whatever the quality of the preconditioner (the update itself
+// estimates e only when (R^T R)^-1 A^T A is close to I).
 // hist: [0] previous rel, [1] consecutive non-contracting updates, [2] the
-// smallest rel so far, [3] 1 once [2] is set, [4] 1 if this iteration set a
-// new smallest rel (the iterate before this update is the best one so far;
-// refine_keep copies it), [5] the iteration that set [2], [6] the first rel.
+// smallest g so far, [3] 1 once [2] is set, [4] 1 if this iteration set a new
+// smallest g (the iterate before this update is the best one so far;
+// refine_keep copies it), [5] the iteration that set [2], [6] the first rel,
+// [7] the rel of the iteration that set [2].
 __global__ __launch_bounds__(256)
-void refine_check_kernel(int S, unsigned long long *dmax, unsigned long long *xmax, double tol, int it,
-                         int max_iters, int stall_limit, double *hist, int *done, ctqr_info *info)
+void refine_check_kernel(int S, unsigned long long *dmax, unsigned long long *xmax, unsigned long long *smax,
+                         double *s0, double tol, int it, int max_iters, int stall_limit, double *hist, int *done,
+                         ctqr_info *info)
 {
     if (*done) {
         if (threadIdx.x == 0) hist[4] = 0.0;
@@ -257,29 +288,48 @@ void refine_check_kernel(int S, unsigned long long *dmax, unsigned long long *xm
         double rel = xv > 0.0 ? dv / xv : (dv > 0.0 ? INFINITY : 0.0);
         worst = fmax(worst, rel);
     }
+    // normal-equation residual of this iteration's starting iterate, relative
+    // to the first iteration's, per slice (zero slices count as 0)
+    __shared__ double gred[256];
+    double gw = 0.0;
+    for (int s = threadIdx.x; s < S; s += 256) {
+        unsigned long long a = smax[s];
+        if (a == ~0ull) { bad = true; continue; }
+        const double sv = __longlong_as_double((long long)a);
+        if (it == 0) s0[s] = sv;
+        const double b = s0[s];
+        gw = fmax(gw, b > 0.0 ? sv / b : 0.0);
+    }
     red[threadIdx.x] = bad ? INFINITY : worst;
+    gred[threadIdx.x] = gw;
     __syncthreads();
     for (int k = 128; k > 0; k >>= 1) {
-        if (threadIdx.x < k) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + k]);
+        if (threadIdx.x < k) {
+            red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + k]);
+            gred[threadIdx.x] = fmax(gred[threadIdx.x], gred[threadIdx.x + k]);
+        }
         __syncthreads();
     }
     for (int s = threadIdx.x; s < S; s += 256) {
         dmax[s] = 0;
         xmax[s] = 0;
+        smax[s] = 0;
     }
     if (threadIdx.x == 0) {
         double rel = red[0];
+        const double g = gred[0];
         info->iters = it + 1;
         info->x_iters = it + 1;
         info->max_rel_update = rel;
         if (it == 0) hist[6] = rel;
         info->contraction = (it > 0 && hist[6] > 0.0 && rel <= 1e300) ? pow(rel / hist[6], 1.0 / it) : 0.0;
-        const bool better = rel <= 1e300 && (hist[3] == 0.0 || rel < hist[2]);
+        const bool better = rel <= 1e300 && (hist[3] == 0.0 || g < hist[2]);
         hist[4] = better ? 1.0 : 0.0;
         if (better) {
-            hist[2] = rel;
+            hist[2] = g;
             hist[3] = 1.0;
             hist[5] = it;
+            hist[7] = rel;
         }
         if (!(rel <= 1e300)) {
             info_event(info, CTQR_NONFINITE, -1);
@@ -309,10 +359,11 @@ __global__ void refine_keep_kernel(int64_t count, const double *__restrict__ xs,
         xbest[e] = xs[e];
 }
 
-// After a refinement that did not converge: x = xbest, the iterate before the
-// smallest update, unless that update was the last one (the iteration was
-// still contracting, so the last iterate is the better one).  The info then
-// reports that iterate: x_iters updates, max_rel_update its own update.
+// After a refinement that did not converge: x = xbest, the iterate with the
+// smallest normal-equation residual, unless that was the last iteration's
+// starting iterate (the residual was still falling, so the last iterate is
+// kept).  The info then reports that iterate: x_iters updates,
+// max_rel_update the update computed from it.
 __global__ void refine_select_kernel(int64_t count, double *__restrict__ x, const double *__restrict__ xbest,
                                      const double *hist, ctqr_info *info)
 {
@@ -325,7 +376,7 @@ __global__ void refine_select_kernel(int64_t count, double *__restrict__ x, cons
     __syncthreads();
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         info->x_iters = best;
-        info->max_rel_update = hist[2];
+        info->max_rel_update = hist[7];
     }
 }
 
@@ -458,12 +509,21 @@ ctqr_status refine_select(int64_t count, double *x, const double *xbest, const d
     return CTQR_OK;
 }
 
-ctqr_status refine_check(int S, unsigned long long *dmax, unsigned long long *xmax, double tol,
-                         int it, int max_iters, int stall_limit, double *hist, int *done, ctqr_info *info,
+ctqr_status refine_check(int S, unsigned long long *dmax, unsigned long long *xmax, unsigned long long *smax,
+                         double *s0, double tol, int it, int max_iters, int stall_limit, double *hist, int *done,
+                         ctqr_info *info, hipStream_t st)
+{
+    LAUNCH_TRY(refine_check_kernel, dim3(1), dim3(256), 0, st, S, dmax, xmax, smax, s0, tol, it, max_iters,
+               stall_limit, hist, done, info);
+    return CTQR_OK;
+}
+
+ctqr_status slice_absmax(int64_t rows, int S, const double *x, unsigned long long *smax, const int *skip,
                          hipStream_t st)
 {
-    LAUNCH_TRY(refine_check_kernel, dim3(1), dim3(256), 0, st, S, dmax, xmax, tol, it, max_iters, stall_limit,
-               hist, done, info);
+    if (rows <= 0 || S <= 0) return CTQR_OK;
+    const unsigned gx = (unsigned)std::min<int64_t>(ceil_div(rows, 4), 1024);
+    LAUNCH_TRY(slice_absmax_kernel, dim3(gx, (unsigned)ceil_div(S, 64)), dim3(256), 0, st, rows, S, x, smax, skip);
     return CTQR_OK;
 }
 

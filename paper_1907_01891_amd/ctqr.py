@@ -45,6 +45,10 @@ class ctqr_sparse(ctypes.Structure):
                 ("colptr", c_vp), ("row", c_vp), ("cval", c_vp)]
 
 
+class ctqr_view_trial(ctypes.Structure):
+    _fields_ = [("views", c_i32), ("status", c_i32), ("kappa", c_dbl), ("rdiag_min", c_dbl), ("rdiag_max", c_dbl)]
+
+
 class ctqr_info(ctypes.Structure):
     _fields_ = [("status", c_i32), ("first_bad_col", c_i32), ("iters", c_i32), ("x_iters", c_i32),
                 ("max_rel_update", c_dbl), ("rdiag_max", c_dbl), ("rdiag_min", c_dbl), ("nnz", c_i64),
@@ -100,6 +104,9 @@ _SIGNATURES = {
     "ctqr_cond_workspace": (c_i32, [c_i64, c_i64, c_i32, c_i32, _P(c_sz)]),
     "ctqr_cond_estimate": (c_i32, [c_i64, c_i64, c_i32, c_vp, c_i64, c_vp, _P(ctqr_sparse), c_i32, c_i32, c_vp,
                                    c_sz, c_vp, c_vp]),
+    "ctqr_view_search_workspace": (c_i32, [_P(ctqr_geometry), c_i32, _P(c_sz)]),
+    "ctqr_view_search": (c_i32, [_P(ctqr_geometry), c_i32, c_i32, c_i32, c_dbl, c_i32, c_vp, c_sz,
+                                 _P(ctqr_view_trial), c_i32, _P(c_i32), _P(c_i32), c_vp]),
     "ctqr_spmm": (c_i32, [_P(ctqr_sparse), c_i32, c_dbl, c_vp, c_i64, c_dbl, c_vp, c_i64, c_vp]),
     "ctqr_set_progress": (c_i32, [ctqr_progress_fn, c_vp]),
     "ctqr_profile_enable": (c_i32, [c_i32]),
@@ -295,6 +302,22 @@ def ctqr_cond_estimate(m, n, dtype, QR_ptr, lda, rinv_ptr, sparse, nvec, iters, 
                        stream):
     return lib().ctqr_cond_estimate(m, n, dtype, QR_ptr, lda, rinv_ptr, ctypes.byref(sparse), nvec, iters, work_ptr,
                                     work_bytes, out_ptr, stream)
+
+
+def ctqr_view_search_workspace(geom, v_max):
+    b = c_sz()
+    check(lib().ctqr_view_search_workspace(ctypes.byref(geom), v_max, ctypes.byref(b)), "ctqr_view_search_workspace")
+    return b.value
+
+
+def ctqr_view_search(geom, v_min, v_max, v_step, kappa_max, iters, work_ptr, work_bytes, stream):
+    """Returns (status, v_best, [ctqr_view_trial])."""
+    cap = (v_max - v_min) // v_step + 1
+    trials = (ctqr_view_trial * cap)()
+    nt, vb = c_i32(), c_i32()
+    st = lib().ctqr_view_search(ctypes.byref(geom), v_min, v_max, v_step, kappa_max, iters, work_ptr, work_bytes,
+                                trials, cap, ctypes.byref(nt), ctypes.byref(vb), stream)
+    return st, vb.value, list(trials[:nt.value])
 
 
 def ctqr_spmm(sparse, nslices, alpha, X_ptr, ldx, beta, Y_ptr, ldy, stream):

@@ -357,3 +357,16 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+def view_search(geom_dict, v_min, v_max, v_step=1, kappa_max=1e8, iters=30, stream=None):
+    """ctqr_view_search for a geometry dict (its n_views is replaced by each
+    candidate): (v_best or 0, [ctqr_view_trial]).  The workspace is allocated
+    here for the largest candidate."""
+    g = geometry(dict(geom_dict, n_views=v_max))
+    ws = Workspace()
+    wp, wb = ws.get(C.ctqr_view_search_workspace(g, v_max))
+    st, vb, trials = C.ctqr_view_search(g, v_min, v_max, v_step, kappa_max, iters, wp, wb, stream_handle(stream))
+    C.check(st, "ctqr_view_search")
+    return vb, trials
+

@@ -144,16 +144,24 @@ def test_sparse_capacity_exceeded(gpu):
     assert (G.indices == Ao.indices).all() and np.abs(G.data - Ao.data).max() <= 1e-12
 
 
-def test_badly_scaled_column_not_converged(gpu):
-    # one column scaled by 1e-9: kappa(A) grows by about 1e9, the FP32
-    # factor's (R^T R)^-1 no longer contracts the error, and the refinement
-    # must say so and return its best iterate
-    _case("scaled column")
+def test_nearly_dependent_column_not_converged(gpu):
+    # column 200 replaced by column 100 plus a 1e-7 relative perturbation:
+    # kappa(A) is about 1e7, so the FP32 factor carries no information about
+    # that direction (its R_jj is at the level of FP32 rounding) and the
+    # corrections (R^T R)^-1 A^T r grow instead of contracting (the rate is
+    # about u32 kappa^2 >> 1).  The refinement must report CTQR_NOT_CONVERGED
+    # and return its best iterate.  (Scaling a column, by contrast, leaves
+    # Householder QR's columnwise backward error and the refinement's rate
+    # unchanged.)
+    _case("nearly dependent column")
     g, A, X, B = oracle_problem("ct24")
-    As = A.tocsc().astype(np.float64)
-    As[:, 200] = As[:, 200] * 1e-9
-    As = As.tocsr()
-    F, info = _factor(As.toarray().astype(np.float32), torch.float32, C.CTQR_PREC_FP32_MFMA, 64)
+    Ad = A.toarray()
+    rng = np.random.default_rng(8)
+    Ad[:, 200] = Ad[:, 100] + 1e-7 * np.linalg.norm(Ad[:, 100]) * rng.standard_normal(Ad.shape[0]) / np.sqrt(
+        Ad.shape[0])
+    import scipy.sparse as sps
+    As = sps.csr_matrix(Ad)
+    F, info = _factor(Ad.astype(np.float32), torch.float32, C.CTQR_PREC_FP32_MFMA, 64)
     assert info.status in (0, C.CTQR_RANK_DEFICIENT)
     Bd = to_colmajor(torch.as_tensor(B), dtype=torch.float64)
     X0 = download(F.solve(Bd))
@@ -161,8 +169,8 @@ def test_badly_scaled_column_not_converged(gpu):
     Xr = download(F.solve(Bd, sparse=spA.sp, tol=1e-12, max_iters=30))
     torch.cuda.synchronize()
     si = F.sinfo.read()
-    print("scaled column: status %d iters %d x_iters %d update %.2e" % (si.status, si.iters, si.x_iters,
-                                                                          si.max_rel_update))
+    print("nearly dependent column: factor status %d, refine status %d iters %d x_iters %d update %.2e "
+          "contraction %.2e" % (info.status, si.status, si.iters, si.x_iters, si.max_rel_update, si.contraction))
     assert si.status == C.CTQR_NOT_CONVERGED
     assert 0 <= si.x_iters <= si.iters <= 30
     assert np.isfinite(Xr).all()
