@@ -349,6 +349,33 @@ ctqr_status ctqr_qr_solve_slices(int64_t m, int64_t n, ctqr_dtype dtype,
                                  int32_t refine_method, void *work, size_t work_bytes,
                                  ctqr_info *info, hipStream_t stream);
 
+/* The solve of ctqr_qr_solve_slices for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same arguments without the workspace, which comes
+ * from a scratch array the library holds in device memory, one copy per GPU,
+ * of CTQR_NOALLOC_SCRATCH_BYTES (256 MiB), kept until the process ends.  The
+ * call allocates nothing: no hipMalloc, hipFree or allocating library
+ * routine, also not for the refinement, which reads its end-of-refinement
+ * flag into ordinary host memory.  Inputs, outputs and results are those of
+ * ctqr_qr_solve_slices (same kernels, same workspace layout).
+ *   Limit  returns CTQR_ENOMEM, with nothing enqueued, when
+ *          ctqr_solve_workspace(m, n, dtype, nb, nslices, refine) exceeds
+ *          CTQR_NOALLOC_SCRATCH_BYTES (the text is in ctqr_last_error).
+ *   Races  every call on one GPU uses that GPU's one scratch array: calls
+ *          that overlap on one GPU (other threads, other streams) race and
+ *          corrupt each other's results; order them.  The array keeps the
+ *          last call's contents; each call initialises what it reads.
+ * The first call on a device looks up the array's device address
+ * (hipGetSymbolAddress) with that device current. */
+#define CTQR_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+ctqr_status ctqr_qr_solve_slices_noalloc(int64_t m, int64_t n, ctqr_dtype dtype,
+                                         const void *QR, int64_t lda, const void *T,
+                                         const double *tau, const void *Rinv, int32_t nb,
+                                         const double *B, int64_t ldb, int32_t nslices,
+                                         double *X, int64_t ldx,
+                                         const ctqr_sparse *A64, double tol, int32_t max_iters,
+                                         int32_t refine_method, ctqr_info *info, hipStream_t stream);
+
 /* ---- Batched solver ------------------------------------------------------
  * One stored factorization serves a stream of reconstruction requests: the
  * factorization does not depend on B, so it is computed once and reused

@@ -10,6 +10,13 @@
 #include "common.h"
 #include "kernels.h"
 
+// Device scratch of ctqr_qr_solve_slices_noalloc, for callers that cannot
+// allocate: one copy per GPU, held until the process ends.  Host code never
+// passes this name to a kernel (on the host it is only a stand-in for the
+// device symbol); it uses the device address hipGetSymbolAddress returns for
+// each device (noalloc_scratch below).
+static __device__ __align__(256) unsigned char scratch[CTQR_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 constexpr int PANEL_W = 32;             // inner panel width
@@ -36,6 +43,7 @@ struct PhaseRec {
 };
 bool g_phase_on = false;
 std::vector<PhaseRec> g_phase;
+thread_local bool t_no_alloc = false;   // inside ctqr_qr_solve_slices_noalloc: no timing events
 
 struct PhaseScope {
     int phase;
@@ -43,6 +51,7 @@ struct PhaseScope {
     hipEvent_t a = nullptr;
     PhaseScope(int p, hipStream_t s) : phase(p), st(s)
     {
+        if (t_no_alloc) return;
         {
             std::lock_guard<std::mutex> lk(g_prof_mu);
             if (!g_phase_on) return;
@@ -1554,6 +1563,28 @@ ctqr_status cond_impl(int64_t m, int64_t n, const T *QR, int64_t lda, const T *R
     return cond_finish(w.est, out, st);
 }
 
+// Device address of `scratch` on the current device, looked up once per
+// device with that device current.
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+ctqr_status noalloc_scratch(void **out)
+{
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return CTQR_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return CTQR_EHIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return CTQR_OK;
+}
+
 bool geometry_ok(const ctqr_geometry *g)
 {
     if (!g) return false;
@@ -1848,6 +1879,54 @@ ctqr_status ctqr_qr_solve_slices(int64_t m, int64_t n, ctqr_dtype dtype, const v
 }
 
 namespace {
+ctqr_status ctqr_qr_solve_slices_noalloc(int64_t m, int64_t n, ctqr_dtype dtype, const void *QR, int64_t lda,
+                                         const void *T, const double *tau, const void *Rinv, int32_t nb,
+                                         const double *B, int64_t ldb, int32_t nslices, double *X, int64_t ldx,
+                                         const ctqr_sparse *A64, double tol, int32_t max_iters,
+                                         int32_t refine_method, ctqr_info *info, hipStream_t stream)
+{
+    try {
+        if (m < n || n < 1 || m >= INT32_MAX || nslices < 1) return CTQR_EINVAL;
+        if (!QR || !T || !tau || !B || !X || !info) return CTQR_EINVAL;
+        if (refine_method != CTQR_REFINE_CSNE && refine_method != CTQR_REFINE_PCG) return CTQR_EINVAL;
+        if (dtype != CTQR_F64 && dtype != CTQR_F32) return CTQR_EINVAL;
+        if (lda < m || lda % 4 != 0 || ldb < m || ldx < n) return CTQR_EINVAL;
+        if (!aligned16(QR) || !aligned16(T)) return CTQR_EINVAL;
+        nb = resolve_nb(nb);
+        if (!nb_ok(nb)) return CTQR_EINVAL;
+        if (A64 && (A64->m != m || A64->n != n || !A64->rowptr || !A64->col || !A64->val ||
+                    !A64->colptr || !A64->row || !A64->cval))
+            return CTQR_EINVAL;
+        if (A64 && (max_iters < 0 || !(tol >= 0.0))) return CTQR_EINVAL;
+        if (Rinv && !aligned16(Rinv)) return CTQR_EINVAL;
+        // the same workspace layout as ctqr_qr_solve_slices, in the scratch
+        size_t need = 0;
+        const int refine = A64 != nullptr && max_iters > 0 ? (refine_method == CTQR_REFINE_PCG ? 2 : 1) : 0;
+        ctqr_status s = ctqr_solve_workspace(m, n, dtype, nb, nslices, refine, &need);
+        if (s) return s;
+        if (need > CTQR_NOALLOC_SCRATCH_BYTES) {
+            g_last_error = "ctqr_qr_solve_slices_noalloc: the solve needs " + std::to_string(need) +
+                           " bytes of scratch, more than CTQR_NOALLOC_SCRATCH_BYTES (" +
+                           std::to_string((size_t)CTQR_NOALLOC_SCRATCH_BYTES) + ")";
+            return CTQR_ENOMEM;
+        }
+        void *work = nullptr;
+        if ((s = noalloc_scratch(&work))) return s;
+        struct NoAlloc {
+            NoAlloc() { t_no_alloc = true; }
+            ~NoAlloc() { t_no_alloc = false; }
+        } no_alloc;
+        if (dtype == CTQR_F64)
+            return solve_impl<double>(m, n, (const double *)QR, lda, (const double *)T, tau, (const double *)Rinv,
+                                      nb, B, ldb, nslices, X, ldx, A64, tol, max_iters, refine_method, work, info,
+                                      stream, true);
+        return solve_impl<float>(m, n, (const float *)QR, lda, (const float *)T, tau, (const float *)Rinv, nb, B,
+                                 ldb, nslices, X, ldx, A64, tol, max_iters, refine_method, work, info, stream, true);
+    } catch (...) {
+        return CTQR_EHIP;
+    }
+}
+
 ctqr_status solver_desc_check(const ctqr_solver_desc *d)
 {
     if (!d) return CTQR_EINVAL;

@@ -93,6 +93,9 @@ _SIGNATURES = {
     "ctqr_qr_solve_slices": (c_i32, [c_i64, c_i64, c_i32, c_vp, c_i64, c_vp, c_vp, c_vp, c_i32,
                                      c_vp, c_i64, c_i32, c_vp, c_i64, _P(ctqr_sparse), c_dbl, c_i32, c_i32,
                                      c_vp, c_sz, c_vp, c_vp]),
+    "ctqr_qr_solve_slices_noalloc": (c_i32, [c_i64, c_i64, c_i32, c_vp, c_i64, c_vp, c_vp, c_vp, c_i32,
+                                             c_vp, c_i64, c_i32, c_vp, c_i64, _P(ctqr_sparse), c_dbl, c_i32,
+                                             c_i32, c_vp, c_vp]),
     "ctqr_solver_workspace": (c_i32, [_P(ctqr_solver_desc), _P(c_sz)]),
     "ctqr_solver_create": (c_i32, [_P(ctqr_solver_desc), c_vp, c_sz, _P(c_vp)]),
     "ctqr_solver_tune": (c_i32, [c_vp, c_i32, c_vp]),
