@@ -118,8 +118,7 @@ def parse():
 
 
 # committed HBM-counter summaries of the trailing-update kernel, per product mode
-TRAFFIC_FILES = {"fp32": os.path.join(ROOT, "profiles", "gemm_nn_trailing_update_ct256_traffic.txt"),
-                 "bf16x3": os.path.join(ROOT, "profiles", "gemm_nn_bf16x3_trailing_update_ct256_traffic.txt")}
+TRAFFIC_FILES = {"bf16x3": os.path.join(ROOT, "profiles", "gemm_nn_bf16x3_trailing_update_ct256_traffic.txt")}
 # the trailing-update kernel of each mode, as rocprofv3 names it
 TRAILING_KERNEL = {"fp32": "gemm_nn_kernel<float, 1, 128, false, 0>",
                    "bf16x3": "gemm_nn_bf16x3_kernel<1>"}
@@ -163,7 +162,7 @@ def measured_traffic(workload, prec, launches):
     try:
         kv = dict(l.strip().split("=", 1) for l in open(TRAFFIC_FILES[prec])
                   if "=" in l and not l.lstrip().startswith("#"))
-    except OSError:
+    except (OSError, KeyError):
         return None
     if kv.get("workload") != workload or kv.get("gemm_hip_sha256") != gemm_source_hash():
         return None

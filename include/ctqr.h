@@ -490,6 +490,37 @@ ctqr_status ctqr_cond_estimate(int64_t m, int64_t n, ctqr_dtype dtype, const voi
                                const void *Rinv, const ctqr_sparse *A64, int32_t nvec, int32_t iters,
                                void *work, size_t work_bytes, double *out, hipStream_t stream);
 
+/* Sinogram simulation with Joseph's projector, the method the paper's
+ * sinograms come from (Section II-A, after Table I): B = J X for the scanner
+ * and grid of g.  Each ray is sampled once per pixel column (when it runs
+ * closer to the x axis; else once per pixel row) on the line through the pixel
+ * centres, the image is linearly interpolated there between the two nearest
+ * pixel centres of that column (row), pixels outside the image counting as
+ * zero, and each sample is weighted by the ray length between consecutive
+ * column (row) lines, in pixel pitches (the unit of A).  J differs from the
+ * Siddon A of ctqr_build_system_matrix, so least-squares reconstructions of
+ * J X with A carry a model error on top of noise.
+ *   X   device, n x nslices FP64 images (pixel iy * side + ix), leading dim ldx.
+ *   B   device, m x nslices FP64 output (row view * n_bins + bin), ldb.
+ * Thread per (ray, slice); the call only enqueues. */
+ctqr_status ctqr_project_joseph(const ctqr_geometry *g, int32_t nslices, const double *X, int64_t ldx,
+                                double *B, int64_t ldb, hipStream_t stream);
+
+/* Image-quality metrics of reconstructions (Section II-B): for each slice s,
+ * PSNR (Eq. 5, Eq. 6: 10 log10(max(I0)^2 / MSE), MSE over the side x side
+ * image, +inf for identical images) and the mean SSIM (Eq. 7) of X[:, s]
+ * against the reference Xref[:, s].  SSIM is evaluated on every 11 x 11 window
+ * inside the image with Gaussian weights (standard deviation 1.5 pixels,
+ * normalised to sum 1) for the window means, variances and covariance, and
+ * c1 = (0.01 L)^2, c2 = (0.03 L)^2 with L = data_range, or the reference
+ * image's max - min when data_range is 0; NaN when side < 11.
+ *   Xref, X  device, n x nslices FP64, leading dims ldr, ldx.
+ *   out      device, 2 nslices doubles: out[s] = PSNR (dB), out[nslices + s] = SSIM.
+ * One workgroup per slice, sums in a fixed order: reproducible. */
+ctqr_status ctqr_image_quality(int32_t side, int32_t nslices, const double *Xref, int64_t ldr,
+                               const double *X, int64_t ldx, double data_range, double *out,
+                               hipStream_t stream);
+
 /* View-count search: the smallest number of views for which A has full
  * column rank.  The direct method needs full rank (Section II-A, Section IV),
  * and the number of views that gives it depends on the resolution; Eq. 2

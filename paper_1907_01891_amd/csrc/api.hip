@@ -1494,9 +1494,9 @@ ctqr_status solver_tune_t(ctqr_solver_t *sv, hipStream_t st, int reps)
 // with the factor's R (sigma_min).  Workspace layout of cond_impl.
 template <typename T>
 struct CondWS {
-    double *x, *r, *y, *dots, *est;
-    T *z, *c, *yt, *w, *part;
-    int64_t ldn, ldm;
+    double *x, *r, *y, *dots, *est, *dpart;   // x, r, y row-major (slice index fastest)
+    T *z, *c, *yt, *w, *part;                 // column-major, leading dimension ldn
+    int64_t ldn;
     size_t bytes;
 };
 
@@ -1506,12 +1506,12 @@ CondWS<T> carve_cond(void *work, int64_t m, int64_t n, int S)
     Carve c(work);
     CondWS<T> w{};
     w.ldn = round_up(n, 4);
-    w.ldm = round_up(m, 4);
-    w.x = c.take<double>(w.ldn * S);
-    w.r = c.take<double>(w.ldm * S);
-    w.y = c.take<double>(w.ldn * S);
+    w.x = c.take<double>(n * S);
+    w.r = c.take<double>(m * S);
+    w.y = c.take<double>(n * S);
     w.dots = c.take<double>(2 * (int64_t)S);
     w.est = c.take<double>(4);
+    w.dpart = c.take<double>((int64_t)slice_dot_partial_elems(S));
     w.z = c.take<T>(w.ldn * S);
     w.c = c.take<T>(w.ldn * S);
     w.yt = c.take<T>(w.ldn * S);
@@ -1530,18 +1530,21 @@ ctqr_status cond_impl(int64_t m, int64_t n, const T *QR, int64_t lda, const T *R
     double *q = w.dots, *nrm = w.dots + S;
     ctqr_status s;
     if ((s = fill_f64(w.est, 4, 0.0, st))) return s;
-    // sigma_max(A)^2: largest Rayleigh quotient x^T A^T A x, ||x|| = 1
-    if ((s = cond_start<double>(n, S, w.x, w.ldn, 0x5eed0001ull, st))) return s;
-    if ((s = col_dot<double, double>(n, S, w.x, w.ldn, w.x, w.ldn, nrm, st))) return s;
-    if ((s = col_scale<double, double>(n, S, w.x, w.ldn, nrm, w.x, w.ldn, st))) return s;
+    // sigma_max(A)^2: largest Rayleigh quotient x^T A^T A x, ||x|| = 1; the
+    // vectors row-major for the gathers of the sparse products
+    if ((s = cond_start<double>(n, S, w.x, 0, 0x5eed0001ull, st))) return s;
+    if ((s = slice_dot(n, S, w.x, w.x, w.dpart, nrm, nullptr, st))) return s;
+    if ((s = rm_scale(n, S, w.x, nrm, st))) return s;
     for (int it = 0; it < iters; ++it) {
-        if ((s = spmm_colmajor(m, n, S, A->rowptr, A->col, A->val, 1.0, w.x, w.ldn, 0.0, w.r, w.ldm, st))) return s;
-        if ((s = spmm_colmajor(n, m, S, A->colptr, A->row, A->cval, 1.0, w.r, w.ldm, 0.0, w.y, w.ldn, st)))
+        if ((s = spmm_rowmajor(m, S, A->rowptr, A->col, A->val, 1.0, w.x, 0.0, nullptr, w.r, nullptr, st)))
             return s;
-        if ((s = col_dot<double, double>(n, S, w.x, w.ldn, w.y, w.ldn, q, st))) return s;
+        if ((s = spmm_rowmajor(n, S, A->colptr, A->row, A->cval, 1.0, w.r, 0.0, nullptr, w.y, nullptr, st)))
+            return s;
+        if ((s = slice_dot(n, S, w.x, w.y, w.dpart, q, nullptr, st))) return s;
         if ((s = cond_max(S, q, w.est, 0, st))) return s;
-        if ((s = col_dot<double, double>(n, S, w.y, w.ldn, w.y, w.ldn, nrm, st))) return s;
-        if ((s = col_scale<double, double>(n, S, w.y, w.ldn, nrm, w.x, w.ldn, st))) return s;
+        if ((s = slice_dot(n, S, w.y, w.y, w.dpart, nrm, nullptr, st))) return s;
+        if ((s = rm_scale(n, S, w.y, nrm, st))) return s;
+        std::swap(w.x, w.y);
     }
     // 1 / sigma_min(R)^2: largest Rayleigh quotient z^T (R^T R)^-1 z, ||z|| = 1
     if ((s = cond_start<T>(n, S, w.z, w.ldn, 0x5eed0002ull, st))) return s;
@@ -2160,6 +2163,32 @@ ctqr_status ctqr_cond_estimate(int64_t m, int64_t n, ctqr_dtype dtype, const voi
                                      out, stream);
         return cond_impl<float>(m, n, (const float *)QR, lda, (const float *)Rinv, A64, nvec, iters, work, out,
                                 stream);
+    } catch (...) {
+        return CTQR_EHIP;
+    }
+}
+
+ctqr_status ctqr_project_joseph(const ctqr_geometry *g, int32_t nslices, const double *X, int64_t ldx, double *B,
+                                int64_t ldb, hipStream_t stream)
+{
+    try {
+        if (!geometry_ok(g) || !X || !B || nslices < 1) return CTQR_EINVAL;
+        const int64_t m = (int64_t)g->n_views * g->n_bins, n = (int64_t)g->side * g->side;
+        if (ldx < n || ldb < m || m >= INT32_MAX) return CTQR_EINVAL;
+        return joseph_project(g, nslices, X, ldx, B, ldb, stream);
+    } catch (...) {
+        return CTQR_EHIP;
+    }
+}
+
+ctqr_status ctqr_image_quality(int32_t side, int32_t nslices, const double *Xref, int64_t ldr, const double *X,
+                               int64_t ldx, double data_range, double *out, hipStream_t stream)
+{
+    try {
+        if (side < 1 || nslices < 1 || !Xref || !X || !out || !(data_range >= 0.0)) return CTQR_EINVAL;
+        const int64_t n = (int64_t)side * side;
+        if (ldr < n || ldx < n) return CTQR_EINVAL;
+        return image_quality(side, nslices, Xref, ldr, X, ldx, data_range, out, stream);
     } catch (...) {
         return CTQR_EHIP;
     }

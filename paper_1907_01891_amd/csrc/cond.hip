@@ -1,6 +1,7 @@
 // Kernels of the condition-number estimate: start vectors, per-column dot
 // products and scaling, and the running maxima of the Rayleigh quotients.
-// All vectors are column-major (rows x S, leading dimension ld).
+// Vectors are column-major (rows x S, leading dimension ld) unless a kernel
+// says row-major (rows x S, slice index fastest).
 #include "common.h"
 #include "kernels.h"
 
@@ -15,15 +16,22 @@ __device__ inline uint64_t mix64(uint64_t z)
     return z ^ (z >> 31);
 }
 
-template <typename T>
+// x[r, s] uniform in [-1, 1): column-major (leading dimension ldx) or, with
+// RM, row-major
+template <typename T, bool RM>
 __global__ void cond_start_kernel(int64_t rows, int S, T *__restrict__ x, int64_t ldx, uint64_t seed)
 {
-    const int s = blockIdx.y;
-    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < rows;
-         r += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t total = rows * S;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = RM ? e / S : e % rows;
+        const int s = (int)(RM ? e % S : e / rows);
         const uint64_t h = mix64(seed ^ mix64(((uint64_t)s << 40) ^ (uint64_t)r));
-        // uniform in [-1, 1)
-        x[(int64_t)s * ldx + r] = (T)((double)(h >> 11) * (1.0 / 4503599627370496.0) - 1.0);
+        const T v = (T)((double)(h >> 11) * (1.0 / 4503599627370496.0) - 1.0);
+        if (RM)
+            x[e] = v;
+        else
+            x[(int64_t)s * ldx + r] = v;
     }
 }
 
@@ -62,6 +70,17 @@ __global__ void col_scale_kernel(int64_t rows, const TS *__restrict__ src, int64
         dst[(int64_t)s * ldd + r] = (TD)((double)src[(int64_t)s * lds + r] * f);
 }
 
+// x[r, s] *= 1 / sqrt(dots[s]) for a row-major rows x S array
+__global__ void rm_scale_kernel(int64_t rows, int S, double *__restrict__ x, const double *__restrict__ dots)
+{
+    const int64_t total = rows * S;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const double d = dots[e % S];
+        x[e] = d > 0.0 ? x[e] / sqrt(d) : 0.0;
+    }
+}
+
 // est[slot] = max(est[slot], max_s q[s]) (NaN is kept: it marks a failure)
 __global__ void cond_max_kernel(int S, const double *__restrict__ q, double *est, int slot)
 {
@@ -94,7 +113,11 @@ unsigned grid_rows(int64_t rows) { return (unsigned)std::min<int64_t>(ceil_div(r
 template <typename T>
 ctqr_status cond_start(int64_t rows, int S, T *x, int64_t ldx, uint64_t seed, hipStream_t st)
 {
-    LAUNCH_TRY(cond_start_kernel<T>, dim3(grid_rows(rows), (unsigned)S), dim3(256), 0, st, rows, S, x, ldx, seed);
+    const unsigned g = (unsigned)std::min<int64_t>(ceil_div(rows * S, 256), 4096);
+    if (ldx == 0)
+        LAUNCH_TRY((cond_start_kernel<T, true>), dim3(g), dim3(256), 0, st, rows, S, x, ldx, seed);
+    else
+        LAUNCH_TRY((cond_start_kernel<T, false>), dim3(g), dim3(256), 0, st, rows, S, x, ldx, seed);
     return CTQR_OK;
 }
 
@@ -112,6 +135,13 @@ ctqr_status col_scale(int64_t rows, int S, const TS *src, int64_t lds, const dou
 {
     LAUNCH_TRY((col_scale_kernel<TD, TS>), dim3(grid_rows(rows), (unsigned)S), dim3(256), 0, st, rows, src, lds,
                dots, dst, ldd);
+    return CTQR_OK;
+}
+
+ctqr_status rm_scale(int64_t rows, int S, double *x, const double *dots, hipStream_t st)
+{
+    const unsigned g = (unsigned)std::min<int64_t>(ceil_div(rows * S, 256), 4096);
+    LAUNCH_TRY(rm_scale_kernel, dim3(g), dim3(256), 0, st, rows, S, x, dots);
     return CTQR_OK;
 }
 

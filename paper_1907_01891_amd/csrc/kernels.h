@@ -138,6 +138,14 @@ ctqr_status rdiag_check(int n, const T *R, int64_t ldr, double *scratch, ctqr_in
 ctqr_status siddon_build(const ctqr_geometry *g, int dtype, void *A, int64_t lda, ctqr_sparse *sp,
                          void *work, size_t work_bytes, ctqr_info *info, hipStream_t st);
 size_t siddon_workspace(const ctqr_geometry *g);
+// B = J X with Joseph's projector (m x S and n x S, column-major FP64)
+ctqr_status joseph_project(const ctqr_geometry *g, int S, const double *X, int64_t ldx, double *B, int64_t ldb,
+                           hipStream_t st);
+
+// ---- quality.hip -------------------------------------------------------------
+// out[s] = PSNR, out[S + s] = mean SSIM of X[:, s] against Xref[:, s]
+ctqr_status image_quality(int side, int S, const double *Xref, int64_t ldr, const double *X, int64_t ldx,
+                          double data_range, double *out, hipStream_t st);
 // columns [c0, c1) of the dense A (FP64 or FP32) from the CSC copy
 ctqr_status sparse_to_dense_cols(const ctqr_sparse *sp, int dtype, int c0, int c1, void *A, int64_t lda,
                                  hipStream_t st);
@@ -209,7 +217,8 @@ ctqr_status pcg_step(int64_t rows, int S, double *x, const double *p, const doub
                      hipStream_t st);
 
 // ---- cond.hip (condition-number estimate) ------------------------------------
-// Column-major rows x S vectors: counter-hashed start values in [-1, 1),
+// Column-major rows x S vectors (cond_start: row-major when ldx = 0):
+// counter-hashed start values in [-1, 1),
 // FP64 column dot products (deterministic), scaling to unit norm, and the
 // running maximum of Rayleigh quotients (est[slot]); cond_finish writes
 // [sigma_max, sigma_min, kappa] from est[0] (A^T A) and est[1] ((R^T R)^-1).
@@ -221,5 +230,7 @@ ctqr_status col_dot(int64_t rows, int S, const TX *x, int64_t ldx, const TY *y, 
 template <typename TD, typename TS>
 ctqr_status col_scale(int64_t rows, int S, const TS *src, int64_t lds, const double *dots, TD *dst, int64_t ldd,
                       hipStream_t st);
+// x[r, s] /= sqrt(dots[s]) (row-major rows x S)
+ctqr_status rm_scale(int64_t rows, int S, double *x, const double *dots, hipStream_t st);
 ctqr_status cond_max(int S, const double *q, double *est, int slot, hipStream_t st);
 ctqr_status cond_finish(const double *est, double *out, hipStream_t st);

@@ -107,6 +107,8 @@ _SIGNATURES = {
     "ctqr_cond_workspace": (c_i32, [c_i64, c_i64, c_i32, c_i32, _P(c_sz)]),
     "ctqr_cond_estimate": (c_i32, [c_i64, c_i64, c_i32, c_vp, c_i64, c_vp, _P(ctqr_sparse), c_i32, c_i32, c_vp,
                                    c_sz, c_vp, c_vp]),
+    "ctqr_project_joseph": (c_i32, [_P(ctqr_geometry), c_i32, c_vp, c_i64, c_vp, c_i64, c_vp]),
+    "ctqr_image_quality": (c_i32, [c_i32, c_i32, c_vp, c_i64, c_vp, c_i64, c_dbl, c_vp, c_vp]),
     "ctqr_view_search_workspace": (c_i32, [_P(ctqr_geometry), c_i32, _P(c_sz)]),
     "ctqr_view_search": (c_i32, [_P(ctqr_geometry), c_i32, c_i32, c_i32, c_dbl, c_i32, c_vp, c_sz,
                                  _P(ctqr_view_trial), c_i32, _P(c_i32), _P(c_i32), c_vp]),
@@ -305,6 +307,14 @@ def ctqr_cond_estimate(m, n, dtype, QR_ptr, lda, rinv_ptr, sparse, nvec, iters, 
                        stream):
     return lib().ctqr_cond_estimate(m, n, dtype, QR_ptr, lda, rinv_ptr, ctypes.byref(sparse), nvec, iters, work_ptr,
                                     work_bytes, out_ptr, stream)
+
+
+def ctqr_project_joseph(geom, nslices, X_ptr, ldx, B_ptr, ldb, stream):
+    return lib().ctqr_project_joseph(ctypes.byref(geom), nslices, X_ptr, ldx, B_ptr, ldb, stream)
+
+
+def ctqr_image_quality(side, nslices, Xref_ptr, ldr, X_ptr, ldx, data_range, out_ptr, stream):
+    return lib().ctqr_image_quality(side, nslices, Xref_ptr, ldr, X_ptr, ldx, data_range, out_ptr, stream)
 
 
 def ctqr_view_search_workspace(geom, v_max):

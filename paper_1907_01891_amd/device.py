@@ -370,3 +370,27 @@ def view_search(geom_dict, v_min, v_max, v_step=1, kappa_max=1e8, iters=30, stre
     C.check(st, "ctqr_view_search")
     return vb, trials
 
+
+def project_joseph(geom_dict, X, B=None, stream=None):
+    """B = J X (ctqr_project_joseph): Joseph-projector sinograms of the images
+    in the columns of the column-major FP64 device tensor X."""
+    g = geometry(geom_dict)
+    m = g.n_views * g.n_bins
+    if B is None:
+        B = colmajor(m, X.shape[1], torch.float64, X.device)
+    C.check(C.ctqr_project_joseph(g, X.shape[1], ctypes.c_void_p(X.data_ptr()), ld_of(X),
+                                  ctypes.c_void_p(B.data_ptr()), ld_of(B), stream_handle(stream)),
+            "ctqr_project_joseph")
+    return B
+
+
+def image_quality(side, Xref, X, data_range=0.0, stream=None):
+    """(PSNR per slice, SSIM per slice) as host lists (ctqr_image_quality)."""
+    S = X.shape[1]
+    out = torch.empty(2 * S, dtype=torch.float64, device=X.device)
+    C.check(C.ctqr_image_quality(side, S, ctypes.c_void_p(Xref.data_ptr()), ld_of(Xref),
+                                 ctypes.c_void_p(X.data_ptr()), ld_of(X), float(data_range),
+                                 ctypes.c_void_p(out.data_ptr()), stream_handle(stream)), "ctqr_image_quality")
+    o = out.cpu().tolist()
+    return o[:S], o[S:]
+
