@@ -536,6 +536,103 @@ def phase_and_conditioning(args, log, C, F, A32, B, sp, Xmixed, sinfo, t_solve, 
     }
 
 
+def tile_qr_leg(log, name="ct64", b=64, nsl=8):
+    """The algorithm-by-blocks QR and solve (Section II-C; ctqr_tile_qr_*) on
+    the FP64 A of a smaller workload, timed, beside the blocked FP64 GPU path
+    on the same matrix (their solutions compared).  The tile tasks run FP64
+    arithmetic on the vector ALUs, one workgroup per b x b task."""
+    import torch
+    from synthetic import get_workload, phantom_batch
+    from paper_1907_01891_amd import ctqr as C
+    from paper_1907_01891_amd.device import SystemMatrix, QRFactor, TileQR, to_colmajor
+    w = get_workload(name)
+    S = SystemMatrix(w.geometry(), C.CTQR_F64, dense=True, sparse=True)
+    X = to_colmajor(torch.as_tensor(phantom_batch(w.side, nsl)), dtype=torch.float64)
+    B = S.spmm(X)
+    A0 = S.A.clone()
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    G = TileQR(S.A, b)
+    G.factor()                                     # warm-up (A overwritten)
+    S.A.copy_(A0)
+    torch.cuda.synchronize()
+    e0, e1, e2 = ev(), ev(), ev()
+    e0.record()
+    G.factor()
+    e1.record()
+    Xt = G.solve(B)
+    e2.record()
+    torch.cuda.synchronize()
+    t_f, t_s = e0.elapsed_time(e1), e1.elapsed_time(e2)
+    Ab = A0.clone()
+    Fb = QRFactor(Ab, C.CTQR_PREC_FP64, nb=256)
+    torch.cuda.synchronize()
+    e0.record()
+    Fb.factor()
+    e1.record()
+    Xb = Fb.solve(B)
+    e2.record()
+    torch.cuda.synchronize()
+    tb_f = e0.elapsed_time(e1)
+    diff = ((Xt - Xb).norm(dim=0) / Xb.norm(dim=0)).max().item()
+    rec = ((Xt - X).norm(dim=0) / X.norm(dim=0)).max().item()
+    fl = qr_flops(w.m, w.n)
+    tf = fl / (t_f * 1e-3) / 1e12
+    mt, nt = -(-w.m // b), -(-w.n // b)
+    out = {"workload": "%s: %d x %d FP64, blocks of %d (%d x %d blocks, %d tasks)"
+                       % (name, w.m, w.n, b, mt, nt, len(C.ctqr_tile_tasks(mt, nt, 0))),
+           "qr_ms": t_f, "qr_tflops": tf, "frac_of_fp64_peak": tf / PEAK_TFLOPS["f64"],
+           "solve_ms": t_s, "slices": nsl, "blocked_fp64_qr_ms": tb_f,
+           "blocked_fp64_qr_tflops": fl / (tb_f * 1e-3) / 1e12,
+           "rel_diff_vs_blocked_solution": diff, "recovery_rel_err": rec}
+    log("tile QR %s: %.1f ms (%.3f TFLOP/s, blocked FP64 %.1f ms), solve %.1f ms, vs blocked %.2e, recovery %.2e"
+        % (name, t_f, tf, tb_f, t_s, diff, rec))
+    return out
+
+
+def image_quality_leg(args, log, w, F, sp, Xtrue, Xc, n_clean):
+    """The evaluation around the solve (Section II-A, II-B): sinograms of the
+    phantoms simulated with Joseph's projector (ctqr_project_joseph, timed),
+    reconstructed with the mixed factor and the Siddon A (refined), and scored
+    with PSNR and SSIM (ctqr_image_quality, timed) against the phantoms; the
+    noise-free Siddon sinograms' reconstructions are scored the same way (the
+    setting of the paper's quality table: data consistent with A)."""
+    import numpy as np
+    import torch
+    from paper_1907_01891_amd.device import project_joseph, image_quality
+    g = w.geometry()
+    S = Xtrue.shape[1]
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    e0, e1, e2, e3 = ev(), ev(), ev(), ev()
+    project_joseph(g, Xtrue)                       # warm-up
+    e0.record()
+    BJ = project_joseph(g, Xtrue)
+    e1.record()
+    torch.cuda.synchronize()
+    t_j = e0.elapsed_time(e1)
+    XJ = F.solve(BJ, sparse=sp.sp, tol=args.tol, max_iters=args.max_iters, method=REFINE[args.refine])
+    torch.cuda.synchronize()
+    sj = F.sinfo.read()
+    image_quality(w.side, Xtrue, XJ)               # warm-up
+    e2.record()
+    pj, qj = image_quality(w.side, Xtrue, XJ)
+    e3.record()
+    torch.cuda.synchronize()
+    t_q = e2.elapsed_time(e3)
+    pc, qc = image_quality(w.side, Xtrue[:, :n_clean], Xc)
+    out = {"joseph_ms": t_j, "joseph_ray_slices_per_s": w.m * S / (t_j * 1e-3), "quality_ms": t_q,
+           "joseph_recon_refine_status": int(sj.status), "joseph_recon_refine_iters": int(sj.iters),
+           "joseph_psnr_db_mean": float(np.mean(pj)), "joseph_psnr_db_min": float(np.min(pj)),
+           "joseph_ssim_mean": float(np.mean(qj)), "joseph_ssim_min": float(np.min(qj)),
+           "consistent_psnr_db_min": float(np.min(pc)), "consistent_ssim_min": float(np.min(qc)),
+           "note": "Joseph sinograms reconstructed with the Siddon A carry a projector mismatch; the consistent "
+                   "(noise-free Siddon) reconstructions are the analogue of the paper's quality table"}
+    log("joseph: %.1f ms for %d x %d rays x slices; reconstructions PSNR mean %.2f dB, SSIM mean %.4f; consistent "
+        "data PSNR min %.1f dB, SSIM min %.6f; quality kernel %.2f ms"
+        % (t_j, w.m, S, out["joseph_psnr_db_mean"], out["joseph_ssim_mean"], out["consistent_psnr_db_min"],
+           out["consistent_ssim_min"], t_q))
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -661,6 +758,7 @@ def main():
     if not args.no_phases:
         extras = phase_and_conditioning(args, log, C, F, A32, B, sp, Xmixed, sinfo, t_solve, build_dense,
                                         m, n, S, dev)
+        extras["image_quality"] = image_quality_leg(args, log, w, F, sp, Xtrue, Xc, n_clean)
     log("mixed path done")
 
     stream_out = None
@@ -713,6 +811,11 @@ def main():
             torch.cuda.empty_cache()
     del A32, F
     torch.cuda.empty_cache()
+
+    tile = None
+    if not args.no_phases:
+        tile = tile_qr_leg(log)
+        torch.cuda.empty_cache()
 
     fp64 = {}
     if not args.no_fp64:
@@ -827,6 +930,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "request_stream": stream_out,
+        "tile_qr": tile,
         "wall_s_timed": wall,
     }
     out.update(fp64)

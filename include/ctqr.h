@@ -490,6 +490,69 @@ ctqr_status ctqr_cond_estimate(int64_t m, int64_t n, ctqr_dtype dtype, const voi
                                const void *Rinv, const ctqr_sparse *A64, int32_t nvec, int32_t iters,
                                void *work, size_t work_bytes, double *out, hipStream_t stream);
 
+/* ---- Algorithm-by-blocks QR and solve (Section II-C) ------------------------
+ * The matrix is cut into b x b blocks A_ij (1 <= b <= 64; the last block row
+ * and column may be smaller) and factored by tasks on a few blocks each, the
+ * paper's four generic tasks:
+ *   CTQR_TASK_DENSE_QR    Compute_dense_QR(A_kk, S_kk): Householder QR of A_kk
+ *                         (R on and above its diagonal, reflectors below; S_kk
+ *                         the compact-WY factor, H_1 ... H_c = I - V S V^T).
+ *   CTQR_TASK_TD_QR       Compute_TD_QR(A_kk, A_ik, S_ik): QR of the triangle
+ *                         R_kk stacked on the dense A_ik (reflectors [e_p; v_p],
+ *                         v_p into A_ik; S_ik for U = [I; A_ik]).
+ *   CTQR_TASK_APPLY_DENSE Apply_left_Qt_of_dense_QR(A_kk, S_kk, C).
+ *   CTQR_TASK_APPLY_TD    Apply_left_Qt_of_TD_QR(A_ik, S_ik, F, G).
+ * and for the solve X = R^-1 (Q^T B) the block substitution and product:
+ *   CTQR_TASK_TRSM        Trsm_lunn: B_i = upper(A_ii)^-1 B_i.
+ *   CTQR_TASK_GEMM        Gemm_nn_mo: B_i = -A_ij B_j + B_i.
+ * The factorization's tasks are generated in the left-looking order of the
+ * paper's task table (for each block column j: the transformations of every
+ * earlier block column k, dense then TD for each block row below, then the
+ * QR of block column j); the solve's in the order of its table (Q^T B block
+ * row by block row, then the substitution by block rows from the last).
+ * Householder vectors follow the larfg convention of ctqr_qr_factor. */
+typedef struct {
+    int32_t type;   /* CTQR_TASK_* */
+    int32_t i;      /* block row the task writes (the TD block; the B row) */
+    int32_t k;      /* block column of the reflectors it creates or applies */
+    int32_t j;      /* target block column (apply, factor: = k; gemm: the X block; solve apply: -1) */
+} ctqr_tile_task;
+#define CTQR_TASK_DENSE_QR    0
+#define CTQR_TASK_TD_QR       1
+#define CTQR_TASK_APPLY_DENSE 2
+#define CTQR_TASK_APPLY_TD    3
+#define CTQR_TASK_TRSM        4
+#define CTQR_TASK_GEMM        5
+
+/* The task list of the factorization (solve = 0) or of the solve (solve = 1)
+ * for mt x nt blocks (mt >= nt), in execution order (host only).  tasks may
+ * be NULL to query *count; otherwise up to cap entries are written. */
+ctqr_status ctqr_tile_tasks(int32_t mt, int32_t nt, int32_t solve, ctqr_tile_task *tasks, int64_t cap,
+                            int64_t *count);
+
+/* Sizes for ctqr_tile_qr_factor / ctqr_tile_qr_solve (host only): the S
+ * factors (*s_elems doubles: one b x b block per block (i, k), i >= k, at
+ * S + (k mt + i) b^2, column-major) and the device workspace (the task list
+ * of the larger of the two runs). */
+ctqr_status ctqr_tile_qr_sizes(int64_t m, int64_t n, int32_t b, int64_t *s_elems, size_t *work_bytes);
+
+/* Algorithm-by-blocks QR of the FP64 A (device, m x n, m >= n, leading dim
+ * lda), in place: R above, reflectors below each diagonal block and in the
+ * blocks under it; S (device) receives the S factors.  The tasks run in
+ * dependency levels (a task waits for the tasks whose blocks it reads or
+ * overwrites; the tasks of one level and type go in one launch, one workgroup
+ * per task).  The call waits on the stream once, after uploading the task
+ * list to work; the kernels are only enqueued. */
+ctqr_status ctqr_tile_qr_factor(int64_t m, int64_t n, double *A, int64_t lda, int32_t b, double *S,
+                                void *work, size_t work_bytes, hipStream_t stream);
+
+/* X = R^-1 (Q^T B) with the outputs of ctqr_tile_qr_factor (same m, n, b):
+ * B (device, m x nslices FP64, leading dim ldb) is overwritten, its first n
+ * rows receiving X.  Waits on the stream once (task list upload). */
+ctqr_status ctqr_tile_qr_solve(int64_t m, int64_t n, const double *QR, int64_t lda, int32_t b, const double *S,
+                               double *B, int64_t ldb, int32_t nslices, void *work, size_t work_bytes,
+                               hipStream_t stream);
+
 /* Sinogram simulation with Joseph's projector, the method the paper's
  * sinograms come from (Section II-A, after Table I): B = J X for the scanner
  * and grid of g.  Each ray is sampled once per pixel column (when it runs

@@ -2168,6 +2168,70 @@ ctqr_status ctqr_cond_estimate(int64_t m, int64_t n, ctqr_dtype dtype, const voi
     }
 }
 
+ctqr_status ctqr_tile_tasks(int32_t mt, int32_t nt, int32_t solve, ctqr_tile_task *tasks, int64_t cap,
+                            int64_t *count)
+{
+    try {
+        if (mt < 1 || nt < 1 || mt < nt || !count || (solve != 0 && solve != 1) || (tasks && cap < 0))
+            return CTQR_EINVAL;
+        const std::vector<int4> v = solve ? tile_solve_tasks(mt, nt) : tile_qr_tasks(mt, nt);
+        *count = (int64_t)v.size();
+        if (tasks)
+            for (int64_t q = 0; q < std::min<int64_t>(cap, (int64_t)v.size()); ++q)
+                tasks[q] = ctqr_tile_task{v[q].x, v[q].y, v[q].z, v[q].w};
+        return CTQR_OK;
+    } catch (...) {
+        return CTQR_EHIP;
+    }
+}
+
+ctqr_status ctqr_tile_qr_sizes(int64_t m, int64_t n, int32_t b, int64_t *s_elems, size_t *work_bytes)
+{
+    if (!s_elems || !work_bytes || m < n || n < 1 || b < 1 || b > 64 || m >= INT32_MAX) return CTQR_EINVAL;
+    const int64_t mt = ceil_div(m, b), nt = ceil_div(n, b);
+    *s_elems = mt * nt * (int64_t)b * b;
+    // apply tasks of the factorization: sum over j of sum_{k<j} (mt - k); plus
+    // the factor tasks; the solve has fewer
+    int64_t cnt = 0;
+    for (int64_t j = 0; j < nt; ++j) cnt += j * mt - j * (j - 1) / 2 + (mt - j);
+    const int64_t scnt = nt * mt - nt * (nt - 1) / 2 + nt * (nt + 1) / 2;
+    *work_bytes = (size_t)std::max(cnt, scnt) * 16 + 256;
+    return CTQR_OK;
+}
+
+ctqr_status ctqr_tile_qr_factor(int64_t m, int64_t n, double *A, int64_t lda, int32_t b, double *S, void *work,
+                                size_t work_bytes, hipStream_t stream)
+{
+    try {
+        int64_t se = 0;
+        size_t wb = 0;
+        ctqr_status s = ctqr_tile_qr_sizes(m, n, b, &se, &wb);
+        if (s) return s;
+        if (!A || !S || !work || lda < m) return CTQR_EINVAL;
+        if (work_bytes < wb) return CTQR_ENOMEM;
+        return tile_qr_run((int)m, (int)n, b, A, lda, S, (int4 *)work, stream);
+    } catch (...) {
+        return CTQR_EHIP;
+    }
+}
+
+ctqr_status ctqr_tile_qr_solve(int64_t m, int64_t n, const double *QR, int64_t lda, int32_t b, const double *S,
+                               double *B, int64_t ldb, int32_t nslices, void *work, size_t work_bytes,
+                               hipStream_t stream)
+{
+    try {
+        int64_t se = 0;
+        size_t wb = 0;
+        ctqr_status s = ctqr_tile_qr_sizes(m, n, b, &se, &wb);
+        if (s) return s;
+        if (!QR || !S || !B || !work || lda < m || ldb < m || nslices < 1) return CTQR_EINVAL;
+        if (work_bytes < wb) return CTQR_ENOMEM;
+        return tile_solve_run((int)m, (int)n, b, QR, lda, S, B, ldb, nslices, (int4 *)work, stream);
+    } catch (...) {
+        return CTQR_EHIP;
+    }
+}
+
 ctqr_status ctqr_project_joseph(const ctqr_geometry *g, int32_t nslices, const double *X, int64_t ldx, double *B,
                                 int64_t ldb, hipStream_t stream)
 {

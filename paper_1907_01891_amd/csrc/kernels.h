@@ -234,3 +234,17 @@ ctqr_status col_scale(int64_t rows, int S, const TS *src, int64_t lds, const dou
 ctqr_status rm_scale(int64_t rows, int S, double *x, const double *dots, hipStream_t st);
 ctqr_status cond_max(int S, const double *q, double *est, int slot, hipStream_t st);
 ctqr_status cond_finish(const double *est, double *out, hipStream_t st);
+
+// ---- tiles.hip (algorithm-by-blocks QR and solve) -------------------------------
+#include <vector>
+// task lists in the order of the paper's task tables (x type, y i, z k, w j)
+std::vector<int4> tile_qr_tasks(int mt, int nt);
+std::vector<int4> tile_solve_tasks(int mt, int nt);
+// dependency level of each task (its reads and writes of blocks, S factors, B rows)
+std::vector<int> tile_levels(const std::vector<int4> &tasks, int mt, int nt, bool solve);
+// run the factorization / solve on the stream (dtasks: device room for the
+// task list; waits on the stream once, after uploading it)
+ctqr_status tile_qr_run(int m, int n, int b, double *A, int64_t lda, double *Sf, int4 *dtasks, hipStream_t st);
+ctqr_status tile_solve_run(int m, int n, int b, const double *A, int64_t lda, const double *Sf, double *B,
+                           int64_t ldb, int S, int4 *dtasks, hipStream_t st);
+

@@ -49,6 +49,10 @@ class ctqr_view_trial(ctypes.Structure):
     _fields_ = [("views", c_i32), ("status", c_i32), ("kappa", c_dbl), ("rdiag_min", c_dbl), ("rdiag_max", c_dbl)]
 
 
+class ctqr_tile_task(ctypes.Structure):
+    _fields_ = [("type", c_i32), ("i", c_i32), ("k", c_i32), ("j", c_i32)]
+
+
 class ctqr_info(ctypes.Structure):
     _fields_ = [("status", c_i32), ("first_bad_col", c_i32), ("iters", c_i32), ("x_iters", c_i32),
                 ("max_rel_update", c_dbl), ("rdiag_max", c_dbl), ("rdiag_min", c_dbl), ("nnz", c_i64),
@@ -107,6 +111,10 @@ _SIGNATURES = {
     "ctqr_cond_workspace": (c_i32, [c_i64, c_i64, c_i32, c_i32, _P(c_sz)]),
     "ctqr_cond_estimate": (c_i32, [c_i64, c_i64, c_i32, c_vp, c_i64, c_vp, _P(ctqr_sparse), c_i32, c_i32, c_vp,
                                    c_sz, c_vp, c_vp]),
+    "ctqr_tile_tasks": (c_i32, [c_i32, c_i32, c_i32, _P(ctqr_tile_task), c_i64, _P(c_i64)]),
+    "ctqr_tile_qr_sizes": (c_i32, [c_i64, c_i64, c_i32, _P(c_i64), _P(c_sz)]),
+    "ctqr_tile_qr_factor": (c_i32, [c_i64, c_i64, c_vp, c_i64, c_i32, c_vp, c_vp, c_sz, c_vp]),
+    "ctqr_tile_qr_solve": (c_i32, [c_i64, c_i64, c_vp, c_i64, c_i32, c_vp, c_vp, c_i64, c_i32, c_vp, c_sz, c_vp]),
     "ctqr_project_joseph": (c_i32, [_P(ctqr_geometry), c_i32, c_vp, c_i64, c_vp, c_i64, c_vp]),
     "ctqr_image_quality": (c_i32, [c_i32, c_i32, c_vp, c_i64, c_vp, c_i64, c_dbl, c_vp, c_vp]),
     "ctqr_view_search_workspace": (c_i32, [_P(ctqr_geometry), c_i32, _P(c_sz)]),
@@ -307,6 +315,32 @@ def ctqr_cond_estimate(m, n, dtype, QR_ptr, lda, rinv_ptr, sparse, nvec, iters, 
                        stream):
     return lib().ctqr_cond_estimate(m, n, dtype, QR_ptr, lda, rinv_ptr, ctypes.byref(sparse), nvec, iters, work_ptr,
                                     work_bytes, out_ptr, stream)
+
+
+CTQR_TASK_DENSE_QR, CTQR_TASK_TD_QR, CTQR_TASK_APPLY_DENSE, CTQR_TASK_APPLY_TD, CTQR_TASK_TRSM, CTQR_TASK_GEMM = range(6)
+
+
+def ctqr_tile_tasks(mt, nt, solve):
+    """[(type, i, k, j)] of the factorization (solve=0) or the solve (solve=1)."""
+    cnt = c_i64()
+    check(lib().ctqr_tile_tasks(mt, nt, solve, None, 0, ctypes.byref(cnt)), "ctqr_tile_tasks")
+    arr = (ctqr_tile_task * max(1, cnt.value))()
+    check(lib().ctqr_tile_tasks(mt, nt, solve, arr, cnt.value, ctypes.byref(cnt)), "ctqr_tile_tasks")
+    return [(t.type, t.i, t.k, t.j) for t in arr[:cnt.value]]
+
+
+def ctqr_tile_qr_sizes(m, n, b):
+    se, wb = c_i64(), c_sz()
+    check(lib().ctqr_tile_qr_sizes(m, n, b, ctypes.byref(se), ctypes.byref(wb)), "ctqr_tile_qr_sizes")
+    return se.value, wb.value
+
+
+def ctqr_tile_qr_factor(m, n, A_ptr, lda, b, S_ptr, work_ptr, work_bytes, stream):
+    return lib().ctqr_tile_qr_factor(m, n, A_ptr, lda, b, S_ptr, work_ptr, work_bytes, stream)
+
+
+def ctqr_tile_qr_solve(m, n, QR_ptr, lda, b, S_ptr, B_ptr, ldb, nslices, work_ptr, work_bytes, stream):
+    return lib().ctqr_tile_qr_solve(m, n, QR_ptr, lda, b, S_ptr, B_ptr, ldb, nslices, work_ptr, work_bytes, stream)
 
 
 def ctqr_project_joseph(geom, nslices, X_ptr, ldx, B_ptr, ldb, stream):

@@ -394,3 +394,31 @@ def image_quality(side, Xref, X, data_range=0.0, stream=None):
     o = out.cpu().tolist()
     return o[:S], o[S:]
 
+
+class TileQR:
+    """Algorithm-by-blocks QR (ctqr_tile_qr_factor) of a column-major FP64
+    device matrix, in place, with block size b, and its solve."""
+
+    def __init__(self, A, b):
+        self.A, self.b = A, b
+        self.m, self.n = A.shape
+        se, wb = C.ctqr_tile_qr_sizes(self.m, self.n, b)
+        self.S = torch.zeros(max(se, 1), dtype=torch.float64, device=A.device)
+        self.work = torch.empty(wb, dtype=torch.uint8, device=A.device)
+
+    def factor(self, stream=None):
+        C.check(C.ctqr_tile_qr_factor(self.m, self.n, ctypes.c_void_p(self.A.data_ptr()), ld_of(self.A), self.b,
+                                      ctypes.c_void_p(self.S.data_ptr()), ctypes.c_void_p(self.work.data_ptr()),
+                                      self.work.numel(), stream_handle(stream)), "ctqr_tile_qr_factor")
+        return self
+
+    def solve(self, B, stream=None):
+        """X = R^-1 Q^T B (B is copied; returns the n x S solution)."""
+        Bw = colmajor(self.m, B.shape[1], torch.float64, B.device)
+        Bw.copy_(B)
+        C.check(C.ctqr_tile_qr_solve(self.m, self.n, ctypes.c_void_p(self.A.data_ptr()), ld_of(self.A), self.b,
+                                     ctypes.c_void_p(self.S.data_ptr()), ctypes.c_void_p(Bw.data_ptr()), ld_of(Bw),
+                                     B.shape[1], ctypes.c_void_p(self.work.data_ptr()), self.work.numel(),
+                                     stream_handle(stream)), "ctqr_tile_qr_solve")
+        return Bw[:self.n]
+
