@@ -95,7 +95,9 @@ def parse():
     p.add_argument("--nb", type=int, default=0,
                    help="outer block width; 0 = picked by ctqr_qr_tune_nb on the benchmark's own A (untimed)")
     p.add_argument("--max-iters", type=int, default=30)
-    p.add_argument("--tol", type=float, default=1e-12)
+    p.add_argument("--tol", type=float, default=1e-11,
+                   help="refinement tolerance on the relative update (the error that remains is about the "
+                        "contraction rate times it)")
     p.add_argument("--prec", choices=["bf16x3", "fp32"], default="bf16x3",
                    help="block-column products of the mixed path: split-BF16 MFMA or FP32 MFMA")
     p.add_argument("--refine", choices=["csne", "pcg"], default="csne",
@@ -110,6 +112,12 @@ def parse():
     p.add_argument("--ooc-tile", type=int, default=8192, help="columns per streamed host tile")
     p.add_argument("--ooc-dev-cols", type=int, default=0,
                    help="cap on the HBM-resident columns (0: as many as fit)")
+    p.add_argument("--ooc-slices", default="",
+                   help="out of core: comma-separated slice counts, each solved in one pass after one "
+                        "factorization (default: the workload's count)")
+    p.add_argument("--save-check", default="",
+                   help="out of core: directory for .npz files of a few solutions and their sinograms, for the "
+                        "host-side least-squares check against the oracle's sparse A")
     p.add_argument("--no-phases", action="store_true",
                    help="skip the untimed phase breakdown, condition estimate and solve roofline (profiled runs)")
     p.add_argument("--calibrate-copy", action="store_true",
@@ -361,12 +369,14 @@ def request_stream_bench(args, log, F256, sp256, B256):
 def ooc_bench(args, log):
     """Out-of-core leg (a matrix whose dense FP32 copy does not fit in HBM):
     the sparse FP64 A and the sinograms are built on the GPU; as many leading
-    columns of the dense FP32 A as fit stay in HBM, the rest go to pinned host
-    memory in tiles (dense column tiles rebuilt from the sparse copy); the
-    factorization streams the host tiles (ctqr_qr_factor_ooc) and the solve
-    of all slices streams them once per pass (ctqr_qr_solve_ooc), refined
-    with FP64 sparse residuals.  Checks: least-squares optimality of every
-    noisy slice and exact recovery of two noise-free slices."""
+    columns of the dense FP32 A as leave room for the largest solve stay in
+    HBM, the rest go to pinned host memory in tiles (dense column tiles rebuilt
+    from the sparse copy); the factorization streams the host tiles
+    (ctqr_qr_factor_ooc) once, then each slice count S is solved in one pass
+    group that streams them once per substitution (ctqr_qr_solve_ooc), refined
+    with FP64 sparse residuals (the paper's Table V times this solve for
+    S = 256 ... 2048, Section III-B).  Checks per S: least-squares optimality
+    of the noisy slices and exact recovery of two noise-free slices."""
     import numpy as np
     import torch
     from synthetic import get_workload, phantom_batch, noise_batch, NOISE_REL_LEVEL
@@ -374,10 +384,13 @@ def ooc_bench(args, log):
     from paper_1907_01891_amd.device import (SystemMatrix, OocFactor, colmajor, to_colmajor, round_up, ld_of,
                                              stream_handle)
     w = get_workload(args.workload)
-    m, n, S = w.m, w.n, w.n_slices
+    m, n = w.m, w.n
+    slist = [int(v) for v in args.ooc_slices.split(",")] if args.ooc_slices else [w.n_slices]
+    S_max = max(slist)
+    n_clean = 2
     dev = torch.device("cuda:0")
     args.nb = args.nb or 256   # the out-of-core factorization is not tuned (tiles are multiples of 256)
-    log("workload %s m=%d n=%d slices=%d (out of core)" % (w.name, m, n, S))
+    log("workload %s m=%d n=%d slices=%s (out of core)" % (w.name, m, n, slist))
     C.ctqr_set_progress(lambda st, d, t: log("%s %d/%d" % ("factor columns" if st == 1 else "solve iterations",
                                                           d, t)))
     t0 = time.perf_counter()
@@ -385,25 +398,35 @@ def ooc_bench(args, log):
     torch.cuda.synchronize()
     nnz = sp.nnz()
     log("sparse A: nnz %d (%.1f s)" % (nnz, time.perf_counter() - t0))
-    n_clean = 2
-    Xtrue = to_colmajor(torch.as_tensor(phantom_batch(w.side, S)), dtype=torch.float64)
-    B = sp.spmm(Xtrue)
-    torch.cuda.synchronize()
-    sigma = NOISE_REL_LEVEL * B.abs().amax(dim=0)
-    sigma[S - n_clean:] = 0.0
-    B.add_(torch.as_tensor(noise_batch(w.side, m, S), device=dev) * sigma[None, :])
+    # the inputs of the largest solve: S_max phantoms (the last n_clean
+    # noise-free) and their sinograms, kept in host memory between solves
+    Xtrue_h = torch.as_tensor(phantom_batch(w.side, S_max))
+    B_h = torch.empty((m, S_max), dtype=torch.float64)
+    for c0 in range(0, S_max, 256):
+        c1 = min(S_max, c0 + 256)
+        Xd = to_colmajor(Xtrue_h[:, c0:c1], dtype=torch.float64)
+        Bd = sp.spmm(Xd)
+        torch.cuda.synchronize()
+        sigma = NOISE_REL_LEVEL * Bd.abs().amax(dim=0)
+        Z = torch.as_tensor(noise_batch(w.side, m, c1 - c0, first=c0), device=dev)
+        B_h[:, c0:c1] = (Bd + Z * sigma[None, :]).cpu()
+        del Xd, Bd, Z
     lda = round_up(m, 64)
     col_bytes = lda * 4
     tile = args.ooc_tile
     free, total = torch.cuda.mem_get_info()
-    reserve = 3 * tile * col_bytes + 2 * 2048 * round_up(n, 2048) * 4 + 4 * 256 * n * 4 + int(6e9)
+    solve_ws = C.ctqr_solve_ooc_workspace(m, n, C.CTQR_F32, args.nb, S_max, REFINE[args.refine] + 1, lda, tile)
+    io = 8 * S_max * (2 * m + 3 * n)          # B, the phantoms, X, and the check's residuals and products
+    reserve = (3 * tile * col_bytes + 2 * 2048 * round_up(n, 2048) * 4 + 4 * 256 * n * 4 + solve_ws + io
+               + int(6e9))
     n_dev = max(0, (free - reserve) // col_bytes // tile * tile)
     n_dev = min(n_dev, (n // tile) * tile)
     if args.ooc_dev_cols:
         n_dev = min(n_dev, args.ooc_dev_cols)
     host_gb = (n - n_dev) * col_bytes / 1e9
-    log("HBM free %.1f GB of %.1f: %d resident columns (%.1f GB), %d host columns (%.1f GB pinned), tiles of %d"
-        % (free / 1e9, total / 1e9, n_dev, n_dev * col_bytes / 1e9, n - n_dev, host_gb, tile))
+    log("HBM free %.1f GB of %.1f: %d resident columns (%.1f GB), %d host columns (%.1f GB pinned), tiles of %d; "
+        "solve workspace for %d slices %.1f GB" % (free / 1e9, total / 1e9, n_dev, n_dev * col_bytes / 1e9, n - n_dev,
+                                                   host_gb, tile, S_max, solve_ws / 1e9))
     O = OocFactor(m, n, C.CTQR_F32, prec_codes(C)[args.prec], n_dev, tile, nb=args.nb)
     t0 = time.perf_counter()
     if n_dev > 0:
@@ -431,47 +454,65 @@ def ooc_bench(args, log):
     log("ooc qr: %.1f s, %.2f TFLOP/s, status %d" % (t_qr * 1e-3, qr_tf, finfo.status))
     O.work.buf = None
     torch.cuda.empty_cache()
-    e2, e3 = ev(), ev()
-    e2.record()
-    X = O.solve(B, sparse=sp.sp, tol=args.tol, max_iters=args.max_iters, method=REFINE[args.refine])
-    e3.record()
-    torch.cuda.synchronize()
-    t_solve = e2.elapsed_time(e3)
-    sinfo = O.sinfo.read()
-    log("ooc solve: %.1f s for %d slices, refine iters %d status %d" % (t_solve * 1e-3, S, sinfo.iters,
-                                                                       sinfo.status))
-    # least-squares optimality ||A^T r|| / (||A||_F ||r||), r = b - A x (FP64, sparse)
-    R = colmajor(m, S, torch.float64, dev)
-    R.copy_(B)
-    sp.spmm(X, alpha=-1.0, beta=1.0, Y=R)
     spT = C.ctqr_sparse(n, m, sp.sp.nnz_cap, sp.colptr.data_ptr(), sp.row.data_ptr(), sp.cval.data_ptr(),
                         sp.rowptr.data_ptr(), sp.col.data_ptr(), sp.val.data_ptr())
-    G = colmajor(n, S, torch.float64, dev)
-    C.check(C.ctqr_spmm(spT, S, 1.0, ctypes.c_void_p(R.data_ptr()), ld_of(R), 0.0,
-                        ctypes.c_void_p(G.data_ptr()), ld_of(G), stream_handle()), "ctqr_spmm")
-    torch.cuda.synchronize()
     normA = sp.val[:nnz].pow(2).sum().sqrt().item()
-    noisy = slice(0, S - n_clean)
-    opt = (G[:, noisy].norm(dim=0) / (normA * R[:, noisy].norm(dim=0))).max().item()
-    rec = ((X[:, S - n_clean:] - Xtrue[:, S - n_clean:]).norm(dim=0)
-           / Xtrue[:, S - n_clean:].norm(dim=0)).max().item()
-    log("ls optimality max %.2e, noise-free recovery %.2e" % (opt, rec))
+    solves = []
+    for S in slist:
+        # the first S - n_clean noisy slices and the n_clean noise-free ones
+        cols = list(range(S - n_clean)) + list(range(S_max - n_clean, S_max))
+        B = to_colmajor(B_h[:, cols], dtype=torch.float64)
+        Xt = to_colmajor(Xtrue_h[:, cols], dtype=torch.float64)
+        Bc = sp.spmm(Xt[:, S - n_clean:])                 # noise-free sinograms of the last slices
+        B[:, S - n_clean:].copy_(Bc)
+        del Bc
+        torch.cuda.synchronize()
+        e2, e3 = ev(), ev()
+        e2.record()
+        X = O.solve(B, sparse=sp.sp, tol=args.tol, max_iters=args.max_iters, method=REFINE[args.refine])
+        e3.record()
+        torch.cuda.synchronize()
+        t_solve = e2.elapsed_time(e3)
+        sinfo = O.sinfo.read()
+        # least-squares optimality ||A^T r|| / (||A||_F ||r||), r = b - A x (FP64, sparse)
+        R = colmajor(m, S, torch.float64, dev)
+        R.copy_(B)
+        sp.spmm(X, alpha=-1.0, beta=1.0, Y=R)
+        G = colmajor(n, S, torch.float64, dev)
+        C.check(C.ctqr_spmm(spT, S, 1.0, ctypes.c_void_p(R.data_ptr()), ld_of(R), 0.0,
+                            ctypes.c_void_p(G.data_ptr()), ld_of(G), stream_handle()), "ctqr_spmm")
+        torch.cuda.synchronize()
+        noisy = slice(0, S - n_clean)
+        opt = (G[:, noisy].norm(dim=0) / (normA * R[:, noisy].norm(dim=0))).max().item()
+        rec = ((X[:, S - n_clean:] - Xt[:, S - n_clean:]).norm(dim=0) / Xt[:, S - n_clean:].norm(dim=0)).max().item()
+        log("ooc solve S=%d: %.1f s (%.4f s per slice), refine iters %d status %d, ls optimality %.2e, "
+            "noise-free recovery %.2e" % (S, t_solve * 1e-3, t_solve * 1e-3 / S, sinfo.iters, sinfo.status, opt, rec))
+        solves.append({"slices": S, "solve_ms": t_solve, "s_per_slice": t_solve * 1e-3 / S,
+                       "slices_per_s": S / (t_solve * 1e-3), "refine_iters": int(sinfo.iters),
+                       "refine_status": int(sinfo.status), "ls_optimality_max": opt, "recovery_rel_err_max": rec})
+        if args.save_check:
+            os.makedirs(args.save_check, exist_ok=True)
+            keep = [0, 1, S - 2, S - 1]
+            np.savez(os.path.join(args.save_check, "%s_S%d.npz" % (w.name, S)), X=X[:, keep].cpu().numpy(),
+                     B=B[:, keep].cpu().numpy(), Xtrue=Xt[:, keep].cpu().numpy(), noise_free=np.array([0, 0, 1, 1]))
+        del B, Xt, X, R, G
+        torch.cuda.empty_cache()
     C.ctqr_set_progress(None)
+    head = solves[0]
     return {
         "metric": "QR TFLOP/s + slices/s at %d^2, out of core (A larger than HBM)" % w.side,
         "value": qr_tf, "unit": "TFLOP/s", "n_gpus": 1, "steps": 1, "warmup": 0,
-        "ms_per_step": t_qr + t_solve, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "%s: %dx%d image, %d views x %d bins (m=%d, n=%d), %d ellipse-phantom slices "
-                               "(%d noise-free); FP32 A %.1f GB: %d columns in HBM, %d in pinned host memory, "
-                               "tiles of %d" % (w.name, w.side, w.side, w.n_views, w.n_bins, m, n, S, n_clean,
-                                                m * n * 4 / 1e9, n_dev, n - n_dev, tile),
-                   "nb": args.nb, "slices": S, "parallelism": "single GPU"},
-        "qr_ms": t_qr, "solve_ms": t_solve, "slices_per_s": S / (t_solve * 1e-3), "fill_s": t_fill,
-        "qr_info_status": int(finfo.status), "rdiag_min_max": [finfo.rdiag_min, finfo.rdiag_max],
-        "refine_method": args.refine, "refine_iters": int(sinfo.iters), "refine_status": int(sinfo.status),
-        "ls_optimality_max": opt, "recovery_rel_err_max": rec, "nnz": nnz,
-        "resident_columns": int(n_dev), "host_columns": int(n - n_dev), "host_gb": host_gb,
+        "ms_per_step": t_qr + head["solve_ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16" if args.prec == "bf16x3" else "f32", "data": "synthetic",
+        "config": {"workload": "%s: %dx%d image, %d views x %d bins (m=%d, n=%d), ellipse-phantom slices "
+                               "(%d noise-free per solve); FP32 A %.1f GB: %d columns in HBM, %d in pinned host "
+                               "memory, tiles of %d" % (w.name, w.side, w.side, w.n_views, w.n_bins, m, n, n_clean,
+                                                        m * n * 4 / 1e9, n_dev, n - n_dev, tile),
+                   "nb": args.nb, "slices": slist, "parallelism": "single GPU"},
+        "qr_ms": t_qr, "fill_s": t_fill, "qr_info_status": int(finfo.status),
+        "rdiag_min_max": [finfo.rdiag_min, finfo.rdiag_max], "refine_method": args.refine, "tol": args.tol,
+        "solves": solves, "nnz": nnz, "resident_columns": int(n_dev), "host_columns": int(n - n_dev),
+        "host_gb": host_gb,
     }
 
 
