@@ -34,6 +34,7 @@ if ROOT not in sys.path:
 
 PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6, "bf16": 2500.0}
 REFINE = {"csne": 0, "pcg": 1}
+CHECK_CHUNK = 256          # slices per chunk of the out-of-core optimality check
 
 
 def prec_codes(C):
@@ -416,9 +417,11 @@ def ooc_bench(args, log):
     tile = args.ooc_tile
     free, total = torch.cuda.mem_get_info()
     solve_ws = C.ctqr_solve_ooc_workspace(m, n, C.CTQR_F32, args.nb, S_max, REFINE[args.refine] + 1, lda, tile)
-    io = 8 * S_max * (2 * m + 3 * n)          # B, the phantoms, X, and the check's residuals and products
-    reserve = (3 * tile * col_bytes + 2 * 2048 * round_up(n, 2048) * 4 + 4 * 256 * n * 4 + solve_ws + io
-               + int(6e9))
+    # the factorization's three tiles and the solve's workspace are never live
+    # together (the factor's workspace is freed before the first solve)
+    io = 8 * S_max * (m + 2 * n) + 8 * CHECK_CHUNK * (m + n)   # B, phantoms, X; the check's chunk buffers
+    reserve = (max(3 * tile * col_bytes, solve_ws + io) + 2 * 2048 * round_up(n, 2048) * 4 + 4 * 256 * n * 4
+               + int(5e9))
     n_dev = max(0, (free - reserve) // col_bytes // tile * tile)
     n_dev = min(n_dev, (n // tile) * tile)
     if args.ooc_dev_cols:
@@ -474,16 +477,20 @@ def ooc_bench(args, log):
         torch.cuda.synchronize()
         t_solve = e2.elapsed_time(e3)
         sinfo = O.sinfo.read()
-        # least-squares optimality ||A^T r|| / (||A||_F ||r||), r = b - A x (FP64, sparse)
-        R = colmajor(m, S, torch.float64, dev)
-        R.copy_(B)
-        sp.spmm(X, alpha=-1.0, beta=1.0, Y=R)
-        G = colmajor(n, S, torch.float64, dev)
-        C.check(C.ctqr_spmm(spT, S, 1.0, ctypes.c_void_p(R.data_ptr()), ld_of(R), 0.0,
-                            ctypes.c_void_p(G.data_ptr()), ld_of(G), stream_handle()), "ctqr_spmm")
-        torch.cuda.synchronize()
-        noisy = slice(0, S - n_clean)
-        opt = (G[:, noisy].norm(dim=0) / (normA * R[:, noisy].norm(dim=0))).max().item()
+        # least-squares optimality ||A^T r|| / (||A||_F ||r||), r = b - A x (FP64,
+        # sparse), over the noisy slices in chunks
+        opt = 0.0
+        for c0 in range(0, S - n_clean, CHECK_CHUNK):
+            c1 = min(S - n_clean, c0 + CHECK_CHUNK)
+            R = colmajor(m, c1 - c0, torch.float64, dev)
+            R.copy_(B[:, c0:c1])
+            sp.spmm(X[:, c0:c1], alpha=-1.0, beta=1.0, Y=R)
+            G = colmajor(n, c1 - c0, torch.float64, dev)
+            C.check(C.ctqr_spmm(spT, c1 - c0, 1.0, ctypes.c_void_p(R.data_ptr()), ld_of(R), 0.0,
+                                ctypes.c_void_p(G.data_ptr()), ld_of(G), stream_handle()), "ctqr_spmm")
+            torch.cuda.synchronize()
+            opt = max(opt, (G.norm(dim=0) / (normA * R.norm(dim=0))).max().item())
+            del R, G
         rec = ((X[:, S - n_clean:] - Xt[:, S - n_clean:]).norm(dim=0) / Xt[:, S - n_clean:].norm(dim=0)).max().item()
         log("ooc solve S=%d: %.1f s (%.4f s per slice), refine iters %d status %d, ls optimality %.2e, "
             "noise-free recovery %.2e" % (S, t_solve * 1e-3, t_solve * 1e-3 / S, sinfo.iters, sinfo.status, opt, rec))
@@ -495,7 +502,7 @@ def ooc_bench(args, log):
             keep = [0, 1, S - 2, S - 1]
             np.savez(os.path.join(args.save_check, "%s_S%d.npz" % (w.name, S)), X=X[:, keep].cpu().numpy(),
                      B=B[:, keep].cpu().numpy(), Xtrue=Xt[:, keep].cpu().numpy(), noise_free=np.array([0, 0, 1, 1]))
-        del B, Xt, X, R, G
+        del B, Xt, X
         torch.cuda.empty_cache()
     C.ctqr_set_progress(None)
     head = solves[0]
