@@ -339,7 +339,15 @@ ctqr_status ctqr_solve_workspace(int64_t m, int64_t n, ctqr_dtype dtype, int32_t
  *          rule above; the conjugate-gradient form allows a longer run of
  *          non-shrinking updates, 6, before it stops).
  *   info   device: iterations, last relative update, CTQR_NOT_CONVERGED /
- *          CTQR_NONFINITE. */
+ *          CTQR_NONFINITE (CTQR_BARRIER_TIMEOUT: see below).
+ * Few slices, as an option: with the environment variable CTQR_FUSED=1 set
+ * (read at every call), a solve of nslices <= 16 (nb a multiple of 64 up to
+ * 256, the rows of B within the LDS of one workgroup per compute unit) runs
+ * Q^T B and every block substitution as persistent kernels, one cooperative
+ * launch each, with the same blocks and the same products per block, summed
+ * in a fixed order (each slice's result does not depend on how many slices
+ * share the call).  The default launch-per-block path is faster on MI355X at
+ * every slice count measured. */
 ctqr_status ctqr_qr_solve_slices(int64_t m, int64_t n, ctqr_dtype dtype,
                                  const void *QR, int64_t lda, const void *T,
                                  const double *tau, const void *Rinv, int32_t nb,
@@ -386,7 +394,11 @@ ctqr_status ctqr_qr_solve_slices_noalloc(int64_t m, int64_t n, ctqr_dtype dtype,
  * bucket >= S -- the powers of two up to 64, then the multiples of 64 (the
  * extra slices are zero and do not change the others' results).  Each bucket's solve -- Q^T B, the back substitution and, with
  * refinement, a calibrated number of refinement iterations -- is captured
- * once into a HIP graph and replayed on the caller's stream.
+ * once into a HIP graph and replayed on the caller's stream.  With the
+ * persistent kernels of ctqr_qr_solve_slices selected (CTQR_FUSED=1), the
+ * buckets of at most 16 slices they take enqueue those kernels directly
+ * instead (a few launches per request, no graph), with the same calibrated
+ * iteration count.
  *
  * Refinement (A64 != NULL, max_iters > 0) follows ctqr_qr_solve_slices.  The
  * first request of a bucket runs eagerly and counts its iterations; the
@@ -400,9 +412,11 @@ ctqr_status ctqr_qr_solve_slices_noalloc(int64_t m, int64_t n, ctqr_dtype dtype,
  * Memory: the solver owns no device memory; the caller passes a workspace
  * of ctqr_solver_workspace bytes, which must outlive the solver.  The
  * factor, T, tau, Rinv and the sparse arrays are referenced, not copied, and
- * must stay valid and unmodified.  Host memory: the graphs and a capture
- * stream.  One solve at a time per solver (calls are serialised by a lock);
- * solvers with different workspaces are independent. */
+ * must stay valid and unmodified.  Host memory: the graphs, a capture
+ * stream and an event.  Calls on one solver are serialised: on the host by a
+ * lock, on the GPU by an event that each call records after its work and
+ * that the next call's stream waits for, so calls may come from different
+ * streams.  Solvers with different workspaces are independent. */
 typedef struct ctqr_solver_t *ctqr_solver;
 
 typedef struct {
@@ -432,7 +446,8 @@ ctqr_status ctqr_solver_create(const ctqr_solver_desc *desc, void *work, size_t 
 /* Autotuner: times Q^T B plus the back substitution of every bucket with the
  * 32-wide and with the 128-wide slice tile of the MFMA products (reps timed
  * runs each, after one warm-up) and keeps the faster (untuned buckets use the
- * 32-wide tile up to 32 slices).  Overwrites the solver's request
+ * 32-wide tile up to 32 slices; buckets of the persistent kernels are
+ * skipped).  Overwrites the solver's request
  * buffer; waits on the stream.  Buckets whose choice changed are recalibrated
  * and recaptured on their next use. */
 ctqr_status ctqr_solver_tune(ctqr_solver solver, int32_t reps, hipStream_t stream);
@@ -457,8 +472,9 @@ ctqr_status ctqr_solver_solve_batch(ctqr_solver solver, int32_t nreq, const doub
                                     const int64_t *ldx, ctqr_info *info, hipStream_t stream);
 
 /* For a request of nslices: its bucket, the slice-tile width its products use
- * (32 or 128) and the refinement iterations its captured graph holds (-1: no
- * graph yet; 0 without refinement).  Host only. */
+ * (32 or 128) and the refinement iterations its captured graph holds, or a
+ * persistent-kernel bucket enqueues per request (-1: not run yet; 0 without
+ * refinement).  Host only. */
 ctqr_status ctqr_solver_query(ctqr_solver solver, int32_t nslices, int32_t *bucket,
                               int32_t *slice_tile, int32_t *graph_iters);
 

@@ -4,6 +4,7 @@
 #include <string>
 #include <vector>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <cmath>
 
@@ -208,6 +209,8 @@ struct SolveWS {
     unsigned long long *dmax, *xmax, *smax;
     double *s0;
     int *done;
+    T *fex;                  // exchange area of the persistent kernels (few slices), or null
+    unsigned *fbar;          // and their grid-barrier words
     int64_t ldbw, ldxw;
     size_t bytes;
 };
@@ -254,6 +257,10 @@ SolveWS<T> carve_solve(void *work, int64_t m, int64_t n, int nb, int S, int refi
     }
     w.Xw = c.take<T>(w.ldxw * S);
     w.done = c.take<int>(64);
+    if (S <= FUSED_MAX_S) {
+        w.fex = c.take<T>((int64_t)fused_exchange_elems());
+        w.fbar = c.take<unsigned>(GB_WORDS);
+    }
     if (refine) {
         w.xr = c.take<double>(n * S);
         w.Br = c.take<double>(m * S);
@@ -873,9 +880,28 @@ struct SolveRun {
     int64_t sp_elems;
     TrsmParts tp{};  // split-BF16 parts of the refinement's substitutions (tp.x null: none)
     bool split_r;    // R's parts are made by this run (refine_setup), not kept by a solver
+    bool fused;      // Q^T B and the substitutions as the persistent kernels (few slices, factor in HBM)
     bool refine() const { return A64 != nullptr && max_iters > 0; }
     const TrsmParts *parts() const { return tp.x ? &tp : nullptr; }
 };
+
+// The persistent kernels take at most FUSED_MAX_S slices, block reflectors
+// of whole 64-row chunks up to 256 wide, and right-hand sides whose rows fit
+// their LDS.  They are selected by the environment variable CTQR_FUSED=1,
+// read at every solve: on MI355X the launch-per-block chains are faster at
+// every slice count measured (each compute unit owns too few rows of R for
+// long column reads), so they are the default.
+bool fused_enabled()
+{
+    const char *e = std::getenv("CTQR_FUSED");
+    return e && e[0] == '1';
+}
+
+template <typename T>
+bool fused_eligible(int64_t m, int nb, int S)
+{
+    return fused_enabled() && S <= FUSED_MAX_S && nb % 64 == 0 && nb <= 256 && fused_fits(m, sizeof(T));
+}
 
 template <typename T>
 SolveRun<T> make_run(int64_t m, int64_t n, const T *QR, int64_t lda, const T *Tf, const T *Rinv, int nb,
@@ -895,6 +921,7 @@ SolveRun<T> make_run(int64_t m, int64_t n, const T *QR, int64_t lda, const T *Tf
     r.tp.x = r.w.xparts;
     r.tp.r = r.w.rparts;
     r.split_r = r.w.rparts != nullptr;
+    r.fused = fused_eligible<T>(m, nb, S) && r.w.fex != nullptr;
     return r;
 }
 
@@ -956,8 +983,13 @@ ctqr_status solve_start(SolveRun<T> &r, hipStream_t st)
     {
         // working copy of B in the factor's precision
         PhaseScope ph(CTQR_PHASE_QTB, st);
-        if ((s = copy_cm<T, double>(m, S, r.B, r.ldb, w.Bw, w.ldbw, st))) return s;
-        if ((s = apply_qt_range(r, r.QR, 0, n, st))) return s;
+        if (r.fused) {
+            s = qtb_fused<T>(m, n, nb, S, r.QR, r.lda, r.Tf, r.B, r.ldb, w.Bw, w.ldbw, w.fex, w.fbar, r.info, st);
+            if (s) return s;
+        } else {
+            if ((s = copy_cm<T, double>(m, S, r.B, r.ldb, w.Bw, w.ldbw, st))) return s;
+            if ((s = apply_qt_range(r, r.QR, 0, n, st))) return s;
+        }
     }
     {
         // back substitution R X = (Q^T B)[0:n], with the factor's diagonal-block
@@ -967,7 +999,12 @@ ctqr_status solve_start(SolveRun<T> &r, hipStream_t st)
             if ((s = trinv_blocks<T>(n, r.QR, r.lda, w.Rinv, w.RinvT, r.info, st))) return s;
             r.Rinv = w.Rinv;
         }
-        s = trsm_upper<T>(n, S, r.QR, r.lda, r.Rinv, w.Bw, w.ldbw, w.Xw, w.ldxw, w.split, r.sp_elems, nullptr, st);
+        if (r.fused)
+            s = trsm_fused<T>(n, S, false, r.QR, r.lda, r.Rinv, w.Bw, w.ldbw, w.Xw, w.ldxw, w.fex, w.fbar, nullptr,
+                              r.info, st);
+        else
+            s = trsm_upper<T>(n, S, r.QR, r.lda, r.Rinv, w.Bw, w.ldbw, w.Xw, w.ldxw, w.split, r.sp_elems, nullptr,
+                              st);
         if (s) return s;
     }
     PhaseScope ph(CTQR_PHASE_REFINE_OTHER, st);
@@ -1070,6 +1107,13 @@ ctqr_status refine_iters(SolveRun<T> &r, int it0, int it1, bool host_sync, hipSt
 {
     SolveWS<T> &w = r.w;
     auto minv = [&](const int *skip) -> ctqr_status {
+        if (r.fused) {
+            ctqr_status s = trsm_fused<T>(r.n, r.S, true, r.QR, r.lda, r.Rinv, w.s32, w.ldxw, w.y32, w.ldxw, w.fex,
+                                          w.fbar, skip, r.info, st);
+            if (s) return s;
+            return trsm_fused<T>(r.n, r.S, false, r.QR, r.lda, r.Rinv, w.y32, w.ldxw, w.d32, w.ldxw, w.fex, w.fbar,
+                                 skip, r.info, st);
+        }
         ctqr_status s = trsm_upper_trans<T>(r.n, r.S, r.QR, r.lda, r.Rinv, w.s32, w.ldxw, w.y32, w.ldxw, w.split,
                                             r.sp_elems, skip, st, r.parts());
         if (s) return s;
@@ -1196,6 +1240,7 @@ ctqr_status solve_ooc_impl(int64_t m64, int64_t n64, const T *QR_dev, const T *Q
 {
     SolveRun<T> r = make_run<T>(m64, n64, QR_dev, lda, Tf, Rinv, nb, B, ldb, S, A64, tol, max_iters, work, info,
                                 false, method);
+    r.fused = false;   // the column tiles of the factor stream through; the persistent kernels need all of it
     r.progress = true;
     Carve c(work);
     c.off = r.w.bytes;
@@ -1245,8 +1290,9 @@ struct SolverBucket {
     int S = 0;
     int narrow = 0;            // slice-tile threshold of its GEMMs
     int iters = -1;            // refinement iterations of its calibration run (-1: none yet)
-    int graph_iters = 0;       // refinement iterations the graph holds
+    int graph_iters = 0;       // refinement iterations the graph holds (or a direct run enqueues)
     hipGraphExec_t exec = nullptr;
+    bool direct = false;       // run through the persistent kernels, without a graph
 };
 
 int next_pow2(int x)
@@ -1285,8 +1331,27 @@ struct ctqr_solver_t {
     __bf16 *rparts = nullptr;   // R's split-BF16 parts (wide refined buckets), made once
     bool rparts_ready = false;
     hipStream_t cap = nullptr;  // capture stream (never executes work)
+    hipEvent_t last = nullptr;  // recorded after each call's work, waited for by the next call
     std::vector<SolverBucket> buckets;
     std::mutex mu;
+};
+
+// Calls on different streams share the request buffer and the workspace: each
+// call's stream first waits for the work of the previous call, and records
+// the end of its own.
+struct SolverOrder {
+    ctqr_solver_t *sv;
+    hipStream_t st;
+    ctqr_status begin()
+    {
+        HIP_TRY(hipStreamWaitEvent(st, sv->last, 0));
+        return CTQR_OK;
+    }
+    ctqr_status end()
+    {
+        HIP_TRY(hipEventRecord(sv->last, st));
+        return CTQR_OK;
+    }
 };
 
 namespace {
@@ -1309,9 +1374,13 @@ SolverLayout solver_layout(const ctqr_solver_desc *d, void *work, int smax, int6
     const bool parts = d->dtype == CTQR_F32 && refine_split_trsm<float>(d->n, smax, refine);
     L.rparts = parts ? c.take<__bf16>((int64_t)trsm_rparts_elems(d->n)) : nullptr;
     L.swork = c.take<char>(0);
-    size_t sb = d->dtype == CTQR_F64
-                    ? carve_solve<double>(nullptr, d->m, d->n, d->nb, smax, refine, false, TRSM_PARTS_X).bytes
-                    : carve_solve<float>(nullptr, d->m, d->n, d->nb, smax, refine, false, TRSM_PARTS_X).bytes;
+    // every bucket carves the shared workspace for its own slice count: the
+    // largest, or the largest that also holds the persistent kernels' exchange
+    size_t sb = 0;
+    for (int sl : {smax, std::min(smax, FUSED_MAX_S)})
+        sb = std::max(sb, d->dtype == CTQR_F64
+                              ? carve_solve<double>(nullptr, d->m, d->n, d->nb, sl, refine, false, TRSM_PARTS_X).bytes
+                              : carve_solve<float>(nullptr, d->m, d->n, d->nb, sl, refine, false, TRSM_PARTS_X).bytes);
     L.bytes = c.off + sb + 256;
     return L;
 }
@@ -1405,11 +1474,17 @@ ctqr_status solver_solve_t(ctqr_solver_t *sv, int nreq, const double *const *B, 
         bk.iters = ran;
         bk.graph_iters = std::min(r.max_iters, ran + GRAPH_EXTRA_ITERS);
     } else {
-        if (!bk.exec) {
-            if (!sv->refine) bk.graph_iters = 0;
-            if ((s = capture_bucket<T>(sv, bk))) return s;
+        if (!sv->refine) bk.graph_iters = 0;
+        if (r.fused) {
+            // few slices: the persistent kernels and graph_iters refinement
+            // iterations, enqueued directly (a handful of launches, no graph)
+            if ((s = solve_start(r, st))) return s;
+            if ((s = refine_iters(r, 0, bk.graph_iters, false, st, nullptr))) return s;
+            bk.direct = true;
+        } else {
+            if (!bk.exec && (s = capture_bucket<T>(sv, bk))) return s;
+            HIP_TRY(hipGraphLaunch(bk.exec, st));
         }
-        HIP_TRY(hipGraphLaunch(bk.exec, st));
         if (sv->refine && bk.graph_iters < r.max_iters) {
             // the refinement may need more iterations than the graph holds:
             // continue eagerly, and recapture with the new count next time
@@ -1449,6 +1524,8 @@ ctqr_status solver_tune_t(ctqr_solver_t *sv, hipStream_t st, int reps)
     HIP_TRY(hipEventCreate(&e1));
     ctqr_status out = CTQR_OK;
     for (auto &bk : sv->buckets) {
+        // buckets of the persistent kernels have no slice tile to choose
+        if (fused_eligible<T>(d.m, d.nb, bk.S)) continue;
         const int cands[2] = {bk.S, 0};   // 32-wide, 128-wide slice tile
         const int ncand = 2;
         float best = 0.f;
@@ -1990,8 +2067,10 @@ ctqr_status ctqr_solver_create(const ctqr_solver_desc *desc, void *work, size_t 
             sv->buckets.push_back(bk);
         }
         hipError_t e = hipStreamCreateWithFlags(&sv->cap, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&sv->last, hipEventDisableTiming);
         if (e != hipSuccess) {
-            ctqr_last_hip_error(e, "hipStreamCreateWithFlags", __FILE__, __LINE__);
+            ctqr_last_hip_error(e, "solver stream and event", __FILE__, __LINE__);
+            if (sv->cap) (void)hipStreamDestroy(sv->cap);
             delete sv;
             return CTQR_EHIP;
         }
@@ -2007,8 +2086,12 @@ ctqr_status ctqr_solver_tune(ctqr_solver sv, int32_t reps, hipStream_t stream)
     try {
         if (!sv || reps < 1 || reps > 100) return CTQR_EINVAL;
         std::lock_guard<std::mutex> lk(sv->mu);
-        if (sv->d.dtype == CTQR_F64) return solver_tune_t<double>(sv, stream, reps);
-        return solver_tune_t<float>(sv, stream, reps);
+        SolverOrder ord{sv, stream};
+        ctqr_status s = ord.begin();
+        if (s) return s;
+        s = sv->d.dtype == CTQR_F64 ? solver_tune_t<double>(sv, stream, reps) : solver_tune_t<float>(sv, stream, reps);
+        ctqr_status e = ord.end();
+        return s ? s : e;
     } catch (...) {
         return CTQR_EHIP;
     }
@@ -2033,9 +2116,13 @@ ctqr_status ctqr_solver_solve_batch(ctqr_solver sv, int32_t nreq, const double *
         }
         if (total > sv->smax) return CTQR_EINVAL;
         std::lock_guard<std::mutex> lk(sv->mu);
-        if (sv->d.dtype == CTQR_F64)
-            return solver_solve_t<double>(sv, nreq, B, ldb, nslices, X, ldx, info, stream);
-        return solver_solve_t<float>(sv, nreq, B, ldb, nslices, X, ldx, info, stream);
+        SolverOrder ord{sv, stream};
+        ctqr_status s = ord.begin();
+        if (s) return s;
+        s = sv->d.dtype == CTQR_F64 ? solver_solve_t<double>(sv, nreq, B, ldb, nslices, X, ldx, info, stream)
+                                    : solver_solve_t<float>(sv, nreq, B, ldb, nslices, X, ldx, info, stream);
+        ctqr_status e = ord.end();
+        return s ? s : e;
     } catch (...) {
         return CTQR_EHIP;
     }
@@ -2050,7 +2137,7 @@ ctqr_status ctqr_solver_query(ctqr_solver sv, int32_t nslices, int32_t *bucket, 
         if (b.S >= nslices) {
             *bucket = b.S;
             *slice_tile = b.narrow >= b.S ? 32 : 128;
-            *graph_iters = b.exec ? b.graph_iters : -1;
+            *graph_iters = b.exec || b.direct ? b.graph_iters : -1;
             return CTQR_OK;
         }
     return CTQR_EINVAL;
@@ -2063,6 +2150,7 @@ ctqr_status ctqr_solver_destroy(ctqr_solver sv)
         std::lock_guard<std::mutex> lk(sv->mu);
         for (auto &b : sv->buckets) drop_graph(b);
         if (sv->cap) (void)hipStreamDestroy(sv->cap);
+        if (sv->last) (void)hipEventDestroy(sv->last);
     }
     delete sv;
     return CTQR_OK;

@@ -248,3 +248,24 @@ ctqr_status tile_qr_run(int m, int n, int b, double *A, int64_t lda, double *Sf,
 ctqr_status tile_solve_run(int m, int n, int b, const double *A, int64_t lda, const double *Sf, double *B,
                            int64_t ldb, int S, int4 *dtasks, hipStream_t st);
 
+
+// ---- fused.hip (persistent solve kernels for few right-hand sides) -----------
+constexpr int FUSED_MAX_S = 16;                   // slices the persistent kernels take
+constexpr size_t FUSED_MAX_LDS = 150 * 1024;      // their LDS per workgroup, at most
+int fused_grid();                                 // workgroups of a launch (compute units)
+size_t fused_lds_bytes(int qmax, size_t esz);
+// the rows of a right-hand side fit the launch's LDS
+bool fused_fits(int64_t rows, size_t esz);
+// elements of the exchange area (in the factor's precision), plus GB_WORDS
+// barrier words
+size_t fused_exchange_elems();
+// R X = C (trans false) or R^T X = C (trans true) with the stored diagonal-block
+// inverses; C is read only.  One cooperative launch; returns at once after
+// the refinement's flag *skip is set.
+template <typename T>
+ctqr_status trsm_fused(int n, int S, bool trans, const T *R, int64_t ldr, const T *Rinv, const T *C, int64_t ldc,
+                       T *X, int64_t ldx, T *ex, unsigned *bar, const int *skip, ctqr_info *info, hipStream_t st);
+// Y = (Q^T B)[0:n] for FP64 B (m x S), in the factor's precision
+template <typename T>
+ctqr_status qtb_fused(int m, int n, int nb, int S, const T *QR, int64_t lda, const T *Tf, const double *B,
+                      int64_t ldb, T *Y, int64_t ldy, T *ex, unsigned *bar, ctqr_info *info, hipStream_t st);

@@ -167,6 +167,26 @@ def test_narrow_and_wide_tiles_agree(gpu):
     assert e <= 1e-5 and e_or < 1e-2
 
 
+def test_solver_calls_on_two_streams(gpu):
+    # calls from two streams, enqueued back to back without host waits, share
+    # the solver's request buffer and workspace: each call's stream waits for
+    # the previous call's work, so every result equals the direct solve
+    A, B, Xo = _problem()
+    F = _factor(A, torch.float64, C.CTQR_PREC_FP64)
+    sv = Solver(F, max_slices=64)
+    reqs = [(0, 6), (6, 40), (46, 3), (49, 64), (0, 6)]
+    Bs = [to_colmajor(torch.as_tensor(B[:, a:a + k]), dtype=torch.float64) for a, k in reqs]
+    ref = [download(F.solve(b)) for b in Bs]
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    _print_case("solver two streams")
+    outs = [sv.solve(b, stream=streams[i % 2]) for i, b in enumerate(Bs)]
+    torch.cuda.synchronize()
+    for i, (x, r) in enumerate(zip(outs, ref)):
+        assert lsq.rel_err(download(x), r).max() <= 1e-12, i
+    sv.close()
+
+
 def test_solver_batch_of_requests(gpu):
     # three queued requests packed into one bucket give each request's own
     # solution (and, refined, the oracle's)
