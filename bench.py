@@ -130,7 +130,7 @@ def parse():
 TRAFFIC_FILES = {"bf16x3": os.path.join(ROOT, "profiles", "gemm_nn_bf16x3_trailing_update_ct256_traffic.txt")}
 # the trailing-update kernel of each mode, as rocprofv3 names it
 TRAILING_KERNEL = {"fp32": "gemm_nn_kernel<float, 1, 128, false, 0>",
-                   "bf16x3": "gemm_nn_bf16x3_kernel<1>"}
+                   "bf16x3": "gemm_nn_bf16x3_w8_kernel"}
 
 
 def trailing_launches(m, n, nb):
@@ -919,7 +919,8 @@ def main():
         exec_tf = 3 * achieved if achieved else None
         flops_method = sum(2.0 * mk * nc * kk for mk, nc, kk in launches_k)
         ridge = PEAK_TFLOPS["bf16"] * 1e12 / (HBM_PEAK_GBS * 1e9)
-        roof = {"bound": "mfma", "kernel": TRAILING_KERNEL["bf16x3"] + " (split-BF16 trailing update C -= V W')",
+        roof = {"bound": "mfma", "kernel": TRAILING_KERNEL["bf16x3"] + " (split-BF16 trailing update C -= V W'; "
+                                           "launches of fewer than 512 tiles of 256 run gemm_nn_bf16x3_kernel<1>)",
                 "achieved": achieved, "peak": PEAK_TFLOPS["bf16"], "unit": "TFLOP/s",
                 "frac": achieved / PEAK_TFLOPS["bf16"] if achieved else None,
                 "achieved_counts": "method flops 2 m_k n_k K per launch (one FP32-equivalent product)",

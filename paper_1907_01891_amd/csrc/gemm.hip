@@ -40,6 +40,7 @@
 // below the FP32 accumulation's own rounding for most sums).  The Householder
 // block V is split once per block column, in the layout each product reads;
 // C, read by only two tiles of [G | W], is split while staged.
+#include <cstdlib>
 #include <type_traits>
 
 #include "common.h"
@@ -438,7 +439,10 @@ __device__ inline void mfma_step_bf(const __bf16 *opA, const __bf16 *opB, int wn
 }
 
 // The same step from split operands (high and low bf16 parts, same layout):
-// per block the low-part products first, then the high-high product.
+// per block the low-part products first, then the high-high product.  Each
+// of the three products is issued for every block before the next product,
+// so consecutive MFMAs never wait on each other's accumulator; every block
+// still takes its three products in that order.
 template <int NI, int NJ>
 __device__ inline void mfma_step_bf2(const __bf16 *opAh, const __bf16 *opAl, const __bf16 *opBh,
                                      const __bf16 *opBl, int wn, int wm, floatx16 (&acc)[NI][NJ])
@@ -449,7 +453,7 @@ __device__ inline void mfma_step_bf2(const __bf16 *opAh, const __bf16 *opAl, con
 #pragma unroll
     for (int g = 0; g < Mf<float>::BK / 16; ++g) {
         const int kk = 16 * g + 8 * slot;
-        bf16x8 bh[NJ], bl[NJ];
+        bf16x8 bh[NJ], bl[NJ], ah[NI], al[NI];
 #pragma unroll
         for (int jb = 0; jb < NJ; ++jb) {
             bh[jb] = *reinterpret_cast<const bf16x8 *>(opBh + (wm + jb * 32 + li) * LDB + kk);
@@ -457,15 +461,69 @@ __device__ inline void mfma_step_bf2(const __bf16 *opAh, const __bf16 *opAl, con
         }
 #pragma unroll
         for (int ib = 0; ib < NI; ++ib) {
-            const bf16x8 ah = *reinterpret_cast<const bf16x8 *>(opAh + (wn + ib * 32 + li) * LDB + kk);
-            const bf16x8 al = *reinterpret_cast<const bf16x8 *>(opAl + (wn + ib * 32 + li) * LDB + kk);
-#pragma unroll
-            for (int jb = 0; jb < NJ; ++jb) {
-                acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[jb], acc[ib][jb], 0, 0, 0);
-                acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[jb], acc[ib][jb], 0, 0, 0);
-                acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[jb], acc[ib][jb], 0, 0, 0);
-            }
+            ah[ib] = *reinterpret_cast<const bf16x8 *>(opAh + (wn + ib * 32 + li) * LDB + kk);
+            al[ib] = *reinterpret_cast<const bf16x8 *>(opAl + (wn + ib * 32 + li) * LDB + kk);
         }
+#pragma unroll
+        for (int ib = 0; ib < NI; ++ib)
+#pragma unroll
+            for (int jb = 0; jb < NJ; ++jb)
+                acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[ib], bh[jb], acc[ib][jb], 0, 0, 0);
+#pragma unroll
+        for (int ib = 0; ib < NI; ++ib)
+#pragma unroll
+            for (int jb = 0; jb < NJ; ++jb)
+                acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[ib], bl[jb], acc[ib][jb], 0, 0, 0);
+#pragma unroll
+        for (int ib = 0; ib < NI; ++ib)
+#pragma unroll
+            for (int jb = 0; jb < NJ; ++jb)
+                acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[ib], bh[jb], acc[ib][jb], 0, 0, 0);
+    }
+}
+
+// Bank-conflict-free LDS layout of the 8-wave update: rows of 32 bf16 (64 B,
+// no padding), the 16-byte chunk c of row r stored at chunk c ^ ((r / 4) % 4).
+// The 16 rows a quarter wave reads (or the 4 rows x 4 chunks it writes) then
+// fall on 16 distinct 16-byte bank groups of the 64-bank LDS.
+__device__ inline int swz_off(int r, int c) { return r * 32 + 8 * (c ^ ((r >> 2) & 3)); }
+
+// mfma_step_bf2 on that layout (the same products in the same order)
+template <int NI, int NJ>
+__device__ inline void mfma_step_bf2_swz(const __bf16 *opAh, const __bf16 *opAl, const __bf16 *opBh,
+                                         const __bf16 *opBl, int wn, int wm, floatx16 (&acc)[NI][NJ])
+{
+    const int lane = threadIdx.x % CTQR_WAVE;
+    const int li = lane % 32, slot = lane / 32;
+#pragma unroll
+    for (int g = 0; g < Mf<float>::BK / 16; ++g) {
+        const int c = 2 * g + slot;
+        bf16x8 bh[NJ], bl[NJ], ah[NI], al[NI];
+#pragma unroll
+        for (int jb = 0; jb < NJ; ++jb) {
+            bh[jb] = *reinterpret_cast<const bf16x8 *>(opBh + swz_off(wm + jb * 32 + li, c));
+            bl[jb] = *reinterpret_cast<const bf16x8 *>(opBl + swz_off(wm + jb * 32 + li, c));
+        }
+#pragma unroll
+        for (int ib = 0; ib < NI; ++ib) {
+            ah[ib] = *reinterpret_cast<const bf16x8 *>(opAh + swz_off(wn + ib * 32 + li, c));
+            al[ib] = *reinterpret_cast<const bf16x8 *>(opAl + swz_off(wn + ib * 32 + li, c));
+        }
+#pragma unroll
+        for (int ib = 0; ib < NI; ++ib)
+#pragma unroll
+            for (int jb = 0; jb < NJ; ++jb)
+                acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[ib], bh[jb], acc[ib][jb], 0, 0, 0);
+#pragma unroll
+        for (int ib = 0; ib < NI; ++ib)
+#pragma unroll
+            for (int jb = 0; jb < NJ; ++jb)
+                acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[ib], bl[jb], acc[ib][jb], 0, 0, 0);
+#pragma unroll
+        for (int ib = 0; ib < NI; ++ib)
+#pragma unroll
+            for (int jb = 0; jb < NJ; ++jb)
+                acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[ib], bh[jb], acc[ib][jb], 0, 0, 0);
     }
 }
 
@@ -919,6 +977,116 @@ void gemm_nn_bf16x3_kernel(int M, int N, int K, const __bf16 *__restrict__ Ah, c
             }
 }
 
+// The same product on 256 x 256 output tiles: 8 waves (two per SIMD), each
+// a 128-row x 64-column sub-tile (4 x 2 MFMA blocks), two LDS stages of
+// 2 x 2 x 256 rows x 32 k in the swizzled layout (swz_off; 128 KiB, dynamic).
+// Per 16-deep k step a wave reads 12 KiB of fragments for 24 MFMAs (the
+// 128 x 128 tile: 8 KiB for 12).  Every output sums the same products in the
+// same order as gemm_nn_bf16x3_kernel, so the two give the same bits.  C is
+// read in the epilogue (the staging and fragment registers are free by then).
+// Operands are padded to whole 256-row (column) tiles.
+constexpr int BIGT = 256;       // output tile edge of the 8-wave form
+constexpr int BIGTHR = 512;     // its threads
+constexpr int BIG_LDS = 2 * 2 * 2 * BIGT * 32 * 2;   // bytes: stages x operands x parts x rows x 32 k
+
+__global__ __launch_bounds__(BIGTHR, 1)
+void gemm_nn_bf16x3_w8_kernel(int M, int N, int K, const __bf16 *__restrict__ Ah, const __bf16 *__restrict__ Al,
+                              int64_t lda, const __bf16 *__restrict__ Bh, const __bf16 *__restrict__ Bl,
+                              int64_t ldb, float alpha, float *__restrict__ C, int64_t ldc, const int *skip)
+{
+    constexpr int BK = Mf<float>::BK;
+    constexpr int LDB = 32;                        // swizzled rows, no padding
+    constexpr int CH = BK / 8;                     // 16-byte chunks per row and stage (4)
+    constexpr int PER = BIGT * CH / BIGTHR;        // chunks per thread, per part and operand (2)
+    constexpr int NI = 2, NJ = 4;                  // MFMA blocks: output columns, output rows
+    constexpr int STAGE = 2 * BIGT * LDB;          // elements of one operand's two parts
+    static_assert(BK == 32 && BIG_LDS == 2 * 2 * STAGE * 2, "LDS layout");
+    if (skip && *skip) return;
+    extern __shared__ __attribute__((aligned(16))) __bf16 big_lds[];
+    __bf16 *sA = big_lds;                          // [stage][part][row][k]
+    __bf16 *sB = big_lds + 2 * STAGE;              // [stage][part][col][k]
+
+    int tm, tn;
+    tile_of_block((M + BIGT - 1) / BIGT, (N + BIGT - 1) / BIGT, tm, tn);
+    const int m0 = tm * BIGT, n0 = tn * BIGT;
+    const int wave = threadIdx.x / CTQR_WAVE;
+    const int wm = (wave % 2) * 128, wn = (wave / 2) * 64;
+
+    floatx16 acc[NI][NJ];
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
+#pragma unroll
+        for (int j = 0; j < NJ; ++j)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
+
+    bf16x8 ra[2][PER], rb[2][PER];
+    auto load = [&](int k) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int f = (int)threadIdx.x + BIGTHR * q, r = f / CH, c = f % CH;
+            const int64_t oa = (int64_t)(m0 + r) * lda + k + 8 * c;
+            const int64_t ob = (int64_t)(n0 + r) * ldb + k + 8 * c;
+            ra[0][q] = *reinterpret_cast<const bf16x8 *>(Ah + oa);
+            ra[1][q] = *reinterpret_cast<const bf16x8 *>(Al + oa);
+            rb[0][q] = *reinterpret_cast<const bf16x8 *>(Bh + ob);
+            rb[1][q] = *reinterpret_cast<const bf16x8 *>(Bl + ob);
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int f = (int)threadIdx.x + BIGTHR * q, r = f / CH, c = f % CH;
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                *reinterpret_cast<bf16x8 *>(&sA[buf * STAGE + p * BIGT * LDB + swz_off(r, c)]) = ra[p][q];
+                *reinterpret_cast<bf16x8 *>(&sB[buf * STAGE + p * BIGT * LDB + swz_off(r, c)]) = rb[p][q];
+            }
+        }
+    };
+    load(0);
+    store(0);
+    __syncthreads();
+    int cur = 0;
+    for (int k = 0; k < K; k += BK) {
+        const bool more = k + BK < K;
+        if (more) load(k + BK);
+        const __bf16 *b0 = sB + cur * STAGE, *a0 = sA + cur * STAGE;
+        mfma_step_bf2_swz<NI, NJ>(b0, b0 + BIGT * LDB, a0, a0 + BIGT * LDB, wn, wm, acc);
+        if (more) store(cur ^ 1);
+        __syncthreads();
+        cur ^= 1;
+    }
+
+    // C += alpha acc, one block column (ib) at a time: its loads first, then
+    // its stores
+#pragma unroll
+    for (int ib = 0; ib < NI; ++ib) {
+        float cv[NJ][16];
+#pragma unroll
+        for (int jb = 0; jb < NJ; ++jb)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                int n, m;
+                acc_coords<float>(ib, jb, r, n, m);
+                n += n0 + wn;
+                m += m0 + wm;
+                cv[jb][r] = (m < M && n < N) ? __builtin_nontemporal_load(C + (int64_t)n * ldc + m) : 0.0f;
+            }
+#pragma unroll
+        for (int jb = 0; jb < NJ; ++jb)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                int n, m;
+                acc_coords<float>(ib, jb, r, n, m);
+                n += n0 + wn;
+                m += m0 + wm;
+                if (m < M && n < N)
+                    __builtin_nontemporal_store(cv[jb][r] + alpha * acc[ib][jb][r], C + (int64_t)n * ldc + m);
+            }
+    }
+}
+
 // V (rows x kc Householder block, column-major) to high / low bf16 parts in
 // its own column-major layout (k = row contiguous), column stride ldk; rows
 // up to ldk and columns up to cols_pad are zero.  These are the A operand of
@@ -1213,10 +1381,17 @@ int64_t up_to(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
 size_t bf16x3_split_elems(int64_t m, int64_t n, int nb)
 {
     const int64_t kp = up_to(nb, 32);
-    return (size_t)(2 * up_to(m, TILE) * kp + 2 * up_to(n, TILE) * kp);
+    return (size_t)(2 * up_to(m, BIGT) * kp + 2 * up_to(n, BIGT) * kp);
 }
 
 namespace {
+// the 8-wave form of the trailing update (CTQR_GEMM_W8=0 keeps the 128 x 128 one)
+bool w8_enabled()
+{
+    const char *e = std::getenv("CTQR_GEMM_W8");
+    return !(e && e[0] == '0');
+}
+
 struct SplitParts {
     int kp, rows_pad, cols_pad;
     __bf16 *vh, *vl, *wh, *wl;
@@ -1224,8 +1399,8 @@ struct SplitParts {
 bool split_parts(int M, int N, int K, __bf16 *split, size_t split_elems, SplitParts &p)
 {
     p.kp = (int)up_to(K, 32);
-    p.rows_pad = (int)up_to(M, TILE);
-    p.cols_pad = (int)up_to(N, TILE);
+    p.rows_pad = (int)up_to(M, BIGT);           // whole tiles of either update kernel
+    p.cols_pad = (int)up_to(N, BIGT);
     const size_t need = 2 * (size_t)p.rows_pad * p.kp + 2 * (size_t)p.cols_pad * p.kp;
     if (split == nullptr || need > split_elems) return false;
     p.vh = split;
@@ -1332,7 +1507,18 @@ ctqr_status gemm_nn_bf16x3(int M, int N, int K, float alpha, float *C, int64_t l
     SplitParts p;
     if (!split_parts(M, N, K, const_cast<__bf16 *>(split), split_elems, p)) return CTQR_ENOMEM;
     dim3 grid((unsigned)(ceil_div(M, TILE) * ceil_div(N, TILE)));
-    if (kind == 1)
+    if (kind == 1 && w8_enabled() && (int64_t)ceil_div(M, BIGT) * ceil_div(N, BIGT) >= 2 * 256) {
+        static bool attr = false;
+        if (!attr) {
+            HIP_TRY(hipFuncSetAttribute((const void *)gemm_nn_bf16x3_w8_kernel,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, BIG_LDS));
+            attr = true;
+        }
+        dim3 g8((unsigned)(ceil_div(M, BIGT) * ceil_div(N, BIGT)));
+        LAUNCH_TRY(gemm_nn_bf16x3_w8_kernel, g8, dim3(BIGTHR), BIG_LDS, st, M, N, K, (const __bf16 *)p.vh,
+                   (const __bf16 *)p.vl, (int64_t)p.kp, (const __bf16 *)p.wh, (const __bf16 *)p.wl, (int64_t)p.kp,
+                   alpha, C, ldc, skip);
+    } else if (kind == 1)
         LAUNCH_TRY(gemm_nn_bf16x3_kernel<1>, grid, dim3(NTHR), 0, st, M, N, K, (const __bf16 *)p.vh,
                    (const __bf16 *)p.vl, (int64_t)p.kp, (const __bf16 *)p.wh, (const __bf16 *)p.wl, (int64_t)p.kp,
                    alpha, C, ldc, skip);

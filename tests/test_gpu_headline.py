@@ -198,3 +198,28 @@ def test_zero_subdiagonal_columns_tau_zero(gpu, oracle_lib):
     assert (np.diag(QRg)[:40] == np.diag(Ad)[:40]).all()
     assert np.abs(taug - tauo).max() <= 1e-11
     assert np.abs(QRg - QRo).max() <= 1e-11 * np.abs(QRo).max()
+
+
+def test_bf16x3_update_kernels_agree_bitwise(gpu, monkeypatch):
+    # The trailing update runs on 256 x 256 tiles of eight waves when a launch
+    # has enough tiles (CTQR_GEMM_W8=0 keeps the 128 x 128 form).  Both sum
+    # every output's products in the same order, so the factors of the
+    # benchmark's configuration are equal bit for bit.  ct128 (m = 23,040,
+    # n = 16,384) has trailing updates of up to 86 x 60 tiles of 256.
+    _case("bf16x3 update kernels ct128")
+    w = get_workload("ct128")
+    S = SystemMatrix(w.geometry(), C.CTQR_F32, dense=True, sparse=False)
+    A0 = S.A.clone()
+    outs = []
+    for flag in ("0", "1"):
+        monkeypatch.setenv("CTQR_GEMM_W8", flag)
+        S.A.copy_(A0)
+        F = QRFactor(S.A, C.CTQR_PREC_BF16X3_MFMA, nb=256).factor()
+        torch.cuda.synchronize()
+        assert F.info.read().status == 0
+        outs.append((F.A.clone(), F.T.clone(), F.tau.clone()))
+        del F
+    for a, b in zip(outs[0], outs[1]):
+        assert torch.equal(a, b)
+    del S, A0, outs
+    torch.cuda.empty_cache()
