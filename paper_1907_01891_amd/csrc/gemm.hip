@@ -880,8 +880,9 @@ void split_w_kernel(int kc, int cols, const float *__restrict__ W, int64_t ldw_i
 // panels that neighbouring tiles re-read out of the L2.  Ah/Al: rows padded to
 // whole tiles, row stride lda; Bh/Bl: columns padded to whole tiles, column
 // stride ldb; both cover k up to K rounded up to a stage.  KIND only separates
-// the launch sites in a profile: 1 is the factorization's trailing update, 2
-// the update of a pair's second block column, 0 the substitutions.
+// the launch sites in a profile: 1 is the factorization's trailing update (the
+// launches too small for the 8-wave form), 2 the update of the rest of a group
+// by one of its block columns, 0 the substitutions.
 template <int KIND>
 __global__ __launch_bounds__(NTHR, 2)
 void gemm_nn_bf16x3_kernel(int M, int N, int K, const __bf16 *__restrict__ Ah, const __bf16 *__restrict__ Al,
