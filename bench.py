@@ -150,7 +150,7 @@ def trailing_launches(m, n, nb):
 
 
 def gemm_source_hash():
-    """Hash of the code of gemm.hip (comments removed) without the host-side
+    """Hash of the code of gemm.hip (comments and blank lines removed) without the host-side
     split-count rule of the TN products (gemm_tn_splits), which the
     trailing-update kernels and their launchers do not use: the key of the
     committed HBM-counter summaries."""
@@ -160,6 +160,7 @@ def gemm_source_hash():
         src = f.read()
     src = re.sub(r"\nint gemm_tn_splits\(int M, int N, int K\)\n\{.*?\n\}\n", "\n", src, count=1, flags=re.S)
     src = re.sub(r"[ \t]*//[^\n]*", "", src)
+    src = "\n".join(l.strip() for l in src.splitlines() if l.strip())   # comment-only edits keep the key
     return hashlib.sha256(src.encode()).hexdigest()[:16]
 
 
