@@ -149,15 +149,16 @@ def trailing_launches(m, n, nb):
     return out
 
 
-def gemm_source_hash():
+def gemm_source_hash(src=None):
     """Hash of the code of gemm.hip (comments and blank lines removed) without the host-side
     split-count rule of the TN products (gemm_tn_splits), which the
     trailing-update kernels and their launchers do not use: the key of the
-    committed HBM-counter summaries."""
+    committed HBM-counter summaries.  src: the file's text (read if None)."""
     import hashlib
     import re
-    with open(os.path.join(ROOT, "paper_1907_01891_amd", "csrc", "gemm.hip")) as f:
-        src = f.read()
+    if src is None:
+        with open(os.path.join(ROOT, "paper_1907_01891_amd", "csrc", "gemm.hip")) as f:
+            src = f.read()
     src = re.sub(r"\nint gemm_tn_splits\(int M, int N, int K\)\n\{.*?\n\}\n", "\n", src, count=1, flags=re.S)
     src = re.sub(r"[ \t]*//[^\n]*", "", src)
     src = "\n".join(l.strip() for l in src.splitlines() if l.strip())   # comment-only edits keep the key

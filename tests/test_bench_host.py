@@ -66,7 +66,12 @@ def test_source_hash_ignores_comments_and_split_rule():
     body = re.sub(r"\nint gemm_tn_splits\(int M, int N, int K\)\n\{.*?\n\}\n", "\n", src, count=1, flags=re.S)
     assert len(body) < len(src) and "gemm_tn_splits(int M, int N, int K)\n{" not in body
     code = re.sub(r"[ \t]*//[^\n]*", "", body)
+    code = "\n".join(line.strip() for line in code.splitlines() if line.strip())
     assert bench.gemm_source_hash() == hashlib.sha256(code.encode()).hexdigest()[:16]
+    # comment, blank-line and indentation edits keep the key; a code edit does not
+    edited = src.replace("\n{", "\n\n  {  // note", 1)
+    assert edited != src and bench.gemm_source_hash(edited) == bench.gemm_source_hash(src)
+    assert bench.gemm_source_hash(src.replace("BIGT", "BIGT2")) != bench.gemm_source_hash(src)
 
 
 def test_more_than_one_gpu_is_refused():
