@@ -206,6 +206,12 @@ ctqr_status ctqr_qr_workspace(int64_t m, int64_t n, ctqr_dtype dtype, ctqr_prec 
  *          triangular T of each block column (the paper's "S factors").
  *   tau    device, n doubles: the reflector scalars (LAPACK larfg convention:
  *          beta = -sign(alpha)||x||, tau = (beta - alpha)/beta).
+ *          The 32-column inner panels held in FP64 form V, tau and R by
+ *          Cholesky QR twice and the Householder reconstruction, which gives
+ *          the larfg results up to rounding, whenever that is safe for the
+ *          panel.  Otherwise, and everywhere with the environment variable
+ *          CTQR_PANEL_ROUTE=columns, they form them one column at a time.
+ *          Each route is bitwise reproducible.
  *   Rinv   device, ctqr_qr_rinv_bytes(n, dtype) bytes in `dtype`, or NULL: the
  *          inverses of the 2048 x 2048 diagonal blocks of R and their
  *          transposes, stored with the factor so every later solve's block

@@ -8,7 +8,13 @@
 // beta = -sign(alpha) ||[alpha; x]||, tau = (beta - alpha) / beta,
 // v = [1; x / (alpha - beta)]; tau = 0 when x = 0.
 //
-// One grid barrier per column: after forming reflector j, each workgroup
+// Two routes.  FP64 slabs first try the reconstruction route described
+// further down (Cholesky QR twice, then the Householder vectors from an LU
+// with sign choice: four grid barriers per panel); it gives the same V, tau
+// and R up to rounding and hands the panel to the column route below when it
+// is not safe.
+//
+// Column route, one grid barrier per column: after forming reflector j, each workgroup
 // publishes its partial products w_c = v^T a_c for the columns c > j and,
 // for column j+1, its partial sums S_aa = sum a^2, S_av = sum a v and
 // S_vv = sum v^2 over the rows below the next pivot.  After the exchange
@@ -28,6 +34,9 @@
 // Taken 32 columns at a time the recurrence reads
 // T(0:32q, q) = -T(0:32q, 0:32q) (G(0:32q, q) T_qq), whose row block p only
 // involves row block p of T, so one workgroup per row block builds it alone.
+#include <cstdlib>
+#include <cstring>
+#include <algorithm>
 #include "common.h"
 #include "kernels.h"
 
@@ -67,6 +76,454 @@ __device__ inline double wave_sum(double v)
     return v;
 }
 
+// ---------------------------------------------------------------------------
+// Reconstruction route for FP64 slabs (four grid barriers per panel instead
+// of one per column).  The panel P (rows r0 .. m-1, w columns) is first
+// orthogonalised twice by Cholesky QR: G1 = P^T P = R1^T R1, Q1 = P R1^-1,
+// G2 = Q1^T Q1 = R2^T R2, Q = Q1 R2^-1, R = R2 R1.  The Householder vectors
+// follow from Q by the reconstruction of Ballard et al. (2015): the unit
+// lower trapezoidal V and the upper triangular U' of the LU factorisation
+// Q - [D; 0] = V U', with D = diag(d_j) chosen during the elimination as
+// d_j = -sign(q_jj) of the current pivot element, so every pivot has modulus
+// at least 1.  Then I - V T V^T with T = -U' D V_1^-T reproduces the
+// factorisation: tau_j = -U'_jj d_j and the R of the Householder form is
+// D R.  In exact arithmetic V, tau and D R are the vectors, scalars and R of
+// the column-at-a-time route (beta = -sign(alpha) ||x||), so the two routes
+// agree to rounding.  Rows below the top block: V = Q1 (U' R2)^-1.
+//
+// The route is taken only where it is safe, decided from exchanged totals so
+// that every workgroup takes the same branch: every column has a nonzero
+// part below its diagonal (the other route gives tau = 0 there), the first
+// Cholesky factorisation has positive finite pivots, and after the first
+// pass max |G2 - I| <= 1e-4 (a panel whose condition number is far below
+// u^-1/2, where two passes leave Q orthonormal to rounding).  Otherwise the
+// column-at-a-time route runs on the original panel.
+// ---------------------------------------------------------------------------
+constexpr int CQ_NE = 1056;          // exchanged partials per workgroup: Gram 32 x 32 (row-major) + 32 sums
+constexpr int CQ_ML = 34;            // leading dimension of the 32 x 32 LDS matrices (16-byte aligned columns)
+constexpr int CQ_MAT = 32 * CQ_ML;
+constexpr int CQ_T1 = 0, CQ_T2 = CQ_NE, CQ_QT = 2 * CQ_NE;   // totals of the two passes, Q1's top rows
+constexpr int CQ_TOT = CQ_QT + 32 * 32;
+constexpr int CQ_NMAT = 6;           // R1, R2, LU, P, R and an inverse
+constexpr int CQ_BUF = 96;           // row broadcasts and pivots of the small factorisations
+constexpr size_t CQ_LDS = (size_t)(CQ_NMAT * CQ_MAT + 64 + CQ_BUF) * sizeof(double);  // + signs, sums
+constexpr size_t CQ_LDS_LIMIT = 150 * 1024;                  // slab + CQ_LDS, plus ~3 KiB static LDS
+constexpr double CQ_ORTH_TOL = 1e-4;
+
+__device__ __attribute__((always_inline)) inline doublex4 mfma_f64(double a, double b, doublex4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Gram matrix of the 32 columns val(rr, c) over the rows rr < nrows on FP64
+// MFMA (v_mfma_f64_16x16x4f64: lane l supplies row k = l/16 of the 4-row
+// step to column l%16 of each operand; output register r of lane l holds
+// block entry (4r + l/16, l%16)).  Wave wv takes the 4-row steps at
+// 16 t + 4 wv and feeds columns l%16 and 16 + l%16 to the blocks (0,0),
+// (0,1) and (1,1); the four waves' sums are then added in wave order through
+// scr (3072 doubles of LDS).  emit(i, j, g) receives every entry, the (1,0)
+// block as the transpose of (0,1).
+template <typename F, typename E>
+__device__ __attribute__((always_inline)) inline void cq_gram(int nrows, F val, double *scr, E emit)
+{
+    const int wave = threadIdx.x / CTQR_WAVE, lane = threadIdx.x % CTQR_WAVE;
+    const int li = lane % 16, kq = lane / 16;
+    doublex4 g00 = {0.0, 0.0, 0.0, 0.0}, g01 = g00, g11 = g00;
+    for (int k0 = 4 * wave; k0 < nrows; k0 += 16) {
+        const int rr = k0 + kq;
+        const bool in = rr < nrows;
+        const int rc = in ? rr : nrows - 1;
+        const double x0 = in ? val(rc, li) : 0.0, x1 = in ? val(rc, 16 + li) : 0.0;
+        g00 = mfma_f64(x0, x0, g00);
+        g01 = mfma_f64(x0, x1, g01);
+        g11 = mfma_f64(x1, x1, g11);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        scr[(3 * wave + 0) * 256 + 64 * r + lane] = g00[r];
+        scr[(3 * wave + 1) * 256 + 64 * r + lane] = g01[r];
+        scr[(3 * wave + 2) * 256 + 64 * r + lane] = g11[r];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 768; e += PNT) {
+        const int b = e / 256, o = e % 256;
+        double g = scr[b * 256 + o];
+#pragma unroll
+        for (int v = 1; v < PNT / CTQR_WAVE; ++v) g += scr[(3 * v + b) * 256 + o];
+        const int i = 4 * ((o / 64) % 4) + (o % 64) / 16, j = o % 16;
+        if (b == 0) {
+            emit(i, j, g);
+        } else if (b == 1) {
+            emit(i, 16 + j, g);
+            emit(16 + j, i, g);
+        } else {
+            emit(16 + i, 16 + j, g);
+        }
+    }
+    __syncthreads();
+}
+
+// tot[e] = sum over the workgroups q < G of part[q * CQ_NE + e], e < ne (a
+// multiple of 16).  One wave per 16 consecutive entries (a 128-byte line of
+// every workgroup's partials); lane group l/16 sums the workgroups
+// q = l/16 (mod 4) in increasing order, and the four group sums combine by a
+// fixed butterfly, so the totals do not depend on timing.
+__device__ __attribute__((always_inline)) inline void cq_reduce(const double *part, int G, int ne, double *tot)
+{
+    constexpr int NW = PNT / CTQR_WAVE, B = 16;
+    const int wave = threadIdx.x / CTQR_WAVE, lane = threadIdx.x % CTQR_WAVE;
+    const int e0 = lane % 16, grp = lane / 16;
+    for (int line = blockIdx.x * NW + wave; line < ne / 16; line += gridDim.x * NW) {
+        const int e = 16 * line + e0;
+        double s = 0.0;
+        for (int q0 = grp; q0 < G; q0 += 4 * B) {
+            double v[B];
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                const int q = q0 + 4 * u;
+                v[u] = q < G ? load_coherent(&part[(int64_t)q * CQ_NE + e]) : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < B; ++u) s += v[u];
+        }
+        s += __shfl_xor(s, 16);
+        s += __shfl_xor(s, 32);
+        if (lane < 16) store_coherent(&tot[e], s);
+    }
+}
+
+// Orders one wave's LDS accesses across its lanes: a lane's read after the
+// fence sees another lane's write before it (the compiler otherwise treats
+// the lanes as independent threads and may hoist the read).
+__device__ __attribute__((always_inline)) inline void wave_lds_fence()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// The three small factorisations below run in one wave with the 32 x 32
+// matrix spread as half rows: lane l holds row i = l % 32, columns
+// 16 h .. 16 h + 15 with h = l / 32, in 16 registers.  Their loops over the
+// pivot index stay rolled: the panel kernel runs once per panel with a cold
+// instruction cache, so compact code is faster than unrolled straight-line
+// code here.  Rows are broadcast through buf (LDS) between wave fences.
+
+// Cholesky factorisation G = R^T R of the leading w x w block of M
+// (column-major, M[j * CQ_ML + i] = (i, j), both triangles present), in
+// place (R in the upper triangle, zeros elsewhere in the 32 x 32 block), and
+// X = R^-1 (same layout).  Right-looking on unscaled rows: step j publishes
+// row j of the reduced matrix G' and row j of Z (Z = R^-T is built by the
+// same elimination from I); rows i > j subtract (G'_ji / G'_jj) times both.
+// Row j of R is G'_j / sqrt(G'_jj), row j of Z is Z_j / sqrt(G'_jj).  buf: 96
+// doubles.  Returns false when a pivot is not positive and finite (the
+// values left are then meaningless).
+__device__ __attribute__((always_inline)) inline bool cq_cholesky_inv(double *M, int w, double *X, double *buf)
+{
+    const int lane = threadIdx.x % CTQR_WAVE, i = lane % 32, h = lane / 32;
+    double g[16], z[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        const int k = 16 * h + t;
+        g[t] = (i < w && k < w) ? M[k * CQ_ML + i] : 0.0;
+        z[t] = (i == k && i < w) ? 1.0 : 0.0;
+    }
+    bool ok = true;
+    for (int j = 0; j < w; ++j) {
+        if (i == j)
+#pragma unroll
+            for (int t = 0; t < 16; ++t) {
+                buf[16 * h + t] = g[t];
+                buf[32 + 16 * h + t] = z[t];
+            }
+        wave_lds_fence();
+        const double d = buf[j];
+        ok = ok && d > 0.0 && !isinf(d);
+        const double invd = 1.0 / d;
+        const double c = i > j ? buf[i] * invd : 0.0;
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            g[t] -= c * buf[16 * h + t];
+            z[t] -= c * buf[32 + 16 * h + t];
+        }
+        if (lane == 0) buf[64 + j] = sqrt(d);
+        wave_lds_fence();
+    }
+    const double r = i < w ? buf[64 + i] : 1.0, rs = 1.0 / r;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        const int k = 16 * h + t;
+        const bool in = i < w && k < w;
+        M[k * CQ_ML + i] = in ? (k > i ? g[t] * rs : (k == i ? r : 0.0)) : 0.0;
+        X[i * CQ_ML + k] = in ? z[t] * rs : 0.0;      // X(k, i) = Z(i, k)
+    }
+    return ok;
+}
+
+// LU factorisation with the reconstruction's sign choice of the w x w block
+// M (column-major), in place: the strict lower triangle becomes V's top block
+// (unit diagonal implied), the upper triangle U'; dsign[j] = d_j.  Entries
+// outside the w x w block stay 0.  Every step writes the current rows to the
+// row-major scratch S (32 x CQ_ML), from which the pivot row and each row's
+// entry in the pivot column are read; rows i > j then subtract
+// l_i = S(i, j) / p_j times the pivot row.  buf: 64 doubles (the pivots and
+// the multipliers' column).
+__device__ __attribute__((always_inline)) inline void cq_lu_signs(double *M, int w, double *dsign, double *S,
+                                                                 double *buf)
+{
+    const int lane = threadIdx.x % CTQR_WAVE, i = lane % 32, h = lane / 32;
+    double a[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        const int k = 16 * h + t;
+        a[t] = (i < w && k < w) ? M[k * CQ_ML + i] : 0.0;
+    }
+    for (int j = 0; j < w; ++j) {
+#pragma unroll
+        for (int t = 0; t < 16; ++t) S[i * CQ_ML + 16 * h + t] = a[t];
+        wave_lds_fence();
+        const double q = S[j * CQ_ML + j];
+        const double d = q >= 0.0 ? -1.0 : 1.0;
+        const double piv = q - d;                 // q + sign(q): modulus >= 1
+        const double rp = 1.0 / piv;
+        const double l = i > j ? S[i * CQ_ML + j] * rp : 0.0;
+#pragma unroll
+        for (int t = 0; t < 16; ++t) a[t] -= l * S[j * CQ_ML + 16 * h + t];
+        if (lane == 0) {
+            dsign[j] = d;
+            buf[j] = piv;
+        }
+        if (h == 0 && i > j) M[j * CQ_ML + i] = l;       // column j of L
+        wave_lds_fence();
+    }
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        const int k = 16 * h + t;
+        if (k >= i) M[k * CQ_ML + i] = (i < w && k < w) ? (k == i ? buf[i] : a[t]) : 0.0;
+        else if (i >= w) M[k * CQ_ML + i] = 0.0;
+    }
+}
+
+// X = U^-1 for the upper triangular leading w x w block of U (column-major),
+// zeros elsewhere in the 32 x 32 block.  Gauss-Jordan from the last row up on
+// unscaled rows (X starts as I): step j publishes row j, and rows i < j
+// subtract (U_ij / U_jj) times it; row i is finally scaled by 1 / U_ii.
+__device__ __attribute__((always_inline)) inline void cq_inverse(const double *U, int w, double *X, double *buf)
+{
+    const int lane = threadIdx.x % CTQR_WAVE, i = lane % 32, h = lane / 32;
+    double x[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) x[t] = (i == 16 * h + t && i < w) ? 1.0 : 0.0;
+    for (int j = w - 1; j >= 0; --j) {
+        if (i == j)
+#pragma unroll
+            for (int t = 0; t < 16; ++t) buf[16 * h + t] = x[t];
+        wave_lds_fence();
+        const double ujj = 1.0 / U[j * CQ_ML + j];
+        const double c = i < j ? U[j * CQ_ML + i] * ujj : 0.0;
+#pragma unroll
+        for (int t = 0; t < 16; ++t) x[t] -= c * buf[16 * h + t];
+        wave_lds_fence();
+    }
+    const double rs = i < w ? 1.0 / U[i * CQ_ML + i] : 0.0;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        const int k = 16 * h + t;
+        X[k * CQ_ML + i] = (i < w && k < w) ? x[t] * rs : 0.0;
+    }
+}
+
+// C = triu(X) Y for 32 x 32 column-major LDS matrices (entries of X below
+// its diagonal taken as 0).  Wave wv forms block (wv / 2, wv % 2) with eight
+// v_mfma_f64_16x16x4f64.
+__device__ __attribute__((always_inline)) inline void cq_upper_product(const double *X, const double *Y, double *C)
+{
+    const int wave = threadIdx.x / CTQR_WAVE, lane = threadIdx.x % CTQR_WAVE;
+    const int bi = 16 * (wave / 2), bj = 16 * (wave % 2);
+    const int li = lane % 16, kq = lane / 16;
+    doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k0 = 0; k0 < 32; k0 += 4) {
+        const int k = k0 + kq;
+        const double a = k >= bi + li ? X[k * CQ_ML + bi + li] : 0.0;
+        acc = mfma_f64(a, Y[(bj + li) * CQ_ML + k], acc);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) C[(bj + li) * CQ_ML + bi + 4 * r + kq] = acc[r];
+}
+
+// Rows [0, nrows) of the column-major matrix S (leading dimension lds, w
+// columns): S := S X for X 32 x 32 in LDS (zero outside w x w), on FP64
+// MFMA.  Wave wv takes the 16-row blocks wv, wv + 4, ...; each block's
+// 16 x 32 inputs are read before any of its outputs is stored.
+__device__ __attribute__((always_inline)) inline void cq_apply_right(double *S, int lds, int nrows, int w,
+                                                                    const double *X)
+{
+    const int wave = threadIdx.x / CTQR_WAVE, lane = threadIdx.x % CTQR_WAVE;
+    const int li = lane % 16, kq = lane / 16;
+    double b0[8], b1[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        b0[s] = X[li * CQ_ML + 4 * s + kq];
+        b1[s] = X[(16 + li) * CQ_ML + 4 * s + kq];
+    }
+    for (int rb = 16 * wave; rb < nrows; rb += 16 * (PNT / CTQR_WAVE)) {
+        const int r = rb + li;
+        const int rc = r < nrows ? r : nrows - 1;
+        double a[8];
+#pragma unroll
+        for (int s = 0; s < 8; ++s) a[s] = (r < nrows && 4 * s + kq < w) ? S[(4 * s + kq) * lds + rc] : 0.0;
+        doublex4 c0 = {0.0, 0.0, 0.0, 0.0}, c1 = c0;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            c0 = mfma_f64(a[s], b0[s], c0);
+            c1 = mfma_f64(a[s], b1[s], c1);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int ro = rb + 4 * q + kq;
+            if (ro < nrows) {
+                if (li < w) S[li * lds + ro] = c0[q];
+                if (16 + li < w) S[(16 + li) * lds + ro] = c1[q];
+            }
+        }
+    }
+}
+
+__device__ __attribute__((always_inline)) inline bool wave_all(bool v)
+{
+    int x = v ? 1 : 0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x &= __shfl_xor(x, o);
+    return x != 0;
+}
+
+// Slab <- the panel's rows [row0, row0 + nrows) (column-major A:
+// consecutive threads on consecutive rows).
+template <typename TS, typename SL>
+__device__ __attribute__((always_inline)) inline void load_slab(const TS *A, int64_t lda, int r0, int w, int row0,
+                                                               int nrows, int ldsl, SL *slab)
+{
+    for (int idx = threadIdx.x; idx < nrows * w; idx += PNT) {
+        const int c = idx / nrows, rr = idx % nrows;
+        slab[c * ldsl + rr] = (SL)A[(int64_t)(r0 + c) * lda + row0 + rr];
+    }
+}
+
+// The reconstruction route on an FP64 slab (described above).  On success the
+// slab holds R (top rows of workgroup 0, on and above the diagonal) and the
+// Householder vectors below it, and tau_s the scalars; returns false, with
+// the slab holding the original panel, when the route is not safe.  Every
+// workgroup returns the same value.  ext: CQ_LDS bytes of LDS; cq_part:
+// CQ_NE doubles per workgroup; cq_tot: CQ_TOT doubles.
+template <typename TS>
+__device__ __attribute__((always_inline)) bool cq_route(const TS *A, int64_t lda, int r0, int w, int row0,
+                                                        int nrows, double *slab, int ldsl, double *ext, double *tau_s,
+                                                        double *cq_part, double *cq_tot, unsigned *bar,
+                                                        unsigned &epoch, ctqr_info *info)
+{
+    const int G = gridDim.x, wg = blockIdx.x, tid = threadIdx.x;
+    const int lane = tid % CTQR_WAVE, wave = tid / CTQR_WAVE;
+    double *R1 = ext, *R2 = ext + CQ_MAT, *LU = ext + 2 * CQ_MAT, *P = ext + 3 * CQ_MAT, *R = ext + 4 * CQ_MAT;
+    double *X = ext + 5 * CQ_MAT;
+    double *dsg = ext + CQ_NMAT * CQ_MAT, *sub = dsg + 32, *buf = sub + 32;
+    double *scr = LU;                  // Gram scratch: LU, P and R are free while the Grams run
+    __shared__ int ok_s;
+    double *mine = cq_part + (int64_t)wg * CQ_NE;
+    auto slab_val = [&](int rr, int c) { return c < w ? slab[c * ldsl + rr] : 0.0; };
+    auto emit_part = [&](int i, int j, double g) { store_coherent(&mine[32 * i + j], g); };
+
+    // pass 1: partial Gram P^T P and, per column, the partial sum of squares
+    // below the diagonal
+    cq_gram(nrows, slab_val, scr, emit_part);
+#pragma unroll
+    for (int q = 0; q < 32 / (PNT / CTQR_WAVE); ++q) {
+        const int c = wave + (PNT / CTQR_WAVE) * q;
+        double s = 0.0;
+        if (c < w)
+            for (int rr = lane; rr < nrows; rr += CTQR_WAVE)
+                if (row0 + rr > r0 + c) {
+                    const double x = slab[c * ldsl + rr];
+                    s += x * x;
+                }
+        s = wave_sum(s);
+        if (lane == 0) store_coherent(&mine[1024 + c], s);
+    }
+    grid_barrier(bar, epoch, info);
+    cq_reduce(cq_part, G, CQ_NE, cq_tot + CQ_T1);
+    grid_barrier(bar, epoch, info);
+    for (int e = tid; e < 1024; e += PNT) R1[(e % 32) * CQ_ML + e / 32] = load_coherent(&cq_tot[CQ_T1 + e]);
+    if (tid < 32) sub[tid] = load_coherent(&cq_tot[CQ_T1 + 1024 + tid]);
+    __syncthreads();
+    if (wave == 0) {
+        const double sc = sub[min(lane, 31)];
+        bool ok = wave_all(lane >= w || (sc > 0.0 && !isinf(sc)));
+        ok = cq_cholesky_inv(R1, w, X, buf) && ok;
+        if (lane == 0) ok_s = ok;
+    }
+    __syncthreads();
+    if (!ok_s) return false;
+
+    // Q1 = P R1^-1; workgroup 0 publishes Q1's top rows; pass 2: Q1^T Q1
+    cq_apply_right(slab, ldsl, nrows, w, X);
+    __syncthreads();
+    if (wg == 0)
+        for (int e = tid; e < 1024; e += PNT) {
+            const int rr = e / 32, c = e % 32;
+            store_coherent(&cq_tot[CQ_QT + e], (rr < w && c < w) ? slab[c * ldsl + rr] : 0.0);
+        }
+    cq_gram(nrows, slab_val, scr, emit_part);
+    grid_barrier(bar, epoch, info);
+    cq_reduce(cq_part, G, 1024, cq_tot + CQ_T2);
+    grid_barrier(bar, epoch, info);
+    for (int e = tid; e < 1024; e += PNT) {
+        R2[(e % 32) * CQ_ML + e / 32] = load_coherent(&cq_tot[CQ_T2 + e]);
+        LU[(e % 32) * CQ_ML + e / 32] = load_coherent(&cq_tot[CQ_QT + e]);   // Q1 top row e/32, column e%32
+    }
+    __syncthreads();
+    if (wave == 0) {
+        bool ok = true;
+        if (lane < w)
+            for (int i = 0; i <= lane; ++i) {
+                const double dev = fabs(R2[lane * CQ_ML + i] - (i == lane ? 1.0 : 0.0));
+                ok = ok && dev <= CQ_ORTH_TOL;
+            }
+        ok = wave_all(ok);
+        ok = cq_cholesky_inv(R2, w, X, buf) && ok;
+        if (lane == 0) ok_s = ok;
+    }
+    __syncthreads();
+    if (!ok_s) {
+        load_slab(A, lda, r0, w, row0, nrows, ldsl, slab);
+        __syncthreads();
+        return false;
+    }
+
+    // Q's top block = Q1's top rows R2^-1, then its LU with the sign choice
+    cq_apply_right(LU, CQ_ML, w, w, X);
+    __syncthreads();
+    if (wave == 0) {
+        cq_lu_signs(LU, w, dsg, P, buf);
+        cq_inverse(LU, w, P, buf);            // U'^-1
+    }
+    __syncthreads();
+    cq_upper_product(R2, R1, R);              // R2 R1
+    __syncthreads();
+    cq_upper_product(X, P, R1);               // (U' R2)^-1 = R2^-1 U'^-1
+    if (tid < w) tau_s[tid] = -LU[tid * CQ_ML + tid] * dsg[tid];
+    __syncthreads();
+    // V = Q1 (U' R2)^-1 (workgroup 0's top rows are then replaced): D R on and
+    // above the diagonal, V's top block below it
+    cq_apply_right(slab, ldsl, nrows, w, R1);
+    __syncthreads();
+    if (wg == 0)
+        for (int e = tid; e < w * w; e += PNT) {
+            const int rr = e % w, c = e / w;
+            slab[c * ldsl + rr] = rr <= c ? dsg[rr] * R[c * CQ_ML + rr] : LU[c * CQ_ML + rr];
+        }
+    __syncthreads();
+    return true;
+}
+
 // SL: element type of the slab.  FP64 whenever it fits in LDS; for very tall
 // FP32 panels (more rows per workgroup than an FP64 slab can hold) an FP32
 // slab, with every sum, norm and reflector scalar still formed in FP64.
@@ -78,7 +535,7 @@ template <typename TS, typename SL>
 __global__ __launch_bounds__(PNT)
 void panel_qr_kernel(TS *__restrict__ A, int64_t lda, int m, int r0, int w, int rows_per_wg,
                      double *__restrict__ tau_out, double *part, double *part2,
-                     double *__restrict__ gram_part, unsigned *bar, ctqr_info *info)
+                     double *__restrict__ gram_part, int route, unsigned *bar, ctqr_info *info)
 {
     constexpr int NW = PNT / CTQR_WAVE;
     constexpr int RPL = rows_per_lane<SL>();
@@ -97,17 +554,23 @@ void panel_qr_kernel(TS *__restrict__ A, int64_t lda, int m, int r0, int w, int 
     const int nrows = max(0, min(rows_per_wg, m - row0));
     unsigned epoch = 0;
 
-    for (int idx = tid; idx < nrows * w; idx += PNT) {
-        int c = idx / nrows, rr = idx % nrows;
-        slab[c * ldsl + rr] = (SL)A[(int64_t)(r0 + c) * lda + row0 + rr];
-    }
+    load_slab(A, lda, r0, w, row0, nrows, ldsl, slab);
     __syncthreads();
 
     // pivot rows r0 .. r0+w-1 all lie in workgroup 0's slab (rows_per_wg >= 64)
     bool have = false;           // norm and alpha of column j known from the last exchange
     double ss = 0.0, alpha = 0.0;
     bool nonfinite = false;
-    for (int j = 0; j < w; ++j) {
+    bool done = false;
+    if constexpr (sizeof(SL) == sizeof(double)) {
+        // the reconstruction route; its totals sit past this launch's
+        // column-route exchange buffers
+        if (route)
+            done = cq_route<TS>(A, lda, r0, w, row0, nrows, reinterpret_cast<double *>(slab), ldsl,
+                                reinterpret_cast<double *>(slab_raw + (size_t)ldsl * PW * sizeof(SL)), tau_s,
+                                gram_part, part2 + (int64_t)2 * G * PS, bar, epoch, info);
+    }
+    for (int j = 0; j < (done ? 0 : w); ++j) {
         const int p = r0 + j;                     // pivot row
         SL *colj = slab + (int64_t)j * ldsl;
         if (!have) {
@@ -288,15 +751,24 @@ void panel_qr_kernel(TS *__restrict__ A, int64_t lda, int m, int r0, int w, int 
     // 16 x 16 block per wave.  Lane l feeds row k0 + l/16 of columns
     // bi + l%16 and bj + l%16; output register r of lane l holds
     // G(bi + 4r + l/16, bj + l%16).
+    // After the reconstruction route the same sums run through cq_gram (three
+    // blocks per wave, wave partials added in wave order).
     __syncthreads();
+    auto vval = [&](int rr, int c) -> double {
+        if (rr >= nrows || c >= w) return 0.0;
+        const int g = row0 + rr;
+        return g == r0 + c ? 1.0 : (g > r0 + c ? (double)(TS)slab[c * ldsl + rr] : 0.0);
+    };
+    if constexpr (sizeof(SL) == sizeof(double)) {
+        if (done) {
+            cq_gram(nrows, vval, reinterpret_cast<double *>(slab_raw + (size_t)ldsl * PW * sizeof(SL)),
+                    [&](int i, int j, double g) { gram_part[(int64_t)wg * PW * PW + i + PW * j] = g; });
+            return;
+        }
+    }
     {
         const int bi = 16 * (wave / 2), bj = 16 * (wave % 2);
         const int li = lane % 16, kq = lane / 16;
-        auto vval = [&](int rr, int c) -> double {
-            if (rr >= nrows || c >= w) return 0.0;
-            const int g = row0 + rr;
-            return g == r0 + c ? 1.0 : (g > r0 + c ? (double)(TS)slab[c * ldsl + rr] : 0.0);
-        };
         doublex4 g4 = {0.0, 0.0, 0.0, 0.0};
         for (int k0 = 0; k0 < nrows; k0 += 4) {
             const double a = vval(k0 + kq, bi + li), b = vval(k0 + kq, bj + li);
@@ -460,8 +932,15 @@ ctqr_status panel_qr(TS *A, int64_t lda, int m, int r0, int w, double *tau, doub
     const bool f32slab = sizeof(TS) == 4 && rows > panel_max_rows_per_wg();
     if (rows > (f32slab ? panel_max_rows_per_wg_f32() : panel_max_rows_per_wg())) return CTQR_EUNSUPPORTED;
     const int G = (int)ceil_div(mrem, rows);
-    const size_t lds = panel_lds_bytes(rows, f32slab ? sizeof(float) : sizeof(double));
-    void *args[] = {&A, (void *)&lda, &m, &r0, &w, (void *)&rows, &tau, &part, &part2, &gram_part, &bar, &info};
+    size_t lds = panel_lds_bytes(rows, f32slab ? sizeof(float) : sizeof(double));
+    // the reconstruction route: FP64 slabs with room for its LDS, at most 256
+    // workgroups (its exchange sits past the column route's), more panel rows
+    // than columns; CTQR_PANEL_ROUTE=columns keeps the column-at-a-time route
+    const char *ev = getenv("CTQR_PANEL_ROUTE");
+    int route = !f32slab && !(ev && !strcmp(ev, "columns")) && G <= 256 && mrem > w &&
+                lds + CQ_LDS <= CQ_LDS_LIMIT;
+    if (route) lds += CQ_LDS;
+    void *args[] = {&A, (void *)&lda, &m, &r0, &w, (void *)&rows, &tau, &part, &part2, &gram_part, &route, &bar, &info};
     if (f32slab)
         HIP_TRY(hipLaunchCooperativeKernel((const void *)panel_qr_kernel<TS, float>, dim3(G), dim3(PNT), args, lds,
                                            st));
@@ -474,7 +953,7 @@ ctqr_status panel_qr(TS *A, int64_t lda, int m, int r0, int w, double *tau, doub
 
 ctqr_status panel_setup(int max_rows)
 {
-    const int l64 = (int)panel_lds_bytes(max_rows, sizeof(double));
+    const int l64 = (int)std::max(panel_lds_bytes(max_rows, sizeof(double)), CQ_LDS_LIMIT);
     const int l32 = (int)panel_lds_bytes(panel_max_rows_per_wg_f32(), sizeof(float));
     HIP_TRY(hipFuncSetAttribute((const void *)panel_qr_kernel<float, double>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, l64));

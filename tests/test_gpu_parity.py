@@ -109,6 +109,58 @@ def test_qr_fp64_random_ragged(gpu, m, n, nb, oracle_lib):
     assert np.linalg.norm(QR_rebuilt - Ad) / np.linalg.norm(Ad) <= 1e-14
 
 
+def _factor_route(monkeypatch, route, Ad, dtype, prec, nb):
+    if route is None:
+        monkeypatch.delenv("CTQR_PANEL_ROUTE", raising=False)
+    else:
+        monkeypatch.setenv("CTQR_PANEL_ROUTE", route)
+    F, info = _gpu_factor(Ad, dtype, prec, nb)
+    assert info.status == 0, C.status_string(info.status)
+    return download(F.A), download(F.tau), download(F.T)
+
+
+@pytest.mark.parametrize("m,n,nb", [(3000, 500, 128), (9000, 256, 256), (777, 300, 96), (64, 1, 32)])
+def test_panel_routes_agree(gpu, monkeypatch, m, n, nb):
+    # The inner panels run by default through Cholesky QR twice and the
+    # Householder reconstruction (four grid barriers per panel);
+    # CTQR_PANEL_ROUTE=columns forms the reflectors one column at a time.
+    # Both give the Householder V, tau and R of the column route in exact
+    # arithmetic: equal to the oracle's at the FP64 bound, to each other to
+    # rounding, and not bit for bit (so the reconstruction did run).
+    # 9000 rows: slabs of the minimum 64 rows, 141 workgroups, the last
+    # slab ragged.
+    _print_case("panel routes", m, n, nb)
+    rng = np.random.default_rng(m + 7 * n)
+    Ad = rng.standard_normal((m, n))
+    QRo, tauo = hh.geqr2(Ad)
+    scale = np.abs(QRo).max()
+    a_c, t_c, T_c = _factor_route(monkeypatch, "columns", Ad, torch.float64, C.CTQR_PREC_FP64, nb)
+    a_r, t_r, T_r = _factor_route(monkeypatch, None, Ad, torch.float64, C.CTQR_PREC_FP64, nb)
+    for a, t in ((a_c, t_c), (a_r, t_r)):
+        assert np.abs(t - tauo).max() <= 1e-11
+        assert np.abs(a - QRo).max() <= 1e-11 * scale
+    assert np.abs(a_r - a_c).max() <= 1e-12 * scale
+    assert np.abs(T_r - T_c).max() <= 1e-12 * np.abs(T_c).max()
+    if n > 1:
+        assert not (a_r == a_c).all()
+
+
+def test_panel_route_falls_back_bitwise(gpu, monkeypatch):
+    # every 32-wide panel holds a column that nearly repeats another
+    # (condition number ~1e8): one Cholesky QR pass leaves Q1^T Q1 far from
+    # I, so each panel takes the column route, and the factor equals the
+    # column route's bit for bit
+    _print_case("panel route fallback")
+    rng = np.random.default_rng(5)
+    m, n = 2000, 96
+    Ad = rng.standard_normal((m, n))
+    for c0 in range(0, n, 32):
+        Ad[:, c0 + 7] = Ad[:, c0 + 3] + 1e-8 * rng.standard_normal(m)
+    a_c, t_c, T_c = _factor_route(monkeypatch, "columns", Ad, torch.float64, C.CTQR_PREC_FP64, 32)
+    a_r, t_r, T_r = _factor_route(monkeypatch, None, Ad, torch.float64, C.CTQR_PREC_FP64, 32)
+    assert (a_r == a_c).all() and (t_r == t_c).all() and (T_r == T_c).all()
+
+
 def test_block_reflector_T(gpu, oracle_lib):
     """I - V T V^T applied to random vectors equals H_1 ... H_nb applied one
     reflector at a time (compact-WY definition of the S factors)."""
