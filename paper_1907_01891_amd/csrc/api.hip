@@ -179,7 +179,7 @@ FactorWS<T> carve_factor(void *work, int64_t m, int64_t n, int nb)
     w.part = c.take<double>(MAX_PANEL_WG + 1);
     w.part2 = c.take<double>(2LL * MAX_PANEL_WG * PANEL_XCH_STRIDE);
     w.gram_part = c.take<double>((int64_t)MAX_PANEL_WG * PANEL_W * PANEL_W);
-    w.gram = c.take<double>(PANEL_W * PANEL_W);
+    w.gram = c.take<double>(PANEL_GRAM_ELEMS);
     w.Tw = c.take<double>((int64_t)nb * nb);
     w.Tin = c.take<T>(PANEL_W * PANEL_W);
     const int g = gw_rows(nb);
@@ -479,14 +479,16 @@ ctqr_status factor_blocks(int m, int n, T *A, int64_t lda, int nb, int kb, int k
             const int wdt = std::min(PANEL_W, k0 + nbk - c0);
             {
                 PhaseScope ph(CTQR_PHASE_PANEL, st);
-                s = panel_qr<T>(A, lda, m, c0, wdt, tau + c0, w.part, w.part2, w.gram_part, w.gram,
+                s = panel_qr<T>(A, lda, m, c0, wdt, tau + c0, w.part, w.part2, w.gram_part, w.gram, w.Tin,
                                 bars + (int64_t)(c0 / PANEL_W) * GB_WORDS, info, ncu, st);
                 if (s) return s;
             }
             const int ncr = k0 + nbk - (c0 + wdt);
             if (ncr <= 0) continue;
             PhaseScope ph(CTQR_PHASE_INNER, st);
-            if ((s = tbuild<double, T>(wdt, w.gram, PANEL_W, tau + c0, w.Tin, PANEL_W, w.Tw, st))) return s;
+            if ((s = tbuild<double, T>(wdt, w.gram, PANEL_W, tau + c0, w.Tin, PANEL_W, w.Tw, st,
+                                       w.gram + PANEL_W * PANEL_W)))
+                return s;
             const T *Vp = A + (int64_t)c0 * lda + c0;
             T *Cp = A + (int64_t)(c0 + wdt) * lda + c0;
             s = gemm_tn<T>(wdt, ncr, m - c0, Vp, lda, wdt, Cp, lda, 0, T(1), T(0), w.GW, PANEL_W,

@@ -104,10 +104,10 @@ constexpr int CQ_ML = 34;            // leading dimension of the 32 x 32 LDS mat
 constexpr int CQ_MAT = 32 * CQ_ML;
 constexpr int CQ_T1 = 0, CQ_T2 = CQ_NE, CQ_QT = 2 * CQ_NE;   // totals of the two passes, Q1's top rows
 constexpr int CQ_TOT = CQ_QT + 32 * 32;
-constexpr int CQ_NMAT = 6;           // R1, R2, LU, P, R and an inverse
+constexpr int CQ_NMAT = 7;           // R1, R2, LU, P, R and two inverses
 constexpr int CQ_BUF = 96;           // row broadcasts and pivots of the small factorisations
 constexpr size_t CQ_LDS = (size_t)(CQ_NMAT * CQ_MAT + 64 + CQ_BUF) * sizeof(double);  // + signs, sums
-constexpr size_t CQ_LDS_LIMIT = 150 * 1024;                  // slab + CQ_LDS, plus ~3 KiB static LDS
+constexpr size_t CQ_LDS_LIMIT = 156 * 1024;                  // slab + CQ_LDS, plus ~3 KiB static LDS
 constexpr double CQ_ORTH_TOL = 1e-4;
 
 __device__ __attribute__((always_inline)) inline doublex4 mfma_f64(double a, double b, doublex4 c)
@@ -307,6 +307,10 @@ __device__ __attribute__((always_inline)) inline void cq_lu_signs(double *M, int
 // zeros elsewhere in the 32 x 32 block.  Gauss-Jordan from the last row up on
 // unscaled rows (X starts as I): step j publishes row j, and rows i < j
 // subtract (U_ij / U_jj) times it; row i is finally scaled by 1 / U_ii.
+// LT: invert L^T instead, for the unit lower triangular L held strictly below
+// the diagonal of U (L^T(i, j) = U[i * CQ_ML + j] for i < j, unit diagonal).
+// buf: 32 doubles.
+template <bool LT>
 __device__ __attribute__((always_inline)) inline void cq_inverse(const double *U, int w, double *X, double *buf)
 {
     const int lane = threadIdx.x % CTQR_WAVE, i = lane % 32, h = lane / 32;
@@ -318,17 +322,43 @@ __device__ __attribute__((always_inline)) inline void cq_inverse(const double *U
 #pragma unroll
             for (int t = 0; t < 16; ++t) buf[16 * h + t] = x[t];
         wave_lds_fence();
-        const double ujj = 1.0 / U[j * CQ_ML + j];
-        const double c = i < j ? U[j * CQ_ML + i] * ujj : 0.0;
+        const double ujj = LT ? 1.0 : 1.0 / U[j * CQ_ML + j];
+        const double c = i < j ? (LT ? U[i * CQ_ML + j] : U[j * CQ_ML + i]) * ujj : 0.0;
 #pragma unroll
         for (int t = 0; t < 16; ++t) x[t] -= c * buf[16 * h + t];
         wave_lds_fence();
     }
-    const double rs = i < w ? 1.0 / U[i * CQ_ML + i] : 0.0;
+    const double rs = i < w ? (LT ? 1.0 : 1.0 / U[i * CQ_ML + i]) : 0.0;
 #pragma unroll
     for (int t = 0; t < 16; ++t) {
         const int k = 16 * h + t;
         X[k * CQ_ML + i] = (i < w && k < w) ? x[t] * rs : 0.0;
+    }
+}
+
+// T = -(U' D) L^-T, the compact-WY factor of the panel's reflectors
+// (I - V T V^T = H_1 ... H_w): from Q D - [I; 0] = V U' D = -V T V_1^T with
+// V_1 = L.  Stored in storage precision, column-major with leading dimension
+// 32 (the w x w block, zeros below the diagonal).  Wave wv forms block
+// (wv / 2, wv % 2) with eight v_mfma_f64_16x16x4f64.
+template <typename TS>
+__device__ __attribute__((always_inline)) inline void cq_store_t(const double *LU, const double *dsg, const double *Lt,
+                                                                int w, TS *T)
+{
+    const int wave = threadIdx.x / CTQR_WAVE, lane = threadIdx.x % CTQR_WAVE;
+    const int bi = 16 * (wave / 2), bj = 16 * (wave % 2);
+    const int li = lane % 16, kq = lane / 16;
+    doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k0 = 0; k0 < 32; k0 += 4) {
+        const int k = k0 + kq;
+        const double a = (k >= bi + li && k < w) ? LU[k * CQ_ML + bi + li] * dsg[k] : 0.0;
+        acc = mfma_f64(a, Lt[(bj + li) * CQ_ML + k], acc);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = bi + 4 * r + kq, j = bj + li;
+        if (i < w && j < w) T[j * PW + i] = (TS)(0.0 - acc[r]);
     }
 }
 
@@ -413,18 +443,19 @@ __device__ __attribute__((always_inline)) inline void load_slab(const TS *A, int
 // slab holds R (top rows of workgroup 0, on and above the diagonal) and the
 // Householder vectors below it, and tau_s the scalars; returns false, with
 // the slab holding the original panel, when the route is not safe.  Every
-// workgroup returns the same value.  ext: CQ_LDS bytes of LDS; cq_part:
-// CQ_NE doubles per workgroup; cq_tot: CQ_TOT doubles.
+// workgroup returns the same value.  Workgroup 0 also stores the panel's
+// compact-WY factor T to Tin.  ext: CQ_LDS bytes of LDS; cq_part: CQ_NE
+// doubles per workgroup; cq_tot: CQ_TOT doubles.
 template <typename TS>
 __device__ __attribute__((always_inline)) bool cq_route(const TS *A, int64_t lda, int r0, int w, int row0,
                                                         int nrows, double *slab, int ldsl, double *ext, double *tau_s,
-                                                        double *cq_part, double *cq_tot, unsigned *bar,
+                                                        double *cq_part, double *cq_tot, TS *Tin, unsigned *bar,
                                                         unsigned &epoch, ctqr_info *info)
 {
     const int G = gridDim.x, wg = blockIdx.x, tid = threadIdx.x;
     const int lane = tid % CTQR_WAVE, wave = tid / CTQR_WAVE;
     double *R1 = ext, *R2 = ext + CQ_MAT, *LU = ext + 2 * CQ_MAT, *P = ext + 3 * CQ_MAT, *R = ext + 4 * CQ_MAT;
-    double *X = ext + 5 * CQ_MAT;
+    double *X = ext + 5 * CQ_MAT, *Lt = ext + 6 * CQ_MAT;
     double *dsg = ext + CQ_NMAT * CQ_MAT, *sub = dsg + 32, *buf = sub + 32;
     double *scr = LU;                  // Gram scratch: LU, P and R are free while the Grams run
     __shared__ int ok_s;
@@ -501,12 +532,13 @@ __device__ __attribute__((always_inline)) bool cq_route(const TS *A, int64_t lda
     // Q's top block = Q1's top rows R2^-1, then its LU with the sign choice
     cq_apply_right(LU, CQ_ML, w, w, X);
     __syncthreads();
-    if (wave == 0) {
-        cq_lu_signs(LU, w, dsg, P, buf);
-        cq_inverse(LU, w, P, buf);            // U'^-1
-    }
+    if (wave == 0) cq_lu_signs(LU, w, dsg, P, buf);
+    __syncthreads();
+    if (wave == 0) cq_inverse<false>(LU, w, P, buf);                    // U'^-1
+    else if (wave == 1 && wg == 0) cq_inverse<true>(LU, w, Lt, buf + 32);   // L^-T
     __syncthreads();
     cq_upper_product(R2, R1, R);              // R2 R1
+    if (wg == 0) cq_store_t(LU, dsg, Lt, w, Tin);
     __syncthreads();
     cq_upper_product(X, P, R1);               // (U' R2)^-1 = R2^-1 U'^-1
     if (tid < w) tau_s[tid] = -LU[tid * CQ_ML + tid] * dsg[tid];
@@ -535,7 +567,8 @@ template <typename TS, typename SL>
 __global__ __launch_bounds__(PNT)
 void panel_qr_kernel(TS *__restrict__ A, int64_t lda, int m, int r0, int w, int rows_per_wg,
                      double *__restrict__ tau_out, double *part, double *part2,
-                     double *__restrict__ gram_part, int route, unsigned *bar, ctqr_info *info)
+                     double *__restrict__ gram_part, int route, TS *__restrict__ Tin,
+                     double *__restrict__ t_done, unsigned *bar, ctqr_info *info)
 {
     constexpr int NW = PNT / CTQR_WAVE;
     constexpr int RPL = rows_per_lane<SL>();
@@ -568,7 +601,7 @@ void panel_qr_kernel(TS *__restrict__ A, int64_t lda, int m, int r0, int w, int 
         if (route)
             done = cq_route<TS>(A, lda, r0, w, row0, nrows, reinterpret_cast<double *>(slab), ldsl,
                                 reinterpret_cast<double *>(slab_raw + (size_t)ldsl * PW * sizeof(SL)), tau_s,
-                                gram_part, part2 + (int64_t)2 * G * PS, bar, epoch, info);
+                                gram_part, part2 + (int64_t)2 * G * PS, Tin, bar, epoch, info);
     }
     for (int j = 0; j < (done ? 0 : w); ++j) {
         const int p = r0 + j;                     // pivot row
@@ -751,21 +784,16 @@ void panel_qr_kernel(TS *__restrict__ A, int64_t lda, int m, int r0, int w, int 
     // 16 x 16 block per wave.  Lane l feeds row k0 + l/16 of columns
     // bi + l%16 and bj + l%16; output register r of lane l holds
     // G(bi + 4r + l/16, bj + l%16).
-    // After the reconstruction route the same sums run through cq_gram (three
-    // blocks per wave, wave partials added in wave order).
+    // After the reconstruction route T is already stored, and t_done tells
+    // the Gram reduction and the T build of this panel to return at once.
+    if (wg == 0 && tid == 0) *t_done = done ? 1.0 : 0.0;
+    if (done) return;
     __syncthreads();
     auto vval = [&](int rr, int c) -> double {
         if (rr >= nrows || c >= w) return 0.0;
         const int g = row0 + rr;
         return g == r0 + c ? 1.0 : (g > r0 + c ? (double)(TS)slab[c * ldsl + rr] : 0.0);
     };
-    if constexpr (sizeof(SL) == sizeof(double)) {
-        if (done) {
-            cq_gram(nrows, vval, reinterpret_cast<double *>(slab_raw + (size_t)ldsl * PW * sizeof(SL)),
-                    [&](int i, int j, double g) { gram_part[(int64_t)wg * PW * PW + i + PW * j] = g; });
-            return;
-        }
-    }
     {
         const int bi = 16 * (wave / 2), bj = 16 * (wave % 2);
         const int li = lane % 16, kq = lane / 16;
@@ -784,8 +812,10 @@ void panel_qr_kernel(TS *__restrict__ A, int64_t lda, int m, int r0, int w, int 
 // workgroup, 16 threads per entry each summing every 16th partial, then the
 // 16 partial sums in thread order.
 __global__ __launch_bounds__(256)
-void gram_reduce_kernel(int G, const double *__restrict__ gram_part, double *__restrict__ gram)
+void gram_reduce_kernel(int G, const double *__restrict__ gram_part, double *__restrict__ gram,
+                        const double *__restrict__ skip)
 {
+    if (*skip != 0.0) return;
     __shared__ double red[16][17];
     const int el = threadIdx.x % 16, grp = threadIdx.x / 16;
     const int e = blockIdx.x * 16 + el;
@@ -850,8 +880,9 @@ __device__ inline void tb_stage(int nb, const TG *__restrict__ Gm, int64_t ldg, 
 template <typename TG, typename TT>
 __global__ __launch_bounds__(256)
 void tbuild_kernel(int nb, const TG *__restrict__ Gm, int64_t ldg, const double *__restrict__ tau,
-                   TT *__restrict__ Tout, int64_t ldt)
+                   TT *__restrict__ Tout, int64_t ldt, const double *__restrict__ skip)
 {
+    if (skip && *skip != 0.0) return;
     __shared__ double Trow[32][TB_LD];      // rows 32p .. 32p+31 of T, all nb columns
     __shared__ double Gs[32][33];
     __shared__ double Tq[32][33];
@@ -924,7 +955,7 @@ int panel_max_rows_per_wg_f32() { return std::min((int)((152 * 1024) / (PW * siz
 
 template <typename TS>
 ctqr_status panel_qr(TS *A, int64_t lda, int m, int r0, int w, double *tau, double *part,
-                     double *part2, double *gram_part, double *gram, unsigned *bar, ctqr_info *info,
+                     double *part2, double *gram_part, double *gram, TS *Tin, unsigned *bar, ctqr_info *info,
                      int ncu, hipStream_t st)
 {
     const int mrem = m - r0;
@@ -940,14 +971,17 @@ ctqr_status panel_qr(TS *A, int64_t lda, int m, int r0, int w, double *tau, doub
     int route = !f32slab && !(ev && !strcmp(ev, "columns")) && G <= 256 && mrem > w &&
                 lds + CQ_LDS <= CQ_LDS_LIMIT;
     if (route) lds += CQ_LDS;
-    void *args[] = {&A, (void *)&lda, &m, &r0, &w, (void *)&rows, &tau, &part, &part2, &gram_part, &route, &bar, &info};
+    double *t_done = gram + PW * PW;
+    void *args[] = {&A,         (void *)&lda, &m,   &r0,     &w,   (void *)&rows, &tau, &part, &part2,
+                    &gram_part, &route,       &Tin, &t_done, &bar, &info};
     if (f32slab)
         HIP_TRY(hipLaunchCooperativeKernel((const void *)panel_qr_kernel<TS, float>, dim3(G), dim3(PNT), args, lds,
                                            st));
     else
         HIP_TRY(hipLaunchCooperativeKernel((const void *)panel_qr_kernel<TS, double>, dim3(G), dim3(PNT), args,
                                            lds, st));
-    LAUNCH_TRY(gram_reduce_kernel, dim3(PW * PW / 16), dim3(256), 0, st, G, (const double *)gram_part, gram);
+    LAUNCH_TRY(gram_reduce_kernel, dim3(PW * PW / 16), dim3(256), 0, st, G, (const double *)gram_part, gram,
+               (const double *)t_done);
     return CTQR_OK;
 }
 
@@ -966,21 +1000,25 @@ ctqr_status panel_setup(int max_rows)
 
 template <typename TG, typename TT>
 ctqr_status tbuild(int nb, const TG *G, int64_t ldg, const double *tau, TT *T, int64_t ldt, double *Tw,
-                   hipStream_t st)
+                   hipStream_t st, const double *skip)
 {
     (void)Tw;
     if (nb < 1 || nb > 32 * TB_MAXQ) return CTQR_EINVAL;
-    LAUNCH_TRY((tbuild_kernel<TG, TT>), dim3((unsigned)ceil_div(nb, 32)), dim3(256), 0, st, nb, G, ldg, tau, T, ldt);
+    LAUNCH_TRY((tbuild_kernel<TG, TT>), dim3((unsigned)ceil_div(nb, 32)), dim3(256), 0, st, nb, G, ldg, tau, T, ldt,
+               skip);
     return CTQR_OK;
 }
 
 template ctqr_status panel_qr<float>(float *, int64_t, int, int, int, double *, double *, double *,
-                                     double *, double *, unsigned *, ctqr_info *, int, hipStream_t);
+                                     double *, double *, float *, unsigned *, ctqr_info *, int, hipStream_t);
 template ctqr_status panel_qr<double>(double *, int64_t, int, int, int, double *, double *, double *,
-                                      double *, double *, unsigned *, ctqr_info *, int, hipStream_t);
+                                      double *, double *, double *, unsigned *, ctqr_info *, int, hipStream_t);
 template ctqr_status tbuild<double, float>(int, const double *, int64_t, const double *, float *, int64_t,
-                                           double *, hipStream_t);
+                                           double *, hipStream_t,
+                                           const double *);
 template ctqr_status tbuild<double, double>(int, const double *, int64_t, const double *, double *, int64_t,
-                                            double *, hipStream_t);
+                                            double *, hipStream_t,
+                                           const double *);
 template ctqr_status tbuild<float, float>(int, const float *, int64_t, const double *, float *, int64_t,
-                                          double *, hipStream_t);
+                                          double *, hipStream_t,
+                                           const double *);
