@@ -881,7 +881,8 @@ struct SolveRun {
     SolveWS<T> w;
     int64_t sp_elems;
     TrsmParts tp{};  // split-BF16 parts of the refinement's substitutions (tp.x null: none)
-    bool split_r;    // R's parts are made by this run (refine_setup), not kept by a solver
+    bool split_r;    // R's parts are made by this run, not kept by a solver
+    bool rparts_made = false;   // ... and already made (before the first substitution)
     bool fused;      // Q^T B and the substitutions as the persistent kernels (few slices, factor in HBM)
     bool refine() const { return A64 != nullptr && max_iters > 0; }
     const TrsmParts *parts() const { return tp.x ? &tp : nullptr; }
@@ -964,7 +965,8 @@ ctqr_status refine_setup(SolveRun<T> &r, hipStream_t st)
     if ((s = fill_u32((unsigned *)w.xmax, 2LL * S, 0u, st))) return s;
     if ((s = fill_u32((unsigned *)w.smax, 2LL * S, 0u, st))) return s;
     if constexpr (sizeof(T) == 4) {
-        if (r.split_r && (s = trsm_split_r(r.n, r.QR, r.lda, w.rparts, st))) return s;
+        if (r.split_r && !r.rparts_made && (s = trsm_split_r(r.n, r.QR, r.lda, w.rparts, st))) return s;
+        r.rparts_made = r.split_r;
     }
     if (r.method != CTQR_REFINE_PCG) return CTQR_OK;
     if ((s = fill_f64(w.p, (int64_t)r.n * S, 0.0, st))) return s;
@@ -1001,12 +1003,24 @@ ctqr_status solve_start(SolveRun<T> &r, hipStream_t st)
             if ((s = trinv_blocks<T>(n, r.QR, r.lda, w.Rinv, w.RinvT, r.info, st))) return s;
             r.Rinv = w.Rinv;
         }
+        // A solution that the refinement corrects needs the factor's own
+        // accuracy only, as the refinement's substitutions do: with R's
+        // split-BF16 parts (made here once for the run) the off-diagonal
+        // products take them too.
+        const TrsmParts *rp = nullptr;
+        if constexpr (sizeof(T) == 4) {
+            if (r.refine() && r.split_r && !r.rparts_made) {
+                if ((s = trsm_split_r(r.n, r.QR, r.lda, w.rparts, st))) return s;
+                r.rparts_made = true;
+            }
+            if (r.refine()) rp = r.parts();
+        }
         if (r.fused)
             s = trsm_fused<T>(n, S, false, r.QR, r.lda, r.Rinv, w.Bw, w.ldbw, w.Xw, w.ldxw, w.fex, w.fbar, nullptr,
                               r.info, st);
         else
             s = trsm_upper<T>(n, S, r.QR, r.lda, r.Rinv, w.Bw, w.ldbw, w.Xw, w.ldxw, w.split, r.sp_elems, nullptr,
-                              st);
+                              st, rp);
         if (s) return s;
     }
     PhaseScope ph(CTQR_PHASE_REFINE_OTHER, st);

@@ -105,7 +105,7 @@ constexpr int CQ_MAT = 32 * CQ_ML;
 constexpr int CQ_T1 = 0, CQ_T2 = CQ_NE, CQ_QT = 2 * CQ_NE;   // totals of the two passes, Q1's top rows
 constexpr int CQ_TOT = CQ_QT + 32 * 32;
 constexpr int CQ_NMAT = 7;           // R1, R2, LU, P, R and two inverses
-constexpr int CQ_BUF = 96;           // row broadcasts and pivots of the small factorisations
+constexpr int CQ_BUF = 192;          // row broadcasts (double-buffered) and pivots of the small factorisations
 constexpr size_t CQ_LDS = (size_t)(CQ_NMAT * CQ_MAT + 64 + CQ_BUF) * sizeof(double);  // + signs, sums
 constexpr size_t CQ_LDS_LIMIT = 156 * 1024;                  // slab + CQ_LDS, plus ~3 KiB static LDS
 constexpr double CQ_ORTH_TOL = 1e-4;
@@ -214,7 +214,7 @@ __device__ __attribute__((always_inline)) inline void wave_lds_fence()
 // X = R^-1 (same layout).  Right-looking on unscaled rows: step j publishes
 // row j of the reduced matrix G' and row j of Z (Z = R^-T is built by the
 // same elimination from I); rows i > j subtract (G'_ji / G'_jj) times both.
-// Row j of R is G'_j / sqrt(G'_jj), row j of Z is Z_j / sqrt(G'_jj).  buf: 96
+// Row j of R is G'_j / sqrt(G'_jj), row j of Z is Z_j / sqrt(G'_jj).  buf: 160
 // doubles.  Returns false when a pivot is not positive and finite (the
 // values left are then meaningless).
 __device__ __attribute__((always_inline)) inline bool cq_cholesky_inv(double *M, int w, double *X, double *buf)
@@ -228,27 +228,31 @@ __device__ __attribute__((always_inline)) inline bool cq_cholesky_inv(double *M,
         z[t] = (i == k && i < w) ? 1.0 : 0.0;
     }
     bool ok = true;
+    double *diag = buf + 128;
     for (int j = 0; j < w; ++j) {
+        // alternate halves: step j + 2 rewrites this half only after step
+        // j + 1's fence, when every read of step j has completed
+        double *b = buf + 64 * (j & 1);
         if (i == j)
 #pragma unroll
             for (int t = 0; t < 16; ++t) {
-                buf[16 * h + t] = g[t];
-                buf[32 + 16 * h + t] = z[t];
+                b[16 * h + t] = g[t];
+                b[32 + 16 * h + t] = z[t];
             }
         wave_lds_fence();
-        const double d = buf[j];
+        const double d = b[j];
         ok = ok && d > 0.0 && !isinf(d);
         const double invd = 1.0 / d;
-        const double c = i > j ? buf[i] * invd : 0.0;
+        const double c = i > j ? b[i] * invd : 0.0;
 #pragma unroll
         for (int t = 0; t < 16; ++t) {
-            g[t] -= c * buf[16 * h + t];
-            z[t] -= c * buf[32 + 16 * h + t];
+            g[t] -= c * b[16 * h + t];
+            z[t] -= c * b[32 + 16 * h + t];
         }
-        if (lane == 0) buf[64 + j] = sqrt(d);
-        wave_lds_fence();
+        if (lane == 0) diag[j] = sqrt(d);
     }
-    const double r = i < w ? buf[64 + i] : 1.0, rs = 1.0 / r;
+    wave_lds_fence();
+    const double r = i < w ? diag[i] : 1.0, rs = 1.0 / r;
 #pragma unroll
     for (int t = 0; t < 16; ++t) {
         const int k = 16 * h + t;
@@ -262,13 +266,12 @@ __device__ __attribute__((always_inline)) inline bool cq_cholesky_inv(double *M,
 // LU factorisation with the reconstruction's sign choice of the w x w block
 // M (column-major), in place: the strict lower triangle becomes V's top block
 // (unit diagonal implied), the upper triangle U'; dsign[j] = d_j.  Entries
-// outside the w x w block stay 0.  Every step writes the current rows to the
-// row-major scratch S (32 x CQ_ML), from which the pivot row and each row's
-// entry in the pivot column are read; rows i > j then subtract
-// l_i = S(i, j) / p_j times the pivot row.  buf: 64 doubles (the pivots and
-// the multipliers' column).
-__device__ __attribute__((always_inline)) inline void cq_lu_signs(double *M, int w, double *dsign, double *S,
-                                                                 double *buf)
+// outside the w x w block stay 0.  Every step writes the current rows to a
+// row-major scratch (32 x CQ_ML, S0 and S1 in turn), from which the pivot row
+// and each row's entry in the pivot column are read; rows i > j then subtract
+// l_i = S(i, j) / p_j times the pivot row.  buf: 32 doubles (the pivots).
+__device__ __attribute__((always_inline)) inline void cq_lu_signs(double *M, int w, double *dsign, double *S0,
+                                                                 double *S1, double *buf)
 {
     const int lane = threadIdx.x % CTQR_WAVE, i = lane % 32, h = lane / 32;
     double a[16];
@@ -278,6 +281,7 @@ __device__ __attribute__((always_inline)) inline void cq_lu_signs(double *M, int
         a[t] = (i < w && k < w) ? M[k * CQ_ML + i] : 0.0;
     }
     for (int j = 0; j < w; ++j) {
+        double *S = (j & 1) ? S1 : S0;         // alternate scratch, as in cq_cholesky_inv
 #pragma unroll
         for (int t = 0; t < 16; ++t) S[i * CQ_ML + 16 * h + t] = a[t];
         wave_lds_fence();
@@ -293,8 +297,8 @@ __device__ __attribute__((always_inline)) inline void cq_lu_signs(double *M, int
             buf[j] = piv;
         }
         if (h == 0 && i > j) M[j * CQ_ML + i] = l;       // column j of L
-        wave_lds_fence();
     }
+    wave_lds_fence();
 #pragma unroll
     for (int t = 0; t < 16; ++t) {
         const int k = 16 * h + t;
@@ -309,7 +313,7 @@ __device__ __attribute__((always_inline)) inline void cq_lu_signs(double *M, int
 // subtract (U_ij / U_jj) times it; row i is finally scaled by 1 / U_ii.
 // LT: invert L^T instead, for the unit lower triangular L held strictly below
 // the diagonal of U (L^T(i, j) = U[i * CQ_ML + j] for i < j, unit diagonal).
-// buf: 32 doubles.
+// buf: 64 doubles.
 template <bool LT>
 __device__ __attribute__((always_inline)) inline void cq_inverse(const double *U, int w, double *X, double *buf)
 {
@@ -318,16 +322,17 @@ __device__ __attribute__((always_inline)) inline void cq_inverse(const double *U
 #pragma unroll
     for (int t = 0; t < 16; ++t) x[t] = (i == 16 * h + t && i < w) ? 1.0 : 0.0;
     for (int j = w - 1; j >= 0; --j) {
+        double *b = buf + 32 * (j & 1);         // alternate halves, as in cq_cholesky_inv
         if (i == j)
 #pragma unroll
-            for (int t = 0; t < 16; ++t) buf[16 * h + t] = x[t];
+            for (int t = 0; t < 16; ++t) b[16 * h + t] = x[t];
         wave_lds_fence();
         const double ujj = LT ? 1.0 : 1.0 / U[j * CQ_ML + j];
         const double c = i < j ? (LT ? U[i * CQ_ML + j] : U[j * CQ_ML + i]) * ujj : 0.0;
 #pragma unroll
-        for (int t = 0; t < 16; ++t) x[t] -= c * buf[16 * h + t];
-        wave_lds_fence();
+        for (int t = 0; t < 16; ++t) x[t] -= c * b[16 * h + t];
     }
+    wave_lds_fence();
     const double rs = i < w ? (LT ? 1.0 : 1.0 / U[i * CQ_ML + i]) : 0.0;
 #pragma unroll
     for (int t = 0; t < 16; ++t) {
@@ -532,10 +537,10 @@ __device__ __attribute__((always_inline)) bool cq_route(const TS *A, int64_t lda
     // Q's top block = Q1's top rows R2^-1, then its LU with the sign choice
     cq_apply_right(LU, CQ_ML, w, w, X);
     __syncthreads();
-    if (wave == 0) cq_lu_signs(LU, w, dsg, P, buf);
+    if (wave == 0) cq_lu_signs(LU, w, dsg, P, R, buf);
     __syncthreads();
     if (wave == 0) cq_inverse<false>(LU, w, P, buf);                    // U'^-1
-    else if (wave == 1 && wg == 0) cq_inverse<true>(LU, w, Lt, buf + 32);   // L^-T
+    else if (wave == 1 && wg == 0) cq_inverse<true>(LU, w, Lt, buf + 64);   // L^-T
     __syncthreads();
     cq_upper_product(R2, R1, R);              // R2 R1
     if (wg == 0) cq_store_t(LU, dsg, Lt, w, Tin);
