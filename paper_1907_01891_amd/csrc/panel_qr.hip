@@ -37,6 +37,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <algorithm>
+#include <mutex>
 #include "common.h"
 #include "kernels.h"
 
@@ -940,6 +941,83 @@ void tbuild_kernel(int nb, const TG *__restrict__ Gm, int64_t ldg, const double 
     }
 }
 
+// Blocks wider than 32: first every diagonal block T_qq by the recurrence
+// above (one workgroup each, FP64, to the workspace Tw), then every block
+// column on its own.  With U = diag(1 / tau) + striu(G), T = U^-1 (the
+// recurrence is the column-by-column form of that inverse), so
+// U_pp T_pq = -sum_{k=p+1}^{q} G_pk T_kq, i.e.
+// T_pq = -T_pp sum_{k=p+1}^{q} G_pk T_kq, for p = q-1 down to 0: each
+// block column is a chain of q products of its own, and the block columns
+// run in parallel.
+template <typename TG>
+__global__ __launch_bounds__(256)
+void tbuild_diag_kernel(int nb, const TG *__restrict__ Gm, int64_t ldg, const double *__restrict__ tau,
+                        double *__restrict__ Tw)
+{
+    __shared__ double Gs[32][33];
+    __shared__ double Tq[32][33];
+    const int q = blockIdx.x;
+    tb_stage(nb, Gm, ldg, q, q, Gs);
+    __syncthreads();
+    tb_diag(q, nb, Gs, tau, Tq);
+    __syncthreads();
+    for (int e = threadIdx.x; e < 1024; e += 256) {
+        const int i = e % 32, j = e / 32, gi = 32 * q + i, gj = 32 * q + j;
+        if (gi < nb && gj < nb) Tw[(int64_t)gj * nb + gi] = Tq[i][j];
+    }
+}
+
+constexpr size_t TB_COL_LDS = (size_t)(32 * TB_MAXQ * 33 + 32 * TB_LD + 2 * 32 * 33) * sizeof(double);
+
+template <typename TG, typename TT>
+__global__ __launch_bounds__(256)
+void tbuild_col_kernel(int nb, const TG *__restrict__ Gm, int64_t ldg, const double *__restrict__ Tw,
+                       TT *__restrict__ Tout, int64_t ldt)
+{
+    extern __shared__ __attribute__((aligned(16))) double tbsm[];
+    double (*Tc)[33] = reinterpret_cast<double (*)[33]>(tbsm);                        // block column q, by rows
+    double (*Gp)[TB_LD] = reinterpret_cast<double (*)[TB_LD]>(tbsm + 32 * TB_MAXQ * 33);   // row panel p of G
+    double (*Tp)[33] = reinterpret_cast<double (*)[33]>(tbsm + 32 * TB_MAXQ * 33 + 32 * TB_LD);   // T_pp
+    double (*Sx)[33] = Tp + 32;                                                       // the sum
+    const int q = blockIdx.x, tid = threadIdx.x;
+    const int i = tid % 32, j0 = tid / 32;
+    for (int e = tid; e < 1024; e += 256) {
+        const int a = e % 32, b = e / 32, ga = 32 * q + a, gb = 32 * q + b;
+        Tc[32 * q + a][b] = (ga < nb && gb < nb) ? Tw[(int64_t)gb * nb + ga] : 0.0;
+    }
+    for (int p = q - 1; p >= 0; --p) {
+        const int c0 = 32 * (p + 1), cw = 32 * (q - p);
+        for (int e = tid; e < 32 * cw; e += 256) {
+            const int a = e % 32, c = e / 32, ga = 32 * p + a, gc = c0 + c;
+            Gp[a][c] = gc < nb ? (double)Gm[(int64_t)gc * ldg + ga] : 0.0;
+        }
+        for (int e = tid; e < 1024; e += 256) {
+            const int a = e % 32, b = e / 32;
+            Tp[a][b] = Tw[(int64_t)(32 * p + b) * nb + 32 * p + a];
+        }
+        __syncthreads();
+        for (int u = 0; u < 4; ++u) {
+            const int j = j0 + 8 * u;
+            double acc = 0.0;
+            for (int c = 0; c < cw; ++c) acc += Gp[i][c] * Tc[c0 + c][j];
+            Sx[i][j] = acc;
+        }
+        __syncthreads();
+        for (int u = 0; u < 4; ++u) {
+            const int j = j0 + 8 * u;
+            double acc = 0.0;
+#pragma unroll 8
+            for (int c = 0; c < 32; ++c) acc += Tp[i][c] * Sx[c][j];
+            Tc[32 * p + i][j] = -acc;
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < 32 * nb; e += 256) {
+        const int r = e % nb, b = e / nb, gb = 32 * q + b;
+        if (gb < nb) Tout[(int64_t)gb * ldt + r] = r < 32 * q + 32 ? (TT)Tc[r][b] : TT(0);
+    }
+}
+
 }  // namespace
 
 int panel_rows_per_wg(int mrem, int ncu)
@@ -1007,10 +1085,24 @@ template <typename TG, typename TT>
 ctqr_status tbuild(int nb, const TG *G, int64_t ldg, const double *tau, TT *T, int64_t ldt, double *Tw,
                    hipStream_t st, const double *skip)
 {
-    (void)Tw;
     if (nb < 1 || nb > 32 * TB_MAXQ) return CTQR_EINVAL;
-    LAUNCH_TRY((tbuild_kernel<TG, TT>), dim3((unsigned)ceil_div(nb, 32)), dim3(256), 0, st, nb, G, ldg, tau, T, ldt,
-               skip);
+    if (nb <= 32 || Tw == nullptr) {
+        LAUNCH_TRY((tbuild_kernel<TG, TT>), dim3((unsigned)ceil_div(nb, 32)), dim3(256), 0, st, nb, G, ldg, tau, T,
+                   ldt, skip);
+        return CTQR_OK;
+    }
+    if (skip) return CTQR_EINVAL;          // (only the 32-wide inner T build is skippable)
+    static std::once_flag once;
+    static hipError_t attr = hipSuccess;
+    std::call_once(once, [] {
+        attr = hipFuncSetAttribute((const void *)tbuild_col_kernel<TG, TT>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)TB_COL_LDS);
+    });
+    HIP_TRY(attr);
+    const unsigned nq = (unsigned)ceil_div(nb, 32);
+    LAUNCH_TRY((tbuild_diag_kernel<TG>), dim3(nq), dim3(256), 0, st, nb, G, ldg, tau, Tw);
+    LAUNCH_TRY((tbuild_col_kernel<TG, TT>), dim3(nq), dim3(256), TB_COL_LDS, st, nb, G, ldg, (const double *)Tw, T,
+               ldt);
     return CTQR_OK;
 }
 
