@@ -787,6 +787,7 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - tw0
     launches, kern_ms, kern_flops = C.ctqr_profile_read()
+    red_launches, red_ms, red_flops = C.ctqr_profile_read_reduction()
     C.ctqr_profile_enable(False)
     finfo, sinfo = F.info.read(), F.sinfo.read()
     t_build = np.mean([t[0] for t in times])
@@ -940,6 +941,20 @@ def main():
         "flops_per_launch_counts": "2 rows cols K (one FP32-equivalent product; the split-BF16 "
                                    "update executes three BF16 products of this size)",
     })
+    # The other large product of the factorization: the reductions
+    # [G | W] = V^T [V | C] (every block column and group), timed the same way
+    # on the last timed step.  Method flops 2 M N K per launch.
+    red_tf = red_flops / (red_ms * 1e-3) / 1e12 if red_ms > 0 else None
+    red_peak = PEAK_TFLOPS["f32"] if args.prec == "fp32" else PEAK_TFLOPS["bf16"]
+    roof_red = {"bound": "mfma",
+                "kernel": ("gemm_tn_kernel (FP32 MFMA)" if args.prec == "fp32" else
+                           "gemm_tn_bf16x3_kernel (split-BF16, C split while staged)") + ": [G | W] = V^T [V | C]",
+                "achieved": red_tf, "peak": red_peak, "unit": "TFLOP/s",
+                "frac": red_tf / red_peak if red_tf else None,
+                "achieved_counts": "method flops 2 M N K per launch (one FP32-equivalent product)",
+                "mfma_tflops_executed_bf16": 3 * red_tf if (red_tf and args.prec == "bf16x3") else None,
+                "launches": red_launches, "avg_launch_ms": red_ms / red_launches if red_launches else None,
+                "total_ms": red_ms, "flops_per_launch": red_flops / red_launches if red_launches else None}
     products = {"bf16x3": "split-BF16 MFMA block-column products (high + low bf16 parts, three products, FP32 "
                           "accumulation)",
                 "fp32": "FP32-MFMA block-column products"}[args.prec]
@@ -979,6 +994,7 @@ def main():
         "qr_info_status": int(finfo.status),
         "rdiag_min_max": [finfo.rdiag_min, finfo.rdiag_max],
         "roofline": roof,
+        "roofline_reduction": roof_red,
         "cpu_baseline": cpu,
         "request_stream": stream_out,
         "tile_qr": tile,

@@ -681,6 +681,12 @@ ctqr_status ctqr_release(void);
 #define CTQR_PROFILE_PHASES 2
 ctqr_status ctqr_profile_enable(int32_t on);
 ctqr_status ctqr_profile_read(int64_t *launches, double *total_ms, double *total_flops);
+/* The same records for the other large product of the factorization, the
+ * reductions [G | W] = V^T [V | C] of every block column and group (one
+ * launch of the product per reduction; K = the rows below the block, flops
+ * 2 * M * N * K with M the reflectors' count and N the columns of [V | C]),
+ * taken while CTQR_PROFILE_UPDATE is enabled. */
+ctqr_status ctqr_profile_read_reduction(int64_t *launches, double *total_ms, double *total_flops);
 
 /* Phase timing (ctqr_profile_enable with the CTQR_PROFILE_PHASES bit): the
  * factorization and every direct solve record HIP events around their phases

@@ -34,6 +34,7 @@ struct ProfRec {
 std::mutex g_prof_mu;
 bool g_prof_on = false;
 std::vector<ProfRec> g_prof;
+std::vector<ProfRec> g_prof_red;   // the [G | W] reductions' products, likewise
 
 // Phase timing (ctqr_profile_enable bit 2): HIP events around the phases of
 // a factorization or a direct solve, on the stream they run on (not inside
@@ -394,16 +395,44 @@ template <typename T>
 ctqr_status block_reduction(int M, int N, int K, const T *V, int64_t lda, const T *B, int64_t ldb, int bmask,
                             FactorWS<T> &w, int ldg, int force_splits, hipStream_t st)
 {
+    bool prof = false;
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        prof = g_prof_on;
+    }
+    ProfRec rec{};
+    ctqr_status s = CTQR_OK;
+    bool done = false;
     if constexpr (sizeof(T) == 4) {
         if (w.bf16 == 2) {
-            ctqr_status s = bf16x3_split_vt(K, M, V, lda, w.vtsplit, w.vtsplit_elems, st);
-            if (s) return s;
-            return gemm_tn_bf16x3(M, N, K, w.vtsplit, w.vtsplit_elems, B, ldb, bmask, 1.0f, 0.0f, w.GW, ldg, w.split,
-                                  SPLIT_PART_ELEMS, nullptr, st, force_splits);
+            if ((s = bf16x3_split_vt(K, M, V, lda, w.vtsplit, w.vtsplit_elems, st))) return s;
+            if (prof) {
+                HIP_TRY(hipEventCreate(&rec.a));
+                HIP_TRY(hipEventCreate(&rec.b));
+                HIP_TRY(hipEventRecord(rec.a, st));
+            }
+            s = gemm_tn_bf16x3(M, N, K, w.vtsplit, w.vtsplit_elems, B, ldb, bmask, 1.0f, 0.0f, w.GW, ldg, w.split,
+                               SPLIT_PART_ELEMS, nullptr, st, force_splits);
+            done = true;
         }
     }
-    return gemm_tn<T>(M, N, K, V, lda, M, B, ldb, bmask, T(1), T(0), w.GW, ldg, w.split, SPLIT_PART_ELEMS, nullptr,
-                      st, force_splits, w.bf16);
+    if (!done) {
+        if (prof) {
+            HIP_TRY(hipEventCreate(&rec.a));
+            HIP_TRY(hipEventCreate(&rec.b));
+            HIP_TRY(hipEventRecord(rec.a, st));
+        }
+        s = gemm_tn<T>(M, N, K, V, lda, M, B, ldb, bmask, T(1), T(0), w.GW, ldg, w.split, SPLIT_PART_ELEMS, nullptr,
+                       st, force_splits, w.bf16);
+    }
+    if (s) return s;
+    if (prof) {
+        HIP_TRY(hipEventRecord(rec.b, st));
+        rec.flops = 2.0 * (double)M * (double)N * (double)K;
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        g_prof_red.push_back(rec);
+    }
+    return CTQR_OK;
 }
 
 // Split counts of the two reductions of block k0 in the all-in-HBM
@@ -2505,11 +2534,13 @@ ctqr_status ctqr_set_progress(ctqr_progress_fn fn, void *user)
 ctqr_status ctqr_profile_enable(int32_t on)
 {
     std::lock_guard<std::mutex> lk(g_prof_mu);
-    for (auto &r : g_prof) {
-        (void)hipEventDestroy(r.a);
-        (void)hipEventDestroy(r.b);
+    for (auto *v : {&g_prof, &g_prof_red}) {
+        for (auto &r : *v) {
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
+        }
+        v->clear();
     }
-    g_prof.clear();
     for (auto &r : g_phase) {
         (void)hipEventDestroy(r.a);
         (void)hipEventDestroy(r.b);
@@ -2526,11 +2557,13 @@ ctqr_status ctqr_release(void)
         HIP_TRY(hipDeviceSynchronize());
         {
             std::lock_guard<std::mutex> lk(g_prof_mu);
-            for (auto &r : g_prof) {
-                (void)hipEventDestroy(r.a);
-                (void)hipEventDestroy(r.b);
+            for (auto *v : {&g_prof, &g_prof_red}) {
+                for (auto &r : *v) {
+                    (void)hipEventDestroy(r.a);
+                    (void)hipEventDestroy(r.b);
+                }
+                v->clear();
             }
-            g_prof.clear();
             for (auto &r : g_phase) {
                 (void)hipEventDestroy(r.a);
                 (void)hipEventDestroy(r.b);
@@ -2569,6 +2602,30 @@ ctqr_status ctqr_profile_phases(double *ms, int64_t *count)
         count[r.phase] += 1;
     }
     return CTQR_OK;
+}
+
+static ctqr_status profile_sum(const std::vector<ProfRec> &v, int64_t *launches, double *total_ms,
+                               double *total_flops)
+{
+    if (!launches || !total_ms || !total_flops) return CTQR_EINVAL;
+    double ms = 0.0, fl = 0.0;
+    for (auto &r : v) {
+        float t = 0.f;
+        HIP_TRY(hipEventSynchronize(r.b));
+        HIP_TRY(hipEventElapsedTime(&t, r.a, r.b));
+        ms += t;
+        fl += r.flops;
+    }
+    *launches = (int64_t)v.size();
+    *total_ms = ms;
+    *total_flops = fl;
+    return CTQR_OK;
+}
+
+ctqr_status ctqr_profile_read_reduction(int64_t *launches, double *total_ms, double *total_flops)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    return profile_sum(g_prof_red, launches, total_ms, total_flops);
 }
 
 ctqr_status ctqr_profile_read(int64_t *launches, double *total_ms, double *total_flops)

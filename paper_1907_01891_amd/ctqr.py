@@ -124,6 +124,7 @@ _SIGNATURES = {
     "ctqr_set_progress": (c_i32, [ctqr_progress_fn, c_vp]),
     "ctqr_profile_enable": (c_i32, [c_i32]),
     "ctqr_profile_read": (c_i32, [_P(c_i64), _P(c_dbl), _P(c_dbl)]),
+    "ctqr_profile_read_reduction": (c_i32, [_P(c_i64), _P(c_dbl), _P(c_dbl)]),
     "ctqr_profile_phases": (c_i32, [_P(c_dbl), _P(c_i64)]),
     "ctqr_release": (c_i32, []),
 }
@@ -405,4 +406,11 @@ def ctqr_profile_phases():
 def ctqr_profile_read():
     n, ms, fl = c_i64(), c_dbl(), c_dbl()
     check(lib().ctqr_profile_read(ctypes.byref(n), ctypes.byref(ms), ctypes.byref(fl)), "ctqr_profile_read")
+    return n.value, ms.value, fl.value
+
+
+def ctqr_profile_read_reduction():
+    n, ms, fl = c_i64(), c_dbl(), c_dbl()
+    check(lib().ctqr_profile_read_reduction(ctypes.byref(n), ctypes.byref(ms), ctypes.byref(fl)),
+          "ctqr_profile_read_reduction")
     return n.value, ms.value, fl.value
