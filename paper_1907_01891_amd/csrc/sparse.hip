@@ -43,6 +43,60 @@ void spmm_rm_kernel(int64_t rows, int S, int SW, const int64_t *__restrict__ ptr
     }
 }
 
+// Wide rows (S > 192, one row per workgroup, slice s0 + 256 p in thread
+// s0): the row's indices and values staged in LDS 256 at a time, so each
+// thread keeps eight gathers of x in flight instead of waiting on an index
+// load before each one.  Same products in the same order as spmm_rm_kernel.
+template <int MAXP>
+__global__ __launch_bounds__(256)
+void spmm_rm_staged_kernel(int64_t rows, int S, const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
+                           const double *__restrict__ val, double alpha, const double *__restrict__ x, double beta,
+                           const double *__restrict__ y_in, double *__restrict__ y, const int *skip)
+{
+    if (skip && *skip) return;
+    __shared__ int32_t si[256];
+    __shared__ double sv[256];
+    unsigned blk = blockIdx.x;
+    const unsigned per = gridDim.x / 8;
+    if (blk < per * 8) blk = (blk % 8) * per + blk / 8;
+    const int64_t i = blk;
+    if (i >= rows) return;
+    const int tid = threadIdx.x;
+    const int P = (S + 255) / 256;
+    const int64_t b = ptr[i], e = ptr[i + 1];
+    double acc[MAXP];
+#pragma unroll
+    for (int p = 0; p < MAXP; ++p) acc[p] = 0.0;
+    for (int64_t c0 = b; c0 < e; c0 += 256) {
+        const int n = (int)min((int64_t)256, e - c0);
+        __syncthreads();
+        if (tid < n) {
+            si[tid] = idx[c0 + tid];
+            sv[tid] = val[c0 + tid];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int p = 0; p < MAXP; ++p) {
+            const int sl = 256 * p + tid;
+            if (p < P && sl < S) {
+                double a = acc[p];
+#pragma unroll 8
+                for (int k = 0; k < n; ++k) a += sv[k] * x[(int64_t)si[k] * S + sl];
+                acc[p] = a;
+            }
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < MAXP; ++p) {
+        const int sl = 256 * p + tid;
+        if (p < P && sl < S) {
+            double out = alpha * acc[p];
+            if (beta != 0.0) out += beta * y_in[i * S + sl];
+            y[i * S + sl] = out;
+        }
+    }
+}
+
 // Narrow form (S <= 64): one wave per row, its lanes split into 64 / SP
 // groups of SP slices (SP = S rounded up to a power of two).  Group g sums the
 // row's nonzeros g, g + G, g + 2G, ... in order; the groups' sums are then
@@ -400,6 +454,17 @@ ctqr_status spmm_rowmajor(int64_t rows, int S, const int64_t *ptr, const int32_t
         else if (S <= 32) CTQR_SPMM_NARROW(32);
         else CTQR_SPMM_NARROW(64);
 #undef CTQR_SPMM_NARROW
+        return CTQR_OK;
+    }
+    if (S > 192 && S <= 2048) {
+#define CTQR_SPMM_STAGED(P)                                                                                    \
+    LAUNCH_TRY(spmm_rm_staged_kernel<P>, dim3((unsigned)rows), dim3(256), 0, st, rows, S, ptr, idx, val, alpha, x, \
+               beta, y_in, y, skip)
+        if (S <= 256) CTQR_SPMM_STAGED(1);
+        else if (S <= 512) CTQR_SPMM_STAGED(2);
+        else if (S <= 1024) CTQR_SPMM_STAGED(4);
+        else CTQR_SPMM_STAGED(8);
+#undef CTQR_SPMM_STAGED
         return CTQR_OK;
     }
     int SW = (int)std::min<int64_t>(256, ceil_div(S, 64) * 64);
