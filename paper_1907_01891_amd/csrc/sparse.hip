@@ -45,7 +45,7 @@ void spmm_rm_kernel(int64_t rows, int S, int SW, const int64_t *__restrict__ ptr
 
 // Wide rows (S > 192, one row per workgroup, slice s0 + 256 p in thread
 // s0): the row's indices and values staged in LDS 256 at a time, so each
-// thread keeps eight gathers of x in flight instead of waiting on an index
+// thread keeps sixteen gathers of x in flight instead of waiting on an index
 // load before each one.  Same products in the same order as spmm_rm_kernel.
 template <int MAXP>
 __global__ __launch_bounds__(256)
@@ -80,7 +80,7 @@ void spmm_rm_staged_kernel(int64_t rows, int S, const int64_t *__restrict__ ptr,
             const int sl = 256 * p + tid;
             if (p < P && sl < S) {
                 double a = acc[p];
-#pragma unroll 8
+#pragma unroll 16
                 for (int k = 0; k < n; ++k) a += sv[k] * x[(int64_t)si[k] * S + sl];
                 acc[p] = a;
             }
