@@ -520,11 +520,9 @@ ctqr_status factor_blocks(int m, int n, T *A, int64_t lda, int nb, int kb, int k
                 return s;
             const T *Vp = A + (int64_t)c0 * lda + c0;
             T *Cp = A + (int64_t)(c0 + wdt) * lda + c0;
-            s = gemm_tn<T>(wdt, ncr, m - c0, Vp, lda, wdt, Cp, lda, 0, T(1), T(0), w.GW, PANEL_W,
-                           w.split, SPLIT_PART_ELEMS, nullptr, st);
-            if (s) return s;
-            s = gemm_tn<T>(wdt, ncr, wdt, w.Tin, PANEL_W, 0, w.GW, PANEL_W, 0, T(1), T(0), w.W2, PANEL_W,
-                           w.split, SPLIT_PART_ELEMS, nullptr, st);
+            // W2 = T^T (V^T C): the split-K sum and the product with T^T in one launch
+            s = gemm_tn_tprod<T>(wdt, ncr, m - c0, Vp, lda, wdt, Cp, lda, w.Tin, PANEL_W, w.GW, PANEL_W, w.W2,
+                                 PANEL_W, w.split, SPLIT_PART_ELEMS, st);
             if (s) return s;
             s = gemm_nn<T>(m - c0, ncr, wdt, Vp, lda, 1, w.W2, PANEL_W, T(-1), Cp, lda, nullptr, st);
             if (s) return s;

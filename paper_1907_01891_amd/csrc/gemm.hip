@@ -685,6 +685,43 @@ void splitk_reduce_kernel(int M, int N, int splits, const T *__restrict__ part,
     }
 }
 
+// W2 = Tt^T W for W = the sum of `splits` partials of an M x N product (M <=
+// 32; partial z of element (m, n) at src[z zstride + n ld + m]), one
+// workgroup of 16 waves per two columns: the sum in the order of
+// splitk_reduce_kernel<T, 16>, then each output as sum_k Tt(k, m) W(k, n) in
+// k order.
+template <typename T>
+__global__ __launch_bounds__(1024)
+void tprod_reduce_kernel(int M, int N, int splits, const T *__restrict__ src, int64_t ld, int64_t zstride,
+                         const T *__restrict__ Tt, int64_t ldt, T *__restrict__ W2, int64_t ldw)
+{
+    __shared__ T red[16][64];
+    __shared__ T col[64];
+    const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+    const int c = lane / 32, m = lane % 32;
+    const int n = blockIdx.x * 2 + c;
+    const bool ok = n < N && m < M;
+    T acc = T(0);
+    if (ok) {
+#pragma unroll 4
+        for (int z = w; z < splits; z += 16) acc += src[(int64_t)z * zstride + (int64_t)n * ld + m];
+    }
+    red[w][lane] = acc;
+    __syncthreads();
+    if (w == 0) {
+        T v = red[0][lane];
+#pragma unroll
+        for (int k = 1; k < 16; ++k) v += red[k][lane];
+        col[lane] = ok ? v : T(0);
+    }
+    __syncthreads();
+    if (w == 0 && ok) {
+        T s = T(0);
+        for (int k = 0; k < M; ++k) s += Tt[(int64_t)m * ldt + k] * col[32 * c + k];
+        W2[(int64_t)n * ldw + m] = s;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // NN:  C += alpha * A B   (A: M x K, optionally a Householder block; B: K x N)
 // ---------------------------------------------------------------------------
@@ -1321,6 +1358,32 @@ ctqr_status gemm_tn(int M, int N, int K, const T *A, int64_t lda, int amask, con
 }
 
 template <typename T>
+ctqr_status gemm_tn_tprod(int M, int N, int K, const T *A, int64_t lda, int amask, const T *B, int64_t ldb,
+                          const T *Tt, int64_t ldt, T *Out, int64_t ldo, T *W2, int64_t ldw, T *part,
+                          size_t part_elems, hipStream_t st)
+{
+    if (M <= 0 || N <= 0) return CTQR_OK;
+    if (M > 32) return CTQR_EINVAL;
+    const bool narrow = N <= t_narrow_max;
+    int splits = gemm_tn_splits(M, N, K);
+    if (splits > 1 && (part == nullptr || part_elems < (size_t)splits * M * N)) splits = 1;
+    int kchunk = (int)ceil_div(ceil_div(K, splits), Mf<T>::BK) * Mf<T>::BK;
+    if (kchunk <= 0) kchunk = Mf<T>::BK;
+    splits = (int)ceil_div(K > 0 ? K : 1, kchunk);
+    dim3 grid((unsigned)(ceil_div(M, TILE) * ceil_div(N, narrow ? NARROW : TILE)), 1, (unsigned)splits);
+    if (narrow)
+        LAUNCH_TRY((gemm_tn_kernel<T, NARROW, 0>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B, ldb, 0,
+                   T(1), T(0), Out, ldo, part, kchunk, (const int *)nullptr);
+    else
+        LAUNCH_TRY((gemm_tn_kernel<T, TILE, 0>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B, ldb, 0,
+                   T(1), T(0), Out, ldo, part, kchunk, (const int *)nullptr);
+    const bool sp = splits > 1;
+    LAUNCH_TRY(tprod_reduce_kernel<T>, dim3((unsigned)ceil_div(N, 2)), dim3(1024), 0, st, M, N, splits,
+               sp ? (const T *)part : (const T *)Out, sp ? (int64_t)M : ldo, (int64_t)M * N, Tt, ldt, W2, ldw);
+    return CTQR_OK;
+}
+
+template <typename T>
 ctqr_status gemm_nn(int M, int N, int K, const T *A, int64_t lda, int amask, const T *B,
                     int64_t ldb, T alpha, T *C, int64_t ldc, const int *skip, hipStream_t st, int kind,
                     int accum, int bf16)
@@ -1536,6 +1599,12 @@ template ctqr_status gemm_tn<float>(int, int, int, const float *, int64_t, int, 
 template ctqr_status gemm_tn<double>(int, int, int, const double *, int64_t, int, const double *,
                                      int64_t, int, double, double, double *, int64_t, double *,
                                      size_t, const int *, hipStream_t, int, int);
+template ctqr_status gemm_tn_tprod<float>(int, int, int, const float *, int64_t, int, const float *, int64_t,
+                                          const float *, int64_t, float *, int64_t, float *, int64_t, float *,
+                                          size_t, hipStream_t);
+template ctqr_status gemm_tn_tprod<double>(int, int, int, const double *, int64_t, int, const double *, int64_t,
+                                           const double *, int64_t, double *, int64_t, double *, int64_t,
+                                           double *, size_t, hipStream_t);
 template ctqr_status gemm_nn<float>(int, int, int, const float *, int64_t, int, const float *,
                                     int64_t, float, float *, int64_t, const int *, hipStream_t, int, int, int);
 template ctqr_status gemm_nn<double>(int, int, int, const double *, int64_t, int, const double *,

@@ -20,6 +20,14 @@ ctqr_status gemm_tn(int M, int N, int K, const T *A, int64_t lda, int amask, con
                     int64_t ldb, int bmask, T alpha, T beta, T *Out, int64_t ldo, T *part,
                     size_t part_elems, const int *skip, hipStream_t st, int force_splits = 0,
                     int bf16 = 0);
+// W2 = Tt^T (A^T B) for a product of at most 32 rows (the update by a 32-wide
+// inner panel, Tt its 32 x 32 factor): A^T B as gemm_tn (written to Out when
+// it is not split over K), then one launch that finishes the split-K sum and
+// multiplies by Tt^T.
+template <typename T>
+ctqr_status gemm_tn_tprod(int M, int N, int K, const T *A, int64_t lda, int amask, const T *B, int64_t ldb,
+                          const T *Tt, int64_t ldt, T *Out, int64_t ldo, T *W2, int64_t ldw, T *part,
+                          size_t part_elems, hipStream_t st);
 template <typename T>
 ctqr_status gemm_nn(int M, int N, int K, const T *A, int64_t lda, int amask, const T *B,
                     int64_t ldb, T alpha, T *C, int64_t ldc, const int *skip, hipStream_t st,
