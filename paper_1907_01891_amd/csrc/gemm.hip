@@ -40,6 +40,7 @@
 // below the FP32 accumulation's own rounding for most sums).  The Householder
 // block V is split once per block column, in the layout each product reads;
 // C, read by only two tiles of [G | W], is split while staged.
+#include <cstdint>
 #include <cstdlib>
 #include <type_traits>
 
@@ -858,31 +859,48 @@ void gemm_nn_kernel(int M, int N, int K,
 
 // V (rows x kc Householder block: unit lower trapezoidal, column-major) to
 // high / low bf16 parts, row-major with row stride ldv (k contiguous); rows up
-// to rows_pad and k up to ldv are zero.  Thread: one row, 8 consecutive k
-// (the 64 lanes of a wave read 64 consecutive rows of each column).
+// to rows_pad and k up to ldv are zero.  A workgroup transposes a 64-row x
+// 64-k tile through LDS: the 64 lanes of a wave read 64 consecutive rows of a
+// column, then eight lanes write one row's 64 k (128 bytes) of each part.
+constexpr int SPLIT_V_T = 64;
 __global__ __launch_bounds__(256)
 void split_v_kernel(int rows, int kc, const float *__restrict__ V, int64_t lda, int rows_pad, int ldv,
                     __bf16 *__restrict__ hi, __bf16 *__restrict__ lo, int mask, const int *skip)
 {
     if (skip && *skip) return;
-    const int r = (int)blockIdx.x * 256 + (int)threadIdx.x;
-    const int k0 = 8 * (int)blockIdx.y;
-    if (r >= rows_pad) return;
-    bf16x8 oh, ol;
+    __shared__ float tile[SPLIT_V_T][SPLIT_V_T + 1];   // [k][row]
+    const int r0 = (int)blockIdx.x * SPLIT_V_T, k0 = (int)blockIdx.y * SPLIT_V_T;
+    const int t = (int)threadIdx.x;
+    {
+        const int r = r0 + t % 64, kq = t / 64;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const int k = k0 + e;
-        float x = 0.0f;
-        if (r < rows && k < kc) {
-            const float a = V[(int64_t)k * lda + r];
-            x = mask ? vmask(a, r, k) : a;
+        for (int e = 0; e < 16; ++e) {
+            const int kl = 16 * kq + e, k = k0 + kl;
+            float x = 0.0f;
+            if (r < rows && k < kc) {
+                const float a = V[(int64_t)k * lda + r];
+                x = mask ? vmask(a, r, k) : a;
+            }
+            tile[kl][t % 64] = x;
         }
-        const __bf16 t = (__bf16)x;
-        oh[e] = t;
-        ol[e] = (__bf16)(x - (float)t);
     }
-    *reinterpret_cast<bf16x8 *>(hi + (int64_t)r * ldv + k0) = oh;
-    *reinterpret_cast<bf16x8 *>(lo + (int64_t)r * ldv + k0) = ol;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int f = t + 256 * q, rl = f / 8, c = f % 8;
+        const int r = r0 + rl, k = k0 + 8 * c;
+        if (r >= rows_pad || k >= ldv) continue;
+        bf16x8 oh, ol;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const float x = tile[8 * c + e][rl];
+            const __bf16 h = (__bf16)x;
+            oh[e] = h;
+            ol[e] = (__bf16)(x - (float)h);
+        }
+        *reinterpret_cast<bf16x8 *>(hi + (int64_t)r * ldv + k) = oh;
+        *reinterpret_cast<bf16x8 *>(lo + (int64_t)r * ldv + k) = ol;
+    }
 }
 
 // W' (kc x cols, column-major, leading dimension ldw_in) to high / low bf16
@@ -1139,15 +1157,27 @@ void split_vt_kernel(int rows, int kc, const float *__restrict__ V, int64_t lda,
     const int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (f >= (int64_t)cols_pad * groups) return;
     const int c = (int)(f / groups), r0 = 8 * (int)(f % groups);
+    float xs[8];
+    const float *p = V + (int64_t)c * lda + r0;
+    if (c < kc && r0 + 8 <= rows && ((uintptr_t)p & 15) == 0) {
+        // whole chunk in range: two 16-byte loads
+        const floatx4 a0 = *reinterpret_cast<const floatx4 *>(p);
+        const floatx4 a1 = *reinterpret_cast<const floatx4 *>(p + 4);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            xs[e] = a0[e];
+            xs[4 + e] = a1[e];
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) xs[e] = (r0 + e < rows && c < kc) ? p[e] : 0.0f;
+    }
     bf16x8 oh, ol;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
         const int r = r0 + e;
-        float x = 0.0f;
-        if (r < rows && c < kc) {
-            const float a = V[(int64_t)c * lda + r];
-            x = mask ? vmask(a, r, c) : a;
-        }
+        float x = xs[e];
+        if (mask && r < rows && c < kc) x = vmask(x, r, c);
         const __bf16 t = (__bf16)x;
         oh[e] = t;
         ol[e] = (__bf16)(x - (float)t);
@@ -1481,8 +1511,8 @@ ctqr_status bf16x3_split(int M, int N, int K, const float *V, int64_t lda, const
     if (M <= 0 || N <= 0 || K <= 0) return CTQR_OK;
     SplitParts p;
     if (!split_parts(M, N, K, split, split_elems, p)) return CTQR_ENOMEM;
-    LAUNCH_TRY(split_v_kernel, dim3((unsigned)ceil_div(p.rows_pad, 256), (unsigned)(p.kp / 8)), dim3(256), 0, st, M,
-               K, V, lda, p.rows_pad, p.kp, p.vh, p.vl, householder ? 1 : 0, skip);
+    LAUNCH_TRY(split_v_kernel, dim3((unsigned)ceil_div(p.rows_pad, SPLIT_V_T), (unsigned)ceil_div(p.kp, SPLIT_V_T)),
+               dim3(256), 0, st, M, K, V, lda, p.rows_pad, p.kp, p.vh, p.vl, householder ? 1 : 0, skip);
     LAUNCH_TRY(split_w_kernel, dim3((unsigned)ceil_div((int64_t)p.cols_pad * (p.kp / 8), 256)), dim3(256), 0, st, K,
                N, W, ldw, p.cols_pad, p.kp, p.wh, p.wl, skip);
     return CTQR_OK;
@@ -1536,8 +1566,8 @@ ctqr_status bf16x3_split_rows(int M, int K, const float *V, int64_t lda, bool ho
 {
     if (M <= 0 || K <= 0) return CTQR_OK;
     if (ldp < K || ldp % 8 != 0 || rows_pad < M || rows_pad % TILE != 0) return CTQR_EINVAL;
-    LAUNCH_TRY(split_v_kernel, dim3((unsigned)ceil_div(rows_pad, 256), (unsigned)(ldp / 8)), dim3(256), 0, st, M, K,
-               V, lda, rows_pad, ldp, hi, lo, householder ? 1 : 0, skip);
+    LAUNCH_TRY(split_v_kernel, dim3((unsigned)ceil_div(rows_pad, SPLIT_V_T), (unsigned)ceil_div(ldp, SPLIT_V_T)),
+               dim3(256), 0, st, M, K, V, lda, rows_pad, ldp, hi, lo, householder ? 1 : 0, skip);
     return CTQR_OK;
 }
 
