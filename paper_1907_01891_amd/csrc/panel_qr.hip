@@ -947,8 +947,8 @@ void tbuild_kernel(int nb, const TG *__restrict__ Gm, int64_t ldg, const double 
 // recurrence is the column-by-column form of that inverse), so
 // U_pp T_pq = -sum_{k=p+1}^{q} G_pk T_kq, i.e.
 // T_pq = -T_pp sum_{k=p+1}^{q} G_pk T_kq, for p = q-1 down to 0: each
-// block column is a chain of q products of its own, and the block columns
-// run in parallel.
+// block column is a chain of q products of its own (FP64 MFMA, a 16 x 16
+// output block per wave), and the block columns run in parallel.
 template <typename TG>
 __global__ __launch_bounds__(256)
 void tbuild_diag_kernel(int nb, const TG *__restrict__ Gm, int64_t ldg, const double *__restrict__ tau,
@@ -980,35 +980,64 @@ void tbuild_col_kernel(int nb, const TG *__restrict__ Gm, int64_t ldg, const dou
     double (*Tp)[33] = reinterpret_cast<double (*)[33]>(tbsm + 32 * TB_MAXQ * 33 + 32 * TB_LD);   // T_pp
     double (*Sx)[33] = Tp + 32;                                                       // the sum
     const int q = blockIdx.x, tid = threadIdx.x;
-    const int i = tid % 32, j0 = tid / 32;
+    // MFMA lanes: lane l feeds row l % 16 / column l % 16 and k = l / 16 of a
+    // 4-deep step; its output register r is block entry (4 r + l / 16, l % 16)
+    const int wv = tid / 64, l = tid % 64, li = l % 16, lk = l / 16;
+    const int bi = wv % 2, bj = wv / 2;
     for (int e = tid; e < 1024; e += 256) {
         const int a = e % 32, b = e / 32, ga = 32 * q + a, gb = 32 * q + b;
         Tc[32 * q + a][b] = (ga < nb && gb < nb) ? Tw[(int64_t)gb * nb + ga] : 0.0;
     }
+    // step p's operands (row panel p of G, T_pp) are loaded into registers
+    // during step p + 1 and stored to LDS at the start of step p
+    constexpr int GREG = 32 * 32 * (TB_MAXQ - 1) / 256;
+    TG gr[GREG];
+    double tr[4];
+    auto fetch = [&](int p) {
+        const int c0 = 32 * (p + 1), cw = 32 * (q - p);
+#pragma unroll
+        for (int u = 0; u < GREG; ++u) {
+            const int e = tid + 256 * u, a = e % 32, gc = c0 + e / 32;
+            if (e < 32 * cw) gr[u] = gc < nb ? Gm[(int64_t)gc * ldg + 32 * p + a] : TG(0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = tid + 256 * u, a = e % 32, b = e / 32;
+            tr[u] = Tw[(int64_t)(32 * p + b) * nb + 32 * p + a];
+        }
+    };
+    if (q > 0) fetch(q - 1);
     for (int p = q - 1; p >= 0; --p) {
         const int c0 = 32 * (p + 1), cw = 32 * (q - p);
-        for (int e = tid; e < 32 * cw; e += 256) {
-            const int a = e % 32, c = e / 32, ga = 32 * p + a, gc = c0 + c;
-            Gp[a][c] = gc < nb ? (double)Gm[(int64_t)gc * ldg + ga] : 0.0;
+#pragma unroll
+        for (int u = 0; u < GREG; ++u) {
+            const int e = tid + 256 * u;
+            if (e < 32 * cw) Gp[e % 32][e / 32] = (double)gr[u];
         }
-        for (int e = tid; e < 1024; e += 256) {
-            const int a = e % 32, b = e / 32;
-            Tp[a][b] = Tw[(int64_t)(32 * p + b) * nb + 32 * p + a];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = tid + 256 * u;
+            Tp[e % 32][e / 32] = tr[u];
         }
         __syncthreads();
-        for (int u = 0; u < 4; ++u) {
-            const int j = j0 + 8 * u;
-            double acc = 0.0;
-            for (int c = 0; c < cw; ++c) acc += Gp[i][c] * Tc[c0 + c][j];
-            Sx[i][j] = acc;
+        if (p > 0) fetch(p - 1);
+        {
+            // Sx = G_p,(p+1..q) T_(p+1..q),q on FP64 MFMA: wave wv the 16 x 16 block (bi, bj)
+            doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+            for (int kk = 0; kk < cw; kk += 4)
+                acc = mfma_f64(Gp[16 * bi + li][kk + lk], Tc[c0 + kk + lk][16 * bj + li], acc);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Sx[16 * bi + 4 * r + lk][16 * bj + li] = acc[r];
         }
         __syncthreads();
-        for (int u = 0; u < 4; ++u) {
-            const int j = j0 + 8 * u;
-            double acc = 0.0;
-#pragma unroll 8
-            for (int c = 0; c < 32; ++c) acc += Tp[i][c] * Sx[c][j];
-            Tc[32 * p + i][j] = -acc;
+        {
+            // T_pq = -T_pp Sx
+            doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kk = 0; kk < 32; kk += 4)
+                acc = mfma_f64(Tp[16 * bi + li][kk + lk], Sx[kk + lk][16 * bj + li], acc);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Tc[32 * p + 16 * bi + 4 * r + lk][16 * bj + li] = -acc[r];
         }
         __syncthreads();
     }
