@@ -1100,7 +1100,8 @@ ctqr_status refine_iters_with(SolveRun<T> &r, int it0, int it1, bool host_sync, 
             PhaseScope ph(CTQR_PHASE_RESIDUAL, st);
             s = spmm_rowmajor(m, S, A->rowptr, A->col, A->val, -1.0, w.xr, 1.0, w.Br, w.r, skip, st);
             if (s) return s;
-            s = spmm_rowmajor(n, S, A->colptr, A->row, A->cval, 1.0, w.r, 0.0, nullptr, w.s, skip, st);
+            s = spmm_rowmajor(n, S, A->colptr, A->row, A->cval, 1.0, w.r, 0.0, nullptr, w.s, skip, st,
+                              pixel_tile_side(n));
             if (s) return s;
             if ((s = slice_absmax(n, S, w.s, w.smax, skip, st))) return s;
         }
@@ -1658,7 +1659,8 @@ ctqr_status cond_impl(int64_t m, int64_t n, const T *QR, int64_t lda, const T *R
     for (int it = 0; it < iters; ++it) {
         if ((s = spmm_rowmajor(m, S, A->rowptr, A->col, A->val, 1.0, w.x, 0.0, nullptr, w.r, nullptr, st)))
             return s;
-        if ((s = spmm_rowmajor(n, S, A->colptr, A->row, A->cval, 1.0, w.r, 0.0, nullptr, w.y, nullptr, st)))
+        if ((s = spmm_rowmajor(n, S, A->colptr, A->row, A->cval, 1.0, w.r, 0.0, nullptr, w.y, nullptr, st,
+                               pixel_tile_side(n))))
             return s;
         if ((s = slice_dot(n, S, w.x, w.y, w.dpart, q, nullptr, st))) return s;
         if ((s = cond_max(S, q, w.est, 0, st))) return s;

@@ -6,10 +6,24 @@
 // CSR for A X, rows of the CSC (= columns of A) for A^T r, with the slice
 // vectors stored row-major (slice index fastest) so that the lanes of a
 // workgroup read one contiguous row of X per nonzero.
+#include <cmath>
+
 #include "common.h"
 #include "kernels.h"
 
 namespace {
+
+// Row visited in place of row i when the rows are the pixels of a tside x
+// tside image (row iy * tside + ix, tside a multiple of 16): the image in
+// 16 x 16 tiles, tile rows in order.  Neighbouring pixels are crossed by the
+// same rays, so the rows gathered for one tile are shared in the L2; the
+// results do not depend on the order.
+__device__ inline int64_t pixel_tile_row(int64_t i, int tside)
+{
+    if (tside <= 0) return i;
+    const int64_t t = i / 256, w = i % 256, tpr = tside / 16;
+    return ((t / tpr) * 16 + w / 16) * tside + (t % tpr) * 16 + w % 16;
+}
 
 // y[i, s] = alpha * sum_k val[k] x[idx[k], s] + beta * y_in[i, s]
 // Wide form (S > 64): SW = min(256, S rounded up to 64) threads per row, one
@@ -18,7 +32,7 @@ __global__ __launch_bounds__(256)
 void spmm_rm_kernel(int64_t rows, int S, int SW, const int64_t *__restrict__ ptr,
                     const int32_t *__restrict__ idx, const double *__restrict__ val, double alpha,
                     const double *__restrict__ x, double beta, const double *__restrict__ y_in,
-                    double *__restrict__ y, const int *skip)
+                    double *__restrict__ y, const int *skip, int tside)
 {
     if (skip && *skip) return;
     const int rpb = 256 / SW;
@@ -27,9 +41,10 @@ void spmm_rm_kernel(int64_t rows, int S, int SW, const int64_t *__restrict__ ptr
     unsigned blk = blockIdx.x;
     const unsigned per = gridDim.x / 8;
     if (blk < per * 8) blk = (blk % 8) * per + blk / 8;
-    const int64_t i = (int64_t)blk * rpb + threadIdx.x / SW;
+    const int64_t i0 = (int64_t)blk * rpb + threadIdx.x / SW;
     const int lane = threadIdx.x % SW;
-    if (i >= rows) return;
+    if (i0 >= rows) return;
+    const int64_t i = pixel_tile_row(i0, tside);
     const int64_t b = ptr[i], e = ptr[i + 1];
     for (int s0 = 0; s0 < S; s0 += SW) {
         const int s = s0 + lane;
@@ -51,7 +66,7 @@ template <int MAXP>
 __global__ __launch_bounds__(256)
 void spmm_rm_staged_kernel(int64_t rows, int S, const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
                            const double *__restrict__ val, double alpha, const double *__restrict__ x, double beta,
-                           const double *__restrict__ y_in, double *__restrict__ y, const int *skip)
+                           const double *__restrict__ y_in, double *__restrict__ y, const int *skip, int tside)
 {
     if (skip && *skip) return;
     __shared__ int32_t si[256];
@@ -59,8 +74,8 @@ void spmm_rm_staged_kernel(int64_t rows, int S, const int64_t *__restrict__ ptr,
     unsigned blk = blockIdx.x;
     const unsigned per = gridDim.x / 8;
     if (blk < per * 8) blk = (blk % 8) * per + blk / 8;
-    const int64_t i = blk;
-    if (i >= rows) return;
+    if ((int64_t)blk >= rows) return;
+    const int64_t i = pixel_tile_row(blk, tside);
     const int tid = threadIdx.x;
     const int P = (S + 255) / 256;
     const int64_t b = ptr[i], e = ptr[i + 1];
@@ -436,11 +451,18 @@ __global__ void refine_select_kernel(int64_t count, double *__restrict__ x, cons
 
 }  // namespace
 
+int pixel_tile_side(int64_t n)
+{
+    const int64_t side = (int64_t)std::llround(std::sqrt((double)n));
+    return side * side == n && side % 16 == 0 ? (int)side : 0;
+}
+
 ctqr_status spmm_rowmajor(int64_t rows, int S, const int64_t *ptr, const int32_t *idx,
                           const double *val, double alpha, const double *x, double beta,
-                          const double *y_in, double *y, const int *skip, hipStream_t st)
+                          const double *y_in, double *y, const int *skip, hipStream_t st, int tside)
 {
     if (rows <= 0 || S <= 0) return CTQR_OK;
+    if (tside > 0 && (tside % 16 != 0 || (int64_t)tside * tside != rows)) return CTQR_EINVAL;
     if (S <= CTQR_WAVE) {
         dim3 grid((unsigned)ceil_div(rows, 4));
 #define CTQR_SPMM_NARROW(SPV)                                                                       \
@@ -459,7 +481,7 @@ ctqr_status spmm_rowmajor(int64_t rows, int S, const int64_t *ptr, const int32_t
     if (S > 192 && S <= 2048) {
 #define CTQR_SPMM_STAGED(P)                                                                                    \
     LAUNCH_TRY(spmm_rm_staged_kernel<P>, dim3((unsigned)rows), dim3(256), 0, st, rows, S, ptr, idx, val, alpha, x, \
-               beta, y_in, y, skip)
+               beta, y_in, y, skip, tside)
         if (S <= 256) CTQR_SPMM_STAGED(1);
         else if (S <= 512) CTQR_SPMM_STAGED(2);
         else if (S <= 1024) CTQR_SPMM_STAGED(4);
@@ -470,7 +492,7 @@ ctqr_status spmm_rowmajor(int64_t rows, int S, const int64_t *ptr, const int32_t
     int SW = (int)std::min<int64_t>(256, ceil_div(S, 64) * 64);
     int rpb = 256 / SW;
     LAUNCH_TRY(spmm_rm_kernel, dim3((unsigned)ceil_div(rows, rpb)), dim3(256), 0, st, rows, S, SW, ptr,
-               idx, val, alpha, x, beta, y_in, y, skip);
+               idx, val, alpha, x, beta, y_in, y, skip, tside);
     return CTQR_OK;
 }
 
