@@ -569,7 +569,7 @@ void gemm_tn_kernel(int M, int N, int K,
                     const T *__restrict__ A, int64_t lda, int amask,
                     const T *__restrict__ B, int64_t ldb, int bmask,
                     T alpha, T beta, T *__restrict__ Out, int64_t ldo,
-                    T *__restrict__ part, int kchunk, const int *skip)
+                    T *__restrict__ part, int kchunk, const int *skip, int tri)
 {
     using Mt = Mf<T>;
     using W = WaveTile<T, TW>;
@@ -585,8 +585,12 @@ void gemm_tn_kernel(int M, int N, int K,
     int tm, tn;
     tile_of_block((M + TILE - 1) / TILE, (N + TW - 1) / TW, tm, tn);
     const int m0 = tm * TILE, n0 = tn * TW;
-    const int kbeg = blockIdx.z * kchunk;
-    const int kend = min(K, kbeg + kchunk);
+    // tri: A(k, m) is zero for k < m (1) or for k > m (2), so the tile's rows
+    // need only k >= m0, or k < m0 + TILE (whole BK steps of exact zeros
+    // skipped: the same sums)
+    const int kbeg = tri == 1 ? max((int)blockIdx.z * kchunk, m0) : (int)blockIdx.z * kchunk;
+    const int kend = tri == 2 ? min(min(K, (int)blockIdx.z * kchunk + kchunk), m0 + TILE)
+                              : min(K, (int)blockIdx.z * kchunk + kchunk);
     const int wave = threadIdx.x / CTQR_WAVE;
     const int wn = W::wn(wave), wm = W::wm(wave);
 
@@ -1353,10 +1357,11 @@ ctqr_status splitk_reduce(int M, int N, int splits, const T *part, T alpha, T be
 template <typename T>
 ctqr_status gemm_tn(int M, int N, int K, const T *A, int64_t lda, int amask, const T *B,
                     int64_t ldb, int bmask, T alpha, T beta, T *Out, int64_t ldo, T *part,
-                    size_t part_elems, const int *skip, hipStream_t st, int force_splits, int bf16)
+                    size_t part_elems, const int *skip, hipStream_t st, int force_splits, int bf16, int tri)
 {
     if (M <= 0 || N <= 0) return CTQR_OK;
     if (bf16 == 2) return CTQR_EINVAL;   // split operands: gemm_tn_bf16x3
+    if (tri < 0 || tri > 2 || (tri != 0 && M != K)) return CTQR_EINVAL;
     const bool narrow = N <= t_narrow_max;
     int splits = force_splits > 0 ? force_splits : gemm_tn_splits(M, N, K);
     if (splits > 1 && (part == nullptr || part_elems < (size_t)splits * M * N)) {
@@ -1371,17 +1376,17 @@ ctqr_status gemm_tn(int M, int N, int K, const T *A, int64_t lda, int amask, con
     if constexpr (sizeof(T) == 4) {
         if (bf16 == 1 && !narrow) {
             LAUNCH_TRY((gemm_tn_kernel<T, TILE, 1>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B, ldb,
-                       bmask, alpha, beta, Out, ldo, part, kchunk, skip);
+                       bmask, alpha, beta, Out, ldo, part, kchunk, skip, tri);
             done = true;
         }
     }
     if (done) {
     } else if (narrow) {
         LAUNCH_TRY((gemm_tn_kernel<T, NARROW, 0>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B, ldb,
-                   bmask, alpha, beta, Out, ldo, part, kchunk, skip);
+                   bmask, alpha, beta, Out, ldo, part, kchunk, skip, tri);
     } else {
         LAUNCH_TRY((gemm_tn_kernel<T, TILE, 0>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B, ldb,
-                   bmask, alpha, beta, Out, ldo, part, kchunk, skip);
+                   bmask, alpha, beta, Out, ldo, part, kchunk, skip, tri);
     }
     if (splits > 1) return splitk_reduce<T>(M, N, splits, part, alpha, beta, Out, ldo, skip, st);
     return CTQR_OK;
@@ -1403,10 +1408,10 @@ ctqr_status gemm_tn_tprod(int M, int N, int K, const T *A, int64_t lda, int amas
     dim3 grid((unsigned)(ceil_div(M, TILE) * ceil_div(N, narrow ? NARROW : TILE)), 1, (unsigned)splits);
     if (narrow)
         LAUNCH_TRY((gemm_tn_kernel<T, NARROW, 0>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B, ldb, 0,
-                   T(1), T(0), Out, ldo, part, kchunk, (const int *)nullptr);
+                   T(1), T(0), Out, ldo, part, kchunk, (const int *)nullptr, 0);
     else
         LAUNCH_TRY((gemm_tn_kernel<T, TILE, 0>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B, ldb, 0,
-                   T(1), T(0), Out, ldo, part, kchunk, (const int *)nullptr);
+                   T(1), T(0), Out, ldo, part, kchunk, (const int *)nullptr, 0);
     const bool sp = splits > 1;
     LAUNCH_TRY(tprod_reduce_kernel<T>, dim3((unsigned)ceil_div(N, 2)), dim3(1024), 0, st, M, N, splits,
                sp ? (const T *)part : (const T *)Out, sp ? (int64_t)M : ldo, (int64_t)M * N, Tt, ldt, W2, ldw);
@@ -1625,10 +1630,10 @@ ctqr_status gemm_nn_bf16x3(int M, int N, int K, float alpha, float *C, int64_t l
 
 template ctqr_status gemm_tn<float>(int, int, int, const float *, int64_t, int, const float *,
                                     int64_t, int, float, float, float *, int64_t, float *, size_t,
-                                    const int *, hipStream_t, int, int);
+                                    const int *, hipStream_t, int, int, int);
 template ctqr_status gemm_tn<double>(int, int, int, const double *, int64_t, int, const double *,
                                      int64_t, int, double, double, double *, int64_t, double *,
-                                     size_t, const int *, hipStream_t, int, int);
+                                     size_t, const int *, hipStream_t, int, int, int);
 template ctqr_status gemm_tn_tprod<float>(int, int, int, const float *, int64_t, int, const float *, int64_t,
                                           const float *, int64_t, float *, int64_t, float *, int64_t, float *,
                                           size_t, hipStream_t);

@@ -15,11 +15,14 @@ size_t gemm_tn_partial_elems(int M, int N, int K);
 // 128-wide tiles): 1 = operands rounded to bf16 while staged, BF16 MFMA with
 // FP32 accumulation (gemm_nn: the trailing update, kind 1, only); 2 (split
 // parts) is refused with CTQR_EINVAL: gemm_tn_bf16x3 / gemm_nn_bf16x3 below.
+// tri (square A, M = K): A(k, m) is zero for k < m (1: A is the transpose of
+// an upper triangular block) or for k > m (2: upper triangular), and the
+// steps of exact zeros are skipped.
 template <typename T>
 ctqr_status gemm_tn(int M, int N, int K, const T *A, int64_t lda, int amask, const T *B,
                     int64_t ldb, int bmask, T alpha, T beta, T *Out, int64_t ldo, T *part,
                     size_t part_elems, const int *skip, hipStream_t st, int force_splits = 0,
-                    int bf16 = 0);
+                    int bf16 = 0, int tri = 0);
 // W2 = Tt^T (A^T B) for a product of at most 32 rows (the update by a 32-wide
 // inner panel, Tt its 32 x 32 factor): A^T B as gemm_tn (written to Out when
 // it is not split over K), then one launch that finishes the split-K sum and

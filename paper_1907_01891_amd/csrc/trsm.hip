@@ -349,7 +349,7 @@ ctqr_status trsm_upper(int n, int S, const T *R, int64_t ldr, const T *Rinv, T *
         }
         // X_i = inv(R_ii) C_i = (inv(R_ii)^T)^T C_i  (split-K TN product)
         s = gemm_tn<T>(bw, S, bw, RinvT + (int64_t)r0 * BIG, BIG, 0, C + r0, ldc, 0, T(1), T(0), X + r0, ldx,
-                       part, part_elems, skip, st);
+                       part, part_elems, skip, st, 0, 0, 1);
         if (s) return s;
         if (!left && r0 > 0) {
             // C_{0:r0} -= R_{0:r0, i} X_i
@@ -393,7 +393,7 @@ ctqr_status trsm_upper_trans(int n, int S, const T *R, int64_t ldr, const T *Rin
         }
         // Y_i = inv(R_ii)^T C_i
         s = gemm_tn<T>(bw, S, bw, Rinv + (int64_t)r0 * BIG, BIG, 0, C + r0, ldc, 0, T(1), T(0), Y + r0, ldy,
-                       part, part_elems, skip, st);
+                       part, part_elems, skip, st, 0, 0, 2);
         if (s) return s;
         const int rest = n - r0 - bw;
         if (!left && rest > 0) {
@@ -432,7 +432,7 @@ ctqr_status trsm_upper_cols(int n, int S, const T *R, int64_t ldr, const T *Rinv
     for (int r0 = (int)(ceil_div(std::min(c_hi, n), BIG) - 1) * BIG; r0 >= c_lo; r0 -= BIG) {
         const int bw = min(BIG, n - r0);
         ctqr_status s = gemm_tn<T>(bw, S, bw, RinvT + (int64_t)r0 * BIG, BIG, 0, C + r0, ldc, 0, T(1), T(0),
-                                   X + r0, ldx, part, part_elems, skip, st);
+                                   X + r0, ldx, part, part_elems, skip, st, 0, 0, 1);
         if (s) return s;
         if (r0 > 0) {
             s = gemm_nn<T>(r0, S, bw, R + (int64_t)r0 * ldr, ldr, 0, X + r0, ldx, T(-1), C, ldc, skip, st);
@@ -456,7 +456,7 @@ ctqr_status trsm_upper_trans_cols(int n, int S, const T *R, int64_t ldr, const T
             if (s) return s;
         }
         s = gemm_tn<T>(bw, S, bw, Rinv + (int64_t)r0 * BIG, BIG, 0, C + r0, ldc, 0, T(1), T(0), Y + r0, ldy,
-                       part, part_elems, skip, st);
+                       part, part_elems, skip, st, 0, 0, 2);
         if (s) return s;
     }
     return CTQR_OK;
