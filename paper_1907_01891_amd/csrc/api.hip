@@ -207,6 +207,8 @@ struct SolveWS {
     T *s32, *y32, *d32;
     __bf16 *rparts;          // split-BF16 parts of R for the refinement's wide substitutions (or null)
     __bf16 *xparts;          // and of their right-hand sides (or null)
+    __bf16 *qsplit;          // split-BF16 parts of a block of V and of W' for Q^T B (with xparts)
+    size_t qsplit_elems;
     unsigned long long *dmax, *xmax, *smax;
     double *s0;
     int *done;
@@ -279,6 +281,8 @@ SolveWS<T> carve_solve(void *work, int64_t m, int64_t n, int nb, int S, int refi
         w.xbest = c.take<double>(n * S);
         const bool parts = trsm_split != TRSM_PARTS_NONE && refine_split_trsm<T>(n, S, refine);
         w.xparts = parts ? c.take<__bf16>((int64_t)trsm_xparts_elems(S)) : nullptr;
+        w.qsplit_elems = parts ? bf16x3_split_elems(m, S, nb) : 0;
+        w.qsplit = parts ? c.take<__bf16>((int64_t)w.qsplit_elems) : nullptr;
         w.rparts = parts && trsm_split == TRSM_PARTS_ALL ? c.take<__bf16>((int64_t)trsm_rparts_elems(n)) : nullptr;
     }
     if (refine >= 2) {
@@ -973,6 +977,16 @@ ctqr_status apply_qt_range(SolveRun<T> &r, const T *QRv, int kb, int ke, hipStre
         s = gemm_tn<T>(nbk, S, nbk, r.Tf + (int64_t)k0 * nb, nb, 0, w.W, nb, 0, T(1), T(0), w.W2, nb, w.split,
                        r.sp_elems, nullptr, st);
         if (s) return s;
+        if constexpr (sizeof(T) == 4) {
+            if (w.qsplit) {
+                // refined solve of many slices: B_k -= V W' on split-BF16 MFMA
+                // (the refinement's corrections need the factor's accuracy only)
+                s = bf16x3_split(m - k0, S, nbk, V, r.lda, w.W2, nb, w.qsplit, w.qsplit_elems, st);
+                if (!s) s = gemm_nn_bf16x3(m - k0, S, nbk, -1.0f, Bk, w.ldbw, w.qsplit, w.qsplit_elems, st, nullptr, 2);
+                if (s) return s;
+                continue;
+            }
+        }
         s = gemm_nn<T>(m - k0, S, nbk, V, r.lda, 1, w.W2, nb, T(-1), Bk, w.ldbw, nullptr, st);
         if (s) return s;
     }
