@@ -338,6 +338,10 @@ ctqr_status ctqr_solve_workspace(int64_t m, int64_t n, ctqr_dtype dtype, int32_t
  *          the preconditioner's quality), or the last iterate if the residual
  *          was still falling at the last iteration (info.x_iters says which).
  *          NULL = no refinement.
+ *          With FP32 storage, CSNE and at least 128 slices, the V W' products
+ *          of Q^T B and the off-diagonal block products of every substitution
+ *          run on split-BF16 MFMA (three BF16 products, FP32 accumulation):
+ *          the refinement needs the factor's own accuracy only.
  *          With refinement the call waits on the stream after each
  *          iteration (it reads the convergence flag back) and returns once
  *          the refinement has ended; without it the call only enqueues.
