@@ -738,15 +738,19 @@ void gemm_nn_kernel(int M, int N, int K,
                     const T *__restrict__ A, int64_t lda, int amask,
                     const T *__restrict__ B, int64_t ldb,
                     T alpha, T *__restrict__ C, int64_t ldc, int accum,
-                    T *__restrict__ part, int kchunk, const int *skip)
+                    T *__restrict__ part, int kchunk, const int *skip, int64_t bsa, int64_t bsb, int64_t bsc)
 {
     // accum != 0: C += alpha A B;  accum == 0: C = alpha A B (C is not read).
+    // blockIdx.y: product of a batch whose operands lie bsa, bsb, bsc apart.
     // SPLIT: split blockIdx.z covers k in [z kchunk, (z+1) kchunk) and writes
     // its raw product to part (reduced by splitk_reduce_kernel).  A
     // compile-time switch: the unsplit kernels carry none of its registers.
     using Mt = Mf<T>;
     using W = WaveTile<T, TW>;
     if (skip && *skip) return;
+    A += (int64_t)blockIdx.y * bsa;
+    B += (int64_t)blockIdx.y * bsb;
+    C += (int64_t)blockIdx.y * bsc;
     // BF > 0: FP32 operands staged as BF bf16 parts (BF16 MFMA, FP32
     // accumulation); the A tile is then stored [row][k]
     static_assert(BF == 0 || (sizeof(T) == 4 && TW == TILE && !SPLIT && BF == 1),
@@ -1435,20 +1439,39 @@ ctqr_status gemm_nn(int M, int N, int K, const T *A, int64_t lda, int amask, con
     if constexpr (sizeof(T) == 4) {
         if (kind == 1 && bf16 == 1) {
             LAUNCH_TRY((gemm_nn_kernel<T, 1, TILE, false, 1>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask,
-                       B, ldb, alpha, C, ldc, accum, (T *)nullptr, kchunk, skip);
+                       B, ldb, alpha, C, ldc, accum, (T *)nullptr, kchunk, skip, (int64_t)0, (int64_t)0,
+                       (int64_t)0);
             return CTQR_OK;
         }
 
     }
     if (kind == 1)
         LAUNCH_TRY((gemm_nn_kernel<T, 1, TILE, false, 0>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B,
-                   ldb, alpha, C, ldc, accum, (T *)nullptr, kchunk, skip);
+                   ldb, alpha, C, ldc, accum, (T *)nullptr, kchunk, skip, (int64_t)0, (int64_t)0, (int64_t)0);
     else if (narrow)
         LAUNCH_TRY((gemm_nn_kernel<T, 0, NARROW, false, 0>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask,
-                   B, ldb, alpha, C, ldc, accum, (T *)nullptr, kchunk, skip);
+                   B, ldb, alpha, C, ldc, accum, (T *)nullptr, kchunk, skip, (int64_t)0, (int64_t)0, (int64_t)0);
     else
         LAUNCH_TRY((gemm_nn_kernel<T, 0, TILE, false, 0>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask,
-                   B, ldb, alpha, C, ldc, accum, (T *)nullptr, kchunk, skip);
+                   B, ldb, alpha, C, ldc, accum, (T *)nullptr, kchunk, skip, (int64_t)0, (int64_t)0, (int64_t)0);
+    return CTQR_OK;
+}
+
+template <typename T>
+ctqr_status gemm_nn_batched(int M, int N, int K, const T *A, int64_t lda, int64_t bsa, const T *B, int64_t ldb,
+                            int64_t bsb, T alpha, T *C, int64_t ldc, int64_t bsc, int batch, int accum,
+                            hipStream_t st)
+{
+    if (M <= 0 || N <= 0 || K <= 0 || batch <= 0) return CTQR_OK;
+    if (batch > 65535) return CTQR_EINVAL;
+    const bool narrow = N <= t_narrow_max;
+    dim3 grid((unsigned)(ceil_div(M, TILE) * ceil_div(N, narrow ? NARROW : TILE)), (unsigned)batch);
+    if (narrow)
+        LAUNCH_TRY((gemm_nn_kernel<T, 0, NARROW, false, 0>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, 0, B, ldb,
+                   alpha, C, ldc, accum, (T *)nullptr, K, (const int *)nullptr, bsa, bsb, bsc);
+    else
+        LAUNCH_TRY((gemm_nn_kernel<T, 0, TILE, false, 0>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, 0, B, ldb,
+                   alpha, C, ldc, accum, (T *)nullptr, K, (const int *)nullptr, bsa, bsb, bsc);
     return CTQR_OK;
 }
 
@@ -1466,10 +1489,10 @@ ctqr_status gemm_nn_split(int M, int N, int K, const T *A, int64_t lda, const T 
     dim3 grid((unsigned)(ceil_div(M, TILE) * ceil_div(N, narrow ? NARROW : TILE)), 1, (unsigned)splits);
     if (narrow)
         LAUNCH_TRY((gemm_nn_kernel<T, 0, NARROW, true, 0>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, 0, B,
-                   ldb, alpha, C, ldc, 0, part, kchunk, skip);
+                   ldb, alpha, C, ldc, 0, part, kchunk, skip, (int64_t)0, (int64_t)0, (int64_t)0);
     else
         LAUNCH_TRY((gemm_nn_kernel<T, 0, TILE, true, 0>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, 0, B,
-                   ldb, alpha, C, ldc, 0, part, kchunk, skip);
+                   ldb, alpha, C, ldc, 0, part, kchunk, skip, (int64_t)0, (int64_t)0, (int64_t)0);
     return splitk_reduce<T>(M, N, splits, part, alpha, T(1), C, ldc, skip, st);
 }
 
@@ -1644,6 +1667,11 @@ template ctqr_status gemm_nn<float>(int, int, int, const float *, int64_t, int, 
                                     int64_t, float, float *, int64_t, const int *, hipStream_t, int, int, int);
 template ctqr_status gemm_nn<double>(int, int, int, const double *, int64_t, int, const double *,
                                      int64_t, double, double *, int64_t, const int *, hipStream_t, int, int, int);
+template ctqr_status gemm_nn_batched<float>(int, int, int, const float *, int64_t, int64_t, const float *, int64_t,
+                                            int64_t, float, float *, int64_t, int64_t, int, int, hipStream_t);
+template ctqr_status gemm_nn_batched<double>(int, int, int, const double *, int64_t, int64_t, const double *,
+                                             int64_t, int64_t, double, double *, int64_t, int64_t, int, int,
+                                             hipStream_t);
 template ctqr_status gemm_nn_split<float>(int, int, int, const float *, int64_t, const float *, int64_t, float,
                                           float *, int64_t, float *, size_t, const int *, hipStream_t);
 template ctqr_status gemm_nn_split<double>(int, int, int, const double *, int64_t, const double *, int64_t,

@@ -35,6 +35,12 @@ template <typename T>
 ctqr_status gemm_nn(int M, int N, int K, const T *A, int64_t lda, int amask, const T *B,
                     int64_t ldb, T alpha, T *C, int64_t ldc, const int *skip, hipStream_t st,
                     int kind = 0, int accum = 1, int bf16 = 0);
+// `batch` products C_b (+)= alpha A_b B_b (A not a Householder block), operand
+// b at A + b bsa, B + b bsb, C + b bsc, in one launch (accum as gemm_nn).
+template <typename T>
+ctqr_status gemm_nn_batched(int M, int N, int K, const T *A, int64_t lda, int64_t bsa, const T *B, int64_t ldb,
+                            int64_t bsb, T alpha, T *C, int64_t ldc, int64_t bsc, int batch, int accum,
+                            hipStream_t st);
 // C += alpha A B (A not a Householder block), split over K into part when the
 // output has too few tiles to fill the chip.
 template <typename T>

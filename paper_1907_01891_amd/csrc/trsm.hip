@@ -222,10 +222,34 @@ ctqr_status trinv_blocks_range(int n, int c0, int c1, const T *R, int64_t ldr, T
                Rinv + z0 * BIG * BIG, span);
     LAUNCH_TRY(trinv_kernel<T>, dim3((unsigned)ceil_div(c1 - c0, BT), NQ), dim3(256), 0, st, n, R, ldr, Rinv,
                c0 / BT);
-    // doubling inside every BIG block: [A B; 0 D] -> X12 = -inv(A) (B inv(D))
+    // doubling inside every BIG block: [A B; 0 D] -> X12 = -inv(A) (B inv(D)).
+    // The whole blocks of the range take each step as one batched launch over
+    // the blocks, the product B inv(D) held in the block-transpose area at
+    // X12's place (written by the transposes only at the end); a last,
+    // partial block takes its steps one by one through tmp.
+    const int64_t zf = std::min<int64_t>(z1, n / BIG);   // whole blocks: [z0, zf)
+    if (zf > z0) {
+        const int nbat = (int)(zf - z0);
+        for (int s = BT; s < BIG; s *= 2) {
+            for (int q = 0; q < BIG / (2 * s); ++q) {
+                const int64_t g0 = z0 * BIG + 2LL * s * q, off = 2LL * s * q;
+                const T *Bblk = R + (g0 + s) * ldr + g0;
+                const T *Dinv = Rinv + (g0 + s) * BIG + off + s;
+                const T *Ainv = Rinv + g0 * BIG + off;
+                T *X12 = Rinv + (g0 + s) * BIG + off;
+                T *Y = X12 + total;
+                const int64_t bsr = (int64_t)BIG * ldr + BIG, bsi = (int64_t)BIG * BIG;
+                ctqr_status e = gemm_nn_batched<T>(s, s, s, Bblk, ldr, bsr, Dinv, BIG, bsi, T(1), Y, BIG, bsi, nbat,
+                                                   0, st);
+                if (e) return e;
+                e = gemm_nn_batched<T>(s, s, s, Ainv, BIG, bsi, Y, BIG, bsi, T(-1), X12, BIG, bsi, nbat, 0, st);
+                if (e) return e;
+            }
+        }
+    }
     const int64_t ldy = BIG / 2;
     for (int s = BT; s < BIG; s *= 2) {
-        for (int g0 = c0; g0 < c1; g0 += 2 * s) {
+        for (int g0 = (int)std::max<int64_t>(c0, zf * BIG); g0 < c1; g0 += 2 * s) {
             const int d = std::min(s, n - (g0 + s));
             if (d <= 0) continue;
             const int off = g0 % BIG;
