@@ -512,16 +512,15 @@ ctqr_status factor_blocks(int m, int n, T *A, int64_t lda, int nb, int kb, int k
             const int wdt = std::min(PANEL_W, k0 + nbk - c0);
             {
                 PhaseScope ph(CTQR_PHASE_PANEL, st);
+                // the panel's T is needed by the update of the rest of its block column
                 s = panel_qr<T>(A, lda, m, c0, wdt, tau + c0, w.part, w.part2, w.gram_part, w.gram, w.Tin,
-                                bars + (int64_t)(c0 / PANEL_W) * GB_WORDS, info, ncu, st);
+                                k0 + nbk - (c0 + wdt) > 0, bars + (int64_t)(c0 / PANEL_W) * GB_WORDS, info, ncu,
+                                st);
                 if (s) return s;
             }
             const int ncr = k0 + nbk - (c0 + wdt);
             if (ncr <= 0) continue;
             PhaseScope ph(CTQR_PHASE_INNER, st);
-            if ((s = tbuild<double, T>(wdt, w.gram, PANEL_W, tau + c0, w.Tin, PANEL_W, w.Tw, st,
-                                       w.gram + PANEL_W * PANEL_W)))
-                return s;
             const T *Vp = A + (int64_t)c0 * lda + c0;
             T *Cp = A + (int64_t)(c0 + wdt) * lda + c0;
             // W2 = T^T (V^T C): the split-K sum and the product with T^T in one launch

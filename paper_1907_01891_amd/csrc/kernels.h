@@ -94,12 +94,12 @@ int panel_max_rows_per_wg_f32();   // FP32 slab (FP32 storage only)
 ctqr_status panel_setup(int max_rows);
 template <typename TS>
 ctqr_status panel_qr(TS *A, int64_t lda, int m, int r0, int w, double *tau, double *part,
-                     double *part2, double *gram_part, double *gram, TS *Tin, unsigned *bar, ctqr_info *info,
-                     int ncu, hipStream_t st);
-// gram: PANEL_GRAM_ELEMS doubles, the panel's V^T V (32 x 32) and, after it, a
-// flag set when the panel kernel has already stored the panel's T to Tin (the
-// Gram reduction then skips, and so does a T build given the flag as skip).
-constexpr int PANEL_GRAM_ELEMS = 32 * 32 + 32;
+                     double *part2, double *gram_part, double *gram, TS *Tin, bool want_t, unsigned *bar,
+                     ctqr_info *info, int ncu, hipStream_t st);
+// The panel's T (PW x PW, leading dimension PW) is stored to Tin by the panel
+// kernel itself: by the reconstruction route, or, when want_t is set, after
+// the column route from the summed Gram V^T V (gram: PANEL_GRAM_ELEMS doubles).
+constexpr int PANEL_GRAM_ELEMS = 32 * 32;
 template <typename TG, typename TT>
 ctqr_status tbuild(int nb, const TG *G, int64_t ldg, const double *tau, TT *T, int64_t ldt, double *Tw,
                    hipStream_t st, const double *skip = nullptr);

@@ -569,12 +569,16 @@ __device__ __attribute__((always_inline)) bool cq_route(const TS *A, int64_t lda
 // slab + c * rows_per_wg): the per-column products and updates give one wave
 // to a column, its 64 lanes on consecutive rows, and each lane keeps the
 // current reflector's values of its rows in registers.
+__device__ inline void tb_diag(int q, int nb, const double (*Gq)[33], const double *__restrict__ tau,
+                               double (*Tq)[33]);
+constexpr size_t PANEL_T_LDS = 2 * 32 * 33 * sizeof(double);   // G and T of the column route's T build
+
 template <typename TS, typename SL>
 __global__ __launch_bounds__(PNT)
 void panel_qr_kernel(TS *__restrict__ A, int64_t lda, int m, int r0, int w, int rows_per_wg,
                      double *__restrict__ tau_out, double *part, double *part2,
                      double *__restrict__ gram_part, int route, TS *__restrict__ Tin,
-                     double *__restrict__ t_done, unsigned *bar, ctqr_info *info)
+                     double *__restrict__ gram_sum, int want_t, unsigned *bar, ctqr_info *info)
 {
     constexpr int NW = PNT / CTQR_WAVE;
     constexpr int RPL = rows_per_lane<SL>();
@@ -790,10 +794,8 @@ void panel_qr_kernel(TS *__restrict__ A, int64_t lda, int m, int r0, int w, int 
     // 16 x 16 block per wave.  Lane l feeds row k0 + l/16 of columns
     // bi + l%16 and bj + l%16; output register r of lane l holds
     // G(bi + 4r + l/16, bj + l%16).
-    // After the reconstruction route T is already stored, and t_done tells
-    // the Gram reduction and the T build of this panel to return at once.
-    if (wg == 0 && tid == 0) *t_done = done ? 1.0 : 0.0;
-    if (done) return;
+    // After the reconstruction route T is already stored.
+    if (done || !want_t) return;
     __syncthreads();
     auto vval = [&](int rr, int c) -> double {
         if (rr >= nrows || c >= w) return 0.0;
@@ -810,29 +812,44 @@ void panel_qr_kernel(TS *__restrict__ A, int64_t lda, int m, int r0, int w, int 
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-            gram_part[(int64_t)wg * PW * PW + (bi + 4 * r + kq) + PW * (bj + li)] = g4[r];
+            store_coherent(&gram_part[(int64_t)wg * PW * PW + (bi + 4 * r + kq) + PW * (bj + li)], g4[r]);
     }
-}
-
-// Sum of the per-workgroup Gram partials in a fixed order: 16 entries per
-// workgroup, 16 threads per entry each summing every 16th partial, then the
-// 16 partial sums in thread order.
-__global__ __launch_bounds__(256)
-void gram_reduce_kernel(int G, const double *__restrict__ gram_part, double *__restrict__ gram,
-                        const double *__restrict__ skip)
-{
-    if (*skip != 0.0) return;
-    __shared__ double red[16][17];
-    const int el = threadIdx.x % 16, grp = threadIdx.x / 16;
-    const int e = blockIdx.x * 16 + el;
-    double s = 0.0;
-    for (int q = grp; q < G; q += 16) s += gram_part[(int64_t)q * PW * PW + e];
-    red[grp][el] = s;
+    // The Gram summed over the workgroups, 16 entries at a time per
+    // workgroup: 16 threads per entry each sum every 16th partial, then the
+    // 16 sums in thread order.
+    grid_barrier(bar, epoch, info);
+    double *gsum = &red4[0][0];   // 16 x 16
+    {
+        const int el = tid % 16, grp = tid / 16;
+        for (int b = wg; b < PW * PW / 16; b += G) {
+            double t = 0.0;
+            for (int q = grp; q < G; q += 16) t += load_coherent(&gram_part[(int64_t)q * PW * PW + 16 * b + el]);
+            gsum[16 * grp + el] = t;
+            __syncthreads();
+            if (tid < 16) {
+                double u = 0.0;
+                for (int q = 0; q < 16; ++q) u += gsum[16 * q + tid];
+                store_coherent(&gram_sum[16 * b + tid], u);
+            }
+            __syncthreads();
+        }
+    }
+    grid_barrier(bar, epoch, info);
+    if (wg != 0) return;
+    // T = (diag(1/tau) + striu(G))^-1 by the recurrence, in workgroup 0 (the
+    // slab's LDS, at least PANEL_T_LDS bytes, is free now)
+    double (*Gs)[33] = reinterpret_cast<double (*)[33]>(slab_raw);
+    double (*Tq)[33] = Gs + 32;
+    for (int e = tid; e < 1024; e += PNT) {
+        const int i = e % 32, j = e / 32;
+        Gs[i][j] = (i < w && j < w) ? load_coherent(&gram_sum[j * PW + i]) : 0.0;
+    }
     __syncthreads();
-    if (threadIdx.x < 16) {
-        double t = 0.0;
-        for (int q = 0; q < 16; ++q) t += red[q][threadIdx.x];
-        gram[blockIdx.x * 16 + threadIdx.x] = t;
+    tb_diag(0, w, Gs, tau_s, Tq);
+    __syncthreads();
+    for (int e = tid; e < 1024; e += PNT) {
+        const int i = e % 32, j = e / 32;
+        if (i < w && j < w) Tin[j * PW + i] = (TS)Tq[i][j];
     }
 }
 
@@ -1067,8 +1084,8 @@ int panel_max_rows_per_wg_f32() { return std::min((int)((152 * 1024) / (PW * siz
 
 template <typename TS>
 ctqr_status panel_qr(TS *A, int64_t lda, int m, int r0, int w, double *tau, double *part,
-                     double *part2, double *gram_part, double *gram, TS *Tin, unsigned *bar, ctqr_info *info,
-                     int ncu, hipStream_t st)
+                     double *part2, double *gram_part, double *gram, TS *Tin, bool want_t, unsigned *bar,
+                     ctqr_info *info, int ncu, hipStream_t st)
 {
     const int mrem = m - r0;
     const int rows = panel_rows_per_wg(mrem, ncu);
@@ -1083,17 +1100,16 @@ ctqr_status panel_qr(TS *A, int64_t lda, int m, int r0, int w, double *tau, doub
     int route = !f32slab && !(ev && !strcmp(ev, "columns")) && G <= 256 && mrem > w &&
                 lds + CQ_LDS <= CQ_LDS_LIMIT;
     if (route) lds += CQ_LDS;
-    double *t_done = gram + PW * PW;
-    void *args[] = {&A,         (void *)&lda, &m,   &r0,     &w,   (void *)&rows, &tau, &part, &part2,
-                    &gram_part, &route,       &Tin, &t_done, &bar, &info};
+    lds = std::max(lds, PANEL_T_LDS);
+    int wt = want_t ? 1 : 0;
+    void *args[] = {&A,         (void *)&lda, &m,   &r0,   &w,  (void *)&rows, &tau, &part, &part2,
+                    &gram_part, &route,       &Tin, &gram, &wt, &bar,          &info};
     if (f32slab)
         HIP_TRY(hipLaunchCooperativeKernel((const void *)panel_qr_kernel<TS, float>, dim3(G), dim3(PNT), args, lds,
                                            st));
     else
         HIP_TRY(hipLaunchCooperativeKernel((const void *)panel_qr_kernel<TS, double>, dim3(G), dim3(PNT), args,
                                            lds, st));
-    LAUNCH_TRY(gram_reduce_kernel, dim3(PW * PW / 16), dim3(256), 0, st, G, (const double *)gram_part, gram,
-               (const double *)t_done);
     return CTQR_OK;
 }
 
@@ -1136,9 +1152,10 @@ ctqr_status tbuild(int nb, const TG *G, int64_t ldg, const double *tau, TT *T, i
 }
 
 template ctqr_status panel_qr<float>(float *, int64_t, int, int, int, double *, double *, double *,
-                                     double *, double *, float *, unsigned *, ctqr_info *, int, hipStream_t);
+                                     double *, double *, float *, bool, unsigned *, ctqr_info *, int, hipStream_t);
 template ctqr_status panel_qr<double>(double *, int64_t, int, int, int, double *, double *, double *,
-                                      double *, double *, double *, unsigned *, ctqr_info *, int, hipStream_t);
+                                      double *, double *, double *, bool, unsigned *, ctqr_info *, int,
+                                      hipStream_t);
 template ctqr_status tbuild<double, float>(int, const double *, int64_t, const double *, float *, int64_t,
                                            double *, hipStream_t,
                                            const double *);
