@@ -415,8 +415,9 @@ ctqr_status block_reduction(int M, int N, int K, const T *V, int64_t lda, const 
                 HIP_TRY(hipEventCreate(&rec.b));
                 HIP_TRY(hipEventRecord(rec.a, st));
             }
+            // B's first bmask columns are V itself: G = V^T V, formed on and above its diagonal only
             s = gemm_tn_bf16x3(M, N, K, w.vtsplit, w.vtsplit_elems, B, ldb, bmask, 1.0f, 0.0f, w.GW, ldg, w.split,
-                               SPLIT_PART_ELEMS, nullptr, st, force_splits);
+                               SPLIT_PART_ELEMS, nullptr, st, force_splits, bmask);
             done = true;
         }
     }
@@ -475,6 +476,9 @@ GroupSplits group_splits(int m, int n, int nb, int kg)
 // column stride ldg).  With W = Vg^T C in Wg (column stride ldg), the rows of
 // W' = T^T W for the group's factor T = [T_0, -T_0 G_01 T_1, ...; 0, T_1, ...]
 // are, block by block, W'_j = T_j^T (W_j - G_{j,<j} W'_{<j}); then C -= Vg W'.
+// G_{j,<j} is read as the transpose of G_{<j,j} (G is symmetric and only its
+// diagonal and upper blocks are formed), unsplit so that every column range
+// sums the same products in the same order.
 template <typename T>
 ctqr_status group_update(int m, int nb, int kg, int nbg, int nc, const T *Vg, int64_t lda, const T *Tf,
                          const T *Gs, T *Wg, int ldg, T *C, const GroupSplits &sp, FactorWS<T> &w, hipStream_t st)
@@ -483,7 +487,8 @@ ctqr_status group_update(int m, int nb, int kg, int nbg, int nc, const T *Vg, in
     for (int j = 0, r0 = 0; r0 < nbg; ++j, r0 += nb) {
         const int wj = std::min(nb, nbg - r0);
         if (r0 > 0) {
-            s = gemm_nn<T>(wj, nc, r0, Gs + r0, ldg, 0, w.W2, ldg, T(-1), Wg + r0, ldg, nullptr, st);
+            s = gemm_tn<T>(wj, nc, r0, Gs + (int64_t)r0 * ldg, ldg, 0, w.W2, ldg, 0, T(-1), T(1), Wg + r0, ldg, w.split,
+                           SPLIT_PART_ELEMS, nullptr, st, 1);
             if (s) return s;
         }
         s = gemm_tn<T>(wj, nc, wj, Tf + (int64_t)(kg + r0) * nb, nb, 0, Wg + r0, ldg, 0, T(1), T(0), w.W2 + r0, ldg,

@@ -1201,7 +1201,8 @@ void split_vt_kernel(int rows, int kc, const float *__restrict__ V, int64_t lda,
 __global__ __launch_bounds__(NTHR, 2)
 void gemm_tn_bf16x3_kernel(int M, int N, int K, const __bf16 *__restrict__ Ah, const __bf16 *__restrict__ Al,
                            int64_t ldk, const float *__restrict__ B, int64_t ldb, int bmask, float alpha, float beta,
-                           float *__restrict__ Out, int64_t ldo, float *__restrict__ part, int kchunk, const int *skip)
+                           float *__restrict__ Out, int64_t ldo, float *__restrict__ part, int kchunk, const int *skip,
+                           int gram_cols)
 {
     using W = WaveTile<float, TILE>;
     constexpr int BK = Mf<float>::BK;
@@ -1215,6 +1216,9 @@ void gemm_tn_bf16x3_kernel(int M, int N, int K, const __bf16 *__restrict__ Ah, c
     int tm, tn;
     tile_of_block((M + TILE - 1) / TILE, (N + TILE - 1) / TILE, tm, tn);
     const int m0 = tm * TILE, n0 = tn * TILE;
+    // the first gram_cols output columns are the symmetric Gram V^T V, read
+    // only on and above its diagonal: tiles wholly below it are not formed
+    if (n0 + TILE <= gram_cols && n0 + TILE <= m0) return;
     const int kbeg = blockIdx.z * kchunk;
     const int kend = min(K, kbeg + kchunk);
     const int wave = threadIdx.x / CTQR_WAVE;
@@ -1564,7 +1568,7 @@ ctqr_status bf16x3_split_vt(int rows, int kc, const float *V, int64_t lda, __bf1
 
 ctqr_status gemm_tn_bf16x3(int M, int N, int K, const __bf16 *vt, size_t vt_elems, const float *B, int64_t ldb,
                            int bmask, float alpha, float beta, float *Out, int64_t ldo, float *part,
-                           size_t part_elems, const int *skip, hipStream_t st, int force_splits)
+                           size_t part_elems, const int *skip, hipStream_t st, int force_splits, int gram_cols)
 {
     if (M <= 0 || N <= 0) return CTQR_OK;
     const int ldk = (int)up_to(K, 32), cols_pad = (int)up_to(M, TILE);
@@ -1584,7 +1588,7 @@ ctqr_status gemm_tn_bf16x3(int M, int N, int K, const __bf16 *vt, size_t vt_elem
     splits = (int)ceil_div(K > 0 ? K : 1, kchunk);
     dim3 grid((unsigned)(ceil_div(M, TILE) * ceil_div(N, TILE)), 1, (unsigned)splits);
     LAUNCH_TRY(gemm_tn_bf16x3_kernel, grid, dim3(NTHR), 0, st, M, N, K, vt, vt + (size_t)ldk * cols_pad,
-               (int64_t)ldk, B, ldb, bmask, alpha, beta, Out, ldo, part, kchunk, skip);
+               (int64_t)ldk, B, ldb, bmask, alpha, beta, Out, ldo, part, kchunk, skip, gram_cols);
     if (splits > 1) return splitk_reduce<float>(M, N, splits, part, alpha, beta, Out, ldo, skip, st);
     return CTQR_OK;
 }

@@ -82,9 +82,12 @@ ctqr_status gemm_nn_bf16x3_parts(int M, int N, int K, float alpha, float *C, int
 size_t bf16x3_vt_elems(int64_t m, int nb);
 ctqr_status bf16x3_split_vt(int rows, int kc, const float *V, int64_t lda, __bf16 *vt, size_t vt_elems,
                             hipStream_t st, bool householder = true, const int *skip = nullptr);
+// gram_cols: the output's first gram_cols columns are the Gram V^T V (B's
+// first columns being V itself); its tiles wholly below the diagonal are not
+// formed (only the diagonal and upper blocks of a Gram are read).
 ctqr_status gemm_tn_bf16x3(int M, int N, int K, const __bf16 *vt, size_t vt_elems, const float *B, int64_t ldb,
                            int bmask, float alpha, float beta, float *Out, int64_t ldo, float *part,
-                           size_t part_elems, const int *skip, hipStream_t st, int force_splits);
+                           size_t part_elems, const int *skip, hipStream_t st, int force_splits, int gram_cols = 0);
 
 // ---- panel_qr.hip ----------------------------------------------------------
 constexpr int PANEL_XCH_STRIDE = 40;   // doubles per workgroup per exchange buffer (two buffers)
