@@ -563,7 +563,10 @@ struct WaveTile {
 // ---------------------------------------------------------------------------
 // TN:  Out = alpha * A^T B + beta * Out   (or split-K partials)
 // ---------------------------------------------------------------------------
-template <typename T, int TW, int BF>
+// TP: the output is written transposed (element (m, n) of Out at m ldo + n,
+// of split z's partial at (z M + m) N + n): a product formed as B^T A on the
+// narrow tile lands where A^T B would.
+template <typename T, int TW, int BF, bool TP = false>
 __global__ __launch_bounds__(NTHR, 2)
 void gemm_tn_kernel(int M, int N, int K,
                     const T *__restrict__ A, int64_t lda, int amask,
@@ -649,9 +652,9 @@ void gemm_tn_kernel(int M, int N, int K,
                 if (m < M && n < N) {
                     T v = acc[ib][jb][r];
                     if (split) {
-                        part[((int64_t)blockIdx.z * N + n) * M + m] = v;
+                        part[TP ? ((int64_t)blockIdx.z * M + m) * N + n : ((int64_t)blockIdx.z * N + n) * M + m] = v;
                     } else {
-                        T *o = Out + (int64_t)n * ldo + m;
+                        T *o = TP ? Out + (int64_t)m * ldo + n : Out + (int64_t)n * ldo + m;
                         *o = beta == T(0) ? alpha * v : alpha * v + beta * *o;
                     }
                 }
@@ -1407,19 +1410,16 @@ ctqr_status gemm_tn_tprod(int M, int N, int K, const T *A, int64_t lda, int amas
 {
     if (M <= 0 || N <= 0) return CTQR_OK;
     if (M > 32) return CTQR_EINVAL;
-    const bool narrow = N <= t_narrow_max;
     int splits = gemm_tn_splits(M, N, K);
     if (splits > 1 && (part == nullptr || part_elems < (size_t)splits * M * N)) splits = 1;
     int kchunk = (int)ceil_div(ceil_div(K, splits), Mf<T>::BK) * Mf<T>::BK;
     if (kchunk <= 0) kchunk = Mf<T>::BK;
     splits = (int)ceil_div(K > 0 ? K : 1, kchunk);
-    dim3 grid((unsigned)(ceil_div(M, TILE) * ceil_div(N, narrow ? NARROW : TILE)), 1, (unsigned)splits);
-    if (narrow)
-        LAUNCH_TRY((gemm_tn_kernel<T, NARROW, 0>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B, ldb, 0,
-                   T(1), T(0), Out, ldo, part, kchunk, (const int *)nullptr, 0);
-    else
-        LAUNCH_TRY((gemm_tn_kernel<T, TILE, 0>), grid, dim3(NTHR), 0, st, M, N, K, A, lda, amask, B, ldb, 0,
-                   T(1), T(0), Out, ldo, part, kchunk, (const int *)nullptr, 0);
+    // A^T B formed as B^T A on the 128 x 32 tile (no output rows padded from
+    // M to 128), written transposed into A^T B's places
+    dim3 grid((unsigned)ceil_div(N, TILE), 1, (unsigned)splits);
+    LAUNCH_TRY((gemm_tn_kernel<T, NARROW, 0, true>), grid, dim3(NTHR), 0, st, N, M, K, B, ldb, 0, A, lda, amask,
+               T(1), T(0), Out, ldo, part, kchunk, (const int *)nullptr, 0);
     const bool sp = splits > 1;
     LAUNCH_TRY(tprod_reduce_kernel<T>, dim3((unsigned)ceil_div(N, 2)), dim3(1024), 0, st, M, N, splits,
                sp ? (const T *)part : (const T *)Out, sp ? (int64_t)M : ldo, (int64_t)M * N, Tt, ldt, W2, ldw);
