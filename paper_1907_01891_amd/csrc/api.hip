@@ -532,7 +532,11 @@ ctqr_status factor_blocks(int m, int n, T *A, int64_t lda, int nb, int kb, int k
             s = gemm_tn_tprod<T>(wdt, ncr, m - c0, Vp, lda, wdt, Cp, lda, w.Tin, PANEL_W, w.GW, PANEL_W, w.W2,
                                  PANEL_W, w.split, SPLIT_PART_ELEMS, st);
             if (s) return s;
+            // C -= V W' (rank 32) on 128 x 32 tiles: no columns padded to 128
+            const int narrow_saved = gemm_narrow_max();
+            gemm_set_narrow_max(std::max(narrow_saved, ncr));
             s = gemm_nn<T>(m - c0, ncr, wdt, Vp, lda, 1, w.W2, PANEL_W, T(-1), Cp, lda, nullptr, st);
+            gemm_set_narrow_max(narrow_saved);
             if (s) return s;
         }
         const T *V = A + (int64_t)k0 * lda + k0;
